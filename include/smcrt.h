@@ -1,0 +1,218 @@
+/*
+ * smcrt.h -- C ABI of libsmcrt, an MI355X (gfx950) implementation of the
+ * signed-distance-function photon random walk of McMillan, Bruce &
+ * Dholakia, "Meshless Monte Carlo Radiation Transfer Method for Curved
+ * Geometries using Signed Distance Functions" (2021).
+ *
+ * Conventions
+ *  - Lengths in cm, attenuation coefficients in 1/cm, angles implicit.
+ *  - Every call returns an smcrt_status; 0 is success, negatives are
+ *    errors and smcrt_last_error() holds a message for the calling thread.
+ *    No C++ exception crosses this boundary.
+ *  - Arguments are validated on the host before any device work is queued;
+ *    an invalid call queues nothing.
+ *  - "Device pointer" means memory on the engine's device (hipMalloc or a
+ *    torch CUDA tensor); "host pointer" means ordinary process memory.
+ *  - Outputs are owned by the caller, live on the device, are zeroed by the
+ *    caller and are ACCUMULATED into (+=), so runs over disjoint packet
+ *    ranges add up (resume, split runs, sharding).
+ *  - Streams are the caller's HIP streams (hipStream_t passed as void*;
+ *    NULL = the null stream).  Runs are asynchronous on that stream; the
+ *    caller synchronises before reading outputs.
+ */
+#ifndef SMCRT_H
+#define SMCRT_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define SMCRT_ABI_VERSION 1
+
+typedef enum {
+  SMCRT_OK = 0,
+  SMCRT_E_INVALID = -1,   /* an argument or scene is invalid (message says which) */
+  SMCRT_E_NOMEM = -2,     /* host or device allocation failed */
+  SMCRT_E_HIP = -3,       /* a HIP runtime call failed */
+  SMCRT_E_BUDGET = -4,    /* a request can never fit the engine's memory budget */
+  SMCRT_E_CANCELLED = -5, /* the request was cancelled */
+  SMCRT_E_STATE = -6      /* the call is not valid in the object's current state */
+} smcrt_status;
+
+/* message of the last failed call on this thread ("" if none) */
+const char* smcrt_last_error(void);
+int smcrt_abi_version(void);
+
+/* ------------------------------------------------------------ scenes ---- */
+/* Geometry initialisation (Sec. 2.3): pick SDF primitives, combine them with
+ * CSG operators into regions, give each region its optical properties
+ * (mu_a, mu_s, n, g), and bound everything with a box.  Scenes are
+ * host-side objects owned by the library. */
+
+typedef struct smcrt_scene smcrt_scene;
+
+enum {
+  SMCRT_PRIM_SPHERE = 0,   /* params: cx cy cz r           (Eq. 3)              */
+  SMCRT_PRIM_BOX = 1,      /* params: cx cy cz hx hy hz    (axis aligned, half extents) */
+  SMCRT_PRIM_CAPSULE = 2,  /* params: ax ay az bx by bz r  (segment a-b swept by r) */
+  SMCRT_PRIM_CYLINDER = 3  /* params: ax ay az bx by bz r  (axis a-b, flat caps) */
+};
+enum { SMCRT_OP_UNION = 0, SMCRT_OP_SMOOTH_UNION = 1 };
+enum {
+  SMCRT_SRC_POINT = 0,   /* params: x y z                    isotropic point source */
+  SMCRT_SRC_PENCIL = 1,  /* params: x y z ux uy uz           collimated beam */
+  SMCRT_SRC_DISC = 2,    /* params: cx cy cz R ux uy uz      top-hat disc in a z-plane */
+  SMCRT_SRC_RECT = 3     /* params: cx cy cz hx hy ux uy uz  uniform z-plane rectangle */
+};
+
+/* n_ambient: refractive index outside every region (> 0).
+ * delta: sphere-tracing surface threshold in cm (Sec. 2.3; > 0).
+ * pad: padding of the simulation volume in cm (>= 0). */
+smcrt_status smcrt_scene_create(smcrt_scene** out, double n_ambient, double delta, double pad);
+smcrt_status smcrt_scene_destroy(smcrt_scene* scene);
+
+/* Adds a primitive (Sec. 2.2).  params: host array of n_params doubles laid
+ * out as listed above; radii and half extents > 0, capsule/cylinder ends
+ * distinct.  *out_prim receives its index. */
+smcrt_status smcrt_scene_add_primitive(smcrt_scene* scene, int kind, const double* params,
+                                       int n_params, int32_t* out_prim);
+
+/* Adds a region: the union (or smooth union of radius k_cm > 0) of the
+ * listed primitives, with absorption mu_a >= 0 and scattering mu_s >= 0
+ * (mu_a + mu_s > 0), Henyey-Greenstein anisotropy -1 < g < 1 and refractive
+ * index n > 0 (Sec. 2.3: one property set per SDF).  Where regions overlap
+ * the one added later owns the point.  prims: host array of n_prims indices. */
+smcrt_status smcrt_scene_add_region(smcrt_scene* scene, const int32_t* prims, int n_prims, int op,
+                                    double k_cm, double mu_a, double mu_s, double g, double n,
+                                    int32_t* out_region);
+
+/* Photon source (Sec. 3.1 uses isotropic point and incident beams).
+ * Direction vectors are normalised by the library. */
+smcrt_status smcrt_scene_set_source(smcrt_scene* scene, int kind, const double* params, int n_params);
+
+/* Rectangular fluence grid (Sec. 3.1): box [lo, hi] cut into dims voxels,
+ * voxel (i, j, k) at index i + nx*(j + ny*k).  Without this call the grid is
+ * the regions' bounding box at 1x1x1; dims of 0 in any axis disable the
+ * tally. */
+smcrt_status smcrt_scene_set_grid(smcrt_scene* scene, const double lo[3], const double hi[3],
+                                  const int32_t dims[3]);
+
+/* Russian roulette: packets whose weight drops below w_threshold survive
+ * with probability 1/m_survive and have their weight multiplied by
+ * m_survive (defaults 1e-4 and 10). */
+smcrt_status smcrt_scene_set_roulette(smcrt_scene* scene, double w_threshold, int32_t m_survive);
+
+/* Safety caps: a packet that needs more than max_steps sphere-tracing steps
+ * for one event, or more than max_events events, is ended and its weight
+ * tallied as stalled (defaults 100000 and 1000000). */
+smcrt_status smcrt_scene_set_limits(smcrt_scene* scene, int32_t max_steps, int64_t max_events);
+
+/* number of regions and primitives; bounding box actually used */
+smcrt_status smcrt_scene_info(const smcrt_scene* scene, int32_t* n_regions, int32_t* n_prims,
+                              double bb_lo[3], double bb_hi[3]);
+
+/* ------------------------------------------------------------ engine ---- */
+/* An engine binds a device and owns its device-side staging (scene tables,
+ * work counters).  Runs on one engine must not overlap in time: queue them
+ * on one stream, or synchronise between streams. */
+
+typedef struct smcrt_engine smcrt_engine;
+
+smcrt_status smcrt_engine_create(smcrt_engine** out, int device);
+smcrt_status smcrt_engine_destroy(smcrt_engine* engine);
+
+enum { SMCRT_PREC_F32 = 0, SMCRT_PREC_F64 = 1 };
+
+/* Launch options.  precision: F32 keeps positions, directions, distances and
+ * transcendentals in FP32 (interface geometry, Fresnel, weights and tallies
+ * stay FP64); F64 runs the whole walk in FP64.  block: threads per workgroup
+ * (64..1024, multiple of 64).  blocks_per_cu: resident workgroups per CU
+ * the grid is sized for (1..32).  refill_min: dead lanes a wave waits for
+ * before it emits new packets (1..64).  surface_min: lanes a wave gathers at
+ * surfaces before it runs the FP64 interface step (1..64). */
+typedef struct {
+  int32_t precision;
+  int32_t block;
+  int32_t blocks_per_cu;
+  int32_t refill_min;
+  int32_t surface_min;
+  int32_t reserved[3];
+} smcrt_opts;
+
+smcrt_status smcrt_engine_get_opts(const smcrt_engine* engine, smcrt_opts* out);
+smcrt_status smcrt_engine_set_opts(smcrt_engine* engine, const smcrt_opts* opts);
+
+/* ------------------------------------------------------------ tallies --- */
+
+typedef struct {
+  double launched;          /* packets emitted (unit weight each) */
+  double escaped_face[6];   /* weight leaving the volume through -x,+x,-y,+y,-z,+z */
+  double roulette_gain;     /* weight added by roulette survivors */
+  double roulette_loss;     /* weight removed by roulette */
+  double stalled;           /* weight of packets ended by the safety caps */
+  uint64_t events;          /* interactions + interface events */
+  uint64_t steps;           /* sphere-tracing steps */
+  uint64_t interactions;
+  uint64_t interfaces;      /* changes of medium met (reflect + refract + cross) */
+  uint64_t reflections;
+  uint64_t refractions;
+  uint64_t crossings;       /* index-matched crossings */
+  uint64_t advances;        /* forced advances past surfaces with no change of medium */
+  uint64_t voxel_pieces;    /* voxel-sized pieces credited to the fluence grid */
+  uint64_t kills;           /* roulette losses */
+  uint64_t stalls;
+  uint64_t escapes;
+  uint64_t grid_atomics;    /* global FP64 atomic updates issued for the grid */
+} smcrt_tallies;
+
+/* ------------------------------------------------------------ runs ------ */
+
+/* Runs packets [first_packet, first_packet + n_packets) of the scene with
+ * random stream seed (Philox4x32-10 keyed by seed, counter by packet id and
+ * event index, so results do not depend on the launch shape).
+ *   d_fluence_raw: device, nx*ny*nz doubles, += sum of weight * path length
+ *                  per voxel (cm); may be NULL when the grid is disabled.
+ *   d_absorbed:    device, n_regions doubles, += absorbed weight per region.
+ *   d_tallies:     device, one smcrt_tallies, += scalar tallies.
+ * Asynchronous on hip_stream. */
+smcrt_status smcrt_run(smcrt_engine* engine, const smcrt_scene* scene, uint64_t seed,
+                       uint64_t first_packet, uint64_t n_packets, double* d_fluence_raw,
+                       double* d_absorbed, smcrt_tallies* d_tallies, void* hip_stream);
+
+/* Fluence normalisation: d_phi[v] = d_raw[v] / (launched * voxel volume),
+ * in cm^-2 per launched unit weight.  d_raw and d_phi: device, nx*ny*nz
+ * doubles (may alias). */
+smcrt_status smcrt_normalize_fluence(const smcrt_scene* scene, const double* d_raw, double launched,
+                                     double* d_phi, void* hip_stream);
+
+/* ------------------------------------------------------------ traces ---- */
+
+enum {
+  SMCRT_EV_EMIT = 0, SMCRT_EV_SCATTER = 1, SMCRT_EV_ABSORB = 2, SMCRT_EV_KILL = 3,
+  SMCRT_EV_REFLECT = 4, SMCRT_EV_REFRACT = 5, SMCRT_EV_CROSS = 6, SMCRT_EV_ESCAPE = 7,
+  SMCRT_EV_STALL = 8
+};
+
+typedef struct {
+  uint32_t event;   /* event index (0 = emission) */
+  uint32_t type;    /* SMCRT_EV_* */
+  int32_t region;   /* region after the event (-1 = ambient) */
+  int32_t pad;
+  double p[3], u[3], w, tau;  /* state after the event */
+} smcrt_event;
+
+/* Event-by-event records of the listed packets through the same device walk
+ * as smcrt_run (with recording compiled in).  d_packet_ids: device, n_ids
+ * uint64.  d_out: device, n_ids * max_events records; packet i writes its
+ * first max_events records from d_out[i * max_events]; d_count: device,
+ * n_ids int32 record counts.  No fluence is tallied. */
+smcrt_status smcrt_trace(smcrt_engine* engine, const smcrt_scene* scene, uint64_t seed,
+                         const uint64_t* d_packet_ids, int n_ids, int max_events,
+                         smcrt_event* d_out, int32_t* d_count, void* hip_stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,650 @@
+/*
+ * smcrt_oracle.c -- plain FP64 CPU oracle of the SDF photon random walk.
+ *
+ * TEST INFRASTRUCTURE ONLY (see smcrt_oracle.h).  Written for a reader to
+ * check against the paper by eye: no acceleration structure, no blocking,
+ * no merging of path segments, brute-force evaluation of every SDF at every
+ * step (Sec. 2.3), a tally that finds voxel pieces by intersecting the
+ * segment with every voxel plane it spans, and OpenMP over packets with
+ * per-thread accumulators reduced in thread order.
+ *
+ * Where the paper is silent the code follows the readings listed in the
+ * repository's design notes; each such place says "reading:".
+ */
+#include "smcrt_oracle.h"
+
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+#define ORC_INF (1.0 / 0.0)
+/* reading: a surface hit is found by snapping along the ray when the ray
+ * meets the surface at a cosine of at least this, else by projecting along
+ * the normal */
+#define ORC_SNAP_COS 0.1
+/* reading: probe distance across a surface, re-placement distance and the
+ * forced advance past a surface that is not a physical interface, in units
+ * of the threshold delta */
+#define ORC_OFFSET 2.0
+/* reading: central-difference step of the numerical normal, in units of delta */
+#define ORC_H_NORMAL 1e-2
+
+/* ---------------------------------------------------------------- RNG --- */
+
+/* Philox4x32-10: ten rounds of the Philox S-box with multipliers
+ * 0xD2511F53 and 0xCD9E8D57 and Weyl key increments 0x9E3779B9, 0xBB67AE85
+ * (Salmon, Moraes, Dror & Shaw, "Parallel random numbers: as easy as 1, 2,
+ * 3", SC'11).  The key is bumped before every round except the first. */
+void orc_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]) {
+  uint32_t c0 = ctr[0], c1 = ctr[1], c2 = ctr[2], c3 = ctr[3];
+  uint32_t k0 = key[0], k1 = key[1];
+  for (int round = 0; round < 10; ++round) {
+    if (round > 0) {
+      k0 += 0x9E3779B9u;
+      k1 += 0xBB67AE85u;
+    }
+    uint64_t prod0 = (uint64_t)0xD2511F53u * (uint64_t)c0;
+    uint64_t prod1 = (uint64_t)0xCD9E8D57u * (uint64_t)c2;
+    uint32_t hi0 = (uint32_t)(prod0 >> 32), lo0 = (uint32_t)prod0;
+    uint32_t hi1 = (uint32_t)(prod1 >> 32), lo1 = (uint32_t)prod1;
+    uint32_t n0 = hi1 ^ c1 ^ k0;
+    uint32_t n1 = lo1;
+    uint32_t n2 = hi0 ^ c3 ^ k1;
+    uint32_t n3 = lo0;
+    c0 = n0; c1 = n1; c2 = n2; c3 = n3;
+  }
+  out[0] = c0; out[1] = c1; out[2] = c2; out[3] = c3;
+}
+
+/* reading of Eq. 1's "xi in [0, 1]": the top 23 bits m of the word give
+ * xi = (m + 1/2) / 2^23, strictly inside (0, 1) and exact in FP32 and FP64 */
+double orc_xi(uint32_t x) {
+  return ((double)(x >> 9) + 0.5) * (1.0 / 8388608.0);
+}
+
+/* the four variates of event k of packet pid */
+static void event_xi(uint64_t seed, uint64_t pid, uint32_t k, double xi[4]) {
+  uint32_t ctr[4] = {k, (uint32_t)pid, (uint32_t)(pid >> 32), 0u};
+  uint32_t key[2] = {(uint32_t)seed, (uint32_t)(seed >> 32)};
+  uint32_t w[4];
+  orc_philox4x32_10(ctr, key, w);
+  for (int i = 0; i < 4; ++i) xi[i] = orc_xi(w[i]);
+}
+
+/* ------------------------------------------------------------ vectors --- */
+
+static double dot3(const double a[3], const double b[3]) {
+  return a[0] * b[0] + a[1] * b[1] + a[2] * b[2];
+}
+static double len3(const double a[3]) { return sqrt(dot3(a, a)); }
+static double clampd(double x, double lo, double hi) { return x < lo ? lo : (x > hi ? hi : x); }
+static double maxd(double a, double b) { return a > b ? a : b; }
+static double mind(double a, double b) { return a < b ? a : b; }
+
+/* --------------------------------------------------------------- SDFs --- */
+
+/* Exact Euclidean distance functions, positive outside (Sec. 2.2, Eq. 2). */
+double orc_prim_sdf(const orc_prim* pr, const double p[3]) {
+  const double* q = pr->p;
+  switch (pr->kind) {
+    case ORC_SPHERE: { /* Eq. 3: |p - c| - r */
+      double d[3] = {p[0] - q[0], p[1] - q[1], p[2] - q[2]};
+      return len3(d) - q[3];
+    }
+    case ORC_BOX: { /* distance to an axis-aligned box with half extents h */
+      double e[3], out[3];
+      for (int i = 0; i < 3; ++i) {
+        e[i] = fabs(p[i] - q[i]) - q[3 + i];
+        out[i] = maxd(e[i], 0.0);
+      }
+      double inside = mind(maxd(e[0], maxd(e[1], e[2])), 0.0);
+      return len3(out) + inside;
+    }
+    case ORC_CAPSULE: { /* distance to the segment a-b, minus r */
+      double ba[3] = {q[3] - q[0], q[4] - q[1], q[5] - q[2]};
+      double pa[3] = {p[0] - q[0], p[1] - q[1], p[2] - q[2]};
+      double t = clampd(dot3(pa, ba) / dot3(ba, ba), 0.0, 1.0);
+      double d[3] = {pa[0] - t * ba[0], pa[1] - t * ba[1], pa[2] - t * ba[2]};
+      return len3(d) - q[6];
+    }
+    case ORC_CYLINDER: { /* solid cylinder of radius r about a-b, flat caps */
+      double ba[3] = {q[3] - q[0], q[4] - q[1], q[5] - q[2]};
+      double L = len3(ba);
+      double e[3] = {ba[0] / L, ba[1] / L, ba[2] / L};
+      double pa[3] = {p[0] - q[0], p[1] - q[1], p[2] - q[2]};
+      double x = dot3(pa, e);
+      double radial[3] = {pa[0] - x * e[0], pa[1] - x * e[1], pa[2] - x * e[2]};
+      double rho = len3(radial);
+      double q1 = rho - q[6];
+      double q2 = fabs(x - 0.5 * L) - 0.5 * L;
+      double o1 = maxd(q1, 0.0), o2 = maxd(q2, 0.0);
+      return mind(maxd(q1, q2), 0.0) + sqrt(o1 * o1 + o2 * o2);
+    }
+    default:
+      return ORC_INF;
+  }
+}
+
+/* polynomial smooth minimum of radius k (Sec. 2.2 gallery, panel e):
+ * equals min(a, b) when |a - b| >= k and is never above it */
+double orc_smooth_union(double a, double b, double k) {
+  double h = clampd(0.5 + 0.5 * (b - a) / k, 0.0, 1.0);
+  return h * a + (1.0 - h) * b - k * h * (1.0 - h);
+}
+
+double orc_region_sdf(const orc_scene* s, int r, const double p[3]) {
+  const orc_region* rg = &s->regions[r];
+  double d = orc_prim_sdf(&s->prims[rg->first_prim], p);
+  for (int i = 1; i < rg->n_prims; ++i) {
+    double di = orc_prim_sdf(&s->prims[rg->first_prim + i], p);
+    d = (rg->op == ORC_SMOOTH_UNION) ? orc_smooth_union(d, di, rg->k) : mind(d, di);
+  }
+  return d;
+}
+
+/* reading: a point belongs to the highest-index region whose SDF is
+ * negative there; -1 (ambient) if none */
+int orc_region_of(const orc_scene* s, const double p[3]) {
+  for (int r = s->n_regions - 1; r >= 0; --r)
+    if (orc_region_sdf(s, r, p) < 0.0) return r;
+  return -1;
+}
+
+/* unit outward normal of region r at p by central differences (Sec. 1:
+ * normals by numerical differentiation) */
+void orc_region_normal(const orc_scene* s, int r, const double p[3], double h, double n[3]) {
+  for (int i = 0; i < 3; ++i) {
+    double a[3] = {p[0], p[1], p[2]}, b[3] = {p[0], p[1], p[2]};
+    a[i] += h;
+    b[i] -= h;
+    n[i] = (orc_region_sdf(s, r, a) - orc_region_sdf(s, r, b)) / (2.0 * h);
+  }
+  double l = len3(n);
+  for (int i = 0; i < 3; ++i) n[i] /= l;
+}
+
+/* signed distance of the simulation volume (Sec. 2.3: positive = outside) */
+double orc_box_sdf(const double lo[3], const double hi[3], const double p[3]) {
+  orc_prim b;
+  b.kind = ORC_BOX;
+  for (int i = 0; i < 3; ++i) {
+    b.p[i] = 0.5 * (lo[i] + hi[i]);
+    b.p[3 + i] = 0.5 * (hi[i] - lo[i]);
+  }
+  return orc_prim_sdf(&b, p);
+}
+
+/* ------------------------------------------------------------ physics --- */
+
+double orc_fresnel(double n1, double n2, double cos_i, double* cos_t) {
+  double eta = n1 / n2;
+  double sin2_t = eta * eta * (1.0 - cos_i * cos_i);
+  if (sin2_t >= 1.0) { /* total internal reflection */
+    *cos_t = 0.0;
+    return 1.0;
+  }
+  double ct = sqrt(1.0 - sin2_t);
+  double rs = (n1 * cos_i - n2 * ct) / (n1 * cos_i + n2 * ct);
+  double rp = (n1 * ct - n2 * cos_i) / (n1 * ct + n2 * cos_i);
+  *cos_t = ct;
+  return 0.5 * (rs * rs + rp * rp);
+}
+
+/* Henyey-Greenstein scattering cosine by inversion of its CDF (Sec. 3.1);
+ * isotropic when |g| < 1e-6 */
+double orc_hg_cos(double g, double xi) {
+  if (fabs(g) < 1e-6) return 2.0 * xi - 1.0;
+  double frac = (1.0 - g * g) / (1.0 - g + 2.0 * g * xi);
+  double c = (1.0 + g * g - frac * frac) / (2.0 * g);
+  return clampd(c, -1.0, 1.0);
+}
+
+/* turn u by polar angle acos(cos_t) and azimuth phi about itself
+ * (the direction update of MCML, Wang, Jacques & Zheng 1995) */
+void orc_rotate(double u[3], double cos_t, double phi) {
+  double sin_t = sqrt(maxd(0.0, 1.0 - cos_t * cos_t));
+  double cp = cos(phi), sp = sin(phi);
+  double ux = u[0], uy = u[1], uz = u[2];
+  double v[3];
+  if (fabs(uz) > 1.0 - 1e-5) {
+    v[0] = sin_t * cp;
+    v[1] = sin_t * sp;
+    v[2] = (uz >= 0.0 ? 1.0 : -1.0) * cos_t;
+  } else {
+    double t = sqrt(1.0 - uz * uz);
+    v[0] = sin_t * (ux * uz * cp - uy * sp) / t + ux * cos_t;
+    v[1] = sin_t * (uy * uz * cp + ux * sp) / t + uy * cos_t;
+    v[2] = -sin_t * cp * t + uz * cos_t;
+  }
+  double l = len3(v);
+  for (int i = 0; i < 3; ++i) u[i] = v[i] / l;
+}
+
+/* ------------------------------------------------------------- tally --- */
+
+static int cmp_double(const void* a, const void* b) {
+  double x = *(const double*)a, y = *(const double*)b;
+  return (x > y) - (x < y);
+}
+
+/* Path-length fluence estimator on rectangular bins (Sec. 3.1, Table 2
+ * runs): every voxel plane the segment crosses splits it; each piece is
+ * credited to the voxel holding its midpoint.  Voxel i spans
+ * [lo + i*D, lo + (i+1)*D); the grid's upper face belongs to the last voxel. */
+int64_t orc_tally_segment(const orc_scene* s, const double a[3], const double b[3],
+                          double w, double* f) {
+  const int* nd = s->g_dims;
+  if (!f || nd[0] <= 0 || nd[1] <= 0 || nd[2] <= 0) return 0;
+  double d[3] = {b[0] - a[0], b[1] - a[1], b[2] - a[2]};
+  double len = len3(d);
+  if (!(len > 0.0)) return 0;
+  double u[3] = {d[0] / len, d[1] / len, d[2] / len};
+  /* clip the parameter range [0, len] to the grid box */
+  double t0 = 0.0, t1 = len;
+  for (int i = 0; i < 3; ++i) {
+    if (u[i] == 0.0) {
+      if (a[i] < s->g_lo[i] || a[i] > s->g_hi[i]) return 0;
+    } else {
+      double ta = (s->g_lo[i] - a[i]) / u[i], tb = (s->g_hi[i] - a[i]) / u[i];
+      t0 = maxd(t0, mind(ta, tb));
+      t1 = mind(t1, maxd(ta, tb));
+    }
+  }
+  if (!(t1 > t0)) return 0;
+  /* every interior voxel plane crossed strictly inside (t0, t1): for each
+   * axis, scan the plane indices between the clipped end coordinates */
+  int lo_j[3] = {0, 0, 0}, hi_j[3] = {-1, -1, -1}, cap = 2;
+  for (int i = 0; i < 3; ++i) {
+    if (u[i] == 0.0) continue;
+    double D = (s->g_hi[i] - s->g_lo[i]) / nd[i];
+    double xa = a[i] + t0 * u[i], xb = a[i] + t1 * u[i];
+    double x0 = mind(xa, xb), x1 = maxd(xa, xb);
+    lo_j[i] = (int)floor((x0 - s->g_lo[i]) / D);
+    hi_j[i] = (int)ceil((x1 - s->g_lo[i]) / D);
+    if (lo_j[i] < 1) lo_j[i] = 1;
+    if (hi_j[i] > nd[i] - 1) hi_j[i] = nd[i] - 1;
+    if (hi_j[i] >= lo_j[i]) cap += hi_j[i] - lo_j[i] + 1;
+  }
+  double stackbuf[512];
+  double* ts = cap <= 512 ? stackbuf : (double*)malloc(sizeof(double) * (size_t)cap);
+  if (!ts) return 0;
+  int m = 0;
+  ts[m++] = t0;
+  for (int i = 0; i < 3; ++i) {
+    if (u[i] == 0.0) continue;
+    double D = (s->g_hi[i] - s->g_lo[i]) / nd[i];
+    for (int j = lo_j[i]; j <= hi_j[i]; ++j) {
+      double plane = s->g_lo[i] + j * D;
+      double t = (plane - a[i]) / u[i];
+      if (t > t0 && t < t1) ts[m++] = t;
+    }
+  }
+  ts[m++] = t1;
+  qsort(ts, (size_t)m, sizeof(double), cmp_double);
+  int64_t pieces = 0;
+  for (int q = 0; q + 1 < m; ++q) {
+    double l = ts[q + 1] - ts[q];
+    if (!(l > 0.0)) continue;
+    double tm = 0.5 * (ts[q] + ts[q + 1]);
+    int idx[3];
+    for (int i = 0; i < 3; ++i) {
+      double D = (s->g_hi[i] - s->g_lo[i]) / nd[i];
+      int v = (int)floor((a[i] + tm * u[i] - s->g_lo[i]) / D);
+      idx[i] = v < 0 ? 0 : (v >= nd[i] ? nd[i] - 1 : v);
+    }
+    f[(size_t)idx[0] + (size_t)nd[0] * ((size_t)idx[1] + (size_t)nd[1] * (size_t)idx[2])] += w * l;
+    ++pieces;
+  }
+  if (ts != stackbuf) free(ts);
+  return pieces;
+}
+
+/* ------------------------------------------------------------ the walk --- */
+
+typedef struct {
+  const orc_scene* s;
+  double* f;
+  double* absorbed;
+  orc_tallies* t;
+  orc_event* rec;
+  int cap, nrec;
+} walker;
+
+typedef struct {
+  double p[3], u[3], w, tau;
+  int region;
+  uint32_t k;
+} packet;
+
+static double reg_mua(const orc_scene* s, int r) { return r < 0 ? 0.0 : s->regions[r].mua; }
+static double reg_mus(const orc_scene* s, int r) { return r < 0 ? 0.0 : s->regions[r].mus; }
+static double reg_n(const orc_scene* s, int r) { return r < 0 ? s->n_ambient : s->regions[r].n; }
+
+static void record(walker* wk, const packet* pk, int type) {
+  if (!wk->rec || wk->nrec >= wk->cap) return;
+  orc_event* e = &wk->rec[wk->nrec++];
+  e->event = pk->k;
+  e->type = (uint32_t)type;
+  e->region = pk->region;
+  e->pad = 0;
+  for (int i = 0; i < 3; ++i) { e->p[i] = pk->p[i]; e->u[i] = pk->u[i]; }
+  e->w = pk->w;
+  e->tau = pk->tau;
+}
+
+/* straight move of length l along u, tallied with the current weight */
+static void move(walker* wk, packet* pk, double l) {
+  double b[3] = {pk->p[0] + l * pk->u[0], pk->p[1] + l * pk->u[1], pk->p[2] + l * pk->u[2]};
+  wk->t->voxel_segments += (uint64_t)orc_tally_segment(wk->s, pk->p, b, pk->w, wk->f);
+  for (int i = 0; i < 3; ++i) pk->p[i] = b[i];
+}
+
+/* emission, event 0 */
+static void emit(walker* wk, packet* pk, uint64_t seed, uint64_t pid) {
+  const orc_scene* s = wk->s;
+  const double* q = s->src;
+  double xi[4];
+  pk->k = 0;
+  event_xi(seed, pid, 0, xi);
+  switch (s->src_kind) {
+    case ORC_SRC_POINT: { /* isotropic point source (Sec. 3.1) */
+      double ct = 2.0 * xi[0] - 1.0, st = sqrt(maxd(0.0, 1.0 - ct * ct));
+      double phi = 2.0 * M_PI * xi[1];
+      for (int i = 0; i < 3; ++i) pk->p[i] = q[i];
+      pk->u[0] = st * cos(phi); pk->u[1] = st * sin(phi); pk->u[2] = ct;
+      break;
+    }
+    case ORC_SRC_PENCIL: /* collimated beam from one point */
+      for (int i = 0; i < 3; ++i) { pk->p[i] = q[i]; pk->u[i] = q[3 + i]; }
+      break;
+    case ORC_SRC_DISC: { /* top-hat disc of radius q[3] in a z-plane */
+      double r = q[3] * sqrt(xi[0]), phi = 2.0 * M_PI * xi[1];
+      pk->p[0] = q[0] + r * cos(phi); pk->p[1] = q[1] + r * sin(phi); pk->p[2] = q[2];
+      for (int i = 0; i < 3; ++i) pk->u[i] = q[4 + i];
+      break;
+    }
+    case ORC_SRC_RECT: /* uniform over a z-plane rectangle of half sides q[3], q[4] */
+      pk->p[0] = q[0] + q[3] * (2.0 * xi[0] - 1.0);
+      pk->p[1] = q[1] + q[4] * (2.0 * xi[1] - 1.0);
+      pk->p[2] = q[2];
+      for (int i = 0; i < 3; ++i) pk->u[i] = q[5 + i];
+      break;
+  }
+  double l = len3(pk->u);
+  for (int i = 0; i < 3; ++i) pk->u[i] /= l;
+  pk->w = 1.0;
+  pk->tau = -log(xi[3]); /* Eq. 1 */
+  pk->region = orc_region_of(s, pk->p);
+  wk->t->launched += 1.0;
+  record(wk, pk, ORC_EV_EMIT);
+}
+
+/* absorption, scattering and roulette at an interaction point; returns 0
+ * when the packet ends */
+static int interact(walker* wk, packet* pk, uint64_t seed, uint64_t pid) {
+  const orc_scene* s = wk->s;
+  const orc_region* rg = &s->regions[pk->region];
+  double xi[4];
+  pk->k += 1;
+  event_xi(seed, pid, pk->k, xi);
+  wk->t->events++;
+  wk->t->interactions++;
+  /* reading: implicit capture, the fraction mu_a/mu_t of the weight is
+   * deposited at every interaction */
+  double dA = pk->w * rg->mua / (rg->mua + rg->mus);
+  wk->absorbed[pk->region] += dA;
+  pk->w -= dA;
+  if (pk->w == 0.0) {
+    record(wk, pk, ORC_EV_ABSORB);
+    return 0;
+  }
+  orc_rotate(pk->u, orc_hg_cos(rg->g, xi[0]), 2.0 * M_PI * xi[1]);
+  if (pk->w < s->w_threshold) { /* Russian roulette */
+    if (xi[2] < 1.0 / (double)s->m_survive) {
+      wk->t->roulette_gain += (double)(s->m_survive - 1) * pk->w;
+      pk->w *= (double)s->m_survive;
+    } else {
+      wk->t->roulette_loss += pk->w;
+      wk->t->kills++;
+      record(wk, pk, ORC_EV_KILL);
+      return 0;
+    }
+  }
+  pk->tau = -log(xi[3]); /* Eq. 1 */
+  record(wk, pk, ORC_EV_SCATTER);
+  return 1;
+}
+
+enum { GO_ON = 0, DO_INTERACT = 1, ENDED = 2 };
+
+/* the packet is within delta of a surface (Sec. 2.3); s_rem is the
+ * remaining free path in cm */
+static int surface(walker* wk, packet* pk, double s_rem, uint64_t seed, uint64_t pid) {
+  const orc_scene* s = wk->s;
+  const double delta = s->delta;
+  double mut = reg_mua(s, pk->region) + reg_mus(s, pk->region);
+  /* nearest surface j: smallest |d_r|, ties to the lowest index */
+  int j = 0;
+  double dj = orc_region_sdf(s, 0, pk->p);
+  for (int r = 1; r < s->n_regions; ++r) {
+    double d = orc_region_sdf(s, r, pk->p);
+    if (fabs(d) < fabs(dj)) { dj = d; j = r; }
+  }
+  double h = ORC_H_NORMAL * delta;
+  double n0[3];
+  orc_region_normal(s, j, pk->p, h, n0);
+  double c0 = dot3(pk->u, n0);
+  /* reading: the surface point is where the ray meets the surface
+   * (one Newton step along u); grazing rays fall back to the normal foot */
+  double t_ray = 0.0, ps[3];
+  if (fabs(c0) >= ORC_SNAP_COS) {
+    t_ray = -dj / c0;
+    for (int i = 0; i < 3; ++i) ps[i] = pk->p[i] + t_ray * pk->u[i];
+  } else {
+    for (int i = 0; i < 3; ++i) ps[i] = pk->p[i] - dj * n0[i];
+  }
+  double nrm[3];
+  orc_region_normal(s, j, ps, h, nrm);
+  double c = dot3(pk->u, nrm);
+  double sg = c > 0.0 ? 1.0 : -1.0;
+  double q[3];
+  for (int i = 0; i < 3; ++i) q[i] = ps[i] + sg * ORC_OFFSET * delta * nrm[i];
+  int r2 = (c == 0.0) ? pk->region : orc_region_of(s, q);
+  if (r2 == pk->region) {
+    /* reading: no change of medium ahead (moving away, parallel, or a face
+     * hidden inside one region): advance 2*delta along the ray */
+    wk->t->advances++;
+    double l = ORC_OFFSET * delta;
+    if (s_rem <= l) {
+      move(wk, pk, s_rem);
+      pk->tau = 0.0;
+      return DO_INTERACT;
+    }
+    move(wk, pk, l);
+    pk->tau -= mut * l;
+    return GO_ON;
+  }
+  /* a change of medium: go to the surface point first */
+  if (t_ray > 0.0) {
+    if (s_rem <= t_ray) {
+      move(wk, pk, s_rem);
+      pk->tau = 0.0;
+      return DO_INTERACT;
+    }
+    move(wk, pk, t_ray);
+    pk->tau -= mut * t_ray;
+  }
+  for (int i = 0; i < 3; ++i) pk->p[i] = ps[i];
+  pk->k += 1;
+  wk->t->events++;
+  wk->t->interfaces++;
+  double n1 = reg_n(s, pk->region), n2 = reg_n(s, r2);
+  if (n1 == n2) { /* index matched: cross without deflection */
+    for (int i = 0; i < 3; ++i) pk->p[i] = q[i];
+    pk->region = r2;
+    wk->t->crossings++;
+    record(wk, pk, ORC_EV_CROSS);
+    return GO_ON;
+  }
+  double xi[4];
+  event_xi(seed, pid, pk->k, xi);
+  double cos_i = fabs(c), cos_t;
+  double R = orc_fresnel(n1, n2, cos_i, &cos_t);
+  if (xi[0] < R) { /* specular reflection back into the current medium */
+    for (int i = 0; i < 3; ++i) {
+      pk->u[i] -= 2.0 * c * nrm[i];
+      pk->p[i] = ps[i] - sg * ORC_OFFSET * delta * nrm[i];
+    }
+    double l = len3(pk->u);
+    for (int i = 0; i < 3; ++i) pk->u[i] /= l;
+    wk->t->reflections++;
+    record(wk, pk, ORC_EV_REFLECT);
+  } else { /* refraction by Snell's law into the far medium */
+    double eta = n1 / n2;
+    for (int i = 0; i < 3; ++i) pk->u[i] = eta * pk->u[i] + (cos_t - eta * cos_i) * sg * nrm[i];
+    double l = len3(pk->u);
+    for (int i = 0; i < 3; ++i) { pk->u[i] /= l; pk->p[i] = q[i]; }
+    pk->region = r2;
+    wk->t->refractions++;
+    record(wk, pk, ORC_EV_REFRACT);
+  }
+  return GO_ON;
+}
+
+static void walk(walker* wk, uint64_t seed, uint64_t pid) {
+  const orc_scene* s = wk->s;
+  packet pk;
+  emit(wk, &pk, seed, pid);
+  for (;;) {
+    /* one event: sphere-trace until interaction (Sec. 2.3) */
+    int32_t steps = 0;
+    int state = GO_ON;
+    while (state == GO_ON) {
+      if (++steps > s->max_steps || (int64_t)pk.k > s->max_events) {
+        wk->t->stalled += pk.w;
+        wk->t->stalls++;
+        record(wk, &pk, ORC_EV_STALL);
+        return;
+      }
+      wk->t->steps++;
+      double dmin = ORC_INF;
+      for (int r = 0; r < s->n_regions; ++r) dmin = mind(dmin, fabs(orc_region_sdf(s, r, pk.p)));
+      if (orc_box_sdf(s->bb_lo, s->bb_hi, pk.p) > 0.0) { /* left the volume */
+        double e[3], best = -ORC_INF;
+        int face = 0;
+        for (int i = 0; i < 3; ++i) {
+          double c = 0.5 * (s->bb_lo[i] + s->bb_hi[i]), hw = 0.5 * (s->bb_hi[i] - s->bb_lo[i]);
+          e[i] = fabs(pk.p[i] - c) - hw;
+          if (e[i] > best) { best = e[i]; face = 2 * i + (pk.p[i] > c ? 1 : 0); }
+        }
+        wk->t->escaped_face[face] += pk.w;
+        wk->t->escapes++;
+        record(wk, &pk, ORC_EV_ESCAPE);
+        return;
+      }
+      double mut = reg_mua(s, pk.region) + reg_mus(s, pk.region);
+      double s_rem = mut > 0.0 ? pk.tau / mut : ORC_INF;
+      if (s_rem <= dmin) { /* the optical depth runs out first */
+        move(wk, &pk, s_rem);
+        pk.tau = 0.0;
+        state = DO_INTERACT;
+      } else if (dmin < s->delta) { /* on a boundary */
+        uint32_t k_before = pk.k;
+        state = surface(wk, &pk, s_rem, seed, pid);
+        if (pk.k != k_before) steps = 0; /* an interface event starts a new event */
+      } else { /* sphere-tracing step of the full distance */
+        move(wk, &pk, dmin);
+        pk.tau -= mut * dmin;
+      }
+    }
+    if (!interact(wk, &pk, seed, pid)) return;
+  }
+}
+
+/* --------------------------------------------------------------- runs --- */
+
+static int check_scene(const orc_scene* s) {
+  if (!s || s->n_regions < 1 || s->n_prims < 1 || !s->prims || !s->regions) return -1;
+  if (!(s->delta > 0.0) || s->m_survive < 1 || s->max_steps < 1) return -1;
+  for (int r = 0; r < s->n_regions; ++r) {
+    const orc_region* rg = &s->regions[r];
+    if (rg->first_prim < 0 || rg->n_prims < 1 || rg->first_prim + rg->n_prims > s->n_prims) return -1;
+    if (!(rg->mua >= 0.0) || !(rg->mus >= 0.0) || !(rg->mua + rg->mus > 0.0)) return -1;
+  }
+  return 0;
+}
+
+int orc_run(const orc_scene* s, uint64_t seed, uint64_t first, uint64_t n,
+            int n_threads, double* f, double* absorbed, orc_tallies* t) {
+  if (check_scene(s) != 0 || !absorbed || !t) return -1;
+  int nt = 1;
+#ifdef _OPENMP
+  nt = n_threads > 0 ? n_threads : omp_get_max_threads();
+#endif
+  size_t nvox = (s->g_dims[0] > 0 && s->g_dims[1] > 0 && s->g_dims[2] > 0 && f)
+                    ? (size_t)s->g_dims[0] * (size_t)s->g_dims[1] * (size_t)s->g_dims[2]
+                    : 0;
+  double** fs = (double**)calloc((size_t)nt, sizeof(double*));
+  double** as = (double**)calloc((size_t)nt, sizeof(double*));
+  orc_tallies* ts = (orc_tallies*)calloc((size_t)nt, sizeof(orc_tallies));
+  int fail = 0;
+  for (int i = 0; i < nt; ++i) {
+    fs[i] = nvox ? (double*)calloc(nvox, sizeof(double)) : NULL;
+    as[i] = (double*)calloc((size_t)s->n_regions, sizeof(double));
+    if ((nvox && !fs[i]) || !as[i]) fail = 1;
+  }
+  if (!fail) {
+#ifdef _OPENMP
+#pragma omp parallel num_threads(nt)
+#endif
+    {
+      int me = 0;
+#ifdef _OPENMP
+      me = omp_get_thread_num();
+#endif
+      walker wk = {s, fs[me], as[me], &ts[me], NULL, 0, 0};
+      /* contiguous, thread-count dependent chunks of packet ids */
+      uint64_t lo = first + n * (uint64_t)me / (uint64_t)nt;
+      uint64_t hi = first + n * (uint64_t)(me + 1) / (uint64_t)nt;
+      for (uint64_t pid = lo; pid < hi; ++pid) walk(&wk, seed, pid);
+    }
+    for (int i = 0; i < nt; ++i) { /* reduce in thread order */
+      for (size_t v = 0; v < nvox; ++v) f[v] += fs[i][v];
+      for (int r = 0; r < s->n_regions; ++r) absorbed[r] += as[i][r];
+      t->launched += ts[i].launched;
+      for (int k = 0; k < 6; ++k) t->escaped_face[k] += ts[i].escaped_face[k];
+      t->roulette_gain += ts[i].roulette_gain;
+      t->roulette_loss += ts[i].roulette_loss;
+      t->stalled += ts[i].stalled;
+      t->events += ts[i].events;
+      t->steps += ts[i].steps;
+      t->interactions += ts[i].interactions;
+      t->interfaces += ts[i].interfaces;
+      t->reflections += ts[i].reflections;
+      t->refractions += ts[i].refractions;
+      t->crossings += ts[i].crossings;
+      t->advances += ts[i].advances;
+      t->voxel_segments += ts[i].voxel_segments;
+      t->kills += ts[i].kills;
+      t->stalls += ts[i].stalls;
+      t->escapes += ts[i].escapes;
+    }
+  }
+  for (int i = 0; i < nt; ++i) { free(fs[i]); free(as[i]); }
+  free(fs); free(as); free(ts);
+  return fail ? -2 : 0;
+}
+
+int orc_trace(const orc_scene* s, uint64_t seed, uint64_t pid, int cap, orc_event* out) {
+  if (check_scene(s) != 0 || !out || cap < 1) return -1;
+  double* absorbed = (double*)calloc((size_t)s->n_regions, sizeof(double));
+  orc_tallies t;
+  memset(&t, 0, sizeof(t));
+  walker wk = {s, NULL, absorbed, &t, out, cap, 0};
+  walk(&wk, seed, pid);
+  free(absorbed);
+  return wk.nrec;
+}

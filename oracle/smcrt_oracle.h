@@ -1,0 +1,109 @@
+/*
+ * smcrt_oracle.h -- plain, slow FP64 CPU oracle of the SDF photon random walk
+ * of McMillan, Bruce & Dholakia, "Meshless Monte Carlo Radiation Transfer
+ * Method for Curved Geometries using Signed Distance Functions" (2021).
+ *
+ * TEST INFRASTRUCTURE ONLY.  Nothing in the product library links, loads or
+ * calls this code; only the test-suite, the smoke check and the CPU-baseline
+ * leg of the benchmark do.  It shares no source, header, table or helper
+ * with the GPU path.
+ *
+ * Units: lengths in cm, coefficients in 1/cm.  Every double is IEEE FP64.
+ */
+#ifndef SMCRT_ORACLE_H
+#define SMCRT_ORACLE_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* primitive kinds (Sec. 2.2, Eq. 3 for the sphere; box, capsule and capped
+ * cylinder are the basic shapes of the Sec. 2.2 gallery) */
+enum { ORC_SPHERE = 0, ORC_BOX = 1, ORC_CAPSULE = 2, ORC_CYLINDER = 3 };
+/* CSG operators (Sec. 2.2: union; gallery panel e: smooth union) */
+enum { ORC_UNION = 0, ORC_SMOOTH_UNION = 1 };
+/* photon sources */
+enum { ORC_SRC_POINT = 0, ORC_SRC_PENCIL = 1, ORC_SRC_DISC = 2, ORC_SRC_RECT = 3 };
+/* trace record types */
+enum {
+  ORC_EV_EMIT = 0, ORC_EV_SCATTER = 1, ORC_EV_ABSORB = 2, ORC_EV_KILL = 3,
+  ORC_EV_REFLECT = 4, ORC_EV_REFRACT = 5, ORC_EV_CROSS = 6, ORC_EV_ESCAPE = 7,
+  ORC_EV_STALL = 8
+};
+
+/* sphere: c[3], r | box: c[3], half[3] | capsule and capped cylinder: a[3], b[3], r */
+typedef struct { int32_t kind; int32_t pad; double p[8]; } orc_prim;
+
+typedef struct {
+  int32_t first_prim, n_prims, op, pad;
+  double k;                       /* smooth-union radius (cm) */
+  double mua, mus, g, n;          /* optical properties (Sec. 2.3) */
+} orc_region;
+
+typedef struct {
+  int32_t n_prims, n_regions;
+  const orc_prim* prims;
+  const orc_region* regions;
+  double n_ambient;               /* refractive index outside every region */
+  double delta;                   /* sphere-tracing surface threshold (cm) */
+  double bb_lo[3], bb_hi[3];      /* simulation volume (escape when outside) */
+  double g_lo[3], g_hi[3];        /* fluence grid extent */
+  int32_t g_dims[3];              /* voxels per axis; 0 in any axis = no grid */
+  int32_t src_kind;
+  double src[8];
+  double w_threshold;             /* roulette threshold on the packet weight */
+  int32_t m_survive;              /* survive with probability 1/m, weight * m */
+  int32_t max_steps;              /* sphere-tracing steps allowed per event */
+  int64_t max_events;             /* events allowed per packet */
+} orc_scene;
+
+typedef struct {
+  double launched, escaped_face[6], roulette_gain, roulette_loss, stalled;
+  uint64_t events, steps, interactions, interfaces, reflections, refractions,
+           crossings, advances, voxel_segments, kills, stalls, escapes;
+} orc_tallies;
+
+typedef struct {
+  uint32_t event, type;
+  int32_t region, pad;
+  double p[3], u[3], w, tau;
+} orc_event;
+
+/* one Philox4x32-10 block (Salmon et al., SC'11) */
+void orc_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]);
+/* the uniform variate (0,1) that a 32-bit word maps to */
+double orc_xi(uint32_t x);
+
+double orc_prim_sdf(const orc_prim* pr, const double p[3]);
+double orc_smooth_union(double a, double b, double k);
+double orc_region_sdf(const orc_scene* s, int r, const double p[3]);
+int orc_region_of(const orc_scene* s, const double p[3]);
+void orc_region_normal(const orc_scene* s, int r, const double p[3], double h, double n[3]);
+double orc_box_sdf(const double lo[3], const double hi[3], const double p[3]);
+
+/* unpolarised Fresnel reflectance; *cos_t gets the transmitted cosine
+ * (0 under total internal reflection, where R = 1) */
+double orc_fresnel(double n1, double n2, double cos_i, double* cos_t);
+double orc_hg_cos(double g, double xi);
+void orc_rotate(double u[3], double cos_t, double phi);
+
+/* adds w * (path length in voxel v) to f[v] for the straight segment a->b;
+ * returns the number of voxel pieces */
+int64_t orc_tally_segment(const orc_scene* s, const double a[3], const double b[3],
+                          double w, double* f);
+
+/* whole-run entry: packets [first, first+n); f (nx*ny*nz, x fastest),
+ * absorbed (n_regions) and t are accumulated into (+=).  Returns 0 or a
+ * negative error code. */
+int orc_run(const orc_scene* s, uint64_t seed, uint64_t first, uint64_t n,
+            int n_threads, double* f, double* absorbed, orc_tallies* t);
+
+/* event records of one packet; returns the number written (<= cap) */
+int orc_trace(const orc_scene* s, uint64_t seed, uint64_t pid, int cap, orc_event* out);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,326 @@
+"""Seeded synthetic scenes and request streams (input data only).
+
+This module is shared by the GPU path, its tests, the benchmark and the CPU
+oracle's tests.  It only describes inputs -- geometry, optical properties,
+sources, grids, seeds -- and holds none of the transport arithmetic.
+
+Scene dictionaries (lengths in cm, coefficients in 1/cm):
+
+  {"name": str,
+   "n_ambient": float,            refractive index outside every region
+   "delta": float,                sphere-tracing surface threshold (Sec. 2.3)
+   "pad": float,                  padding of the simulation volume
+   "prims": [prim, ...],          see below
+   "regions": [{"prims": [i, ...], "op": "union" | "smooth_union", "k": float,
+                "mua": float, "mus": float, "g": float, "n": float}, ...],
+   "source": source,
+   "grid": {"lo": [3], "hi": [3], "dims": [nx, ny, nz]}   (optional),
+   "roulette": {"w_threshold": float, "m": int},
+   "max_steps": int, "max_events": int}
+
+  prim:   {"kind": "sphere",   "c": [3], "r": float}
+          {"kind": "box",      "c": [3], "half": [3]}
+          {"kind": "capsule",  "a": [3], "b": [3], "r": float}
+          {"kind": "cylinder", "a": [3], "b": [3], "r": float}   (flat caps)
+  source: {"kind": "point",  "p": [3]}                             isotropic
+          {"kind": "pencil", "p": [3], "u": [3]}
+          {"kind": "disc",   "c": [3], "r": float, "u": [3]}       top hat, z-plane
+          {"kind": "rect",   "c": [3], "half": [hx, hy], "u": [3]} uniform, z-plane
+
+Later regions take priority where regions overlap; outside every region the
+medium is ambient (no absorption or scattering, index n_ambient).
+"""
+from __future__ import annotations
+
+import copy
+import math
+
+import numpy as np
+
+AIR = 1.0
+ROULETTE = {"w_threshold": 1e-4, "m": 10}
+MAX_STEPS = 100_000
+MAX_EVENTS = 1_000_000
+
+
+def _scene(name, prims, regions, source, grid=None, delta=1e-5, pad=None, n_ambient=AIR):
+    return {
+        "name": name,
+        "n_ambient": n_ambient,
+        "delta": delta,
+        "pad": 10.0 * delta if pad is None else pad,
+        "prims": prims,
+        "regions": regions,
+        "source": source,
+        "grid": grid,
+        "roulette": dict(ROULETTE),
+        "max_steps": MAX_STEPS,
+        "max_events": MAX_EVENTS,
+    }
+
+
+def _region(prims, mua, mus, g, n, op="union", k=0.0):
+    return {"prims": list(prims), "op": op, "k": k, "mua": mua, "mus": mus, "g": g, "n": n}
+
+
+# --------------------------------------------------------------------------
+# the five workload families
+# --------------------------------------------------------------------------
+
+def sphere_scene(n_grid=50):
+    """Homogeneous sphere, r = 1 cm (mu_a 0.1, mu_s 10, g 0.9, n 1.38) in
+    air, isotropic point source at the centre, fluence on n_grid^3 voxels over
+    the sphere's bounding box."""
+    prims = [{"kind": "sphere", "c": [0.0, 0.0, 0.0], "r": 1.0}]
+    regions = [_region([0], 0.1, 10.0, 0.9, 1.38)]
+    grid = {"lo": [-1.0] * 3, "hi": [1.0] * 3, "dims": [n_grid] * 3}
+    return _scene("sphere", prims, regions, {"kind": "point", "p": [0.0, 0.0, 0.0]}, grid)
+
+
+SLAB_LAYERS = (  # (top z, bottom z, mu_a, mu_s, g, n)
+    (0.0, -0.01, 1.0, 100.0, 0.8, 1.5),
+    (-0.01, -0.21, 0.2, 200.0, 0.9, 1.4),
+    (-0.21, -1.21, 0.1, 100.0, 0.9, 1.4),
+)
+
+
+def slab_scene(n_grid=200, layers=SLAB_LAYERS, half_xy=1.0):
+    """Three stacked boxes, 2 x 2 cm laterally, 0.01 / 0.2 / 1 cm thick, top
+    face at z = 0; normally incident pencil beam along -z starting half a pad
+    above the top face; fluence on n_grid^3 voxels over the tissue."""
+    prims, regions = [], []
+    for i, (top, bot, mua, mus, g, n) in enumerate(layers):
+        prims.append({"kind": "box", "c": [0.0, 0.0, 0.5 * (top + bot)],
+                      "half": [half_xy, half_xy, 0.5 * (top - bot)]})
+        regions.append(_region([i], mua, mus, g, n))
+    z_top, z_bot = layers[0][0], layers[-1][1]
+    grid = {"lo": [-half_xy, -half_xy, z_bot], "hi": [half_xy, half_xy, z_top], "dims": [n_grid] * 3}
+    sc = _scene("slab", prims, regions, None, grid)
+    sc["source"] = {"kind": "pencil", "p": [0.0, 0.0, z_top + 0.5 * sc["pad"]], "u": [0.0, 0.0, -1.0]}
+    return sc
+
+
+def cylinder_scene(n_grid=256):
+    """1 cm tissue cube (mu_a 0.2, mu_s 100, g 0.9, n 1.38) holding a capped
+    cylinder vessel of radius 0.05 cm and length 0.8 cm (mu_a 20, mu_s 400,
+    g 0.98, n 1.4) 0.2 cm below the top face, perpendicular to the beam;
+    tissue = smooth union (k = 0.01 cm) of the cube and the vessel; top-hat
+    beam of radius 0.1 cm along -z."""
+    prims = [
+        {"kind": "box", "c": [0.0, 0.0, 0.0], "half": [0.5, 0.5, 0.5]},
+        {"kind": "cylinder", "a": [-0.4, 0.0, 0.3], "b": [0.4, 0.0, 0.3], "r": 0.05},
+    ]
+    regions = [
+        _region([0, 1], 0.2, 100.0, 0.9, 1.38, op="smooth_union", k=0.01),
+        _region([1], 20.0, 400.0, 0.98, 1.4),
+    ]
+    grid = {"lo": [-0.5] * 3, "hi": [0.5] * 3, "dims": [n_grid] * 3}
+    sc = _scene("cylinder", prims, regions, None, grid)
+    sc["source"] = {"kind": "disc", "c": [0.0, 0.0, 0.5 + 0.5 * sc["pad"]], "r": 0.1,
+                    "u": [0.0, 0.0, -1.0]}
+    return sc
+
+
+def vessel_tree(seed, n_caps=2000, side=0.2, r_min=5e-4, r_max=5e-3,
+                angle_deg=(20.0, 60.0), length_per_radius=8.0):
+    """Seeded random branching tree of capsules inside the cube [0, side]^3.
+
+    Roots start at the centre of the top face pointing -z (later roots at
+    random points of the top face if a tree dies out).  Breadth first, every
+    capsule end spawns two children at branch angles uniform in angle_deg
+    and opposite random azimuths.  Radii are log-uniform in [r_min, r_max],
+    lengths length_per_radius * radius; a child is shortened to stay inside
+    the cube (one radius from every face) and dropped if that leaves less
+    than one radius.  Returns a list of (a, b, r)."""
+    rng = np.random.default_rng(seed)
+    lo, hi = 0.0, side
+    caps = []
+
+    def inside(x, r):
+        return np.all(x >= lo + r) and np.all(x <= hi - r)
+
+    def clip_length(a, d, length, r):
+        # largest t <= length with a + t d inside [lo + r, hi - r]^3
+        t = length
+        for i in range(3):
+            if d[i] > 0:
+                t = min(t, (hi - r - a[i]) / d[i])
+            elif d[i] < 0:
+                t = min(t, (lo + r - a[i]) / d[i])
+        return t
+
+    def new_root(first):
+        r = float(math.exp(rng.uniform(math.log(r_min), math.log(r_max))))
+        if first:
+            a = np.array([0.5 * side, 0.5 * side, hi - r])
+        else:
+            a = np.array([rng.uniform(lo + r, hi - r), rng.uniform(lo + r, hi - r), hi - r])
+        return [(a, np.array([0.0, 0.0, -1.0]))]
+
+    queue = new_root(True)
+    while len(caps) < n_caps:
+        if not queue:
+            queue = new_root(False)
+        a, d = queue.pop(0)
+        r = float(math.exp(rng.uniform(math.log(r_min), math.log(r_max))))
+        if not inside(a, r):
+            continue
+        length = clip_length(a, d, length_per_radius * r, r)
+        if length < r:
+            continue
+        b = a + length * d
+        caps.append((a.tolist(), b.tolist(), r))
+        # two children
+        d = d / np.linalg.norm(d)
+        helper = np.array([1.0, 0.0, 0.0]) if abs(d[0]) < 0.9 else np.array([0.0, 1.0, 0.0])
+        e1 = np.cross(d, helper)
+        e1 /= np.linalg.norm(e1)
+        e2 = np.cross(d, e1)
+        az = rng.uniform(0.0, 2.0 * math.pi)
+        for k in range(2):
+            th = math.radians(rng.uniform(*angle_deg))
+            phi = az + k * math.pi
+            nd = math.cos(th) * d + math.sin(th) * (math.cos(phi) * e1 + math.sin(phi) * e2)
+            queue.append((b.copy(), nd / np.linalg.norm(nd)))
+    return caps[:n_caps]
+
+
+TISSUE = (0.2, 100.0, 0.9, 1.38)
+BLOOD = (20.0, 400.0, 0.98, 1.4)
+
+
+def vessel_scene(seed, mus_scale=1.0, n_caps=2000, n_grid=128, side=0.2):
+    """Tissue cube [0, 0.2]^3 cm holding a union of n_caps capsules (the
+    seeded vessel tree), tissue and blood properties of the cylinder scene
+    with mu_s scaled by mus_scale, uniform illumination of the top face."""
+    caps = vessel_tree(seed, n_caps=n_caps, side=side)
+    prims = [{"kind": "box", "c": [0.5 * side] * 3, "half": [0.5 * side] * 3}]
+    prims += [{"kind": "capsule", "a": a, "b": b, "r": r} for a, b, r in caps]
+    t, bl = TISSUE, BLOOD
+    regions = [
+        _region([0], t[0], t[1] * mus_scale, t[2], t[3]),
+        _region(range(1, 1 + len(caps)), bl[0], bl[1] * mus_scale, bl[2], bl[3]),
+    ]
+    grid = {"lo": [0.0] * 3, "hi": [side] * 3, "dims": [n_grid] * 3}
+    sc = _scene("vessels", prims, regions, None, grid, delta=1e-6)
+    sc["source"] = {"kind": "rect", "c": [0.5 * side, 0.5 * side, side + 0.5 * sc["pad"]],
+                    "half": [0.5 * side, 0.5 * side], "u": [0.0, 0.0, -1.0]}
+    sc["seed_tree"] = int(seed)
+    sc["accel_cells"] = [32, 32, 32]
+    return sc
+
+
+def vessel_batch(n_scenes=64, base_seed=1000, n_caps=2000, n_grid=128):
+    """n_scenes vessel scenes with seeds base_seed + i and mu_s scaled
+    log-uniformly in [0.5, 2]."""
+    rng = np.random.default_rng(base_seed)
+    scales = np.exp(rng.uniform(math.log(0.5), math.log(2.0), size=n_scenes))
+    return [vessel_scene(base_seed + i, float(scales[i]), n_caps=n_caps, n_grid=n_grid)
+            for i in range(n_scenes)]
+
+
+def request_stream(seed, n_requests=1000, rate_hz=10.0, families=("sphere", "slab", "cylinder", "vessels"),
+                   packets=(1e4, 1e7), grid_sides=(32, 64, 128, 256), vessel_caps=2000):
+    """Poisson stream of requests: (arrival time s, scene, seed, n_packets).
+    Family uniform over the given ones; every region's mu_a log-uniform in
+    [0.01, 5], mu_s log-uniform in [10, 500], g uniform in [0.7, 0.99], n
+    uniform in [1.33, 1.5]; packets log-uniform; grid side uniform over
+    grid_sides."""
+    rng = np.random.default_rng(seed)
+    t = 0.0
+    out = []
+    for i in range(n_requests):
+        t += float(rng.exponential(1.0 / rate_hz))
+        fam = families[int(rng.integers(len(families)))]
+        side = int(grid_sides[int(rng.integers(len(grid_sides)))])
+        if fam == "sphere":
+            sc = sphere_scene(side)
+        elif fam == "slab":
+            sc = slab_scene(side)
+        elif fam == "cylinder":
+            sc = cylinder_scene(side)
+        else:
+            sc = vessel_scene(int(rng.integers(1 << 30)), 1.0, n_caps=vessel_caps, n_grid=side)
+        for rg in sc["regions"]:
+            rg["mua"] = float(math.exp(rng.uniform(math.log(0.01), math.log(5.0))))
+            rg["mus"] = float(math.exp(rng.uniform(math.log(10.0), math.log(500.0))))
+            rg["g"] = float(rng.uniform(0.7, 0.99))
+            rg["n"] = float(rng.uniform(1.33, 1.5))
+        n_pk = int(round(math.exp(rng.uniform(math.log(packets[0]), math.log(packets[1])))))
+        out.append({"id": i, "arrival": t, "scene": sc,
+                    "seed": int(rng.integers(1 << 62)), "n_packets": n_pk})
+    return out
+
+
+# --------------------------------------------------------------------------
+# validation scenes (closed-form special cases)
+# --------------------------------------------------------------------------
+
+def beer_lambert_slab(mua=2.0, thickness=0.5, n=1.5, half_xy=50.0):
+    """Non-scattering slab at normal incidence: a box of the given thickness
+    (top face z = 0) under a pencil beam along -z."""
+    prims = [{"kind": "box", "c": [0.0, 0.0, -0.5 * thickness], "half": [half_xy, half_xy, 0.5 * thickness]}]
+    regions = [_region([0], mua, 0.0, 0.0, n)]
+    grid = {"lo": [-half_xy, -half_xy, -thickness], "hi": [half_xy, half_xy, 0.0], "dims": [1, 1, 50]}
+    sc = _scene("beer_lambert", prims, regions, None, grid)
+    sc["source"] = {"kind": "pencil", "p": [0.0, 0.0, 0.5 * sc["pad"]], "u": [0.0, 0.0, -1.0]}
+    return sc
+
+
+def stack_scene(layers, half_xy=50.0):
+    """Non-scattering stack of boxes; layers = [(thickness, mua, n), ...] from
+    the top face z = 0 down; pencil beam along -z."""
+    prims, regions, z = [], [], 0.0
+    for i, (th, mua, n) in enumerate(layers):
+        prims.append({"kind": "box", "c": [0.0, 0.0, z - 0.5 * th], "half": [half_xy, half_xy, 0.5 * th]})
+        regions.append(_region([i], mua, 0.0, 0.0, n))
+        z -= th
+    sc = _scene("stack", prims, regions, None, None)
+    sc["source"] = {"kind": "pencil", "p": [0.0, 0.0, 0.5 * sc["pad"]], "u": [0.0, 0.0, -1.0]}
+    return sc
+
+
+def absorbing_sphere(mua=1.0, r=1.0, n=1.0, n_grid=0):
+    """Non-scattering sphere with an isotropic point source at its centre."""
+    prims = [{"kind": "sphere", "c": [0.0, 0.0, 0.0], "r": r}]
+    regions = [_region([0], mua, 0.0, 0.0, n)]
+    grid = {"lo": [-r] * 3, "hi": [r] * 3, "dims": [n_grid] * 3} if n_grid else None
+    return _scene("absorbing_sphere", prims, regions, {"kind": "point", "p": [0.0, 0.0, 0.0]}, grid)
+
+
+def scattering_sphere(tau, r=0.5, n=1.0):
+    """Eq. 4 test: purely scattering (mu_a = 0), isotropic (g = 0),
+    index-matched sphere of radius r and radial optical depth tau, point
+    source at the centre."""
+    prims = [{"kind": "sphere", "c": [0.0, 0.0, 0.0], "r": r}]
+    regions = [_region([0], 0.0, tau / r, 0.0, n)]
+    return _scene("scattering_sphere", prims, regions, {"kind": "point", "p": [0.0, 0.0, 0.0]}, None)
+
+
+def semi_infinite_slab(mua, mus_reduced, g=0.9, n=1.38, thickness=4.0, half_xy=50.0, nz=400):
+    """Sec. 3.1 validation medium: a slab much wider and deeper than the
+    penetration depth, light incident along -z.  A pencil beam with one
+    lateral bin gives the laterally integrated depth profile, which equals
+    the profile under uniform incidence on an infinite slab."""
+    mus = mus_reduced / (1.0 - g)
+    prims = [{"kind": "box", "c": [0.0, 0.0, -0.5 * thickness], "half": [half_xy, half_xy, 0.5 * thickness]}]
+    regions = [_region([0], mua, mus, g, n)]
+    grid = {"lo": [-half_xy, -half_xy, -thickness], "hi": [half_xy, half_xy, 0.0], "dims": [1, 1, nz]}
+    sc = _scene("semi_infinite", prims, regions, None, grid)
+    sc["source"] = {"kind": "pencil", "p": [0.0, 0.0, 0.5 * sc["pad"]], "u": [0.0, 0.0, -1.0]}
+    return sc
+
+
+def with_grid(scene, dims, lo=None, hi=None):
+    sc = copy.deepcopy(scene)
+    g = sc.get("grid") or {}
+    sc["grid"] = {"lo": list(lo if lo is not None else g["lo"]), "hi": list(hi if hi is not None else g["hi"]),
+                  "dims": list(dims)}
+    return sc
+
+
+WORKLOADS = {
+    "sphere": sphere_scene,
+    "slab": slab_scene,
+    "cylinder": cylinder_scene,
+}
