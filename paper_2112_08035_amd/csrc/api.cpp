@@ -1,0 +1,610 @@
+// api.cpp -- host side of libsmcrt: scene building and validation, packing of
+// the device tables, engines, and the C entry points declared in smcrt.h.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/smcrt.h"
+#include "launch.h"
+#include "layout.h"
+
+using namespace smcrt;
+
+// ------------------------------------------------------------------ errors
+
+static thread_local std::string g_last_error;
+
+static smcrt_status fail(smcrt_status st, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof(buf), fmt, ap);
+  va_end(ap);
+  g_last_error = buf;
+  return st;
+}
+
+static smcrt_status hip_fail(hipError_t e, const char* what) {
+  return fail(SMCRT_E_HIP, "%s: %s", what, hipGetErrorString(e));
+}
+
+#define HIP_TRY(call, what)                  \
+  do {                                       \
+    hipError_t e_ = (call);                  \
+    if (e_ != hipSuccess) return hip_fail(e_, what); \
+  } while (0)
+
+extern "C" const char* smcrt_last_error(void) { return g_last_error.c_str(); }
+extern "C" int smcrt_abi_version(void) { return SMCRT_ABI_VERSION; }
+
+// ------------------------------------------------------------------ scenes
+
+struct HostPrim {
+  int kind;
+  double p[7];
+};
+struct HostRegion {
+  std::vector<int32_t> prims;
+  int op;
+  double k, mua, mus, g, n;
+};
+
+struct smcrt_scene {
+  double n_ambient = 1.0, delta = 1e-5, pad = 1e-4;
+  std::vector<HostPrim> prims;
+  std::vector<HostRegion> regions;
+  bool has_source = false;
+  int src_kind = 0;
+  double src[8] = {0};
+  bool grid_set = false;
+  double g_lo[3] = {0}, g_hi[3] = {0};
+  int32_t g_dims[3] = {1, 1, 1};
+  double w_threshold = 1e-4;
+  int32_t m_survive = 10;
+  int32_t max_steps = 100000;
+  int64_t max_events = 1000000;
+  // packed device tables (rebuilt when dirty)
+  bool dirty = true;
+  std::vector<unsigned char> blob;
+};
+
+static bool finite3(const double* v) { return std::isfinite(v[0]) && std::isfinite(v[1]) && std::isfinite(v[2]); }
+
+extern "C" smcrt_status smcrt_scene_create(smcrt_scene** out, double n_ambient, double delta, double pad) {
+  if (!out) return fail(SMCRT_E_INVALID, "scene_create: out is NULL");
+  if (!(n_ambient > 0) || !std::isfinite(n_ambient)) return fail(SMCRT_E_INVALID, "scene_create: n_ambient must be > 0");
+  if (!(delta > 0) || !std::isfinite(delta)) return fail(SMCRT_E_INVALID, "scene_create: delta must be > 0");
+  if (!(pad >= 0) || !std::isfinite(pad)) return fail(SMCRT_E_INVALID, "scene_create: pad must be >= 0");
+  smcrt_scene* s = new (std::nothrow) smcrt_scene();
+  if (!s) return fail(SMCRT_E_NOMEM, "scene_create: out of host memory");
+  s->n_ambient = n_ambient;
+  s->delta = delta;
+  s->pad = pad;
+  *out = s;
+  return SMCRT_OK;
+}
+
+extern "C" smcrt_status smcrt_scene_destroy(smcrt_scene* s) {
+  delete s;
+  return SMCRT_OK;
+}
+
+extern "C" smcrt_status smcrt_scene_add_primitive(smcrt_scene* s, int kind, const double* params, int n_params,
+                                                  int32_t* out_prim) {
+  if (!s || !params) return fail(SMCRT_E_INVALID, "add_primitive: NULL argument");
+  static const int need[4] = {4, 6, 7, 7};
+  if (kind < 0 || kind > 3) return fail(SMCRT_E_INVALID, "add_primitive: unknown kind %d", kind);
+  if (n_params != need[kind]) return fail(SMCRT_E_INVALID, "add_primitive: kind %d takes %d params, got %d", kind, need[kind], n_params);
+  for (int i = 0; i < n_params; ++i)
+    if (!std::isfinite(params[i])) return fail(SMCRT_E_INVALID, "add_primitive: param %d is not finite", i);
+  if ((int)s->prims.size() >= kMaxPrims) return fail(SMCRT_E_INVALID, "add_primitive: more than %d primitives", kMaxPrims);
+  HostPrim p;
+  p.kind = kind;
+  std::memset(p.p, 0, sizeof(p.p));
+  std::memcpy(p.p, params, sizeof(double) * n_params);
+  if (kind == kSphere && !(p.p[3] > 0)) return fail(SMCRT_E_INVALID, "add_primitive: sphere radius must be > 0");
+  if (kind == kBox && !(p.p[3] > 0 && p.p[4] > 0 && p.p[5] > 0))
+    return fail(SMCRT_E_INVALID, "add_primitive: box half extents must be > 0");
+  if (kind == kCapsule || kind == kCylinder) {
+    double d[3] = {p.p[3] - p.p[0], p.p[4] - p.p[1], p.p[5] - p.p[2]};
+    if (!(d[0] * d[0] + d[1] * d[1] + d[2] * d[2] > 0)) return fail(SMCRT_E_INVALID, "add_primitive: segment ends must differ");
+    if (!(p.p[6] > 0)) return fail(SMCRT_E_INVALID, "add_primitive: radius must be > 0");
+  }
+  s->prims.push_back(p);
+  s->dirty = true;
+  if (out_prim) *out_prim = (int32_t)s->prims.size() - 1;
+  return SMCRT_OK;
+}
+
+extern "C" smcrt_status smcrt_scene_add_region(smcrt_scene* s, const int32_t* prims, int n_prims, int op, double k_cm,
+                                               double mu_a, double mu_s, double g, double n, int32_t* out_region) {
+  if (!s || !prims) return fail(SMCRT_E_INVALID, "add_region: NULL argument");
+  if ((int)s->regions.size() >= kMaxRegions) return fail(SMCRT_E_INVALID, "add_region: at most %d regions", kMaxRegions);
+  if (n_prims < 1) return fail(SMCRT_E_INVALID, "add_region: needs at least one primitive");
+  for (int i = 0; i < n_prims; ++i)
+    if (prims[i] < 0 || prims[i] >= (int32_t)s->prims.size())
+      return fail(SMCRT_E_INVALID, "add_region: primitive index %d out of range", prims[i]);
+  if (op != SMCRT_OP_UNION && op != SMCRT_OP_SMOOTH_UNION) return fail(SMCRT_E_INVALID, "add_region: unknown op %d", op);
+  if (op == SMCRT_OP_SMOOTH_UNION && !(k_cm > 0 && std::isfinite(k_cm)))
+    return fail(SMCRT_E_INVALID, "add_region: smooth union needs k > 0");
+  if (!(mu_a >= 0 && std::isfinite(mu_a)) || !(mu_s >= 0 && std::isfinite(mu_s)) || !(mu_a + mu_s > 0))
+    return fail(SMCRT_E_INVALID, "add_region: need mu_a >= 0, mu_s >= 0, mu_a + mu_s > 0");
+  if (!(g > -1 && g < 1)) return fail(SMCRT_E_INVALID, "add_region: need -1 < g < 1");
+  if (!(n > 0 && std::isfinite(n))) return fail(SMCRT_E_INVALID, "add_region: need n > 0");
+  HostRegion r;
+  r.prims.assign(prims, prims + n_prims);
+  r.op = op;
+  r.k = op == SMCRT_OP_SMOOTH_UNION ? k_cm : 0.0;
+  r.mua = mu_a;
+  r.mus = mu_s;
+  r.g = g;
+  r.n = n;
+  s->regions.push_back(r);
+  s->dirty = true;
+  if (out_region) *out_region = (int32_t)s->regions.size() - 1;
+  return SMCRT_OK;
+}
+
+extern "C" smcrt_status smcrt_scene_set_source(smcrt_scene* s, int kind, const double* params, int n_params) {
+  if (!s || !params) return fail(SMCRT_E_INVALID, "set_source: NULL argument");
+  static const int need[4] = {3, 6, 7, 8};
+  if (kind < 0 || kind > 3) return fail(SMCRT_E_INVALID, "set_source: unknown kind %d", kind);
+  if (n_params != need[kind]) return fail(SMCRT_E_INVALID, "set_source: kind %d takes %d params, got %d", kind, need[kind], n_params);
+  for (int i = 0; i < n_params; ++i)
+    if (!std::isfinite(params[i])) return fail(SMCRT_E_INVALID, "set_source: param %d is not finite", i);
+  double v[8] = {0};
+  std::memcpy(v, params, sizeof(double) * n_params);
+  int du = kind == kPencil ? 3 : kind == kDisc ? 4 : kind == kRect ? 5 : -1;
+  if (kind == kDisc && !(v[3] > 0)) return fail(SMCRT_E_INVALID, "set_source: disc radius must be > 0");
+  if (kind == kRect && !(v[3] > 0 && v[4] > 0)) return fail(SMCRT_E_INVALID, "set_source: rectangle half sides must be > 0");
+  if (du >= 0) {
+    double l = std::sqrt(v[du] * v[du] + v[du + 1] * v[du + 1] + v[du + 2] * v[du + 2]);
+    if (!(l > 0)) return fail(SMCRT_E_INVALID, "set_source: direction must be non-zero");
+    for (int i = 0; i < 3; ++i) v[du + i] /= l;
+  }
+  s->src_kind = kind;
+  std::memcpy(s->src, v, sizeof(v));
+  s->has_source = true;
+  s->dirty = true;
+  return SMCRT_OK;
+}
+
+extern "C" smcrt_status smcrt_scene_set_grid(smcrt_scene* s, const double lo[3], const double hi[3], const int32_t dims[3]) {
+  if (!s || !lo || !hi || !dims) return fail(SMCRT_E_INVALID, "set_grid: NULL argument");
+  if (!finite3(lo) || !finite3(hi)) return fail(SMCRT_E_INVALID, "set_grid: bounds must be finite");
+  for (int i = 0; i < 3; ++i) {
+    if (!(hi[i] > lo[i])) return fail(SMCRT_E_INVALID, "set_grid: need lo < hi on every axis");
+    if (dims[i] < 0 || dims[i] > 4096) return fail(SMCRT_E_INVALID, "set_grid: dims must be in [0, 4096]");
+  }
+  if ((double)dims[0] * dims[1] * dims[2] > 2147483647.0) return fail(SMCRT_E_INVALID, "set_grid: more than 2^31-1 voxels");
+  std::memcpy(s->g_lo, lo, sizeof(s->g_lo));
+  std::memcpy(s->g_hi, hi, sizeof(s->g_hi));
+  std::memcpy(s->g_dims, dims, sizeof(s->g_dims));
+  s->grid_set = true;
+  s->dirty = true;
+  return SMCRT_OK;
+}
+
+extern "C" smcrt_status smcrt_scene_set_roulette(smcrt_scene* s, double w_threshold, int32_t m_survive) {
+  if (!s) return fail(SMCRT_E_INVALID, "set_roulette: NULL scene");
+  if (!(w_threshold >= 0 && w_threshold < 1)) return fail(SMCRT_E_INVALID, "set_roulette: need 0 <= w_threshold < 1");
+  if (m_survive < 1) return fail(SMCRT_E_INVALID, "set_roulette: need m_survive >= 1");
+  s->w_threshold = w_threshold;
+  s->m_survive = m_survive;
+  s->dirty = true;
+  return SMCRT_OK;
+}
+
+extern "C" smcrt_status smcrt_scene_set_limits(smcrt_scene* s, int32_t max_steps, int64_t max_events) {
+  if (!s) return fail(SMCRT_E_INVALID, "set_limits: NULL scene");
+  if (max_steps < 1 || max_events < 1) return fail(SMCRT_E_INVALID, "set_limits: limits must be >= 1");
+  if (max_events > 0xFFFFFFF0LL) return fail(SMCRT_E_INVALID, "set_limits: max_events must fit the 32-bit event counter");
+  s->max_steps = max_steps;
+  s->max_events = max_events;
+  s->dirty = true;
+  return SMCRT_OK;
+}
+
+// conservative box of a primitive
+static void prim_box(const HostPrim& p, double lo[3], double hi[3]) {
+  for (int i = 0; i < 3; ++i) {
+    switch (p.kind) {
+      case kSphere: lo[i] = p.p[i] - p.p[3]; hi[i] = p.p[i] + p.p[3]; break;
+      case kBox: lo[i] = p.p[i] - p.p[3 + i]; hi[i] = p.p[i] + p.p[3 + i]; break;
+      default:
+        lo[i] = std::min(p.p[i], p.p[3 + i]) - p.p[6];
+        hi[i] = std::max(p.p[i], p.p[3 + i]) + p.p[6];
+    }
+  }
+}
+
+// emission points of the source (for the simulation volume)
+static void source_box(const smcrt_scene* s, double lo[3], double hi[3]) {
+  const double* v = s->src;
+  for (int i = 0; i < 3; ++i) lo[i] = hi[i] = v[i];
+  if (s->src_kind == kDisc) {
+    for (int i = 0; i < 2; ++i) { lo[i] -= v[3]; hi[i] += v[3]; }
+  } else if (s->src_kind == kRect) {
+    for (int i = 0; i < 2; ++i) { lo[i] -= v[3 + i]; hi[i] += v[3 + i]; }
+  }
+}
+
+static void scene_bbox(const smcrt_scene* s, double lo[3], double hi[3], bool with_source, double pad) {
+  for (int i = 0; i < 3; ++i) { lo[i] = 1e300; hi[i] = -1e300; }
+  for (const HostPrim& p : s->prims) {
+    double a[3], b[3];
+    prim_box(p, a, b);
+    for (int i = 0; i < 3; ++i) { lo[i] = std::min(lo[i], a[i]); hi[i] = std::max(hi[i], b[i]); }
+  }
+  if (with_source) {
+    double a[3], b[3];
+    source_box(s, a, b);
+    for (int i = 0; i < 3; ++i) { lo[i] = std::min(lo[i], a[i]); hi[i] = std::max(hi[i], b[i]); }
+  }
+  for (int i = 0; i < 3; ++i) { lo[i] -= pad; hi[i] += pad; }
+}
+
+static smcrt_status check_complete(const smcrt_scene* s) {
+  if (s->regions.empty()) return fail(SMCRT_E_INVALID, "scene has no region");
+  if (!s->has_source) return fail(SMCRT_E_INVALID, "scene has no source");
+  double lo[3], hi[3];
+  scene_bbox(s, lo, hi, true, s->pad);
+  const double* v = s->src;
+  for (int i = 0; i < 3; ++i)
+    if (!(v[i] >= lo[i] && v[i] <= hi[i])) return fail(SMCRT_E_INVALID, "source outside the simulation volume");
+  return SMCRT_OK;
+}
+
+template <typename T>
+static void pack_prim(const HostPrim& h, Prim<T>& o) {
+  std::memset(&o, 0, sizeof(o));
+  o.kind = h.kind;
+  const double* p = h.p;
+  switch (h.kind) {
+    case kSphere:
+      for (int i = 0; i < 4; ++i) o.v[i] = (T)p[i];
+      break;
+    case kBox:
+      for (int i = 0; i < 6; ++i) o.v[i] = (T)p[i];
+      break;
+    case kCapsule: {
+      double ba[3] = {p[3] - p[0], p[4] - p[1], p[5] - p[2]};
+      double bb = ba[0] * ba[0] + ba[1] * ba[1] + ba[2] * ba[2];
+      for (int i = 0; i < 3; ++i) { o.v[i] = (T)p[i]; o.v[3 + i] = (T)ba[i]; }
+      o.v[6] = (T)(1.0 / bb);
+      o.v[7] = (T)p[6];
+      break;
+    }
+    case kCylinder: {
+      double ba[3] = {p[3] - p[0], p[4] - p[1], p[5] - p[2]};
+      double L = std::sqrt(ba[0] * ba[0] + ba[1] * ba[1] + ba[2] * ba[2]);
+      for (int i = 0; i < 3; ++i) { o.v[i] = (T)p[i]; o.v[3 + i] = (T)(ba[i] / L); }
+      o.v[6] = (T)L;
+      o.v[7] = (T)(0.5 * L);
+      o.v[8] = (T)p[6];
+      break;
+    }
+  }
+}
+
+static void fill_region(Region& r, double mua, double mus, double g, double n, double k, int op, int first, int count) {
+  std::memset(&r, 0, sizeof(r));
+  r.first = first;
+  r.count = count;
+  r.op = op;
+  r.k = k;
+  r.inv_k = k > 0 ? 1.0 / k : 0.0;
+  r.mua = mua;
+  r.mus = mus;
+  r.mut = mua + mus;
+  r.inv_mut = r.mut > 0 ? 1.0 / r.mut : 0.0;
+  r.absorb = r.mut > 0 ? mua / r.mut : 0.0;
+  r.g = g;
+  r.n = n;
+  r.iso = std::fabs(g) < 1e-6;
+  r.hg_a = 1 + g * g;
+  r.hg_b = 1 - g * g;
+  r.hg_c = 1 - g;
+  r.hg_d = 2 * g;
+  r.hg_e = r.iso ? 0.0 : 1.0 / (2 * g);
+  r.kf = (float)r.k;
+  r.inv_kf = (float)r.inv_k;
+  r.mutf = (float)r.mut;
+  r.inv_mutf = (float)r.inv_mut;
+  r.gf = (float)g;
+  r.hg_af = (float)r.hg_a;
+  r.hg_bf = (float)r.hg_b;
+  r.hg_cf = (float)r.hg_c;
+  r.hg_df = (float)r.hg_d;
+  r.hg_ef = (float)r.hg_e;
+}
+
+static smcrt_status pack(smcrt_scene* s) {
+  if (!s->dirty) return SMCRT_OK;
+  smcrt_status st = check_complete(s);
+  if (st != SMCRT_OK) return st;
+  // primitives in region order, each region's list contiguous
+  std::vector<int> order;
+  for (const HostRegion& r : s->regions) order.insert(order.end(), r.prims.begin(), r.prims.end());
+  size_t np = order.size();
+  size_t off_d = (sizeof(SceneHeader) + 255) & ~size_t(255);
+  size_t off_f = (off_d + np * sizeof(PrimD) + 255) & ~size_t(255);
+  size_t bytes = off_f + np * sizeof(PrimF);
+  s->blob.assign(bytes, 0);
+  SceneHeader* h = reinterpret_cast<SceneHeader*>(s->blob.data());
+  PrimD* pd = reinterpret_cast<PrimD*>(s->blob.data() + off_d);
+  PrimF* pf = reinterpret_cast<PrimF*>(s->blob.data() + off_f);
+  for (size_t i = 0; i < np; ++i) {
+    pack_prim(s->prims[order[i]], pd[i]);
+    pack_prim(s->prims[order[i]], pf[i]);
+  }
+  h->n_prims = (int32_t)np;
+  h->n_regions = (int32_t)s->regions.size();
+  int first = 0;
+  for (size_t r = 0; r < s->regions.size(); ++r) {
+    const HostRegion& hr = s->regions[r];
+    fill_region(h->reg[r], hr.mua, hr.mus, hr.g, hr.n, hr.k, hr.op, first, (int)hr.prims.size());
+    first += (int)hr.prims.size();
+  }
+  fill_region(h->reg[s->regions.size()], 0.0, 0.0, 0.0, s->n_ambient, 0.0, kUnion, 0, 0);
+  h->delta = s->delta;
+  h->deltaf = (float)s->delta;
+  h->h_normal = 1e-2 * s->delta;
+  h->snap_cos = 0.1;
+  h->offset = 2.0 * s->delta;
+  double lo[3], hi[3];
+  scene_bbox(s, lo, hi, true, s->pad);
+  for (int i = 0; i < 3; ++i) {
+    h->bb_c[i] = 0.5 * (lo[i] + hi[i]);
+    h->bb_h[i] = 0.5 * (hi[i] - lo[i]);
+    h->bb_cf[i] = (float)h->bb_c[i];
+    h->bb_hf[i] = (float)h->bb_h[i];
+  }
+  double glo[3], ghi[3];
+  int32_t gd[3];
+  if (s->grid_set) {
+    std::memcpy(glo, s->g_lo, sizeof(glo));
+    std::memcpy(ghi, s->g_hi, sizeof(ghi));
+    std::memcpy(gd, s->g_dims, sizeof(gd));
+  } else {
+    scene_bbox(s, glo, ghi, false, 0.0);
+    gd[0] = gd[1] = gd[2] = 1;
+  }
+  h->has_grid = gd[0] > 0 && gd[1] > 0 && gd[2] > 0;
+  for (int i = 0; i < 3; ++i) {
+    h->g_dims[i] = gd[i];
+    h->g_lo[i] = glo[i];
+    h->g_d[i] = gd[i] > 0 ? (ghi[i] - glo[i]) / gd[i] : 1.0;
+    h->g_inv_d[i] = gd[i] > 0 ? gd[i] / (ghi[i] - glo[i]) : 1.0;
+    h->g_lof[i] = (float)glo[i];
+    h->g_inv_df[i] = (float)h->g_inv_d[i];
+  }
+  h->src_kind = s->src_kind;
+  std::memcpy(h->src, s->src, sizeof(h->src));
+  h->w_threshold = s->w_threshold;
+  h->m_survive = s->m_survive;
+  h->m_d = (double)s->m_survive;
+  h->inv_m = 1.0 / (double)s->m_survive;
+  h->max_steps = s->max_steps;
+  h->max_events = s->max_events;
+  h->prim_offset_d = off_d;
+  h->prim_offset_f = off_f;
+  h->blob_bytes = bytes;
+  s->dirty = false;
+  return SMCRT_OK;
+}
+
+extern "C" smcrt_status smcrt_scene_info(const smcrt_scene* s, int32_t* n_regions, int32_t* n_prims, double bb_lo[3],
+                                         double bb_hi[3]) {
+  if (!s) return fail(SMCRT_E_INVALID, "scene_info: NULL scene");
+  if (n_regions) *n_regions = (int32_t)s->regions.size();
+  if (n_prims) *n_prims = (int32_t)s->prims.size();
+  if (bb_lo || bb_hi) {
+    if (!s->has_source) return fail(SMCRT_E_STATE, "scene_info: set a source before asking for the volume");
+    double lo[3], hi[3];
+    scene_bbox(s, lo, hi, true, s->pad);
+    if (bb_lo) std::memcpy(bb_lo, lo, sizeof(lo));
+    if (bb_hi) std::memcpy(bb_hi, hi, sizeof(hi));
+  }
+  return SMCRT_OK;
+}
+
+// ------------------------------------------------------------------ engines
+
+struct smcrt_engine {
+  int device = 0;
+  int n_cu = 0;
+  smcrt_opts opts;
+  void* d_blob = nullptr;
+  size_t blob_cap = 0;
+  unsigned long long* d_counter = nullptr;
+};
+
+static void default_opts(smcrt_opts* o) {
+  std::memset(o, 0, sizeof(*o));
+  o->precision = SMCRT_PREC_F32;
+  o->block = 256;
+  o->blocks_per_cu = 0;  // 0 = as many as fit
+  o->refill_min = 16;
+  o->surface_min = 8;
+}
+
+static smcrt_status check_opts(const smcrt_opts* o) {
+  if (o->precision != SMCRT_PREC_F32 && o->precision != SMCRT_PREC_F64)
+    return fail(SMCRT_E_INVALID, "opts: unknown precision %d", o->precision);
+  if (o->block < 64 || o->block > 1024 || o->block % 64) return fail(SMCRT_E_INVALID, "opts: block must be a multiple of 64 in [64, 1024]");
+  if (o->blocks_per_cu < 0 || o->blocks_per_cu > 32) return fail(SMCRT_E_INVALID, "opts: blocks_per_cu must be in [0, 32]");
+  if (o->refill_min < 1 || o->refill_min > 64) return fail(SMCRT_E_INVALID, "opts: refill_min must be in [1, 64]");
+  if (o->surface_min < 1 || o->surface_min > 64) return fail(SMCRT_E_INVALID, "opts: surface_min must be in [1, 64]");
+  return SMCRT_OK;
+}
+
+extern "C" smcrt_status smcrt_engine_create(smcrt_engine** out, int device) {
+  if (!out) return fail(SMCRT_E_INVALID, "engine_create: out is NULL");
+  int count = 0;
+  HIP_TRY(hipGetDeviceCount(&count), "hipGetDeviceCount");
+  if (device < 0 || device >= count) return fail(SMCRT_E_INVALID, "engine_create: device %d not present (%d devices)", device, count);
+  HIP_TRY(hipSetDevice(device), "hipSetDevice");
+  hipDeviceProp_t prop;
+  HIP_TRY(hipGetDeviceProperties(&prop, device), "hipGetDeviceProperties");
+  smcrt_engine* e = new (std::nothrow) smcrt_engine();
+  if (!e) return fail(SMCRT_E_NOMEM, "engine_create: out of host memory");
+  e->device = device;
+  e->n_cu = prop.multiProcessorCount;
+  default_opts(&e->opts);
+  hipError_t err = hipMalloc(&e->d_counter, 256);
+  if (err != hipSuccess) {
+    delete e;
+    return hip_fail(err, "hipMalloc(counter)");
+  }
+  *out = e;
+  return SMCRT_OK;
+}
+
+extern "C" smcrt_status smcrt_engine_destroy(smcrt_engine* e) {
+  if (!e) return SMCRT_OK;
+  hipSetDevice(e->device);
+  hipDeviceSynchronize();
+  if (e->d_blob) hipFree(e->d_blob);
+  if (e->d_counter) hipFree(e->d_counter);
+  delete e;
+  return SMCRT_OK;
+}
+
+extern "C" smcrt_status smcrt_engine_get_opts(const smcrt_engine* e, smcrt_opts* out) {
+  if (!e || !out) return fail(SMCRT_E_INVALID, "engine_get_opts: NULL argument");
+  *out = e->opts;
+  return SMCRT_OK;
+}
+
+extern "C" smcrt_status smcrt_engine_set_opts(smcrt_engine* e, const smcrt_opts* o) {
+  if (!e || !o) return fail(SMCRT_E_INVALID, "engine_set_opts: NULL argument");
+  smcrt_status st = check_opts(o);
+  if (st != SMCRT_OK) return st;
+  e->opts = *o;
+  return SMCRT_OK;
+}
+
+// upload the packed tables of a scene (stream ordered; the host copy is
+// consumed before the call returns because the source is pageable memory)
+static smcrt_status upload(smcrt_engine* e, smcrt_scene* s, hipStream_t st) {
+  smcrt_status r = pack(s);
+  if (r != SMCRT_OK) return r;
+  size_t bytes = s->blob.size();
+  if (bytes > e->blob_cap) {
+    if (e->d_blob) {
+      HIP_TRY(hipStreamSynchronize(st), "hipStreamSynchronize");
+      HIP_TRY(hipFree(e->d_blob), "hipFree");
+      e->d_blob = nullptr;
+      e->blob_cap = 0;
+    }
+    HIP_TRY(hipMalloc(&e->d_blob, bytes), "hipMalloc(scene tables)");
+    e->blob_cap = bytes;
+  }
+  HIP_TRY(hipMemcpyAsync(e->d_blob, s->blob.data(), bytes, hipMemcpyHostToDevice, st), "hipMemcpyAsync(scene tables)");
+  return SMCRT_OK;
+}
+
+static WalkArgs base_args(smcrt_engine* e, const smcrt_scene* s) {
+  WalkArgs a;
+  std::memset(&a, 0, sizeof(a));
+  const SceneHeader* h = reinterpret_cast<const SceneHeader*>(s->blob.data());
+  a.sc = reinterpret_cast<const SceneHeader*>(e->d_blob);
+  a.pd = reinterpret_cast<const PrimD*>((const char*)e->d_blob + h->prim_offset_d);
+  a.pf = reinterpret_cast<const PrimF*>((const char*)e->d_blob + h->prim_offset_f);
+  a.counter = e->d_counter;
+  a.refill_min = e->opts.refill_min;
+  a.surface_min = e->opts.surface_min;
+  return a;
+}
+
+static LaunchCfg launch_cfg(smcrt_engine* e) {
+  LaunchCfg c;
+  c.block = e->opts.block;
+  int per_cu = e->opts.blocks_per_cu;
+  if (per_cu <= 0) per_cu = walk_max_blocks_per_cu(e->opts.precision, c.block);
+  if (per_cu <= 0) per_cu = 1;
+  c.grid = e->n_cu * per_cu;
+  c.refill_min = e->opts.refill_min;
+  c.surface_min = e->opts.surface_min;
+  return c;
+}
+
+extern "C" smcrt_status smcrt_run(smcrt_engine* e, const smcrt_scene* scene, uint64_t seed, uint64_t first_packet,
+                                  uint64_t n_packets, double* d_fluence_raw, double* d_absorbed, smcrt_tallies* d_tallies,
+                                  void* hip_stream) {
+  if (!e || !scene) return fail(SMCRT_E_INVALID, "run: NULL engine or scene");
+  if (!d_absorbed || !d_tallies) return fail(SMCRT_E_INVALID, "run: d_absorbed and d_tallies are required");
+  if (n_packets == 0) return SMCRT_OK;
+  if (first_packet + n_packets < first_packet) return fail(SMCRT_E_INVALID, "run: packet range overflows 64 bits");
+  smcrt_scene* s = const_cast<smcrt_scene*>(scene);
+  smcrt_status st = pack(s);
+  if (st != SMCRT_OK) return st;
+  const SceneHeader* h = reinterpret_cast<const SceneHeader*>(s->blob.data());
+  if (h->has_grid && !d_fluence_raw) return fail(SMCRT_E_INVALID, "run: the scene has a grid but d_fluence_raw is NULL");
+  HIP_TRY(hipSetDevice(e->device), "hipSetDevice");
+  hipStream_t stream = (hipStream_t)hip_stream;
+  st = upload(e, s, stream);
+  if (st != SMCRT_OK) return st;
+  WalkArgs a = base_args(e, s);
+  a.seed = seed;
+  a.first = first_packet;
+  a.n = n_packets;
+  a.fluence = h->has_grid ? d_fluence_raw : nullptr;
+  a.absorbed = d_absorbed;
+  a.tallies = d_tallies;
+  LaunchCfg c = launch_cfg(e);
+  HIP_TRY(launch_zero_u64(e->d_counter, stream), "zero counter");
+  HIP_TRY(launch_walk(e->opts.precision, false, c, a, stream), "walk kernel");
+  return SMCRT_OK;
+}
+
+extern "C" smcrt_status smcrt_trace(smcrt_engine* e, const smcrt_scene* scene, uint64_t seed, const uint64_t* d_packet_ids,
+                                    int n_ids, int max_events, smcrt_event* d_out, int32_t* d_count, void* hip_stream) {
+  if (!e || !scene || !d_packet_ids || !d_out || !d_count) return fail(SMCRT_E_INVALID, "trace: NULL argument");
+  if (n_ids < 1 || max_events < 1) return fail(SMCRT_E_INVALID, "trace: need n_ids >= 1 and max_events >= 1");
+  if ((int64_t)n_ids * max_events > (1LL << 31)) return fail(SMCRT_E_INVALID, "trace: too many records");
+  smcrt_scene* s = const_cast<smcrt_scene*>(scene);
+  smcrt_status st = pack(s);
+  if (st != SMCRT_OK) return st;
+  HIP_TRY(hipSetDevice(e->device), "hipSetDevice");
+  hipStream_t stream = (hipStream_t)hip_stream;
+  st = upload(e, s, stream);
+  if (st != SMCRT_OK) return st;
+  WalkArgs a = base_args(e, s);
+  a.seed = seed;
+  a.trace_ids = d_packet_ids;
+  a.trace_out = d_out;
+  a.trace_count = d_count;
+  a.n_trace = n_ids;
+  a.max_records = max_events;
+  LaunchCfg c;
+  c.block = 64;
+  c.grid = (n_ids + 63) / 64;
+  c.refill_min = 1;
+  c.surface_min = 1;
+  HIP_TRY(launch_walk(e->opts.precision, true, c, a, stream), "trace kernel");
+  return SMCRT_OK;
+}
+
+extern "C" smcrt_status smcrt_normalize_fluence(const smcrt_scene* scene, const double* d_raw, double launched,
+                                                double* d_phi, void* hip_stream) {
+  if (!scene || !d_raw || !d_phi) return fail(SMCRT_E_INVALID, "normalize_fluence: NULL argument");
+  if (!(launched > 0)) return fail(SMCRT_E_INVALID, "normalize_fluence: launched must be > 0");
+  smcrt_scene* s = const_cast<smcrt_scene*>(scene);
+  smcrt_status st = pack(s);
+  if (st != SMCRT_OK) return st;
+  const SceneHeader* h = reinterpret_cast<const SceneHeader*>(s->blob.data());
+  if (!h->has_grid) return fail(SMCRT_E_INVALID, "normalize_fluence: the scene has no grid");
+  size_t n = (size_t)h->g_dims[0] * h->g_dims[1] * h->g_dims[2];
+  double vol = h->g_d[0] * h->g_d[1] * h->g_d[2];
+  HIP_TRY(launch_scale(d_raw, d_phi, n, 1.0 / (launched * vol), (hipStream_t)hip_stream), "scale kernel");
+  return SMCRT_OK;
+}

@@ -1,0 +1,18 @@
+// launch.h -- host-callable launchers of the device kernels (walk.hip).
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include "layout.h"
+
+namespace smcrt {
+
+// precision: 0 = FP32 transport, 1 = FP64 transport; trace: record events
+hipError_t launch_walk(int precision, bool trace, const LaunchCfg& cfg, const WalkArgs& args, hipStream_t stream);
+// *p = 0 (a one-thread kernel, so the reset can sit inside captured graphs)
+hipError_t launch_zero_u64(unsigned long long* p, hipStream_t stream);
+// out[i] = in[i] * scale for i < n
+hipError_t launch_scale(const double* in, double* out, size_t n, double scale, hipStream_t stream);
+// resident workgroups per CU of the walk kernel at this block size
+int walk_max_blocks_per_cu(int precision, int block);
+
+}  // namespace smcrt

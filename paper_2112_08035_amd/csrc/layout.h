@@ -1,0 +1,91 @@
+// layout.h -- device-side scene tables of libsmcrt (host packer <-> kernels).
+//
+// One contiguous blob per scene: a SceneHeader, then n_prims PrimD (FP64
+// parameters, used by the interface step and by FP64 transport), then
+// n_prims PrimF (FP32 copies for FP32 transport).  Every table is read with
+// wave-uniform indices, so the kernels fetch it through the scalar cache into
+// SGPRs; nothing per lane.
+#pragma once
+#include <stdint.h>
+
+namespace smcrt {
+
+constexpr int kMaxRegions = 16;     // regions per scene (ambient adds one slot)
+constexpr int kMaxPrims = 1 << 20;  // primitives per scene
+
+enum PrimKind : int32_t { kSphere = 0, kBox = 1, kCapsule = 2, kCylinder = 3 };
+enum RegionOp : int32_t { kUnion = 0, kSmoothUnion = 1 };
+enum SourceKind : int32_t { kPoint = 0, kPencil = 1, kDisc = 2, kRect = 3 };
+
+// Primitive parameters, precomputed on the host:
+//   sphere   : c0 c1 c2 r
+//   box      : c0 c1 c2 h0 h1 h2
+//   capsule  : a0 a1 a2 ba0 ba1 ba2 1/|ba|^2 r
+//   cylinder : a0 a1 a2 e0 e1 e2 L L/2 r          (e = unit axis)
+template <typename T>
+struct Prim {
+  int32_t kind;
+  int32_t pad;
+  T v[10];
+};
+using PrimD = Prim<double>;
+using PrimF = Prim<float>;
+
+struct Region {
+  int32_t first, count, op, pad;  // primitive range (region order) and CSG op
+  double k, inv_k;                // smooth-union radius
+  double mua, mus, mut, inv_mut;  // inv_mut = 0 for the ambient slot
+  double absorb;                  // mua / mut
+  double g, n;
+  // HG constants: 1 + g^2, 1 - g^2, 1 - g, 2g, 1/(2g); iso = |g| < 1e-6
+  double hg_a, hg_b, hg_c, hg_d, hg_e;
+  int32_t iso, pad2;
+  float kf, inv_kf, mutf, inv_mutf, gf, hg_af, hg_bf, hg_cf, hg_df, hg_ef;
+};
+
+struct SceneHeader {
+  int32_t n_prims, n_regions;     // the ambient medium is region slot n_regions
+  int32_t has_grid, src_kind;
+  int32_t g_dims[3], m_survive;
+  int32_t max_steps, pad0;
+  int64_t max_events;
+  double delta, h_normal, snap_cos, offset;  // surface threshold and surface-step constants
+  double bb_c[3], bb_h[3];        // simulation volume (centre, half extents)
+  float bb_cf[3], bb_hf[3];
+  double g_lo[3], g_inv_d[3], g_d[3];
+  float g_lof[3], g_inv_df[3];
+  double src[8];
+  double w_threshold, m_d, inv_m;
+  float deltaf, pad1;
+  Region reg[kMaxRegions + 1];
+  uint64_t prim_offset_d, prim_offset_f;  // byte offsets of the tables in the blob
+  uint64_t blob_bytes;
+};
+
+// Launch configuration chosen by the host.
+struct LaunchCfg {
+  int block;          // threads per workgroup
+  int grid;           // workgroups
+  int refill_min;     // dead lanes gathered before a wave emits
+  int surface_min;    // lanes gathered before a wave runs the interface step
+};
+
+// Per-run device arguments of the walk kernel.
+struct WalkArgs {
+  const SceneHeader* sc;
+  const PrimD* pd;
+  const PrimF* pf;
+  uint64_t seed, first, n;
+  unsigned long long* counter;   // packets handed out so far (zeroed before launch)
+  double* fluence;               // nx*ny*nz, may be null
+  double* absorbed;              // n_regions
+  void* tallies;                 // smcrt_tallies
+  // trace mode
+  const uint64_t* trace_ids;
+  void* trace_out;
+  int32_t* trace_count;
+  int32_t n_trace, max_records;
+  int32_t refill_min, surface_min;
+};
+
+}  // namespace smcrt

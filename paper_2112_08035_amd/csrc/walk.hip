@@ -1,0 +1,814 @@
+// walk.hip -- the persistent photon-packet walk through an SDF scene on
+// gfx950 (McMillan, Bruce & Dholakia 2021, Sec. 2.3), one packet per lane.
+//
+// Each lane owns a packet: emission (Sec. 3.1 sources, Eq. 1 free path),
+// sphere-tracing steps over every region SDF (Sec. 2.3, Fig. 3), the
+// interface step in FP64 (Fresnel, numerical normals; Sec. 1 and Sec. 2.3),
+// interactions (implicit capture, Henyey-Greenstein, roulette), and the
+// path-length fluence tally (Sec. 3.1, rectangular bins).  When its packet
+// ends the lane takes the next packet id from a global counter, so the grid
+// is sized to the machine, not to the packet count.
+//
+// T is the transport type (float or double): positions, directions, step
+// lengths, the SDFs of the stepping loop and the transcendentals.  The
+// interface step, weights, absorbed energy and tallies are FP64 in both.
+//
+// Divergence control: lanes that reach a surface wait until surface_min
+// lanes of the wave are there (or nothing else can move), so the long FP64
+// interface step runs with many lanes on; dead lanes wait for refill_min
+// before a wave emits.
+//
+// Tally: each lane merges consecutive pieces that fall in the same voxel
+// (across steps, events and even packets) and issues one FP64 atomic per
+// run of equal voxels.
+#include <hip/hip_runtime.h>
+
+#include "../../include/smcrt.h"
+#include "launch.h"
+#include "layout.h"
+
+namespace smcrt {
+
+// ------------------------------------------------------------------ types
+
+template <typename T>
+struct V3 {
+  T x, y, z;
+};
+template <typename T>
+__device__ __forceinline__ V3<T> mk(T x, T y, T z) { return V3<T>{x, y, z}; }
+template <typename T>
+__device__ __forceinline__ V3<T> operator+(V3<T> a, V3<T> b) { return {a.x + b.x, a.y + b.y, a.z + b.z}; }
+template <typename T>
+__device__ __forceinline__ V3<T> operator-(V3<T> a, V3<T> b) { return {a.x - b.x, a.y - b.y, a.z - b.z}; }
+template <typename T>
+__device__ __forceinline__ V3<T> operator*(T s, V3<T> a) { return {s * a.x, s * a.y, s * a.z}; }
+template <typename T>
+__device__ __forceinline__ T dot(V3<T> a, V3<T> b) { return a.x * b.x + a.y * b.y + a.z * b.z; }
+template <typename T>
+__device__ __forceinline__ V3<double> to_d(V3<T> a) { return {(double)a.x, (double)a.y, (double)a.z}; }
+template <typename T>
+__device__ __forceinline__ V3<T> from_d(V3<double> a) { return {(T)a.x, (T)a.y, (T)a.z}; }
+
+__device__ __forceinline__ float tsqrt(float x) { return __builtin_sqrtf(x); }
+__device__ __forceinline__ double tsqrt(double x) { return __builtin_sqrt(x); }
+__device__ __forceinline__ float tlog(float x) { return __logf(x); }
+__device__ __forceinline__ double tlog(double x) { return log(x); }
+__device__ __forceinline__ void tsincos_2pi(float xi, float* s, float* c) {
+  float a = 6.2831853071795864769f * xi;
+  *s = __sinf(a);
+  *c = __cosf(a);
+}
+__device__ __forceinline__ void tsincos_2pi(double xi, double* s, double* c) { sincos(2.0 * M_PI * xi, s, c); }
+__device__ __forceinline__ float tdiv(float a, float b) { return __fdividef(a, b); }
+__device__ __forceinline__ double tdiv(double a, double b) { return a / b; }
+template <typename T>
+__device__ __forceinline__ T tmin(T a, T b) { return a < b ? a : b; }
+template <typename T>
+__device__ __forceinline__ T tmax(T a, T b) { return a > b ? a : b; }
+template <typename T>
+__device__ __forceinline__ T tabs(T a) { return a < T(0) ? -a : a; }
+template <typename T>
+__device__ __forceinline__ T tclamp(T x, T lo, T hi) { return x < lo ? lo : (x > hi ? hi : x); }
+template <typename T>
+__device__ __forceinline__ T tinf();
+template <>
+__device__ __forceinline__ float tinf<float>() { return __builtin_inff(); }
+template <>
+__device__ __forceinline__ double tinf<double>() { return __builtin_inf(); }
+
+// ------------------------------------------------------------------ Philox
+
+// Philox4x32-10 (Salmon et al., SC'11): ten rounds; each multiplies words 0
+// and 2 by the round constants, swaps in the high halves xor-ed with the
+// other words and the round key, and bumps the key by the Weyl constants.
+struct U4 {
+  uint32_t w0, w1, w2, w3;
+};
+__device__ __forceinline__ U4 philox10(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3, uint32_t k0, uint32_t k1) {
+#pragma unroll
+  for (int r = 0; r < 10; ++r) {
+    const uint64_t m0 = (uint64_t)0xD2511F53u * (uint64_t)c0;
+    const uint64_t m1 = (uint64_t)0xCD9E8D57u * (uint64_t)c2;
+    const uint32_t x0 = (uint32_t)(m1 >> 32) ^ c1 ^ k0;
+    const uint32_t x2 = (uint32_t)(m0 >> 32) ^ c3 ^ k1;
+    c1 = (uint32_t)m1;
+    c3 = (uint32_t)m0;
+    c0 = x0;
+    c2 = x2;
+    k0 += 0x9E3779B9u;
+    k1 += 0xBB67AE85u;
+  }
+  return U4{c0, c1, c2, c3};
+}
+
+// a 32-bit word -> (m + 1/2) / 2^23 with m its top 23 bits; exact in FP32
+template <typename T>
+__device__ __forceinline__ T xi_of(uint32_t w) {
+  return ((T)(w >> 9) + T(0.5)) * T(1.0 / 8388608.0);
+}
+
+// ------------------------------------------------------------------ scene
+
+template <typename T>
+struct Tab;
+template <>
+struct Tab<float> {
+  static __device__ __forceinline__ const PrimF* prims(const WalkArgs& a) { return a.pf; }
+  static __device__ __forceinline__ float k(const Region& r) { return r.kf; }
+  static __device__ __forceinline__ float inv_k(const Region& r) { return r.inv_kf; }
+  static __device__ __forceinline__ float mut(const Region& r) { return r.mutf; }
+  static __device__ __forceinline__ float inv_mut(const Region& r) { return r.inv_mutf; }
+  static __device__ __forceinline__ V3<float> bb_c(const SceneHeader* s) { return {s->bb_cf[0], s->bb_cf[1], s->bb_cf[2]}; }
+  static __device__ __forceinline__ V3<float> bb_h(const SceneHeader* s) { return {s->bb_hf[0], s->bb_hf[1], s->bb_hf[2]}; }
+  static __device__ __forceinline__ V3<float> g_lo(const SceneHeader* s) { return {s->g_lof[0], s->g_lof[1], s->g_lof[2]}; }
+  static __device__ __forceinline__ V3<float> g_inv(const SceneHeader* s) { return {s->g_inv_df[0], s->g_inv_df[1], s->g_inv_df[2]}; }
+  static __device__ __forceinline__ float delta(const SceneHeader* s) { return s->deltaf; }
+};
+template <>
+struct Tab<double> {
+  static __device__ __forceinline__ const PrimD* prims(const WalkArgs& a) { return a.pd; }
+  static __device__ __forceinline__ double k(const Region& r) { return r.k; }
+  static __device__ __forceinline__ double inv_k(const Region& r) { return r.inv_k; }
+  static __device__ __forceinline__ double mut(const Region& r) { return r.mut; }
+  static __device__ __forceinline__ double inv_mut(const Region& r) { return r.inv_mut; }
+  static __device__ __forceinline__ V3<double> bb_c(const SceneHeader* s) { return {s->bb_c[0], s->bb_c[1], s->bb_c[2]}; }
+  static __device__ __forceinline__ V3<double> bb_h(const SceneHeader* s) { return {s->bb_h[0], s->bb_h[1], s->bb_h[2]}; }
+  static __device__ __forceinline__ V3<double> g_lo(const SceneHeader* s) { return {s->g_lo[0], s->g_lo[1], s->g_lo[2]}; }
+  static __device__ __forceinline__ V3<double> g_inv(const SceneHeader* s) { return {s->g_inv_d[0], s->g_inv_d[1], s->g_inv_d[2]}; }
+  static __device__ __forceinline__ double delta(const SceneHeader* s) { return s->delta; }
+};
+
+// exact Euclidean SDF of one primitive (Sec. 2.2; Eq. 3 for the sphere)
+template <typename T>
+__device__ __forceinline__ T prim_sdf(const Prim<T>* __restrict__ P, int i, V3<T> p) {
+  const int kind = P[i].kind;
+  const T* v = P[i].v;
+  const V3<T> q = p - mk(v[0], v[1], v[2]);
+  if (kind == kSphere) return tsqrt(dot(q, q)) - v[3];
+  if (kind == kBox) {
+    const T ex = tabs(q.x) - v[3], ey = tabs(q.y) - v[4], ez = tabs(q.z) - v[5];
+    const V3<T> o = mk(tmax(ex, T(0)), tmax(ey, T(0)), tmax(ez, T(0)));
+    return tsqrt(dot(o, o)) + tmin(tmax(ex, tmax(ey, ez)), T(0));
+  }
+  const V3<T> e = mk(v[3], v[4], v[5]);
+  if (kind == kCapsule) {  // e = b - a, v[6] = 1/|b-a|^2
+    const T t = tclamp(dot(q, e) * v[6], T(0), T(1));
+    const V3<T> d = q - t * e;
+    return tsqrt(dot(d, d)) - v[7];
+  }
+  // capped cylinder: e unit axis, v[6] = L, v[7] = L/2, v[8] = r
+  const T x = dot(q, e);
+  const V3<T> rad = q - x * e;
+  const T q1 = tsqrt(dot(rad, rad)) - v[8];
+  const T q2 = tabs(x - v[7]) - v[7];
+  const T o1 = tmax(q1, T(0)), o2 = tmax(q2, T(0));
+  return tmin(tmax(q1, q2), T(0)) + tsqrt(o1 * o1 + o2 * o2);
+}
+
+// region SDF: union (min) or polynomial smooth union of its primitives
+template <typename T>
+__device__ __forceinline__ T region_sdf(const WalkArgs& a, const Region& R, V3<T> p) {
+  const Prim<T>* __restrict__ P = Tab<T>::prims(a);
+  T d = prim_sdf(P, R.first, p);
+  if (R.op == kSmoothUnion) {
+    const T k = Tab<T>::k(R), ik = Tab<T>::inv_k(R);
+    for (int i = 1; i < R.count; ++i) {
+      const T b = prim_sdf(P, R.first + i, p);
+      const T h = tclamp(T(0.5) + T(0.5) * (b - d) * ik, T(0), T(1));
+      d = h * d + (T(1) - h) * b - k * h * (T(1) - h);
+    }
+  } else {
+    for (int i = 1; i < R.count; ++i) d = tmin(d, prim_sdf(P, R.first + i, p));
+  }
+  return d;
+}
+
+// owner of a point: the highest-index region with a negative SDF, else the
+// ambient slot n_regions
+template <typename T>
+__device__ __forceinline__ int region_of(const WalkArgs& a, V3<T> p) {
+  const SceneHeader* sc = a.sc;
+  const int nr = sc->n_regions;
+  int owner = nr;
+  for (int r = nr - 1; r >= 0; --r) {
+    if (region_sdf<T>(a, sc->reg[r], p) < T(0)) {
+      owner = r;
+      break;
+    }
+  }
+  return owner;
+}
+
+// signed distance of the simulation volume and, when outside, the face
+template <typename T>
+__device__ __forceinline__ T volume_sdf(const SceneHeader* sc, V3<T> p, int* face) {
+  const V3<T> c = Tab<T>::bb_c(sc), h = Tab<T>::bb_h(sc);
+  const V3<T> q = p - c;
+  const T ex = tabs(q.x) - h.x, ey = tabs(q.y) - h.y, ez = tabs(q.z) - h.z;
+  int ax = 0;
+  T best = ex;
+  if (ey > best) { best = ey; ax = 1; }
+  if (ez > best) { best = ez; ax = 2; }
+  const T qa = ax == 0 ? q.x : (ax == 1 ? q.y : q.z);
+  *face = 2 * ax + (qa > T(0) ? 1 : 0);
+  const V3<T> o = mk(tmax(ex, T(0)), tmax(ey, T(0)), tmax(ez, T(0)));
+  return tsqrt(dot(o, o)) + tmin(best, T(0));
+}
+
+// unit outward normal of region R at p by central differences of step h
+__device__ __forceinline__ V3<double> region_normal(const WalkArgs& a, const Region& R, V3<double> p, double h) {
+  V3<double> n;
+  n.x = region_sdf<double>(a, R, mk(p.x + h, p.y, p.z)) - region_sdf<double>(a, R, mk(p.x - h, p.y, p.z));
+  n.y = region_sdf<double>(a, R, mk(p.x, p.y + h, p.z)) - region_sdf<double>(a, R, mk(p.x, p.y - h, p.z));
+  n.z = region_sdf<double>(a, R, mk(p.x, p.y, p.z + h)) - region_sdf<double>(a, R, mk(p.x, p.y, p.z - h));
+  const double inv = 1.0 / __builtin_sqrt(dot(n, n));
+  return inv * n;
+}
+
+// ------------------------------------------------------------------ tallies
+
+struct LdsTallies {
+  double absorbed[kMaxRegions];
+  double escaped[6];
+  double gain, loss, stalled;
+  unsigned long long cnt[16];
+};
+enum CountSlot {
+  kCInterfaces = 0, kCReflections, kCRefractions, kCCrossings, kCAdvances, kCKills, kCStalls, kCEscapes,
+  kCLaunched, kCSteps, kCInteractions, kCPieces, kCAtomics
+};
+
+// per-lane run of equal voxels waiting to be added to the grid
+struct Run {
+  int v;
+  double sum;
+};
+
+__device__ __forceinline__ void run_add(double* __restrict__ F, Run& run, int v, double val, uint32_t& n_pieces,
+                                        uint32_t& n_atomics) {
+  ++n_pieces;
+  if (v == run.v) {
+    run.sum += val;
+  } else {
+    if (run.v >= 0) {
+      unsafeAtomicAdd(F + run.v, run.sum);
+      ++n_atomics;
+    }
+    run.v = v;
+    run.sum = val;
+  }
+}
+
+// Path-length estimator (Sec. 3.1): weight * length of the straight move
+// p -> p + len*u credited to every voxel it crosses, by a 3-D DDA in voxel
+// units.  Voxel i spans [lo + i*D, lo + (i+1)*D); indices are clamped on
+// entry and the walk stops when it steps off the grid.
+template <typename T>
+__device__ __forceinline__ void tally_move(const WalkArgs& a, V3<T> p, V3<T> u, T len, double w, Run& run,
+                                           uint32_t& n_pieces, uint32_t& n_atomics) {
+  const SceneHeader* sc = a.sc;
+  if (a.fluence == nullptr || !(len > T(0))) return;
+  const int nx = sc->g_dims[0], ny = sc->g_dims[1], nz = sc->g_dims[2];
+  const V3<T> inv = Tab<T>::g_inv(sc);
+  const V3<T> lo = Tab<T>::g_lo(sc);
+  const T g[3] = {(p.x - lo.x) * inv.x, (p.y - lo.y) * inv.y, (p.z - lo.z) * inv.z};
+  const T gu[3] = {u.x * inv.x, u.y * inv.y, u.z * inv.z};
+  const int dims[3] = {nx, ny, nz};
+  if (!__builtin_isfinite(g[0] + g[1] + g[2] + gu[0] + gu[1] + gu[2] + len)) return;
+  T t0 = T(0), t1 = len;
+#pragma unroll
+  for (int i = 0; i < 3; ++i) {
+    if (gu[i] == T(0)) {
+      if (g[i] < T(0) || g[i] > T(dims[i])) return;
+    } else {
+      const T ta = tdiv(-g[i], gu[i]), tb = tdiv(T(dims[i]) - g[i], gu[i]);
+      t0 = tmax(t0, tmin(ta, tb));
+      t1 = tmin(t1, tmax(ta, tb));
+    }
+  }
+  if (!(t1 > t0)) return;
+  int idx[3], stp[3];
+  T tnext[3], tdel[3];
+#pragma unroll
+  for (int i = 0; i < 3; ++i) {
+    const T x = g[i] + t0 * gu[i];
+    T fl = floor(x);
+    if (gu[i] < T(0) && x == fl) fl -= T(1);  // on a plane, moving down: the voxel below
+    fl = tclamp(fl, T(-1), T(dims[i]));
+    int k = (int)fl;
+    k = k < 0 ? 0 : (k >= dims[i] ? dims[i] - 1 : k);
+    idx[i] = k;
+    if (gu[i] > T(0)) {
+      stp[i] = 1;
+      tnext[i] = tdiv(T(k + 1) - g[i], gu[i]);
+      tdel[i] = tdiv(T(1), gu[i]);
+    } else if (gu[i] < T(0)) {
+      stp[i] = -1;
+      tnext[i] = tdiv(T(k) - g[i], gu[i]);
+      tdel[i] = -tdiv(T(1), gu[i]);
+    } else {
+      stp[i] = 0;
+      tnext[i] = tinf<T>();
+      tdel[i] = tinf<T>();
+    }
+  }
+  T t = t0;
+  const int cap = nx + ny + nz + 3;
+  for (int it = 0; it < cap; ++it) {
+    const T tn = tmin(tmin(tnext[0], tnext[1]), tmin(tnext[2], t1));
+    const T piece = tn - t;
+    if (piece > T(0)) run_add(a.fluence, run, idx[0] + nx * (idx[1] + ny * idx[2]), w * (double)piece, n_pieces, n_atomics);
+    if (tn >= t1) break;
+    int ax = (tnext[0] <= tnext[1] && tnext[0] <= tnext[2]) ? 0 : (tnext[1] <= tnext[2] ? 1 : 2);
+    idx[ax] += stp[ax];
+    if (idx[ax] < 0 || idx[ax] >= dims[ax]) break;
+    tnext[ax] += tdel[ax];
+    t = tn;
+  }
+}
+
+// ------------------------------------------------------------------ packet
+
+enum State : int { kTransport = 0, kSurface = 1, kInteract = 2 };
+
+template <typename T>
+struct Packet {
+  V3<T> p, u;
+  T tau;
+  T mut, inv_mut;   // of the current region (0 and 0 in ambient)
+  double w;
+  uint64_t pid;
+  uint32_t k;       // event index
+  int region;       // n_regions = ambient
+  int state;
+  int steps;        // sphere-tracing steps in the current event
+};
+
+struct Lane {
+  Run run;
+  double abs_sum;   // absorbed weight not yet added to the workgroup sums
+  int abs_region;
+  uint32_t n_steps, n_inter, n_pieces, n_atomics;
+  // trace
+  smcrt_event* rec;
+  int n_rec;
+};
+
+template <typename T>
+__device__ __forceinline__ void set_region(const SceneHeader* sc, Packet<T>& pk, int r) {
+  pk.region = r;
+  pk.mut = Tab<T>::mut(sc->reg[r]);
+  pk.inv_mut = Tab<T>::inv_mut(sc->reg[r]);
+}
+
+template <typename T, bool TRACE>
+__device__ __forceinline__ void record(const WalkArgs& a, const Packet<T>& pk, Lane& ln, int type) {
+  if constexpr (TRACE) {
+    if (ln.n_rec < a.max_records) {
+      smcrt_event e;
+      e.event = pk.k;
+      e.type = (uint32_t)type;
+      e.region = pk.region == a.sc->n_regions ? -1 : pk.region;
+      e.pad = 0;
+      e.p[0] = pk.p.x; e.p[1] = pk.p.y; e.p[2] = pk.p.z;
+      e.u[0] = pk.u.x; e.u[1] = pk.u.y; e.u[2] = pk.u.z;
+      e.w = pk.w;
+      e.tau = (double)pk.tau;
+      ln.rec[ln.n_rec] = e;
+    }
+    ++ln.n_rec;
+  }
+}
+
+template <typename T>
+__device__ __forceinline__ void move(const WalkArgs& a, Packet<T>& pk, Lane& ln, T len) {
+  tally_move<T>(a, pk.p, pk.u, len, pk.w, ln.run, ln.n_pieces, ln.n_atomics);
+  pk.p = pk.p + len * pk.u;
+}
+
+__device__ __forceinline__ void add_absorbed(LdsTallies& L, Lane& ln, int r, double dA) {
+  if (r != ln.abs_region) {
+    if (ln.abs_region >= 0) atomicAdd(&L.absorbed[ln.abs_region], ln.abs_sum);
+    ln.abs_region = r;
+    ln.abs_sum = 0.0;
+  }
+  ln.abs_sum += dA;
+}
+
+// emission, event 0 (Sec. 3.1 sources; Eq. 1)
+template <typename T, bool TRACE>
+__device__ void emit(const WalkArgs& a, Packet<T>& pk, Lane& ln, LdsTallies& L) {
+  const SceneHeader* sc = a.sc;
+  const U4 r = philox10(0u, (uint32_t)pk.pid, (uint32_t)(pk.pid >> 32), 0u, (uint32_t)a.seed, (uint32_t)(a.seed >> 32));
+  const T x0 = xi_of<T>(r.w0), x1 = xi_of<T>(r.w1), x3 = xi_of<T>(r.w3);
+  const double* s = sc->src;
+  V3<T> p = mk((T)s[0], (T)s[1], (T)s[2]);
+  V3<T> u;
+  const int kind = sc->src_kind;
+  if (kind == kPoint) {
+    const T ct = T(2) * x0 - T(1);
+    const T st = tsqrt(tmax(T(0), T(1) - ct * ct));
+    T sp, cp;
+    tsincos_2pi(x1, &sp, &cp);
+    u = mk(st * cp, st * sp, ct);
+  } else if (kind == kPencil) {
+    u = mk((T)s[3], (T)s[4], (T)s[5]);
+  } else if (kind == kDisc) {
+    const T rr = (T)s[3] * tsqrt(x0);
+    T sp, cp;
+    tsincos_2pi(x1, &sp, &cp);
+    p = mk(p.x + rr * cp, p.y + rr * sp, p.z);
+    u = mk((T)s[4], (T)s[5], (T)s[6]);
+  } else {
+    p = mk(p.x + (T)s[3] * (T(2) * x0 - T(1)), p.y + (T)s[4] * (T(2) * x1 - T(1)), p.z);
+    u = mk((T)s[5], (T)s[6], (T)s[7]);
+  }
+  const T il = T(1) / tsqrt(dot(u, u));
+  pk.p = p;
+  pk.u = il * u;
+  pk.w = 1.0;
+  pk.tau = -tlog(x3);
+  pk.k = 0;
+  pk.steps = 0;
+  pk.state = kTransport;
+  set_region(sc, pk, region_of<T>(a, p));
+  atomicAdd(&L.cnt[kCLaunched], 1ull);
+  record<T, TRACE>(a, pk, ln, SMCRT_EV_EMIT);
+}
+
+// absorption, Henyey-Greenstein scattering, roulette, next free path.
+// Returns false when the packet ends.
+template <typename T, bool TRACE>
+__device__ bool interact(const WalkArgs& a, Packet<T>& pk, Lane& ln, LdsTallies& L) {
+  const SceneHeader* sc = a.sc;
+  const Region& R = sc->reg[pk.region];
+  pk.k += 1;
+  ++ln.n_inter;
+  const U4 r = philox10(pk.k, (uint32_t)pk.pid, (uint32_t)(pk.pid >> 32), 0u, (uint32_t)a.seed, (uint32_t)(a.seed >> 32));
+  // implicit capture: the fraction mu_a/mu_t of the weight stays here
+  const double dA = pk.w * R.mua / R.mut;
+  add_absorbed(L, ln, pk.region, dA);
+  pk.w -= dA;
+  if (pk.w == 0.0) {
+    record<T, TRACE>(a, pk, ln, SMCRT_EV_ABSORB);
+    return false;
+  }
+  // scattering angle from the HG inverse CDF; azimuth uniform
+  const T x0 = xi_of<T>(r.w0), x1 = xi_of<T>(r.w1);
+  T ct;
+  if (R.iso) {
+    ct = T(2) * x0 - T(1);
+  } else if constexpr (sizeof(T) == 4) {
+    const float f = tdiv(R.hg_bf, R.hg_cf + R.hg_df * x0);
+    ct = tclamp((R.hg_af - f * f) * R.hg_ef, -1.0f, 1.0f);
+  } else {
+    const double f = R.hg_b / (R.hg_c + R.hg_d * x0);
+    ct = tclamp((R.hg_a - f * f) / R.hg_d, -1.0, 1.0);
+  }
+  const T st = tsqrt(tmax(T(0), T(1) - ct * ct));
+  T sp, cp;
+  tsincos_2pi(x1, &sp, &cp);
+  const V3<T> u = pk.u;
+  V3<T> v;
+  if (tabs(u.z) > T(1) - T(1e-5)) {
+    v = mk(st * cp, st * sp, (u.z >= T(0) ? ct : -ct));
+  } else {
+    const T tt = tsqrt(T(1) - u.z * u.z);
+    const T itt = T(1) / tt;
+    v.x = st * (u.x * u.z * cp - u.y * sp) * itt + u.x * ct;
+    v.y = st * (u.y * u.z * cp + u.x * sp) * itt + u.y * ct;
+    v.z = -st * cp * tt + u.z * ct;
+  }
+  pk.u = (T(1) / tsqrt(dot(v, v))) * v;
+  // Russian roulette on the weight
+  if (pk.w < sc->w_threshold) {
+    const double x2 = xi_of<double>(r.w2);
+    if (x2 < sc->inv_m) {
+      atomicAdd(&L.gain, (sc->m_d - 1.0) * pk.w);
+      pk.w *= sc->m_d;
+    } else {
+      atomicAdd(&L.loss, pk.w);
+      atomicAdd(&L.cnt[kCKills], 1ull);
+      record<T, TRACE>(a, pk, ln, SMCRT_EV_KILL);
+      return false;
+    }
+  }
+  pk.tau = -tlog(xi_of<T>(r.w3));
+  pk.steps = 0;
+  record<T, TRACE>(a, pk, ln, SMCRT_EV_SCATTER);
+  return true;
+}
+
+// The packet is within delta of a surface.  FP64 throughout: nearest
+// surface, numerical normal, the hit where the ray meets the surface, a
+// probe across it for the medium ahead, then cross, reflect or refract.
+// Sets pk.state to kTransport or kInteract.
+template <typename T, bool TRACE>
+__device__ void surface(const WalkArgs& a, Packet<T>& pk, Lane& ln, LdsTallies& L) {
+  const SceneHeader* sc = a.sc;
+  const V3<double> p = to_d(pk.p), u = to_d(pk.u);
+  const int nr = sc->n_regions;
+  int j = 0;
+  double dj = region_sdf<double>(a, sc->reg[0], p);
+  for (int r = 1; r < nr; ++r) {
+    const double d = region_sdf<double>(a, sc->reg[r], p);
+    if (__builtin_fabs(d) < __builtin_fabs(dj)) {
+      dj = d;
+      j = r;
+    }
+  }
+  const Region& Rj = sc->reg[j];
+  const double h = sc->h_normal, off = sc->offset;
+  const V3<double> n0 = region_normal(a, Rj, p, h);
+  const double c0 = dot(u, n0);
+  double t_ray = 0.0;
+  V3<double> ps;
+  if (__builtin_fabs(c0) >= sc->snap_cos) {
+    t_ray = -dj / c0;
+    ps = p + t_ray * u;
+  } else {
+    ps = p - dj * n0;
+  }
+  const V3<double> nrm = region_normal(a, Rj, ps, h);
+  const double c = dot(u, nrm);
+  const double sg = c > 0.0 ? 1.0 : -1.0;
+  const V3<double> q = ps + (sg * off) * nrm;
+  const int r2 = (c == 0.0) ? pk.region : region_of<double>(a, q);
+  const Region& R1 = sc->reg[pk.region];
+  double tau = (double)pk.tau;
+  const double s_rem = R1.mut > 0.0 ? tau / R1.mut : __builtin_inf();
+  if (r2 == pk.region) {
+    // no change of medium ahead: advance 2*delta along the ray
+    atomicAdd(&L.cnt[kCAdvances], 1ull);
+    if (s_rem <= off) {
+      move<T>(a, pk, ln, (T)s_rem);
+      pk.tau = T(0);
+      pk.state = kInteract;
+      return;
+    }
+    move<T>(a, pk, ln, (T)off);
+    pk.tau = (T)(tau - R1.mut * off);
+    pk.state = kTransport;
+    return;
+  }
+  if (t_ray > 0.0) {
+    if (s_rem <= t_ray) {
+      move<T>(a, pk, ln, (T)s_rem);
+      pk.tau = T(0);
+      pk.state = kInteract;
+      return;
+    }
+    move<T>(a, pk, ln, (T)t_ray);
+    tau -= R1.mut * t_ray;
+  }
+  pk.k += 1;
+  pk.steps = 0;
+  atomicAdd(&L.cnt[kCInterfaces], 1ull);
+  pk.tau = (T)tau;
+  pk.state = kTransport;
+  const double n1 = R1.n, n2 = sc->reg[r2].n;
+  if (n1 == n2) {  // index matched: cross undeflected
+    pk.p = from_d<T>(q);
+    set_region(sc, pk, r2);
+    atomicAdd(&L.cnt[kCCrossings], 1ull);
+    record<T, TRACE>(a, pk, ln, SMCRT_EV_CROSS);
+    return;
+  }
+  const U4 rr = philox10(pk.k, (uint32_t)pk.pid, (uint32_t)(pk.pid >> 32), 0u, (uint32_t)a.seed, (uint32_t)(a.seed >> 32));
+  const double x0 = xi_of<double>(rr.w0);
+  // unpolarised Fresnel reflectance; total internal reflection gives 1
+  const double ci = __builtin_fabs(c), eta = n1 / n2;
+  const double s2t = eta * eta * (1.0 - ci * ci);
+  double R = 1.0, ctr = 0.0;
+  if (s2t < 1.0) {
+    ctr = __builtin_sqrt(1.0 - s2t);
+    const double rs = (n1 * ci - n2 * ctr) / (n1 * ci + n2 * ctr);
+    const double rp = (n1 * ctr - n2 * ci) / (n1 * ctr + n2 * ci);
+    R = 0.5 * (rs * rs + rp * rp);
+  }
+  V3<double> v;
+  if (x0 < R) {  // specular reflection, back on the incident side
+    v = u - (2.0 * c) * nrm;
+    pk.p = from_d<T>(ps - (sg * off) * nrm);
+    v = (1.0 / __builtin_sqrt(dot(v, v))) * v;
+    pk.u = from_d<T>(v);
+    atomicAdd(&L.cnt[kCReflections], 1ull);
+    record<T, TRACE>(a, pk, ln, SMCRT_EV_REFLECT);
+  } else {  // refraction (vector Snell's law) into the far medium
+    v = eta * u + ((ctr - eta * ci) * sg) * nrm;
+    v = (1.0 / __builtin_sqrt(dot(v, v))) * v;
+    pk.u = from_d<T>(v);
+    pk.p = from_d<T>(q);
+    set_region(sc, pk, r2);
+    atomicAdd(&L.cnt[kCRefractions], 1ull);
+    record<T, TRACE>(a, pk, ln, SMCRT_EV_REFRACT);
+  }
+}
+
+__device__ __forceinline__ int lane_id() { return __lane_id(); }
+
+template <typename T, bool TRACE>
+__global__ void __launch_bounds__(256) walk_kernel(WalkArgs a) {
+  __shared__ LdsTallies L;
+  const SceneHeader* sc = a.sc;
+  const int nr = sc->n_regions;
+  for (int i = threadIdx.x; i < kMaxRegions; i += blockDim.x) L.absorbed[i] = 0.0;
+  for (int i = threadIdx.x; i < 6; i += blockDim.x) L.escaped[i] = 0.0;
+  for (int i = threadIdx.x; i < 16; i += blockDim.x) L.cnt[i] = 0ull;
+  if (threadIdx.x == 0) L.gain = L.loss = L.stalled = 0.0;
+  __syncthreads();
+
+  Lane ln;
+  ln.run.v = -1;
+  ln.run.sum = 0.0;
+  ln.abs_sum = 0.0;
+  ln.abs_region = -1;
+  ln.n_steps = ln.n_inter = ln.n_pieces = ln.n_atomics = 0;
+  ln.rec = nullptr;
+  ln.n_rec = 0;
+
+  Packet<T> pk;
+  bool live = false;
+  bool exhausted = false;  // wave uniform
+  const int lane = lane_id();
+  const T delta = Tab<T>::delta(sc);
+  const int max_steps = sc->max_steps;
+  const uint32_t max_events = (uint32_t)sc->max_events;
+
+  if constexpr (TRACE) {
+    const int id = blockIdx.x * blockDim.x + threadIdx.x;
+    exhausted = true;
+    if (id < a.n_trace) {
+      ln.rec = reinterpret_cast<smcrt_event*>(a.trace_out) + (size_t)id * a.max_records;
+      pk.pid = a.trace_ids[id];
+      live = true;
+      emit<T, TRACE>(a, pk, ln, L);
+    }
+  }
+
+  for (;;) {
+    // ---- refill dead lanes from the global packet counter
+    if constexpr (!TRACE) {
+      const uint64_t dmask = __ballot(!live);
+      const int ndead = __popcll(dmask);
+      if (!exhausted && ndead > 0 && (ndead >= a.refill_min || ndead == __popcll(__ballot(1)))) {
+        const int leader = __ffsll((unsigned long long)dmask) - 1;
+        unsigned long long base = 0;
+        if (lane == leader) base = atomicAdd(a.counter, (unsigned long long)ndead);
+        base = __shfl(base, leader);
+        if (base + (uint64_t)ndead >= a.n) exhausted = true;
+        if (!live) {
+          const int rank = __popcll(dmask & ((1ull << lane) - 1ull));
+          const uint64_t id = base + (uint64_t)rank;
+          if (id < a.n) {
+            pk.pid = a.first + id;
+            live = true;
+            emit<T, TRACE>(a, pk, ln, L);
+          }
+        }
+      }
+    }
+    const uint64_t lmask = __ballot(live);
+    if (lmask == 0ull) {
+      if (exhausted) break;
+      continue;
+    }
+
+    // ---- one sphere-tracing step (Sec. 2.3)
+    if (live && pk.state == kTransport) {
+      if (++pk.steps > max_steps || pk.k > max_events) {
+        atomicAdd(&L.stalled, pk.w);
+        atomicAdd(&L.cnt[kCStalls], 1ull);
+        record<T, TRACE>(a, pk, ln, SMCRT_EV_STALL);
+        live = false;
+      } else {
+        ++ln.n_steps;
+        T dmin = tinf<T>();
+        for (int r = 0; r < nr; ++r) dmin = tmin(dmin, tabs(region_sdf<T>(a, sc->reg[r], pk.p)));
+        int face;
+        const T dbb = volume_sdf<T>(sc, pk.p, &face);
+        if (dbb > T(0)) {  // outside the simulation volume
+          atomicAdd(&L.escaped[face], pk.w);
+          atomicAdd(&L.cnt[kCEscapes], 1ull);
+          record<T, TRACE>(a, pk, ln, SMCRT_EV_ESCAPE);
+          live = false;
+        } else {
+          const T s = pk.mut > T(0) ? pk.tau * pk.inv_mut : tinf<T>();
+          if (s <= dmin) {  // the optical depth runs out before any surface
+            move<T>(a, pk, ln, s);
+            pk.tau = T(0);
+            pk.state = kInteract;
+          } else if (dmin < delta) {
+            pk.state = kSurface;
+          } else {
+            move<T>(a, pk, ln, dmin);
+            pk.tau -= pk.mut * dmin;
+          }
+        }
+      }
+    }
+
+    // ---- interface steps, gathered
+    {
+      const uint64_t smask = __ballot(live && pk.state == kSurface);
+      const int nsurf = __popcll(smask);
+      if (nsurf > 0 && (nsurf >= a.surface_min || nsurf == __popcll(__ballot(live)))) {
+        if (live && pk.state == kSurface) surface<T, TRACE>(a, pk, ln, L);
+      }
+    }
+
+    // ---- interactions
+    if (live && pk.state == kInteract) {
+      pk.state = kTransport;
+      if (!interact<T, TRACE>(a, pk, ln, L)) live = false;
+    }
+  }
+
+  // ---- flush per-lane sums
+  if (ln.run.v >= 0) {
+    unsafeAtomicAdd(a.fluence + ln.run.v, ln.run.sum);
+    ++ln.n_atomics;
+  }
+  if (ln.abs_region >= 0) atomicAdd(&L.absorbed[ln.abs_region], ln.abs_sum);
+  atomicAdd(&L.cnt[kCSteps], (unsigned long long)ln.n_steps);
+  atomicAdd(&L.cnt[kCInteractions], (unsigned long long)ln.n_inter);
+  atomicAdd(&L.cnt[kCPieces], (unsigned long long)ln.n_pieces);
+  atomicAdd(&L.cnt[kCAtomics], (unsigned long long)ln.n_atomics);
+  if constexpr (TRACE) {
+    const int id = blockIdx.x * blockDim.x + threadIdx.x;
+    if (id < a.n_trace) a.trace_count[id] = ln.n_rec < a.max_records ? ln.n_rec : a.max_records;
+  }
+  __syncthreads();
+  smcrt_tallies* G = reinterpret_cast<smcrt_tallies*>(a.tallies);
+  if (a.absorbed != nullptr && threadIdx.x < (unsigned)nr)
+    unsafeAtomicAdd(a.absorbed + threadIdx.x, L.absorbed[threadIdx.x]);
+  if (threadIdx.x == 0 && G) {
+    for (int f = 0; f < 6; ++f) unsafeAtomicAdd(&G->escaped_face[f], L.escaped[f]);
+    unsafeAtomicAdd(&G->launched, (double)L.cnt[kCLaunched]);
+    unsafeAtomicAdd(&G->roulette_gain, L.gain);
+    unsafeAtomicAdd(&G->roulette_loss, L.loss);
+    unsafeAtomicAdd(&G->stalled, L.stalled);
+    atomicAdd((unsigned long long*)&G->events, L.cnt[kCInteractions] + L.cnt[kCInterfaces]);
+    atomicAdd((unsigned long long*)&G->steps, L.cnt[kCSteps]);
+    atomicAdd((unsigned long long*)&G->interactions, L.cnt[kCInteractions]);
+    atomicAdd((unsigned long long*)&G->interfaces, L.cnt[kCInterfaces]);
+    atomicAdd((unsigned long long*)&G->reflections, L.cnt[kCReflections]);
+    atomicAdd((unsigned long long*)&G->refractions, L.cnt[kCRefractions]);
+    atomicAdd((unsigned long long*)&G->crossings, L.cnt[kCCrossings]);
+    atomicAdd((unsigned long long*)&G->advances, L.cnt[kCAdvances]);
+    atomicAdd((unsigned long long*)&G->voxel_pieces, L.cnt[kCPieces]);
+    atomicAdd((unsigned long long*)&G->kills, L.cnt[kCKills]);
+    atomicAdd((unsigned long long*)&G->stalls, L.cnt[kCStalls]);
+    atomicAdd((unsigned long long*)&G->escapes, L.cnt[kCEscapes]);
+    atomicAdd((unsigned long long*)&G->grid_atomics, L.cnt[kCAtomics]);
+  }
+}
+
+__global__ void zero_u64_kernel(unsigned long long* p) { *p = 0ull; }
+
+__global__ void scale_kernel(const double* __restrict__ in, double* __restrict__ out, size_t n, double s) {
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+    out[i] = in[i] * s;
+}
+
+hipError_t launch_walk(int precision, bool trace, const LaunchCfg& cfg, const WalkArgs& args, hipStream_t stream) {
+  // every pointer the chosen mode dereferences must be set
+  if (!args.sc || !args.pd || !args.pf) return hipErrorInvalidValue;
+  if (trace && (!args.trace_ids || !args.trace_out || !args.trace_count || args.n_trace < 1 || args.max_records < 1))
+    return hipErrorInvalidValue;
+  if (!trace && (!args.counter || !args.absorbed || !args.tallies)) return hipErrorInvalidValue;
+  if (cfg.block < 64 || cfg.block > 256 || cfg.block % 64 || cfg.grid < 1) return hipErrorInvalidConfiguration;
+  dim3 grid(cfg.grid), block(cfg.block);
+  if (precision == 1) {
+    if (trace) hipLaunchKernelGGL((walk_kernel<double, true>), grid, block, 0, stream, args);
+    else hipLaunchKernelGGL((walk_kernel<double, false>), grid, block, 0, stream, args);
+  } else {
+    if (trace) hipLaunchKernelGGL((walk_kernel<float, true>), grid, block, 0, stream, args);
+    else hipLaunchKernelGGL((walk_kernel<float, false>), grid, block, 0, stream, args);
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_zero_u64(unsigned long long* p, hipStream_t stream) {
+  hipLaunchKernelGGL(zero_u64_kernel, dim3(1), dim3(1), 0, stream, p);
+  return hipGetLastError();
+}
+
+hipError_t launch_scale(const double* in, double* out, size_t n, double scale, hipStream_t stream) {
+  size_t blocks = (n + 255) / 256;
+  if (blocks > 65536) blocks = 65536;
+  if (blocks == 0) return hipSuccess;
+  hipLaunchKernelGGL(scale_kernel, dim3((unsigned)blocks), dim3(256), 0, stream, in, out, n, scale);
+  return hipGetLastError();
+}
+
+int walk_max_blocks_per_cu(int precision, int block) {
+  int n = 0;
+  hipError_t e = precision == 1
+                     ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, walk_kernel<double, false>, block, 0)
+                     : hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, walk_kernel<float, false>, block, 0);
+  return e == hipSuccess ? n : 0;
+}
+
+}  // namespace smcrt

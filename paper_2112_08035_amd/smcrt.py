@@ -1,0 +1,370 @@
+"""ctypes binding of libsmcrt (include/smcrt.h).
+
+The ``smcrt_*`` functions mirror the C entry points one to one and only
+marshal arguments; every step of the walk runs in the HIP kernels of
+``libsmcrt.so``.  If the library is missing this module raises: there is no
+CPU fallback.  Device buffers are torch CUDA tensors (ROCm); streams are
+torch streams.
+
+Convenience layer: :class:`Scene` builds a library scene from a scene
+dictionary of :mod:`paper_2112_08035_amd.workloads`, :class:`Engine` owns a
+device engine, and :func:`run` / :func:`trace` allocate outputs and return
+them.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libsmcrt.so")
+
+OK, E_INVALID, E_NOMEM, E_HIP, E_BUDGET, E_CANCELLED, E_STATE = 0, -1, -2, -3, -4, -5, -6
+PRIM = {"sphere": 0, "box": 1, "capsule": 2, "cylinder": 3}
+OP = {"union": 0, "smooth_union": 1}
+SRC = {"point": 0, "pencil": 1, "disc": 2, "rect": 3}
+PREC = {"f32": 0, "f64": 1}
+EVENT_TYPES = ["EMIT", "SCATTER", "ABSORB", "KILL", "REFLECT", "REFRACT", "CROSS", "ESCAPE", "STALL"]
+
+
+class SmcrtError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"smcrt status {status}: {msg}")
+        self.status = status
+
+
+class Tallies(C.Structure):
+    _fields_ = [("launched", C.c_double), ("escaped_face", C.c_double * 6), ("roulette_gain", C.c_double),
+                ("roulette_loss", C.c_double), ("stalled", C.c_double)] + [
+        (n, C.c_uint64) for n in ("events", "steps", "interactions", "interfaces", "reflections", "refractions",
+                                  "crossings", "advances", "voxel_pieces", "kills", "stalls", "escapes",
+                                  "grid_atomics")]
+
+
+class Event(C.Structure):
+    _fields_ = [("event", C.c_uint32), ("type", C.c_uint32), ("region", C.c_int32), ("pad", C.c_int32),
+                ("p", C.c_double * 3), ("u", C.c_double * 3), ("w", C.c_double), ("tau", C.c_double)]
+
+
+class Opts(C.Structure):
+    _fields_ = [("precision", C.c_int32), ("block", C.c_int32), ("blocks_per_cu", C.c_int32),
+                ("refill_min", C.c_int32), ("surface_min", C.c_int32), ("reserved", C.c_int32 * 3)]
+
+
+_lib = None
+_vp = C.c_void_p
+_dp = C.POINTER(C.c_double)
+_SIGS = {
+    "smcrt_last_error": ([], C.c_char_p),
+    "smcrt_abi_version": ([], C.c_int),
+    "smcrt_scene_create": ([C.POINTER(_vp), C.c_double, C.c_double, C.c_double], C.c_int),
+    "smcrt_scene_destroy": ([_vp], C.c_int),
+    "smcrt_scene_add_primitive": ([_vp, C.c_int, _dp, C.c_int, C.POINTER(C.c_int32)], C.c_int),
+    "smcrt_scene_add_region": ([_vp, C.POINTER(C.c_int32), C.c_int, C.c_int, C.c_double, C.c_double, C.c_double,
+                                C.c_double, C.c_double, C.POINTER(C.c_int32)], C.c_int),
+    "smcrt_scene_set_source": ([_vp, C.c_int, _dp, C.c_int], C.c_int),
+    "smcrt_scene_set_grid": ([_vp, _dp, _dp, C.POINTER(C.c_int32)], C.c_int),
+    "smcrt_scene_set_roulette": ([_vp, C.c_double, C.c_int32], C.c_int),
+    "smcrt_scene_set_limits": ([_vp, C.c_int32, C.c_int64], C.c_int),
+    "smcrt_scene_info": ([_vp, C.POINTER(C.c_int32), C.POINTER(C.c_int32), _dp, _dp], C.c_int),
+    "smcrt_engine_create": ([C.POINTER(_vp), C.c_int], C.c_int),
+    "smcrt_engine_destroy": ([_vp], C.c_int),
+    "smcrt_engine_get_opts": ([_vp, C.POINTER(Opts)], C.c_int),
+    "smcrt_engine_set_opts": ([_vp, C.POINTER(Opts)], C.c_int),
+    "smcrt_run": ([_vp, _vp, C.c_uint64, C.c_uint64, C.c_uint64, _vp, _vp, _vp, _vp], C.c_int),
+    "smcrt_normalize_fluence": ([_vp, _vp, C.c_double, _vp, _vp], C.c_int),
+    "smcrt_trace": ([_vp, _vp, C.c_uint64, _vp, C.c_int, C.c_int, _vp, _vp, _vp], C.c_int),
+}
+
+
+def lib():
+    """Loads libsmcrt.so (built in-tree by build_lib.py); raises if absent."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it first (python -m paper_2112_08035_amd.build_lib)")
+        L = C.CDLL(LIB_PATH)
+        for name, (args, res) in _SIGS.items():
+            f = getattr(L, name)
+            f.argtypes = args
+            f.restype = res
+        _lib = L
+    return _lib
+
+
+def _check(st):
+    if st != OK:
+        raise SmcrtError(st, lib().smcrt_last_error().decode())
+
+
+def _darr(vals):
+    return (C.c_double * len(vals))(*[float(v) for v in vals])
+
+
+# ---------------------------------------------------------------- 1:1 ABI
+
+def smcrt_abi_version():
+    return lib().smcrt_abi_version()
+
+
+def smcrt_last_error():
+    return lib().smcrt_last_error().decode()
+
+
+def smcrt_scene_create(n_ambient, delta, pad):
+    h = _vp()
+    _check(lib().smcrt_scene_create(C.byref(h), n_ambient, delta, pad))
+    return h
+
+
+def smcrt_scene_destroy(scene):
+    _check(lib().smcrt_scene_destroy(scene))
+
+
+def smcrt_scene_add_primitive(scene, kind, params):
+    out = C.c_int32()
+    _check(lib().smcrt_scene_add_primitive(scene, kind, _darr(params), len(params), C.byref(out)))
+    return out.value
+
+
+def smcrt_scene_add_region(scene, prims, op, k_cm, mu_a, mu_s, g, n):
+    arr = (C.c_int32 * len(prims))(*[int(p) for p in prims])
+    out = C.c_int32()
+    _check(lib().smcrt_scene_add_region(scene, arr, len(prims), op, k_cm, mu_a, mu_s, g, n, C.byref(out)))
+    return out.value
+
+
+def smcrt_scene_set_source(scene, kind, params):
+    _check(lib().smcrt_scene_set_source(scene, kind, _darr(params), len(params)))
+
+
+def smcrt_scene_set_grid(scene, lo, hi, dims):
+    _check(lib().smcrt_scene_set_grid(scene, _darr(lo), _darr(hi), (C.c_int32 * 3)(*[int(d) for d in dims])))
+
+
+def smcrt_scene_set_roulette(scene, w_threshold, m_survive):
+    _check(lib().smcrt_scene_set_roulette(scene, w_threshold, m_survive))
+
+
+def smcrt_scene_set_limits(scene, max_steps, max_events):
+    _check(lib().smcrt_scene_set_limits(scene, max_steps, max_events))
+
+
+def smcrt_scene_info(scene):
+    nr, npr = C.c_int32(), C.c_int32()
+    lo, hi = (C.c_double * 3)(), (C.c_double * 3)()
+    _check(lib().smcrt_scene_info(scene, C.byref(nr), C.byref(npr), lo, hi))
+    return nr.value, npr.value, np.array(lo[:]), np.array(hi[:])
+
+
+def smcrt_engine_create(device):
+    h = _vp()
+    _check(lib().smcrt_engine_create(C.byref(h), device))
+    return h
+
+
+def smcrt_engine_destroy(engine):
+    _check(lib().smcrt_engine_destroy(engine))
+
+
+def smcrt_engine_get_opts(engine):
+    o = Opts()
+    _check(lib().smcrt_engine_get_opts(engine, C.byref(o)))
+    return o
+
+
+def smcrt_engine_set_opts(engine, opts):
+    _check(lib().smcrt_engine_set_opts(engine, C.byref(opts)))
+
+
+def smcrt_run(engine, scene, seed, first_packet, n_packets, d_fluence_raw, d_absorbed, d_tallies, stream):
+    _check(lib().smcrt_run(engine, scene, seed, first_packet, n_packets, d_fluence_raw, d_absorbed, d_tallies, stream))
+
+
+def smcrt_normalize_fluence(scene, d_raw, launched, d_phi, stream):
+    _check(lib().smcrt_normalize_fluence(scene, d_raw, launched, d_phi, stream))
+
+
+def smcrt_trace(engine, scene, seed, d_packet_ids, n_ids, max_events, d_out, d_count, stream):
+    _check(lib().smcrt_trace(engine, scene, seed, d_packet_ids, n_ids, max_events, d_out, d_count, stream))
+
+
+# ---------------------------------------------------------------- helpers
+
+class Scene:
+    """A library scene built from a workloads scene dictionary."""
+
+    def __init__(self, desc):
+        self.desc = desc
+        self.h = smcrt_scene_create(desc["n_ambient"], desc["delta"], desc["pad"])
+        ids = []
+        for p in desc["prims"]:
+            if p["kind"] == "sphere":
+                vals = list(p["c"]) + [p["r"]]
+            elif p["kind"] == "box":
+                vals = list(p["c"]) + list(p["half"])
+            else:
+                vals = list(p["a"]) + list(p["b"]) + [p["r"]]
+            ids.append(smcrt_scene_add_primitive(self.h, PRIM[p["kind"]], vals))
+        for rg in desc["regions"]:
+            smcrt_scene_add_region(self.h, [ids[i] for i in rg["prims"]], OP[rg["op"]], rg.get("k", 0.0),
+                                   rg["mua"], rg["mus"], rg["g"], rg["n"])
+        s = desc["source"]
+        if s["kind"] == "point":
+            vals = list(s["p"])
+        elif s["kind"] == "pencil":
+            vals = list(s["p"]) + list(s["u"])
+        elif s["kind"] == "disc":
+            vals = list(s["c"]) + [s["r"]] + list(s["u"])
+        else:
+            vals = list(s["c"]) + list(s["half"]) + list(s["u"])
+        smcrt_scene_set_source(self.h, SRC[s["kind"]], vals)
+        g = desc.get("grid")
+        if g:
+            smcrt_scene_set_grid(self.h, g["lo"], g["hi"], g["dims"])
+            self.dims = tuple(int(d) for d in g["dims"])
+        else:
+            smcrt_scene_set_grid(self.h, [0, 0, 0], [1, 1, 1], [0, 0, 0])
+            self.dims = (0, 0, 0)
+        ro = desc["roulette"]
+        smcrt_scene_set_roulette(self.h, ro["w_threshold"], ro["m"])
+        smcrt_scene_set_limits(self.h, desc["max_steps"], desc["max_events"])
+        self.n_regions = len(desc["regions"])
+
+    @property
+    def n_voxels(self):
+        return self.dims[0] * self.dims[1] * self.dims[2]
+
+    def close(self):
+        if self.h:
+            smcrt_scene_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Engine:
+    def __init__(self, device=0, **opts):
+        self.device = device
+        self.h = smcrt_engine_create(device)
+        if opts:
+            self.set_opts(**opts)
+
+    def set_opts(self, precision=None, block=None, blocks_per_cu=None, refill_min=None, surface_min=None):
+        o = smcrt_engine_get_opts(self.h)
+        if precision is not None:
+            o.precision = PREC[precision] if isinstance(precision, str) else int(precision)
+        for k, v in (("block", block), ("blocks_per_cu", blocks_per_cu), ("refill_min", refill_min),
+                     ("surface_min", surface_min)):
+            if v is not None:
+                setattr(o, k, int(v))
+        smcrt_engine_set_opts(self.h, o)
+
+    def opts(self):
+        o = smcrt_engine_get_opts(self.h)
+        return {k: getattr(o, k) for k in ("precision", "block", "blocks_per_cu", "refill_min", "surface_min")}
+
+    def close(self):
+        if self.h:
+            smcrt_engine_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def _stream_ptr(stream):
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return C.c_void_p(s.cuda_stream)
+
+
+class Outputs:
+    """Device outputs of a run (caller-owned, zeroed, accumulated into)."""
+
+    def __init__(self, scene, device=0):
+        import torch
+        dev = torch.device("cuda", device)
+        self.fluence = torch.zeros(max(scene.n_voxels, 1), dtype=torch.float64, device=dev)
+        self.absorbed = torch.zeros(scene.n_regions, dtype=torch.float64, device=dev)
+        self.tallies = torch.zeros(C.sizeof(Tallies), dtype=torch.uint8, device=dev)
+        self.dims = scene.dims
+
+    def zero_(self):
+        self.fluence.zero_()
+        self.absorbed.zero_()
+        self.tallies.zero_()
+        return self
+
+    def ptrs(self):
+        f = C.c_void_p(self.fluence.data_ptr()) if self.dims[0] * self.dims[1] * self.dims[2] else None
+        return f, C.c_void_p(self.absorbed.data_ptr()), C.c_void_p(self.tallies.data_ptr())
+
+    def host(self):
+        """Copies to host: dict of numpy arrays and tally values."""
+        t = Tallies.from_buffer_copy(bytes(self.tallies.cpu().numpy().tobytes()))
+        out = {"launched": t.launched, "escaped_face": np.array(t.escaped_face[:]),
+               "roulette_gain": t.roulette_gain, "roulette_loss": t.roulette_loss, "stalled": t.stalled}
+        for name, _ in Tallies._fields_[5:]:
+            out[name] = int(getattr(t, name))
+        out["absorbed"] = self.absorbed.cpu().numpy()
+        nx, ny, nz = self.dims
+        out["fluence_raw"] = self.fluence.cpu().numpy().reshape(nz, ny, nx) if nx * ny * nz else None
+        return out
+
+
+def launch(engine, scene, seed, n, first=0, outputs=None, stream=None):
+    """Queues one run on the stream; returns the Outputs (not synchronised)."""
+    out = outputs if outputs is not None else Outputs(scene, engine.device)
+    f, a, t = out.ptrs()
+    smcrt_run(engine.h, scene.h, seed, first, n, f, a, t, _stream_ptr(stream))
+    return out
+
+
+def run(desc, seed, n, first=0, engine=None, precision="f32", **opts):
+    """Runs packets [first, first + n) of a scene dictionary on the GPU and
+    returns host copies of the tallies."""
+    import torch
+    eng = engine if engine is not None else Engine(0)
+    eng.set_opts(precision=precision, **opts)
+    sc = desc if isinstance(desc, Scene) else Scene(desc)
+    out = launch(eng, sc, seed, n, first)
+    torch.cuda.synchronize()
+    return out.host()
+
+
+def trace(desc, seed, pids, max_events=50, engine=None, precision="f32"):
+    """Event records of the given packets: list (per packet) of dicts."""
+    import torch
+    eng = engine if engine is not None else Engine(0)
+    eng.set_opts(precision=precision)
+    sc = desc if isinstance(desc, Scene) else Scene(desc)
+    dev = torch.device("cuda", eng.device)
+    ids = torch.tensor(np.asarray(pids, dtype=np.uint64).view(np.int64), device=dev)
+    n = len(pids)
+    out = torch.zeros(n * max_events * C.sizeof(Event), dtype=torch.uint8, device=dev)
+    cnt = torch.zeros(n, dtype=torch.int32, device=dev)
+    smcrt_trace(eng.h, sc.h, seed, C.c_void_p(ids.data_ptr()), n, max_events, C.c_void_p(out.data_ptr()),
+                C.c_void_p(cnt.data_ptr()), _stream_ptr(None))
+    torch.cuda.synchronize()
+    raw = out.cpu().numpy().tobytes()
+    counts = cnt.cpu().numpy()
+    res = []
+    sz = C.sizeof(Event)
+    for i in range(n):
+        evs = []
+        for j in range(int(counts[i])):
+            e = Event.from_buffer_copy(raw[(i * max_events + j) * sz:(i * max_events + j + 1) * sz])
+            evs.append({"event": e.event, "type": EVENT_TYPES[e.type], "region": e.region, "p": np.array(e.p[:]),
+                        "u": np.array(e.u[:]), "w": e.w, "tau": e.tau})
+        res.append(evs)
+    return res
