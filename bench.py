@@ -1,0 +1,223 @@
+#!/usr/bin/env python3
+"""Throughput benchmark of the SDF photon random walk on one MI355X.
+
+Workload: the layered slab -- three stacked boxes 2 x 2 cm laterally,
+0.01 / 0.2 / 1 cm thick (mu_a 1 / 0.2 / 0.1 /cm, mu_s 100 / 200 / 100 /cm,
+g 0.8 / 0.9 / 0.9, n 1.5 / 1.4 / 1.4) in air, a normally incident pencil
+beam, 1e7 packets per step, FP64 fluence on a 200^3 grid.  A step is one
+smcrt_run over 1e7 packets: emission, sphere tracing, interfaces,
+interactions, roulette and the fluence tally, with the scene already
+resident.  Prints one JSON line.
+
+Beside the GPU number: the fluence error against the FP64 oracle on the
+first packets of the same stream, the VALU roofline of the walk kernel and
+the oracle's own throughput on the host cores (a baseline, not a target).
+"""
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "photon packets/s at fixed fluence error vs FP64 oracle; p50/p99 request latency"
+PEAK_LANE_OPS = 256 * 4 * 16 * 2.4e9  # CUs x SIMDs x lanes x clock = 3.93e13 lane-ops/s
+
+# Algorithmic VALU work per unit in lane-slots (full-rate op = 1, quarter-rate
+# transcendental or 32-bit multiply-high = 4, FP64 FMA = 1):
+COST = {
+    "philox": 140,        # one Philox4x32-10 block
+    "log": 8,             # free-path sample
+    "sdf_box": 20,        # one box SDF (sphere 12, capsule 22, cylinder 25)
+    "step_overhead": 12,  # min, abs, compares and the move of one sphere-tracing step
+    "volume": 20,         # simulation-volume SDF per step
+    "interaction": 70,    # absorption, HG, rotation, roulette (FP64 weight)
+    "interface": 250,     # FP64 interface step without its SDF evaluations
+    "surface_sdfs": 14,   # region SDF evaluations in one interface step (2 normals + nearest)
+    "voxel": 15,          # DDA step and run merge per voxel piece
+}
+
+
+def slab_lane_ops(t, n_prims):
+    """lane-slots of one run from its own work counters"""
+    sdf = COST["sdf_box"]
+    per_step = COST["step_overhead"] + n_prims * sdf + COST["volume"]
+    emit = COST["philox"] + COST["log"] + n_prims * sdf
+    inter = COST["interaction"] + COST["philox"] + COST["log"]
+    surf = COST["interface"] + COST["surface_sdfs"] * sdf + n_prims * sdf + COST["philox"]
+    return (t["launched"] * emit + t["steps"] * per_step + t["interactions"] * inter
+            + (t["interfaces"] + t["advances"]) * surf + t["voxel_pieces"] * COST["voxel"])
+
+
+def measured_traffic():
+    """HBM-side bytes per launch from the committed rocprofv3 counter summary,
+    or None when the kernel sources changed since those counters were taken."""
+    import hashlib
+    csrc = os.path.join(ROOT, "paper_2112_08035_amd", "csrc")
+    h = hashlib.sha256()
+    for f in ("walk.hip", "layout.h"):
+        with open(os.path.join(csrc, f), "rb") as fh:
+            h.update(fh.read())
+    path = os.path.join(ROOT, "profiles", "walk_kernel_slab_1e7_f32_traffic.md")
+    if not os.path.exists(path):
+        return None
+    vals = {}
+    for line in open(path):
+        if ":" in line and not line.startswith((" ", "|", "#")):
+            k, v = line.split(":", 1)
+            vals[k.strip()] = v.strip()
+    if vals.get("kernel_source_sha256_16") != h.hexdigest()[:16]:
+        return None
+    return float(vals["traffic_bytes_per_launch"])
+
+
+def copy_calibration(smcrt, desc, steps):
+    import torch
+    sc = smcrt.Scene(desc)
+    n = sc.n_voxels
+    src = torch.ones(n, dtype=torch.float64, device="cuda")
+    dst = torch.empty_like(src)
+    st = torch.cuda.current_stream()
+    ptr = smcrt._stream_ptr(st)
+    smcrt.smcrt_normalize_fluence(sc.h, smcrt.C.c_void_p(src.data_ptr()), 1.0, smcrt.C.c_void_p(dst.data_ptr()), ptr)
+    torch.cuda.synchronize()
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record(st)
+    for _ in range(steps):
+        smcrt.smcrt_normalize_fluence(sc.h, smcrt.C.c_void_p(src.data_ptr()), 1.0, smcrt.C.c_void_p(dst.data_ptr()), ptr)
+    b.record(st)
+    torch.cuda.synchronize()
+    ms = a.elapsed_time(b) / steps
+    print(json.dumps({"copy_calibration": {"bytes_read": 8 * n, "bytes_written": 8 * n, "ms": ms,
+                                           "GB/s": 16 * n / (ms * 1e-3) / 1e9, "launches": steps + 1}}))
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--precision", default="f32", choices=["f32", "f64"])
+    ap.add_argument("--packets", type=float, default=1e7)
+    ap.add_argument("--cpu-seconds", type=float, default=15.0, help="target length of the oracle sample")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the oracle leg (profiling runs)")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only stream the 200^3 FP64 grid through the fluence normalisation kernel "
+                         "(a plain read-once/write-once copy of known size) and report its bandwidth")
+    args = ap.parse_args()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from paper_2112_08035_amd import smcrt, workloads
+
+    desc = workloads.slab_scene()
+    if args.copy_calibration:
+        copy_calibration(smcrt, desc, args.steps)
+        return
+    n = int(args.packets)
+    eng = smcrt.Engine(0, precision=args.precision)
+    sc = smcrt.Scene(desc)
+    out = smcrt.Outputs(sc)
+    stream = torch.cuda.current_stream()
+
+    for w in range(args.warmup):
+        smcrt.launch(eng, sc, 900 + w, n, outputs=out, stream=stream)
+    torch.cuda.synchronize()
+    out.zero_()
+    torch.cuda.synchronize()
+
+    marks = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(args.steps)]
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        marks[k][0].record(stream)
+        smcrt.launch(eng, sc, k, n, outputs=out, stream=stream)
+        marks[k][1].record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    launch_ms = float(np.mean([a.elapsed_time(b) for a, b in marks]))
+    h = out.host()
+    steps = args.steps
+    value = n * steps / wall
+    per = {k: h[k] / steps for k in ("launched", "steps", "interactions", "interfaces", "advances",
+                                      "voxel_pieces", "grid_atomics")}
+    lane_ops = slab_lane_ops(per, len(desc["prims"]))
+    achieved = lane_ops / (launch_ms * 1e-3)
+    identity = (h["absorbed"].sum() + h["escaped_face"].sum() + h["roulette_loss"] - h["roulette_gain"]
+                + h["stalled"] - h["launched"])
+
+    result = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "packets/s",
+        "n_gpus": 1,
+        "steps": steps,
+        "warmup": args.warmup,
+        "ms_per_step": wall / steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": args.precision,
+        "data": "synthetic",
+        "config": {
+            "workload": "layered slab, 3 boxes 2x2 cm (0.01/0.2/1 cm), pencil beam, 1e7 packets/step, 200^3 FP64 fluence grid",
+            "packets_per_step": n,
+            "grid": [200, 200, 200],
+            "transport": args.precision,
+            "tallies": "f64",
+            "launch": eng.opts(),
+        },
+        "per_packet": {k: per[k] / n for k in ("steps", "interactions", "interfaces", "voxel_pieces", "grid_atomics")},
+        "energy_identity_residual": identity / h["launched"],
+        "roofline": {
+            "bound": "alu",
+            "achieved": achieved / 1e12,
+            "peak": PEAK_LANE_OPS / 1e12,
+            "unit": "Tlane-op/s",
+            "frac": achieved / PEAK_LANE_OPS,
+            "traffic": measured_traffic() if args.precision == "f32" else None,
+            "kernel_ms": launch_ms,
+            "lane_ops_per_launch": lane_ops,
+            "grid_atomics_per_s": per["grid_atomics"] / (launch_ms * 1e-3),
+        },
+    }
+
+    if not args.no_cpu:
+        from oracle import oracle as orc
+        threads = os.cpu_count() or 1
+        # calibrate on a run long enough to hide the per-thread grid set-up,
+        # then time a sample of about cpu_seconds
+        t = time.perf_counter()
+        orc.run(desc, 0, 20000)
+        rate0 = 20000 / (time.perf_counter() - t)
+        n_cpu = int(max(20000, min(3_000_000, rate0 * args.cpu_seconds)) // 1000 * 1000)
+        t = time.perf_counter()
+        o = orc.run(desc, 0, n_cpu)
+        cpu_s = time.perf_counter() - t
+        result["cpu_baseline"] = {
+            "value": n_cpu / cpu_s,
+            "unit": "packets/s",
+            "cores": threads,
+            "kind": "oracle",
+            "sample": f"packets [0, {n_cpu}) of the same slab workload, seed 0, FP64 oracle, {cpu_s:.1f} s",
+        }
+        # fluence error of the GPU path on the same packets
+        g = smcrt.run(sc, 0, n_cpu, engine=eng, precision=args.precision)
+        Fo, Fg = o["fluence_raw"], g["fluence_raw"]
+        result["fluence_error"] = {
+            "packets": n_cpu,
+            "relative_l2": float(np.linalg.norm(Fg - Fo) / np.linalg.norm(Fo)),
+            "absorbed_relative": float(abs(g["absorbed"].sum() - o["absorbed"].sum()) / o["absorbed"].sum()),
+        }
+    print(json.dumps(result))
+
+
+if __name__ == "__main__":
+    main()

@@ -470,10 +470,11 @@ extern "C" smcrt_status smcrt_engine_create(smcrt_engine** out, int device) {
 
 extern "C" smcrt_status smcrt_engine_destroy(smcrt_engine* e) {
   if (!e) return SMCRT_OK;
-  hipSetDevice(e->device);
-  hipDeviceSynchronize();
-  if (e->d_blob) hipFree(e->d_blob);
-  if (e->d_counter) hipFree(e->d_counter);
+  // best effort: the engine is going away whatever these return
+  (void)hipSetDevice(e->device);
+  (void)hipDeviceSynchronize();
+  if (e->d_blob) (void)hipFree(e->d_blob);
+  if (e->d_counter) (void)hipFree(e->d_counter);
   delete e;
   return SMCRT_OK;
 }

@@ -408,7 +408,7 @@ __device__ void emit(const WalkArgs& a, Packet<T>& pk, Lane& ln, LdsTallies& L) 
   const int kind = sc->src_kind;
   if (kind == kPoint) {
     const T ct = T(2) * x0 - T(1);
-    const T st = tsqrt(tmax(T(0), T(1) - ct * ct));
+    const T st = T(2) * tsqrt(x0 * (T(1) - x0));  // sqrt(1 - ct^2) without cancellation
     T sp, cp;
     tsincos_2pi(x1, &sp, &cp);
     u = mk(st * cp, st * sp, ct);
@@ -454,19 +454,28 @@ __device__ bool interact(const WalkArgs& a, Packet<T>& pk, Lane& ln, LdsTallies&
     record<T, TRACE>(a, pk, ln, SMCRT_EV_ABSORB);
     return false;
   }
-  // scattering angle from the HG inverse CDF; azimuth uniform
+  // scattering angle from the HG inverse CDF; azimuth uniform.  The CDF is
+  // inverted for 1 - cos(theta) directly,
+  //   1 - cos = (1 - g)(1 - xi)(f + 1 - g) / D,  D = 1 - g + 2 g xi,
+  //   f = (1 - g^2) / D,
+  // which has no cancellation near forward scattering, so FP32 keeps
+  // sin(theta) = sqrt((1 - cos)(1 + cos)) to full relative precision.
   const T x0 = xi_of<T>(r.w0), x1 = xi_of<T>(r.w1);
-  T ct;
+  T omc;
   if (R.iso) {
-    ct = T(2) * x0 - T(1);
+    omc = T(2) * (T(1) - x0);
   } else if constexpr (sizeof(T) == 4) {
-    const float f = tdiv(R.hg_bf, R.hg_cf + R.hg_df * x0);
-    ct = tclamp((R.hg_af - f * f) * R.hg_ef, -1.0f, 1.0f);
+    const float D = R.hg_cf + R.hg_df * x0;
+    const float f = tdiv(R.hg_bf, D);
+    omc = tdiv(R.hg_cf * (1.0f - x0) * (f + R.hg_cf), D);
   } else {
-    const double f = R.hg_b / (R.hg_c + R.hg_d * x0);
-    ct = tclamp((R.hg_a - f * f) / R.hg_d, -1.0, 1.0);
+    const double D = R.hg_c + R.hg_d * x0;
+    const double f = R.hg_b / D;
+    omc = R.hg_c * (1.0 - x0) * (f + R.hg_c) / D;
   }
-  const T st = tsqrt(tmax(T(0), T(1) - ct * ct));
+  omc = tclamp(omc, T(0), T(2));
+  const T ct = T(1) - omc;
+  const T st = tsqrt(omc * (T(2) - omc));
   T sp, cp;
   tsincos_2pi(x1, &sp, &cp);
   const V3<T> u = pk.u;
@@ -474,7 +483,8 @@ __device__ bool interact(const WalkArgs& a, Packet<T>& pk, Lane& ln, LdsTallies&
   if (tabs(u.z) > T(1) - T(1e-5)) {
     v = mk(st * cp, st * sp, (u.z >= T(0) ? ct : -ct));
   } else {
-    const T tt = tsqrt(T(1) - u.z * u.z);
+    // sqrt(1 - uz^2) from the other two components: no cancellation near the poles
+    const T tt = tsqrt(u.x * u.x + u.y * u.y);
     const T itt = T(1) / tt;
     v.x = st * (u.x * u.z * cp - u.y * sp) * itt + u.x * ct;
     v.y = st * (u.y * u.z * cp + u.x * sp) * itt + u.y * ct;
