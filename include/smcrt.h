@@ -109,6 +109,15 @@ smcrt_status smcrt_scene_set_roulette(smcrt_scene* scene, double w_threshold, in
  * tallied as stalled (defaults 100000 and 1000000). */
 smcrt_status smcrt_scene_set_limits(smcrt_scene* scene, int32_t max_steps, int64_t max_events);
 
+/* Uniform-grid acceleration of one union region (Sec. 5 proposes a
+ * space-partitioning structure for large SDF collections).  The grid is the
+ * box of the region's primitives grown by a margin of one cell, cut into
+ * cells[0] x cells[1] x cells[2] cells (1..256 each); it is built on the
+ * device at every run.  A step then evaluates only the primitives listed in
+ * its cell and never steps further than the margin, so results match the
+ * brute-force walk.  region = -1 removes the acceleration. */
+smcrt_status smcrt_scene_set_accel(smcrt_scene* scene, int32_t region, const int32_t cells[3]);
+
 /* number of regions and primitives; bounding box actually used */
 smcrt_status smcrt_scene_info(const smcrt_scene* scene, int32_t* n_regions, int32_t* n_prims,
                               double bb_lo[3], double bb_hi[3]);
@@ -128,8 +137,8 @@ enum { SMCRT_PREC_F32 = 0, SMCRT_PREC_F64 = 1 };
 /* Launch options.  precision: F32 keeps positions, directions, distances and
  * transcendentals in FP32 (interface geometry, Fresnel, weights and tallies
  * stay FP64); F64 runs the whole walk in FP64.  block: threads per workgroup
- * (64..1024, multiple of 64).  blocks_per_cu: resident workgroups per CU
- * the grid is sized for (1..32).  refill_min: dead lanes a wave waits for
+ * (64, 128, 192 or 256).  blocks_per_cu: resident workgroups per CU the
+ * grid is sized for (1..32; 0 = as many as fit).  refill_min: dead lanes a wave waits for
  * before it emits new packets (1..64).  surface_min: lanes a wave gathers at
  * surfaces before it runs the FP64 interface step (1..64). */
 typedef struct {

@@ -1,0 +1,128 @@
+// accel.hip -- device build of the uniform-grid acceleration of one union
+// region (Sec. 5: a space-partitioning structure so that a step need not
+// evaluate every SDF of a large collection).
+//
+// Three passes over the region's primitives, all on the device:
+//   count : every primitive adds 1 to each cell its bounding box, grown by
+//           the margin, overlaps;
+//   scan  : one workgroup turns the counts into CSR offsets;
+//   fill  : every primitive writes its index into those cells' lists.
+// count and fill share one cell-range routine, so they agree exactly; fill
+// still checks every write against the capacity the host allocated.
+#include <hip/hip_runtime.h>
+
+#include "launch.h"
+#include "layout.h"
+
+namespace smcrt {
+
+// conservative box of a packed primitive
+__device__ __forceinline__ void packed_prim_box(const PrimD& P, double lo[3], double hi[3]) {
+  const double* v = P.v;
+  for (int i = 0; i < 3; ++i) {
+    if (P.kind == kSphere) {
+      lo[i] = v[i] - v[3];
+      hi[i] = v[i] + v[3];
+    } else if (P.kind == kBox) {
+      lo[i] = v[i] - v[3 + i];
+      hi[i] = v[i] + v[3 + i];
+    } else if (P.kind == kCapsule) {  // a, b - a, ., r
+      const double b = v[i] + v[3 + i];
+      lo[i] = fmin(v[i], b) - v[7];
+      hi[i] = fmax(v[i], b) + v[7];
+    } else {  // cylinder: a, unit axis, L, L/2, r
+      const double b = v[i] + v[3 + i] * v[6];
+      lo[i] = fmin(v[i], b) - v[8];
+      hi[i] = fmax(v[i], b) + v[8];
+    }
+  }
+}
+
+// inclusive cell range [c0, c1] of a primitive's grown box, clamped
+__device__ __forceinline__ void cell_range(const Accel& A, const PrimD& P, int c0[3], int c1[3]) {
+  double lo[3], hi[3];
+  packed_prim_box(P, lo, hi);
+  for (int i = 0; i < 3; ++i) {
+    const double a = (lo[i] - A.margin - A.lo[i]) * A.inv_cell[i];
+    const double b = (hi[i] + A.margin - A.lo[i]) * A.inv_cell[i];
+    int x0 = (int)floor(fmax(a, -1.0)), x1 = (int)floor(fmin(b, (double)A.dims[i]));
+    x0 = x0 < 0 ? 0 : (x0 >= A.dims[i] ? A.dims[i] - 1 : x0);
+    x1 = x1 < 0 ? 0 : (x1 >= A.dims[i] ? A.dims[i] - 1 : x1);
+    c0[i] = x0;
+    c1[i] = x1;
+  }
+}
+
+__global__ void accel_zero(uint32_t* __restrict__ a, uint32_t* __restrict__ b, int n) {
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+    a[i] = 0u;
+    b[i] = 0u;
+  }
+}
+
+__global__ void accel_count(const SceneHeader* __restrict__ sc, const PrimD* __restrict__ pd, uint32_t* __restrict__ counts) {
+  const Accel& A = sc->acc;
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= A.n_prims) return;
+  int c0[3], c1[3];
+  cell_range(A, pd[A.first_prim + i], c0, c1);
+  for (int z = c0[2]; z <= c1[2]; ++z)
+    for (int y = c0[1]; y <= c1[1]; ++y)
+      for (int x = c0[0]; x <= c1[0]; ++x) atomicAdd(&counts[x + A.dims[0] * (y + A.dims[1] * z)], 1u);
+}
+
+// exclusive scan of counts into offsets[0..n_cells]; one workgroup of 1024
+__global__ void __launch_bounds__(1024) accel_scan(const SceneHeader* __restrict__ sc, const uint32_t* __restrict__ counts,
+                                                   uint32_t* __restrict__ offsets) {
+  __shared__ uint32_t part[1024];
+  const int n = sc->acc.n_cells;
+  const int t = threadIdx.x;
+  const int chunk = (n + 1023) / 1024;
+  const int b = t * chunk, e = min(n, b + chunk);
+  uint32_t s = 0;
+  for (int i = b; i < e; ++i) s += counts[i];
+  part[t] = s;
+  __syncthreads();
+  for (int off = 1; off < 1024; off <<= 1) {  // Hillis-Steele inclusive scan
+    const uint32_t v = t >= off ? part[t - off] : 0u;
+    __syncthreads();
+    part[t] += v;
+    __syncthreads();
+  }
+  uint32_t run = t ? part[t - 1] : 0u;
+  for (int i = b; i < e; ++i) {
+    offsets[i] = run;
+    run += counts[i];
+  }
+  if (t == 1023) offsets[n] = part[1023];
+}
+
+__global__ void accel_fill(const SceneHeader* __restrict__ sc, const PrimD* __restrict__ pd,
+                           const uint32_t* __restrict__ offsets, uint32_t* __restrict__ cursors, uint32_t* __restrict__ ids) {
+  const Accel& A = sc->acc;
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= A.n_prims) return;
+  int c0[3], c1[3];
+  cell_range(A, pd[A.first_prim + i], c0, c1);
+  for (int z = c0[2]; z <= c1[2]; ++z)
+    for (int y = c0[1]; y <= c1[1]; ++y)
+      for (int x = c0[0]; x <= c1[0]; ++x) {
+        const int c = x + A.dims[0] * (y + A.dims[1] * z);
+        const uint64_t slot = (uint64_t)offsets[c] + atomicAdd(&cursors[c], 1u);
+        if (slot < A.capacity) ids[slot] = (uint32_t)(A.first_prim + i);
+      }
+}
+
+hipError_t launch_accel_build(const SceneHeader* d_sc, const PrimD* d_pd, int n_prims, int n_cells, uint32_t* counts,
+                              uint32_t* cursors, uint32_t* offsets, uint32_t* ids, hipStream_t stream) {
+  if (!d_sc || !d_pd || !counts || !cursors || !offsets || !ids || n_prims < 1 || n_cells < 1) return hipErrorInvalidValue;
+  const int zb = (n_cells + 255) / 256;
+  hipLaunchKernelGGL(accel_zero, dim3(zb < 4096 ? zb : 4096), dim3(256), 0, stream, counts, cursors, n_cells);
+  const int pb = (n_prims + 255) / 256;
+  hipLaunchKernelGGL(accel_count, dim3(pb), dim3(256), 0, stream, d_sc, d_pd, counts);
+  hipLaunchKernelGGL(accel_scan, dim3(1), dim3(1024), 0, stream, d_sc, counts, offsets);
+  hipLaunchKernelGGL(accel_fill, dim3(pb), dim3(256), 0, stream, d_sc, d_pd, offsets, cursors, ids);
+  return hipGetLastError();
+}
+
+}  // namespace smcrt

@@ -70,6 +70,8 @@ struct smcrt_scene {
   int32_t m_survive = 10;
   int32_t max_steps = 100000;
   int64_t max_events = 1000000;
+  int32_t accel_region = -1;
+  int32_t accel_cells[3] = {0, 0, 0};
   // packed device tables (rebuilt when dirty)
   bool dirty = true;
   std::vector<unsigned char> blob;
@@ -212,6 +214,24 @@ extern "C" smcrt_status smcrt_scene_set_limits(smcrt_scene* s, int32_t max_steps
   return SMCRT_OK;
 }
 
+extern "C" smcrt_status smcrt_scene_set_accel(smcrt_scene* s, int32_t region, const int32_t cells[3]) {
+  if (!s) return fail(SMCRT_E_INVALID, "set_accel: NULL scene");
+  if (region < 0) {
+    s->accel_region = -1;
+    s->dirty = true;
+    return SMCRT_OK;
+  }
+  if (!cells) return fail(SMCRT_E_INVALID, "set_accel: NULL cells");
+  if (region >= (int32_t)s->regions.size()) return fail(SMCRT_E_INVALID, "set_accel: region %d does not exist", region);
+  if (s->regions[region].op != SMCRT_OP_UNION) return fail(SMCRT_E_INVALID, "set_accel: only union regions can be accelerated");
+  for (int i = 0; i < 3; ++i)
+    if (cells[i] < 1 || cells[i] > 256) return fail(SMCRT_E_INVALID, "set_accel: cells must be in [1, 256] per axis");
+  s->accel_region = region;
+  std::memcpy(s->accel_cells, cells, sizeof(s->accel_cells));
+  s->dirty = true;
+  return SMCRT_OK;
+}
+
 // conservative box of a primitive
 static void prim_box(const HostPrim& p, double lo[3], double hi[3]) {
   for (int i = 0; i < 3; ++i) {
@@ -326,6 +346,66 @@ static void fill_region(Region& r, double mua, double mus, double g, double n, d
   r.hg_ef = (float)r.hg_e;
 }
 
+// grid of the accelerated region: the primitives' box grown by a margin of
+// one cell (the largest cell edge of the ungrown box), cut into the requested
+// cells; capacity bounds the list entries from above (each primitive's cell
+// range widened by one cell per side)
+static smcrt_status pack_accel(const smcrt_scene* s, SceneHeader* h, const std::vector<int>& order) {
+  Accel& A = h->acc;
+  std::memset(&A, 0, sizeof(A));
+  A.region = -1;
+  if (s->accel_region < 0) return SMCRT_OK;
+  const HostRegion& R = s->regions[s->accel_region];
+  if (R.op != SMCRT_OP_UNION) return fail(SMCRT_E_INVALID, "accelerated region must be a union");
+  int first = 0;
+  for (int r = 0; r < s->accel_region; ++r) first += (int)s->regions[r].prims.size();
+  double lo[3] = {1e300, 1e300, 1e300}, hi[3] = {-1e300, -1e300, -1e300};
+  for (int id : R.prims) {
+    double a[3], b[3];
+    prim_box(s->prims[id], a, b);
+    for (int i = 0; i < 3; ++i) { lo[i] = std::min(lo[i], a[i]); hi[i] = std::max(hi[i], b[i]); }
+  }
+  double margin = 0.0;
+  for (int i = 0; i < 3; ++i) margin = std::max(margin, (hi[i] - lo[i]) / s->accel_cells[i]);
+  if (!(margin > 0)) return fail(SMCRT_E_INVALID, "accelerated region has an empty box");
+  A.region = s->accel_region;
+  A.first_prim = first;
+  A.n_prims = (int32_t)R.prims.size();
+  A.margin = margin;
+  A.marginf = (float)margin;
+  int64_t cells = 1;
+  for (int i = 0; i < 3; ++i) {
+    A.dims[i] = s->accel_cells[i];
+    cells *= A.dims[i];
+    A.lo[i] = lo[i] - margin;
+    A.inv_cell[i] = A.dims[i] / (hi[i] - lo[i] + 2.0 * margin);
+    A.box_lo[i] = lo[i];
+    A.box_hi[i] = hi[i];
+    A.lof[i] = (float)A.lo[i];
+    A.inv_cellf[i] = (float)A.inv_cell[i];
+    A.box_lof[i] = (float)lo[i];
+    A.box_hif[i] = (float)hi[i];
+  }
+  A.n_cells = (int32_t)cells;
+  uint64_t cap = 0;
+  for (int id : R.prims) {
+    double a[3], b[3];
+    prim_box(s->prims[id], a, b);
+    uint64_t c = 1;
+    for (int i = 0; i < 3; ++i) {
+      int x0 = (int)std::floor((a[i] - margin - A.lo[i]) * A.inv_cell[i]) - 1;
+      int x1 = (int)std::floor((b[i] + margin - A.lo[i]) * A.inv_cell[i]) + 1;
+      x0 = std::max(x0, 0);
+      x1 = std::min(x1, A.dims[i] - 1);
+      c *= (uint64_t)std::max(x1 - x0 + 1, 1);
+    }
+    cap += c;
+  }
+  A.capacity = cap;
+  (void)order;
+  return SMCRT_OK;
+}
+
 static smcrt_status pack(smcrt_scene* s) {
   if (!s->dirty) return SMCRT_OK;
   smcrt_status st = check_complete(s);
@@ -394,6 +474,8 @@ static smcrt_status pack(smcrt_scene* s) {
   h->inv_m = 1.0 / (double)s->m_survive;
   h->max_steps = s->max_steps;
   h->max_events = s->max_events;
+  st = pack_accel(s, h, order);
+  if (st != SMCRT_OK) return st;
   h->prim_offset_d = off_d;
   h->prim_offset_f = off_f;
   h->blob_bytes = bytes;
@@ -425,6 +507,9 @@ struct smcrt_engine {
   void* d_blob = nullptr;
   size_t blob_cap = 0;
   unsigned long long* d_counter = nullptr;
+  // uniform-grid buffers of the accelerated region
+  uint32_t *d_acc_counts = nullptr, *d_acc_cursors = nullptr, *d_acc_offsets = nullptr, *d_acc_ids = nullptr;
+  size_t acc_cells_cap = 0, acc_ids_cap = 0;
 };
 
 static void default_opts(smcrt_opts* o) {
@@ -439,7 +524,7 @@ static void default_opts(smcrt_opts* o) {
 static smcrt_status check_opts(const smcrt_opts* o) {
   if (o->precision != SMCRT_PREC_F32 && o->precision != SMCRT_PREC_F64)
     return fail(SMCRT_E_INVALID, "opts: unknown precision %d", o->precision);
-  if (o->block < 64 || o->block > 1024 || o->block % 64) return fail(SMCRT_E_INVALID, "opts: block must be a multiple of 64 in [64, 1024]");
+  if (o->block < 64 || o->block > 256 || o->block % 64) return fail(SMCRT_E_INVALID, "opts: block must be 64, 128, 192 or 256");
   if (o->blocks_per_cu < 0 || o->blocks_per_cu > 32) return fail(SMCRT_E_INVALID, "opts: blocks_per_cu must be in [0, 32]");
   if (o->refill_min < 1 || o->refill_min > 64) return fail(SMCRT_E_INVALID, "opts: refill_min must be in [1, 64]");
   if (o->surface_min < 1 || o->surface_min > 64) return fail(SMCRT_E_INVALID, "opts: surface_min must be in [1, 64]");
@@ -474,6 +559,10 @@ extern "C" smcrt_status smcrt_engine_destroy(smcrt_engine* e) {
   (void)hipSetDevice(e->device);
   (void)hipDeviceSynchronize();
   if (e->d_blob) (void)hipFree(e->d_blob);
+  if (e->d_acc_counts) (void)hipFree(e->d_acc_counts);
+  if (e->d_acc_cursors) (void)hipFree(e->d_acc_cursors);
+  if (e->d_acc_offsets) (void)hipFree(e->d_acc_offsets);
+  if (e->d_acc_ids) (void)hipFree(e->d_acc_ids);
   if (e->d_counter) (void)hipFree(e->d_counter);
   delete e;
   return SMCRT_OK;
@@ -513,6 +602,42 @@ static smcrt_status upload(smcrt_engine* e, smcrt_scene* s, hipStream_t st) {
   return SMCRT_OK;
 }
 
+// builds the uniform grid of the scene's accelerated region on the device
+// (stream ordered after the table upload)
+static smcrt_status build_accel(smcrt_engine* e, const smcrt_scene* s, hipStream_t st) {
+  const SceneHeader* h = reinterpret_cast<const SceneHeader*>(s->blob.data());
+  const Accel& A = h->acc;
+  if (A.region < 0) return SMCRT_OK;
+  const size_t cells = (size_t)A.n_cells;
+  if (cells + 1 > e->acc_cells_cap || A.capacity > e->acc_ids_cap) {
+    HIP_TRY(hipStreamSynchronize(st), "hipStreamSynchronize");
+    if (cells + 1 > e->acc_cells_cap) {
+      if (e->d_acc_counts) HIP_TRY(hipFree(e->d_acc_counts), "hipFree");
+      if (e->d_acc_cursors) HIP_TRY(hipFree(e->d_acc_cursors), "hipFree");
+      if (e->d_acc_offsets) HIP_TRY(hipFree(e->d_acc_offsets), "hipFree");
+      e->d_acc_counts = e->d_acc_cursors = e->d_acc_offsets = nullptr;
+      e->acc_cells_cap = 0;
+      HIP_TRY(hipMalloc(&e->d_acc_counts, sizeof(uint32_t) * (cells + 1)), "hipMalloc(accel)");
+      HIP_TRY(hipMalloc(&e->d_acc_cursors, sizeof(uint32_t) * (cells + 1)), "hipMalloc(accel)");
+      HIP_TRY(hipMalloc(&e->d_acc_offsets, sizeof(uint32_t) * (cells + 1)), "hipMalloc(accel)");
+      e->acc_cells_cap = cells + 1;
+    }
+    if (A.capacity > e->acc_ids_cap) {
+      if (e->d_acc_ids) HIP_TRY(hipFree(e->d_acc_ids), "hipFree");
+      e->d_acc_ids = nullptr;
+      e->acc_ids_cap = 0;
+      HIP_TRY(hipMalloc(&e->d_acc_ids, sizeof(uint32_t) * A.capacity), "hipMalloc(accel ids)");
+      e->acc_ids_cap = A.capacity;
+    }
+  }
+  const SceneHeader* d_sc = reinterpret_cast<const SceneHeader*>(e->d_blob);
+  const PrimD* d_pd = reinterpret_cast<const PrimD*>((const char*)e->d_blob + h->prim_offset_d);
+  HIP_TRY(launch_accel_build(d_sc, d_pd, A.n_prims, A.n_cells, e->d_acc_counts, e->d_acc_cursors, e->d_acc_offsets,
+                             e->d_acc_ids, st),
+          "accel build");
+  return SMCRT_OK;
+}
+
 static WalkArgs base_args(smcrt_engine* e, const smcrt_scene* s) {
   WalkArgs a;
   std::memset(&a, 0, sizeof(a));
@@ -521,6 +646,8 @@ static WalkArgs base_args(smcrt_engine* e, const smcrt_scene* s) {
   a.pd = reinterpret_cast<const PrimD*>((const char*)e->d_blob + h->prim_offset_d);
   a.pf = reinterpret_cast<const PrimF*>((const char*)e->d_blob + h->prim_offset_f);
   a.counter = e->d_counter;
+  a.acc_offsets = e->d_acc_offsets;
+  a.acc_ids = e->d_acc_ids;
   a.refill_min = e->opts.refill_min;
   a.surface_min = e->opts.surface_min;
   return a;
@@ -554,6 +681,8 @@ extern "C" smcrt_status smcrt_run(smcrt_engine* e, const smcrt_scene* scene, uin
   hipStream_t stream = (hipStream_t)hip_stream;
   st = upload(e, s, stream);
   if (st != SMCRT_OK) return st;
+  st = build_accel(e, s, stream);
+  if (st != SMCRT_OK) return st;
   WalkArgs a = base_args(e, s);
   a.seed = seed;
   a.first = first_packet;
@@ -578,6 +707,8 @@ extern "C" smcrt_status smcrt_trace(smcrt_engine* e, const smcrt_scene* scene, u
   HIP_TRY(hipSetDevice(e->device), "hipSetDevice");
   hipStream_t stream = (hipStream_t)hip_stream;
   st = upload(e, s, stream);
+  if (st != SMCRT_OK) return st;
+  st = build_accel(e, s, stream);
   if (st != SMCRT_OK) return st;
   WalkArgs a = base_args(e, s);
   a.seed = seed;

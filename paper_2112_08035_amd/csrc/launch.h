@@ -12,6 +12,10 @@ hipError_t launch_walk(int precision, bool trace, const LaunchCfg& cfg, const Wa
 hipError_t launch_zero_u64(unsigned long long* p, hipStream_t stream);
 // out[i] = in[i] * scale for i < n
 hipError_t launch_scale(const double* in, double* out, size_t n, double scale, hipStream_t stream);
+// device build of the uniform grid of the accelerated region (counts and
+// cursors: n_cells each; offsets: n_cells + 1; ids: the capacity in the header)
+hipError_t launch_accel_build(const SceneHeader* d_sc, const PrimD* d_pd, int n_prims, int n_cells, uint32_t* counts,
+                              uint32_t* cursors, uint32_t* offsets, uint32_t* ids, hipStream_t stream);
 // resident workgroups per CU of the walk kernel at this block size
 int walk_max_blocks_per_cu(int precision, int block);
 

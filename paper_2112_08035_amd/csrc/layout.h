@@ -43,6 +43,23 @@ struct Region {
   float kf, inv_kf, mutf, inv_mutf, gf, hg_af, hg_bf, hg_cf, hg_df, hg_ef;
 };
 
+// Uniform-grid acceleration of one union region with many primitives (the
+// space partitioning proposed in Sec. 5 against evaluating every SDF at every
+// step).  Cell c lists the primitives whose bounding box grown by `margin`
+// overlaps c; a query returns min(margin, min over the listed primitives),
+// which equals the region SDF wherever that is below margin and is a lower
+// bound elsewhere.  Built on the device into the engine's accel buffers.
+struct Accel {
+  int32_t region;                 // accelerated region, -1 = none
+  int32_t dims[3];
+  int32_t n_cells, first_prim, n_prims, pad;
+  uint64_t capacity;              // entries the id list can hold
+  double lo[3], inv_cell[3], margin;
+  double box_lo[3], box_hi[3];    // bounding box of the region's primitives
+  float lof[3], inv_cellf[3], marginf, padf;
+  float box_lof[3], box_hif[3];
+};
+
 struct SceneHeader {
   int32_t n_prims, n_regions;     // the ambient medium is region slot n_regions
   int32_t has_grid, src_kind;
@@ -58,6 +75,7 @@ struct SceneHeader {
   double w_threshold, m_d, inv_m;
   float deltaf, pad1;
   Region reg[kMaxRegions + 1];
+  Accel acc;
   uint64_t prim_offset_d, prim_offset_f;  // byte offsets of the tables in the blob
   uint64_t blob_bytes;
 };
@@ -79,6 +97,8 @@ struct WalkArgs {
   unsigned long long* counter;   // packets handed out so far (zeroed before launch)
   double* fluence;               // nx*ny*nz, may be null
   double* absorbed;              // n_regions
+  const uint32_t* acc_offsets;   // n_cells + 1 (accelerated scenes)
+  const uint32_t* acc_ids;       // capacity
   void* tallies;                 // smcrt_tallies
   // trace mode
   const uint64_t* trace_ids;

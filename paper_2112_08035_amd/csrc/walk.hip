@@ -124,6 +124,11 @@ struct Tab<float> {
   static __device__ __forceinline__ V3<float> g_lo(const SceneHeader* s) { return {s->g_lof[0], s->g_lof[1], s->g_lof[2]}; }
   static __device__ __forceinline__ V3<float> g_inv(const SceneHeader* s) { return {s->g_inv_df[0], s->g_inv_df[1], s->g_inv_df[2]}; }
   static __device__ __forceinline__ float delta(const SceneHeader* s) { return s->deltaf; }
+  static __device__ __forceinline__ V3<float> acc_lo(const Accel& A) { return {A.lof[0], A.lof[1], A.lof[2]}; }
+  static __device__ __forceinline__ V3<float> acc_inv(const Accel& A) { return {A.inv_cellf[0], A.inv_cellf[1], A.inv_cellf[2]}; }
+  static __device__ __forceinline__ V3<float> acc_blo(const Accel& A) { return {A.box_lof[0], A.box_lof[1], A.box_lof[2]}; }
+  static __device__ __forceinline__ V3<float> acc_bhi(const Accel& A) { return {A.box_hif[0], A.box_hif[1], A.box_hif[2]}; }
+  static __device__ __forceinline__ float acc_margin(const Accel& A) { return A.marginf; }
 };
 template <>
 struct Tab<double> {
@@ -137,6 +142,11 @@ struct Tab<double> {
   static __device__ __forceinline__ V3<double> g_lo(const SceneHeader* s) { return {s->g_lo[0], s->g_lo[1], s->g_lo[2]}; }
   static __device__ __forceinline__ V3<double> g_inv(const SceneHeader* s) { return {s->g_inv_d[0], s->g_inv_d[1], s->g_inv_d[2]}; }
   static __device__ __forceinline__ double delta(const SceneHeader* s) { return s->delta; }
+  static __device__ __forceinline__ V3<double> acc_lo(const Accel& A) { return {A.lo[0], A.lo[1], A.lo[2]}; }
+  static __device__ __forceinline__ V3<double> acc_inv(const Accel& A) { return {A.inv_cell[0], A.inv_cell[1], A.inv_cell[2]}; }
+  static __device__ __forceinline__ V3<double> acc_blo(const Accel& A) { return {A.box_lo[0], A.box_lo[1], A.box_lo[2]}; }
+  static __device__ __forceinline__ V3<double> acc_bhi(const Accel& A) { return {A.box_hi[0], A.box_hi[1], A.box_hi[2]}; }
+  static __device__ __forceinline__ double acc_margin(const Accel& A) { return A.margin; }
 };
 
 // exact Euclidean SDF of one primitive (Sec. 2.2; Eq. 3 for the sphere)
@@ -184,6 +194,48 @@ __device__ __forceinline__ T region_sdf(const WalkArgs& a, const Region& R, V3<T
   return d;
 }
 
+// SDF of the accelerated region through its uniform grid: min(margin, min
+// over the primitives listed in p's cell).  Equal to the region SDF where
+// that is below the margin, a lower bound elsewhere; outside the grid box
+// (which is the primitives' box grown by the margin) the distance to the
+// primitives' box is the lower bound.  Every index is checked.
+template <typename T>
+__device__ __forceinline__ T accel_sdf(const WalkArgs& a, V3<T> p) {
+  const Accel& A = a.sc->acc;
+  const V3<T> lo = Tab<T>::acc_lo(A), ic = Tab<T>::acc_inv(A);
+  const T cx = (p.x - lo.x) * ic.x, cy = (p.y - lo.y) * ic.y, cz = (p.z - lo.z) * ic.z;
+  const int dx = A.dims[0], dy = A.dims[1], dz = A.dims[2];
+  if (!(cx >= T(0) && cy >= T(0) && cz >= T(0) && cx < T(dx) && cy < T(dy) && cz < T(dz))) {
+    const V3<T> bl = Tab<T>::acc_blo(A), bh = Tab<T>::acc_bhi(A);
+    const V3<T> o = mk(tmax(tmax(bl.x - p.x, p.x - bh.x), T(0)), tmax(tmax(bl.y - p.y, p.y - bh.y), T(0)),
+                       tmax(tmax(bl.z - p.z, p.z - bh.z), T(0)));
+    return tsqrt(dot(o, o));
+  }
+  int ix = (int)cx, iy = (int)cy, iz = (int)cz;
+  ix = ix < dx ? ix : dx - 1;
+  iy = iy < dy ? iy : dy - 1;
+  iz = iz < dz ? iz : dz - 1;
+  const int c = ix + dx * (iy + dy * iz);
+  const uint32_t b = a.acc_offsets[c];
+  uint64_t e = a.acc_offsets[c + 1];
+  e = e < A.capacity ? e : A.capacity;
+  const Prim<T>* __restrict__ P = Tab<T>::prims(a);
+  const uint32_t lo_id = (uint32_t)A.first_prim, hi_id = (uint32_t)(A.first_prim + A.n_prims);
+  T d = Tab<T>::acc_margin(A);
+  for (uint64_t i = b; i < e; ++i) {
+    const uint32_t id = a.acc_ids[i];
+    if (id >= lo_id && id < hi_id) d = tmin(d, prim_sdf(P, (int)id, p));
+  }
+  return d;
+}
+
+// SDF of region r (through the grid when r is the accelerated region)
+template <typename T>
+__device__ __forceinline__ T region_dist(const WalkArgs& a, int r, V3<T> p) {
+  if (r == a.sc->acc.region) return accel_sdf<T>(a, p);
+  return region_sdf<T>(a, a.sc->reg[r], p);
+}
+
 // owner of a point: the highest-index region with a negative SDF, else the
 // ambient slot n_regions
 template <typename T>
@@ -192,7 +244,7 @@ __device__ __forceinline__ int region_of(const WalkArgs& a, V3<T> p) {
   const int nr = sc->n_regions;
   int owner = nr;
   for (int r = nr - 1; r >= 0; --r) {
-    if (region_sdf<T>(a, sc->reg[r], p) < T(0)) {
+    if (region_dist<T>(a, r, p) < T(0)) {
       owner = r;
       break;
     }
@@ -217,11 +269,11 @@ __device__ __forceinline__ T volume_sdf(const SceneHeader* sc, V3<T> p, int* fac
 }
 
 // unit outward normal of region R at p by central differences of step h
-__device__ __forceinline__ V3<double> region_normal(const WalkArgs& a, const Region& R, V3<double> p, double h) {
+__device__ __forceinline__ V3<double> region_normal(const WalkArgs& a, int r, V3<double> p, double h) {
   V3<double> n;
-  n.x = region_sdf<double>(a, R, mk(p.x + h, p.y, p.z)) - region_sdf<double>(a, R, mk(p.x - h, p.y, p.z));
-  n.y = region_sdf<double>(a, R, mk(p.x, p.y + h, p.z)) - region_sdf<double>(a, R, mk(p.x, p.y - h, p.z));
-  n.z = region_sdf<double>(a, R, mk(p.x, p.y, p.z + h)) - region_sdf<double>(a, R, mk(p.x, p.y, p.z - h));
+  n.x = region_dist<double>(a, r, mk(p.x + h, p.y, p.z)) - region_dist<double>(a, r, mk(p.x - h, p.y, p.z));
+  n.y = region_dist<double>(a, r, mk(p.x, p.y + h, p.z)) - region_dist<double>(a, r, mk(p.x, p.y - h, p.z));
+  n.z = region_dist<double>(a, r, mk(p.x, p.y, p.z + h)) - region_dist<double>(a, r, mk(p.x, p.y, p.z - h));
   const double inv = 1.0 / __builtin_sqrt(dot(n, n));
   return inv * n;
 }
@@ -520,17 +572,16 @@ __device__ void surface(const WalkArgs& a, Packet<T>& pk, Lane& ln, LdsTallies& 
   const V3<double> p = to_d(pk.p), u = to_d(pk.u);
   const int nr = sc->n_regions;
   int j = 0;
-  double dj = region_sdf<double>(a, sc->reg[0], p);
+  double dj = region_dist<double>(a, 0, p);
   for (int r = 1; r < nr; ++r) {
-    const double d = region_sdf<double>(a, sc->reg[r], p);
+    const double d = region_dist<double>(a, r, p);
     if (__builtin_fabs(d) < __builtin_fabs(dj)) {
       dj = d;
       j = r;
     }
   }
-  const Region& Rj = sc->reg[j];
   const double h = sc->h_normal, off = sc->offset;
-  const V3<double> n0 = region_normal(a, Rj, p, h);
+  const V3<double> n0 = region_normal(a, j, p, h);
   const double c0 = dot(u, n0);
   double t_ray = 0.0;
   V3<double> ps;
@@ -540,7 +591,7 @@ __device__ void surface(const WalkArgs& a, Packet<T>& pk, Lane& ln, LdsTallies& 
   } else {
     ps = p - dj * n0;
   }
-  const V3<double> nrm = region_normal(a, Rj, ps, h);
+  const V3<double> nrm = region_normal(a, j, ps, h);
   const double c = dot(u, nrm);
   const double sg = c > 0.0 ? 1.0 : -1.0;
   const V3<double> q = ps + (sg * off) * nrm;
@@ -695,7 +746,7 @@ __global__ void __launch_bounds__(256) walk_kernel(WalkArgs a) {
       } else {
         ++ln.n_steps;
         T dmin = tinf<T>();
-        for (int r = 0; r < nr; ++r) dmin = tmin(dmin, tabs(region_sdf<T>(a, sc->reg[r], pk.p)));
+        for (int r = 0; r < nr; ++r) dmin = tmin(dmin, tabs(region_dist<T>(a, r, pk.p)));
         int face;
         const T dbb = volume_sdf<T>(sc, pk.p, &face);
         if (dbb > T(0)) {  // outside the simulation volume

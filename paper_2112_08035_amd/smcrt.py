@@ -68,6 +68,7 @@ _SIGS = {
     "smcrt_scene_set_grid": ([_vp, _dp, _dp, C.POINTER(C.c_int32)], C.c_int),
     "smcrt_scene_set_roulette": ([_vp, C.c_double, C.c_int32], C.c_int),
     "smcrt_scene_set_limits": ([_vp, C.c_int32, C.c_int64], C.c_int),
+    "smcrt_scene_set_accel": ([_vp, C.c_int32, C.POINTER(C.c_int32)], C.c_int),
     "smcrt_scene_info": ([_vp, C.POINTER(C.c_int32), C.POINTER(C.c_int32), _dp, _dp], C.c_int),
     "smcrt_engine_create": ([C.POINTER(_vp), C.c_int], C.c_int),
     "smcrt_engine_destroy": ([_vp], C.c_int),
@@ -152,6 +153,10 @@ def smcrt_scene_set_limits(scene, max_steps, max_events):
     _check(lib().smcrt_scene_set_limits(scene, max_steps, max_events))
 
 
+def smcrt_scene_set_accel(scene, region, cells):
+    _check(lib().smcrt_scene_set_accel(scene, region, (C.c_int32 * 3)(*[int(c) for c in cells]) if cells else None))
+
+
 def smcrt_scene_info(scene):
     nr, npr = C.c_int32(), C.c_int32()
     lo, hi = (C.c_double * 3)(), (C.c_double * 3)()
@@ -231,6 +236,12 @@ class Scene:
         ro = desc["roulette"]
         smcrt_scene_set_roulette(self.h, ro["w_threshold"], ro["m"])
         smcrt_scene_set_limits(self.h, desc["max_steps"], desc["max_events"])
+        if desc.get("accel_cells"):
+            # accelerate the union region with the most primitives
+            counts = [len(rg["prims"]) if rg["op"] == "union" else 0 for rg in desc["regions"]]
+            r = max(range(len(counts)), key=lambda i: counts[i])
+            if counts[r] > 1:
+                smcrt_scene_set_accel(self.h, r, desc["accel_cells"])
         self.n_regions = len(desc["regions"])
 
     @property
