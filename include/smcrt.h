@@ -190,6 +190,18 @@ smcrt_status smcrt_run(smcrt_engine* engine, const smcrt_scene* scene, uint64_t 
                        uint64_t first_packet, uint64_t n_packets, double* d_fluence_raw,
                        double* d_absorbed, smcrt_tallies* d_tallies, void* hip_stream);
 
+/* Batched runs: job j runs packets [first_packets[j], first_packets[j] +
+ * n_packets[j]) of scenes[j] with seeds[j] into its own outputs, all jobs in
+ * ONE persistent launch.  Waves spread over the jobs in proportion and move
+ * to jobs with packets left when theirs are handed out, so many small scenes
+ * fill the device together.  Host arrays of length n; first_packets may be
+ * NULL (all 0); jobs with n_packets[j] = 0 are skipped; the same scene may
+ * appear in several jobs.  Output rules as for smcrt_run (per job).  Each
+ * job's result equals its smcrt_run alone up to FP64 summation order. */
+smcrt_status smcrt_run_batch(smcrt_engine* engine, int n, const smcrt_scene* const* scenes, const uint64_t* seeds,
+                             const uint64_t* first_packets, const uint64_t* n_packets, double* const* d_fluence_raw,
+                             double* const* d_absorbed, smcrt_tallies* const* d_tallies, void* hip_stream);
+
 /* Fluence normalisation: d_phi[v] = d_raw[v] / (launched * voxel volume),
  * in cm^-2 per launched unit weight.  d_raw and d_phi: device, nx*ny*nz
  * doubles (may alias). */

@@ -504,12 +504,17 @@ struct smcrt_engine {
   int device = 0;
   int n_cu = 0;
   smcrt_opts opts;
-  void* d_blob = nullptr;
-  size_t blob_cap = 0;
-  unsigned long long* d_counter = nullptr;
-  // uniform-grid buffers of the accelerated region
-  uint32_t *d_acc_counts = nullptr, *d_acc_cursors = nullptr, *d_acc_offsets = nullptr, *d_acc_ids = nullptr;
-  size_t acc_cells_cap = 0, acc_ids_cap = 0;
+  // one device arena per engine: scene tables, job table, per-job packet
+  // counters and the uniform-grid buffers, laid out afresh at every launch
+  void* d_arena = nullptr;
+  size_t arena_cap = 0;
+  std::vector<unsigned char> image;  // host copy of the arena's uploaded prefix
+  // pinned staging of that prefix; stage_done marks when the last upload
+  // from it has been consumed by the device
+  void* h_stage = nullptr;
+  size_t stage_cap = 0;
+  hipEvent_t stage_done = nullptr;
+  bool stage_pending = false;
 };
 
 static void default_opts(smcrt_opts* o) {
@@ -517,7 +522,7 @@ static void default_opts(smcrt_opts* o) {
   o->precision = SMCRT_PREC_F32;
   o->block = 256;
   o->blocks_per_cu = 0;  // 0 = as many as fit
-  o->refill_min = 16;
+  o->refill_min = 4;
   o->surface_min = 8;
 }
 
@@ -544,11 +549,6 @@ extern "C" smcrt_status smcrt_engine_create(smcrt_engine** out, int device) {
   e->device = device;
   e->n_cu = prop.multiProcessorCount;
   default_opts(&e->opts);
-  hipError_t err = hipMalloc(&e->d_counter, 256);
-  if (err != hipSuccess) {
-    delete e;
-    return hip_fail(err, "hipMalloc(counter)");
-  }
   *out = e;
   return SMCRT_OK;
 }
@@ -558,12 +558,9 @@ extern "C" smcrt_status smcrt_engine_destroy(smcrt_engine* e) {
   // best effort: the engine is going away whatever these return
   (void)hipSetDevice(e->device);
   (void)hipDeviceSynchronize();
-  if (e->d_blob) (void)hipFree(e->d_blob);
-  if (e->d_acc_counts) (void)hipFree(e->d_acc_counts);
-  if (e->d_acc_cursors) (void)hipFree(e->d_acc_cursors);
-  if (e->d_acc_offsets) (void)hipFree(e->d_acc_offsets);
-  if (e->d_acc_ids) (void)hipFree(e->d_acc_ids);
-  if (e->d_counter) (void)hipFree(e->d_counter);
+  if (e->d_arena) (void)hipFree(e->d_arena);
+  if (e->h_stage) (void)hipHostFree(e->h_stage);
+  if (e->stage_done) (void)hipEventDestroy(e->stage_done);
   delete e;
   return SMCRT_OK;
 }
@@ -582,77 +579,6 @@ extern "C" smcrt_status smcrt_engine_set_opts(smcrt_engine* e, const smcrt_opts*
   return SMCRT_OK;
 }
 
-// upload the packed tables of a scene (stream ordered; the host copy is
-// consumed before the call returns because the source is pageable memory)
-static smcrt_status upload(smcrt_engine* e, smcrt_scene* s, hipStream_t st) {
-  smcrt_status r = pack(s);
-  if (r != SMCRT_OK) return r;
-  size_t bytes = s->blob.size();
-  if (bytes > e->blob_cap) {
-    if (e->d_blob) {
-      HIP_TRY(hipStreamSynchronize(st), "hipStreamSynchronize");
-      HIP_TRY(hipFree(e->d_blob), "hipFree");
-      e->d_blob = nullptr;
-      e->blob_cap = 0;
-    }
-    HIP_TRY(hipMalloc(&e->d_blob, bytes), "hipMalloc(scene tables)");
-    e->blob_cap = bytes;
-  }
-  HIP_TRY(hipMemcpyAsync(e->d_blob, s->blob.data(), bytes, hipMemcpyHostToDevice, st), "hipMemcpyAsync(scene tables)");
-  return SMCRT_OK;
-}
-
-// builds the uniform grid of the scene's accelerated region on the device
-// (stream ordered after the table upload)
-static smcrt_status build_accel(smcrt_engine* e, const smcrt_scene* s, hipStream_t st) {
-  const SceneHeader* h = reinterpret_cast<const SceneHeader*>(s->blob.data());
-  const Accel& A = h->acc;
-  if (A.region < 0) return SMCRT_OK;
-  const size_t cells = (size_t)A.n_cells;
-  if (cells + 1 > e->acc_cells_cap || A.capacity > e->acc_ids_cap) {
-    HIP_TRY(hipStreamSynchronize(st), "hipStreamSynchronize");
-    if (cells + 1 > e->acc_cells_cap) {
-      if (e->d_acc_counts) HIP_TRY(hipFree(e->d_acc_counts), "hipFree");
-      if (e->d_acc_cursors) HIP_TRY(hipFree(e->d_acc_cursors), "hipFree");
-      if (e->d_acc_offsets) HIP_TRY(hipFree(e->d_acc_offsets), "hipFree");
-      e->d_acc_counts = e->d_acc_cursors = e->d_acc_offsets = nullptr;
-      e->acc_cells_cap = 0;
-      HIP_TRY(hipMalloc(&e->d_acc_counts, sizeof(uint32_t) * (cells + 1)), "hipMalloc(accel)");
-      HIP_TRY(hipMalloc(&e->d_acc_cursors, sizeof(uint32_t) * (cells + 1)), "hipMalloc(accel)");
-      HIP_TRY(hipMalloc(&e->d_acc_offsets, sizeof(uint32_t) * (cells + 1)), "hipMalloc(accel)");
-      e->acc_cells_cap = cells + 1;
-    }
-    if (A.capacity > e->acc_ids_cap) {
-      if (e->d_acc_ids) HIP_TRY(hipFree(e->d_acc_ids), "hipFree");
-      e->d_acc_ids = nullptr;
-      e->acc_ids_cap = 0;
-      HIP_TRY(hipMalloc(&e->d_acc_ids, sizeof(uint32_t) * A.capacity), "hipMalloc(accel ids)");
-      e->acc_ids_cap = A.capacity;
-    }
-  }
-  const SceneHeader* d_sc = reinterpret_cast<const SceneHeader*>(e->d_blob);
-  const PrimD* d_pd = reinterpret_cast<const PrimD*>((const char*)e->d_blob + h->prim_offset_d);
-  HIP_TRY(launch_accel_build(d_sc, d_pd, A.n_prims, A.n_cells, e->d_acc_counts, e->d_acc_cursors, e->d_acc_offsets,
-                             e->d_acc_ids, st),
-          "accel build");
-  return SMCRT_OK;
-}
-
-static WalkArgs base_args(smcrt_engine* e, const smcrt_scene* s) {
-  WalkArgs a;
-  std::memset(&a, 0, sizeof(a));
-  const SceneHeader* h = reinterpret_cast<const SceneHeader*>(s->blob.data());
-  a.sc = reinterpret_cast<const SceneHeader*>(e->d_blob);
-  a.pd = reinterpret_cast<const PrimD*>((const char*)e->d_blob + h->prim_offset_d);
-  a.pf = reinterpret_cast<const PrimF*>((const char*)e->d_blob + h->prim_offset_f);
-  a.counter = e->d_counter;
-  a.acc_offsets = e->d_acc_offsets;
-  a.acc_ids = e->d_acc_ids;
-  a.refill_min = e->opts.refill_min;
-  a.surface_min = e->opts.surface_min;
-  return a;
-}
-
 static LaunchCfg launch_cfg(smcrt_engine* e) {
   LaunchCfg c;
   c.block = e->opts.block;
@@ -665,6 +591,155 @@ static LaunchCfg launch_cfg(smcrt_engine* e) {
   return c;
 }
 
+struct JobSpec {
+  smcrt_scene* s;
+  uint64_t seed, first, n;
+  double* fluence;
+  double* absorbed;
+  smcrt_tallies* tallies;
+};
+
+struct TraceSpec {
+  const uint64_t* ids;
+  smcrt_event* out;
+  int32_t* count;
+  int n_ids, max_records;
+};
+
+static size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+// Lays the jobs' scenes, the job table, the per-job counters and the grid
+// buffers out in the engine arena, uploads the tables, builds the uniform
+// grids, zeroes the counters and launches the walk -- all on `st`.
+static smcrt_status launch_jobs(smcrt_engine* e, const std::vector<JobSpec>& jobs, const TraceSpec* tr, hipStream_t st) {
+  if (jobs.empty()) return SMCRT_OK;
+  std::vector<smcrt_scene*> uniq;
+  std::vector<int> job_scene(jobs.size());
+  for (size_t j = 0; j < jobs.size(); ++j) {
+    smcrt_status r = pack(jobs[j].s);
+    if (r != SMCRT_OK) return r;
+    const SceneHeader* h = reinterpret_cast<const SceneHeader*>(jobs[j].s->blob.data());
+    if (h->has_grid && !jobs[j].fluence && !tr) return fail(SMCRT_E_INVALID, "job %zu: the scene has a grid but its fluence buffer is NULL", j);
+    int k = -1;
+    for (size_t u = 0; u < uniq.size(); ++u)
+      if (uniq[u] == jobs[j].s) k = (int)u;
+    if (k < 0) {
+      k = (int)uniq.size();
+      uniq.push_back(jobs[j].s);
+    }
+    job_scene[j] = k;
+  }
+  // layout
+  std::vector<size_t> blob_off(uniq.size()), acc_off(uniq.size(), 0);
+  size_t off = 0;
+  for (size_t u = 0; u < uniq.size(); ++u) {
+    blob_off[u] = off;
+    off = align256(off + uniq[u]->blob.size());
+  }
+  const size_t jobs_off = off;
+  off = align256(off + jobs.size() * sizeof(WalkArgs));
+  const size_t image_bytes = off;
+  const size_t counters_off = off;
+  off = align256(off + jobs.size() * sizeof(unsigned long long));
+  for (size_t u = 0; u < uniq.size(); ++u) {
+    const Accel& A = reinterpret_cast<const SceneHeader*>(uniq[u]->blob.data())->acc;
+    if (A.region < 0) continue;
+    acc_off[u] = off;
+    off += 3 * align256(sizeof(uint32_t) * ((size_t)A.n_cells + 1)) + align256(sizeof(uint32_t) * A.capacity);
+  }
+  const size_t total = off;
+  if (total > e->arena_cap) {
+    if (e->d_arena) {
+      HIP_TRY(hipStreamSynchronize(st), "hipStreamSynchronize");
+      HIP_TRY(hipFree(e->d_arena), "hipFree(arena)");
+      e->d_arena = nullptr;
+      e->arena_cap = 0;
+    }
+    const size_t cap = total + total / 4;
+    HIP_TRY(hipMalloc(&e->d_arena, cap), "hipMalloc(arena)");
+    e->arena_cap = cap;
+  }
+  char* base = static_cast<char*>(e->d_arena);
+  // host image: scene tables and the job table
+  e->image.assign(image_bytes, 0);
+  for (size_t u = 0; u < uniq.size(); ++u) std::memcpy(e->image.data() + blob_off[u], uniq[u]->blob.data(), uniq[u]->blob.size());
+  WalkArgs* table = reinterpret_cast<WalkArgs*>(e->image.data() + jobs_off);
+  for (size_t j = 0; j < jobs.size(); ++j) {
+    const int u = job_scene[j];
+    const SceneHeader* h = reinterpret_cast<const SceneHeader*>(uniq[u]->blob.data());
+    WalkArgs& a = table[j];
+    std::memset(&a, 0, sizeof(a));
+    char* sc = base + blob_off[u];
+    a.sc = reinterpret_cast<const SceneHeader*>(sc);
+    a.pd = reinterpret_cast<const PrimD*>(sc + h->prim_offset_d);
+    a.pf = reinterpret_cast<const PrimF*>(sc + h->prim_offset_f);
+    a.seed = jobs[j].seed;
+    a.first = jobs[j].first;
+    a.n = jobs[j].n;
+    a.counter = reinterpret_cast<unsigned long long*>(base + counters_off) + j;
+    a.fluence = h->has_grid ? jobs[j].fluence : nullptr;
+    a.absorbed = jobs[j].absorbed;
+    a.tallies = jobs[j].tallies;
+    a.acc_region = h->acc.region;
+    if (h->acc.region >= 0) {
+      const size_t cb = align256(sizeof(uint32_t) * ((size_t)h->acc.n_cells + 1));
+      a.acc_offsets = reinterpret_cast<const uint32_t*>(base + acc_off[u] + 2 * cb);
+      a.acc_ids = reinterpret_cast<const uint32_t*>(base + acc_off[u] + 3 * cb);
+    }
+    if (tr) {
+      a.trace_ids = tr->ids;
+      a.trace_out = tr->out;
+      a.trace_count = tr->count;
+      a.n_trace = tr->n_ids;
+      a.max_records = tr->max_records;
+      a.fluence = nullptr;
+    }
+  }
+  // upload through pinned staging; wait until the previous upload left it
+  if (e->stage_pending) {
+    HIP_TRY(hipEventSynchronize(e->stage_done), "hipEventSynchronize(stage)");
+    e->stage_pending = false;
+  }
+  if (image_bytes > e->stage_cap) {
+    if (e->h_stage) HIP_TRY(hipHostFree(e->h_stage), "hipHostFree");
+    e->h_stage = nullptr;
+    e->stage_cap = 0;
+    HIP_TRY(hipHostMalloc(&e->h_stage, image_bytes + image_bytes / 4, hipHostMallocDefault), "hipHostMalloc(stage)");
+    e->stage_cap = image_bytes + image_bytes / 4;
+  }
+  if (!e->stage_done) HIP_TRY(hipEventCreateWithFlags(&e->stage_done, hipEventDisableTiming), "hipEventCreate");
+  std::memcpy(e->h_stage, e->image.data(), image_bytes);
+  HIP_TRY(hipMemcpyAsync(e->d_arena, e->h_stage, image_bytes, hipMemcpyHostToDevice, st), "hipMemcpyAsync(tables)");
+  HIP_TRY(hipEventRecord(e->stage_done, st), "hipEventRecord(stage)");
+  e->stage_pending = true;
+  for (size_t u = 0; u < uniq.size(); ++u) {
+    const SceneHeader* h = reinterpret_cast<const SceneHeader*>(uniq[u]->blob.data());
+    if (h->acc.region < 0) continue;
+    const size_t cb = align256(sizeof(uint32_t) * ((size_t)h->acc.n_cells + 1));
+    char* ab = base + acc_off[u];
+    char* sc = base + blob_off[u];
+    HIP_TRY(launch_accel_build(reinterpret_cast<const SceneHeader*>(sc), reinterpret_cast<const PrimD*>(sc + h->prim_offset_d),
+                               h->acc.n_prims, h->acc.n_cells, reinterpret_cast<uint32_t*>(ab),
+                               reinterpret_cast<uint32_t*>(ab + cb), reinterpret_cast<uint32_t*>(ab + 2 * cb),
+                               reinterpret_cast<uint32_t*>(ab + 3 * cb), st),
+            "accel build");
+  }
+  HIP_TRY(launch_zero_u64_n(reinterpret_cast<unsigned long long*>(base + counters_off), (int)jobs.size(), st), "zero counters");
+  BatchArgs B;
+  std::memset(&B, 0, sizeof(B));
+  B.jobs = reinterpret_cast<const WalkArgs*>(base + jobs_off);
+  B.n_jobs = (int32_t)jobs.size();
+  B.refill_min = e->opts.refill_min;
+  B.surface_min = e->opts.surface_min;
+  LaunchCfg c = launch_cfg(e);
+  if (tr) {
+    c.block = 64;
+    c.grid = (tr->n_ids + 63) / 64;
+  }
+  HIP_TRY(launch_walk(e->opts.precision, tr != nullptr, c, B, st), "walk kernel");
+  return SMCRT_OK;
+}
+
 extern "C" smcrt_status smcrt_run(smcrt_engine* e, const smcrt_scene* scene, uint64_t seed, uint64_t first_packet,
                                   uint64_t n_packets, double* d_fluence_raw, double* d_absorbed, smcrt_tallies* d_tallies,
                                   void* hip_stream) {
@@ -672,28 +747,30 @@ extern "C" smcrt_status smcrt_run(smcrt_engine* e, const smcrt_scene* scene, uin
   if (!d_absorbed || !d_tallies) return fail(SMCRT_E_INVALID, "run: d_absorbed and d_tallies are required");
   if (n_packets == 0) return SMCRT_OK;
   if (first_packet + n_packets < first_packet) return fail(SMCRT_E_INVALID, "run: packet range overflows 64 bits");
-  smcrt_scene* s = const_cast<smcrt_scene*>(scene);
-  smcrt_status st = pack(s);
-  if (st != SMCRT_OK) return st;
-  const SceneHeader* h = reinterpret_cast<const SceneHeader*>(s->blob.data());
-  if (h->has_grid && !d_fluence_raw) return fail(SMCRT_E_INVALID, "run: the scene has a grid but d_fluence_raw is NULL");
   HIP_TRY(hipSetDevice(e->device), "hipSetDevice");
-  hipStream_t stream = (hipStream_t)hip_stream;
-  st = upload(e, s, stream);
-  if (st != SMCRT_OK) return st;
-  st = build_accel(e, s, stream);
-  if (st != SMCRT_OK) return st;
-  WalkArgs a = base_args(e, s);
-  a.seed = seed;
-  a.first = first_packet;
-  a.n = n_packets;
-  a.fluence = h->has_grid ? d_fluence_raw : nullptr;
-  a.absorbed = d_absorbed;
-  a.tallies = d_tallies;
-  LaunchCfg c = launch_cfg(e);
-  HIP_TRY(launch_zero_u64(e->d_counter, stream), "zero counter");
-  HIP_TRY(launch_walk(e->opts.precision, false, c, a, stream), "walk kernel");
-  return SMCRT_OK;
+  std::vector<JobSpec> jobs(1);
+  jobs[0] = JobSpec{const_cast<smcrt_scene*>(scene), seed, first_packet, n_packets, d_fluence_raw, d_absorbed, d_tallies};
+  return launch_jobs(e, jobs, nullptr, (hipStream_t)hip_stream);
+}
+
+extern "C" smcrt_status smcrt_run_batch(smcrt_engine* e, int n, const smcrt_scene* const* scenes, const uint64_t* seeds,
+                                        const uint64_t* first_packets, const uint64_t* n_packets, double* const* d_fluence_raw,
+                                        double* const* d_absorbed, smcrt_tallies* const* d_tallies, void* hip_stream) {
+  if (!e || n < 1 || !scenes || !seeds || !n_packets || !d_fluence_raw || !d_absorbed || !d_tallies)
+    return fail(SMCRT_E_INVALID, "run_batch: NULL argument or n < 1");
+  std::vector<JobSpec> jobs;
+  for (int j = 0; j < n; ++j) {
+    if (!scenes[j]) return fail(SMCRT_E_INVALID, "run_batch: scene %d is NULL", j);
+    if (!d_absorbed[j] || !d_tallies[j]) return fail(SMCRT_E_INVALID, "run_batch: job %d lacks d_absorbed or d_tallies", j);
+    const uint64_t first = first_packets ? first_packets[j] : 0;
+    if (first + n_packets[j] < first) return fail(SMCRT_E_INVALID, "run_batch: job %d packet range overflows", j);
+    if (n_packets[j] == 0) continue;
+    jobs.push_back(JobSpec{const_cast<smcrt_scene*>(scenes[j]), seeds[j], first, n_packets[j], d_fluence_raw[j],
+                           d_absorbed[j], d_tallies[j]});
+  }
+  if (jobs.empty()) return SMCRT_OK;
+  HIP_TRY(hipSetDevice(e->device), "hipSetDevice");
+  return launch_jobs(e, jobs, nullptr, (hipStream_t)hip_stream);
 }
 
 extern "C" smcrt_status smcrt_trace(smcrt_engine* e, const smcrt_scene* scene, uint64_t seed, const uint64_t* d_packet_ids,
@@ -701,29 +778,11 @@ extern "C" smcrt_status smcrt_trace(smcrt_engine* e, const smcrt_scene* scene, u
   if (!e || !scene || !d_packet_ids || !d_out || !d_count) return fail(SMCRT_E_INVALID, "trace: NULL argument");
   if (n_ids < 1 || max_events < 1) return fail(SMCRT_E_INVALID, "trace: need n_ids >= 1 and max_events >= 1");
   if ((int64_t)n_ids * max_events > (1LL << 31)) return fail(SMCRT_E_INVALID, "trace: too many records");
-  smcrt_scene* s = const_cast<smcrt_scene*>(scene);
-  smcrt_status st = pack(s);
-  if (st != SMCRT_OK) return st;
   HIP_TRY(hipSetDevice(e->device), "hipSetDevice");
-  hipStream_t stream = (hipStream_t)hip_stream;
-  st = upload(e, s, stream);
-  if (st != SMCRT_OK) return st;
-  st = build_accel(e, s, stream);
-  if (st != SMCRT_OK) return st;
-  WalkArgs a = base_args(e, s);
-  a.seed = seed;
-  a.trace_ids = d_packet_ids;
-  a.trace_out = d_out;
-  a.trace_count = d_count;
-  a.n_trace = n_ids;
-  a.max_records = max_events;
-  LaunchCfg c;
-  c.block = 64;
-  c.grid = (n_ids + 63) / 64;
-  c.refill_min = 1;
-  c.surface_min = 1;
-  HIP_TRY(launch_walk(e->opts.precision, true, c, a, stream), "trace kernel");
-  return SMCRT_OK;
+  std::vector<JobSpec> jobs(1);
+  jobs[0] = JobSpec{const_cast<smcrt_scene*>(scene), seed, 0, 0, nullptr, nullptr, nullptr};
+  TraceSpec tr{d_packet_ids, d_out, d_count, n_ids, max_events};
+  return launch_jobs(e, jobs, &tr, (hipStream_t)hip_stream);
 }
 
 extern "C" smcrt_status smcrt_normalize_fluence(const smcrt_scene* scene, const double* d_raw, double launched,

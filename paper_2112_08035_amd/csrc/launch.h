@@ -7,7 +7,10 @@
 namespace smcrt {
 
 // precision: 0 = FP32 transport, 1 = FP64 transport; trace: record events
-hipError_t launch_walk(int precision, bool trace, const LaunchCfg& cfg, const WalkArgs& args, hipStream_t stream);
+// (trace launches take exactly one job)
+hipError_t launch_walk(int precision, bool trace, const LaunchCfg& cfg, const BatchArgs& args, hipStream_t stream);
+// p[i] = 0 for i < n (a kernel, so resets can sit inside captured graphs)
+hipError_t launch_zero_u64_n(unsigned long long* p, int n, hipStream_t stream);
 // *p = 0 (a one-thread kernel, so the reset can sit inside captured graphs)
 hipError_t launch_zero_u64(unsigned long long* p, hipStream_t stream);
 // out[i] = in[i] * scale for i < n

@@ -94,7 +94,7 @@ struct WalkArgs {
   const PrimD* pd;
   const PrimF* pf;
   uint64_t seed, first, n;
-  unsigned long long* counter;   // packets handed out so far (zeroed before launch)
+  unsigned long long* counter;   // packets of this job handed out so far (zeroed before launch)
   double* fluence;               // nx*ny*nz, may be null
   double* absorbed;              // n_regions
   const uint32_t* acc_offsets;   // n_cells + 1 (accelerated scenes)
@@ -105,7 +105,16 @@ struct WalkArgs {
   void* trace_out;
   int32_t* trace_count;
   int32_t n_trace, max_records;
+  int32_t acc_region;            // copy of sc->acc.region (-1 = none)
+  int32_t pad;
+};
+
+// Arguments of one walk launch: a table of jobs in device memory.
+struct BatchArgs {
+  const WalkArgs* jobs;
+  int32_t n_jobs;
   int32_t refill_min, surface_min;
+  int32_t pad;
 };
 
 }  // namespace smcrt

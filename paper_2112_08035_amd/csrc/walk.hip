@@ -29,6 +29,20 @@
 
 namespace smcrt {
 
+// Scene tables, primitives, uniform grids and job tables are read-only for a
+// kernel's lifetime: they are read through the constant address space, so
+// wave-uniform reads become scalar loads into SGPRs and per-lane reads plain
+// global loads.  The fluence grid is written through the global space.
+#define SMCRT_K __attribute__((address_space(4)))
+#define SMCRT_G __attribute__((address_space(1)))
+using ScP = const SMCRT_K SceneHeader*;
+using RegRef = const SMCRT_K Region&;
+using JobRef = const SMCRT_K WalkArgs&;
+template <class X>
+__device__ __forceinline__ const SMCRT_K X* kptr(const X* p) {
+  return (const SMCRT_K X*)p;
+}
+
 // ------------------------------------------------------------------ types
 
 template <typename T>
@@ -114,46 +128,46 @@ template <typename T>
 struct Tab;
 template <>
 struct Tab<float> {
-  static __device__ __forceinline__ const PrimF* prims(const WalkArgs& a) { return a.pf; }
-  static __device__ __forceinline__ float k(const Region& r) { return r.kf; }
-  static __device__ __forceinline__ float inv_k(const Region& r) { return r.inv_kf; }
-  static __device__ __forceinline__ float mut(const Region& r) { return r.mutf; }
-  static __device__ __forceinline__ float inv_mut(const Region& r) { return r.inv_mutf; }
-  static __device__ __forceinline__ V3<float> bb_c(const SceneHeader* s) { return {s->bb_cf[0], s->bb_cf[1], s->bb_cf[2]}; }
-  static __device__ __forceinline__ V3<float> bb_h(const SceneHeader* s) { return {s->bb_hf[0], s->bb_hf[1], s->bb_hf[2]}; }
-  static __device__ __forceinline__ V3<float> g_lo(const SceneHeader* s) { return {s->g_lof[0], s->g_lof[1], s->g_lof[2]}; }
-  static __device__ __forceinline__ V3<float> g_inv(const SceneHeader* s) { return {s->g_inv_df[0], s->g_inv_df[1], s->g_inv_df[2]}; }
-  static __device__ __forceinline__ float delta(const SceneHeader* s) { return s->deltaf; }
-  static __device__ __forceinline__ V3<float> acc_lo(const Accel& A) { return {A.lof[0], A.lof[1], A.lof[2]}; }
-  static __device__ __forceinline__ V3<float> acc_inv(const Accel& A) { return {A.inv_cellf[0], A.inv_cellf[1], A.inv_cellf[2]}; }
-  static __device__ __forceinline__ V3<float> acc_blo(const Accel& A) { return {A.box_lof[0], A.box_lof[1], A.box_lof[2]}; }
-  static __device__ __forceinline__ V3<float> acc_bhi(const Accel& A) { return {A.box_hif[0], A.box_hif[1], A.box_hif[2]}; }
-  static __device__ __forceinline__ float acc_margin(const Accel& A) { return A.marginf; }
+  static __device__ __forceinline__ const SMCRT_K PrimF* prims(JobRef a) { return kptr(a.pf); }
+  static __device__ __forceinline__ float k(RegRef r) { return r.kf; }
+  static __device__ __forceinline__ float inv_k(RegRef r) { return r.inv_kf; }
+  static __device__ __forceinline__ float mut(RegRef r) { return r.mutf; }
+  static __device__ __forceinline__ float inv_mut(RegRef r) { return r.inv_mutf; }
+  static __device__ __forceinline__ V3<float> bb_c(ScP s) { return {s->bb_cf[0], s->bb_cf[1], s->bb_cf[2]}; }
+  static __device__ __forceinline__ V3<float> bb_h(ScP s) { return {s->bb_hf[0], s->bb_hf[1], s->bb_hf[2]}; }
+  static __device__ __forceinline__ V3<float> g_lo(ScP s) { return {s->g_lof[0], s->g_lof[1], s->g_lof[2]}; }
+  static __device__ __forceinline__ V3<float> g_inv(ScP s) { return {s->g_inv_df[0], s->g_inv_df[1], s->g_inv_df[2]}; }
+  static __device__ __forceinline__ float delta(ScP s) { return s->deltaf; }
+  static __device__ __forceinline__ V3<float> acc_lo(const SMCRT_K Accel& A) { return {A.lof[0], A.lof[1], A.lof[2]}; }
+  static __device__ __forceinline__ V3<float> acc_inv(const SMCRT_K Accel& A) { return {A.inv_cellf[0], A.inv_cellf[1], A.inv_cellf[2]}; }
+  static __device__ __forceinline__ V3<float> acc_blo(const SMCRT_K Accel& A) { return {A.box_lof[0], A.box_lof[1], A.box_lof[2]}; }
+  static __device__ __forceinline__ V3<float> acc_bhi(const SMCRT_K Accel& A) { return {A.box_hif[0], A.box_hif[1], A.box_hif[2]}; }
+  static __device__ __forceinline__ float acc_margin(const SMCRT_K Accel& A) { return A.marginf; }
 };
 template <>
 struct Tab<double> {
-  static __device__ __forceinline__ const PrimD* prims(const WalkArgs& a) { return a.pd; }
-  static __device__ __forceinline__ double k(const Region& r) { return r.k; }
-  static __device__ __forceinline__ double inv_k(const Region& r) { return r.inv_k; }
-  static __device__ __forceinline__ double mut(const Region& r) { return r.mut; }
-  static __device__ __forceinline__ double inv_mut(const Region& r) { return r.inv_mut; }
-  static __device__ __forceinline__ V3<double> bb_c(const SceneHeader* s) { return {s->bb_c[0], s->bb_c[1], s->bb_c[2]}; }
-  static __device__ __forceinline__ V3<double> bb_h(const SceneHeader* s) { return {s->bb_h[0], s->bb_h[1], s->bb_h[2]}; }
-  static __device__ __forceinline__ V3<double> g_lo(const SceneHeader* s) { return {s->g_lo[0], s->g_lo[1], s->g_lo[2]}; }
-  static __device__ __forceinline__ V3<double> g_inv(const SceneHeader* s) { return {s->g_inv_d[0], s->g_inv_d[1], s->g_inv_d[2]}; }
-  static __device__ __forceinline__ double delta(const SceneHeader* s) { return s->delta; }
-  static __device__ __forceinline__ V3<double> acc_lo(const Accel& A) { return {A.lo[0], A.lo[1], A.lo[2]}; }
-  static __device__ __forceinline__ V3<double> acc_inv(const Accel& A) { return {A.inv_cell[0], A.inv_cell[1], A.inv_cell[2]}; }
-  static __device__ __forceinline__ V3<double> acc_blo(const Accel& A) { return {A.box_lo[0], A.box_lo[1], A.box_lo[2]}; }
-  static __device__ __forceinline__ V3<double> acc_bhi(const Accel& A) { return {A.box_hi[0], A.box_hi[1], A.box_hi[2]}; }
-  static __device__ __forceinline__ double acc_margin(const Accel& A) { return A.margin; }
+  static __device__ __forceinline__ const SMCRT_K PrimD* prims(JobRef a) { return kptr(a.pd); }
+  static __device__ __forceinline__ double k(RegRef r) { return r.k; }
+  static __device__ __forceinline__ double inv_k(RegRef r) { return r.inv_k; }
+  static __device__ __forceinline__ double mut(RegRef r) { return r.mut; }
+  static __device__ __forceinline__ double inv_mut(RegRef r) { return r.inv_mut; }
+  static __device__ __forceinline__ V3<double> bb_c(ScP s) { return {s->bb_c[0], s->bb_c[1], s->bb_c[2]}; }
+  static __device__ __forceinline__ V3<double> bb_h(ScP s) { return {s->bb_h[0], s->bb_h[1], s->bb_h[2]}; }
+  static __device__ __forceinline__ V3<double> g_lo(ScP s) { return {s->g_lo[0], s->g_lo[1], s->g_lo[2]}; }
+  static __device__ __forceinline__ V3<double> g_inv(ScP s) { return {s->g_inv_d[0], s->g_inv_d[1], s->g_inv_d[2]}; }
+  static __device__ __forceinline__ double delta(ScP s) { return s->delta; }
+  static __device__ __forceinline__ V3<double> acc_lo(const SMCRT_K Accel& A) { return {A.lo[0], A.lo[1], A.lo[2]}; }
+  static __device__ __forceinline__ V3<double> acc_inv(const SMCRT_K Accel& A) { return {A.inv_cell[0], A.inv_cell[1], A.inv_cell[2]}; }
+  static __device__ __forceinline__ V3<double> acc_blo(const SMCRT_K Accel& A) { return {A.box_lo[0], A.box_lo[1], A.box_lo[2]}; }
+  static __device__ __forceinline__ V3<double> acc_bhi(const SMCRT_K Accel& A) { return {A.box_hi[0], A.box_hi[1], A.box_hi[2]}; }
+  static __device__ __forceinline__ double acc_margin(const SMCRT_K Accel& A) { return A.margin; }
 };
 
 // exact Euclidean SDF of one primitive (Sec. 2.2; Eq. 3 for the sphere)
 template <typename T>
-__device__ __forceinline__ T prim_sdf(const Prim<T>* __restrict__ P, int i, V3<T> p) {
+__device__ __forceinline__ T prim_sdf(const SMCRT_K Prim<T>* P, int i, V3<T> p) {
   const int kind = P[i].kind;
-  const T* v = P[i].v;
+  const SMCRT_K T* v = P[i].v;
   const V3<T> q = p - mk(v[0], v[1], v[2]);
   if (kind == kSphere) return tsqrt(dot(q, q)) - v[3];
   if (kind == kBox) {
@@ -178,8 +192,8 @@ __device__ __forceinline__ T prim_sdf(const Prim<T>* __restrict__ P, int i, V3<T
 
 // region SDF: union (min) or polynomial smooth union of its primitives
 template <typename T>
-__device__ __forceinline__ T region_sdf(const WalkArgs& a, const Region& R, V3<T> p) {
-  const Prim<T>* __restrict__ P = Tab<T>::prims(a);
+__device__ __forceinline__ T region_sdf(JobRef a, RegRef R, V3<T> p) {
+  const SMCRT_K Prim<T>* P = Tab<T>::prims(a);
   T d = prim_sdf(P, R.first, p);
   if (R.op == kSmoothUnion) {
     const T k = Tab<T>::k(R), ik = Tab<T>::inv_k(R);
@@ -200,8 +214,8 @@ __device__ __forceinline__ T region_sdf(const WalkArgs& a, const Region& R, V3<T
 // (which is the primitives' box grown by the margin) the distance to the
 // primitives' box is the lower bound.  Every index is checked.
 template <typename T>
-__device__ __forceinline__ T accel_sdf(const WalkArgs& a, V3<T> p) {
-  const Accel& A = a.sc->acc;
+__device__ __forceinline__ T accel_sdf(JobRef a, V3<T> p) {
+  const SMCRT_K Accel& A = kptr(a.sc)->acc;
   const V3<T> lo = Tab<T>::acc_lo(A), ic = Tab<T>::acc_inv(A);
   const T cx = (p.x - lo.x) * ic.x, cy = (p.y - lo.y) * ic.y, cz = (p.z - lo.z) * ic.z;
   const int dx = A.dims[0], dy = A.dims[1], dz = A.dims[2];
@@ -216,14 +230,16 @@ __device__ __forceinline__ T accel_sdf(const WalkArgs& a, V3<T> p) {
   iy = iy < dy ? iy : dy - 1;
   iz = iz < dz ? iz : dz - 1;
   const int c = ix + dx * (iy + dy * iz);
-  const uint32_t b = a.acc_offsets[c];
-  uint64_t e = a.acc_offsets[c + 1];
+  const SMCRT_K uint32_t* offs = kptr(a.acc_offsets);
+  const SMCRT_K uint32_t* ids = kptr(a.acc_ids);
+  const uint32_t b = offs[c];
+  uint64_t e = offs[c + 1];
   e = e < A.capacity ? e : A.capacity;
-  const Prim<T>* __restrict__ P = Tab<T>::prims(a);
+  const SMCRT_K Prim<T>* P = Tab<T>::prims(a);
   const uint32_t lo_id = (uint32_t)A.first_prim, hi_id = (uint32_t)(A.first_prim + A.n_prims);
   T d = Tab<T>::acc_margin(A);
   for (uint64_t i = b; i < e; ++i) {
-    const uint32_t id = a.acc_ids[i];
+    const uint32_t id = ids[i];
     if (id >= lo_id && id < hi_id) d = tmin(d, prim_sdf(P, (int)id, p));
   }
   return d;
@@ -231,16 +247,16 @@ __device__ __forceinline__ T accel_sdf(const WalkArgs& a, V3<T> p) {
 
 // SDF of region r (through the grid when r is the accelerated region)
 template <typename T>
-__device__ __forceinline__ T region_dist(const WalkArgs& a, int r, V3<T> p) {
-  if (r == a.sc->acc.region) return accel_sdf<T>(a, p);
-  return region_sdf<T>(a, a.sc->reg[r], p);
+__device__ __forceinline__ T region_dist(JobRef a, int r, V3<T> p) {
+  if (r == a.acc_region) return accel_sdf<T>(a, p);
+  return region_sdf<T>(a, kptr(a.sc)->reg[r], p);
 }
 
 // owner of a point: the highest-index region with a negative SDF, else the
 // ambient slot n_regions
 template <typename T>
-__device__ __forceinline__ int region_of(const WalkArgs& a, V3<T> p) {
-  const SceneHeader* sc = a.sc;
+__device__ __forceinline__ int region_of(JobRef a, V3<T> p) {
+  ScP sc = kptr(a.sc);
   const int nr = sc->n_regions;
   int owner = nr;
   for (int r = nr - 1; r >= 0; --r) {
@@ -254,7 +270,7 @@ __device__ __forceinline__ int region_of(const WalkArgs& a, V3<T> p) {
 
 // signed distance of the simulation volume and, when outside, the face
 template <typename T>
-__device__ __forceinline__ T volume_sdf(const SceneHeader* sc, V3<T> p, int* face) {
+__device__ __forceinline__ T volume_sdf(ScP sc, V3<T> p, int* face) {
   const V3<T> c = Tab<T>::bb_c(sc), h = Tab<T>::bb_h(sc);
   const V3<T> q = p - c;
   const T ex = tabs(q.x) - h.x, ey = tabs(q.y) - h.y, ez = tabs(q.z) - h.z;
@@ -269,7 +285,7 @@ __device__ __forceinline__ T volume_sdf(const SceneHeader* sc, V3<T> p, int* fac
 }
 
 // unit outward normal of region R at p by central differences of step h
-__device__ __forceinline__ V3<double> region_normal(const WalkArgs& a, int r, V3<double> p, double h) {
+__device__ __forceinline__ V3<double> region_normal(JobRef a, int r, V3<double> p, double h) {
   V3<double> n;
   n.x = region_dist<double>(a, r, mk(p.x + h, p.y, p.z)) - region_dist<double>(a, r, mk(p.x - h, p.y, p.z));
   n.y = region_dist<double>(a, r, mk(p.x, p.y + h, p.z)) - region_dist<double>(a, r, mk(p.x, p.y - h, p.z));
@@ -297,14 +313,18 @@ struct Run {
   double sum;
 };
 
-__device__ __forceinline__ void run_add(double* __restrict__ F, Run& run, int v, double val, uint32_t& n_pieces,
+__device__ __forceinline__ void grid_add(double* F, int v, double val) {
+  __builtin_amdgcn_global_atomic_fadd_f64((SMCRT_G double*)F + v, val);
+}
+
+__device__ __forceinline__ void run_add(double* F, Run& run, int v, double val, uint32_t& n_pieces,
                                         uint32_t& n_atomics) {
   ++n_pieces;
   if (v == run.v) {
     run.sum += val;
   } else {
     if (run.v >= 0) {
-      unsafeAtomicAdd(F + run.v, run.sum);
+      grid_add(F, run.v, run.sum);
       ++n_atomics;
     }
     run.v = v;
@@ -317,9 +337,9 @@ __device__ __forceinline__ void run_add(double* __restrict__ F, Run& run, int v,
 // units.  Voxel i spans [lo + i*D, lo + (i+1)*D); indices are clamped on
 // entry and the walk stops when it steps off the grid.
 template <typename T>
-__device__ __forceinline__ void tally_move(const WalkArgs& a, V3<T> p, V3<T> u, T len, double w, Run& run,
+__device__ __forceinline__ void tally_move(JobRef a, V3<T> p, V3<T> u, T len, double w, Run& run,
                                            uint32_t& n_pieces, uint32_t& n_atomics) {
-  const SceneHeader* sc = a.sc;
+  ScP sc = kptr(a.sc);
   if (a.fluence == nullptr || !(len > T(0))) return;
   const int nx = sc->g_dims[0], ny = sc->g_dims[1], nz = sc->g_dims[2];
   const V3<T> inv = Tab<T>::g_inv(sc);
@@ -408,14 +428,14 @@ struct Lane {
 };
 
 template <typename T>
-__device__ __forceinline__ void set_region(const SceneHeader* sc, Packet<T>& pk, int r) {
+__device__ __forceinline__ void set_region(ScP sc, Packet<T>& pk, int r) {
   pk.region = r;
   pk.mut = Tab<T>::mut(sc->reg[r]);
   pk.inv_mut = Tab<T>::inv_mut(sc->reg[r]);
 }
 
 template <typename T, bool TRACE>
-__device__ __forceinline__ void record(const WalkArgs& a, const Packet<T>& pk, Lane& ln, int type) {
+__device__ __forceinline__ void record(JobRef a, const Packet<T>& pk, Lane& ln, int type) {
   if constexpr (TRACE) {
     if (ln.n_rec < a.max_records) {
       smcrt_event e;
@@ -434,7 +454,7 @@ __device__ __forceinline__ void record(const WalkArgs& a, const Packet<T>& pk, L
 }
 
 template <typename T>
-__device__ __forceinline__ void move(const WalkArgs& a, Packet<T>& pk, Lane& ln, T len) {
+__device__ __forceinline__ void move(JobRef a, Packet<T>& pk, Lane& ln, T len) {
   tally_move<T>(a, pk.p, pk.u, len, pk.w, ln.run, ln.n_pieces, ln.n_atomics);
   pk.p = pk.p + len * pk.u;
 }
@@ -450,11 +470,11 @@ __device__ __forceinline__ void add_absorbed(LdsTallies& L, Lane& ln, int r, dou
 
 // emission, event 0 (Sec. 3.1 sources; Eq. 1)
 template <typename T, bool TRACE>
-__device__ void emit(const WalkArgs& a, Packet<T>& pk, Lane& ln, LdsTallies& L) {
-  const SceneHeader* sc = a.sc;
+__device__ void emit(JobRef a, Packet<T>& pk, Lane& ln, LdsTallies& L) {
+  ScP sc = kptr(a.sc);
   const U4 r = philox10(0u, (uint32_t)pk.pid, (uint32_t)(pk.pid >> 32), 0u, (uint32_t)a.seed, (uint32_t)(a.seed >> 32));
   const T x0 = xi_of<T>(r.w0), x1 = xi_of<T>(r.w1), x3 = xi_of<T>(r.w3);
-  const double* s = sc->src;
+  const SMCRT_K double* s = sc->src;
   V3<T> p = mk((T)s[0], (T)s[1], (T)s[2]);
   V3<T> u;
   const int kind = sc->src_kind;
@@ -492,9 +512,9 @@ __device__ void emit(const WalkArgs& a, Packet<T>& pk, Lane& ln, LdsTallies& L) 
 // absorption, Henyey-Greenstein scattering, roulette, next free path.
 // Returns false when the packet ends.
 template <typename T, bool TRACE>
-__device__ bool interact(const WalkArgs& a, Packet<T>& pk, Lane& ln, LdsTallies& L) {
-  const SceneHeader* sc = a.sc;
-  const Region& R = sc->reg[pk.region];
+__device__ bool interact(JobRef a, Packet<T>& pk, Lane& ln, LdsTallies& L) {
+  ScP sc = kptr(a.sc);
+  RegRef R = sc->reg[pk.region];
   pk.k += 1;
   ++ln.n_inter;
   const U4 r = philox10(pk.k, (uint32_t)pk.pid, (uint32_t)(pk.pid >> 32), 0u, (uint32_t)a.seed, (uint32_t)(a.seed >> 32));
@@ -567,8 +587,8 @@ __device__ bool interact(const WalkArgs& a, Packet<T>& pk, Lane& ln, LdsTallies&
 // probe across it for the medium ahead, then cross, reflect or refract.
 // Sets pk.state to kTransport or kInteract.
 template <typename T, bool TRACE>
-__device__ void surface(const WalkArgs& a, Packet<T>& pk, Lane& ln, LdsTallies& L) {
-  const SceneHeader* sc = a.sc;
+__device__ void surface(JobRef a, Packet<T>& pk, Lane& ln, LdsTallies& L) {
+  ScP sc = kptr(a.sc);
   const V3<double> p = to_d(pk.p), u = to_d(pk.u);
   const int nr = sc->n_regions;
   int j = 0;
@@ -596,7 +616,7 @@ __device__ void surface(const WalkArgs& a, Packet<T>& pk, Lane& ln, LdsTallies& 
   const double sg = c > 0.0 ? 1.0 : -1.0;
   const V3<double> q = ps + (sg * off) * nrm;
   const int r2 = (c == 0.0) ? pk.region : region_of<double>(a, q);
-  const Region& R1 = sc->reg[pk.region];
+  RegRef R1 = sc->reg[pk.region];
   double tau = (double)pk.tau;
   const double s_rem = R1.mut > 0.0 ? tau / R1.mut : __builtin_inf();
   if (r2 == pk.region) {
@@ -669,16 +689,92 @@ __device__ void surface(const WalkArgs& a, Packet<T>& pk, Lane& ln, LdsTallies& 
 
 __device__ __forceinline__ int lane_id() { return __lane_id(); }
 
+// First job, scanning from `start`, whose packet counter has not reached its
+// packet count; -1 when every job is handed out.  Wave uniform.
+__device__ __forceinline__ int pick_job(const SMCRT_K WalkArgs* jobs, const BatchArgs& B, int start) {
+  for (int i = 0; i < B.n_jobs; ++i) {
+    const int j = (start + i) % B.n_jobs;
+    JobRef J = jobs[j];
+    const unsigned long long c = __hip_atomic_load(J.counter, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    const uint64_t cu = ((uint64_t)__builtin_amdgcn_readfirstlane((unsigned)(c >> 32)) << 32) |
+                        (uint64_t)__builtin_amdgcn_readfirstlane((unsigned)c);
+    if (cu < J.n) return j;
+  }
+  return -1;
+}
+
+// Adds a wave's pending sums to job a's outputs and clears them.  Called with
+// every lane of the wave active.
+__device__ __forceinline__ void flush_wave(JobRef a, Lane& ln, LdsTallies& L, int lane) {
+  if (ln.run.v >= 0) {
+    grid_add(a.fluence, ln.run.v, ln.run.sum);
+    ++ln.n_atomics;
+  }
+  if (ln.abs_region >= 0) atomicAdd(&L.absorbed[ln.abs_region], ln.abs_sum);
+  atomicAdd(&L.cnt[kCSteps], (unsigned long long)ln.n_steps);
+  atomicAdd(&L.cnt[kCInteractions], (unsigned long long)ln.n_inter);
+  atomicAdd(&L.cnt[kCPieces], (unsigned long long)ln.n_pieces);
+  atomicAdd(&L.cnt[kCAtomics], (unsigned long long)ln.n_atomics);
+  ln.run.v = -1;
+  ln.run.sum = 0.0;
+  ln.abs_region = -1;
+  ln.abs_sum = 0.0;
+  ln.n_steps = ln.n_inter = ln.n_pieces = ln.n_atomics = 0;
+  __threadfence_block();
+  if (lane == 0) {
+    const int nr = a.sc->n_regions;
+    if (a.absorbed != nullptr)
+      for (int r = 0; r < nr; ++r) unsafeAtomicAdd(a.absorbed + r, L.absorbed[r]);
+    smcrt_tallies* G = reinterpret_cast<smcrt_tallies*>(a.tallies);
+    if (G != nullptr) {
+      for (int f = 0; f < 6; ++f) unsafeAtomicAdd(&G->escaped_face[f], L.escaped[f]);
+      unsafeAtomicAdd(&G->launched, (double)L.cnt[kCLaunched]);
+      unsafeAtomicAdd(&G->roulette_gain, L.gain);
+      unsafeAtomicAdd(&G->roulette_loss, L.loss);
+      unsafeAtomicAdd(&G->stalled, L.stalled);
+      atomicAdd((unsigned long long*)&G->events, L.cnt[kCInteractions] + L.cnt[kCInterfaces]);
+      atomicAdd((unsigned long long*)&G->steps, L.cnt[kCSteps]);
+      atomicAdd((unsigned long long*)&G->interactions, L.cnt[kCInteractions]);
+      atomicAdd((unsigned long long*)&G->interfaces, L.cnt[kCInterfaces]);
+      atomicAdd((unsigned long long*)&G->reflections, L.cnt[kCReflections]);
+      atomicAdd((unsigned long long*)&G->refractions, L.cnt[kCRefractions]);
+      atomicAdd((unsigned long long*)&G->crossings, L.cnt[kCCrossings]);
+      atomicAdd((unsigned long long*)&G->advances, L.cnt[kCAdvances]);
+      atomicAdd((unsigned long long*)&G->voxel_pieces, L.cnt[kCPieces]);
+      atomicAdd((unsigned long long*)&G->kills, L.cnt[kCKills]);
+      atomicAdd((unsigned long long*)&G->stalls, L.cnt[kCStalls]);
+      atomicAdd((unsigned long long*)&G->escapes, L.cnt[kCEscapes]);
+      atomicAdd((unsigned long long*)&G->grid_atomics, L.cnt[kCAtomics]);
+    }
+    for (int r = 0; r < kMaxRegions; ++r) L.absorbed[r] = 0.0;
+    for (int f = 0; f < 6; ++f) L.escaped[f] = 0.0;
+    for (int c = 0; c < 16; ++c) L.cnt[c] = 0ull;
+    L.gain = L.loss = L.stalled = 0.0;
+  }
+  __threadfence_block();
+}
+
+// The persistent walk over a table of jobs (scene tables, seed, packet
+// range, outputs).  Each wave works on one job at a time, so the job's
+// tables are wave uniform and come through the scalar cache; waves start
+// spread over the jobs in proportion to their count and, when their job's
+// packets are all handed out and their lanes have drained, flush their sums
+// into that job's outputs and move on to the next job with packets left.
 template <typename T, bool TRACE>
-__global__ void __launch_bounds__(256) walk_kernel(WalkArgs a) {
-  __shared__ LdsTallies L;
-  const SceneHeader* sc = a.sc;
-  const int nr = sc->n_regions;
-  for (int i = threadIdx.x; i < kMaxRegions; i += blockDim.x) L.absorbed[i] = 0.0;
-  for (int i = threadIdx.x; i < 6; i += blockDim.x) L.escaped[i] = 0.0;
-  for (int i = threadIdx.x; i < 16; i += blockDim.x) L.cnt[i] = 0ull;
-  if (threadIdx.x == 0) L.gain = L.loss = L.stalled = 0.0;
-  __syncthreads();
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 5 : 3)))
+walk_kernel(const WalkArgs* __restrict__ job_table, BatchArgs B) {
+  const SMCRT_K WalkArgs* jobs = kptr(job_table);
+  __shared__ LdsTallies Lw[4];
+  const int lane = lane_id();
+  const int wib = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // wave index in the block (wave uniform)
+  LdsTallies& L = Lw[wib];
+  if (lane == 0) {
+    for (int r = 0; r < kMaxRegions; ++r) L.absorbed[r] = 0.0;
+    for (int f = 0; f < 6; ++f) L.escaped[f] = 0.0;
+    for (int c = 0; c < 16; ++c) L.cnt[c] = 0ull;
+    L.gain = L.loss = L.stalled = 0.0;
+  }
+  __threadfence_block();
 
   Lane ln;
   ln.run.v = -1;
@@ -689,140 +785,129 @@ __global__ void __launch_bounds__(256) walk_kernel(WalkArgs a) {
   ln.rec = nullptr;
   ln.n_rec = 0;
 
+  int cur = 0;
+  if constexpr (!TRACE) {
+    const int waves_per_block = blockDim.x >> 6;
+    const long gw = (long)blockIdx.x * waves_per_block + wib;
+    const long tw = (long)gridDim.x * waves_per_block;
+    cur = pick_job(jobs, B, (int)((gw * B.n_jobs) / tw));
+    if (cur < 0) return;
+  }
   Packet<T> pk;
   bool live = false;
-  bool exhausted = false;  // wave uniform
-  const int lane = lane_id();
-  const T delta = Tab<T>::delta(sc);
-  const int max_steps = sc->max_steps;
-  const uint32_t max_events = (uint32_t)sc->max_events;
 
-  if constexpr (TRACE) {
-    const int id = blockIdx.x * blockDim.x + threadIdx.x;
-    exhausted = true;
-    if (id < a.n_trace) {
-      ln.rec = reinterpret_cast<smcrt_event*>(a.trace_out) + (size_t)id * a.max_records;
-      pk.pid = a.trace_ids[id];
-      live = true;
-      emit<T, TRACE>(a, pk, ln, L);
-    }
-  }
-
+  // outer loop over jobs, inner loop over that job's packets: within the
+  // inner loop the job is fixed, so its fields (a noalias read-only kernel
+  // argument) and the scene scalars below stay in registers
   for (;;) {
-    // ---- refill dead lanes from the global packet counter
-    if constexpr (!TRACE) {
-      const uint64_t dmask = __ballot(!live);
-      const int ndead = __popcll(dmask);
-      if (!exhausted && ndead > 0 && (ndead >= a.refill_min || ndead == __popcll(__ballot(1)))) {
-        const int leader = __ffsll((unsigned long long)dmask) - 1;
-        unsigned long long base = 0;
-        if (lane == leader) base = atomicAdd(a.counter, (unsigned long long)ndead);
-        base = __shfl(base, leader);
-        if (base + (uint64_t)ndead >= a.n) exhausted = true;
-        if (!live) {
-          const int rank = __popcll(dmask & ((1ull << lane) - 1ull));
-          const uint64_t id = base + (uint64_t)rank;
-          if (id < a.n) {
-            pk.pid = a.first + id;
-            live = true;
-            emit<T, TRACE>(a, pk, ln, L);
+    JobRef a = jobs[cur];
+    ScP sc = kptr(a.sc);
+    const int nr = sc->n_regions;
+    const T delta = Tab<T>::delta(sc);
+    const int max_steps = sc->max_steps;
+    const uint32_t max_events = (uint32_t)sc->max_events;
+    bool exhausted = false;  // wave uniform
+
+    if constexpr (TRACE) {
+      const int id = blockIdx.x * blockDim.x + threadIdx.x;
+      exhausted = true;
+      if (id < a.n_trace) {
+        ln.rec = reinterpret_cast<smcrt_event*>(a.trace_out) + (size_t)id * a.max_records;
+        pk.pid = a.trace_ids[id];
+        live = true;
+        emit<T, TRACE>(a, pk, ln, L);
+      }
+    }
+
+    for (;;) {
+      // ---- refill dead lanes from the job's packet counter
+      if constexpr (!TRACE) {
+        const uint64_t dmask = __ballot(!live);
+        const int ndead = __popcll(dmask);
+        if (!exhausted && ndead > 0 && (ndead >= B.refill_min || ndead == __popcll(__ballot(1)))) {
+          const int leader = __ffsll((unsigned long long)dmask) - 1;
+          unsigned long long base = 0;
+          if (lane == leader) base = atomicAdd(a.counter, (unsigned long long)ndead);
+          base = __shfl(base, leader);
+          if (base + (uint64_t)ndead >= a.n) exhausted = true;
+          if (!live) {
+            const int rank = __popcll(dmask & ((1ull << lane) - 1ull));
+            const uint64_t id = base + (uint64_t)rank;
+            if (id < a.n) {
+              pk.pid = a.first + id;
+              live = true;
+              emit<T, TRACE>(a, pk, ln, L);
+            }
           }
         }
       }
-    }
-    const uint64_t lmask = __ballot(live);
-    if (lmask == 0ull) {
-      if (exhausted) break;
-      continue;
-    }
+      const uint64_t lmask = __ballot(live);
+      if (lmask == 0ull) {
+        if (exhausted) break;
+        continue;
+      }
 
-    // ---- one sphere-tracing step (Sec. 2.3)
-    if (live && pk.state == kTransport) {
-      if (++pk.steps > max_steps || pk.k > max_events) {
-        atomicAdd(&L.stalled, pk.w);
-        atomicAdd(&L.cnt[kCStalls], 1ull);
-        record<T, TRACE>(a, pk, ln, SMCRT_EV_STALL);
-        live = false;
-      } else {
-        ++ln.n_steps;
-        T dmin = tinf<T>();
-        for (int r = 0; r < nr; ++r) dmin = tmin(dmin, tabs(region_dist<T>(a, r, pk.p)));
-        int face;
-        const T dbb = volume_sdf<T>(sc, pk.p, &face);
-        if (dbb > T(0)) {  // outside the simulation volume
-          atomicAdd(&L.escaped[face], pk.w);
-          atomicAdd(&L.cnt[kCEscapes], 1ull);
-          record<T, TRACE>(a, pk, ln, SMCRT_EV_ESCAPE);
+      // ---- one sphere-tracing step (Sec. 2.3)
+      if (live && pk.state == kTransport) {
+        if (++pk.steps > max_steps || pk.k > max_events) {
+          atomicAdd(&L.stalled, pk.w);
+          atomicAdd(&L.cnt[kCStalls], 1ull);
+          record<T, TRACE>(a, pk, ln, SMCRT_EV_STALL);
           live = false;
         } else {
-          const T s = pk.mut > T(0) ? pk.tau * pk.inv_mut : tinf<T>();
-          if (s <= dmin) {  // the optical depth runs out before any surface
-            move<T>(a, pk, ln, s);
-            pk.tau = T(0);
-            pk.state = kInteract;
-          } else if (dmin < delta) {
-            pk.state = kSurface;
+          ++ln.n_steps;
+          T dmin = tinf<T>();
+          for (int r = 0; r < nr; ++r) dmin = tmin(dmin, tabs(region_dist<T>(a, r, pk.p)));
+          int face;
+          const T dbb = volume_sdf<T>(sc, pk.p, &face);
+          if (dbb > T(0)) {  // outside the simulation volume
+            atomicAdd(&L.escaped[face], pk.w);
+            atomicAdd(&L.cnt[kCEscapes], 1ull);
+            record<T, TRACE>(a, pk, ln, SMCRT_EV_ESCAPE);
+            live = false;
           } else {
-            move<T>(a, pk, ln, dmin);
-            pk.tau -= pk.mut * dmin;
+            const T s = pk.mut > T(0) ? pk.tau * pk.inv_mut : tinf<T>();
+            if (s <= dmin) {  // the optical depth runs out before any surface
+              move<T>(a, pk, ln, s);
+              pk.tau = T(0);
+              pk.state = kInteract;
+            } else if (dmin < delta) {
+              pk.state = kSurface;
+            } else {
+              move<T>(a, pk, ln, dmin);
+              pk.tau -= pk.mut * dmin;
+            }
           }
         }
       }
-    }
 
-    // ---- interface steps, gathered
-    {
-      const uint64_t smask = __ballot(live && pk.state == kSurface);
-      const int nsurf = __popcll(smask);
-      if (nsurf > 0 && (nsurf >= a.surface_min || nsurf == __popcll(__ballot(live)))) {
-        if (live && pk.state == kSurface) surface<T, TRACE>(a, pk, ln, L);
+      // ---- interface steps, gathered
+      {
+        const uint64_t smask = __ballot(live && pk.state == kSurface);
+        const int nsurf = __popcll(smask);
+        if (nsurf > 0 && (nsurf >= B.surface_min || nsurf == __popcll(__ballot(live)))) {
+          if (live && pk.state == kSurface) surface<T, TRACE>(a, pk, ln, L);
+        }
+      }
+
+      // ---- interactions
+      if (live && pk.state == kInteract) {
+        pk.state = kTransport;
+        if (!interact<T, TRACE>(a, pk, ln, L)) live = false;
       }
     }
 
-    // ---- interactions
-    if (live && pk.state == kInteract) {
-      pk.state = kTransport;
-      if (!interact<T, TRACE>(a, pk, ln, L)) live = false;
+    if constexpr (TRACE) {
+      const int id = blockIdx.x * blockDim.x + threadIdx.x;
+      if (id < a.n_trace) a.trace_count[id] = ln.n_rec < a.max_records ? ln.n_rec : a.max_records;
+      flush_wave(a, ln, L, lane);
+      break;
+    } else {
+      // job drained by this wave: hand in its sums, take the next job
+      flush_wave(a, ln, L, lane);
+      cur = pick_job(jobs, B, cur + 1);
+      if (cur < 0) break;
     }
-  }
-
-  // ---- flush per-lane sums
-  if (ln.run.v >= 0) {
-    unsafeAtomicAdd(a.fluence + ln.run.v, ln.run.sum);
-    ++ln.n_atomics;
-  }
-  if (ln.abs_region >= 0) atomicAdd(&L.absorbed[ln.abs_region], ln.abs_sum);
-  atomicAdd(&L.cnt[kCSteps], (unsigned long long)ln.n_steps);
-  atomicAdd(&L.cnt[kCInteractions], (unsigned long long)ln.n_inter);
-  atomicAdd(&L.cnt[kCPieces], (unsigned long long)ln.n_pieces);
-  atomicAdd(&L.cnt[kCAtomics], (unsigned long long)ln.n_atomics);
-  if constexpr (TRACE) {
-    const int id = blockIdx.x * blockDim.x + threadIdx.x;
-    if (id < a.n_trace) a.trace_count[id] = ln.n_rec < a.max_records ? ln.n_rec : a.max_records;
-  }
-  __syncthreads();
-  smcrt_tallies* G = reinterpret_cast<smcrt_tallies*>(a.tallies);
-  if (a.absorbed != nullptr && threadIdx.x < (unsigned)nr)
-    unsafeAtomicAdd(a.absorbed + threadIdx.x, L.absorbed[threadIdx.x]);
-  if (threadIdx.x == 0 && G) {
-    for (int f = 0; f < 6; ++f) unsafeAtomicAdd(&G->escaped_face[f], L.escaped[f]);
-    unsafeAtomicAdd(&G->launched, (double)L.cnt[kCLaunched]);
-    unsafeAtomicAdd(&G->roulette_gain, L.gain);
-    unsafeAtomicAdd(&G->roulette_loss, L.loss);
-    unsafeAtomicAdd(&G->stalled, L.stalled);
-    atomicAdd((unsigned long long*)&G->events, L.cnt[kCInteractions] + L.cnt[kCInterfaces]);
-    atomicAdd((unsigned long long*)&G->steps, L.cnt[kCSteps]);
-    atomicAdd((unsigned long long*)&G->interactions, L.cnt[kCInteractions]);
-    atomicAdd((unsigned long long*)&G->interfaces, L.cnt[kCInterfaces]);
-    atomicAdd((unsigned long long*)&G->reflections, L.cnt[kCReflections]);
-    atomicAdd((unsigned long long*)&G->refractions, L.cnt[kCRefractions]);
-    atomicAdd((unsigned long long*)&G->crossings, L.cnt[kCCrossings]);
-    atomicAdd((unsigned long long*)&G->advances, L.cnt[kCAdvances]);
-    atomicAdd((unsigned long long*)&G->voxel_pieces, L.cnt[kCPieces]);
-    atomicAdd((unsigned long long*)&G->kills, L.cnt[kCKills]);
-    atomicAdd((unsigned long long*)&G->stalls, L.cnt[kCStalls]);
-    atomicAdd((unsigned long long*)&G->escapes, L.cnt[kCEscapes]);
-    atomicAdd((unsigned long long*)&G->grid_atomics, L.cnt[kCAtomics]);
   }
 }
 
@@ -833,21 +918,29 @@ __global__ void scale_kernel(const double* __restrict__ in, double* __restrict__
     out[i] = in[i] * s;
 }
 
-hipError_t launch_walk(int precision, bool trace, const LaunchCfg& cfg, const WalkArgs& args, hipStream_t stream) {
-  // every pointer the chosen mode dereferences must be set
-  if (!args.sc || !args.pd || !args.pf) return hipErrorInvalidValue;
-  if (trace && (!args.trace_ids || !args.trace_out || !args.trace_count || args.n_trace < 1 || args.max_records < 1))
-    return hipErrorInvalidValue;
-  if (!trace && (!args.counter || !args.absorbed || !args.tallies)) return hipErrorInvalidValue;
+hipError_t launch_walk(int precision, bool trace, const LaunchCfg& cfg, const BatchArgs& args, hipStream_t stream) {
+  if (!args.jobs || args.n_jobs < 1 || (trace && args.n_jobs != 1)) return hipErrorInvalidValue;
+  if (args.refill_min < 1 || args.refill_min > 64 || args.surface_min < 1 || args.surface_min > 64) return hipErrorInvalidValue;
   if (cfg.block < 64 || cfg.block > 256 || cfg.block % 64 || cfg.grid < 1) return hipErrorInvalidConfiguration;
   dim3 grid(cfg.grid), block(cfg.block);
   if (precision == 1) {
-    if (trace) hipLaunchKernelGGL((walk_kernel<double, true>), grid, block, 0, stream, args);
-    else hipLaunchKernelGGL((walk_kernel<double, false>), grid, block, 0, stream, args);
+    if (trace) hipLaunchKernelGGL((walk_kernel<double, true>), grid, block, 0, stream, args.jobs, args);
+    else hipLaunchKernelGGL((walk_kernel<double, false>), grid, block, 0, stream, args.jobs, args);
   } else {
-    if (trace) hipLaunchKernelGGL((walk_kernel<float, true>), grid, block, 0, stream, args);
-    else hipLaunchKernelGGL((walk_kernel<float, false>), grid, block, 0, stream, args);
+    if (trace) hipLaunchKernelGGL((walk_kernel<float, true>), grid, block, 0, stream, args.jobs, args);
+    else hipLaunchKernelGGL((walk_kernel<float, false>), grid, block, 0, stream, args.jobs, args);
   }
+  return hipGetLastError();
+}
+
+__global__ void zero_u64_n_kernel(unsigned long long* p, int n) {
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) p[i] = 0ull;
+}
+
+hipError_t launch_zero_u64_n(unsigned long long* p, int n, hipStream_t stream) {
+  if (!p || n < 1) return hipErrorInvalidValue;
+  const int blocks = (n + 255) / 256;
+  hipLaunchKernelGGL(zero_u64_n_kernel, dim3(blocks < 1024 ? blocks : 1024), dim3(256), 0, stream, p, n);
   return hipGetLastError();
 }
 

@@ -75,6 +75,8 @@ _SIGS = {
     "smcrt_engine_get_opts": ([_vp, C.POINTER(Opts)], C.c_int),
     "smcrt_engine_set_opts": ([_vp, C.POINTER(Opts)], C.c_int),
     "smcrt_run": ([_vp, _vp, C.c_uint64, C.c_uint64, C.c_uint64, _vp, _vp, _vp, _vp], C.c_int),
+    "smcrt_run_batch": ([_vp, C.c_int, C.POINTER(_vp), C.POINTER(C.c_uint64), C.POINTER(C.c_uint64),
+                         C.POINTER(C.c_uint64), C.POINTER(_vp), C.POINTER(_vp), C.POINTER(_vp), _vp], C.c_int),
     "smcrt_normalize_fluence": ([_vp, _vp, C.c_double, _vp, _vp], C.c_int),
     "smcrt_trace": ([_vp, _vp, C.c_uint64, _vp, C.c_int, C.c_int, _vp, _vp, _vp], C.c_int),
 }
@@ -186,6 +188,15 @@ def smcrt_engine_set_opts(engine, opts):
 
 def smcrt_run(engine, scene, seed, first_packet, n_packets, d_fluence_raw, d_absorbed, d_tallies, stream):
     _check(lib().smcrt_run(engine, scene, seed, first_packet, n_packets, d_fluence_raw, d_absorbed, d_tallies, stream))
+
+
+def smcrt_run_batch(engine, scenes, seeds, first_packets, n_packets, d_fluence_raw, d_absorbed, d_tallies, stream):
+    n = len(scenes)
+    arr = lambda T, v: (T * n)(*v)
+    _check(lib().smcrt_run_batch(engine, n, arr(_vp, scenes), arr(C.c_uint64, seeds),
+                                 arr(C.c_uint64, first_packets) if first_packets is not None else None,
+                                 arr(C.c_uint64, n_packets), arr(_vp, d_fluence_raw), arr(_vp, d_absorbed),
+                                 arr(_vp, d_tallies), stream))
 
 
 def smcrt_normalize_fluence(scene, d_raw, launched, d_phi, stream):
@@ -339,6 +350,28 @@ def launch(engine, scene, seed, n, first=0, outputs=None, stream=None):
     f, a, t = out.ptrs()
     smcrt_run(engine.h, scene.h, seed, first, n, f, a, t, _stream_ptr(stream))
     return out
+
+
+def launch_batch(engine, scenes, seeds, n_packets, firsts=None, outputs=None, stream=None):
+    """Queues one batched run (one persistent launch for all jobs); returns
+    the list of Outputs (not synchronised)."""
+    outs = outputs if outputs is not None else [Outputs(sc, engine.device) for sc in scenes]
+    ptrs = [o.ptrs() for o in outs]
+    smcrt_run_batch(engine.h, [sc.h for sc in scenes], list(seeds), list(firsts) if firsts is not None else None,
+                    list(n_packets), [p[0] for p in ptrs], [p[1] for p in ptrs], [p[2] for p in ptrs],
+                    _stream_ptr(stream))
+    return outs
+
+
+def run_batch(descs, seeds, n_packets, engine=None, precision="f32", firsts=None):
+    """Runs several scenes in one launch; returns host copies per job."""
+    import torch
+    eng = engine if engine is not None else Engine(0)
+    eng.set_opts(precision=precision)
+    scenes = [d if isinstance(d, Scene) else Scene(d) for d in descs]
+    outs = launch_batch(eng, scenes, seeds, n_packets, firsts)
+    torch.cuda.synchronize()
+    return [o.host() for o in outs]
 
 
 def run(desc, seed, n, first=0, engine=None, precision="f32", **opts):

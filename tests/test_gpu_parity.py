@@ -184,6 +184,46 @@ def test_uniform_grid_matches_brute_force(S, eng, W, prec):
         assert np.linalg.norm(with_grid["fluence_raw"] - brute["fluence_raw"]) <= 1e-2 * np.linalg.norm(brute["fluence_raw"])
 
 
+# ------------------------------------------------------------ batching ---
+
+def _close(a, b, rtol):
+    np.testing.assert_allclose(a["absorbed"], b["absorbed"], rtol=rtol)
+    np.testing.assert_allclose(a["escaped_face"], b["escaped_face"], rtol=rtol, atol=1e-12)
+    if a["fluence_raw"] is not None:
+        np.testing.assert_allclose(a["fluence_raw"], b["fluence_raw"], rtol=rtol, atol=1e-12)
+    for k in ("launched", "interactions", "interfaces", "voxel_pieces", "kills"):
+        assert a[k] == b[k], k
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_batch_equals_runs_alone(S, eng, W, prec):
+    """Mixed scene families in one persistent launch: every job's tallies
+    equal its run alone (same packets, same walks; FP64 sums reordered)."""
+    descs = [W.sphere_scene(n_grid=20), W.slab_scene(n_grid=24), W.cylinder_scene(n_grid=16),
+             W.vessel_scene(3, 0.7, n_caps=300, n_grid=16), W.sphere_scene(n_grid=20)]
+    seeds = [11, 12, 13, 14, 15]
+    ns = [20000, 5000, 4000, 3000, 777]
+    batch = S.run_batch(descs, seeds, ns, engine=eng, precision=prec)
+    for d, sd, n, b in zip(descs, seeds, ns, batch):
+        alone = S.run(d, sd, n, engine=eng, precision=prec)
+        _close(b, alone, 1e-11 if prec == "f64" else 1e-9)
+
+
+def test_many_small_jobs_share_one_launch(S, eng, W):
+    import torch
+    desc = W.sphere_scene(n_grid=8)
+    sc = S.Scene(desc)
+    eng.set_opts(precision="f64")
+    outs = S.launch_batch(eng, [sc] * 200, list(range(200)), [500] * 200)
+    torch.cuda.synchronize()
+    for j in (0, 7, 199):
+        h = outs[j].host()
+        alone = S.run(desc, j, 500, engine=eng, precision="f64")
+        _close(h, alone, 1e-11)
+    total = sum(o.host()["launched"] for o in outs)
+    assert total == 200 * 500
+
+
 # ------------------------------------------------------------ closed forms
 
 @pytest.mark.parametrize("prec", ["f32", "f64"])
