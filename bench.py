@@ -74,6 +74,68 @@ def measured_traffic():
     return float(vals["traffic_bytes_per_launch"])
 
 
+def serving(smcrt, workloads, n_requests, rate_hz, max_packets, precision, seed=2112):
+    """Continuous-batching leg: a seeded Poisson stream of requests drawn
+    from the four scene families (randomised optical properties, grids 32^3
+    to 128^3, packets log-uniform from 1e4 to max_packets) submitted at
+    their arrival times to one server; latency = completion - submission.
+    Three small check requests (2000 packets) ride in the stream and are
+    compared with the FP64 oracle on the same packets."""
+    import numpy as np
+    import torch
+
+    from oracle import oracle as orc
+    reqs = workloads.request_stream(seed, n_requests, rate_hz, packets=(1e4, max_packets),
+                                    grid_sides=(32, 64, 128))
+    checks = [workloads.sphere_scene(32), workloads.slab_scene(32), workloads.cylinder_scene(32)]
+    for i, d in enumerate(checks):
+        reqs.insert(1 + i * (len(reqs) // 3), {"id": -1 - i, "arrival": None, "scene": d, "seed": 77 + i, "n_packets": 2000})
+    for i, r in enumerate(reqs):  # checks arrive with their neighbours
+        if r["arrival"] is None:
+            r["arrival"] = reqs[i - 1]["arrival"]
+    scenes = [smcrt.Scene(r["scene"]) for r in reqs]
+    outs = [smcrt.Outputs(sc) for sc in scenes]
+    torch.cuda.synchronize()
+    sv = smcrt.Server(0, hbm_budget_bytes=16 << 30, epoch_packets=2_000_000, precision=precision)
+    t0 = time.perf_counter()
+    ids = []
+    for r, sc, o in zip(reqs, scenes, outs):
+        delay = r["arrival"] - (time.perf_counter() - t0)
+        if delay > 0:
+            time.sleep(delay)
+        ids.append(sv.submit(sc, r["seed"], r["n_packets"], outputs=o)[0])
+    for rid in ids:
+        sv.wait(rid, 600.0)
+    polls = [sv.poll(rid) for rid in ids]
+    lat = np.array([p[3] - p[1] for p in polls])
+    t_first = min(p[1] for p in polls)
+    t_last = max(p[3] for p in polls)
+    total = sum(r["n_packets"] for r in reqs)
+    st = sv.stats()
+    errs = []
+    for r, o in zip(reqs, outs):
+        if r["id"] >= 0:
+            continue
+        g = o.host()
+        ro = orc.run(r["scene"], r["seed"], r["n_packets"])
+        errs.append({"family": r["scene"]["name"],
+                     "relative_l2": float(np.linalg.norm(g["fluence_raw"] - ro["fluence_raw"]) / np.linalg.norm(ro["fluence_raw"])),
+                     "absorbed_relative": float(abs(g["absorbed"].sum() - ro["absorbed"].sum()) / ro["absorbed"].sum())})
+    sv.close()
+    return {
+        "requests": len(reqs),
+        "rate_hz": rate_hz,
+        "packets_range": [1e4, max_packets],
+        "p50_latency_s": float(np.percentile(lat, 50)),
+        "p99_latency_s": float(np.percentile(lat, 99)),
+        "aggregate_packets_per_s": total / (t_last - t_first),
+        "packets": total,
+        "epochs": st["epochs"],
+        "device_busy_fraction": st["busy_s"] / max(t_last - t_first, 1e-9),
+        "check_requests_vs_oracle": errs,
+    }
+
+
 def copy_calibration(smcrt, desc, steps):
     import torch
     sc = smcrt.Scene(desc)
@@ -104,6 +166,9 @@ def main():
     ap.add_argument("--packets", type=float, default=1e7)
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="target length of the oracle sample")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle leg (profiling runs)")
+    ap.add_argument("--serve-requests", type=int, default=200, help="requests in the serving leg (0 = skip)")
+    ap.add_argument("--serve-rate", type=float, default=40.0, help="Poisson arrival rate of the serving leg (1/s)")
+    ap.add_argument("--serve-max-packets", type=float, default=1e6, help="largest request of the serving leg")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only stream the 200^3 FP64 grid through the fluence normalisation kernel "
                          "(a plain read-once/write-once copy of known size) and report its bandwidth")
@@ -216,6 +281,9 @@ def main():
             "relative_l2": float(np.linalg.norm(Fg - Fo) / np.linalg.norm(Fo)),
             "absorbed_relative": float(abs(g["absorbed"].sum() - o["absorbed"].sum()) / o["absorbed"].sum()),
         }
+    if args.serve_requests > 0 and not args.no_cpu:
+        result["serving"] = serving(smcrt, workloads, args.serve_requests, args.serve_rate,
+                                    args.serve_max_packets, args.precision)
     print(json.dumps(result))
 
 

@@ -140,18 +140,31 @@ enum { SMCRT_PREC_F32 = 0, SMCRT_PREC_F64 = 1 };
  * (64, 128, 192 or 256).  blocks_per_cu: resident workgroups per CU the
  * grid is sized for (1..32; 0 = as many as fit).  refill_min: dead lanes a wave waits for
  * before it emits new packets (1..64).  surface_min: lanes a wave gathers at
- * surfaces before it runs the FP64 interface step (1..64). */
+ * surfaces before it runs the FP64 interface step (1..64).  Results do not
+ * depend on any of these except precision. */
 typedef struct {
   int32_t precision;
   int32_t block;
   int32_t blocks_per_cu;
   int32_t refill_min;
   int32_t surface_min;
-  int32_t reserved[3];
+  int32_t use_graph;    /* 1: capture the device work of a launch (grid builds,
+                           counter reset, walk) in a hipGraph and replay it
+                           while the launch shape is unchanged */
+  int32_t reserved[2];
 } smcrt_opts;
 
 smcrt_status smcrt_engine_get_opts(const smcrt_engine* engine, smcrt_opts* out);
 smcrt_status smcrt_engine_set_opts(smcrt_engine* engine, const smcrt_opts* opts);
+
+/* Autotuner: times runs of n_trial packets (>= 1000) of the scene under a
+ * small grid of launch options -- block 256 or 128, as many workgroups per
+ * CU as fit or one fewer, refill_min 1/4/16, surface_min 4/8/16 -- keeping
+ * the engine's precision, and sets the fastest as the engine's options.
+ * Synchronous; allocates and frees its own scratch outputs and stream.
+ * out_best and out_packets_per_s (host, may be NULL) receive the winner. */
+smcrt_status smcrt_engine_autotune(smcrt_engine* engine, const smcrt_scene* scene, uint64_t n_trial,
+                                   smcrt_opts* out_best, double* out_packets_per_s);
 
 /* ------------------------------------------------------------ tallies --- */
 
@@ -207,6 +220,46 @@ smcrt_status smcrt_run_batch(smcrt_engine* engine, int n, const smcrt_scene* con
  * doubles (may alias). */
 smcrt_status smcrt_normalize_fluence(const smcrt_scene* scene, const double* d_raw, double launched,
                                      double* d_phi, void* hip_stream);
+
+/* ------------------------------------------------------------ serving --- */
+/* Continuous batching of requests.  A server owns an engine on `device` and
+ * a worker thread.  Requests are admitted in arrival order while the device
+ * bytes they hold (outputs, scene tables, grid buffers) fit the budget; the
+ * worker runs epochs -- one batched launch in which every admitted request
+ * runs its next chunk of packet ids (about epoch_packets in total, split
+ * evenly) -- so requests arriving while others run join the next epoch.  A
+ * request is done when all its packets have run; its outputs then equal an
+ * smcrt_run of the same scene, seed and packets up to FP64 summation order.
+ * Scenes and outputs are borrowed until the request is DONE, FAILED or
+ * CANCELLED and must not change meanwhile.  device = -1 runs the scheduler
+ * without a device (epochs complete at once, outputs untouched): a dry run
+ * for admission, ordering, budget and cancellation.  Times are seconds since
+ * the server was created. */
+
+typedef struct smcrt_server smcrt_server;
+enum { SMCRT_REQ_QUEUED = 0, SMCRT_REQ_RUNNING = 1, SMCRT_REQ_DONE = 2, SMCRT_REQ_FAILED = 3, SMCRT_REQ_CANCELLED = 4 };
+
+typedef struct {
+  uint64_t epochs, packets_done, queued, active, bytes_in_use;
+  double busy_s, uptime_s;
+} smcrt_server_info;
+
+/* hbm_budget_bytes > 0; epoch_packets 0 = 2e6; opts NULL = engine defaults */
+smcrt_status smcrt_server_create(smcrt_server** out, int device, uint64_t hbm_budget_bytes,
+                                 uint64_t epoch_packets, const smcrt_opts* opts);
+/* cancels queued requests, finishes the running epoch, frees everything */
+smcrt_status smcrt_server_destroy(smcrt_server* server);
+/* SMCRT_E_BUDGET if the request alone exceeds the budget */
+smcrt_status smcrt_submit(smcrt_server* server, const smcrt_scene* scene, uint64_t seed, uint64_t n_packets,
+                          double* d_fluence_raw, double* d_absorbed, smcrt_tallies* d_tallies, uint64_t* out_request);
+/* state SMCRT_REQ_*; times of submission, admission and completion (-1 = not yet) */
+smcrt_status smcrt_poll(smcrt_server* server, uint64_t request, int* out_state, double* out_t_submit,
+                        double* out_t_admit, double* out_t_done);
+/* blocks until the request finishes (timeout_s < 0: no limit); returns its outcome */
+smcrt_status smcrt_wait(smcrt_server* server, uint64_t request, double timeout_s);
+/* queued: dropped; running: dropped at the end of the current epoch */
+smcrt_status smcrt_cancel(smcrt_server* server, uint64_t request);
+smcrt_status smcrt_server_stats(smcrt_server* server, smcrt_server_info* out);
 
 /* ------------------------------------------------------------ traces ---- */
 

@@ -515,6 +515,12 @@ struct smcrt_engine {
   size_t stage_cap = 0;
   hipEvent_t stage_done = nullptr;
   bool stage_pending = false;
+  // captured kernel sequence of the last launch shape (grid builds, counter
+  // reset, walk), replayed while the arena layout and options are unchanged
+  hipStream_t capture_stream = nullptr;
+  hipGraphExec_t graph_exec = nullptr;
+  std::vector<uint64_t> graph_key;
+  uint64_t graph_replays = 0;
 };
 
 static void default_opts(smcrt_opts* o) {
@@ -559,6 +565,8 @@ extern "C" smcrt_status smcrt_engine_destroy(smcrt_engine* e) {
   (void)hipSetDevice(e->device);
   (void)hipDeviceSynchronize();
   if (e->d_arena) (void)hipFree(e->d_arena);
+  if (e->graph_exec) (void)hipGraphExecDestroy(e->graph_exec);
+  if (e->capture_stream) (void)hipStreamDestroy(e->capture_stream);
   if (e->h_stage) (void)hipHostFree(e->h_stage);
   if (e->stage_done) (void)hipEventDestroy(e->stage_done);
   delete e;
@@ -712,19 +720,6 @@ static smcrt_status launch_jobs(smcrt_engine* e, const std::vector<JobSpec>& job
   HIP_TRY(hipMemcpyAsync(e->d_arena, e->h_stage, image_bytes, hipMemcpyHostToDevice, st), "hipMemcpyAsync(tables)");
   HIP_TRY(hipEventRecord(e->stage_done, st), "hipEventRecord(stage)");
   e->stage_pending = true;
-  for (size_t u = 0; u < uniq.size(); ++u) {
-    const SceneHeader* h = reinterpret_cast<const SceneHeader*>(uniq[u]->blob.data());
-    if (h->acc.region < 0) continue;
-    const size_t cb = align256(sizeof(uint32_t) * ((size_t)h->acc.n_cells + 1));
-    char* ab = base + acc_off[u];
-    char* sc = base + blob_off[u];
-    HIP_TRY(launch_accel_build(reinterpret_cast<const SceneHeader*>(sc), reinterpret_cast<const PrimD*>(sc + h->prim_offset_d),
-                               h->acc.n_prims, h->acc.n_cells, reinterpret_cast<uint32_t*>(ab),
-                               reinterpret_cast<uint32_t*>(ab + cb), reinterpret_cast<uint32_t*>(ab + 2 * cb),
-                               reinterpret_cast<uint32_t*>(ab + 3 * cb), st),
-            "accel build");
-  }
-  HIP_TRY(launch_zero_u64_n(reinterpret_cast<unsigned long long*>(base + counters_off), (int)jobs.size(), st), "zero counters");
   BatchArgs B;
   std::memset(&B, 0, sizeof(B));
   B.jobs = reinterpret_cast<const WalkArgs*>(base + jobs_off);
@@ -736,7 +731,62 @@ static smcrt_status launch_jobs(smcrt_engine* e, const std::vector<JobSpec>& job
     c.block = 64;
     c.grid = (tr->n_ids + 63) / 64;
   }
-  HIP_TRY(launch_walk(e->opts.precision, tr != nullptr, c, B, st), "walk kernel");
+  // the device-side sequence after the upload
+  auto enqueue = [&](hipStream_t q) -> smcrt_status {
+    for (size_t u = 0; u < uniq.size(); ++u) {
+      const SceneHeader* h = reinterpret_cast<const SceneHeader*>(uniq[u]->blob.data());
+      if (h->acc.region < 0) continue;
+      const size_t cb = align256(sizeof(uint32_t) * ((size_t)h->acc.n_cells + 1));
+      char* ab = base + acc_off[u];
+      char* sc = base + blob_off[u];
+      HIP_TRY(launch_accel_build(reinterpret_cast<const SceneHeader*>(sc), reinterpret_cast<const PrimD*>(sc + h->prim_offset_d),
+                                 h->acc.n_prims, h->acc.n_cells, reinterpret_cast<uint32_t*>(ab),
+                                 reinterpret_cast<uint32_t*>(ab + cb), reinterpret_cast<uint32_t*>(ab + 2 * cb),
+                                 reinterpret_cast<uint32_t*>(ab + 3 * cb), q),
+              "accel build");
+    }
+    HIP_TRY(launch_zero_u64_n(reinterpret_cast<unsigned long long*>(base + counters_off), (int)jobs.size(), q), "zero counters");
+    HIP_TRY(launch_walk(e->opts.precision, tr != nullptr, c, B, q), "walk kernel");
+    return SMCRT_OK;
+  };
+  if (!e->opts.use_graph || tr) return enqueue(st);
+  // replay the captured sequence when the launch shape is the same
+  std::vector<uint64_t> key = {(uint64_t)(uintptr_t)base, image_bytes, total, jobs.size(), (uint64_t)c.grid,
+                               (uint64_t)c.block, (uint64_t)e->opts.precision, (uint64_t)B.refill_min,
+                               (uint64_t)B.surface_min};
+  for (size_t u = 0; u < uniq.size(); ++u) {
+    const Accel& A = reinterpret_cast<const SceneHeader*>(uniq[u]->blob.data())->acc;
+    key.push_back(blob_off[u]);
+    key.push_back((uint64_t)A.region);
+    key.push_back((uint64_t)A.n_prims);
+    key.push_back((uint64_t)A.n_cells);
+  }
+  if (!e->graph_exec || key != e->graph_key) {
+    if (e->graph_exec) {
+      HIP_TRY(hipGraphExecDestroy(e->graph_exec), "hipGraphExecDestroy");
+      e->graph_exec = nullptr;
+    }
+    if (!e->capture_stream) HIP_TRY(hipStreamCreateWithFlags(&e->capture_stream, hipStreamNonBlocking), "hipStreamCreate");
+    HIP_TRY(hipStreamBeginCapture(e->capture_stream, hipStreamCaptureModeThreadLocal), "hipStreamBeginCapture");
+    smcrt_status r = enqueue(e->capture_stream);
+    hipGraph_t g = nullptr;
+    hipError_t ce = hipStreamEndCapture(e->capture_stream, &g);
+    if (r != SMCRT_OK) {
+      if (g) (void)hipGraphDestroy(g);
+      return r;
+    }
+    if (ce != hipSuccess) return hip_fail(ce, "hipStreamEndCapture");
+    hipError_t ie = hipGraphInstantiate(&e->graph_exec, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (ie != hipSuccess) {
+      e->graph_exec = nullptr;
+      return hip_fail(ie, "hipGraphInstantiate");
+    }
+    e->graph_key = key;
+  } else {
+    ++e->graph_replays;
+  }
+  HIP_TRY(hipGraphLaunch(e->graph_exec, st), "hipGraphLaunch");
   return SMCRT_OK;
 }
 
@@ -773,6 +823,89 @@ extern "C" smcrt_status smcrt_run_batch(smcrt_engine* e, int n, const smcrt_scen
   return launch_jobs(e, jobs, nullptr, (hipStream_t)hip_stream);
 }
 
+extern "C" smcrt_status smcrt_engine_autotune(smcrt_engine* e, const smcrt_scene* scene, uint64_t n_trial,
+                                              smcrt_opts* out_best, double* out_packets_per_s) {
+  if (!e || !scene) return fail(SMCRT_E_INVALID, "autotune: NULL engine or scene");
+  if (n_trial < 1000) return fail(SMCRT_E_INVALID, "autotune: n_trial must be >= 1000");
+  smcrt_scene* s = const_cast<smcrt_scene*>(scene);
+  smcrt_status st = pack(s);
+  if (st != SMCRT_OK) return st;
+  HIP_TRY(hipSetDevice(e->device), "hipSetDevice");
+  const SceneHeader* h = reinterpret_cast<const SceneHeader*>(s->blob.data());
+  const size_t nvox = h->has_grid ? (size_t)h->g_dims[0] * h->g_dims[1] * h->g_dims[2] : 0;
+  // scratch outputs and a private stream
+  double *f = nullptr, *ab = nullptr;
+  smcrt_tallies* t = nullptr;
+  hipStream_t q = nullptr;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  auto cleanup = [&]() {
+    if (q) (void)hipStreamSynchronize(q);
+    if (f) (void)hipFree(f);
+    if (ab) (void)hipFree(ab);
+    if (t) (void)hipFree(t);
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    if (q) (void)hipStreamDestroy(q);
+  };
+  hipError_t err = hipStreamCreateWithFlags(&q, hipStreamNonBlocking);
+  if (err == hipSuccess && nvox) err = hipMalloc(&f, sizeof(double) * nvox);
+  if (err == hipSuccess) err = hipMalloc(&ab, sizeof(double) * kMaxRegions);
+  if (err == hipSuccess) err = hipMalloc(&t, sizeof(smcrt_tallies));
+  if (err == hipSuccess) err = hipEventCreate(&e0);
+  if (err == hipSuccess) err = hipEventCreate(&e1);
+  if (err != hipSuccess) {
+    cleanup();
+    return hip_fail(err, "autotune set-up");
+  }
+  const smcrt_opts base = e->opts;
+  const int max_per_cu = walk_max_blocks_per_cu(base.precision, 256);
+  struct Shape { int block, per_cu; };
+  std::vector<Shape> shapes = {{256, 0}, {128, 0}};
+  if (max_per_cu > 1) shapes.push_back({256, max_per_cu - 1});
+  const int refills[3] = {1, 4, 16}, surfaces[3] = {4, 8, 16};
+  smcrt_opts best = base;
+  double best_rate = -1.0;
+  smcrt_status r = SMCRT_OK;
+  std::vector<JobSpec> jobs(1);
+  jobs[0] = JobSpec{s, 0x5eedull, 0, n_trial, f, ab, t};
+  for (const Shape& sh : shapes) {
+    for (int rf : refills) {
+      for (int sf : surfaces) {
+        smcrt_opts o = base;
+        o.block = sh.block;
+        o.blocks_per_cu = sh.per_cu;
+        o.refill_min = rf;
+        o.surface_min = sf;
+        o.use_graph = 0;
+        e->opts = o;
+        r = launch_jobs(e, jobs, nullptr, q);  // warm
+        if (r != SMCRT_OK) break;
+        if ((err = hipEventRecord(e0, q)) != hipSuccess) break;
+        r = launch_jobs(e, jobs, nullptr, q);
+        if (r != SMCRT_OK) break;
+        if ((err = hipEventRecord(e1, q)) != hipSuccess || (err = hipEventSynchronize(e1)) != hipSuccess) break;
+        float ms = 0.f;
+        if ((err = hipEventElapsedTime(&ms, e0, e1)) != hipSuccess) break;
+        const double rate = (double)n_trial / (ms * 1e-3);
+        if (rate > best_rate) {
+          best_rate = rate;
+          best = o;
+          best.use_graph = base.use_graph;
+        }
+      }
+      if (r != SMCRT_OK || err != hipSuccess) break;
+    }
+    if (r != SMCRT_OK || err != hipSuccess) break;
+  }
+  cleanup();
+  e->opts = (r == SMCRT_OK && err == hipSuccess) ? best : base;
+  if (r != SMCRT_OK) return r;
+  if (err != hipSuccess) return hip_fail(err, "autotune timing");
+  if (out_best) *out_best = best;
+  if (out_packets_per_s) *out_packets_per_s = best_rate;
+  return SMCRT_OK;
+}
+
 extern "C" smcrt_status smcrt_trace(smcrt_engine* e, const smcrt_scene* scene, uint64_t seed, const uint64_t* d_packet_ids,
                                     int n_ids, int max_events, smcrt_event* d_out, int32_t* d_count, void* hip_stream) {
   if (!e || !scene || !d_packet_ids || !d_out || !d_count) return fail(SMCRT_E_INVALID, "trace: NULL argument");
@@ -797,5 +930,300 @@ extern "C" smcrt_status smcrt_normalize_fluence(const smcrt_scene* scene, const 
   size_t n = (size_t)h->g_dims[0] * h->g_dims[1] * h->g_dims[2];
   double vol = h->g_d[0] * h->g_d[1] * h->g_d[2];
   HIP_TRY(launch_scale(d_raw, d_phi, n, 1.0 / (launched * vol), (hipStream_t)hip_stream), "scale kernel");
+  return SMCRT_OK;
+}
+
+// ------------------------------------------------------------------ serving
+//
+// Continuous batching: a worker thread admits queued requests in arrival
+// order while their device footprint fits the budget, then runs epochs.
+// An epoch is ONE batched launch in which every admitted request takes its
+// next chunk of packet ids; requests admitted while an epoch runs join the
+// next one, and a request is done once all its packets have run.  Packets
+// are keyed by (seed, packet id, event), and tallies add, so a request's
+// result equals its run alone up to FP64 summation order.
+
+#include <chrono>
+#include <condition_variable>
+#include <deque>
+#include <map>
+#include <mutex>
+#include <thread>
+
+namespace {
+
+struct Request {
+  uint64_t id = 0;
+  smcrt_scene* scene = nullptr;
+  uint64_t seed = 0, n = 0, next = 0;
+  double* fluence = nullptr;
+  double* absorbed = nullptr;
+  smcrt_tallies* tallies = nullptr;
+  uint64_t footprint = 0;
+  int state = SMCRT_REQ_QUEUED;
+  bool cancel = false;
+  double t_submit = 0, t_admit = -1, t_done = -1;
+  std::string error;
+};
+
+}  // namespace
+
+struct smcrt_server {
+  smcrt_engine* engine = nullptr;  // NULL: dry run (scheduling only)
+  uint64_t budget = 0, used = 0, epoch_packets = 0, min_chunk = 0;
+  std::mutex mu;
+  std::condition_variable cv_work, cv_done;
+  std::deque<Request*> queue;
+  std::vector<Request*> active;
+  std::map<uint64_t, Request*> all;
+  uint64_t next_id = 1;
+  bool stop = false;
+  std::thread worker;
+  hipStream_t stream = nullptr;
+  std::chrono::steady_clock::time_point t0;
+  uint64_t epochs = 0, packets_done = 0;
+  double busy_s = 0;
+};
+
+static double server_now(const smcrt_server* sv) {
+  return std::chrono::duration<double>(std::chrono::steady_clock::now() - sv->t0).count();
+}
+
+// device bytes a request holds while admitted: its outputs, its scene tables
+// and the grid buffers of its accelerated region
+static uint64_t request_footprint(const smcrt_scene* s) {
+  const SceneHeader* h = reinterpret_cast<const SceneHeader*>(s->blob.data());
+  uint64_t b = s->blob.size() + sizeof(WalkArgs) + sizeof(smcrt_tallies) + 8 * kMaxRegions + 256;
+  if (h->has_grid) b += 8ull * h->g_dims[0] * h->g_dims[1] * h->g_dims[2];
+  if (h->acc.region >= 0) b += 12ull * ((uint64_t)h->acc.n_cells + 1) + 4ull * h->acc.capacity;
+  return b;
+}
+
+static void server_loop(smcrt_server* sv) {
+  std::unique_lock<std::mutex> lk(sv->mu);
+  for (;;) {
+    // admit in arrival order while the budget allows
+    while (!sv->queue.empty()) {
+      Request* r = sv->queue.front();
+      if (r->cancel) {
+        sv->queue.pop_front();
+        r->state = SMCRT_REQ_CANCELLED;
+        r->t_done = server_now(sv);
+        sv->cv_done.notify_all();
+        continue;
+      }
+      if (sv->used + r->footprint > sv->budget) break;
+      sv->queue.pop_front();
+      sv->used += r->footprint;
+      r->state = SMCRT_REQ_RUNNING;
+      r->t_admit = server_now(sv);
+      sv->active.push_back(r);
+    }
+    if (sv->active.empty()) {
+      if (sv->stop) return;
+      sv->cv_work.wait(lk);
+      continue;
+    }
+    // one epoch over every admitted request
+    std::vector<JobSpec> jobs;
+    std::vector<std::pair<Request*, uint64_t>> taken;
+    const uint64_t share = std::max<uint64_t>(sv->min_chunk, sv->epoch_packets / sv->active.size());
+    for (Request* r : sv->active) {
+      if (r->cancel) continue;
+      const uint64_t chunk = std::min<uint64_t>(r->n - r->next, share);
+      if (chunk == 0) continue;
+      jobs.push_back(JobSpec{r->scene, r->seed, r->next, chunk, r->fluence, r->absorbed, r->tallies});
+      taken.push_back({r, chunk});
+    }
+    lk.unlock();
+    const double t_start = server_now(sv);
+    smcrt_status st = SMCRT_OK;
+    std::string err;
+    if (sv->engine && !jobs.empty()) {
+      st = launch_jobs(sv->engine, jobs, nullptr, sv->stream);
+      if (st == SMCRT_OK) {
+        hipError_t e = hipStreamSynchronize(sv->stream);
+        if (e != hipSuccess) st = hip_fail(e, "epoch");
+      }
+      if (st != SMCRT_OK) err = smcrt_last_error();
+    }
+    lk.lock();
+    sv->busy_s += server_now(sv) - t_start;
+    ++sv->epochs;
+    for (auto& rc : taken) {
+      rc.first->next += rc.second;
+      if (st == SMCRT_OK) sv->packets_done += rc.second;
+    }
+    const double t = server_now(sv);
+    std::vector<Request*> keep;
+    for (Request* r : sv->active) {
+      bool finished = false;
+      if (st != SMCRT_OK) {
+        r->state = SMCRT_REQ_FAILED;
+        r->error = err;
+        finished = true;
+      } else if (r->cancel) {
+        r->state = SMCRT_REQ_CANCELLED;
+        finished = true;
+      } else if (r->next >= r->n) {
+        r->state = SMCRT_REQ_DONE;
+        finished = true;
+      }
+      if (finished) {
+        r->t_done = t;
+        sv->used -= r->footprint;
+      } else {
+        keep.push_back(r);
+      }
+    }
+    sv->active.swap(keep);
+    sv->cv_done.notify_all();
+  }
+}
+
+extern "C" smcrt_status smcrt_server_create(smcrt_server** out, int device, uint64_t hbm_budget_bytes,
+                                            uint64_t epoch_packets, const smcrt_opts* opts) {
+  if (!out) return fail(SMCRT_E_INVALID, "server_create: out is NULL");
+  if (hbm_budget_bytes == 0) return fail(SMCRT_E_INVALID, "server_create: budget must be > 0");
+  if (opts) {
+    smcrt_status st = check_opts(opts);
+    if (st != SMCRT_OK) return st;
+  }
+  smcrt_server* sv = new (std::nothrow) smcrt_server();
+  if (!sv) return fail(SMCRT_E_NOMEM, "server_create: out of host memory");
+  sv->budget = hbm_budget_bytes;
+  sv->epoch_packets = epoch_packets ? epoch_packets : 2000000;
+  sv->min_chunk = std::max<uint64_t>(1, std::min<uint64_t>(10000, sv->epoch_packets));
+  sv->t0 = std::chrono::steady_clock::now();
+  if (device >= 0) {
+    smcrt_status st = smcrt_engine_create(&sv->engine, device);
+    if (st != SMCRT_OK) {
+      delete sv;
+      return st;
+    }
+    if (opts) sv->engine->opts = *opts;
+    hipError_t e = hipStreamCreateWithFlags(&sv->stream, hipStreamNonBlocking);
+    if (e != hipSuccess) {
+      smcrt_engine_destroy(sv->engine);
+      delete sv;
+      return hip_fail(e, "server stream");
+    }
+  }
+  sv->worker = std::thread([sv]() {
+    if (sv->engine) (void)hipSetDevice(sv->engine->device);
+    server_loop(sv);
+  });
+  *out = sv;
+  return SMCRT_OK;
+}
+
+extern "C" smcrt_status smcrt_server_destroy(smcrt_server* sv) {
+  if (!sv) return SMCRT_OK;
+  {
+    std::lock_guard<std::mutex> g(sv->mu);
+    sv->stop = true;
+    for (Request* r : sv->queue) r->cancel = true;
+  }
+  sv->cv_work.notify_all();
+  if (sv->worker.joinable()) sv->worker.join();
+  for (auto& kv : sv->all) delete kv.second;
+  if (sv->stream) (void)hipStreamDestroy(sv->stream);
+  if (sv->engine) smcrt_engine_destroy(sv->engine);
+  delete sv;
+  return SMCRT_OK;
+}
+
+extern "C" smcrt_status smcrt_submit(smcrt_server* sv, const smcrt_scene* scene, uint64_t seed, uint64_t n_packets,
+                                     double* d_fluence_raw, double* d_absorbed, smcrt_tallies* d_tallies,
+                                     uint64_t* out_request) {
+  if (!sv || !scene || !out_request) return fail(SMCRT_E_INVALID, "submit: NULL argument");
+  if (n_packets == 0) return fail(SMCRT_E_INVALID, "submit: n_packets must be >= 1");
+  smcrt_scene* s = const_cast<smcrt_scene*>(scene);
+  uint64_t fp;
+  {
+    std::lock_guard<std::mutex> g(sv->mu);  // the worker packs scenes under this lock's protection too
+    smcrt_status st = pack(s);
+    if (st != SMCRT_OK) return st;
+    const SceneHeader* h = reinterpret_cast<const SceneHeader*>(s->blob.data());
+    if (sv->engine && (!d_absorbed || !d_tallies || (h->has_grid && !d_fluence_raw)))
+      return fail(SMCRT_E_INVALID, "submit: output buffers missing");
+    fp = request_footprint(s);
+    if (fp > sv->budget)
+      return fail(SMCRT_E_BUDGET, "submit: request needs %llu bytes, budget is %llu", (unsigned long long)fp,
+                  (unsigned long long)sv->budget);
+    if (sv->stop) return fail(SMCRT_E_STATE, "submit: server is shutting down");
+    Request* r = new (std::nothrow) Request();
+    if (!r) return fail(SMCRT_E_NOMEM, "submit: out of host memory");
+    r->id = sv->next_id++;
+    r->scene = s;
+    r->seed = seed;
+    r->n = n_packets;
+    r->fluence = d_fluence_raw;
+    r->absorbed = d_absorbed;
+    r->tallies = d_tallies;
+    r->footprint = fp;
+    r->t_submit = server_now(sv);
+    sv->all[r->id] = r;
+    sv->queue.push_back(r);
+    *out_request = r->id;
+  }
+  sv->cv_work.notify_all();
+  return SMCRT_OK;
+}
+
+extern "C" smcrt_status smcrt_poll(smcrt_server* sv, uint64_t req, int* out_state, double* out_t_submit,
+                                   double* out_t_admit, double* out_t_done) {
+  if (!sv) return fail(SMCRT_E_INVALID, "poll: NULL server");
+  std::lock_guard<std::mutex> g(sv->mu);
+  auto it = sv->all.find(req);
+  if (it == sv->all.end()) return fail(SMCRT_E_INVALID, "poll: unknown request %llu", (unsigned long long)req);
+  const Request* r = it->second;
+  if (out_state) *out_state = r->state;
+  if (out_t_submit) *out_t_submit = r->t_submit;
+  if (out_t_admit) *out_t_admit = r->t_admit;
+  if (out_t_done) *out_t_done = r->t_done;
+  if (r->state == SMCRT_REQ_FAILED) g_last_error = r->error;
+  return SMCRT_OK;
+}
+
+extern "C" smcrt_status smcrt_wait(smcrt_server* sv, uint64_t req, double timeout_s) {
+  if (!sv) return fail(SMCRT_E_INVALID, "wait: NULL server");
+  std::unique_lock<std::mutex> lk(sv->mu);
+  auto it = sv->all.find(req);
+  if (it == sv->all.end()) return fail(SMCRT_E_INVALID, "wait: unknown request %llu", (unsigned long long)req);
+  Request* r = it->second;
+  auto done = [r]() { return r->state == SMCRT_REQ_DONE || r->state == SMCRT_REQ_FAILED || r->state == SMCRT_REQ_CANCELLED; };
+  if (timeout_s < 0) {
+    sv->cv_done.wait(lk, done);
+  } else if (!sv->cv_done.wait_for(lk, std::chrono::duration<double>(timeout_s), done)) {
+    return fail(SMCRT_E_STATE, "wait: request %llu not finished after %.3f s", (unsigned long long)req, timeout_s);
+  }
+  if (r->state == SMCRT_REQ_FAILED) return fail(SMCRT_E_HIP, "request failed: %s", r->error.c_str());
+  if (r->state == SMCRT_REQ_CANCELLED) return fail(SMCRT_E_CANCELLED, "request %llu was cancelled", (unsigned long long)req);
+  return SMCRT_OK;
+}
+
+extern "C" smcrt_status smcrt_cancel(smcrt_server* sv, uint64_t req) {
+  if (!sv) return fail(SMCRT_E_INVALID, "cancel: NULL server");
+  {
+    std::lock_guard<std::mutex> g(sv->mu);
+    auto it = sv->all.find(req);
+    if (it == sv->all.end()) return fail(SMCRT_E_INVALID, "cancel: unknown request %llu", (unsigned long long)req);
+    it->second->cancel = true;
+  }
+  sv->cv_work.notify_all();
+  return SMCRT_OK;
+}
+
+extern "C" smcrt_status smcrt_server_stats(smcrt_server* sv, smcrt_server_info* out) {
+  if (!sv || !out) return fail(SMCRT_E_INVALID, "server_stats: NULL argument");
+  std::lock_guard<std::mutex> g(sv->mu);
+  out->epochs = sv->epochs;
+  out->packets_done = sv->packets_done;
+  out->queued = sv->queue.size();
+  out->active = sv->active.size();
+  out->bytes_in_use = sv->used;
+  out->busy_s = sv->busy_s;
+  out->uptime_s = server_now(sv);
   return SMCRT_OK;
 }

@@ -48,9 +48,18 @@ class Event(C.Structure):
                 ("p", C.c_double * 3), ("u", C.c_double * 3), ("w", C.c_double), ("tau", C.c_double)]
 
 
+class ServerInfo(C.Structure):
+    _fields_ = [("epochs", C.c_uint64), ("packets_done", C.c_uint64), ("queued", C.c_uint64), ("active", C.c_uint64),
+                ("bytes_in_use", C.c_uint64), ("busy_s", C.c_double), ("uptime_s", C.c_double)]
+
+
+REQ_STATES = ["QUEUED", "RUNNING", "DONE", "FAILED", "CANCELLED"]
+
+
 class Opts(C.Structure):
     _fields_ = [("precision", C.c_int32), ("block", C.c_int32), ("blocks_per_cu", C.c_int32),
-                ("refill_min", C.c_int32), ("surface_min", C.c_int32), ("reserved", C.c_int32 * 3)]
+                ("refill_min", C.c_int32), ("surface_min", C.c_int32), ("use_graph", C.c_int32),
+                ("reserved", C.c_int32 * 2)]
 
 
 _lib = None
@@ -74,11 +83,20 @@ _SIGS = {
     "smcrt_engine_destroy": ([_vp], C.c_int),
     "smcrt_engine_get_opts": ([_vp, C.POINTER(Opts)], C.c_int),
     "smcrt_engine_set_opts": ([_vp, C.POINTER(Opts)], C.c_int),
+    "smcrt_engine_autotune": ([_vp, _vp, C.c_uint64, C.POINTER(Opts), C.POINTER(C.c_double)], C.c_int),
     "smcrt_run": ([_vp, _vp, C.c_uint64, C.c_uint64, C.c_uint64, _vp, _vp, _vp, _vp], C.c_int),
     "smcrt_run_batch": ([_vp, C.c_int, C.POINTER(_vp), C.POINTER(C.c_uint64), C.POINTER(C.c_uint64),
                          C.POINTER(C.c_uint64), C.POINTER(_vp), C.POINTER(_vp), C.POINTER(_vp), _vp], C.c_int),
     "smcrt_normalize_fluence": ([_vp, _vp, C.c_double, _vp, _vp], C.c_int),
     "smcrt_trace": ([_vp, _vp, C.c_uint64, _vp, C.c_int, C.c_int, _vp, _vp, _vp], C.c_int),
+    "smcrt_server_create": ([C.POINTER(_vp), C.c_int, C.c_uint64, C.c_uint64, C.POINTER(Opts)], C.c_int),
+    "smcrt_server_destroy": ([_vp], C.c_int),
+    "smcrt_submit": ([_vp, _vp, C.c_uint64, C.c_uint64, _vp, _vp, _vp, C.POINTER(C.c_uint64)], C.c_int),
+    "smcrt_poll": ([_vp, C.c_uint64, C.POINTER(C.c_int), C.POINTER(C.c_double), C.POINTER(C.c_double),
+                    C.POINTER(C.c_double)], C.c_int),
+    "smcrt_wait": ([_vp, C.c_uint64, C.c_double], C.c_int),
+    "smcrt_cancel": ([_vp, C.c_uint64], C.c_int),
+    "smcrt_server_stats": ([_vp, C.POINTER(ServerInfo)], C.c_int),
 }
 
 
@@ -186,6 +204,13 @@ def smcrt_engine_set_opts(engine, opts):
     _check(lib().smcrt_engine_set_opts(engine, C.byref(opts)))
 
 
+def smcrt_engine_autotune(engine, scene, n_trial):
+    o = Opts()
+    rate = C.c_double()
+    _check(lib().smcrt_engine_autotune(engine, scene, n_trial, C.byref(o), C.byref(rate)))
+    return o, rate.value
+
+
 def smcrt_run(engine, scene, seed, first_packet, n_packets, d_fluence_raw, d_absorbed, d_tallies, stream):
     _check(lib().smcrt_run(engine, scene, seed, first_packet, n_packets, d_fluence_raw, d_absorbed, d_tallies, stream))
 
@@ -205,6 +230,43 @@ def smcrt_normalize_fluence(scene, d_raw, launched, d_phi, stream):
 
 def smcrt_trace(engine, scene, seed, d_packet_ids, n_ids, max_events, d_out, d_count, stream):
     _check(lib().smcrt_trace(engine, scene, seed, d_packet_ids, n_ids, max_events, d_out, d_count, stream))
+
+
+def smcrt_server_create(device, hbm_budget_bytes, epoch_packets=0, opts=None):
+    h = _vp()
+    _check(lib().smcrt_server_create(C.byref(h), device, hbm_budget_bytes, epoch_packets,
+                                     C.byref(opts) if opts is not None else None))
+    return h
+
+
+def smcrt_server_destroy(server):
+    _check(lib().smcrt_server_destroy(server))
+
+
+def smcrt_submit(server, scene, seed, n_packets, d_fluence_raw, d_absorbed, d_tallies):
+    rid = C.c_uint64()
+    _check(lib().smcrt_submit(server, scene, seed, n_packets, d_fluence_raw, d_absorbed, d_tallies, C.byref(rid)))
+    return rid.value
+
+
+def smcrt_poll(server, request):
+    st, ts, ta, td = C.c_int(), C.c_double(), C.c_double(), C.c_double()
+    _check(lib().smcrt_poll(server, request, C.byref(st), C.byref(ts), C.byref(ta), C.byref(td)))
+    return REQ_STATES[st.value], ts.value, ta.value, td.value
+
+
+def smcrt_wait(server, request, timeout_s=-1.0):
+    _check(lib().smcrt_wait(server, request, timeout_s))
+
+
+def smcrt_cancel(server, request):
+    _check(lib().smcrt_cancel(server, request))
+
+
+def smcrt_server_stats(server):
+    info = ServerInfo()
+    _check(lib().smcrt_server_stats(server, C.byref(info)))
+    return {k: getattr(info, k) for k, _ in ServerInfo._fields_}
 
 
 # ---------------------------------------------------------------- helpers
@@ -278,19 +340,28 @@ class Engine:
         if opts:
             self.set_opts(**opts)
 
-    def set_opts(self, precision=None, block=None, blocks_per_cu=None, refill_min=None, surface_min=None):
+    def set_opts(self, precision=None, block=None, blocks_per_cu=None, refill_min=None, surface_min=None,
+                 use_graph=None):
         o = smcrt_engine_get_opts(self.h)
         if precision is not None:
             o.precision = PREC[precision] if isinstance(precision, str) else int(precision)
         for k, v in (("block", block), ("blocks_per_cu", blocks_per_cu), ("refill_min", refill_min),
-                     ("surface_min", surface_min)):
+                     ("surface_min", surface_min), ("use_graph", use_graph)):
             if v is not None:
                 setattr(o, k, int(v))
         smcrt_engine_set_opts(self.h, o)
 
+    def autotune(self, scene, n_trial=500_000):
+        """Times launch options on the scene and keeps the fastest; returns
+        (options dict, packets/s of the winner)."""
+        sc = scene if isinstance(scene, Scene) else Scene(scene)
+        _, rate = smcrt_engine_autotune(self.h, sc.h, n_trial)
+        return self.opts(), rate
+
     def opts(self):
         o = smcrt_engine_get_opts(self.h)
-        return {k: getattr(o, k) for k in ("precision", "block", "blocks_per_cu", "refill_min", "surface_min")}
+        return {k: getattr(o, k) for k in ("precision", "block", "blocks_per_cu", "refill_min", "surface_min",
+                                           "use_graph")}
 
     def close(self):
         if self.h:
@@ -412,3 +483,55 @@ def trace(desc, seed, pids, max_events=50, engine=None, precision="f32"):
                         "u": np.array(e.u[:]), "w": e.w, "tau": e.tau})
         res.append(evs)
     return res
+
+
+class Server:
+    """Continuous-batching request server (smcrt_server_*).  device=-1 runs
+    the scheduler alone (no device work)."""
+
+    def __init__(self, device=0, hbm_budget_bytes=32 << 30, epoch_packets=0, **opts):
+        o = None
+        if opts:
+            o = Opts()
+            o.precision, o.block, o.blocks_per_cu, o.refill_min, o.surface_min = 0, 256, 0, 4, 8
+            for k, v in opts.items():
+                setattr(o, k, PREC[v] if k == "precision" and isinstance(v, str) else int(v))
+        self.device = device
+        self.h = smcrt_server_create(device, hbm_budget_bytes, epoch_packets, o)
+        self._keep = {}
+
+    def submit(self, scene, seed, n_packets, outputs=None):
+        """Queues a request; returns (request id, Outputs or None)."""
+        sc = scene if isinstance(scene, Scene) else Scene(scene)
+        if self.device >= 0:
+            out = outputs if outputs is not None else Outputs(sc, self.device)
+            f, a, t = out.ptrs()
+        else:
+            out, f, a, t = None, None, None, None
+        rid = smcrt_submit(self.h, sc.h, seed, n_packets, f, a, t)
+        self._keep[rid] = (sc, out)
+        return rid, out
+
+    def poll(self, rid):
+        return smcrt_poll(self.h, rid)
+
+    def wait(self, rid, timeout_s=-1.0):
+        smcrt_wait(self.h, rid, timeout_s)
+
+    def cancel(self, rid):
+        smcrt_cancel(self.h, rid)
+
+    def stats(self):
+        return smcrt_server_stats(self.h)
+
+    def close(self):
+        if self.h:
+            smcrt_server_destroy(self.h)
+            self.h = None
+            self._keep.clear()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -69,8 +69,8 @@ def test_scene_validation_rejects_bad_input(S):
         with pytest.raises(S.SmcrtError, match="source"):
             S.smcrt_scene_info(h)
         S.smcrt_scene_add_region(h, [p], 0, 0.0, 0.1, 10, 0.9, 1.4)
-        S.smcrt_scene_set_source(h, 0, [5.0, 0, 0])  # outside everything but inside the padded volume? no:
-        nr, npr, lo, hi = S.smcrt_scene_info(h)       # the volume grows to hold the source
+        S.smcrt_scene_set_source(h, 0, [5.0, 0, 0])  # a source outside every region:
+        nr, npr, lo, hi = S.smcrt_scene_info(h)       # the volume grows to hold it
         assert nr == 1 and npr == 1 and hi[0] >= 5.0
     finally:
         S.smcrt_scene_destroy(h)
@@ -114,3 +114,64 @@ def test_binding_fails_loudly_without_library(S, monkeypatch, tmp_path):
     monkeypatch.setattr(S, "LIB_PATH", str(tmp_path / "missing.so"))
     with pytest.raises(RuntimeError, match="missing"):
         S.lib()
+
+
+# ---------------------------------------------------------------- serving
+# device = -1: the request scheduler without a device (epochs complete at
+# once), so admission order, the memory budget and cancellation run here.
+
+def _small_scene(S, W, n_grid):
+    return S.Scene(W.sphere_scene(n_grid=n_grid))
+
+
+def test_server_dry_run_completes_in_arrival_order(S, W):
+    sv = S.Server(device=-1, hbm_budget_bytes=1 << 30, epoch_packets=1000)
+    try:
+        sc = _small_scene(S, W, 8)
+        ids = [sv.submit(sc, i, 500 + 1000 * i)[0] for i in range(6)]
+        for rid in ids:
+            sv.wait(rid, 10.0)
+        states = [sv.poll(r) for r in ids]
+        assert all(s[0] == "DONE" for s in states)
+        admits = [s[2] for s in states]
+        assert admits == sorted(admits)
+        assert all(s[3] >= s[2] >= s[1] >= 0 for s in states)
+        st = sv.stats()
+        assert st["packets_done"] == sum(500 + 1000 * i for i in range(6))
+        assert st["bytes_in_use"] == 0 and st["queued"] == 0 and st["active"] == 0
+    finally:
+        sv.close()
+
+
+def test_server_budget_admits_one_at_a_time_and_rejects_oversize(S, W):
+    big = _small_scene(S, W, 64)      # 64^3 doubles = 2 MiB grid
+    sv = S.Server(device=-1, hbm_budget_bytes=3 << 20, epoch_packets=100)
+    try:
+        with pytest.raises(S.SmcrtError, match="budget"):
+            sv.submit(_small_scene(S, W, 128), 1, 10)  # 16 MiB grid never fits
+        ids = [sv.submit(big, i, 1000)[0] for i in range(3)]
+        for rid in ids:
+            sv.wait(rid, 10.0)
+        t = [sv.poll(r) for r in ids]
+        # only one request fits at a time: each is admitted after the previous finished
+        assert t[1][2] >= t[0][3] and t[2][2] >= t[1][3]
+    finally:
+        sv.close()
+
+
+def test_server_cancel_queued_request(S, W):
+    big = _small_scene(S, W, 64)
+    sv = S.Server(device=-1, hbm_budget_bytes=3 << 20, epoch_packets=10)
+    try:
+        a = sv.submit(big, 1, 200000)[0]   # many epochs
+        b = sv.submit(big, 2, 1000)[0]     # waits for the budget
+        sv.cancel(b)
+        with pytest.raises(S.SmcrtError, match="cancelled"):
+            sv.wait(b, 10.0)
+        assert sv.poll(b)[0] == "CANCELLED"
+        sv.wait(a, 30.0)
+        assert sv.poll(a)[0] == "DONE"
+        with pytest.raises(S.SmcrtError, match="unknown"):
+            sv.poll(12345)
+    finally:
+        sv.close()

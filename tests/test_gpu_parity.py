@@ -224,6 +224,86 @@ def test_many_small_jobs_share_one_launch(S, eng, W):
     assert total == 200 * 500
 
 
+def test_graph_replays_match_eager_runs(S, W):
+    """A captured launch sequence (grid builds, counter reset, walk) replayed
+    several times, with eager work and synchronisations in between: every
+    replay equals the eager run of the same seeds."""
+    import torch
+    descs = [W.vessel_scene(21, 1.0, n_caps=200, n_grid=16), W.sphere_scene(n_grid=12)]
+    g_eng = S.Engine(0, precision="f64", use_graph=1)
+    e_eng = S.Engine(0, precision="f64")
+    scenes = [S.Scene(d) for d in descs]
+    for rep in range(4):
+        seeds = [100 + rep, 200 + rep]
+        got = S.launch_batch(g_eng, scenes, seeds, [3000, 5000])
+        torch.cuda.synchronize()
+        want = S.launch_batch(e_eng, scenes, seeds, [3000, 5000])   # eager work between replays
+        torch.cuda.synchronize()
+        for a, b in zip(got, want):
+            _close(a.host(), b.host(), 1e-11)
+    g_eng.close()
+    e_eng.close()
+
+
+def test_autotune_picks_valid_options_and_keeps_results(S, W):
+    desc = W.sphere_scene(n_grid=16)
+    e = S.Engine(0, precision="f64")
+    opts, rate = e.autotune(desc, n_trial=200_000)
+    assert rate > 0
+    assert opts["block"] in (128, 256) and opts["refill_min"] in (1, 4, 16) and opts["surface_min"] in (4, 8, 16)
+    tuned = S.run(desc, 9, 20000, engine=e, precision="f64")
+    plain = S.run(desc, 9, 20000, engine=S.Engine(0), precision="f64")
+    _close(tuned, plain, 1e-11)
+    e.close()
+
+
+# ------------------------------------------------------------ serving ----
+
+def test_served_requests_equal_runs_alone(S, W):
+    """Continuous batching: requests of different families and sizes,
+    submitted while others run, each finish with the result of their run
+    alone (same packets; FP64 sums reordered)."""
+    import time
+    import torch
+    descs = [W.sphere_scene(n_grid=24), W.slab_scene(n_grid=32), W.cylinder_scene(n_grid=24),
+             W.vessel_scene(4, 1.2, n_caps=300, n_grid=24), W.sphere_scene(n_grid=16), W.slab_scene(n_grid=16)]
+    ns = [300000, 40000, 30000, 20000, 5000, 7000]
+    sv = S.Server(0, hbm_budget_bytes=1 << 30, epoch_packets=100000, precision="f64")
+    reqs = []
+    for i, (d, n) in enumerate(zip(descs, ns)):
+        reqs.append((d, n) + sv.submit(d, 500 + i, n))
+        time.sleep(0.01)
+    for d, n, rid, out in reqs:
+        sv.wait(rid, 120.0)
+        state, t_sub, t_adm, t_done = sv.poll(rid)
+        assert state == "DONE" and t_done >= t_adm >= t_sub
+    st = sv.stats()
+    assert st["epochs"] > 1 and st["packets_done"] == sum(ns)
+    torch.cuda.synchronize()
+    eng = S.Engine(0)
+    for i, (d, n, rid, out) in enumerate(reqs):
+        _close(out.host(), S.run(d, 500 + i, n, engine=eng, precision="f64"), 1e-11)
+    sv.close()
+    eng.close()
+
+
+def test_cancel_running_request_leaves_others_intact(S, W):
+    import time
+    import torch
+    sv = S.Server(0, hbm_budget_bytes=1 << 30, epoch_packets=20000, precision="f64")
+    d = W.sphere_scene(n_grid=16)
+    long_id, _ = sv.submit(d, 1, 5_000_000)
+    short_id, short_out = sv.submit(d, 2, 30000)
+    time.sleep(0.05)
+    sv.cancel(long_id)
+    with pytest.raises(S.SmcrtError, match="cancelled"):
+        sv.wait(long_id, 120.0)
+    sv.wait(short_id, 120.0)
+    torch.cuda.synchronize()
+    _close(short_out.host(), S.run(d, 2, 30000, engine=S.Engine(0), precision="f64"), 1e-11)
+    sv.close()
+
+
 # ------------------------------------------------------------ closed forms
 
 @pytest.mark.parametrize("prec", ["f32", "f64"])
