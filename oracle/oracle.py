@@ -90,6 +90,11 @@ def lib():
         L.orc_run.restype = C.c_int
         L.orc_trace.argtypes = [C.POINTER(Scene), C.c_uint64, C.c_uint64, C.c_int, C.POINTER(Event)]
         L.orc_trace.restype = C.c_int
+        L.orc_voxelize.argtypes = [C.POINTER(Scene), C.POINTER(C.c_int8)]
+        L.orc_run_voxel.argtypes = L.orc_run.argtypes
+        L.orc_run_voxel.restype = C.c_int
+        L.orc_trace_voxel.argtypes = L.orc_trace.argtypes
+        L.orc_trace_voxel.restype = C.c_int
         _lib = L
     return _lib
 
@@ -218,9 +223,11 @@ def tallies_dict(t):
     return d
 
 
-def run(scene, seed, n, first=0, threads=0, with_grid=True):
+def run(scene, seed, n, first=0, threads=0, with_grid=True, voxel=False):
     """Runs packets [first, first + n).  Returns a dict with the raw
-    fluence F (nz, ny, nx), absorbed weight per region and the tallies."""
+    fluence F (nz, ny, nx), absorbed weight per region and the tallies.
+    voxel=True runs the voxel-geometry model on the fluence grid instead of
+    the SDF walk."""
     cs = CScene(scene)
     dims = grid_dims(scene)
     nvox = dims[0] * dims[1] * dims[2]
@@ -229,7 +236,8 @@ def run(scene, seed, n, first=0, threads=0, with_grid=True):
     t = Tallies()
     if not with_grid:
         cs.s.g_dims = (C.c_int32 * 3)(0, 0, 0)
-    rc = lib().orc_run(cs.ref, C.c_uint64(seed), C.c_uint64(first), C.c_uint64(n), threads,
+    fn = lib().orc_run_voxel if voxel else lib().orc_run
+    rc = fn(cs.ref, C.c_uint64(seed), C.c_uint64(first), C.c_uint64(n), threads,
                        f.ctypes.data_as(C.POINTER(C.c_double)) if (nvox and with_grid) else None,
                        absorbed.ctypes.data_as(C.POINTER(C.c_double)), C.byref(t))
     if rc != 0:
@@ -240,11 +248,12 @@ def run(scene, seed, n, first=0, threads=0, with_grid=True):
     return out
 
 
-def trace(scene, seed, pid, cap=50):
+def trace(scene, seed, pid, cap=50, voxel=False):
     """Event records of packet pid: list of dicts (event, type, region, p, u, w, tau)."""
     cs = CScene(scene)
     buf = (Event * cap)()
-    n = lib().orc_trace(cs.ref, C.c_uint64(seed), C.c_uint64(pid), cap, buf)
+    fn = lib().orc_trace_voxel if voxel else lib().orc_trace
+    n = fn(cs.ref, C.c_uint64(seed), C.c_uint64(pid), cap, buf)
     if n < 0:
         raise RuntimeError("oracle trace failed")
     return [{"event": e.event, "type": EVENT_TYPES[e.type], "region": e.region, "p": np.array(e.p[:]),
@@ -313,6 +322,15 @@ def tally_segment(scene, a, b, w):
     f = np.zeros(dims[0] * dims[1] * dims[2])
     n = lib().orc_tally_segment(cs.ref, _d3(a), _d3(b), w, f.ctypes.data_as(C.POINTER(C.c_double)))
     return f.reshape(dims[2], dims[1], dims[0]), n
+
+
+def voxelize(scene):
+    """Region index (-1 ambient) of every voxel centre, shape (nz, ny, nx)."""
+    cs = CScene(scene)
+    dims = grid_dims(scene)
+    vox = np.zeros(dims[0] * dims[1] * dims[2], dtype=np.int8)
+    lib().orc_voxelize(cs.ref, vox.ctypes.data_as(C.POINTER(C.c_int8)))
+    return vox.reshape(dims[2], dims[1], dims[0])
 
 
 def lib_path():

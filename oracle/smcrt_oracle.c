@@ -648,3 +648,299 @@ int orc_trace(const orc_scene* s, uint64_t seed, uint64_t pid, int cap, orc_even
   free(absorbed);
   return wk.nrec;
 }
+
+
+/* ------------------------------------------------------ voxel model --- */
+/* The voxel-geometry MCRT the paper compares against (Sec. 2.3, Sec. 3.2):
+ * every voxel of the fluence grid carries the optical properties of the
+ * region that owns its centre; a packet is ray traced from voxel to voxel
+ * until its optical depth runs out or it leaves the grid.  Refractive
+ * index changes happen only on voxel faces, whose normals are the axes.
+ * reading: a source outside the grid first travels (untallied, unattenuated)
+ * to the grid; beyond the grid lies the ambient medium, so a packet leaving
+ * it meets Fresnel at that face like at any index change, and escapes when
+ * transmitted; faces between voxels of equal index are crossed without an
+ * event; faces with an index change are interface events (event index + 1,
+ * variate xi0). */
+
+void orc_voxelize(const orc_scene* s, int8_t* vox) {
+  const int* nd = s->g_dims;
+  for (int k = 0; k < nd[2]; ++k)
+    for (int j = 0; j < nd[1]; ++j)
+      for (int i = 0; i < nd[0]; ++i) {
+        double c[3];
+        const int ijk[3] = {i, j, k};
+        for (int a = 0; a < 3; ++a) {
+          double D = (s->g_hi[a] - s->g_lo[a]) / nd[a];
+          c[a] = s->g_lo[a] + (ijk[a] + 0.5) * D;
+        }
+        vox[(size_t)i + (size_t)nd[0] * ((size_t)j + (size_t)nd[1] * (size_t)k)] = (int8_t)orc_region_of(s, c);
+      }
+}
+
+typedef struct {
+  const int8_t* vox;
+} voxel_geo;
+
+static int vox_region(const orc_scene* s, const voxel_geo* vg, const int v[3]) {
+  return vg->vox[(size_t)v[0] + (size_t)s->g_dims[0] * ((size_t)v[1] + (size_t)s->g_dims[1] * (size_t)v[2])];
+}
+
+/* tally a straight piece that lies inside voxel v */
+static void vox_tally(walker* wk, const int v[3], double w, double l) {
+  const orc_scene* s = wk->s;
+  if (!wk->f || !(l > 0.0)) return;
+  wk->f[(size_t)v[0] + (size_t)s->g_dims[0] * ((size_t)v[1] + (size_t)s->g_dims[1] * (size_t)v[2])] += w * l;
+  wk->t->voxel_segments++;
+}
+
+static void walk_voxel(walker* wk, const voxel_geo* vg, uint64_t seed, uint64_t pid) {
+  const orc_scene* s = wk->s;
+  const int* nd = s->g_dims;
+  double D[3];
+  for (int a = 0; a < 3; ++a) D[a] = (s->g_hi[a] - s->g_lo[a]) / nd[a];
+  packet pk;
+  emit(wk, &pk, seed, pid);  /* sets the SDF-model region; replaced below */
+  int v[3];
+  int inside = 1;
+  for (int a = 0; a < 3; ++a)
+    if (pk.p[a] < s->g_lo[a] || pk.p[a] > s->g_hi[a]) inside = 0;
+  int entry_axis = -1;
+  if (!inside) { /* reach the grid through ambient, or miss it */
+    double t0 = 0.0, t1 = ORC_INF;
+    for (int a = 0; a < 3; ++a) {
+      if (pk.u[a] == 0.0) {
+        if (pk.p[a] < s->g_lo[a] || pk.p[a] > s->g_hi[a]) t1 = -1.0;
+      } else {
+        double ta = (s->g_lo[a] - pk.p[a]) / pk.u[a], tb = (s->g_hi[a] - pk.p[a]) / pk.u[a];
+        double tn = mind(ta, tb), tx = maxd(ta, tb);
+        if (tn > t0) { t0 = tn; entry_axis = a; }
+        t1 = mind(t1, tx);
+      }
+    }
+    if (!(t1 > t0) || entry_axis < 0) {
+      int face = 0;
+      double best = -ORC_INF;
+      for (int a = 0; a < 3; ++a) {
+        double c = 0.5 * (s->g_lo[a] + s->g_hi[a]), e = fabs(pk.p[a] - c) - 0.5 * (s->g_hi[a] - s->g_lo[a]);
+        if (e > best) { best = e; face = 2 * a + (pk.p[a] > c ? 1 : 0); }
+      }
+      pk.region = -1;
+      wk->t->escaped_face[face] += pk.w;
+      wk->t->escapes++;
+      record(wk, &pk, ORC_EV_ESCAPE);
+      return;
+    }
+    for (int a = 0; a < 3; ++a) pk.p[a] += t0 * pk.u[a];
+    pk.region = -1; /* still in ambient, on the grid face */
+  }
+  /* voxel holding the point, ties broken by the direction of travel */
+  for (int a = 0; a < 3; ++a) {
+    double x = (pk.p[a] - s->g_lo[a]) / D[a];
+    int i = (int)floor(x);
+    if (pk.u[a] < 0.0 && x == floor(x)) i -= 1;
+    if (a == entry_axis) i = pk.u[a] > 0.0 ? 0 : nd[a] - 1;
+    v[a] = i < 0 ? 0 : (i >= nd[a] ? nd[a] - 1 : i);
+  }
+  if (entry_axis >= 0) { /* crossing the grid face from ambient into voxel v */
+    int r2 = vox_region(s, vg, v);
+    double n1 = s->n_ambient, n2 = reg_n(s, r2);
+    if (n1 != n2) {
+      pk.k += 1;
+      wk->t->events++;
+      wk->t->interfaces++;
+      double xi[4];
+      event_xi(seed, pid, pk.k, xi);
+      double ci = fabs(pk.u[entry_axis]), ct;
+      double R = orc_fresnel(n1, n2, ci, &ct);
+      if (xi[0] < R) { /* reflected off the grid: it leaves */
+        pk.u[entry_axis] = -pk.u[entry_axis];
+        wk->t->reflections++;
+        record(wk, &pk, ORC_EV_REFLECT);
+        int face = 2 * entry_axis + (pk.u[entry_axis] > 0.0 ? 1 : 0);
+        wk->t->escaped_face[face] += pk.w;
+        wk->t->escapes++;
+        record(wk, &pk, ORC_EV_ESCAPE);
+        return;
+      }
+      double eta = n1 / n2, sg = pk.u[entry_axis] > 0.0 ? 1.0 : -1.0;
+      for (int a = 0; a < 3; ++a) pk.u[a] *= eta;
+      pk.u[entry_axis] += (ct - eta * ci) * sg;
+      double l = len3(pk.u);
+      for (int a = 0; a < 3; ++a) pk.u[a] /= l;
+      wk->t->refractions++;
+      pk.region = r2;
+      record(wk, &pk, ORC_EV_REFRACT);
+    } else {
+      pk.region = r2;
+    }
+  } else {
+    pk.region = vox_region(s, vg, v);
+  }
+  int32_t steps = 0; /* voxel faces crossed since the last event */
+  for (;;) {
+    if (++steps > s->max_steps || (int64_t)pk.k > s->max_events) {
+      wk->t->stalled += pk.w;
+      wk->t->stalls++;
+      record(wk, &pk, ORC_EV_STALL);
+      return;
+    }
+    wk->t->steps++;
+    /* distance to the exit face of voxel v along each axis */
+    double texit = ORC_INF;
+    int ax = -1;
+    for (int a = 0; a < 3; ++a) {
+      if (pk.u[a] == 0.0) continue;
+      double face = s->g_lo[a] + (v[a] + (pk.u[a] > 0.0 ? 1 : 0)) * D[a];
+      double t = (face - pk.p[a]) / pk.u[a];
+      if (t < 0.0) t = 0.0;
+      if (t < texit) { texit = t; ax = a; }
+    }
+    double mut = reg_mua(s, pk.region) + reg_mus(s, pk.region);
+    double s_rem = mut > 0.0 ? pk.tau / mut : ORC_INF;
+    if (s_rem <= texit) { /* interaction inside this voxel */
+      vox_tally(wk, v, pk.w, s_rem);
+      for (int a = 0; a < 3; ++a) pk.p[a] += s_rem * pk.u[a];
+      pk.tau = 0.0;
+      if (!interact(wk, &pk, seed, pid)) return;
+      steps = 0;
+      continue;
+    }
+    vox_tally(wk, v, pk.w, texit);
+    for (int a = 0; a < 3; ++a) pk.p[a] += texit * pk.u[a];
+    pk.tau -= mut * texit;
+    int w2[3] = {v[0], v[1], v[2]};
+    w2[ax] += pk.u[ax] > 0.0 ? 1 : -1;
+    const int off_grid = w2[ax] < 0 || w2[ax] >= nd[ax];
+    /* beyond the grid lies the ambient medium */
+    int r2 = off_grid ? -1 : vox_region(s, vg, w2);
+    double n1 = reg_n(s, pk.region), n2 = reg_n(s, r2);
+    if (off_grid && n1 == n2) {
+      int face = 2 * ax + (pk.u[ax] > 0.0 ? 1 : 0);
+      pk.region = -1;
+      wk->t->escaped_face[face] += pk.w;
+      wk->t->escapes++;
+      record(wk, &pk, ORC_EV_ESCAPE);
+      return;
+    }
+    if (n1 == n2) {
+      v[0] = w2[0]; v[1] = w2[1]; v[2] = w2[2];
+      pk.region = r2;
+      continue;
+    }
+    pk.k += 1;
+    steps = 0;
+    wk->t->events++;
+    wk->t->interfaces++;
+    double xi[4];
+    event_xi(seed, pid, pk.k, xi);
+    double ci = fabs(pk.u[ax]), ct;
+    double R = orc_fresnel(n1, n2, ci, &ct);
+    if (xi[0] < R) { /* reflect off the face, stay in v */
+      pk.u[ax] = -pk.u[ax];
+      wk->t->reflections++;
+      record(wk, &pk, ORC_EV_REFLECT);
+    } else {
+      double eta = n1 / n2, sg = pk.u[ax] > 0.0 ? 1.0 : -1.0;
+      for (int a = 0; a < 3; ++a) pk.u[a] *= eta;
+      pk.u[ax] += (ct - eta * ci) * sg;
+      double l = len3(pk.u);
+      for (int a = 0; a < 3; ++a) pk.u[a] /= l;
+      pk.region = r2;
+      wk->t->refractions++;
+      record(wk, &pk, ORC_EV_REFRACT);
+      if (off_grid) { /* transmitted out of the grid */
+        int face = 2 * ax + (sg > 0.0 ? 1 : 0);
+        wk->t->escaped_face[face] += pk.w;
+        wk->t->escapes++;
+        record(wk, &pk, ORC_EV_ESCAPE);
+        return;
+      }
+      v[0] = w2[0]; v[1] = w2[1]; v[2] = w2[2];
+    }
+  }
+}
+
+int orc_run_voxel(const orc_scene* s, uint64_t seed, uint64_t first, uint64_t n, int n_threads, double* f,
+                  double* absorbed, orc_tallies* t) {
+  if (check_scene(s) != 0 || !absorbed || !t) return -1;
+  const int* nd = s->g_dims;
+  if (nd[0] <= 0 || nd[1] <= 0 || nd[2] <= 0) return -1;
+  size_t nvox = (size_t)nd[0] * (size_t)nd[1] * (size_t)nd[2];
+  int8_t* vox = (int8_t*)malloc(nvox);
+  if (!vox) return -2;
+  orc_voxelize(s, vox);
+  voxel_geo vg = {vox};
+  int nt = 1;
+#ifdef _OPENMP
+  nt = n_threads > 0 ? n_threads : omp_get_max_threads();
+#endif
+  double** fs = (double**)calloc((size_t)nt, sizeof(double*));
+  double** as = (double**)calloc((size_t)nt, sizeof(double*));
+  orc_tallies* ts = (orc_tallies*)calloc((size_t)nt, sizeof(orc_tallies));
+  int fail = 0;
+  for (int i = 0; i < nt; ++i) {
+    fs[i] = f ? (double*)calloc(nvox, sizeof(double)) : NULL;
+    as[i] = (double*)calloc((size_t)s->n_regions, sizeof(double));
+    if ((f && !fs[i]) || !as[i]) fail = 1;
+  }
+  if (!fail) {
+#ifdef _OPENMP
+#pragma omp parallel num_threads(nt)
+#endif
+    {
+      int me = 0;
+#ifdef _OPENMP
+      me = omp_get_thread_num();
+#endif
+      walker wk = {s, fs[me], as[me], &ts[me], NULL, 0, 0};
+      uint64_t lo = first + n * (uint64_t)me / (uint64_t)nt;
+      uint64_t hi = first + n * (uint64_t)(me + 1) / (uint64_t)nt;
+      for (uint64_t pid = lo; pid < hi; ++pid) walk_voxel(&wk, &vg, seed, pid);
+    }
+    for (int i = 0; i < nt; ++i) {
+      if (f)
+        for (size_t q = 0; q < nvox; ++q) f[q] += fs[i][q];
+      for (int r = 0; r < s->n_regions; ++r) absorbed[r] += as[i][r];
+      t->launched += ts[i].launched;
+      for (int k = 0; k < 6; ++k) t->escaped_face[k] += ts[i].escaped_face[k];
+      t->roulette_gain += ts[i].roulette_gain;
+      t->roulette_loss += ts[i].roulette_loss;
+      t->stalled += ts[i].stalled;
+      t->events += ts[i].events;
+      t->steps += ts[i].steps;
+      t->interactions += ts[i].interactions;
+      t->interfaces += ts[i].interfaces;
+      t->reflections += ts[i].reflections;
+      t->refractions += ts[i].refractions;
+      t->crossings += ts[i].crossings;
+      t->advances += ts[i].advances;
+      t->voxel_segments += ts[i].voxel_segments;
+      t->kills += ts[i].kills;
+      t->stalls += ts[i].stalls;
+      t->escapes += ts[i].escapes;
+    }
+  }
+  for (int i = 0; i < nt; ++i) { free(fs[i]); free(as[i]); }
+  free(fs); free(as); free(ts); free(vox);
+  return fail ? -2 : 0;
+}
+
+int orc_trace_voxel(const orc_scene* s, uint64_t seed, uint64_t pid, int cap, orc_event* out) {
+  if (check_scene(s) != 0 || !out || cap < 1) return -1;
+  const int* nd = s->g_dims;
+  if (nd[0] <= 0 || nd[1] <= 0 || nd[2] <= 0) return -1;
+  size_t nvox = (size_t)nd[0] * (size_t)nd[1] * (size_t)nd[2];
+  int8_t* vox = (int8_t*)malloc(nvox);
+  double* absorbed = (double*)calloc((size_t)s->n_regions, sizeof(double));
+  if (!vox || !absorbed) { free(vox); free(absorbed); return -2; }
+  orc_voxelize(s, vox);
+  voxel_geo vg = {vox};
+  orc_tallies t;
+  memset(&t, 0, sizeof(t));
+  walker wk = {s, NULL, absorbed, &t, out, cap, 0};
+  walk_voxel(&wk, &vg, seed, pid);
+  free(vox);
+  free(absorbed);
+  return wk.nrec;
+}

@@ -103,6 +103,15 @@ int orc_run(const orc_scene* s, uint64_t seed, uint64_t first, uint64_t n,
 /* event records of one packet; returns the number written (<= cap) */
 int orc_trace(const orc_scene* s, uint64_t seed, uint64_t pid, int cap, orc_event* out);
 
+/* voxel-geometry model (the paper's comparison model): region per voxel of
+ * the fluence grid at its centre; vox receives nx*ny*nz region indices
+ * (-1 ambient).  orc_run_voxel / orc_trace_voxel walk packets through that
+ * voxel grid with the same emission, interaction and RNG protocol. */
+void orc_voxelize(const orc_scene* s, int8_t* vox);
+int orc_run_voxel(const orc_scene* s, uint64_t seed, uint64_t first, uint64_t n, int n_threads, double* f,
+                  double* absorbed, orc_tallies* t);
+int orc_trace_voxel(const orc_scene* s, uint64_t seed, uint64_t pid, int cap, orc_event* out);
+
 #ifdef __cplusplus
 }
 #endif

@@ -121,8 +121,18 @@ def cylinder_scene(n_grid=256):
     return sc
 
 
+_TREES = {}
+
+
 def vessel_tree(seed, n_caps=2000, side=0.2, r_min=5e-4, r_max=5e-3,
                 angle_deg=(20.0, 60.0), length_per_radius=8.0):
+    key = (int(seed), n_caps, side, r_min, r_max, tuple(angle_deg), length_per_radius)
+    if key not in _TREES:
+        _TREES[key] = _vessel_tree(*key[:5], key[5], key[6])
+    return [tuple(c) for c in _TREES[key]]
+
+
+def _vessel_tree(seed, n_caps, side, r_min, r_max, angle_deg, length_per_radius):
     """Seeded random branching tree of capsules inside the cube [0, side]^3.
 
     Roots start at the centre of the top face pointing -z (later roots at
@@ -239,8 +249,8 @@ def request_stream(seed, n_requests=1000, rate_hz=10.0, families=("sphere", "sla
             sc = slab_scene(side)
         elif fam == "cylinder":
             sc = cylinder_scene(side)
-        else:
-            sc = vessel_scene(int(rng.integers(1 << 30)), 1.0, n_caps=vessel_caps, n_grid=side)
+        else:  # one of eight trees; the optical properties below make each request distinct
+            sc = vessel_scene(int(rng.integers(8)), 1.0, n_caps=vessel_caps, n_grid=side)
         for rg in sc["regions"]:
             rg["mua"] = float(math.exp(rng.uniform(math.log(0.01), math.log(5.0))))
             rg["mus"] = float(math.exp(rng.uniform(math.log(10.0), math.log(500.0))))
@@ -267,15 +277,17 @@ def beer_lambert_slab(mua=2.0, thickness=0.5, n=1.5, half_xy=50.0):
     return sc
 
 
-def stack_scene(layers, half_xy=50.0):
+def stack_scene(layers, half_xy=50.0, nz=0):
     """Non-scattering stack of boxes; layers = [(thickness, mua, n), ...] from
-    the top face z = 0 down; pencil beam along -z."""
+    the top face z = 0 down; pencil beam along -z.  nz > 0 adds a 1 x 1 x nz
+    depth grid over the whole stack."""
     prims, regions, z = [], [], 0.0
     for i, (th, mua, n) in enumerate(layers):
         prims.append({"kind": "box", "c": [0.0, 0.0, z - 0.5 * th], "half": [half_xy, half_xy, 0.5 * th]})
         regions.append(_region([i], mua, 0.0, 0.0, n))
         z -= th
-    sc = _scene("stack", prims, regions, None, None)
+    grid = {"lo": [-half_xy, -half_xy, z], "hi": [half_xy, half_xy, 0.0], "dims": [1, 1, nz]} if nz else None
+    sc = _scene("stack", prims, regions, None, grid)
     sc["source"] = {"kind": "pencil", "p": [0.0, 0.0, 0.5 * sc["pad"]], "u": [0.0, 0.0, -1.0]}
     return sc
 
