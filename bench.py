@@ -58,7 +58,7 @@ def measured_traffic():
     import hashlib
     csrc = os.path.join(ROOT, "paper_2112_08035_amd", "csrc")
     h = hashlib.sha256()
-    for f in ("walk.hip", "layout.h"):
+    for f in ("walk.hip", "walk_common.h", "voxel_model.h", "layout.h"):
         with open(os.path.join(csrc, f), "rb") as fh:
             h.update(fh.read())
     path = os.path.join(ROOT, "profiles", "walk_kernel_slab_1e7_f32_traffic.md")
@@ -74,19 +74,48 @@ def measured_traffic():
     return float(vals["traffic_bytes_per_launch"])
 
 
-def serving(smcrt, workloads, n_requests, rate_hz, max_packets, precision, seed=2112):
+SERVE_GRIDS = (32, 64, 128)
+
+
+def serving_capacity(smcrt, workloads, max_packets, precision, seed, n_requests=48):
+    """Closed-loop capacity of the server on the request mix: a calibration
+    stream (its own seed) submitted all at once; packets per second from
+    the first submission to the last completion."""
+    import torch
+    reqs = workloads.request_stream(seed, n_requests, 1.0, packets=(1e4, max_packets), grid_sides=SERVE_GRIDS)
+    scenes = [smcrt.Scene(r["scene"]) for r in reqs]
+    outs = [smcrt.Outputs(sc) for sc in scenes]
+    torch.cuda.synchronize()
+    sv = smcrt.Server(0, hbm_budget_bytes=16 << 30, epoch_packets=2_000_000, precision=precision)
+    ids = [sv.submit(sc, r["seed"], r["n_packets"], outputs=o)[0] for r, sc, o in zip(reqs, scenes, outs)]
+    for rid in ids:
+        sv.wait(rid, 600.0)
+    polls = [sv.poll(rid) for rid in ids]
+    sv.close()
+    span = max(p[3] for p in polls) - min(p[1] for p in polls)
+    return sum(r["n_packets"] for r in reqs) / span
+
+
+def serving(smcrt, workloads, n_requests, rate_hz, max_packets, precision, seed=2112, load=0.7):
     """Continuous-batching leg: a seeded Poisson stream of requests drawn
     from the four scene families (randomised optical properties, grids 32^3
     to 128^3, packets log-uniform from 1e4 to max_packets) submitted at
     their arrival times to one server; latency = completion - submission.
+    Without a given rate, arrivals are set for the offered load `load`
+    (mean packets per request x rate / measured closed-loop capacity).
     Three small check requests (2000 packets) ride in the stream and are
     compared with the FP64 oracle on the same packets."""
+    import math
+
     import numpy as np
     import torch
 
     from oracle import oracle as orc
-    reqs = workloads.request_stream(seed, n_requests, rate_hz, packets=(1e4, max_packets),
-                                    grid_sides=(32, 64, 128))
+    mean_packets = (max_packets - 1e4) / math.log(max_packets / 1e4)  # log-uniform on [1e4, max]
+    capacity = serving_capacity(smcrt, workloads, max_packets, precision, seed + 1)
+    if rate_hz <= 0:
+        rate_hz = load * capacity / mean_packets
+    reqs = workloads.request_stream(seed, n_requests, rate_hz, packets=(1e4, max_packets), grid_sides=SERVE_GRIDS)
     checks = [workloads.sphere_scene(32), workloads.slab_scene(32), workloads.cylinder_scene(32)]
     for i, d in enumerate(checks):
         reqs.insert(1 + i * (len(reqs) // 3), {"id": -1 - i, "arrival": None, "scene": d, "seed": 77 + i, "n_packets": 2000})
@@ -125,6 +154,8 @@ def serving(smcrt, workloads, n_requests, rate_hz, max_packets, precision, seed=
     return {
         "requests": len(reqs),
         "rate_hz": rate_hz,
+        "capacity_packets_per_s": capacity,
+        "offered_load": rate_hz * mean_packets / capacity,
         "packets_range": [1e4, max_packets],
         "p50_latency_s": float(np.percentile(lat, 50)),
         "p99_latency_s": float(np.percentile(lat, 99)),
@@ -134,6 +165,53 @@ def serving(smcrt, workloads, n_requests, rate_hz, max_packets, precision, seed=
         "device_busy_fraction": st["busy_s"] / max(t_last - t_first, 1e-9),
         "check_requests_vs_oracle": errs,
     }
+
+
+def comparator(smcrt, workloads, precision, n=10_000_000, seed=3):
+    """Voxelised vs SDF geometry (the comparison of Sec. 3) on the curved
+    vessel workload: a capped-cylinder vessel across a 1 cm tissue cube,
+    top-hat beam, 256^3 FP64 grid.  Both models walk the same packets and
+    seeds; reported are each one's packets/s (whole run: tables, grids,
+    voxelisation, walk) and the voxel model's deviation from the SDF model's
+    tallies, beside the SDF model's own seed-to-seed Monte Carlo spread."""
+    import numpy as np
+    import torch
+    desc = workloads.cylinder_scene(256)
+    res, outs = {}, {}
+    for geom, sd in (("sdf", seed), ("voxel", seed), ("sdf_reseeded", seed + 1)):
+        eng = smcrt.Engine(0, precision=precision)
+        sc = smcrt.Scene(dict(desc, geometry="voxel" if geom == "voxel" else "sdf"))
+        out = smcrt.Outputs(sc)
+        smcrt.launch(eng, sc, seed + 100, 1_000_000, outputs=out)  # warm-up
+        torch.cuda.synchronize()
+        out.zero_()
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        smcrt.launch(eng, sc, sd, n, outputs=out)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t
+        outs[geom] = out.host()
+        if geom != "sdf_reseeded":
+            res[geom + "_packets_per_s"] = n / dt
+        eng.close()
+
+    def coarse(F):  # 32^3 blocks of 8^3 voxels
+        return F.reshape(32, 8, 32, 8, 32, 8).sum(axis=(1, 3, 5))
+
+    def rel_l2(a, b):
+        return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+    Fs, Fv, Fr = (outs[k]["fluence_raw"] for k in ("sdf", "voxel", "sdf_reseeded"))
+    res.update({
+        "workload": "capped-cylinder vessel (r 0.05 cm) in a 1 cm tissue cube, disc beam, 256^3 grid",
+        "packets": n,
+        "fluence_relative_l2_voxel_vs_sdf": rel_l2(Fv, Fs),
+        "fluence_relative_l2_voxel_vs_sdf_32cubed": rel_l2(coarse(Fv), coarse(Fs)),
+        "fluence_relative_l2_sdf_seed_to_seed": rel_l2(Fr, Fs),
+        "fluence_relative_l2_sdf_seed_to_seed_32cubed": rel_l2(coarse(Fr), coarse(Fs)),
+        "absorbed_fraction": {k: [float(x) / n for x in outs[k]["absorbed"]] for k in outs},
+    })
+    return res
 
 
 def copy_calibration(smcrt, desc, steps):
@@ -165,9 +243,11 @@ def main():
     ap.add_argument("--precision", default="f32", choices=["f32", "f64"])
     ap.add_argument("--packets", type=float, default=1e7)
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="target length of the oracle sample")
-    ap.add_argument("--no-cpu", action="store_true", help="skip the oracle leg (profiling runs)")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the oracle, comparator and serving legs (profiling runs)")
+    ap.add_argument("--no-comparator", action="store_true", help="skip the voxel-vs-SDF geometry comparison")
     ap.add_argument("--serve-requests", type=int, default=200, help="requests in the serving leg (0 = skip)")
-    ap.add_argument("--serve-rate", type=float, default=40.0, help="Poisson arrival rate of the serving leg (1/s)")
+    ap.add_argument("--serve-rate", type=float, default=0.0,
+                    help="Poisson arrival rate of the serving leg (1/s); 0 = 70%% of the measured capacity")
     ap.add_argument("--serve-max-packets", type=float, default=1e6, help="largest request of the serving leg")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only stream the 200^3 FP64 grid through the fluence normalisation kernel "
@@ -259,10 +339,16 @@ def main():
         threads = os.cpu_count() or 1
         # calibrate on a run long enough to hide the per-thread grid set-up,
         # then time a sample of about cpu_seconds
-        t = time.perf_counter()
-        orc.run(desc, 0, 20000)
-        rate0 = 20000 / (time.perf_counter() - t)
-        n_cpu = int(max(20000, min(3_000_000, rate0 * args.cpu_seconds)) // 1000 * 1000)
+        # time = fixed set-up (per-thread grids) + packets / rate: fit both
+        # from two short runs, then size the sample to about cpu_seconds
+        tt = []
+        for m in (20000, 80000):
+            t = time.perf_counter()
+            orc.run(desc, 0, m)
+            tt.append(time.perf_counter() - t)
+        rate0 = 60000 / max(tt[1] - tt[0], 1e-3)
+        setup = max(tt[0] - 20000 / rate0, 0.0)
+        n_cpu = int(max(20000, min(5_000_000, rate0 * max(args.cpu_seconds - setup, 1.0))) // 1000 * 1000)
         t = time.perf_counter()
         o = orc.run(desc, 0, n_cpu)
         cpu_s = time.perf_counter() - t
@@ -281,6 +367,8 @@ def main():
             "relative_l2": float(np.linalg.norm(Fg - Fo) / np.linalg.norm(Fo)),
             "absorbed_relative": float(abs(g["absorbed"].sum() - o["absorbed"].sum()) / o["absorbed"].sum()),
         }
+    if not args.no_cpu and not args.no_comparator:
+        result["voxel_comparator"] = comparator(smcrt, workloads, args.precision)
     if args.serve_requests > 0 and not args.no_cpu:
         result["serving"] = serving(smcrt, workloads, args.serve_requests, args.serve_rate,
                                     args.serve_max_packets, args.precision)

@@ -118,6 +118,22 @@ smcrt_status smcrt_scene_set_limits(smcrt_scene* scene, int32_t max_steps, int64
  * brute-force walk.  region = -1 removes the acceleration. */
 smcrt_status smcrt_scene_set_accel(smcrt_scene* scene, int32_t region, const int32_t cells[3]);
 
+/* Geometry model.  Sec. 3 measures the SDF model against a voxelised one;
+ * both run here on the same emission, interactions and random stream.
+ *   SMCRT_GEOM_SDF (default): packets sphere-trace the region SDFs.
+ *   SMCRT_GEOM_VOXEL: at every run the scene is first sampled onto its
+ *     fluence grid (each voxel takes the region that owns its centre, as
+ *     smcrt_voxelize returns) and packets move voxel face to voxel face;
+ *     a face where the refractive index changes is a Fresnel interface with
+ *     the face normal, beyond the grid lies the ambient medium, and a packet
+ *     transmitted through a grid face escapes through it.  A packet born
+ *     outside the grid travels to it unattenuated (escapes if it misses).
+ *     Needs a grid set with dims >= 1 in every axis; the step cap of
+ *     smcrt_scene_set_limits then counts voxel faces per event.
+ * Errors: SMCRT_E_INVALID for an unknown mode. */
+enum { SMCRT_GEOM_SDF = 0, SMCRT_GEOM_VOXEL = 1 };
+smcrt_status smcrt_scene_set_geometry(smcrt_scene* scene, int mode);
+
 /* number of regions and primitives; bounding box actually used */
 smcrt_status smcrt_scene_info(const smcrt_scene* scene, int32_t* n_regions, int32_t* n_prims,
                               double bb_lo[3], double bb_hi[3]);
@@ -285,6 +301,15 @@ typedef struct {
 smcrt_status smcrt_trace(smcrt_engine* engine, const smcrt_scene* scene, uint64_t seed,
                          const uint64_t* d_packet_ids, int n_ids, int max_events,
                          smcrt_event* d_out, int32_t* d_count, void* hip_stream);
+
+/* The voxelised geometry of Sec. 3: the region owning each voxel centre of
+ * the scene's fluence grid, from the FP64 region SDFs (the highest-index
+ * region whose SDF is negative, else the ambient medium).  d_out: device,
+ * nx*ny*nz bytes, x fastest; each byte is a region index, or n_regions for
+ * the ambient medium.  Asynchronous on hip_stream; the caller owns d_out.
+ * Errors: SMCRT_E_INVALID without a grid (dims >= 1 in every axis) or with
+ * a NULL argument; SMCRT_E_HIP on a device failure. */
+smcrt_status smcrt_voxelize(smcrt_engine* engine, const smcrt_scene* scene, uint8_t* d_out, void* hip_stream);
 
 #ifdef __cplusplus
 }

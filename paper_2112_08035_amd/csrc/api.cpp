@@ -72,6 +72,7 @@ struct smcrt_scene {
   int64_t max_events = 1000000;
   int32_t accel_region = -1;
   int32_t accel_cells[3] = {0, 0, 0};
+  int32_t geometry = kGeomSdf;
   // packed device tables (rebuilt when dirty)
   bool dirty = true;
   std::vector<unsigned char> blob;
@@ -233,6 +234,14 @@ extern "C" smcrt_status smcrt_scene_set_accel(smcrt_scene* s, int32_t region, co
 }
 
 // conservative box of a primitive
+extern "C" smcrt_status smcrt_scene_set_geometry(smcrt_scene* s, int mode) {
+  if (!s) return fail(SMCRT_E_INVALID, "set_geometry: NULL scene");
+  if (mode != SMCRT_GEOM_SDF && mode != SMCRT_GEOM_VOXEL) return fail(SMCRT_E_INVALID, "set_geometry: unknown mode %d", mode);
+  s->geometry = mode == SMCRT_GEOM_VOXEL ? kGeomVoxel : kGeomSdf;
+  s->dirty = true;
+  return SMCRT_OK;
+}
+
 static void prim_box(const HostPrim& p, double lo[3], double hi[3]) {
   for (int i = 0; i < 3; ++i) {
     switch (p.kind) {
@@ -279,6 +288,8 @@ static smcrt_status check_complete(const smcrt_scene* s) {
   const double* v = s->src;
   for (int i = 0; i < 3; ++i)
     if (!(v[i] >= lo[i] && v[i] <= hi[i])) return fail(SMCRT_E_INVALID, "source outside the simulation volume");
+  if (s->geometry == kGeomVoxel && !(s->grid_set && s->g_dims[0] > 0 && s->g_dims[1] > 0 && s->g_dims[2] > 0))
+    return fail(SMCRT_E_INVALID, "the voxel geometry needs a fluence grid with dims >= 1 in every axis");
   return SMCRT_OK;
 }
 
@@ -463,9 +474,13 @@ static smcrt_status pack(smcrt_scene* s) {
     h->g_lo[i] = glo[i];
     h->g_d[i] = gd[i] > 0 ? (ghi[i] - glo[i]) / gd[i] : 1.0;
     h->g_inv_d[i] = gd[i] > 0 ? gd[i] / (ghi[i] - glo[i]) : 1.0;
+    h->g_hi[i] = ghi[i];
     h->g_lof[i] = (float)glo[i];
     h->g_inv_df[i] = (float)h->g_inv_d[i];
+    h->g_df[i] = (float)h->g_d[i];
+    h->g_hif[i] = (float)ghi[i];
   }
+  h->geometry = s->geometry;
   h->src_kind = s->src_kind;
   std::memcpy(h->src, s->src, sizeof(h->src));
   h->w_threshold = s->w_threshold;
@@ -587,11 +602,11 @@ extern "C" smcrt_status smcrt_engine_set_opts(smcrt_engine* e, const smcrt_opts*
   return SMCRT_OK;
 }
 
-static LaunchCfg launch_cfg(smcrt_engine* e) {
+static LaunchCfg launch_cfg(smcrt_engine* e, int geometry) {
   LaunchCfg c;
   c.block = e->opts.block;
   int per_cu = e->opts.blocks_per_cu;
-  if (per_cu <= 0) per_cu = walk_max_blocks_per_cu(e->opts.precision, c.block);
+  if (per_cu <= 0) per_cu = walk_max_blocks_per_cu(e->opts.precision, c.block, geometry);
   if (per_cu <= 0) per_cu = 1;
   c.grid = e->n_cu * per_cu;
   c.refill_min = e->opts.refill_min;
@@ -616,10 +631,13 @@ struct TraceSpec {
 
 static size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
-// Lays the jobs' scenes, the job table, the per-job counters and the grid
-// buffers out in the engine arena, uploads the tables, builds the uniform
-// grids, zeroes the counters and launches the walk -- all on `st`.
-static smcrt_status launch_jobs(smcrt_engine* e, const std::vector<JobSpec>& jobs, const TraceSpec* tr, hipStream_t st) {
+// Lays the jobs' scenes, the job table, the per-job counters, the uniform
+// grids and the voxel grids out in the engine arena, uploads the tables,
+// builds the uniform grids, voxelises the voxel-model scenes, zeroes the
+// counters and launches the walk of each geometry present -- all on `st`.
+// With vox_out (one job) it stops after voxelising that scene into vox_out.
+static smcrt_status launch_jobs(smcrt_engine* e, const std::vector<JobSpec>& jobs, const TraceSpec* tr, hipStream_t st,
+                                uint8_t* vox_out = nullptr) {
   if (jobs.empty()) return SMCRT_OK;
   std::vector<smcrt_scene*> uniq;
   std::vector<int> job_scene(jobs.size());
@@ -627,7 +645,7 @@ static smcrt_status launch_jobs(smcrt_engine* e, const std::vector<JobSpec>& job
     smcrt_status r = pack(jobs[j].s);
     if (r != SMCRT_OK) return r;
     const SceneHeader* h = reinterpret_cast<const SceneHeader*>(jobs[j].s->blob.data());
-    if (h->has_grid && !jobs[j].fluence && !tr) return fail(SMCRT_E_INVALID, "job %zu: the scene has a grid but its fluence buffer is NULL", j);
+    if (h->has_grid && !jobs[j].fluence && !tr && !vox_out) return fail(SMCRT_E_INVALID, "job %zu: the scene has a grid but its fluence buffer is NULL", j);
     int k = -1;
     for (size_t u = 0; u < uniq.size(); ++u)
       if (uniq[u] == jobs[j].s) k = (int)u;
@@ -638,7 +656,7 @@ static smcrt_status launch_jobs(smcrt_engine* e, const std::vector<JobSpec>& job
     job_scene[j] = k;
   }
   // layout
-  std::vector<size_t> blob_off(uniq.size()), acc_off(uniq.size(), 0);
+  std::vector<size_t> blob_off(uniq.size()), acc_off(uniq.size(), 0), vox_off(uniq.size(), 0), vox_n(uniq.size(), 0);
   size_t off = 0;
   for (size_t u = 0; u < uniq.size(); ++u) {
     blob_off[u] = off;
@@ -654,6 +672,14 @@ static smcrt_status launch_jobs(smcrt_engine* e, const std::vector<JobSpec>& job
     if (A.region < 0) continue;
     acc_off[u] = off;
     off += 3 * align256(sizeof(uint32_t) * ((size_t)A.n_cells + 1)) + align256(sizeof(uint32_t) * A.capacity);
+  }
+  for (size_t u = 0; u < uniq.size(); ++u) {
+    const SceneHeader* h = reinterpret_cast<const SceneHeader*>(uniq[u]->blob.data());
+    if (h->geometry != kGeomVoxel && !vox_out) continue;
+    vox_n[u] = (size_t)h->g_dims[0] * h->g_dims[1] * h->g_dims[2];
+    if (vox_out) continue;
+    vox_off[u] = off;
+    off = align256(off + vox_n[u]);
   }
   const size_t total = off;
   if (total > e->arena_cap) {
@@ -689,6 +715,8 @@ static smcrt_status launch_jobs(smcrt_engine* e, const std::vector<JobSpec>& job
     a.absorbed = jobs[j].absorbed;
     a.tallies = jobs[j].tallies;
     a.acc_region = h->acc.region;
+    a.geometry = h->geometry;
+    if (vox_n[u]) a.vox = vox_out ? vox_out : reinterpret_cast<uint8_t*>(base + vox_off[u]);
     if (h->acc.region >= 0) {
       const size_t cb = align256(sizeof(uint32_t) * ((size_t)h->acc.n_cells + 1));
       a.acc_offsets = reinterpret_cast<const uint32_t*>(base + acc_off[u] + 2 * cb);
@@ -726,10 +754,14 @@ static smcrt_status launch_jobs(smcrt_engine* e, const std::vector<JobSpec>& job
   B.n_jobs = (int32_t)jobs.size();
   B.refill_min = e->opts.refill_min;
   B.surface_min = e->opts.surface_min;
-  LaunchCfg c = launch_cfg(e);
+  bool has_geom[2] = {false, false};
+  for (size_t j = 0; j < jobs.size(); ++j) has_geom[table[j].geometry == kGeomVoxel ? 1 : 0] = true;
+  LaunchCfg cg[2] = {launch_cfg(e, kGeomSdf), launch_cfg(e, kGeomVoxel)};
   if (tr) {
-    c.block = 64;
-    c.grid = (tr->n_ids + 63) / 64;
+    for (LaunchCfg& c : cg) {
+      c.block = 64;
+      c.grid = (tr->n_ids + 63) / 64;
+    }
   }
   // the device-side sequence after the upload
   auto enqueue = [&](hipStream_t q) -> smcrt_status {
@@ -745,21 +777,37 @@ static smcrt_status launch_jobs(smcrt_engine* e, const std::vector<JobSpec>& job
                                  reinterpret_cast<uint32_t*>(ab + 3 * cb), q),
               "accel build");
     }
+    for (size_t u = 0; u < uniq.size(); ++u) {
+      if (!vox_n[u]) continue;
+      int j0 = 0;
+      while (job_scene[j0] != (int)u) ++j0;
+      uint8_t* vb = vox_out ? vox_out : reinterpret_cast<uint8_t*>(base + vox_off[u]);
+      HIP_TRY(launch_voxelize(B.jobs, j0, vb, vox_n[u], q), "voxelize");
+    }
+    if (vox_out) return SMCRT_OK;
     HIP_TRY(launch_zero_u64_n(reinterpret_cast<unsigned long long*>(base + counters_off), (int)jobs.size(), q), "zero counters");
-    HIP_TRY(launch_walk(e->opts.precision, tr != nullptr, c, B, q), "walk kernel");
+    for (int g = 0; g < 2; ++g) {
+      if (!has_geom[g]) continue;
+      BatchArgs Bg = B;
+      Bg.geometry = g == 1 ? kGeomVoxel : kGeomSdf;
+      HIP_TRY(launch_walk(e->opts.precision, tr != nullptr, cg[g], Bg, q), "walk kernel");
+    }
     return SMCRT_OK;
   };
-  if (!e->opts.use_graph || tr) return enqueue(st);
+  if (!e->opts.use_graph || tr || vox_out) return enqueue(st);
   // replay the captured sequence when the launch shape is the same
-  std::vector<uint64_t> key = {(uint64_t)(uintptr_t)base, image_bytes, total, jobs.size(), (uint64_t)c.grid,
-                               (uint64_t)c.block, (uint64_t)e->opts.precision, (uint64_t)B.refill_min,
-                               (uint64_t)B.surface_min};
+  std::vector<uint64_t> key = {(uint64_t)(uintptr_t)base, image_bytes, total, jobs.size(), (uint64_t)cg[0].grid,
+                               (uint64_t)cg[1].grid, (uint64_t)cg[0].block, (uint64_t)e->opts.precision,
+                               (uint64_t)B.refill_min, (uint64_t)B.surface_min, (uint64_t)has_geom[0],
+                               (uint64_t)has_geom[1]};
   for (size_t u = 0; u < uniq.size(); ++u) {
     const Accel& A = reinterpret_cast<const SceneHeader*>(uniq[u]->blob.data())->acc;
     key.push_back(blob_off[u]);
     key.push_back((uint64_t)A.region);
     key.push_back((uint64_t)A.n_prims);
     key.push_back((uint64_t)A.n_cells);
+    key.push_back(vox_off[u]);
+    key.push_back(vox_n[u]);
   }
   if (!e->graph_exec || key != e->graph_key) {
     if (e->graph_exec) {
@@ -858,7 +906,7 @@ extern "C" smcrt_status smcrt_engine_autotune(smcrt_engine* e, const smcrt_scene
     return hip_fail(err, "autotune set-up");
   }
   const smcrt_opts base = e->opts;
-  const int max_per_cu = walk_max_blocks_per_cu(base.precision, 256);
+  const int max_per_cu = walk_max_blocks_per_cu(base.precision, 256, kGeomSdf);
   struct Shape { int block, per_cu; };
   std::vector<Shape> shapes = {{256, 0}, {128, 0}};
   if (max_per_cu > 1) shapes.push_back({256, max_per_cu - 1});
@@ -916,6 +964,16 @@ extern "C" smcrt_status smcrt_trace(smcrt_engine* e, const smcrt_scene* scene, u
   jobs[0] = JobSpec{const_cast<smcrt_scene*>(scene), seed, 0, 0, nullptr, nullptr, nullptr};
   TraceSpec tr{d_packet_ids, d_out, d_count, n_ids, max_events};
   return launch_jobs(e, jobs, &tr, (hipStream_t)hip_stream);
+}
+
+extern "C" smcrt_status smcrt_voxelize(smcrt_engine* e, const smcrt_scene* scene, uint8_t* d_out, void* hip_stream) {
+  if (!e || !scene || !d_out) return fail(SMCRT_E_INVALID, "voxelize: NULL engine, scene or output");
+  if (!(scene->grid_set && scene->g_dims[0] > 0 && scene->g_dims[1] > 0 && scene->g_dims[2] > 0))
+    return fail(SMCRT_E_INVALID, "voxelize: the scene needs a fluence grid with dims >= 1 in every axis");
+  HIP_TRY(hipSetDevice(e->device), "hipSetDevice");
+  std::vector<JobSpec> jobs(1);
+  jobs[0] = JobSpec{const_cast<smcrt_scene*>(scene), 0, 0, 0, nullptr, nullptr, nullptr};
+  return launch_jobs(e, jobs, nullptr, (hipStream_t)hip_stream, d_out);
 }
 
 extern "C" smcrt_status smcrt_normalize_fluence(const smcrt_scene* scene, const double* d_raw, double launched,
@@ -996,6 +1054,7 @@ static uint64_t request_footprint(const smcrt_scene* s) {
   uint64_t b = s->blob.size() + sizeof(WalkArgs) + sizeof(smcrt_tallies) + 8 * kMaxRegions + 256;
   if (h->has_grid) b += 8ull * h->g_dims[0] * h->g_dims[1] * h->g_dims[2];
   if (h->acc.region >= 0) b += 12ull * ((uint64_t)h->acc.n_cells + 1) + 4ull * h->acc.capacity;
+  if (h->geometry == kGeomVoxel) b += (uint64_t)h->g_dims[0] * h->g_dims[1] * h->g_dims[2];
   return b;
 }
 

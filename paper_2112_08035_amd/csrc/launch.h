@@ -7,8 +7,11 @@
 namespace smcrt {
 
 // precision: 0 = FP32 transport, 1 = FP64 transport; trace: record events
-// (trace launches take exactly one job)
+// (trace launches take exactly one job).  args.geometry selects the kernel
+// (sphere tracing or voxel walk) and the jobs it takes.
 hipError_t launch_walk(int precision, bool trace, const LaunchCfg& cfg, const BatchArgs& args, hipStream_t stream);
+// region slot of every voxel centre of job `job`'s scene into vox (n_vox bytes)
+hipError_t launch_voxelize(const WalkArgs* d_jobs, int job, uint8_t* vox, size_t n_vox, hipStream_t stream);
 // p[i] = 0 for i < n (a kernel, so resets can sit inside captured graphs)
 hipError_t launch_zero_u64_n(unsigned long long* p, int n, hipStream_t stream);
 // *p = 0 (a one-thread kernel, so the reset can sit inside captured graphs)
@@ -19,7 +22,7 @@ hipError_t launch_scale(const double* in, double* out, size_t n, double scale, h
 // cursors: n_cells each; offsets: n_cells + 1; ids: the capacity in the header)
 hipError_t launch_accel_build(const SceneHeader* d_sc, const PrimD* d_pd, int n_prims, int n_cells, uint32_t* counts,
                               uint32_t* cursors, uint32_t* offsets, uint32_t* ids, hipStream_t stream);
-// resident workgroups per CU of the walk kernel at this block size
-int walk_max_blocks_per_cu(int precision, int block);
+// resident workgroups per CU of the walk kernel of this geometry at this block size
+int walk_max_blocks_per_cu(int precision, int block, int geometry);
 
 }  // namespace smcrt

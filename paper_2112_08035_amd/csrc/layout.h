@@ -16,6 +16,10 @@ constexpr int kMaxPrims = 1 << 20;  // primitives per scene
 enum PrimKind : int32_t { kSphere = 0, kBox = 1, kCapsule = 2, kCylinder = 3 };
 enum RegionOp : int32_t { kUnion = 0, kSmoothUnion = 1 };
 enum SourceKind : int32_t { kPoint = 0, kPencil = 1, kDisc = 2, kRect = 3 };
+// geometry model of a scene: the signed distance functions themselves, or
+// the voxel grid they induce (region of each voxel centre) -- the voxelised
+// comparison model of Sec. 3
+enum Geometry : int32_t { kGeomSdf = 0, kGeomVoxel = 1 };
 
 // Primitive parameters, precomputed on the host:
 //   sphere   : c0 c1 c2 r
@@ -64,13 +68,13 @@ struct SceneHeader {
   int32_t n_prims, n_regions;     // the ambient medium is region slot n_regions
   int32_t has_grid, src_kind;
   int32_t g_dims[3], m_survive;
-  int32_t max_steps, pad0;
+  int32_t max_steps, geometry;    // steps per event: sphere-tracing steps or voxel faces
   int64_t max_events;
   double delta, h_normal, snap_cos, offset;  // surface threshold and surface-step constants
   double bb_c[3], bb_h[3];        // simulation volume (centre, half extents)
   float bb_cf[3], bb_hf[3];
-  double g_lo[3], g_inv_d[3], g_d[3];
-  float g_lof[3], g_inv_df[3];
+  double g_lo[3], g_inv_d[3], g_d[3], g_hi[3];
+  float g_lof[3], g_inv_df[3], g_df[3], g_hif[3];
   double src[8];
   double w_threshold, m_d, inv_m;
   float deltaf, pad1;
@@ -106,7 +110,8 @@ struct WalkArgs {
   int32_t* trace_count;
   int32_t n_trace, max_records;
   int32_t acc_region;            // copy of sc->acc.region (-1 = none)
-  int32_t pad;
+  int32_t geometry;              // copy of sc->geometry
+  uint8_t* vox;                  // voxel model: region slot per voxel (nx*ny*nz, x fastest)
 };
 
 // Arguments of one walk launch: a table of jobs in device memory.
@@ -114,7 +119,7 @@ struct BatchArgs {
   const WalkArgs* jobs;
   int32_t n_jobs;
   int32_t refill_min, surface_min;
-  int32_t pad;
+  int32_t geometry;              // the launch takes only the jobs of this geometry
 };
 
 }  // namespace smcrt

@@ -1,0 +1,656 @@
+// walk_common.h -- device code shared by the SDF walk (walk.hip) and the
+// voxel-model walk (voxel.hip): vector types, the Philox stream, scene
+// table access, the region SDFs, the path-length tally, the packet state,
+// emission, interactions, and the wave-level job picking and flushing.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include "../../include/smcrt.h"
+#include "layout.h"
+
+namespace smcrt {
+
+// Scene tables, primitives, uniform grids and job tables are read-only for a
+// kernel's lifetime: they are read through the constant address space, so
+// wave-uniform reads become scalar loads into SGPRs and per-lane reads plain
+// global loads.  The fluence grid is written through the global space.
+#define SMCRT_K __attribute__((address_space(4)))
+#define SMCRT_G __attribute__((address_space(1)))
+using ScP = const SMCRT_K SceneHeader*;
+using RegRef = const SMCRT_K Region&;
+using JobRef = const SMCRT_K WalkArgs&;
+template <class X>
+__device__ __forceinline__ const SMCRT_K X* kptr(const X* p) {
+  return (const SMCRT_K X*)p;
+}
+
+// ------------------------------------------------------------------ types
+
+template <typename T>
+struct V3 {
+  T x, y, z;
+};
+template <typename T>
+__device__ __forceinline__ V3<T> mk(T x, T y, T z) { return V3<T>{x, y, z}; }
+template <typename T>
+__device__ __forceinline__ V3<T> operator+(V3<T> a, V3<T> b) { return {a.x + b.x, a.y + b.y, a.z + b.z}; }
+template <typename T>
+__device__ __forceinline__ V3<T> operator-(V3<T> a, V3<T> b) { return {a.x - b.x, a.y - b.y, a.z - b.z}; }
+template <typename T>
+__device__ __forceinline__ V3<T> operator*(T s, V3<T> a) { return {s * a.x, s * a.y, s * a.z}; }
+template <typename T>
+__device__ __forceinline__ T dot(V3<T> a, V3<T> b) { return a.x * b.x + a.y * b.y + a.z * b.z; }
+template <typename T>
+__device__ __forceinline__ V3<double> to_d(V3<T> a) { return {(double)a.x, (double)a.y, (double)a.z}; }
+template <typename T>
+__device__ __forceinline__ V3<T> from_d(V3<double> a) { return {(T)a.x, (T)a.y, (T)a.z}; }
+
+__device__ __forceinline__ float tsqrt(float x) { return __builtin_sqrtf(x); }
+__device__ __forceinline__ double tsqrt(double x) { return __builtin_sqrt(x); }
+__device__ __forceinline__ float tlog(float x) { return __logf(x); }
+__device__ __forceinline__ double tlog(double x) { return log(x); }
+__device__ __forceinline__ void tsincos_2pi(float xi, float* s, float* c) {
+  float a = 6.2831853071795864769f * xi;
+  *s = __sinf(a);
+  *c = __cosf(a);
+}
+__device__ __forceinline__ void tsincos_2pi(double xi, double* s, double* c) { sincos(2.0 * M_PI * xi, s, c); }
+__device__ __forceinline__ float tdiv(float a, float b) { return __fdividef(a, b); }
+__device__ __forceinline__ double tdiv(double a, double b) { return a / b; }
+template <typename T>
+__device__ __forceinline__ T tmin(T a, T b) { return a < b ? a : b; }
+template <typename T>
+__device__ __forceinline__ T tmax(T a, T b) { return a > b ? a : b; }
+template <typename T>
+__device__ __forceinline__ T tabs(T a) { return a < T(0) ? -a : a; }
+template <typename T>
+__device__ __forceinline__ T tclamp(T x, T lo, T hi) { return x < lo ? lo : (x > hi ? hi : x); }
+template <typename T>
+__device__ __forceinline__ T tinf();
+template <>
+__device__ __forceinline__ float tinf<float>() { return __builtin_inff(); }
+template <>
+__device__ __forceinline__ double tinf<double>() { return __builtin_inf(); }
+
+// ------------------------------------------------------------------ Philox
+
+// Philox4x32-10 (Salmon et al., SC'11): ten rounds; each multiplies words 0
+// and 2 by the round constants, swaps in the high halves xor-ed with the
+// other words and the round key, and bumps the key by the Weyl constants.
+struct U4 {
+  uint32_t w0, w1, w2, w3;
+};
+__device__ __forceinline__ U4 philox10(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3, uint32_t k0, uint32_t k1) {
+#pragma unroll
+  for (int r = 0; r < 10; ++r) {
+    const uint64_t m0 = (uint64_t)0xD2511F53u * (uint64_t)c0;
+    const uint64_t m1 = (uint64_t)0xCD9E8D57u * (uint64_t)c2;
+    const uint32_t x0 = (uint32_t)(m1 >> 32) ^ c1 ^ k0;
+    const uint32_t x2 = (uint32_t)(m0 >> 32) ^ c3 ^ k1;
+    c1 = (uint32_t)m1;
+    c3 = (uint32_t)m0;
+    c0 = x0;
+    c2 = x2;
+    k0 += 0x9E3779B9u;
+    k1 += 0xBB67AE85u;
+  }
+  return U4{c0, c1, c2, c3};
+}
+
+// a 32-bit word -> (m + 1/2) / 2^23 with m its top 23 bits; exact in FP32
+template <typename T>
+__device__ __forceinline__ T xi_of(uint32_t w) {
+  return ((T)(w >> 9) + T(0.5)) * T(1.0 / 8388608.0);
+}
+
+// ------------------------------------------------------------------ scene
+
+template <typename T>
+struct Tab;
+template <>
+struct Tab<float> {
+  static __device__ __forceinline__ const SMCRT_K PrimF* prims(JobRef a) { return kptr(a.pf); }
+  static __device__ __forceinline__ float k(RegRef r) { return r.kf; }
+  static __device__ __forceinline__ float inv_k(RegRef r) { return r.inv_kf; }
+  static __device__ __forceinline__ float mut(RegRef r) { return r.mutf; }
+  static __device__ __forceinline__ float inv_mut(RegRef r) { return r.inv_mutf; }
+  static __device__ __forceinline__ V3<float> bb_c(ScP s) { return {s->bb_cf[0], s->bb_cf[1], s->bb_cf[2]}; }
+  static __device__ __forceinline__ V3<float> bb_h(ScP s) { return {s->bb_hf[0], s->bb_hf[1], s->bb_hf[2]}; }
+  static __device__ __forceinline__ V3<float> g_lo(ScP s) { return {s->g_lof[0], s->g_lof[1], s->g_lof[2]}; }
+  static __device__ __forceinline__ V3<float> g_inv(ScP s) { return {s->g_inv_df[0], s->g_inv_df[1], s->g_inv_df[2]}; }
+  static __device__ __forceinline__ float g_d(ScP s, int i) { return s->g_df[i]; }
+  static __device__ __forceinline__ float g_lo(ScP s, int i) { return s->g_lof[i]; }
+  static __device__ __forceinline__ float g_hi(ScP s, int i) { return s->g_hif[i]; }
+  static __device__ __forceinline__ float delta(ScP s) { return s->deltaf; }
+  static __device__ __forceinline__ V3<float> acc_lo(const SMCRT_K Accel& A) { return {A.lof[0], A.lof[1], A.lof[2]}; }
+  static __device__ __forceinline__ V3<float> acc_inv(const SMCRT_K Accel& A) { return {A.inv_cellf[0], A.inv_cellf[1], A.inv_cellf[2]}; }
+  static __device__ __forceinline__ V3<float> acc_blo(const SMCRT_K Accel& A) { return {A.box_lof[0], A.box_lof[1], A.box_lof[2]}; }
+  static __device__ __forceinline__ V3<float> acc_bhi(const SMCRT_K Accel& A) { return {A.box_hif[0], A.box_hif[1], A.box_hif[2]}; }
+  static __device__ __forceinline__ float acc_margin(const SMCRT_K Accel& A) { return A.marginf; }
+};
+template <>
+struct Tab<double> {
+  static __device__ __forceinline__ const SMCRT_K PrimD* prims(JobRef a) { return kptr(a.pd); }
+  static __device__ __forceinline__ double k(RegRef r) { return r.k; }
+  static __device__ __forceinline__ double inv_k(RegRef r) { return r.inv_k; }
+  static __device__ __forceinline__ double mut(RegRef r) { return r.mut; }
+  static __device__ __forceinline__ double inv_mut(RegRef r) { return r.inv_mut; }
+  static __device__ __forceinline__ V3<double> bb_c(ScP s) { return {s->bb_c[0], s->bb_c[1], s->bb_c[2]}; }
+  static __device__ __forceinline__ V3<double> bb_h(ScP s) { return {s->bb_h[0], s->bb_h[1], s->bb_h[2]}; }
+  static __device__ __forceinline__ V3<double> g_lo(ScP s) { return {s->g_lo[0], s->g_lo[1], s->g_lo[2]}; }
+  static __device__ __forceinline__ V3<double> g_inv(ScP s) { return {s->g_inv_d[0], s->g_inv_d[1], s->g_inv_d[2]}; }
+  static __device__ __forceinline__ double g_d(ScP s, int i) { return s->g_d[i]; }
+  static __device__ __forceinline__ double g_lo(ScP s, int i) { return s->g_lo[i]; }
+  static __device__ __forceinline__ double g_hi(ScP s, int i) { return s->g_hi[i]; }
+  static __device__ __forceinline__ double delta(ScP s) { return s->delta; }
+  static __device__ __forceinline__ V3<double> acc_lo(const SMCRT_K Accel& A) { return {A.lo[0], A.lo[1], A.lo[2]}; }
+  static __device__ __forceinline__ V3<double> acc_inv(const SMCRT_K Accel& A) { return {A.inv_cell[0], A.inv_cell[1], A.inv_cell[2]}; }
+  static __device__ __forceinline__ V3<double> acc_blo(const SMCRT_K Accel& A) { return {A.box_lo[0], A.box_lo[1], A.box_lo[2]}; }
+  static __device__ __forceinline__ V3<double> acc_bhi(const SMCRT_K Accel& A) { return {A.box_hi[0], A.box_hi[1], A.box_hi[2]}; }
+  static __device__ __forceinline__ double acc_margin(const SMCRT_K Accel& A) { return A.margin; }
+};
+
+// exact Euclidean SDF of one primitive (Sec. 2.2; Eq. 3 for the sphere)
+template <typename T>
+__device__ __forceinline__ T prim_sdf(const SMCRT_K Prim<T>* P, int i, V3<T> p) {
+  const int kind = P[i].kind;
+  const SMCRT_K T* v = P[i].v;
+  const V3<T> q = p - mk(v[0], v[1], v[2]);
+  if (kind == kSphere) return tsqrt(dot(q, q)) - v[3];
+  if (kind == kBox) {
+    const T ex = tabs(q.x) - v[3], ey = tabs(q.y) - v[4], ez = tabs(q.z) - v[5];
+    const V3<T> o = mk(tmax(ex, T(0)), tmax(ey, T(0)), tmax(ez, T(0)));
+    return tsqrt(dot(o, o)) + tmin(tmax(ex, tmax(ey, ez)), T(0));
+  }
+  const V3<T> e = mk(v[3], v[4], v[5]);
+  if (kind == kCapsule) {  // e = b - a, v[6] = 1/|b-a|^2
+    const T t = tclamp(dot(q, e) * v[6], T(0), T(1));
+    const V3<T> d = q - t * e;
+    return tsqrt(dot(d, d)) - v[7];
+  }
+  // capped cylinder: e unit axis, v[6] = L, v[7] = L/2, v[8] = r
+  const T x = dot(q, e);
+  const V3<T> rad = q - x * e;
+  const T q1 = tsqrt(dot(rad, rad)) - v[8];
+  const T q2 = tabs(x - v[7]) - v[7];
+  const T o1 = tmax(q1, T(0)), o2 = tmax(q2, T(0));
+  return tmin(tmax(q1, q2), T(0)) + tsqrt(o1 * o1 + o2 * o2);
+}
+
+// region SDF: union (min) or polynomial smooth union of its primitives
+template <typename T>
+__device__ __forceinline__ T region_sdf(JobRef a, RegRef R, V3<T> p) {
+  const SMCRT_K Prim<T>* P = Tab<T>::prims(a);
+  T d = prim_sdf(P, R.first, p);
+  if (R.op == kSmoothUnion) {
+    const T k = Tab<T>::k(R), ik = Tab<T>::inv_k(R);
+    for (int i = 1; i < R.count; ++i) {
+      const T b = prim_sdf(P, R.first + i, p);
+      const T h = tclamp(T(0.5) + T(0.5) * (b - d) * ik, T(0), T(1));
+      d = h * d + (T(1) - h) * b - k * h * (T(1) - h);
+    }
+  } else {
+    for (int i = 1; i < R.count; ++i) d = tmin(d, prim_sdf(P, R.first + i, p));
+  }
+  return d;
+}
+
+// SDF of the accelerated region through its uniform grid: min(margin, min
+// over the primitives listed in p's cell).  Equal to the region SDF where
+// that is below the margin, a lower bound elsewhere; outside the grid box
+// (which is the primitives' box grown by the margin) the distance to the
+// primitives' box is the lower bound.  Every index is checked.
+template <typename T>
+__device__ __forceinline__ T accel_sdf(JobRef a, V3<T> p) {
+  const SMCRT_K Accel& A = kptr(a.sc)->acc;
+  const V3<T> lo = Tab<T>::acc_lo(A), ic = Tab<T>::acc_inv(A);
+  const T cx = (p.x - lo.x) * ic.x, cy = (p.y - lo.y) * ic.y, cz = (p.z - lo.z) * ic.z;
+  const int dx = A.dims[0], dy = A.dims[1], dz = A.dims[2];
+  if (!(cx >= T(0) && cy >= T(0) && cz >= T(0) && cx < T(dx) && cy < T(dy) && cz < T(dz))) {
+    const V3<T> bl = Tab<T>::acc_blo(A), bh = Tab<T>::acc_bhi(A);
+    const V3<T> o = mk(tmax(tmax(bl.x - p.x, p.x - bh.x), T(0)), tmax(tmax(bl.y - p.y, p.y - bh.y), T(0)),
+                       tmax(tmax(bl.z - p.z, p.z - bh.z), T(0)));
+    return tsqrt(dot(o, o));
+  }
+  int ix = (int)cx, iy = (int)cy, iz = (int)cz;
+  ix = ix < dx ? ix : dx - 1;
+  iy = iy < dy ? iy : dy - 1;
+  iz = iz < dz ? iz : dz - 1;
+  const int c = ix + dx * (iy + dy * iz);
+  const SMCRT_K uint32_t* offs = kptr(a.acc_offsets);
+  const SMCRT_K uint32_t* ids = kptr(a.acc_ids);
+  const uint32_t b = offs[c];
+  uint64_t e = offs[c + 1];
+  e = e < A.capacity ? e : A.capacity;
+  const SMCRT_K Prim<T>* P = Tab<T>::prims(a);
+  const uint32_t lo_id = (uint32_t)A.first_prim, hi_id = (uint32_t)(A.first_prim + A.n_prims);
+  T d = Tab<T>::acc_margin(A);
+  for (uint64_t i = b; i < e; ++i) {
+    const uint32_t id = ids[i];
+    if (id >= lo_id && id < hi_id) d = tmin(d, prim_sdf(P, (int)id, p));
+  }
+  return d;
+}
+
+// SDF of region r (through the grid when r is the accelerated region)
+template <typename T>
+__device__ __forceinline__ T region_dist(JobRef a, int r, V3<T> p) {
+  if (r == a.acc_region) return accel_sdf<T>(a, p);
+  return region_sdf<T>(a, kptr(a.sc)->reg[r], p);
+}
+
+// owner of a point: the highest-index region with a negative SDF, else the
+// ambient slot n_regions
+template <typename T>
+__device__ __forceinline__ int region_of(JobRef a, V3<T> p) {
+  ScP sc = kptr(a.sc);
+  const int nr = sc->n_regions;
+  int owner = nr;
+  for (int r = nr - 1; r >= 0; --r) {
+    if (region_dist<T>(a, r, p) < T(0)) {
+      owner = r;
+      break;
+    }
+  }
+  return owner;
+}
+
+// signed distance of the simulation volume and, when outside, the face
+template <typename T>
+__device__ __forceinline__ T volume_sdf(ScP sc, V3<T> p, int* face) {
+  const V3<T> c = Tab<T>::bb_c(sc), h = Tab<T>::bb_h(sc);
+  const V3<T> q = p - c;
+  const T ex = tabs(q.x) - h.x, ey = tabs(q.y) - h.y, ez = tabs(q.z) - h.z;
+  int ax = 0;
+  T best = ex;
+  if (ey > best) { best = ey; ax = 1; }
+  if (ez > best) { best = ez; ax = 2; }
+  const T qa = ax == 0 ? q.x : (ax == 1 ? q.y : q.z);
+  *face = 2 * ax + (qa > T(0) ? 1 : 0);
+  const V3<T> o = mk(tmax(ex, T(0)), tmax(ey, T(0)), tmax(ez, T(0)));
+  return tsqrt(dot(o, o)) + tmin(best, T(0));
+}
+
+// unit outward normal of region R at p by central differences of step h
+__device__ __forceinline__ V3<double> region_normal(JobRef a, int r, V3<double> p, double h) {
+  V3<double> n;
+  n.x = region_dist<double>(a, r, mk(p.x + h, p.y, p.z)) - region_dist<double>(a, r, mk(p.x - h, p.y, p.z));
+  n.y = region_dist<double>(a, r, mk(p.x, p.y + h, p.z)) - region_dist<double>(a, r, mk(p.x, p.y - h, p.z));
+  n.z = region_dist<double>(a, r, mk(p.x, p.y, p.z + h)) - region_dist<double>(a, r, mk(p.x, p.y, p.z - h));
+  const double inv = 1.0 / __builtin_sqrt(dot(n, n));
+  return inv * n;
+}
+
+// ------------------------------------------------------------------ tallies
+
+struct LdsTallies {
+  double absorbed[kMaxRegions];
+  double escaped[6];
+  double gain, loss, stalled;
+  unsigned long long cnt[16];
+};
+enum CountSlot {
+  kCInterfaces = 0, kCReflections, kCRefractions, kCCrossings, kCAdvances, kCKills, kCStalls, kCEscapes,
+  kCLaunched, kCSteps, kCInteractions, kCPieces, kCAtomics
+};
+
+// per-lane run of equal voxels waiting to be added to the grid
+struct Run {
+  int v;
+  double sum;
+};
+
+__device__ __forceinline__ void grid_add(double* F, int v, double val) {
+  __builtin_amdgcn_global_atomic_fadd_f64((SMCRT_G double*)F + v, val);
+}
+
+__device__ __forceinline__ void run_add(double* F, Run& run, int v, double val, uint32_t& n_pieces,
+                                        uint32_t& n_atomics) {
+  ++n_pieces;
+  if (v == run.v) {
+    run.sum += val;
+  } else {
+    if (run.v >= 0) {
+      grid_add(F, run.v, run.sum);
+      ++n_atomics;
+    }
+    run.v = v;
+    run.sum = val;
+  }
+}
+
+// Path-length estimator (Sec. 3.1): weight * length of the straight move
+// p -> p + len*u credited to every voxel it crosses, by a 3-D DDA in voxel
+// units.  Voxel i spans [lo + i*D, lo + (i+1)*D); indices are clamped on
+// entry and the walk stops when it steps off the grid.
+template <typename T>
+__device__ __forceinline__ void tally_move(JobRef a, V3<T> p, V3<T> u, T len, double w, Run& run,
+                                           uint32_t& n_pieces, uint32_t& n_atomics) {
+  ScP sc = kptr(a.sc);
+  if (a.fluence == nullptr || !(len > T(0))) return;
+  const int nx = sc->g_dims[0], ny = sc->g_dims[1], nz = sc->g_dims[2];
+  const V3<T> inv = Tab<T>::g_inv(sc);
+  const V3<T> lo = Tab<T>::g_lo(sc);
+  const T g[3] = {(p.x - lo.x) * inv.x, (p.y - lo.y) * inv.y, (p.z - lo.z) * inv.z};
+  const T gu[3] = {u.x * inv.x, u.y * inv.y, u.z * inv.z};
+  const int dims[3] = {nx, ny, nz};
+  if (!__builtin_isfinite(g[0] + g[1] + g[2] + gu[0] + gu[1] + gu[2] + len)) return;
+  T t0 = T(0), t1 = len;
+#pragma unroll
+  for (int i = 0; i < 3; ++i) {
+    if (gu[i] == T(0)) {
+      if (g[i] < T(0) || g[i] > T(dims[i])) return;
+    } else {
+      const T ta = tdiv(-g[i], gu[i]), tb = tdiv(T(dims[i]) - g[i], gu[i]);
+      t0 = tmax(t0, tmin(ta, tb));
+      t1 = tmin(t1, tmax(ta, tb));
+    }
+  }
+  if (!(t1 > t0)) return;
+  int idx[3], stp[3];
+  T tnext[3], tdel[3];
+#pragma unroll
+  for (int i = 0; i < 3; ++i) {
+    const T x = g[i] + t0 * gu[i];
+    T fl = floor(x);
+    if (gu[i] < T(0) && x == fl) fl -= T(1);  // on a plane, moving down: the voxel below
+    fl = tclamp(fl, T(-1), T(dims[i]));
+    int k = (int)fl;
+    k = k < 0 ? 0 : (k >= dims[i] ? dims[i] - 1 : k);
+    idx[i] = k;
+    if (gu[i] > T(0)) {
+      stp[i] = 1;
+      tnext[i] = tdiv(T(k + 1) - g[i], gu[i]);
+      tdel[i] = tdiv(T(1), gu[i]);
+    } else if (gu[i] < T(0)) {
+      stp[i] = -1;
+      tnext[i] = tdiv(T(k) - g[i], gu[i]);
+      tdel[i] = -tdiv(T(1), gu[i]);
+    } else {
+      stp[i] = 0;
+      tnext[i] = tinf<T>();
+      tdel[i] = tinf<T>();
+    }
+  }
+  T t = t0;
+  const int cap = nx + ny + nz + 3;
+  for (int it = 0; it < cap; ++it) {
+    const T tn = tmin(tmin(tnext[0], tnext[1]), tmin(tnext[2], t1));
+    const T piece = tn - t;
+    if (piece > T(0)) run_add(a.fluence, run, idx[0] + nx * (idx[1] + ny * idx[2]), w * (double)piece, n_pieces, n_atomics);
+    if (tn >= t1) break;
+    int ax = (tnext[0] <= tnext[1] && tnext[0] <= tnext[2]) ? 0 : (tnext[1] <= tnext[2] ? 1 : 2);
+    idx[ax] += stp[ax];
+    if (idx[ax] < 0 || idx[ax] >= dims[ax]) break;
+    tnext[ax] += tdel[ax];
+    t = tn;
+  }
+}
+
+// Unpolarised Fresnel reflectance between indices n1 -> n2 at incidence
+// cosine ci (Sec. 1); *ct receives the transmitted cosine.  Total internal
+// reflection gives 1 (and *ct = 0).
+__device__ __forceinline__ double fresnel(double n1, double n2, double ci, double* ct) {
+  const double eta = n1 / n2;
+  const double s2t = eta * eta * (1.0 - ci * ci);
+  *ct = 0.0;
+  if (s2t >= 1.0) return 1.0;
+  const double c2 = __builtin_sqrt(1.0 - s2t);
+  const double rs = (n1 * ci - n2 * c2) / (n1 * ci + n2 * c2);
+  const double rp = (n1 * c2 - n2 * ci) / (n1 * c2 + n2 * ci);
+  *ct = c2;
+  return 0.5 * (rs * rs + rp * rp);
+}
+
+// ------------------------------------------------------------------ packet
+
+enum State : int { kTransport = 0, kSurface = 1, kInteract = 2 };
+
+template <typename T>
+struct Packet {
+  V3<T> p, u;
+  T tau;
+  T mut, inv_mut;   // of the current region (0 and 0 in ambient)
+  double w;
+  uint64_t pid;
+  uint32_t k;       // event index
+  int region;       // n_regions = ambient
+  int state;
+  int steps;        // sphere-tracing steps in the current event
+};
+
+struct Lane {
+  Run run;
+  double abs_sum;   // absorbed weight not yet added to the workgroup sums
+  int abs_region;
+  uint32_t n_steps, n_inter, n_pieces, n_atomics;
+  // trace
+  smcrt_event* rec;
+  int n_rec;
+};
+
+template <typename T>
+__device__ __forceinline__ void set_region(ScP sc, Packet<T>& pk, int r) {
+  pk.region = r;
+  pk.mut = Tab<T>::mut(sc->reg[r]);
+  pk.inv_mut = Tab<T>::inv_mut(sc->reg[r]);
+}
+
+template <typename T, bool TRACE>
+__device__ __forceinline__ void record(JobRef a, const Packet<T>& pk, Lane& ln, int type) {
+  if constexpr (TRACE) {
+    if (ln.n_rec < a.max_records) {
+      smcrt_event e;
+      e.event = pk.k;
+      e.type = (uint32_t)type;
+      e.region = pk.region == a.sc->n_regions ? -1 : pk.region;
+      e.pad = 0;
+      e.p[0] = pk.p.x; e.p[1] = pk.p.y; e.p[2] = pk.p.z;
+      e.u[0] = pk.u.x; e.u[1] = pk.u.y; e.u[2] = pk.u.z;
+      e.w = pk.w;
+      e.tau = (double)pk.tau;
+      ln.rec[ln.n_rec] = e;
+    }
+    ++ln.n_rec;
+  }
+}
+
+template <typename T>
+__device__ __forceinline__ void move(JobRef a, Packet<T>& pk, Lane& ln, T len) {
+  tally_move<T>(a, pk.p, pk.u, len, pk.w, ln.run, ln.n_pieces, ln.n_atomics);
+  pk.p = pk.p + len * pk.u;
+}
+
+__device__ __forceinline__ void add_absorbed(LdsTallies& L, Lane& ln, int r, double dA) {
+  if (r != ln.abs_region) {
+    if (ln.abs_region >= 0) atomicAdd(&L.absorbed[ln.abs_region], ln.abs_sum);
+    ln.abs_region = r;
+    ln.abs_sum = 0.0;
+  }
+  ln.abs_sum += dA;
+}
+
+// emission, event 0 (Sec. 3.1 sources; Eq. 1)
+template <typename T, bool TRACE>
+__device__ void emit(JobRef a, Packet<T>& pk, Lane& ln, LdsTallies& L) {
+  ScP sc = kptr(a.sc);
+  const U4 r = philox10(0u, (uint32_t)pk.pid, (uint32_t)(pk.pid >> 32), 0u, (uint32_t)a.seed, (uint32_t)(a.seed >> 32));
+  const T x0 = xi_of<T>(r.w0), x1 = xi_of<T>(r.w1), x3 = xi_of<T>(r.w3);
+  const SMCRT_K double* s = sc->src;
+  V3<T> p = mk((T)s[0], (T)s[1], (T)s[2]);
+  V3<T> u;
+  const int kind = sc->src_kind;
+  if (kind == kPoint) {
+    const T ct = T(2) * x0 - T(1);
+    const T st = T(2) * tsqrt(x0 * (T(1) - x0));  // sqrt(1 - ct^2) without cancellation
+    T sp, cp;
+    tsincos_2pi(x1, &sp, &cp);
+    u = mk(st * cp, st * sp, ct);
+  } else if (kind == kPencil) {
+    u = mk((T)s[3], (T)s[4], (T)s[5]);
+  } else if (kind == kDisc) {
+    const T rr = (T)s[3] * tsqrt(x0);
+    T sp, cp;
+    tsincos_2pi(x1, &sp, &cp);
+    p = mk(p.x + rr * cp, p.y + rr * sp, p.z);
+    u = mk((T)s[4], (T)s[5], (T)s[6]);
+  } else {
+    p = mk(p.x + (T)s[3] * (T(2) * x0 - T(1)), p.y + (T)s[4] * (T(2) * x1 - T(1)), p.z);
+    u = mk((T)s[5], (T)s[6], (T)s[7]);
+  }
+  const T il = T(1) / tsqrt(dot(u, u));
+  pk.p = p;
+  pk.u = il * u;
+  pk.w = 1.0;
+  pk.tau = -tlog(x3);
+  pk.k = 0;
+  pk.steps = 0;
+  pk.state = kTransport;
+  set_region(sc, pk, region_of<T>(a, p));
+  atomicAdd(&L.cnt[kCLaunched], 1ull);
+  record<T, TRACE>(a, pk, ln, SMCRT_EV_EMIT);
+}
+
+// absorption, Henyey-Greenstein scattering, roulette, next free path.
+// Returns false when the packet ends.
+template <typename T, bool TRACE>
+__device__ bool interact(JobRef a, Packet<T>& pk, Lane& ln, LdsTallies& L) {
+  ScP sc = kptr(a.sc);
+  RegRef R = sc->reg[pk.region];
+  pk.k += 1;
+  ++ln.n_inter;
+  const U4 r = philox10(pk.k, (uint32_t)pk.pid, (uint32_t)(pk.pid >> 32), 0u, (uint32_t)a.seed, (uint32_t)(a.seed >> 32));
+  // implicit capture: the fraction mu_a/mu_t of the weight stays here
+  const double dA = pk.w * R.mua / R.mut;
+  add_absorbed(L, ln, pk.region, dA);
+  pk.w -= dA;
+  if (pk.w == 0.0) {
+    record<T, TRACE>(a, pk, ln, SMCRT_EV_ABSORB);
+    return false;
+  }
+  // scattering angle from the HG inverse CDF; azimuth uniform.  The CDF is
+  // inverted for 1 - cos(theta) directly,
+  //   1 - cos = (1 - g)(1 - xi)(f + 1 - g) / D,  D = 1 - g + 2 g xi,
+  //   f = (1 - g^2) / D,
+  // which has no cancellation near forward scattering, so FP32 keeps
+  // sin(theta) = sqrt((1 - cos)(1 + cos)) to full relative precision.
+  const T x0 = xi_of<T>(r.w0), x1 = xi_of<T>(r.w1);
+  T omc;
+  if (R.iso) {
+    omc = T(2) * (T(1) - x0);
+  } else if constexpr (sizeof(T) == 4) {
+    const float D = R.hg_cf + R.hg_df * x0;
+    const float f = tdiv(R.hg_bf, D);
+    omc = tdiv(R.hg_cf * (1.0f - x0) * (f + R.hg_cf), D);
+  } else {
+    const double D = R.hg_c + R.hg_d * x0;
+    const double f = R.hg_b / D;
+    omc = R.hg_c * (1.0 - x0) * (f + R.hg_c) / D;
+  }
+  omc = tclamp(omc, T(0), T(2));
+  const T ct = T(1) - omc;
+  const T st = tsqrt(omc * (T(2) - omc));
+  T sp, cp;
+  tsincos_2pi(x1, &sp, &cp);
+  const V3<T> u = pk.u;
+  V3<T> v;
+  if (tabs(u.z) > T(1) - T(1e-5)) {
+    v = mk(st * cp, st * sp, (u.z >= T(0) ? ct : -ct));
+  } else {
+    // sqrt(1 - uz^2) from the other two components: no cancellation near the poles
+    const T tt = tsqrt(u.x * u.x + u.y * u.y);
+    const T itt = T(1) / tt;
+    v.x = st * (u.x * u.z * cp - u.y * sp) * itt + u.x * ct;
+    v.y = st * (u.y * u.z * cp + u.x * sp) * itt + u.y * ct;
+    v.z = -st * cp * tt + u.z * ct;
+  }
+  pk.u = (T(1) / tsqrt(dot(v, v))) * v;
+  // Russian roulette on the weight
+  if (pk.w < sc->w_threshold) {
+    const double x2 = xi_of<double>(r.w2);
+    if (x2 < sc->inv_m) {
+      atomicAdd(&L.gain, (sc->m_d - 1.0) * pk.w);
+      pk.w *= sc->m_d;
+    } else {
+      atomicAdd(&L.loss, pk.w);
+      atomicAdd(&L.cnt[kCKills], 1ull);
+      record<T, TRACE>(a, pk, ln, SMCRT_EV_KILL);
+      return false;
+    }
+  }
+  pk.tau = -tlog(xi_of<T>(r.w3));
+  pk.steps = 0;
+  record<T, TRACE>(a, pk, ln, SMCRT_EV_SCATTER);
+  return true;
+}
+
+__device__ __forceinline__ int lane_id() { return __lane_id(); }
+
+// First job of the launch's geometry, scanning from `start`, whose packet
+// counter has not reached its packet count; -1 when every such job is handed
+// out.  Wave uniform.
+__device__ __forceinline__ int pick_job(const SMCRT_K WalkArgs* jobs, const BatchArgs& B, int start) {
+  for (int i = 0; i < B.n_jobs; ++i) {
+    const int j = (start + i) % B.n_jobs;
+    JobRef J = jobs[j];
+    if (J.geometry != B.geometry) continue;
+    const unsigned long long c = __hip_atomic_load(J.counter, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    const uint64_t cu = ((uint64_t)__builtin_amdgcn_readfirstlane((unsigned)(c >> 32)) << 32) |
+                        (uint64_t)__builtin_amdgcn_readfirstlane((unsigned)c);
+    if (cu < J.n) return j;
+  }
+  return -1;
+}
+
+// Adds a wave's pending sums to job a's outputs and clears them.  Called with
+// every lane of the wave active.
+__device__ __forceinline__ void flush_wave(JobRef a, Lane& ln, LdsTallies& L, int lane) {
+  if (ln.run.v >= 0) {
+    grid_add(a.fluence, ln.run.v, ln.run.sum);
+    ++ln.n_atomics;
+  }
+  if (ln.abs_region >= 0) atomicAdd(&L.absorbed[ln.abs_region], ln.abs_sum);
+  atomicAdd(&L.cnt[kCSteps], (unsigned long long)ln.n_steps);
+  atomicAdd(&L.cnt[kCInteractions], (unsigned long long)ln.n_inter);
+  atomicAdd(&L.cnt[kCPieces], (unsigned long long)ln.n_pieces);
+  atomicAdd(&L.cnt[kCAtomics], (unsigned long long)ln.n_atomics);
+  ln.run.v = -1;
+  ln.run.sum = 0.0;
+  ln.abs_region = -1;
+  ln.abs_sum = 0.0;
+  ln.n_steps = ln.n_inter = ln.n_pieces = ln.n_atomics = 0;
+  __threadfence_block();
+  if (lane == 0) {
+    const int nr = a.sc->n_regions;
+    if (a.absorbed != nullptr)
+      for (int r = 0; r < nr; ++r) unsafeAtomicAdd(a.absorbed + r, L.absorbed[r]);
+    smcrt_tallies* G = reinterpret_cast<smcrt_tallies*>(a.tallies);
+    if (G != nullptr) {
+      for (int f = 0; f < 6; ++f) unsafeAtomicAdd(&G->escaped_face[f], L.escaped[f]);
+      unsafeAtomicAdd(&G->launched, (double)L.cnt[kCLaunched]);
+      unsafeAtomicAdd(&G->roulette_gain, L.gain);
+      unsafeAtomicAdd(&G->roulette_loss, L.loss);
+      unsafeAtomicAdd(&G->stalled, L.stalled);
+      atomicAdd((unsigned long long*)&G->events, L.cnt[kCInteractions] + L.cnt[kCInterfaces]);
+      atomicAdd((unsigned long long*)&G->steps, L.cnt[kCSteps]);
+      atomicAdd((unsigned long long*)&G->interactions, L.cnt[kCInteractions]);
+      atomicAdd((unsigned long long*)&G->interfaces, L.cnt[kCInterfaces]);
+      atomicAdd((unsigned long long*)&G->reflections, L.cnt[kCReflections]);
+      atomicAdd((unsigned long long*)&G->refractions, L.cnt[kCRefractions]);
+      atomicAdd((unsigned long long*)&G->crossings, L.cnt[kCCrossings]);
+      atomicAdd((unsigned long long*)&G->advances, L.cnt[kCAdvances]);
+      atomicAdd((unsigned long long*)&G->voxel_pieces, L.cnt[kCPieces]);
+      atomicAdd((unsigned long long*)&G->kills, L.cnt[kCKills]);
+      atomicAdd((unsigned long long*)&G->stalls, L.cnt[kCStalls]);
+      atomicAdd((unsigned long long*)&G->escapes, L.cnt[kCEscapes]);
+      atomicAdd((unsigned long long*)&G->grid_atomics, L.cnt[kCAtomics]);
+    }
+    for (int r = 0; r < kMaxRegions; ++r) L.absorbed[r] = 0.0;
+    for (int f = 0; f < 6; ++f) L.escaped[f] = 0.0;
+    for (int c = 0; c < 16; ++c) L.cnt[c] = 0ull;
+    L.gain = L.loss = L.stalled = 0.0;
+  }
+  __threadfence_block();
+}
+
+}  // namespace smcrt

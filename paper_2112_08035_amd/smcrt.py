@@ -78,6 +78,7 @@ _SIGS = {
     "smcrt_scene_set_roulette": ([_vp, C.c_double, C.c_int32], C.c_int),
     "smcrt_scene_set_limits": ([_vp, C.c_int32, C.c_int64], C.c_int),
     "smcrt_scene_set_accel": ([_vp, C.c_int32, C.POINTER(C.c_int32)], C.c_int),
+    "smcrt_scene_set_geometry": ([_vp, C.c_int], C.c_int),
     "smcrt_scene_info": ([_vp, C.POINTER(C.c_int32), C.POINTER(C.c_int32), _dp, _dp], C.c_int),
     "smcrt_engine_create": ([C.POINTER(_vp), C.c_int], C.c_int),
     "smcrt_engine_destroy": ([_vp], C.c_int),
@@ -89,6 +90,7 @@ _SIGS = {
                          C.POINTER(C.c_uint64), C.POINTER(_vp), C.POINTER(_vp), C.POINTER(_vp), _vp], C.c_int),
     "smcrt_normalize_fluence": ([_vp, _vp, C.c_double, _vp, _vp], C.c_int),
     "smcrt_trace": ([_vp, _vp, C.c_uint64, _vp, C.c_int, C.c_int, _vp, _vp, _vp], C.c_int),
+    "smcrt_voxelize": ([_vp, _vp, _vp, _vp], C.c_int),
     "smcrt_server_create": ([C.POINTER(_vp), C.c_int, C.c_uint64, C.c_uint64, C.POINTER(Opts)], C.c_int),
     "smcrt_server_destroy": ([_vp], C.c_int),
     "smcrt_submit": ([_vp, _vp, C.c_uint64, C.c_uint64, _vp, _vp, _vp, C.POINTER(C.c_uint64)], C.c_int),
@@ -177,6 +179,13 @@ def smcrt_scene_set_accel(scene, region, cells):
     _check(lib().smcrt_scene_set_accel(scene, region, (C.c_int32 * 3)(*[int(c) for c in cells]) if cells else None))
 
 
+GEOM = {"sdf": 0, "voxel": 1}
+
+
+def smcrt_scene_set_geometry(scene, mode):
+    _check(lib().smcrt_scene_set_geometry(scene, GEOM[mode] if isinstance(mode, str) else int(mode)))
+
+
 def smcrt_scene_info(scene):
     nr, npr = C.c_int32(), C.c_int32()
     lo, hi = (C.c_double * 3)(), (C.c_double * 3)()
@@ -230,6 +239,10 @@ def smcrt_normalize_fluence(scene, d_raw, launched, d_phi, stream):
 
 def smcrt_trace(engine, scene, seed, d_packet_ids, n_ids, max_events, d_out, d_count, stream):
     _check(lib().smcrt_trace(engine, scene, seed, d_packet_ids, n_ids, max_events, d_out, d_count, stream))
+
+
+def smcrt_voxelize(engine, scene, d_out, stream):
+    _check(lib().smcrt_voxelize(engine, scene, d_out, stream))
 
 
 def smcrt_server_create(device, hbm_budget_bytes, epoch_packets=0, opts=None):
@@ -315,6 +328,8 @@ class Scene:
             r = max(range(len(counts)), key=lambda i: counts[i])
             if counts[r] > 1:
                 smcrt_scene_set_accel(self.h, r, desc["accel_cells"])
+        if desc.get("geometry", "sdf") != "sdf":
+            smcrt_scene_set_geometry(self.h, desc["geometry"])
         self.n_regions = len(desc["regions"])
 
     @property
@@ -333,9 +348,18 @@ class Scene:
             pass
 
 
+def _torch_device_init():
+    """Device memory and streams of this binding come from torch: its HIP
+    context must exist before the library first touches the device, or
+    torch's own lazy initialisation fails afterwards."""
+    import torch
+    torch.cuda.init()
+
+
 class Engine:
     def __init__(self, device=0, **opts):
         self.device = device
+        _torch_device_init()
         self.h = smcrt_engine_create(device)
         if opts:
             self.set_opts(**opts)
@@ -485,6 +509,20 @@ def trace(desc, seed, pids, max_events=50, engine=None, precision="f32"):
     return res
 
 
+def voxelize(desc, engine=None):
+    """Region of every voxel centre of the scene's grid from the device
+    (-1 = ambient), shape (nz, ny, nx)."""
+    import torch
+    eng = engine if engine is not None else Engine(0)
+    sc = desc if isinstance(desc, Scene) else Scene(desc)
+    out = torch.empty(sc.n_voxels, dtype=torch.uint8, device=torch.device("cuda", eng.device))
+    smcrt_voxelize(eng.h, sc.h, C.c_void_p(out.data_ptr()), _stream_ptr(None))
+    torch.cuda.synchronize()
+    v = out.cpu().numpy().astype(np.int8)
+    v[v == sc.n_regions] = -1
+    return v.reshape(sc.dims[2], sc.dims[1], sc.dims[0])
+
+
 class Server:
     """Continuous-batching request server (smcrt_server_*).  device=-1 runs
     the scheduler alone (no device work)."""
@@ -497,6 +535,8 @@ class Server:
             for k, v in opts.items():
                 setattr(o, k, PREC[v] if k == "precision" and isinstance(v, str) else int(v))
         self.device = device
+        if device >= 0:
+            _torch_device_init()
         self.h = smcrt_server_create(device, hbm_budget_bytes, epoch_packets, o)
         self._keep = {}
 

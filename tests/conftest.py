@@ -24,3 +24,22 @@ def orc():
 def W():
     from paper_2112_08035_amd import workloads
     return workloads
+
+
+@pytest.fixture(scope="module")
+def S():
+    """The library binding on a GPU machine; GPU tests skip without a device.
+    (Host-side test modules define their own S that needs no device.)"""
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2112_08035_amd import smcrt
+    smcrt.lib()
+    return smcrt
+
+
+@pytest.fixture(scope="module")
+def eng(S):
+    e = S.Engine(0)
+    yield e
+    e.close()

@@ -2,6 +2,13 @@
 import numpy as np
 
 
+def extent_of(S, desc):
+    """Largest side of the simulation volume the library uses for a scene."""
+    sc = S.Scene(desc)
+    _, _, lo, hi = S.smcrt_scene_info(sc.h)
+    return float(np.max(hi - lo))
+
+
 def compare_traces(o_traces, g_traces, extent, tol, cap=50, mut=None):
     """Event-by-event comparison of oracle and GPU traces of the same
     packets.  A packet agrees when, for its first min(cap, length) records,
@@ -14,7 +21,11 @@ def compare_traces(o_traces, g_traces, extent, tol, cap=50, mut=None):
     oracle's exit ray.  The remaining optical depth is compared as the
     remaining path tau/mu_t relative to the extent (mut: attenuation per
     region index, -1 = ambient), because that is what fixes the next
-    interaction point; in ambient media it is compared relative, floor 1.
+    interaction point.  The attenuation is that of the medium the depth was
+    last consumed in: the larger of the record's region and the most recent
+    earlier record's non-ambient region (a packet in the ambient medium
+    carries the depth left over from the medium it left).  Where no medium
+    has attenuated it yet, it is compared relative, floor 1.
     Returns (agreeing fraction, worst errors, list of (packet, record) of
     first disagreements)."""
     agree = 0
@@ -23,6 +34,7 @@ def compare_traces(o_traces, g_traces, extent, tol, cap=50, mut=None):
     for pid, (o, g) in enumerate(zip(o_traces, g_traces)):
         o, g = o[:cap], g[:cap]
         ok = len(o) == len(g)
+        m_prev = 0.0  # attenuation of the last medium (not ambient) before record i
         for i in range(min(len(o), len(g))):
             a, b = o[i], g[i]
             if (a["type"], a["region"], a["event"]) != (b["type"], b["region"], b["event"]):
@@ -37,7 +49,10 @@ def compare_traces(o_traces, g_traces, extent, tol, cap=50, mut=None):
             errs = {"p": ep, "u": np.max(np.abs(a["u"] - b["u"])),
                     "w": abs(a["w"] - b["w"]) / max(abs(a["w"]), 1e-300),
                     "tau": abs(a["tau"] - b["tau"]) / max(1.0, abs(a["tau"]))}
-            m = mut[a["region"]] if (mut is not None and a["region"] >= 0) else 0.0
+            m = m_prev
+            if mut is not None and a["region"] >= 0:
+                m = max(m, mut[a["region"]])
+                m_prev = mut[a["region"]]
             if m > 0:
                 errs["tau"] = abs(a["tau"] - b["tau"]) / (m * extent)
             for k, v in errs.items():
@@ -60,3 +75,45 @@ def batch_se(batches):
 def identity_residual(r):
     return (r["absorbed"].sum() + r["escaped_face"].sum() + r["roulette_loss"] - r["roulette_gain"]
             + r["stalled"] - r["launched"])
+
+
+def oracle_batches(orc, desc, seed, n, n_batches, voxel=False):
+    """Oracle run of packets [0, n) in n_batches equal batches: summed
+    tallies and the per-voxel standard error of the fluence sum."""
+    step = n // n_batches
+    outs = [orc.run(desc, seed, step, first=b * step, voxel=voxel) for b in range(n_batches)]
+    tot = {k: sum(o[k] for o in outs) for k in ("absorbed", "escaped_face", "roulette_gain", "roulette_loss",
+                                                "stalled", "launched", "interactions", "interfaces")}
+    tot["fluence_raw"] = sum(o["fluence_raw"] for o in outs)
+    se = batch_se([o["fluence_raw"] for o in outs])
+    return tot, se
+
+
+def voxel_diagonal(desc):
+    g = desc["grid"]
+    d = (np.array(g["hi"]) - np.array(g["lo"])) / np.array(g["dims"])
+    return float(np.linalg.norm(d))
+
+
+def check_fluence(g, o, se, desc, prec, frac_needed=0.995):
+    """Per voxel within 3 Monte Carlo SE (estimated from oracle batches).
+    FP64: where no batch varies, the two must agree to rounding.  FP32: a
+    packet whose FP32 walk flips a discrete decision becomes another valid
+    walk; the voxels only it reaches have zero oracle variance, so the SE
+    is floored at one packet's largest possible deposit (weight <= 1 times
+    the voxel diagonal)."""
+    Fg, Fo = g["fluence_raw"], o["fluence_raw"]
+    if prec == "f64":
+        zero = se == 0
+        assert np.all(np.abs(Fg[zero] - Fo[zero]) <= 1e-9 * Fo.max())
+        sel = ~zero
+        se_eff = se[sel]
+    else:
+        sel = (se > 0) | (Fg != Fo)
+        se_eff = np.maximum(se[sel], voxel_diagonal(desc))
+    z = np.abs(Fg[sel] - Fo[sel]) / se_eff
+    within = np.mean(z <= 3.0)
+    l2 = np.linalg.norm(Fg - Fo) / np.linalg.norm(Fo)
+    print(f"voxels within 3 SE: {within:.5f}, max z {z.max():.3f}, relative L2 {l2:.3e}")
+    assert within >= frac_needed
+    return l2

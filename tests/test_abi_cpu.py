@@ -175,3 +175,35 @@ def test_server_cancel_queued_request(S, W):
             sv.poll(12345)
     finally:
         sv.close()
+
+
+# ---------------------------------------------------------- voxel model
+
+def test_geometry_mode_validation(S, W):
+    h = S.smcrt_scene_create(1.0, 1e-5, 1e-4)
+    try:
+        with pytest.raises(S.SmcrtError, match="unknown mode"):
+            S.smcrt_scene_set_geometry(h, 7)
+    finally:
+        S.smcrt_scene_destroy(h)
+    sv = S.Server(device=-1, hbm_budget_bytes=1 << 30, epoch_packets=100)
+    try:
+        # the voxel model needs a grid: rejected when the scene is packed
+        nogrid = S.Scene(dict(W.stack_scene([(0.1, 1.0, 1.5)]), geometry="voxel"))
+        with pytest.raises(S.SmcrtError, match="voxel geometry needs a fluence grid"):
+            sv.submit(nogrid, 1, 10)
+        # with a grid it is accepted, and its footprint counts the voxel bytes
+        sdf = S.Scene(W.sphere_scene(n_grid=64))
+        vox = S.Scene(dict(W.sphere_scene(n_grid=64), geometry="voxel"))
+        for sc in (sdf, vox):
+            rid = sv.submit(sc, 1, 100)[0]
+            sv.wait(rid, 10.0)
+    finally:
+        sv.close()
+    small = S.Server(device=-1, hbm_budget_bytes=64 ** 3 * 8 + 64 ** 3 // 2, epoch_packets=100)
+    try:
+        small.submit(S.Scene(W.sphere_scene(n_grid=64)), 1, 10)
+        with pytest.raises(S.SmcrtError, match="budget"):
+            small.submit(S.Scene(dict(W.sphere_scene(n_grid=64), geometry="voxel")), 1, 10)
+    finally:
+        small.close()

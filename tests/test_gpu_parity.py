@@ -20,32 +20,11 @@ import math
 import numpy as np
 import pytest
 
-from gpu_helpers import batch_se, compare_traces, identity_residual
+from gpu_helpers import batch_se, check_fluence, compare_traces, extent_of, identity_residual, oracle_batches
 
 pytestmark = pytest.mark.gpu
 
 
-@pytest.fixture(scope="module")
-def S():
-    import torch
-    if not torch.cuda.is_available():
-        pytest.skip("no GPU")
-    from paper_2112_08035_amd import smcrt
-    smcrt.lib()
-    return smcrt
-
-
-@pytest.fixture(scope="module")
-def eng(S):
-    e = S.Engine(0)
-    yield e
-    e.close()
-
-
-def extent_of(S, desc):
-    sc = S.Scene(desc)
-    _, _, lo, hi = S.smcrt_scene_info(sc.h)
-    return float(np.max(hi - lo))
 
 
 # ------------------------------------------------------------ traces -----
@@ -79,52 +58,12 @@ def test_event_traces_match_oracle(S, eng, orc, W, name, prec, need):
 
 # ------------------------------------------------------------ full runs --
 
-def _oracle_batches(orc, desc, seed, n, n_batches):
-    step = n // n_batches
-    outs = [orc.run(desc, seed, step, first=b * step) for b in range(n_batches)]
-    tot = {k: sum(o[k] for o in outs) for k in ("absorbed", "escaped_face", "roulette_gain", "roulette_loss",
-                                                "stalled", "launched", "interactions", "interfaces")}
-    tot["fluence_raw"] = sum(o["fluence_raw"] for o in outs)
-    se = batch_se([o["fluence_raw"] for o in outs])
-    return tot, se
-
-
-def _voxel_diagonal(desc):
-    g = desc["grid"]
-    d = (np.array(g["hi"]) - np.array(g["lo"])) / np.array(g["dims"])
-    return float(np.linalg.norm(d))
-
-
-def _check_fluence(g, o, se, desc, prec, frac_needed=0.995):
-    """Per voxel within 3 Monte Carlo SE (estimated from oracle batches).
-    FP64: where no batch varies, the two must agree to rounding.  FP32: a
-    packet whose FP32 walk flips a discrete decision becomes another valid
-    walk; the voxels only it reaches have zero oracle variance, so the SE
-    is floored at one packet's largest possible deposit (weight <= 1 times
-    the voxel diagonal)."""
-    Fg, Fo = g["fluence_raw"], o["fluence_raw"]
-    if prec == "f64":
-        zero = se == 0
-        assert np.all(np.abs(Fg[zero] - Fo[zero]) <= 1e-9 * Fo.max())
-        sel = ~zero
-        se_eff = se[sel]
-    else:
-        sel = (se > 0) | (Fg != Fo)
-        se_eff = np.maximum(se[sel], _voxel_diagonal(desc))
-    z = np.abs(Fg[sel] - Fo[sel]) / se_eff
-    within = np.mean(z <= 3.0)
-    l2 = np.linalg.norm(Fg - Fo) / np.linalg.norm(Fo)
-    print(f"voxels within 3 SE: {within:.5f}, max z {z.max():.3f}, relative L2 {l2:.3e}")
-    assert within >= frac_needed
-    return l2
-
-
 @pytest.mark.parametrize("prec,abs_tol", [("f64", 1e-9), ("f32", 1e-4)])
 def test_sphere_full_config_parity(S, eng, orc, W, prec, abs_tol):
     """Plain small case at its full size: 1e5 packets, 50^3 grid."""
     desc = W.sphere_scene()
     n, seed = 100000, 4242
-    o, se = _oracle_batches(orc, desc, seed, n, 10)
+    o, se = oracle_batches(orc, desc, seed, n, 10)
     g = S.run(desc, seed, n, engine=eng, precision=prec)
     assert g["launched"] == n
     assert abs(identity_residual(g)) <= 1e-9 * n
@@ -132,7 +71,7 @@ def test_sphere_full_config_parity(S, eng, orc, W, prec, abs_tol):
     print(f"{prec}: absorbed relative difference {rel:.3e}")
     assert rel <= abs_tol
     assert np.allclose(g["escaped_face"], o["escaped_face"], rtol=10 * abs_tol)
-    _check_fluence(g, o, se, desc, prec)
+    check_fluence(g, o, se, desc, prec)
 
 
 @pytest.mark.parametrize("prec,abs_tol", [("f64", 1e-9), ("f32", 1e-4)])
@@ -141,24 +80,24 @@ def test_workload_prefix_parity(S, eng, orc, W, name, n, prec, abs_tol):
     """Full-resolution grids, packet-id prefix the oracle finishes quickly."""
     desc = W.WORKLOADS[name]()
     seed = 777
-    o, se = _oracle_batches(orc, desc, seed, n, 10)
+    o, se = oracle_batches(orc, desc, seed, n, 10)
     g = S.run(desc, seed, n, engine=eng, precision=prec)
     assert g["launched"] == n
     assert abs(identity_residual(g)) <= 1e-9 * n
     rel = abs(g["absorbed"].sum() - o["absorbed"].sum()) / o["absorbed"].sum()
     print(f"{name} {prec}: absorbed relative difference {rel:.3e}")
     assert rel <= abs_tol
-    _check_fluence(g, o, se, desc, prec)
+    check_fluence(g, o, se, desc, prec)
 
 
 def test_vessel_scene_parity(S, eng, orc, W):
     desc = W.vessel_scene(5, 1.5, n_caps=200, n_grid=32)
     n, seed = 2000, 99
-    o, se = _oracle_batches(orc, desc, seed, n, 10)
+    o, se = oracle_batches(orc, desc, seed, n, 10)
     g = S.run(desc, seed, n, engine=eng, precision="f64")
     rel = abs(g["absorbed"].sum() - o["absorbed"].sum()) / o["absorbed"].sum()
     assert rel <= 1e-9
-    _check_fluence(g, o, se, desc, "f64")
+    check_fluence(g, o, se, desc, "f64")
 
 
 @pytest.mark.parametrize("prec", ["f64", "f32"])
