@@ -70,26 +70,29 @@ __device__ void surface(JobRef a, Packet<T>& pk, Lane& ln, LdsTallies& L) {
     // no change of medium ahead: advance 2*delta along the ray
     atomicAdd(&L.cnt[kCAdvances], 1ull);
     if (s_rem <= off) {
-      move<T>(a, pk, ln, (T)s_rem);
+      advance(pk, (T)s_rem);
       pk.tau = T(0);
       pk.state = kInteract;
       return;
     }
-    move<T>(a, pk, ln, (T)off);
+    advance(pk, (T)off);
     pk.tau = (T)(tau - R1.mut * off);
     pk.state = kTransport;
     return;
   }
   if (t_ray > 0.0) {
     if (s_rem <= t_ray) {
-      move<T>(a, pk, ln, (T)s_rem);
+      advance(pk, (T)s_rem);
       pk.tau = T(0);
       pk.state = kInteract;
       return;
     }
-    move<T>(a, pk, ln, (T)t_ray);
+    advance(pk, (T)t_ray);
     tau -= R1.mut * t_ray;
   }
+  // the position jumps or the direction changes below: credit the straight
+  // path up to the surface first
+  flush_tally<T>(a, pk, ln);
   pk.k += 1;
   pk.steps = 0;
   atomicAdd(&L.cnt[kCInterfaces], 1ull);
@@ -141,10 +144,12 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof
 walk_kernel(const WalkArgs* __restrict__ job_table, BatchArgs B) {
   const SMCRT_K WalkArgs* jobs = kptr(job_table);
   __shared__ LdsTallies Lw[4];
+  __shared__ WaveStage Sw[4];
   const int lane = lane_id();
   const int wib = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // wave index in the block (wave uniform)
   LdsTallies& L = Lw[wib];
   if (lane == 0) {
+    Sw[wib].n = 0;
     for (int r = 0; r < kMaxRegions; ++r) L.absorbed[r] = 0.0;
     for (int f = 0; f < 6; ++f) L.escaped[f] = 0.0;
     for (int c = 0; c < 16; ++c) L.cnt[c] = 0ull;
@@ -153,6 +158,7 @@ walk_kernel(const WalkArgs* __restrict__ job_table, BatchArgs B) {
   __threadfence_block();
 
   Lane ln;
+  ln.stage = &Sw[wib];
   ln.run.v = -1;
   ln.run.sum = 0.0;
   ln.abs_sum = 0.0;
@@ -170,6 +176,7 @@ walk_kernel(const WalkArgs* __restrict__ job_table, BatchArgs B) {
     if (cur < 0) return;
   }
   Packet<T> pk;
+  pk.pend = T(0);  // lanes that never get a packet have nothing to credit
   int vx[3] = {0, 0, 0};  // voxel model: the packet's voxel
   bool live = false;
 
@@ -252,13 +259,13 @@ walk_kernel(const WalkArgs* __restrict__ job_table, BatchArgs B) {
           } else {
             const T s = pk.mut > T(0) ? pk.tau * pk.inv_mut : tinf<T>();
             if (s <= dmin) {  // the optical depth runs out before any surface
-              move<T>(a, pk, ln, s);
+              advance(pk, s);
               pk.tau = T(0);
               pk.state = kInteract;
             } else if (dmin < delta) {
               pk.state = kSurface;
             } else {
-              move<T>(a, pk, ln, dmin);
+              advance(pk, dmin);
               pk.tau -= pk.mut * dmin;
             }
           }
@@ -273,6 +280,15 @@ walk_kernel(const WalkArgs* __restrict__ job_table, BatchArgs B) {
           if (live && pk.state == kSurface) surface<T, TRACE>(a, pk, ln, L);
         }
       }
+
+      // ---- tally: lanes whose packet ended or is about to scatter credit
+      // their straight path since the last event to the grid, together
+      if constexpr (GEOM == kGeomSdf) {
+        if (pk.pend > T(0) && (!live || pk.state == kInteract)) flush_tally<T>(a, pk, ln);
+      }
+
+      // ---- grid additions staged this iteration, as full-wave atomics
+      if (a.fluence != nullptr) stage_drain(a.fluence, *ln.stage, kDrain, lane);
 
       // ---- interactions
       if (live && pk.state == kInteract) {

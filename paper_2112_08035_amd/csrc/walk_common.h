@@ -300,89 +300,161 @@ struct Run {
   double sum;
 };
 
+// Grid additions of one wave staged in LDS.  Runs end in the middle of
+// divergent DDA loops, a few lanes at a time; staging them and draining the
+// stage with every lane active issues the FP64 atomics as full 64-lane
+// instructions, which keeps the memory-side atomic units fed steadily.
+constexpr int kStage = 256;  // entries per wave
+constexpr int kDrain = 64;   // entries that trigger a drain in the walk loop
+struct WaveStage {
+  double val[kStage];
+  int v[kStage];
+  int n;
+};
+
+struct Lane {
+  Run run;
+  WaveStage* stage; // this wave's staging area (LDS)
+  double abs_sum;   // absorbed weight not yet added to the workgroup sums
+  int abs_region;
+  uint32_t n_steps, n_inter, n_pieces, n_atomics;
+  // trace
+  smcrt_event* rec;
+  int n_rec;
+};
+
 __device__ __forceinline__ void grid_add(double* F, int v, double val) {
   __builtin_amdgcn_global_atomic_fadd_f64((SMCRT_G double*)F + v, val);
 }
 
-__device__ __forceinline__ void run_add(double* F, Run& run, int v, double val, uint32_t& n_pieces,
-                                        uint32_t& n_atomics) {
-  ++n_pieces;
-  if (v == run.v) {
-    run.sum += val;
+// Stages F[v] += val for the lanes active at the call (any subset of the
+// wave); when the stage is full it adds directly.
+__device__ __forceinline__ void stage_add(double* F, WaveStage& S, int v, double val) {
+  const uint64_t m = __ballot(1);
+  const int n = __popcll(m);
+  const int rank = __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+  const int base = __builtin_amdgcn_readfirstlane(S.n);
+  if (base + n <= kStage) {
+    S.v[base + rank] = v;
+    S.val[base + rank] = val;
+    if (rank == 0) S.n = base + n;
   } else {
-    if (run.v >= 0) {
-      grid_add(F, run.v, run.sum);
-      ++n_atomics;
-    }
-    run.v = v;
-    run.sum = val;
+    grid_add(F, v, val);
   }
+}
+
+// Adds the staged entries to F once at least min_count are waiting.  Called
+// with every lane of the wave active.
+__device__ __forceinline__ void stage_drain(double* F, WaveStage& S, int min_count, int lane) {
+  const int cnt = __builtin_amdgcn_readfirstlane(S.n);
+  if (cnt > 0 && cnt >= min_count) {
+    for (int i = lane; i < cnt; i += 64) grid_add(F, S.v[i], S.val[i]);
+    if (lane == 0) S.n = 0;
+  }
+}
+
+__device__ __forceinline__ void run_add(double* F, Lane& ln, int v, double val) {
+  ++ln.n_pieces;
+  if (v == ln.run.v) {
+    ln.run.sum += val;
+  } else {
+    if (ln.run.v >= 0) {
+      stage_add(F, *ln.stage, ln.run.v, ln.run.sum);
+      ++ln.n_atomics;
+    }
+    ln.run.v = v;
+    ln.run.sum = val;
+  }
+}
+
+template <typename T>
+__device__ __forceinline__ T trcp(T x);
+template <>
+__device__ __forceinline__ float trcp<float>(float x) { return __builtin_amdgcn_rcpf(x); }
+template <>
+__device__ __forceinline__ double trcp<double>(double x) { return 1.0 / x; }
+
+// One axis of the voxel walk: voxel index, step (+1, -1 or 0), ray
+// parameter of the next plane crossing, and the spacing of the crossings.
+template <typename T>
+struct DdaAxis {
+  int i, s;
+  T tn, dt;
+};
+
+// Narrows [t0, t1] to the part of the ray g + t*gu inside the slab [0, n]
+// of one axis (grid units; r = 1/gu); false when the ray misses the slab.
+template <typename T>
+__device__ __forceinline__ bool clip_axis(T g, T gu, T r, int n, T& t0, T& t1) {
+  if (gu == T(0)) return !(g < T(0) || g > T(n));
+  const T ta = -g * r, tb = (T(n) - g) * r;
+  t0 = tmax(t0, tmin(ta, tb));
+  t1 = tmin(t1, tmax(ta, tb));
+  return true;
+}
+
+// The voxel of one axis holding the ray at t0 (on a plane while moving down:
+// the voxel below), clamped into the grid, and its next crossing.
+template <typename T>
+__device__ __forceinline__ DdaAxis<T> start_axis(T g, T gu, T r, int n, T t0) {
+  DdaAxis<T> A;
+  const T x = g + t0 * gu;
+  T fl = floor(x);
+  if (gu < T(0) && x == fl) fl -= T(1);
+  fl = tclamp(fl, T(-1), T(n));
+  int k = (int)fl;
+  k = k < 0 ? 0 : (k >= n ? n - 1 : k);
+  A.i = k;
+  A.s = gu > T(0) ? 1 : (gu < T(0) ? -1 : 0);
+  A.tn = gu > T(0) ? (T(k + 1) - g) * r : (gu < T(0) ? (T(k) - g) * r : tinf<T>());
+  A.dt = gu != T(0) ? tabs(r) : tinf<T>();
+  return A;
 }
 
 // Path-length estimator (Sec. 3.1): weight * length of the straight move
 // p -> p + len*u credited to every voxel it crosses, by a 3-D DDA in voxel
 // units.  Voxel i spans [lo + i*D, lo + (i+1)*D); indices are clamped on
-// entry and the walk stops when it steps off the grid.
+// entry and the walk stops when it steps off the grid.  The axes are kept
+// in named registers and the linear voxel index is stepped by the axis
+// stride, so a crossing costs a few compares and selects.
 template <typename T>
-__device__ __forceinline__ void tally_move(JobRef a, V3<T> p, V3<T> u, T len, double w, Run& run,
-                                           uint32_t& n_pieces, uint32_t& n_atomics) {
+__device__ __forceinline__ void tally_move(JobRef a, V3<T> p, V3<T> u, T len, double w, Lane& ln) {
   ScP sc = kptr(a.sc);
   if (a.fluence == nullptr || !(len > T(0))) return;
   const int nx = sc->g_dims[0], ny = sc->g_dims[1], nz = sc->g_dims[2];
   const V3<T> inv = Tab<T>::g_inv(sc);
   const V3<T> lo = Tab<T>::g_lo(sc);
-  const T g[3] = {(p.x - lo.x) * inv.x, (p.y - lo.y) * inv.y, (p.z - lo.z) * inv.z};
-  const T gu[3] = {u.x * inv.x, u.y * inv.y, u.z * inv.z};
-  const int dims[3] = {nx, ny, nz};
-  if (!__builtin_isfinite(g[0] + g[1] + g[2] + gu[0] + gu[1] + gu[2] + len)) return;
+  const T gx = (p.x - lo.x) * inv.x, gy = (p.y - lo.y) * inv.y, gz = (p.z - lo.z) * inv.z;
+  const T ux = u.x * inv.x, uy = u.y * inv.y, uz = u.z * inv.z;
+  if (!__builtin_isfinite(gx + gy + gz + ux + uy + uz + len)) return;
+  const T rx = trcp(ux), ry = trcp(uy), rz = trcp(uz);
   T t0 = T(0), t1 = len;
-#pragma unroll
-  for (int i = 0; i < 3; ++i) {
-    if (gu[i] == T(0)) {
-      if (g[i] < T(0) || g[i] > T(dims[i])) return;
-    } else {
-      const T ta = tdiv(-g[i], gu[i]), tb = tdiv(T(dims[i]) - g[i], gu[i]);
-      t0 = tmax(t0, tmin(ta, tb));
-      t1 = tmin(t1, tmax(ta, tb));
-    }
-  }
+  if (!clip_axis(gx, ux, rx, nx, t0, t1) || !clip_axis(gy, uy, ry, ny, t0, t1) || !clip_axis(gz, uz, rz, nz, t0, t1))
+    return;
   if (!(t1 > t0)) return;
-  int idx[3], stp[3];
-  T tnext[3], tdel[3];
-#pragma unroll
-  for (int i = 0; i < 3; ++i) {
-    const T x = g[i] + t0 * gu[i];
-    T fl = floor(x);
-    if (gu[i] < T(0) && x == fl) fl -= T(1);  // on a plane, moving down: the voxel below
-    fl = tclamp(fl, T(-1), T(dims[i]));
-    int k = (int)fl;
-    k = k < 0 ? 0 : (k >= dims[i] ? dims[i] - 1 : k);
-    idx[i] = k;
-    if (gu[i] > T(0)) {
-      stp[i] = 1;
-      tnext[i] = tdiv(T(k + 1) - g[i], gu[i]);
-      tdel[i] = tdiv(T(1), gu[i]);
-    } else if (gu[i] < T(0)) {
-      stp[i] = -1;
-      tnext[i] = tdiv(T(k) - g[i], gu[i]);
-      tdel[i] = -tdiv(T(1), gu[i]);
-    } else {
-      stp[i] = 0;
-      tnext[i] = tinf<T>();
-      tdel[i] = tinf<T>();
-    }
-  }
+  DdaAxis<T> X = start_axis(gx, ux, rx, nx, t0), Y = start_axis(gy, uy, ry, ny, t0),
+             Z = start_axis(gz, uz, rz, nz, t0);
+  int lin = X.i + nx * (Y.i + ny * Z.i);
+  const int sy = Y.s * nx, sz = Z.s * (nx * ny);
   T t = t0;
   const int cap = nx + ny + nz + 3;
   for (int it = 0; it < cap; ++it) {
-    const T tn = tmin(tmin(tnext[0], tnext[1]), tmin(tnext[2], t1));
+    const T tn = tmin(tmin(X.tn, Y.tn), tmin(Z.tn, t1));
     const T piece = tn - t;
-    if (piece > T(0)) run_add(a.fluence, run, idx[0] + nx * (idx[1] + ny * idx[2]), w * (double)piece, n_pieces, n_atomics);
+    if (piece > T(0)) run_add(a.fluence, ln, lin, w * (double)piece);
     if (tn >= t1) break;
-    int ax = (tnext[0] <= tnext[1] && tnext[0] <= tnext[2]) ? 0 : (tnext[1] <= tnext[2] ? 1 : 2);
-    idx[ax] += stp[ax];
-    if (idx[ax] < 0 || idx[ax] >= dims[ax]) break;
-    tnext[ax] += tdel[ax];
+    // cross the nearest plane (ties: x before y before z)
+    const bool bx = X.tn <= Y.tn && X.tn <= Z.tn;
+    const bool by = !bx && Y.tn <= Z.tn;
+    const bool bz = !bx && !by;
+    X.i += bx ? X.s : 0;
+    Y.i += by ? Y.s : 0;
+    Z.i += bz ? Z.s : 0;
+    X.tn = bx ? X.tn + X.dt : X.tn;
+    Y.tn = by ? Y.tn + Y.dt : Y.tn;
+    Z.tn = bz ? Z.tn + Z.dt : Z.tn;
+    lin += bx ? X.s : (by ? sy : sz);
+    if ((unsigned)X.i >= (unsigned)nx || (unsigned)Y.i >= (unsigned)ny || (unsigned)Z.i >= (unsigned)nz) break;
     t = tn;
   }
 }
@@ -417,16 +489,7 @@ struct Packet {
   int region;       // n_regions = ambient
   int state;
   int steps;        // sphere-tracing steps in the current event
-};
-
-struct Lane {
-  Run run;
-  double abs_sum;   // absorbed weight not yet added to the workgroup sums
-  int abs_region;
-  uint32_t n_steps, n_inter, n_pieces, n_atomics;
-  // trace
-  smcrt_event* rec;
-  int n_rec;
+  T pend;           // straight path along u since the last tally, ending at p
 };
 
 template <typename T>
@@ -455,10 +518,23 @@ __device__ __forceinline__ void record(JobRef a, const Packet<T>& pk, Lane& ln, 
   }
 }
 
+// Moves the packet len along u.  The tally is deferred: the straight path
+// since the last change of direction collects in pend and is credited to
+// the grid in one pass by flush_tally, which runs before the direction
+// changes or the position jumps (interactions, interface events) and when
+// the packet ends.  Collinear sphere-tracing steps thus share one DDA, and
+// the lanes of a wave run it together.
 template <typename T>
-__device__ __forceinline__ void move(JobRef a, Packet<T>& pk, Lane& ln, T len) {
-  tally_move<T>(a, pk.p, pk.u, len, pk.w, ln.run, ln.n_pieces, ln.n_atomics);
+__device__ __forceinline__ void advance(Packet<T>& pk, T len) {
   pk.p = pk.p + len * pk.u;
+  pk.pend += len;
+}
+
+template <typename T>
+__device__ __forceinline__ void flush_tally(JobRef a, Packet<T>& pk, Lane& ln) {
+  if (pk.pend > T(0))
+    tally_move<T>(a, pk.p - pk.pend * pk.u, pk.u, pk.pend, pk.w, ln);
+  pk.pend = T(0);
 }
 
 __device__ __forceinline__ void add_absorbed(LdsTallies& L, Lane& ln, int r, double dA) {
@@ -505,6 +581,7 @@ __device__ void emit(JobRef a, Packet<T>& pk, Lane& ln, LdsTallies& L) {
   pk.tau = -tlog(x3);
   pk.k = 0;
   pk.steps = 0;
+  pk.pend = T(0);
   pk.state = kTransport;
   set_region(sc, pk, region_of<T>(a, p));
   atomicAdd(&L.cnt[kCLaunched], 1ull);
@@ -605,6 +682,7 @@ __device__ __forceinline__ int pick_job(const SMCRT_K WalkArgs* jobs, const Batc
 // Adds a wave's pending sums to job a's outputs and clears them.  Called with
 // every lane of the wave active.
 __device__ __forceinline__ void flush_wave(JobRef a, Lane& ln, LdsTallies& L, int lane) {
+  if (a.fluence != nullptr) stage_drain(a.fluence, *ln.stage, 1, lane);
   if (ln.run.v >= 0) {
     grid_add(a.fluence, ln.run.v, ln.run.sum);
     ++ln.n_atomics;

@@ -100,6 +100,23 @@ def test_vessel_scene_parity(S, eng, orc, W):
     check_fluence(g, o, se, desc, "f64")
 
 
+@pytest.mark.parametrize("prec,abs_tol", [("f64", 1e-9), ("f32", 1e-4)])
+def test_long_straight_paths(S, eng, orc, W, prec, abs_tol):
+    """Non-scattering sphere on a fine grid: every packet is one straight
+    path across 50-100 voxels, so each flush of a wave stages thousands of
+    grid additions (well past the per-wave stage) and most go straight to
+    the grid."""
+    desc = W.absorbing_sphere(mua=1.0, n_grid=96)
+    n, seed = 6000, 1234
+    o, se = oracle_batches(orc, desc, seed, n, 6)
+    g = S.run(desc, seed, n, engine=eng, precision=prec)
+    assert g["launched"] == n
+    assert g["voxel_pieces"] > 40 * n
+    rel = abs(g["absorbed"].sum() - o["absorbed"].sum()) / o["absorbed"].sum()
+    assert rel <= abs_tol
+    check_fluence(g, o, se, desc, prec)
+
+
 @pytest.mark.parametrize("prec", ["f64", "f32"])
 def test_uniform_grid_matches_brute_force(S, eng, W, prec):
     """The device-built grid changes how far a step may go, never a
