@@ -77,6 +77,18 @@ def measured_traffic():
 SERVE_GRIDS = (32, 64, 128)
 
 
+def atomic_ceiling():
+    """FP64 global atomic adds per second measured on the device by
+    paper_2112_08035_amd/atomic_ceiling (committed summary), or None."""
+    path = os.path.join(ROOT, "profiles", "fp64_atomic_ceiling.md")
+    if not os.path.exists(path):
+        return None
+    for line in open(path):
+        if line.startswith("atomics_per_s:"):
+            return float(line.split(":", 1)[1])
+    return None
+
+
 def serving_capacity(smcrt, workloads, max_packets, precision, seed, n_requests=48):
     """Closed-loop capacity of the server on the request mix: a calibration
     stream (its own seed) submitted all at once; packets per second from
@@ -239,7 +251,7 @@ def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
-    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--precision", default="f32", choices=["f32", "f64"])
     ap.add_argument("--packets", type=float, default=1e7)
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="target length of the oracle sample")
@@ -295,6 +307,7 @@ def main():
                                       "voxel_pieces", "grid_atomics")}
     lane_ops = slab_lane_ops(per, len(desc["prims"]))
     achieved = lane_ops / (launch_ms * 1e-3)
+    ceiling = atomic_ceiling()
     identity = (h["absorbed"].sum() + h["escaped_face"].sum() + h["roulette_loss"] - h["roulette_gain"]
                 + h["stalled"] - h["launched"])
 
@@ -331,6 +344,8 @@ def main():
             "kernel_ms": launch_ms,
             "lane_ops_per_launch": lane_ops,
             "grid_atomics_per_s": per["grid_atomics"] / (launch_ms * 1e-3),
+            "atomic_ceiling_per_s": ceiling,
+            "atomic_frac": (per["grid_atomics"] / (launch_ms * 1e-3) / ceiling) if ceiling else None,
         },
     }
 

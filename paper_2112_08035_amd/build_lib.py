@@ -18,6 +18,23 @@ FLAGS = [
 ]
 
 
+PROBE_SRC = os.path.join(CSRC, "atomic_ceiling.hip")
+PROBE = os.path.join(HERE, "atomic_ceiling")
+
+
+def build_probe(verbose=False):
+    """The FP64 atomic-throughput microbenchmark (a measurement tool, not
+    part of the library)."""
+    cmd = ["hipcc", "--offload-arch=gfx950", "-O3", "-std=c++17",
+           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops", "-o", PROBE, PROBE_SRC]
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    res = subprocess.run(cmd, capture_output=True, text=True)
+    if res.returncode != 0:
+        raise RuntimeError("hipcc failed:\n" + res.stdout + res.stderr)
+    return PROBE
+
+
 def build(verbose=False, extra=()):
     cmd = ["hipcc", *FLAGS, *extra, "-o", LIB + ".tmp", *SOURCES]
     if verbose:
@@ -42,3 +59,4 @@ def is_stale():
 
 if __name__ == "__main__":
     print(build(verbose=True, extra=sys.argv[1:]))
+    print(build_probe(verbose=True))
