@@ -226,6 +226,56 @@ def comparator(smcrt, workloads, precision, n=10_000_000, seed=3):
     return res
 
 
+def paper_speed_tests(smcrt, workloads, precision):
+    """The paper's speed experiments (Sec. 3.2) on this GPU, both geometry
+    models, whole runs timed (tables, voxelisation, walk):
+    - tally-free speed test: isotropic scattering sphere (r = 0.5 cm, source
+      at the centre) at radial optical depths 0.1, 1, 10, 100; 1e7 photons;
+      no fluence tally (the voxel model walks a 200^3 grid);
+    - Table 2, Jacques slab: the 420 nm medium of Table 1 (mu_a 1.8, mu_s'
+      82 /cm, g 0.9, n 1.38) as a 2 x 2 x 4 cm slab under uniform normal
+      illumination of its top face, 200 x 200 x 400 grid, 1e7 photons;
+    - Table 2, isotropic sphere: tau = 100 with a 200^3 grid, 1e6 photons.
+    The paper's CPU timings (Table 2) are returned beside them as context."""
+    import torch
+    gold = json.load(open(os.path.join(ROOT, "tests", "golden", "paper_values.json")))["table2_timings_cpu"]
+
+    def timed(desc, n, geometry, tally, seed=1):
+        eng = smcrt.Engine(0, precision=precision)
+        sc = smcrt.Scene(dict(desc, geometry=geometry))
+        smcrt.launch(eng, sc, seed + 1000, min(n, 200_000), outputs=smcrt.Outputs(sc, tally=tally))  # warm-up
+        out = smcrt.Outputs(sc, tally=tally)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        smcrt.launch(eng, sc, seed, n, outputs=out)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t
+        h = out.host()
+        eng.close()
+        return dt, h["interactions"] / n
+
+    sweep = []
+    for tau in (0.1, 1.0, 10.0, 100.0):
+        desc = workloads.with_grid(workloads.scattering_sphere(tau), [200] * 3, lo=[-0.5] * 3, hi=[0.5] * 3)
+        ts, ns = timed(desc, 10_000_000, "sdf", False)
+        tv, nv = timed(desc, 10_000_000, "voxel", False)
+        sweep.append({"tau": tau, "sdf_s": ts, "voxel_s": tv, "sdf_over_voxel_speed": tv / ts,
+                      "mean_scatterings": ns, "eq4": tau * tau / 2 + tau})
+    slab = workloads.semi_infinite_slab(1.8, 82.0, half_xy=1.0, nz=400)
+    slab = workloads.with_grid(slab, [200, 200, 400], lo=[-1.0, -1.0, -4.0], hi=[1.0, 1.0, 0.0])
+    slab["source"] = {"kind": "rect", "c": [0.0, 0.0, 0.5 * slab["pad"]], "half": [1.0, 1.0], "u": [0.0, 0.0, -1.0]}
+    sphere = workloads.with_grid(workloads.scattering_sphere(100.0), [200] * 3, lo=[-0.5] * 3, hi=[0.5] * 3)
+    table2 = {}
+    for name, desc, n in (("jacques_slab", slab, 10_000_000), ("isotropic_sphere", sphere, 1_000_000)):
+        ts, _ = timed(desc, n, "sdf", True)
+        tv, _ = timed(desc, n, "voxel", True)
+        g = gold[name]
+        table2[name] = {"photons": n, "grid": g["grid"], "sdf_s": ts, "voxel_s": tv, "sdf_over_voxel_speed": tv / ts,
+                        "paper_cpu_sdf_s": g["smcrt_s"], "paper_cpu_voxel_s": g["voxel_s"],
+                        "paper_sdf_over_voxel_speed": g["voxel_s"] / g["smcrt_s"]}
+    return {"tally_free_sphere": sweep, "table2": table2}
+
+
 def copy_calibration(smcrt, desc, steps):
     import torch
     sc = smcrt.Scene(desc)
@@ -256,7 +306,8 @@ def main():
     ap.add_argument("--packets", type=float, default=1e7)
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="target length of the oracle sample")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle, comparator and serving legs (profiling runs)")
-    ap.add_argument("--no-comparator", action="store_true", help="skip the voxel-vs-SDF geometry comparison")
+    ap.add_argument("--no-comparator", action="store_true",
+                    help="skip the voxel-vs-SDF geometry comparison and the paper's speed experiments")
     ap.add_argument("--serve-requests", type=int, default=200, help="requests in the serving leg (0 = skip)")
     ap.add_argument("--serve-rate", type=float, default=0.0,
                     help="Poisson arrival rate of the serving leg (1/s); 0 = 70%% of the measured capacity")
@@ -384,6 +435,7 @@ def main():
         }
     if not args.no_cpu and not args.no_comparator:
         result["voxel_comparator"] = comparator(smcrt, workloads, args.precision)
+        result["paper_speed_tests"] = paper_speed_tests(smcrt, workloads, args.precision)
     if args.serve_requests > 0 and not args.no_cpu:
         result["serving"] = serving(smcrt, workloads, args.serve_requests, args.serve_rate,
                                     args.serve_max_packets, args.precision)

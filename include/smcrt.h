@@ -211,7 +211,9 @@ typedef struct {
  * random stream seed (Philox4x32-10 keyed by seed, counter by packet id and
  * event index, so results do not depend on the launch shape).
  *   d_fluence_raw: device, nx*ny*nz doubles, += sum of weight * path length
- *                  per voxel (cm); may be NULL when the grid is disabled.
+ *                  per voxel (cm).  NULL runs without the fluence tally (the
+ *                  scalar tallies only; a voxel-geometry scene still walks
+ *                  its grid): the tally-free regime of Sec. 3's speed test.
  *   d_absorbed:    device, n_regions doubles, += absorbed weight per region.
  *   d_tallies:     device, one smcrt_tallies, += scalar tallies.
  * Asynchronous on hip_stream. */

@@ -645,7 +645,6 @@ static smcrt_status launch_jobs(smcrt_engine* e, const std::vector<JobSpec>& job
     smcrt_status r = pack(jobs[j].s);
     if (r != SMCRT_OK) return r;
     const SceneHeader* h = reinterpret_cast<const SceneHeader*>(jobs[j].s->blob.data());
-    if (h->has_grid && !jobs[j].fluence && !tr && !vox_out) return fail(SMCRT_E_INVALID, "job %zu: the scene has a grid but its fluence buffer is NULL", j);
     int k = -1;
     for (size_t u = 0; u < uniq.size(); ++u)
       if (uniq[u] == jobs[j].s) k = (int)u;
@@ -1204,7 +1203,7 @@ extern "C" smcrt_status smcrt_submit(smcrt_server* sv, const smcrt_scene* scene,
     smcrt_status st = pack(s);
     if (st != SMCRT_OK) return st;
     const SceneHeader* h = reinterpret_cast<const SceneHeader*>(s->blob.data());
-    if (sv->engine && (!d_absorbed || !d_tallies || (h->has_grid && !d_fluence_raw)))
+    if (sv->engine && (!d_absorbed || !d_tallies))
       return fail(SMCRT_E_INVALID, "submit: output buffers missing");
     fp = request_footprint(s);
     if (fp > sv->budget)

@@ -408,10 +408,11 @@ def _stream_ptr(stream):
 class Outputs:
     """Device outputs of a run (caller-owned, zeroed, accumulated into)."""
 
-    def __init__(self, scene, device=0):
+    def __init__(self, scene, device=0, tally=True):
         import torch
         dev = torch.device("cuda", device)
-        self.fluence = torch.zeros(max(scene.n_voxels, 1), dtype=torch.float64, device=dev)
+        self.tally = bool(tally) and scene.n_voxels > 0
+        self.fluence = torch.zeros(scene.n_voxels if self.tally else 1, dtype=torch.float64, device=dev)
         self.absorbed = torch.zeros(scene.n_regions, dtype=torch.float64, device=dev)
         self.tallies = torch.zeros(C.sizeof(Tallies), dtype=torch.uint8, device=dev)
         self.dims = scene.dims
@@ -423,7 +424,7 @@ class Outputs:
         return self
 
     def ptrs(self):
-        f = C.c_void_p(self.fluence.data_ptr()) if self.dims[0] * self.dims[1] * self.dims[2] else None
+        f = C.c_void_p(self.fluence.data_ptr()) if self.tally else None
         return f, C.c_void_p(self.absorbed.data_ptr()), C.c_void_p(self.tallies.data_ptr())
 
     def host(self):
@@ -435,7 +436,7 @@ class Outputs:
             out[name] = int(getattr(t, name))
         out["absorbed"] = self.absorbed.cpu().numpy()
         nx, ny, nz = self.dims
-        out["fluence_raw"] = self.fluence.cpu().numpy().reshape(nz, ny, nx) if nx * ny * nz else None
+        out["fluence_raw"] = self.fluence.cpu().numpy().reshape(nz, ny, nx) if self.tally else None
         return out
 
 
@@ -469,14 +470,15 @@ def run_batch(descs, seeds, n_packets, engine=None, precision="f32", firsts=None
     return [o.host() for o in outs]
 
 
-def run(desc, seed, n, first=0, engine=None, precision="f32", **opts):
+def run(desc, seed, n, first=0, engine=None, precision="f32", tally=True, **opts):
     """Runs packets [first, first + n) of a scene dictionary on the GPU and
-    returns host copies of the tallies."""
+    returns host copies of the tallies; tally=False runs without the
+    fluence tally (fluence_raw is None)."""
     import torch
     eng = engine if engine is not None else Engine(0)
     eng.set_opts(precision=precision, **opts)
     sc = desc if isinstance(desc, Scene) else Scene(desc)
-    out = launch(eng, sc, seed, n, first)
+    out = launch(eng, sc, seed, n, first, outputs=Outputs(sc, eng.device, tally=tally))
     torch.cuda.synchronize()
     return out.host()
 
