@@ -276,6 +276,30 @@ def paper_speed_tests(smcrt, workloads, precision):
     return {"tally_free_sphere": sweep, "table2": table2}
 
 
+def csg_scenes(smcrt, workloads, precision, n=10_000_000):
+    """Packets/s of the SDF walk on the two CSG scenes: the
+    glass sphere under a beam in a scattering medium and the partly filled
+    glass bottle (intersection and difference regions), 64^3 grids."""
+    import torch
+    res = {}
+    for name in ("glass_sphere", "bottle"):
+        desc = workloads.WORKLOADS[name](n_grid=64)
+        eng = smcrt.Engine(0, precision=precision)
+        sc = smcrt.Scene(desc)
+        smcrt.launch(eng, sc, 77, 500_000, outputs=smcrt.Outputs(sc))  # warm-up
+        out = smcrt.Outputs(sc)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        smcrt.launch(eng, sc, 1, n, outputs=out)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t
+        h = out.host()
+        res[name] = {"packets": n, "packets_per_s": n / dt, "steps_per_packet": h["steps"] / n,
+                     "interfaces_per_packet": h["interfaces"] / n, "interactions_per_packet": h["interactions"] / n}
+        eng.close()
+    return res
+
+
 def copy_calibration(smcrt, desc, steps):
     import torch
     sc = smcrt.Scene(desc)
@@ -436,6 +460,7 @@ def main():
     if not args.no_cpu and not args.no_comparator:
         result["voxel_comparator"] = comparator(smcrt, workloads, args.precision)
         result["paper_speed_tests"] = paper_speed_tests(smcrt, workloads, args.precision)
+        result["csg_scenes"] = csg_scenes(smcrt, workloads, args.precision)
     if args.serve_requests > 0 and not args.no_cpu:
         result["serving"] = serving(smcrt, workloads, args.serve_requests, args.serve_rate,
                                     args.serve_max_packets, args.precision)

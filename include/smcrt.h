@@ -57,9 +57,18 @@ enum {
   SMCRT_PRIM_SPHERE = 0,   /* params: cx cy cz r           (Eq. 3)              */
   SMCRT_PRIM_BOX = 1,      /* params: cx cy cz hx hy hz    (axis aligned, half extents) */
   SMCRT_PRIM_CAPSULE = 2,  /* params: ax ay az bx by bz r  (segment a-b swept by r) */
-  SMCRT_PRIM_CYLINDER = 3  /* params: ax ay az bx by bz r  (axis a-b, flat caps) */
+  SMCRT_PRIM_CYLINDER = 3, /* params: ax ay az bx by bz r  (axis a-b, flat caps) */
+  SMCRT_PRIM_TORUS = 4     /* params: cx cy cz ex ey ez R r (centre, axis of any length,
+                                      ring radius R >= 0, tube radius r > 0) */
 };
-enum { SMCRT_OP_UNION = 0, SMCRT_OP_SMOOTH_UNION = 1 };
+/* region operators over the region's primitives, in the order given
+ * (Sec. 2.2: union, intersection and difference):
+ *   UNION min; SMOOTH_UNION polynomial smooth minimum of radius k;
+ *   INTERSECT max; SUBTRACT the first primitive minus all the others,
+ *   max(d_first, -d_i).  INTERSECT and SUBTRACT give lower bounds of the
+ *   distance with Lipschitz constant 1 and the exact sign, which keeps
+ *   sphere tracing conservative. */
+enum { SMCRT_OP_UNION = 0, SMCRT_OP_SMOOTH_UNION = 1, SMCRT_OP_INTERSECT = 2, SMCRT_OP_SUBTRACT = 3 };
 enum {
   SMCRT_SRC_POINT = 0,   /* params: x y z                    isotropic point source */
   SMCRT_SRC_PENCIL = 1,  /* params: x y z ux uy uz           collimated beam */
@@ -75,12 +84,13 @@ smcrt_status smcrt_scene_destroy(smcrt_scene* scene);
 
 /* Adds a primitive (Sec. 2.2).  params: host array of n_params doubles laid
  * out as listed above; radii and half extents > 0, capsule/cylinder ends
- * distinct.  *out_prim receives its index. */
+ * distinct, torus axis non-zero.  *out_prim receives its index. */
 smcrt_status smcrt_scene_add_primitive(smcrt_scene* scene, int kind, const double* params,
                                        int n_params, int32_t* out_prim);
 
-/* Adds a region: the union (or smooth union of radius k_cm > 0) of the
- * listed primitives, with absorption mu_a >= 0 and scattering mu_s >= 0
+/* Adds a region: the listed primitives combined by op (SMCRT_OP_*; smooth
+ * union takes its radius k_cm > 0, the others ignore k_cm), with absorption
+ * mu_a >= 0 and scattering mu_s >= 0
  * (mu_a + mu_s > 0), Henyey-Greenstein anisotropy -1 < g < 1 and refractive
  * index n > 0 (Sec. 2.3: one property set per SDF).  Where regions overlap
  * the one added later owns the point.  prims: host array of n_prims indices. */

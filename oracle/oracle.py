@@ -14,8 +14,8 @@ import numpy as np
 
 from . import build as _build
 
-PRIM_KINDS = {"sphere": 0, "box": 1, "capsule": 2, "cylinder": 3}
-OPS = {"union": 0, "smooth_union": 1}
+PRIM_KINDS = {"sphere": 0, "box": 1, "capsule": 2, "cylinder": 3, "torus": 4}
+OPS = {"union": 0, "smooth_union": 1, "intersect": 2, "subtract": 3}
 SRC_KINDS = {"point": 0, "pencil": 1, "disc": 2, "rect": 3}
 EVENT_TYPES = ["EMIT", "SCATTER", "ABSORB", "KILL", "REFLECT", "REFRACT", "CROSS", "ESCAPE", "STALL"]
 
@@ -110,6 +110,8 @@ def prim_struct(p):
         vals = list(p["c"]) + [p["r"]]
     elif p["kind"] == "box":
         vals = list(p["c"]) + list(p["half"])
+    elif p["kind"] == "torus":
+        vals = list(p["c"]) + list(p["axis"]) + [p["R"], p["r"]]
     else:
         vals = list(p["a"]) + list(p["b"]) + [p["r"]]
     for i, v in enumerate(vals):
@@ -119,13 +121,20 @@ def prim_struct(p):
 
 def prim_aabb(p):
     """Conservative box of a primitive: sphere c -/+ r, box c -/+ half,
-    capsule and cylinder the end points' box grown by r."""
+    capsule and cylinder the end points' box grown by r, torus with unit
+    axis e: c -/+ (R sqrt(1 - e_i^2) + r) per axis (the ring's box grown by
+    the tube radius)."""
     if p["kind"] == "sphere":
         c, r = np.array(p["c"], float), float(p["r"])
         return c - r, c + r
     if p["kind"] == "box":
         c, h = np.array(p["c"], float), np.array(p["half"], float)
         return c - h, c + h
+    if p["kind"] == "torus":
+        c, e = np.array(p["c"], float), np.array(p["axis"], float)
+        e = e / np.linalg.norm(e)
+        ext = float(p["R"]) * np.sqrt(np.maximum(1.0 - e * e, 0.0)) + float(p["r"])
+        return c - ext, c + ext
     a, b, r = np.array(p["a"], float), np.array(p["b"], float), float(p["r"])
     return np.minimum(a, b) - r, np.maximum(a, b) + r
 

@@ -123,6 +123,16 @@ double orc_prim_sdf(const orc_prim* pr, const double p[3]) {
       double o1 = maxd(q1, 0.0), o2 = maxd(q2, 0.0);
       return mind(maxd(q1, q2), 0.0) + sqrt(o1 * o1 + o2 * o2);
     }
+    case ORC_TORUS: { /* distance to the ring of radius R about the axis, minus r */
+      double a[3] = {q[3], q[4], q[5]};
+      double al = len3(a);
+      double e[3] = {a[0] / al, a[1] / al, a[2] / al};
+      double pc[3] = {p[0] - q[0], p[1] - q[1], p[2] - q[2]};
+      double x = dot3(pc, e);
+      double radial[3] = {pc[0] - x * e[0], pc[1] - x * e[1], pc[2] - x * e[2]};
+      double rho = len3(radial) - q[6];
+      return sqrt(rho * rho + x * x) - q[7];
+    }
     default:
       return ORC_INF;
   }
@@ -135,12 +145,24 @@ double orc_smooth_union(double a, double b, double k) {
   return h * a + (1.0 - h) * b - k * h * (1.0 - h);
 }
 
+/* A region's SDF from its primitives, in their order:
+ *   union min, smooth union folded left to right (reading 17),
+ *   intersection max, difference max(d_first, -d_i) over the others
+ *   (the first primitive minus all the others).
+ * Intersection and difference give lower bounds of the true distance that
+ * keep Lipschitz constant 1 and the correct sign, which is what sphere
+ * tracing needs (Sec. 2.3). */
 double orc_region_sdf(const orc_scene* s, int r, const double p[3]) {
   const orc_region* rg = &s->regions[r];
   double d = orc_prim_sdf(&s->prims[rg->first_prim], p);
   for (int i = 1; i < rg->n_prims; ++i) {
     double di = orc_prim_sdf(&s->prims[rg->first_prim + i], p);
-    d = (rg->op == ORC_SMOOTH_UNION) ? orc_smooth_union(d, di, rg->k) : mind(d, di);
+    switch (rg->op) {
+      case ORC_SMOOTH_UNION: d = orc_smooth_union(d, di, rg->k); break;
+      case ORC_INTERSECT: d = maxd(d, di); break;
+      case ORC_SUBTRACT: d = maxd(d, -di); break;
+      default: d = mind(d, di); break;
+    }
   }
   return d;
 }

@@ -19,11 +19,12 @@
 extern "C" {
 #endif
 
-/* primitive kinds (Sec. 2.2, Eq. 3 for the sphere; box, capsule and capped
- * cylinder are the basic shapes of the Sec. 2.2 gallery) */
-enum { ORC_SPHERE = 0, ORC_BOX = 1, ORC_CAPSULE = 2, ORC_CYLINDER = 3 };
-/* CSG operators (Sec. 2.2: union; gallery panel e: smooth union) */
-enum { ORC_UNION = 0, ORC_SMOOTH_UNION = 1 };
+/* primitive kinds (Sec. 2.2, Eq. 3 for the sphere; box, capsule, capped
+ * cylinder and torus are basic shapes of the Sec. 2.2 gallery) */
+enum { ORC_SPHERE = 0, ORC_BOX = 1, ORC_CAPSULE = 2, ORC_CYLINDER = 3, ORC_TORUS = 4 };
+/* CSG operators (Sec. 2.2: union, intersection and difference; gallery
+ * panels e to h) */
+enum { ORC_UNION = 0, ORC_SMOOTH_UNION = 1, ORC_INTERSECT = 2, ORC_SUBTRACT = 3 };
 /* photon sources */
 enum { ORC_SRC_POINT = 0, ORC_SRC_PENCIL = 1, ORC_SRC_DISC = 2, ORC_SRC_RECT = 3 };
 /* trace record types */
@@ -33,7 +34,8 @@ enum {
   ORC_EV_STALL = 8
 };
 
-/* sphere: c[3], r | box: c[3], half[3] | capsule and capped cylinder: a[3], b[3], r */
+/* sphere: c[3], r | box: c[3], half[3] | capsule and capped cylinder: a[3], b[3], r
+ * | torus: c[3], axis[3] (any length), R (ring radius), r (tube radius) */
 typedef struct { int32_t kind; int32_t pad; double p[8]; } orc_prim;
 
 typedef struct {

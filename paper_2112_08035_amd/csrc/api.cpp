@@ -48,7 +48,7 @@ extern "C" int smcrt_abi_version(void) { return SMCRT_ABI_VERSION; }
 
 struct HostPrim {
   int kind;
-  double p[7];
+  double p[8];
 };
 struct HostRegion {
   std::vector<int32_t> prims;
@@ -102,8 +102,8 @@ extern "C" smcrt_status smcrt_scene_destroy(smcrt_scene* s) {
 extern "C" smcrt_status smcrt_scene_add_primitive(smcrt_scene* s, int kind, const double* params, int n_params,
                                                   int32_t* out_prim) {
   if (!s || !params) return fail(SMCRT_E_INVALID, "add_primitive: NULL argument");
-  static const int need[4] = {4, 6, 7, 7};
-  if (kind < 0 || kind > 3) return fail(SMCRT_E_INVALID, "add_primitive: unknown kind %d", kind);
+  static const int need[5] = {4, 6, 7, 7, 8};
+  if (kind < 0 || kind > 4) return fail(SMCRT_E_INVALID, "add_primitive: unknown kind %d", kind);
   if (n_params != need[kind]) return fail(SMCRT_E_INVALID, "add_primitive: kind %d takes %d params, got %d", kind, need[kind], n_params);
   for (int i = 0; i < n_params; ++i)
     if (!std::isfinite(params[i])) return fail(SMCRT_E_INVALID, "add_primitive: param %d is not finite", i);
@@ -120,6 +120,10 @@ extern "C" smcrt_status smcrt_scene_add_primitive(smcrt_scene* s, int kind, cons
     if (!(d[0] * d[0] + d[1] * d[1] + d[2] * d[2] > 0)) return fail(SMCRT_E_INVALID, "add_primitive: segment ends must differ");
     if (!(p.p[6] > 0)) return fail(SMCRT_E_INVALID, "add_primitive: radius must be > 0");
   }
+  if (kind == kTorus) {
+    if (!(p.p[3] * p.p[3] + p.p[4] * p.p[4] + p.p[5] * p.p[5] > 0)) return fail(SMCRT_E_INVALID, "add_primitive: torus axis must be non-zero");
+    if (!(p.p[6] >= 0 && p.p[7] > 0)) return fail(SMCRT_E_INVALID, "add_primitive: torus needs R >= 0 and tube radius r > 0");
+  }
   s->prims.push_back(p);
   s->dirty = true;
   if (out_prim) *out_prim = (int32_t)s->prims.size() - 1;
@@ -134,7 +138,7 @@ extern "C" smcrt_status smcrt_scene_add_region(smcrt_scene* s, const int32_t* pr
   for (int i = 0; i < n_prims; ++i)
     if (prims[i] < 0 || prims[i] >= (int32_t)s->prims.size())
       return fail(SMCRT_E_INVALID, "add_region: primitive index %d out of range", prims[i]);
-  if (op != SMCRT_OP_UNION && op != SMCRT_OP_SMOOTH_UNION) return fail(SMCRT_E_INVALID, "add_region: unknown op %d", op);
+  if (op < SMCRT_OP_UNION || op > SMCRT_OP_SUBTRACT) return fail(SMCRT_E_INVALID, "add_region: unknown op %d", op);
   if (op == SMCRT_OP_SMOOTH_UNION && !(k_cm > 0 && std::isfinite(k_cm)))
     return fail(SMCRT_E_INVALID, "add_region: smooth union needs k > 0");
   if (!(mu_a >= 0 && std::isfinite(mu_a)) || !(mu_s >= 0 && std::isfinite(mu_s)) || !(mu_a + mu_s > 0))
@@ -247,6 +251,14 @@ static void prim_box(const HostPrim& p, double lo[3], double hi[3]) {
     switch (p.kind) {
       case kSphere: lo[i] = p.p[i] - p.p[3]; hi[i] = p.p[i] + p.p[3]; break;
       case kBox: lo[i] = p.p[i] - p.p[3 + i]; hi[i] = p.p[i] + p.p[3 + i]; break;
+      case kTorus: {  // the ring's box grown by the tube radius
+        const double al = std::sqrt(p.p[3] * p.p[3] + p.p[4] * p.p[4] + p.p[5] * p.p[5]);
+        const double e = p.p[3 + i] / al;
+        const double ext = p.p[6] * std::sqrt(std::max(1.0 - e * e, 0.0)) + p.p[7];
+        lo[i] = p.p[i] - ext;
+        hi[i] = p.p[i] + ext;
+        break;
+      }
       default:
         lo[i] = std::min(p.p[i], p.p[3 + i]) - p.p[6];
         hi[i] = std::max(p.p[i], p.p[3 + i]) + p.p[6];
@@ -320,6 +332,13 @@ static void pack_prim(const HostPrim& h, Prim<T>& o) {
       o.v[6] = (T)L;
       o.v[7] = (T)(0.5 * L);
       o.v[8] = (T)p[6];
+      break;
+    }
+    case kTorus: {
+      const double al = std::sqrt(p[3] * p[3] + p[4] * p[4] + p[5] * p[5]);
+      for (int i = 0; i < 3; ++i) { o.v[i] = (T)p[i]; o.v[3 + i] = (T)(p[3 + i] / al); }
+      o.v[6] = (T)p[6];
+      o.v[7] = (T)p[7];
       break;
     }
   }
@@ -644,7 +663,6 @@ static smcrt_status launch_jobs(smcrt_engine* e, const std::vector<JobSpec>& job
   for (size_t j = 0; j < jobs.size(); ++j) {
     smcrt_status r = pack(jobs[j].s);
     if (r != SMCRT_OK) return r;
-    const SceneHeader* h = reinterpret_cast<const SceneHeader*>(jobs[j].s->blob.data());
     int k = -1;
     for (size_t u = 0; u < uniq.size(); ++u)
       if (uniq[u] == jobs[j].s) k = (int)u;
@@ -1202,7 +1220,6 @@ extern "C" smcrt_status smcrt_submit(smcrt_server* sv, const smcrt_scene* scene,
     std::lock_guard<std::mutex> g(sv->mu);  // the worker packs scenes under this lock's protection too
     smcrt_status st = pack(s);
     if (st != SMCRT_OK) return st;
-    const SceneHeader* h = reinterpret_cast<const SceneHeader*>(s->blob.data());
     if (sv->engine && (!d_absorbed || !d_tallies))
       return fail(SMCRT_E_INVALID, "submit: output buffers missing");
     fp = request_footprint(s);

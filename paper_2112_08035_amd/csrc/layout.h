@@ -13,8 +13,8 @@ namespace smcrt {
 constexpr int kMaxRegions = 16;     // regions per scene (ambient adds one slot)
 constexpr int kMaxPrims = 1 << 20;  // primitives per scene
 
-enum PrimKind : int32_t { kSphere = 0, kBox = 1, kCapsule = 2, kCylinder = 3 };
-enum RegionOp : int32_t { kUnion = 0, kSmoothUnion = 1 };
+enum PrimKind : int32_t { kSphere = 0, kBox = 1, kCapsule = 2, kCylinder = 3, kTorus = 4 };
+enum RegionOp : int32_t { kUnion = 0, kSmoothUnion = 1, kIntersect = 2, kSubtract = 3 };
 enum SourceKind : int32_t { kPoint = 0, kPencil = 1, kDisc = 2, kRect = 3 };
 // geometry model of a scene: the signed distance functions themselves, or
 // the voxel grid they induce (region of each voxel centre) -- the voxelised
@@ -26,6 +26,7 @@ enum Geometry : int32_t { kGeomSdf = 0, kGeomVoxel = 1 };
 //   box      : c0 c1 c2 h0 h1 h2
 //   capsule  : a0 a1 a2 ba0 ba1 ba2 1/|ba|^2 r
 //   cylinder : a0 a1 a2 e0 e1 e2 L L/2 r          (e = unit axis)
+//   torus    : c0 c1 c2 e0 e1 e2 R r              (e = unit axis)
 template <typename T>
 struct Prim {
   int32_t kind;

@@ -179,17 +179,17 @@ __device__ bool voxel_step(JobRef a, Packet<T>& pk, int v[3], Lane& ln, LdsTalli
     }
   }
   const int idx = vox_index(sc, v);
-  const T s = pk.mut > T(0) ? pk.tau * pk.inv_mut : tinf<T>();
+  const T s = pk.mut > T(0) ? (T)(pk.tau * (double)pk.inv_mut) : tinf<T>();
   if (s <= texit) {  // interaction inside this voxel
     if (a.fluence != nullptr && s > T(0)) run_add(a.fluence, ln, idx, pk.w * (double)s);
     pk.p = pk.p + s * pk.u;
-    pk.tau = T(0);
+    pk.tau = 0.0;
     pk.state = kInteract;
     return true;
   }
   if (a.fluence != nullptr && texit > T(0)) run_add(a.fluence, ln, idx, pk.w * (double)texit);
   pk.p = pk.p + texit * pk.u;
-  pk.tau -= pk.mut * texit;
+  pk.tau -= (double)pk.mut * (double)texit;
   const T ua = comp(pk.u, ax);
   int w2[3] = {v[0], v[1], v[2]};
   w2[ax] += ua > T(0) ? 1 : -1;

@@ -64,26 +64,26 @@ __device__ void surface(JobRef a, Packet<T>& pk, Lane& ln, LdsTallies& L) {
   const V3<double> q = ps + (sg * off) * nrm;
   const int r2 = (c == 0.0) ? pk.region : region_of<double>(a, q);
   RegRef R1 = sc->reg[pk.region];
-  double tau = (double)pk.tau;
+  double tau = pk.tau;
   const double s_rem = R1.mut > 0.0 ? tau / R1.mut : __builtin_inf();
   if (r2 == pk.region) {
     // no change of medium ahead: advance 2*delta along the ray
     atomicAdd(&L.cnt[kCAdvances], 1ull);
     if (s_rem <= off) {
       advance(pk, (T)s_rem);
-      pk.tau = T(0);
+      pk.tau = 0.0;
       pk.state = kInteract;
       return;
     }
     advance(pk, (T)off);
-    pk.tau = (T)(tau - R1.mut * off);
+    pk.tau = tau - R1.mut * off;
     pk.state = kTransport;
     return;
   }
   if (t_ray > 0.0) {
     if (s_rem <= t_ray) {
       advance(pk, (T)s_rem);
-      pk.tau = T(0);
+      pk.tau = 0.0;
       pk.state = kInteract;
       return;
     }
@@ -96,7 +96,7 @@ __device__ void surface(JobRef a, Packet<T>& pk, Lane& ln, LdsTallies& L) {
   pk.k += 1;
   pk.steps = 0;
   atomicAdd(&L.cnt[kCInterfaces], 1ull);
-  pk.tau = (T)tau;
+  pk.tau = tau;
   pk.state = kTransport;
   const double n1 = R1.n, n2 = sc->reg[r2].n;
   if (n1 == n2) {  // index matched: cross undeflected
@@ -257,16 +257,26 @@ walk_kernel(const WalkArgs* __restrict__ job_table, BatchArgs B) {
             record<T, TRACE>(a, pk, ln, SMCRT_EV_ESCAPE);
             live = false;
           } else {
-            const T s = pk.mut > T(0) ? pk.tau * pk.inv_mut : tinf<T>();
+            const T s = pk.mut > T(0) ? (T)(pk.tau * (double)pk.inv_mut) : tinf<T>();
             if (s <= dmin) {  // the optical depth runs out before any surface
               advance(pk, s);
-              pk.tau = T(0);
+              pk.tau = 0.0;
               pk.state = kInteract;
             } else if (dmin < delta) {
               pk.state = kSurface;
+            } else if constexpr (sizeof(T) == 4) {
+              // charge the distance the rounded position really moved: for
+              // steps far below the position's ulp-scaled size (grazing
+              // paths far from the origin) it differs from dmin, and
+              // charging dmin would let depth and position drift apart
+              const V3<T> p0 = pk.p;
+              pk.p = pk.p + dmin * pk.u;
+              const T moved = dot(pk.p - p0, pk.u);
+              pk.pend += moved;
+              pk.tau -= (double)pk.mut * (double)moved;
             } else {
               advance(pk, dmin);
-              pk.tau -= pk.mut * dmin;
+              pk.tau -= (double)pk.mut * (double)dmin;
             }
           }
         }

@@ -163,6 +163,12 @@ __device__ __forceinline__ T prim_sdf(const SMCRT_K Prim<T>* P, int i, V3<T> p) 
     return tsqrt(dot(o, o)) + tmin(tmax(ex, tmax(ey, ez)), T(0));
   }
   const V3<T> e = mk(v[3], v[4], v[5]);
+  if (kind == kTorus) {  // e unit axis, v[6] = ring radius R, v[7] = tube radius r
+    const T x = dot(q, e);
+    const V3<T> rad = q - x * e;
+    const T rho = tsqrt(dot(rad, rad)) - v[6];
+    return tsqrt(rho * rho + x * x) - v[7];
+  }
   if (kind == kCapsule) {  // e = b - a, v[6] = 1/|b-a|^2
     const T t = tclamp(dot(q, e) * v[6], T(0), T(1));
     const V3<T> d = q - t * e;
@@ -177,20 +183,25 @@ __device__ __forceinline__ T prim_sdf(const SMCRT_K Prim<T>* P, int i, V3<T> p) 
   return tmin(tmax(q1, q2), T(0)) + tsqrt(o1 * o1 + o2 * o2);
 }
 
-// region SDF: union (min) or polynomial smooth union of its primitives
+// region SDF from its primitives in order (CSG of Sec. 2.2): union (min),
+// polynomial smooth union, intersection (max) or difference, the first
+// primitive minus the others (max(d, -d_i)).  Intersection and difference
+// are lower bounds of the distance with Lipschitz constant 1, so sphere
+// tracing stays conservative.
 template <typename T>
 __device__ __forceinline__ T region_sdf(JobRef a, RegRef R, V3<T> p) {
   const SMCRT_K Prim<T>* P = Tab<T>::prims(a);
+  const int op = R.op;  // wave uniform: one loop, primitive SDFs inlined once
   T d = prim_sdf(P, R.first, p);
-  if (R.op == kSmoothUnion) {
-    const T k = Tab<T>::k(R), ik = Tab<T>::inv_k(R);
-    for (int i = 1; i < R.count; ++i) {
-      const T b = prim_sdf(P, R.first + i, p);
-      const T h = tclamp(T(0.5) + T(0.5) * (b - d) * ik, T(0), T(1));
-      d = h * d + (T(1) - h) * b - k * h * (T(1) - h);
+  for (int i = 1; i < R.count; ++i) {
+    const T b = prim_sdf(P, R.first + i, p);
+    if (op == kSmoothUnion) {
+      const T h = tclamp(T(0.5) + T(0.5) * (b - d) * Tab<T>::inv_k(R), T(0), T(1));
+      d = h * d + (T(1) - h) * b - Tab<T>::k(R) * h * (T(1) - h);
+    } else {
+      const T nb = op == kSubtract ? -b : b;
+      d = op == kUnion ? tmin(d, nb) : tmax(d, nb);
     }
-  } else {
-    for (int i = 1; i < R.count; ++i) d = tmin(d, prim_sdf(P, R.first + i, p));
   }
   return d;
 }
@@ -481,7 +492,10 @@ enum State : int { kTransport = 0, kSurface = 1, kInteract = 2 };
 template <typename T>
 struct Packet {
   V3<T> p, u;
-  T tau;
+  // remaining optical depth, FP64 in both transport precisions: it is used
+  // up over many sphere-tracing steps, and along a grazing path (thousands
+  // of steps of delta size) FP32 rounding would let it drift
+  double tau;
   T mut, inv_mut;   // of the current region (0 and 0 in ambient)
   double w;
   uint64_t pid;
@@ -511,7 +525,7 @@ __device__ __forceinline__ void record(JobRef a, const Packet<T>& pk, Lane& ln, 
       e.p[0] = pk.p.x; e.p[1] = pk.p.y; e.p[2] = pk.p.z;
       e.u[0] = pk.u.x; e.u[1] = pk.u.y; e.u[2] = pk.u.z;
       e.w = pk.w;
-      e.tau = (double)pk.tau;
+      e.tau = pk.tau;
       ln.rec[ln.n_rec] = e;
     }
     ++ln.n_rec;
@@ -578,7 +592,7 @@ __device__ void emit(JobRef a, Packet<T>& pk, Lane& ln, LdsTallies& L) {
   pk.p = p;
   pk.u = il * u;
   pk.w = 1.0;
-  pk.tau = -tlog(x3);
+  pk.tau = (double)(-tlog(x3));
   pk.k = 0;
   pk.steps = 0;
   pk.pend = T(0);
@@ -655,7 +669,7 @@ __device__ bool interact(JobRef a, Packet<T>& pk, Lane& ln, LdsTallies& L) {
       return false;
     }
   }
-  pk.tau = -tlog(xi_of<T>(r.w3));
+  pk.tau = (double)(-tlog(xi_of<T>(r.w3)));
   pk.steps = 0;
   record<T, TRACE>(a, pk, ln, SMCRT_EV_SCATTER);
   return true;

@@ -22,8 +22,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libsmcrt.so")
 
 OK, E_INVALID, E_NOMEM, E_HIP, E_BUDGET, E_CANCELLED, E_STATE = 0, -1, -2, -3, -4, -5, -6
-PRIM = {"sphere": 0, "box": 1, "capsule": 2, "cylinder": 3}
-OP = {"union": 0, "smooth_union": 1}
+PRIM = {"sphere": 0, "box": 1, "capsule": 2, "cylinder": 3, "torus": 4}
+OP = {"union": 0, "smooth_union": 1, "intersect": 2, "subtract": 3}
 SRC = {"point": 0, "pencil": 1, "disc": 2, "rect": 3}
 PREC = {"f32": 0, "f64": 1}
 EVENT_TYPES = ["EMIT", "SCATTER", "ABSORB", "KILL", "REFLECT", "REFRACT", "CROSS", "ESCAPE", "STALL"]
@@ -296,6 +296,8 @@ class Scene:
                 vals = list(p["c"]) + [p["r"]]
             elif p["kind"] == "box":
                 vals = list(p["c"]) + list(p["half"])
+            elif p["kind"] == "torus":
+                vals = list(p["c"]) + list(p["axis"]) + [p["R"], p["r"]]
             else:
                 vals = list(p["a"]) + list(p["b"]) + [p["r"]]
             ids.append(smcrt_scene_add_primitive(self.h, PRIM[p["kind"]], vals))

@@ -11,7 +11,7 @@ Scene dictionaries (lengths in cm, coefficients in 1/cm):
    "delta": float,                sphere-tracing surface threshold (Sec. 2.3)
    "pad": float,                  padding of the simulation volume
    "prims": [prim, ...],          see below
-   "regions": [{"prims": [i, ...], "op": "union" | "smooth_union", "k": float,
+   "regions": [{"prims": [i, ...], "op": "union" | "smooth_union" | "intersect" | "subtract", "k": float,
                 "mua": float, "mus": float, "g": float, "n": float}, ...],
    "source": source,
    "grid": {"lo": [3], "hi": [3], "dims": [nx, ny, nz]}   (optional),
@@ -22,6 +22,8 @@ Scene dictionaries (lengths in cm, coefficients in 1/cm):
           {"kind": "box",      "c": [3], "half": [3]}
           {"kind": "capsule",  "a": [3], "b": [3], "r": float}
           {"kind": "cylinder", "a": [3], "b": [3], "r": float}   (flat caps)
+          {"kind": "torus",    "c": [3], "axis": [3], "R": float, "r": float}
+  "subtract" is the first listed primitive minus all the others.
   source: {"kind": "point",  "p": [3]}                             isotropic
           {"kind": "pencil", "p": [3], "u": [3]}
           {"kind": "disc",   "c": [3], "r": float, "u": [3]}       top hat, z-plane
@@ -323,6 +325,74 @@ def semi_infinite_slab(mua, mus_reduced, g=0.9, n=1.38, thickness=4.0, half_xy=5
     return sc
 
 
+def absorbing_shell(mua=2.0, r_in=0.7, r_out=1.0, n=1.5):
+    """Non-scattering spherical shell (a sphere minus a concentric sphere)
+    around an isotropic point source in its hollow centre: every path is
+    radial, so escape follows the normal-incidence slab formulas."""
+    prims = [{"kind": "sphere", "c": [0.0, 0.0, 0.0], "r": r_out}, {"kind": "sphere", "c": [0.0, 0.0, 0.0], "r": r_in}]
+    regions = [_region([0, 1], mua, 0.0, 0.0, n, op="subtract")]
+    return _scene("shell", prims, regions, {"kind": "point", "p": [0.0, 0.0, 0.0]}, None)
+
+
+def absorbing_lens(mua=1.5, r=1.0, sep=1.2):
+    """Non-scattering, index-matched lens: the intersection of two unit
+    spheres whose centres lie sep apart on x, point source at its centre."""
+    prims = [{"kind": "sphere", "c": [-0.5 * sep, 0.0, 0.0], "r": r}, {"kind": "sphere", "c": [0.5 * sep, 0.0, 0.0], "r": r}]
+    regions = [_region([0, 1], mua, 0.0, 0.0, 1.0, op="intersect")]
+    return _scene("lens", prims, regions, {"kind": "point", "p": [0.0, 0.0, 0.0]}, None)
+
+
+def torus_beam(mua=2.0, R=1.0, r=0.3, x=1.0):
+    """Non-scattering, index-matched torus (axis z, ring radius R, tube
+    radius r) under a pencil beam along -z at lateral position x."""
+    prims = [{"kind": "torus", "c": [0.0, 0.0, 0.0], "axis": [0.0, 0.0, 1.0], "R": R, "r": r}]
+    regions = [_region([0], mua, 0.0, 0.0, 1.0)]
+    sc = _scene("torus_beam", prims, regions, None, None)
+    sc["source"] = {"kind": "pencil", "p": [x, 0.0, r + 0.5 * sc["pad"]], "u": [0.0, 0.0, -1.0]}
+    return sc
+
+
+def glass_sphere_scene(n_grid=64):
+    """Shaped like the paper's curved-surface test (Sec. 3.2): a glass
+    sphere (n 1.46, radius 1 cm) at (0.5, 0, -1) cm inside a weakly
+    scattering water-like medium (mu_a 0.05, mu_s 2, g 0.9, n 1.33) that
+    fills z in [-3, 0.5] over 4 x 4 cm, lit from above by a 0.3 cm top-hat
+    beam centred over the sphere's top.  The medium around the sphere is not
+    given in the paper; this one is synthetic."""
+    prims = [{"kind": "box", "c": [0.0, 0.0, -1.25], "half": [2.0, 2.0, 1.75]},
+             {"kind": "sphere", "c": [0.5, 0.0, -1.0], "r": 1.0}]
+    regions = [_region([0], 0.05, 2.0, 0.9, 1.33), _region([1], 0.01, 0.0, 0.0, 1.46)]
+    grid = {"lo": [-2.0, -2.0, -3.0], "hi": [2.0, 2.0, 0.5], "dims": [n_grid, n_grid, n_grid]}
+    sc = _scene("glass_sphere", prims, regions, None, grid)
+    sc["source"] = {"kind": "disc", "c": [0.5, 0.0, 0.5 + 0.5 * sc["pad"]], "r": 0.3, "u": [0.0, 0.0, -1.0]}
+    return sc
+
+
+def bottle_scene(n_grid=64):
+    """Shaped like the paper's bottle example (Sec. 4 gallery): a glass
+    bottle (n 1.5) whose body and neck are each a capped cylinder minus a
+    thinner one, partly filled with a milky liquid (the inner cylinder
+    intersected with a box below the fill line), lit from above through the
+    neck by a 0.3 cm top-hat beam.  Regions: liquid, body, neck (later ones
+    own the overlaps).  Synthetic dimensions (cm)."""
+    prims = [
+        {"kind": "cylinder", "a": [0.0, 0.0, 0.1], "b": [0.0, 0.0, 2.4], "r": 0.9},    # 0 body inside
+        {"kind": "box", "c": [0.0, 0.0, 0.8], "half": [1.0, 1.0, 0.8]},                  # 1 below the fill line
+        {"kind": "cylinder", "a": [0.0, 0.0, 0.0], "b": [0.0, 0.0, 2.5], "r": 1.0},    # 2 body outside
+        {"kind": "cylinder", "a": [0.0, 0.0, 2.3], "b": [0.0, 0.0, 3.5], "r": 0.35},   # 3 neck outside
+        {"kind": "cylinder", "a": [0.0, 0.0, 2.2], "b": [0.0, 0.0, 3.6], "r": 0.25},   # 4 neck inside
+    ]
+    regions = [
+        _region([0, 1], 0.05, 20.0, 0.8, 1.33, op="intersect"),   # liquid
+        _region([2, 0, 4], 0.02, 0.0, 0.0, 1.5, op="subtract"),   # body glass
+        _region([3, 4], 0.02, 0.0, 0.0, 1.5, op="subtract"),      # neck glass
+    ]
+    grid = {"lo": [-1.0, -1.0, 0.0], "hi": [1.0, 1.0, 3.5], "dims": [n_grid, n_grid, n_grid]}
+    sc = _scene("bottle", prims, regions, None, grid)
+    sc["source"] = {"kind": "disc", "c": [0.0, 0.0, 3.5 + 0.5 * sc["pad"]], "r": 0.3, "u": [0.0, 0.0, -1.0]}
+    return sc
+
+
 def with_grid(scene, dims, lo=None, hi=None):
     sc = copy.deepcopy(scene)
     g = sc.get("grid") or {}
@@ -335,4 +405,6 @@ WORKLOADS = {
     "sphere": sphere_scene,
     "slab": slab_scene,
     "cylinder": cylinder_scene,
+    "glass_sphere": glass_sphere_scene,
+    "bottle": bottle_scene,
 }

@@ -21,11 +21,12 @@ def compare_traces(o_traces, g_traces, extent, tol, cap=50, mut=None):
     oracle's exit ray.  The remaining optical depth is compared as the
     remaining path tau/mu_t relative to the extent (mut: attenuation per
     region index, -1 = ambient), because that is what fixes the next
-    interaction point.  The attenuation is that of the medium the depth was
-    last consumed in: the larger of the record's region and the most recent
-    earlier record's non-ambient region (a packet in the ambient medium
-    carries the depth left over from the medium it left).  Where no medium
-    has attenuated it yet, it is compared relative, floor 1.
+    interaction point.  The depth a record carries has been used up since
+    the last time it was drawn (emission or scattering), in every medium
+    crossed since, so its rounding error scales with the largest
+    attenuation among those media (and the record's own): that one
+    normalises it.  Where no medium has attenuated it yet, it is compared
+    relative, floor 1.
     Returns (agreeing fraction, worst errors, list of (packet, record) of
     first disagreements)."""
     agree = 0
@@ -34,7 +35,7 @@ def compare_traces(o_traces, g_traces, extent, tol, cap=50, mut=None):
     for pid, (o, g) in enumerate(zip(o_traces, g_traces)):
         o, g = o[:cap], g[:cap]
         ok = len(o) == len(g)
-        m_prev = 0.0  # attenuation of the last medium (not ambient) before record i
+        m_seg = 0.0  # largest attenuation met since the depth was last drawn
         for i in range(min(len(o), len(g))):
             a, b = o[i], g[i]
             if (a["type"], a["region"], a["event"]) != (b["type"], b["region"], b["event"]):
@@ -49,10 +50,11 @@ def compare_traces(o_traces, g_traces, extent, tol, cap=50, mut=None):
             errs = {"p": ep, "u": np.max(np.abs(a["u"] - b["u"])),
                     "w": abs(a["w"] - b["w"]) / max(abs(a["w"]), 1e-300),
                     "tau": abs(a["tau"] - b["tau"]) / max(1.0, abs(a["tau"]))}
-            m = m_prev
+            if a["type"] in ("EMIT", "SCATTER"):
+                m_seg = 0.0
             if mut is not None and a["region"] >= 0:
-                m = max(m, mut[a["region"]])
-                m_prev = mut[a["region"]]
+                m_seg = max(m_seg, mut[a["region"]])
+            m = m_seg
             if m > 0:
                 errs["tau"] = abs(a["tau"] - b["tau"]) / (m * extent)
             for k, v in errs.items():

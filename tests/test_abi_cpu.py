@@ -51,6 +51,12 @@ def test_scene_validation_rejects_bad_input(S):
             S.smcrt_scene_add_primitive(h, 0, [0, float("nan"), 0, 1])
         with pytest.raises(S.SmcrtError, match="differ"):
             S.smcrt_scene_add_primitive(h, 2, [1, 1, 1, 1, 1, 1, 0.1])
+        with pytest.raises(S.SmcrtError, match="axis"):
+            S.smcrt_scene_add_primitive(h, 4, [0, 0, 0, 0, 0, 0, 1.0, 0.2])
+        with pytest.raises(S.SmcrtError, match="tube radius"):
+            S.smcrt_scene_add_primitive(h, 4, [0, 0, 0, 0, 0, 1, 1.0, 0.0])
+        with pytest.raises(S.SmcrtError, match="unknown kind"):
+            S.smcrt_scene_add_primitive(h, 5, [0, 0, 0, 1])
         p = S.smcrt_scene_add_primitive(h, 0, [0, 0, 0, 1])
         with pytest.raises(S.SmcrtError, match="out of range"):
             S.smcrt_scene_add_region(h, [p + 1], 0, 0.0, 0.1, 10, 0.9, 1.4)
@@ -60,6 +66,8 @@ def test_scene_validation_rejects_bad_input(S):
             S.smcrt_scene_add_region(h, [p], 0, 0.0, 0.0, 0.0, 0.5, 1.4)
         with pytest.raises(S.SmcrtError, match="k > 0"):
             S.smcrt_scene_add_region(h, [p], 1, 0.0, 0.1, 10, 0.5, 1.4)
+        with pytest.raises(S.SmcrtError, match="unknown op"):
+            S.smcrt_scene_add_region(h, [p], 4, 0.0, 0.1, 10, 0.5, 1.4)
         with pytest.raises(S.SmcrtError, match="lo < hi"):
             S.smcrt_scene_set_grid(h, [0, 0, 0], [1, 0, 1], [4, 4, 4])
         with pytest.raises(S.SmcrtError, match="direction"):
@@ -88,9 +96,15 @@ def test_regions_limit(S):
         S.smcrt_scene_destroy(h)
 
 
-@pytest.mark.parametrize("name", ["sphere", "slab", "cylinder", "vessels"])
+@pytest.mark.parametrize("name", ["sphere", "slab", "cylinder", "vessels", "glass_sphere", "bottle", "torus"])
 def test_volume_rule_agrees_with_oracle(S, orc, W, name):
-    desc = W.vessel_scene(3, 1.0, n_caps=50, n_grid=8) if name == "vessels" else W.WORKLOADS[name](n_grid=8)
+    if name == "vessels":
+        desc = W.vessel_scene(3, 1.0, n_caps=50, n_grid=8)
+    elif name == "torus":
+        desc = W.torus_beam()
+        desc["prims"][0]["axis"] = [0.3, -0.4, 0.9]   # a tilted ring: every axis of the box differs
+    else:
+        desc = W.WORKLOADS[name](n_grid=8)
     sc = S.Scene(desc)
     _, npr, lo, hi = S.smcrt_scene_info(sc.h)
     olo, ohi = orc.bounding_box(desc)

@@ -1,0 +1,103 @@
+"""GPU parity on the wider SDF library (Sec. 2.2): the torus primitive,
+intersection and difference regions, and two scenes shaped like the
+paper's curved-geometry examples (a glass sphere under a beam in a
+scattering medium; a partly filled glass bottle).  Same tolerances as the
+SDF walk's parity tests."""
+import math
+
+import numpy as np
+import pytest
+
+from gpu_helpers import check_fluence, compare_traces, extent_of, identity_residual, oracle_batches
+
+pytestmark = pytest.mark.gpu
+
+
+def _torus_scatter(W):
+    prims = [{"kind": "torus", "c": [0.0, 0.0, 0.0], "axis": [0.2, -0.3, 0.9], "R": 0.8, "r": 0.3}]
+    regions = [W._region([0], 0.5, 20.0, 0.8, 1.4)]
+    centre = np.array([0.8, 0.0, 0.0])
+    e = np.array([0.2, -0.3, 0.9]) / np.linalg.norm([0.2, -0.3, 0.9])
+    centre = centre - (centre @ e) * e       # a point on the ring: inside the tube
+    centre = 0.8 * centre / np.linalg.norm(centre)
+    return W._scene("torus", prims, regions, {"kind": "point", "p": [float(x) for x in centre]},
+                    {"lo": [-1.2] * 3, "hi": [1.2] * 3, "dims": [32] * 3})
+
+
+def _scene(W, name):
+    if name == "torus":
+        return _torus_scatter(W)
+    if name == "shell":
+        return W.absorbing_shell()
+    return W.WORKLOADS[name](n_grid=32)
+
+
+@pytest.mark.parametrize("prec,need", [("f64", 0.99), ("f32", 0.97)])
+@pytest.mark.parametrize("name", ["glass_sphere", "bottle", "shell", "torus"])
+def test_csg_traces_match_oracle(S, eng, orc, W, name, prec, need):
+    desc = _scene(W, name)
+    # light trapped in the 0.3 cm torus tube by total internal reflection
+    # doubles the rounding error of its normal at every bounce, so that
+    # scene's FP32 records are held to 1e-4 (as the 5-50 um vessels are)
+    tol = 1e-6 if prec == "f64" else (1e-4 if name == "torus" else 1e-5)
+    n, seed = 256, 4711
+    g = S.trace(desc, seed, list(range(n)), 50, engine=eng, precision=prec)
+    o = [orc.trace(desc, seed, pid, 50) for pid in range(n)]
+    mut = [rg["mua"] + rg["mus"] for rg in desc["regions"]]
+    frac, worst, bad = compare_traces(o, g, extent_of(S, desc), tol, mut=mut)
+    print(f"{name} {prec}: agree {frac:.4f} worst {worst} first disagreements {bad[:5]}")
+    assert frac >= need, (frac, worst, bad[:10])
+
+
+@pytest.mark.parametrize("prec,abs_tol", [("f64", 1e-9), ("f32", 1e-4)])
+@pytest.mark.parametrize("name", ["glass_sphere", "bottle"])
+def test_csg_run_parity(S, eng, orc, W, name, prec, abs_tol):
+    desc = W.WORKLOADS[name](n_grid=48)
+    n, seed = 10000, 99
+    o, se = oracle_batches(orc, desc, seed, n, 10)
+    g = S.run(desc, seed, n, engine=eng, precision=prec)
+    assert g["launched"] == n
+    assert abs(identity_residual(g)) <= 1e-9 * n
+    diff = abs(g["absorbed"].sum() - o["absorbed"].sum())
+    rel = diff / o["absorbed"].sum()
+    print(f"{name} {prec}: absorbed relative difference {rel:.3e}")
+    if prec == "f64":
+        assert rel <= abs_tol
+        assert g["interfaces"] == o["interfaces"]
+    else:
+        assert rel <= abs_tol or diff <= 1.0   # at most one packet's weight
+    check_fluence(g, o, se, desc, prec)
+
+
+def test_csg_closed_forms_on_gpu(S, eng, W):
+    N = 1_000_000
+    # difference: shell at normal incidence (slab formulas, light reflected
+    # into the hollow meets the shell again)
+    mua, r_in, r_out, n = 2.0, 0.7, 1.0, 1.5
+    g = S.run(W.absorbing_shell(mua, r_in, r_out, n), 3, N, engine=eng, precision="f32")
+    R = ((n - 1) / (n + 1)) ** 2
+    a = math.exp(-mua * (r_out - r_in))
+    T_slab = (1 - R) ** 2 * a / (1 - R * R * a * a)
+    R_slab = R + R * (1 - R) ** 2 * a * a / (1 - R * R * a * a)
+    want = T_slab / (1 - R_slab)
+    assert abs(g["escaped_face"].sum() / N - want) < 4 * math.sqrt(want * (1 - want) / N)
+    # intersection: lens, escape by quadrature over directions
+    h, mua = 0.6, 1.5
+    x, wts = np.polynomial.legendre.leggauss(200)
+    root = np.sqrt(h * h * x * x + 1.0 - h * h)
+    want = 0.5 * np.sum(wts * np.exp(-mua * np.minimum(-h * x + root, h * x + root)))
+    g = S.run(W.absorbing_lens(mua, 1.0, 2 * h), 4, N, engine=eng, precision="f32")
+    assert abs(g["escaped_face"].sum() / N - want) < 4 * math.sqrt(want * (1 - want) / N)
+    # torus: chords through the tube
+    for off, chord in ((0.0, 2.0), (0.5, math.sqrt(3.0))):
+        g = S.run(W.torus_beam(2.0, 1.0, 0.3, x=1.0 + 0.3 * off), 5, N, engine=eng, precision="f32")
+        want = math.exp(-2.0 * chord * 0.3)
+        assert abs(g["escaped_face"][4] / N - want) < 4 * math.sqrt(want * (1 - want) / N)
+
+
+def test_bottle_voxelises_like_the_oracle(S, eng, orc, W):
+    desc = W.bottle_scene(n_grid=48)
+    gv, ov = S.voxelize(desc, engine=eng), orc.voxelize(desc)
+    bad = np.argwhere(gv != ov)
+    assert len(bad) <= max(2, 1e-4 * ov.size), len(bad)
+    assert set(np.unique(gv)) == {-1, 0, 1, 2}

@@ -375,3 +375,56 @@ def test_voxel_model_converges_to_sdf_on_curved_scene(orc, W):
         err[ng] = np.abs(v - ref).sum()
     assert err[128] < err[16]
     assert err[128] < 0.01
+
+
+# ------------------------------------------------------- CSG transport -----
+
+def test_absorbing_shell_difference(orc, W):
+    # sphere minus a concentric sphere, source in the hollow centre: every
+    # path is radial, so the shell is a slab at normal incidence and light
+    # reflected back crosses the hollow to meet the shell again
+    mua, r_in, r_out, n = 2.0, 0.7, 1.0, 1.5
+    sc = W.absorbing_shell(mua, r_in, r_out, n)
+    N = 200000
+    r = orc.run(sc, seed=31, n=N)
+    R = ((n - 1) / (n + 1)) ** 2
+    a = math.exp(-mua * (r_out - r_in))
+    T_slab = (1 - R) ** 2 * a / (1 - R * R * a * a)
+    R_slab = R + R * (1 - R) ** 2 * a * a / (1 - R * R * a * a)
+    want = T_slab / (1 - R_slab)
+    got = r["escaped_face"].sum() / N
+    assert abs(got - want) < 4 * math.sqrt(want * (1 - want) / N)
+    assert abs(identity_residual(r)) < 1e-12 * N
+
+
+def test_absorbing_lens_intersection(orc, W):
+    # intersection of two unit spheres centred at x = -/+ 0.6, index matched,
+    # point source at the centre: escape = mean over directions of
+    # exp(-mu_a t(u)), t the exit distance, by Gauss-Legendre quadrature in
+    # cos(angle to x) (the lens is symmetric about x)
+    mua, sep = 1.5, 1.2
+    sc = W.absorbing_lens(mua, 1.0, sep)
+    h = 0.5 * sep
+    x, wts = np.polynomial.legendre.leggauss(200)
+    root = np.sqrt(h * h * x * x + 1.0 - h * h)
+    t = np.minimum(-h * x + root, h * x + root)  # exits of the two spheres
+    want = 0.5 * np.sum(wts * np.exp(-mua * t))
+    N = 200000
+    r = orc.run(sc, seed=32, n=N)
+    got = r["escaped_face"].sum() / N
+    assert abs(got - want) < 4 * math.sqrt(want * (1 - want) / N)
+
+
+@pytest.mark.parametrize("offset,chord", [(0.0, 2.0), (0.5, math.sqrt(3.0))])
+def test_torus_tube_chord(orc, W, offset, chord):
+    # pencil beam along the torus axis at distance R + offset*r from it: the
+    # chord through the tube is 2 sqrt(r^2 - (offset r)^2)
+    mua, R_ring, r_tube = 2.0, 1.0, 0.3
+    sc = W.torus_beam(mua, R_ring, r_tube, x=R_ring + offset * r_tube)
+    N = 100000
+    r = orc.run(sc, seed=33, n=N)
+    want = math.exp(-mua * chord * r_tube)
+    got = r["escaped_face"][4] / N
+    assert abs(got - want) < 4 * math.sqrt(want * (1 - want) / N)
+    # every packet enters the tube; those that leave it make a second crossing
+    assert r["interfaces"] == N + r["escapes"]
