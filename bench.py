@@ -276,6 +276,43 @@ def paper_speed_tests(smcrt, workloads, precision):
     return {"tally_free_sphere": sweep, "table2": table2}
 
 
+def batching(smcrt, workloads, precision):
+    """Batched persistent launches against the plain one-scene-per-launch
+    walk on the same jobs (identical packets and results, so equal fluence
+    error): 64 copies of the small sphere case at its full 1e5 packets
+    (seeds differ), and 16 vessel-network scenes (2000 capsules, 128^3
+    grids, mu_s scaled 0.5-2x) at 2e5 packets each."""
+    import torch
+    res = {}
+    cases = (("sphere_1e5_x64", [workloads.sphere_scene()] * 64, 100_000),
+             ("vessels_2e5_x16", workloads.vessel_batch(16, n_caps=2000, n_grid=128), 200_000))
+    for name, descs, n in cases:
+        eng = smcrt.Engine(0, precision=precision)
+        scenes = [smcrt.Scene(d) for d in descs]
+        seeds = list(range(len(scenes)))
+        ns = [n] * len(scenes)
+        smcrt.launch_batch(eng, scenes, seeds, [min(n, 20_000)] * len(scenes))  # warm-up
+        torch.cuda.synchronize()
+        outs = [smcrt.Outputs(sc) for sc in scenes]
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        smcrt.launch_batch(eng, scenes, seeds, ns, outputs=outs)
+        torch.cuda.synchronize()
+        t_batch = time.perf_counter() - t
+        outs = [smcrt.Outputs(sc) for sc in scenes]
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for sc, sd, o in zip(scenes, seeds, outs):
+            smcrt.launch(eng, sc, sd, n, outputs=o)
+        torch.cuda.synchronize()
+        t_plain = time.perf_counter() - t
+        total = n * len(scenes)
+        res[name] = {"jobs": len(scenes), "packets_per_job": n, "batched_packets_per_s": total / t_batch,
+                     "one_per_launch_packets_per_s": total / t_plain, "speedup": t_plain / t_batch}
+        eng.close()
+    return res
+
+
 def csg_scenes(smcrt, workloads, precision, n=10_000_000):
     """Packets/s of the SDF walk on the two CSG scenes: the
     glass sphere under a beam in a scattering medium and the partly filled
@@ -461,6 +498,7 @@ def main():
         result["voxel_comparator"] = comparator(smcrt, workloads, args.precision)
         result["paper_speed_tests"] = paper_speed_tests(smcrt, workloads, args.precision)
         result["csg_scenes"] = csg_scenes(smcrt, workloads, args.precision)
+        result["batching"] = batching(smcrt, workloads, args.precision)
     if args.serve_requests > 0 and not args.no_cpu:
         result["serving"] = serving(smcrt, workloads, args.serve_requests, args.serve_rate,
                                     args.serve_max_packets, args.precision)

@@ -128,6 +128,19 @@ smcrt_status smcrt_scene_set_limits(smcrt_scene* scene, int32_t max_steps, int64
  * brute-force walk.  region = -1 removes the acceleration. */
 smcrt_status smcrt_scene_set_accel(smcrt_scene* scene, int32_t region, const int32_t cells[3]);
 
+/* Escape image: the light leaving through one face of the simulation volume
+ * (of the fluence grid in the voxel model).  Sec. 3.2 and Sec. 5 single out
+ * outputs at a single plane of interest as the case where the SDF walk
+ * needs no voxel grid.  face = 2*axis + side: 0 -x, 1 +x, 2 -y, 3 +y, 4 -z,
+ * 5 +z.  A packet leaving through that face adds its weight to the pixel
+ * holding the point where its straight path crosses the face's plane.  The
+ * image spans [lo[0], hi[0]] x [lo[1], hi[1]] in the face's two other axes
+ * in increasing order (x then y for a z face) with dims[0] x dims[1]
+ * pixels, first axis fastest; dims of 0 remove the detector.  Errors:
+ * SMCRT_E_INVALID for a face outside 0..5, lo >= hi or negative dims. */
+smcrt_status smcrt_scene_set_detector(smcrt_scene* scene, int face, const double lo[2], const double hi[2],
+                                      const int32_t dims[2]);
+
 /* Geometry model.  Sec. 3 measures the SDF model against a voxelised one;
  * both run here on the same emission, interactions and random stream.
  *   SMCRT_GEOM_SDF (default): packets sphere-trace the region SDFs.
@@ -242,6 +255,28 @@ smcrt_status smcrt_run(smcrt_engine* engine, const smcrt_scene* scene, uint64_t 
 smcrt_status smcrt_run_batch(smcrt_engine* engine, int n, const smcrt_scene* const* scenes, const uint64_t* seeds,
                              const uint64_t* first_packets, const uint64_t* n_packets, double* const* d_fluence_raw,
                              double* const* d_absorbed, smcrt_tallies* const* d_tallies, void* hip_stream);
+
+/* Outputs of one job: caller-owned device buffers on the engine's device,
+ * zeroed by the caller and accumulated into (+=).
+ *   fluence_raw: as d_fluence_raw of smcrt_run (NULL: no fluence tally);
+ *   absorbed, tallies: as d_absorbed and d_tallies of smcrt_run (required);
+ *   detector: dims[0] * dims[1] doubles of the scene's escape image
+ *             (smcrt_scene_set_detector), += escaped weight per pixel;
+ *             NULL: no image. */
+typedef struct {
+  double* fluence_raw;
+  double* absorbed;
+  smcrt_tallies* tallies;
+  double* detector;
+} smcrt_outputs;
+
+/* smcrt_run and smcrt_run_batch with the outputs of each job in one
+ * smcrt_outputs (outs: host array of n for the batch). */
+smcrt_status smcrt_run_ex(smcrt_engine* engine, const smcrt_scene* scene, uint64_t seed, uint64_t first_packet,
+                          uint64_t n_packets, const smcrt_outputs* out, void* hip_stream);
+smcrt_status smcrt_run_batch_ex(smcrt_engine* engine, int n, const smcrt_scene* const* scenes, const uint64_t* seeds,
+                                const uint64_t* first_packets, const uint64_t* n_packets, const smcrt_outputs* outs,
+                                void* hip_stream);
 
 /* Fluence normalisation: d_phi[v] = d_raw[v] / (launched * voxel volume),
  * in cm^-2 per launched unit weight.  d_raw and d_phi: device, nx*ny*nz

@@ -38,7 +38,9 @@ class Scene(C.Structure):
                 ("g_lo", C.c_double * 3), ("g_hi", C.c_double * 3), ("g_dims", C.c_int32 * 3),
                 ("src_kind", C.c_int32), ("src", C.c_double * 8),
                 ("w_threshold", C.c_double), ("m_survive", C.c_int32), ("max_steps", C.c_int32),
-                ("max_events", C.c_int64)]
+                ("max_events", C.c_int64),
+                ("det_face", C.c_int32), ("det_dims", C.c_int32 * 2),
+                ("det_lo", C.c_double * 2), ("det_hi", C.c_double * 2)]
 
 
 class Tallies(C.Structure):
@@ -93,6 +95,10 @@ def lib():
         L.orc_voxelize.argtypes = [C.POINTER(Scene), C.POINTER(C.c_int8)]
         L.orc_run_voxel.argtypes = L.orc_run.argtypes
         L.orc_run_voxel.restype = C.c_int
+        L.orc_run_ex.argtypes = [C.POINTER(Scene), C.c_uint64, C.c_uint64, C.c_uint64, C.c_int, C.c_int,
+                                 C.POINTER(C.c_double), C.POINTER(C.c_double), C.POINTER(C.c_double),
+                                 C.POINTER(Tallies)]
+        L.orc_run_ex.restype = C.c_int
         L.orc_trace_voxel.argtypes = L.orc_trace.argtypes
         L.orc_trace_voxel.restype = C.c_int
         _lib = L
@@ -211,6 +217,11 @@ class CScene:
         s.m_survive = int(ro["m"])
         s.max_steps = int(scene["max_steps"])
         s.max_events = int(scene["max_events"])
+        det = scene.get("detector")
+        if det:
+            s.det_face = int(det["face"])
+            s.det_dims = (C.c_int32 * 2)(*[int(x) for x in det["dims"]])
+            s.det_lo, s.det_hi = (C.c_double * 2)(*det["lo"]), (C.c_double * 2)(*det["hi"])
         self.s = s
         self.bbox = (lo, hi)
 
@@ -234,26 +245,32 @@ def tallies_dict(t):
 
 def run(scene, seed, n, first=0, threads=0, with_grid=True, voxel=False):
     """Runs packets [first, first + n).  Returns a dict with the raw
-    fluence F (nz, ny, nx), absorbed weight per region and the tallies.
+    fluence F (nz, ny, nx), absorbed weight per region, the tallies and,
+    when the scene has a detector, its escape image (dims[1], dims[0]).
     voxel=True runs the voxel-geometry model on the fluence grid instead of
-    the SDF walk."""
+    the SDF walk; with_grid=False skips the fluence tally."""
     cs = CScene(scene)
     dims = grid_dims(scene)
     nvox = dims[0] * dims[1] * dims[2]
-    f = np.zeros(nvox if (nvox and with_grid) else 1, dtype=np.float64)
+    tally = bool(nvox and with_grid)
+    f = np.zeros(nvox, dtype=np.float64) if tally else None
     absorbed = np.zeros(len(scene["regions"]), dtype=np.float64)
+    det = scene.get("detector")
+    img = np.zeros(int(det["dims"][0]) * int(det["dims"][1]), dtype=np.float64) if det else None
     t = Tallies()
-    if not with_grid:
+    if not with_grid and not voxel:
         cs.s.g_dims = (C.c_int32 * 3)(0, 0, 0)
-    fn = lib().orc_run_voxel if voxel else lib().orc_run
-    rc = fn(cs.ref, C.c_uint64(seed), C.c_uint64(first), C.c_uint64(n), threads,
-                       f.ctypes.data_as(C.POINTER(C.c_double)) if (nvox and with_grid) else None,
-                       absorbed.ctypes.data_as(C.POINTER(C.c_double)), C.byref(t))
+    dp = C.POINTER(C.c_double)
+    rc = lib().orc_run_ex(cs.ref, C.c_uint64(seed), C.c_uint64(first), C.c_uint64(n), threads, 1 if voxel else 0,
+                          f.ctypes.data_as(dp) if tally else None, absorbed.ctypes.data_as(dp),
+                          img.ctypes.data_as(dp) if det else None, C.byref(t))
     if rc != 0:
         raise RuntimeError(f"oracle run failed ({rc})")
     out = tallies_dict(t)
     out["absorbed"] = absorbed
-    out["fluence_raw"] = f.reshape(dims[2], dims[1], dims[0]) if (nvox and with_grid) else None
+    out["fluence_raw"] = f.reshape(dims[2], dims[1], dims[0]) if tally else None
+    if det:
+        out["image"] = img.reshape(int(det["dims"][1]), int(det["dims"][0]))
     return out
 
 

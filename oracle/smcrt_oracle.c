@@ -333,6 +333,7 @@ typedef struct {
   orc_tallies* t;
   orc_event* rec;
   int cap, nrec;
+  double* img; /* escape image, or NULL */
 } walker;
 
 typedef struct {
@@ -344,6 +345,31 @@ typedef struct {
 static double reg_mua(const orc_scene* s, int r) { return r < 0 ? 0.0 : s->regions[r].mua; }
 static double reg_mus(const orc_scene* s, int r) { return r < 0 ? 0.0 : s->regions[r].mus; }
 static double reg_n(const orc_scene* s, int r) { return r < 0 ? s->n_ambient : s->regions[r].n; }
+
+/* reading: the escape image (Sec. 3.2 and Sec. 5: the light at a single
+ * plane of interest).  A packet leaving through the detector face adds its
+ * weight to the pixel holding the point where its straight path crosses
+ * the face's plane: traced back along u from its position when that lies
+ * beyond the plane and the packet moves outward, else its position. */
+static void detect(walker* wk, const packet* pk, int face, double plane) {
+  const orc_scene* s = wk->s;
+  if (!wk->img || face != s->det_face || s->det_dims[0] < 1 || s->det_dims[1] < 1) return;
+  const int ax = face / 2;
+  const double sg = (face % 2) ? 1.0 : -1.0;
+  double q[3] = {pk->p[0], pk->p[1], pk->p[2]};
+  double over = (pk->p[ax] - plane) * sg, out = pk->u[ax] * sg;
+  if (over > 0.0 && out > 0.0) {
+    double t = over / out;
+    for (int a = 0; a < 3; ++a) q[a] = pk->p[a] - t * pk->u[a];
+  }
+  const int a1 = ax == 0 ? 1 : 0, a2 = ax == 2 ? 1 : 2;
+  double x = (q[a1] - s->det_lo[0]) / (s->det_hi[0] - s->det_lo[0]) * s->det_dims[0];
+  double y = (q[a2] - s->det_lo[1]) / (s->det_hi[1] - s->det_lo[1]) * s->det_dims[1];
+  if (!(x >= 0.0 && y >= 0.0)) return;
+  int i = (int)floor(x), j = (int)floor(y);
+  if (i >= s->det_dims[0] || j >= s->det_dims[1]) return;
+  wk->img[(size_t)i + (size_t)s->det_dims[0] * (size_t)j] += pk->w;
+}
 
 static void record(walker* wk, const packet* pk, int type) {
   if (!wk->rec || wk->nrec >= wk->cap) return;
@@ -564,6 +590,7 @@ static void walk(walker* wk, uint64_t seed, uint64_t pid) {
         }
         wk->t->escaped_face[face] += pk.w;
         wk->t->escapes++;
+        detect(wk, &pk, face, (face % 2) ? s->bb_hi[face / 2] : s->bb_lo[face / 2]);
         record(wk, &pk, ORC_EV_ESCAPE);
         return;
       }
@@ -599,73 +626,12 @@ static int check_scene(const orc_scene* s) {
   return 0;
 }
 
-int orc_run(const orc_scene* s, uint64_t seed, uint64_t first, uint64_t n,
-            int n_threads, double* f, double* absorbed, orc_tallies* t) {
-  if (check_scene(s) != 0 || !absorbed || !t) return -1;
-  int nt = 1;
-#ifdef _OPENMP
-  nt = n_threads > 0 ? n_threads : omp_get_max_threads();
-#endif
-  size_t nvox = (s->g_dims[0] > 0 && s->g_dims[1] > 0 && s->g_dims[2] > 0 && f)
-                    ? (size_t)s->g_dims[0] * (size_t)s->g_dims[1] * (size_t)s->g_dims[2]
-                    : 0;
-  double** fs = (double**)calloc((size_t)nt, sizeof(double*));
-  double** as = (double**)calloc((size_t)nt, sizeof(double*));
-  orc_tallies* ts = (orc_tallies*)calloc((size_t)nt, sizeof(orc_tallies));
-  int fail = 0;
-  for (int i = 0; i < nt; ++i) {
-    fs[i] = nvox ? (double*)calloc(nvox, sizeof(double)) : NULL;
-    as[i] = (double*)calloc((size_t)s->n_regions, sizeof(double));
-    if ((nvox && !fs[i]) || !as[i]) fail = 1;
-  }
-  if (!fail) {
-#ifdef _OPENMP
-#pragma omp parallel num_threads(nt)
-#endif
-    {
-      int me = 0;
-#ifdef _OPENMP
-      me = omp_get_thread_num();
-#endif
-      walker wk = {s, fs[me], as[me], &ts[me], NULL, 0, 0};
-      /* contiguous, thread-count dependent chunks of packet ids */
-      uint64_t lo = first + n * (uint64_t)me / (uint64_t)nt;
-      uint64_t hi = first + n * (uint64_t)(me + 1) / (uint64_t)nt;
-      for (uint64_t pid = lo; pid < hi; ++pid) walk(&wk, seed, pid);
-    }
-    for (int i = 0; i < nt; ++i) { /* reduce in thread order */
-      for (size_t v = 0; v < nvox; ++v) f[v] += fs[i][v];
-      for (int r = 0; r < s->n_regions; ++r) absorbed[r] += as[i][r];
-      t->launched += ts[i].launched;
-      for (int k = 0; k < 6; ++k) t->escaped_face[k] += ts[i].escaped_face[k];
-      t->roulette_gain += ts[i].roulette_gain;
-      t->roulette_loss += ts[i].roulette_loss;
-      t->stalled += ts[i].stalled;
-      t->events += ts[i].events;
-      t->steps += ts[i].steps;
-      t->interactions += ts[i].interactions;
-      t->interfaces += ts[i].interfaces;
-      t->reflections += ts[i].reflections;
-      t->refractions += ts[i].refractions;
-      t->crossings += ts[i].crossings;
-      t->advances += ts[i].advances;
-      t->voxel_segments += ts[i].voxel_segments;
-      t->kills += ts[i].kills;
-      t->stalls += ts[i].stalls;
-      t->escapes += ts[i].escapes;
-    }
-  }
-  for (int i = 0; i < nt; ++i) { free(fs[i]); free(as[i]); }
-  free(fs); free(as); free(ts);
-  return fail ? -2 : 0;
-}
-
 int orc_trace(const orc_scene* s, uint64_t seed, uint64_t pid, int cap, orc_event* out) {
   if (check_scene(s) != 0 || !out || cap < 1) return -1;
   double* absorbed = (double*)calloc((size_t)s->n_regions, sizeof(double));
   orc_tallies t;
   memset(&t, 0, sizeof(t));
-  walker wk = {s, NULL, absorbed, &t, out, cap, 0};
+  walker wk = {s, NULL, absorbed, &t, out, cap, 0, NULL};
   walk(&wk, seed, pid);
   free(absorbed);
   return wk.nrec;
@@ -782,6 +748,7 @@ static void walk_voxel(walker* wk, const voxel_geo* vg, uint64_t seed, uint64_t 
         int face = 2 * entry_axis + (pk.u[entry_axis] > 0.0 ? 1 : 0);
         wk->t->escaped_face[face] += pk.w;
         wk->t->escapes++;
+        detect(wk, &pk, face, (face % 2) ? s->g_hi[face / 2] : s->g_lo[face / 2]);
         record(wk, &pk, ORC_EV_ESCAPE);
         return;
       }
@@ -842,6 +809,7 @@ static void walk_voxel(walker* wk, const voxel_geo* vg, uint64_t seed, uint64_t 
       pk.region = -1;
       wk->t->escaped_face[face] += pk.w;
       wk->t->escapes++;
+      detect(wk, &pk, face, (face % 2) ? s->g_hi[face / 2] : s->g_lo[face / 2]);
       record(wk, &pk, ORC_EV_ESCAPE);
       return;
     }
@@ -875,6 +843,7 @@ static void walk_voxel(walker* wk, const voxel_geo* vg, uint64_t seed, uint64_t 
         int face = 2 * ax + (sg > 0.0 ? 1 : 0);
         wk->t->escaped_face[face] += pk.w;
         wk->t->escapes++;
+        detect(wk, &pk, face, (face % 2) ? s->g_hi[face / 2] : s->g_lo[face / 2]);
         record(wk, &pk, ORC_EV_ESCAPE);
         return;
       }
@@ -883,28 +852,31 @@ static void walk_voxel(walker* wk, const voxel_geo* vg, uint64_t seed, uint64_t 
   }
 }
 
-int orc_run_voxel(const orc_scene* s, uint64_t seed, uint64_t first, uint64_t n, int n_threads, double* f,
-                  double* absorbed, orc_tallies* t) {
-  if (check_scene(s) != 0 || !absorbed || !t) return -1;
-  const int* nd = s->g_dims;
-  if (nd[0] <= 0 || nd[1] <= 0 || nd[2] <= 0) return -1;
-  size_t nvox = (size_t)nd[0] * (size_t)nd[1] * (size_t)nd[2];
-  int8_t* vox = (int8_t*)malloc(nvox);
-  if (!vox) return -2;
-  orc_voxelize(s, vox);
-  voxel_geo vg = {vox};
+/* packets [first, first + n) over n_threads OpenMP threads in contiguous
+ * chunks, each thread with private outputs, reduced in thread order; the
+ * SDF walk, or the voxel walk when vg is given */
+static int run_impl(const orc_scene* s, const voxel_geo* vg, uint64_t seed, uint64_t first, uint64_t n,
+                    int n_threads, double* f, double* absorbed, double* image, orc_tallies* t) {
   int nt = 1;
 #ifdef _OPENMP
   nt = n_threads > 0 ? n_threads : omp_get_max_threads();
 #endif
+  size_t nvox = (s->g_dims[0] > 0 && s->g_dims[1] > 0 && s->g_dims[2] > 0 && f)
+                    ? (size_t)s->g_dims[0] * (size_t)s->g_dims[1] * (size_t)s->g_dims[2]
+                    : 0;
+  size_t npix = (image && s->det_dims[0] > 0 && s->det_dims[1] > 0)
+                    ? (size_t)s->det_dims[0] * (size_t)s->det_dims[1]
+                    : 0;
   double** fs = (double**)calloc((size_t)nt, sizeof(double*));
   double** as = (double**)calloc((size_t)nt, sizeof(double*));
+  double** is = (double**)calloc((size_t)nt, sizeof(double*));
   orc_tallies* ts = (orc_tallies*)calloc((size_t)nt, sizeof(orc_tallies));
-  int fail = 0;
-  for (int i = 0; i < nt; ++i) {
-    fs[i] = f ? (double*)calloc(nvox, sizeof(double)) : NULL;
+  int fail = !fs || !as || !is || !ts;
+  for (int i = 0; !fail && i < nt; ++i) {
+    fs[i] = nvox ? (double*)calloc(nvox, sizeof(double)) : NULL;
     as[i] = (double*)calloc((size_t)s->n_regions, sizeof(double));
-    if ((f && !fs[i]) || !as[i]) fail = 1;
+    is[i] = npix ? (double*)calloc(npix, sizeof(double)) : NULL;
+    if ((nvox && !fs[i]) || !as[i] || (npix && !is[i])) fail = 1;
   }
   if (!fail) {
 #ifdef _OPENMP
@@ -915,14 +887,17 @@ int orc_run_voxel(const orc_scene* s, uint64_t seed, uint64_t first, uint64_t n,
 #ifdef _OPENMP
       me = omp_get_thread_num();
 #endif
-      walker wk = {s, fs[me], as[me], &ts[me], NULL, 0, 0};
+      walker wk = {s, fs[me], as[me], &ts[me], NULL, 0, 0, is[me]};
       uint64_t lo = first + n * (uint64_t)me / (uint64_t)nt;
       uint64_t hi = first + n * (uint64_t)(me + 1) / (uint64_t)nt;
-      for (uint64_t pid = lo; pid < hi; ++pid) walk_voxel(&wk, &vg, seed, pid);
+      for (uint64_t pid = lo; pid < hi; ++pid) {
+        if (vg) walk_voxel(&wk, vg, seed, pid);
+        else walk(&wk, seed, pid);
+      }
     }
-    for (int i = 0; i < nt; ++i) {
-      if (f)
-        for (size_t q = 0; q < nvox; ++q) f[q] += fs[i][q];
+    for (int i = 0; i < nt; ++i) { /* reduce in thread order */
+      for (size_t v = 0; v < nvox; ++v) f[v] += fs[i][v];
+      for (size_t q = 0; q < npix; ++q) image[q] += is[i][q];
       for (int r = 0; r < s->n_regions; ++r) absorbed[r] += as[i][r];
       t->launched += ts[i].launched;
       for (int k = 0; k < 6; ++k) t->escaped_face[k] += ts[i].escaped_face[k];
@@ -943,9 +918,38 @@ int orc_run_voxel(const orc_scene* s, uint64_t seed, uint64_t first, uint64_t n,
       t->escapes += ts[i].escapes;
     }
   }
-  for (int i = 0; i < nt; ++i) { free(fs[i]); free(as[i]); }
-  free(fs); free(as); free(ts); free(vox);
+  for (int i = 0; i < nt; ++i) {
+    if (fs) free(fs[i]);
+    if (as) free(as[i]);
+    if (is) free(is[i]);
+  }
+  free(fs); free(as); free(is); free(ts);
   return fail ? -2 : 0;
+}
+
+int orc_run_ex(const orc_scene* s, uint64_t seed, uint64_t first, uint64_t n, int n_threads, int voxel,
+               double* f, double* absorbed, double* image, orc_tallies* t) {
+  if (check_scene(s) != 0 || !absorbed || !t) return -1;
+  if (!voxel) return run_impl(s, NULL, seed, first, n, n_threads, f, absorbed, image, t);
+  const int* nd = s->g_dims;
+  if (nd[0] <= 0 || nd[1] <= 0 || nd[2] <= 0) return -1;
+  int8_t* vox = (int8_t*)malloc((size_t)nd[0] * (size_t)nd[1] * (size_t)nd[2]);
+  if (!vox) return -2;
+  orc_voxelize(s, vox);
+  voxel_geo vg = {vox};
+  int rc = run_impl(s, &vg, seed, first, n, n_threads, f, absorbed, image, t);
+  free(vox);
+  return rc;
+}
+
+int orc_run(const orc_scene* s, uint64_t seed, uint64_t first, uint64_t n,
+            int n_threads, double* f, double* absorbed, orc_tallies* t) {
+  return orc_run_ex(s, seed, first, n, n_threads, 0, f, absorbed, NULL, t);
+}
+
+int orc_run_voxel(const orc_scene* s, uint64_t seed, uint64_t first, uint64_t n, int n_threads, double* f,
+                  double* absorbed, orc_tallies* t) {
+  return orc_run_ex(s, seed, first, n, n_threads, 1, f, absorbed, NULL, t);
 }
 
 int orc_trace_voxel(const orc_scene* s, uint64_t seed, uint64_t pid, int cap, orc_event* out) {
@@ -960,7 +964,7 @@ int orc_trace_voxel(const orc_scene* s, uint64_t seed, uint64_t pid, int cap, or
   voxel_geo vg = {vox};
   orc_tallies t;
   memset(&t, 0, sizeof(t));
-  walker wk = {s, NULL, absorbed, &t, out, cap, 0};
+  walker wk = {s, NULL, absorbed, &t, out, cap, 0, NULL};
   walk_voxel(&wk, &vg, seed, pid);
   free(vox);
   free(absorbed);

@@ -59,6 +59,12 @@ typedef struct {
   int32_t m_survive;              /* survive with probability 1/m, weight * m */
   int32_t max_steps;              /* sphere-tracing steps allowed per event */
   int64_t max_events;             /* events allowed per packet */
+  /* escape image: face 2*axis + side of the simulation volume (of the grid
+   * in the voxel model), pixels over [det_lo, det_hi] in the face's two
+   * other axes (increasing axis order, first fastest); det_dims 0 = none */
+  int32_t det_face;
+  int32_t det_dims[2];
+  double det_lo[2], det_hi[2];
 } orc_scene;
 
 typedef struct {
@@ -101,6 +107,11 @@ int64_t orc_tally_segment(const orc_scene* s, const double a[3], const double b[
  * negative error code. */
 int orc_run(const orc_scene* s, uint64_t seed, uint64_t first, uint64_t n,
             int n_threads, double* f, double* absorbed, orc_tallies* t);
+
+/* as orc_run (voxel = 0) or orc_run_voxel (voxel = 1), with the escape
+ * image accumulated into image (det_dims[0] * det_dims[1]; may be NULL) */
+int orc_run_ex(const orc_scene* s, uint64_t seed, uint64_t first, uint64_t n, int n_threads, int voxel,
+               double* f, double* absorbed, double* image, orc_tallies* t);
 
 /* event records of one packet; returns the number written (<= cap) */
 int orc_trace(const orc_scene* s, uint64_t seed, uint64_t pid, int cap, orc_event* out);

@@ -73,6 +73,9 @@ struct smcrt_scene {
   int32_t accel_region = -1;
   int32_t accel_cells[3] = {0, 0, 0};
   int32_t geometry = kGeomSdf;
+  int32_t det_face = -1;
+  int32_t det_dims[2] = {0, 0};
+  double det_lo[2] = {0, 0}, det_hi[2] = {0, 0};
   // packed device tables (rebuilt when dirty)
   bool dirty = true;
   std::vector<unsigned char> blob;
@@ -238,6 +241,29 @@ extern "C" smcrt_status smcrt_scene_set_accel(smcrt_scene* s, int32_t region, co
 }
 
 // conservative box of a primitive
+extern "C" smcrt_status smcrt_scene_set_detector(smcrt_scene* s, int face, const double lo[2], const double hi[2],
+                                                 const int32_t dims[2]) {
+  if (!s || !lo || !hi || !dims) return fail(SMCRT_E_INVALID, "set_detector: NULL argument");
+  if (dims[0] < 0 || dims[1] < 0) return fail(SMCRT_E_INVALID, "set_detector: negative dims");
+  if (dims[0] == 0 || dims[1] == 0) {
+    s->det_face = -1;
+    s->dirty = true;
+    return SMCRT_OK;
+  }
+  if (face < 0 || face > 5) return fail(SMCRT_E_INVALID, "set_detector: face %d outside 0..5", face);
+  for (int i = 0; i < 2; ++i)
+    if (!(std::isfinite(lo[i]) && std::isfinite(hi[i]) && lo[i] < hi[i]))
+      return fail(SMCRT_E_INVALID, "set_detector: need finite lo < hi");
+  s->det_face = face;
+  for (int i = 0; i < 2; ++i) {
+    s->det_dims[i] = dims[i];
+    s->det_lo[i] = lo[i];
+    s->det_hi[i] = hi[i];
+  }
+  s->dirty = true;
+  return SMCRT_OK;
+}
+
 extern "C" smcrt_status smcrt_scene_set_geometry(smcrt_scene* s, int mode) {
   if (!s) return fail(SMCRT_E_INVALID, "set_geometry: NULL scene");
   if (mode != SMCRT_GEOM_SDF && mode != SMCRT_GEOM_VOXEL) return fail(SMCRT_E_INVALID, "set_geometry: unknown mode %d", mode);
@@ -502,6 +528,12 @@ static smcrt_status pack(smcrt_scene* s) {
   h->geometry = s->geometry;
   h->src_kind = s->src_kind;
   std::memcpy(h->src, s->src, sizeof(h->src));
+  h->det_face = s->det_face;
+  for (int i = 0; i < 2; ++i) {
+    h->det_dims[i] = s->det_face >= 0 ? s->det_dims[i] : 0;
+    h->det_lo[i] = s->det_lo[i];
+    h->det_hi[i] = s->det_hi[i];
+  }
   h->w_threshold = s->w_threshold;
   h->m_survive = s->m_survive;
   h->m_d = (double)s->m_survive;
@@ -639,6 +671,7 @@ struct JobSpec {
   double* fluence;
   double* absorbed;
   smcrt_tallies* tallies;
+  double* detector = nullptr;
 };
 
 struct TraceSpec {
@@ -730,6 +763,7 @@ static smcrt_status launch_jobs(smcrt_engine* e, const std::vector<JobSpec>& job
     a.counter = reinterpret_cast<unsigned long long*>(base + counters_off) + j;
     a.fluence = h->has_grid ? jobs[j].fluence : nullptr;
     a.absorbed = jobs[j].absorbed;
+    a.detector = h->det_face >= 0 ? jobs[j].detector : nullptr;
     a.tallies = jobs[j].tallies;
     a.acc_region = h->acc.region;
     a.geometry = h->geometry;
@@ -746,6 +780,7 @@ static smcrt_status launch_jobs(smcrt_engine* e, const std::vector<JobSpec>& job
       a.n_trace = tr->n_ids;
       a.max_records = tr->max_records;
       a.fluence = nullptr;
+      a.detector = nullptr;
     }
   }
   // upload through pinned staging; wait until the previous upload left it
@@ -855,16 +890,43 @@ static smcrt_status launch_jobs(smcrt_engine* e, const std::vector<JobSpec>& job
   return SMCRT_OK;
 }
 
-extern "C" smcrt_status smcrt_run(smcrt_engine* e, const smcrt_scene* scene, uint64_t seed, uint64_t first_packet,
-                                  uint64_t n_packets, double* d_fluence_raw, double* d_absorbed, smcrt_tallies* d_tallies,
-                                  void* hip_stream) {
-  if (!e || !scene) return fail(SMCRT_E_INVALID, "run: NULL engine or scene");
-  if (!d_absorbed || !d_tallies) return fail(SMCRT_E_INVALID, "run: d_absorbed and d_tallies are required");
+extern "C" smcrt_status smcrt_run_ex(smcrt_engine* e, const smcrt_scene* scene, uint64_t seed, uint64_t first_packet,
+                                     uint64_t n_packets, const smcrt_outputs* out, void* hip_stream) {
+  if (!e || !scene || !out) return fail(SMCRT_E_INVALID, "run: NULL engine, scene or outputs");
+  if (!out->absorbed || !out->tallies) return fail(SMCRT_E_INVALID, "run: absorbed and tallies are required");
   if (n_packets == 0) return SMCRT_OK;
   if (first_packet + n_packets < first_packet) return fail(SMCRT_E_INVALID, "run: packet range overflows 64 bits");
   HIP_TRY(hipSetDevice(e->device), "hipSetDevice");
   std::vector<JobSpec> jobs(1);
-  jobs[0] = JobSpec{const_cast<smcrt_scene*>(scene), seed, first_packet, n_packets, d_fluence_raw, d_absorbed, d_tallies};
+  jobs[0] = JobSpec{const_cast<smcrt_scene*>(scene), seed, first_packet, n_packets, out->fluence_raw, out->absorbed,
+                    out->tallies, out->detector};
+  return launch_jobs(e, jobs, nullptr, (hipStream_t)hip_stream);
+}
+
+extern "C" smcrt_status smcrt_run(smcrt_engine* e, const smcrt_scene* scene, uint64_t seed, uint64_t first_packet,
+                                  uint64_t n_packets, double* d_fluence_raw, double* d_absorbed, smcrt_tallies* d_tallies,
+                                  void* hip_stream) {
+  const smcrt_outputs out{d_fluence_raw, d_absorbed, d_tallies, nullptr};
+  return smcrt_run_ex(e, scene, seed, first_packet, n_packets, &out, hip_stream);
+}
+
+extern "C" smcrt_status smcrt_run_batch_ex(smcrt_engine* e, int n, const smcrt_scene* const* scenes, const uint64_t* seeds,
+                                           const uint64_t* first_packets, const uint64_t* n_packets,
+                                           const smcrt_outputs* outs, void* hip_stream) {
+  if (!e || n < 1 || !scenes || !seeds || !n_packets || !outs)
+    return fail(SMCRT_E_INVALID, "run_batch: NULL argument or n < 1");
+  std::vector<JobSpec> jobs;
+  for (int j = 0; j < n; ++j) {
+    if (!scenes[j]) return fail(SMCRT_E_INVALID, "run_batch: scene %d is NULL", j);
+    if (!outs[j].absorbed || !outs[j].tallies) return fail(SMCRT_E_INVALID, "run_batch: job %d lacks absorbed or tallies", j);
+    const uint64_t first = first_packets ? first_packets[j] : 0;
+    if (first + n_packets[j] < first) return fail(SMCRT_E_INVALID, "run_batch: job %d packet range overflows", j);
+    if (n_packets[j] == 0) continue;
+    jobs.push_back(JobSpec{const_cast<smcrt_scene*>(scenes[j]), seeds[j], first, n_packets[j], outs[j].fluence_raw,
+                           outs[j].absorbed, outs[j].tallies, outs[j].detector});
+  }
+  if (jobs.empty()) return SMCRT_OK;
+  HIP_TRY(hipSetDevice(e->device), "hipSetDevice");
   return launch_jobs(e, jobs, nullptr, (hipStream_t)hip_stream);
 }
 
@@ -873,19 +935,9 @@ extern "C" smcrt_status smcrt_run_batch(smcrt_engine* e, int n, const smcrt_scen
                                         double* const* d_absorbed, smcrt_tallies* const* d_tallies, void* hip_stream) {
   if (!e || n < 1 || !scenes || !seeds || !n_packets || !d_fluence_raw || !d_absorbed || !d_tallies)
     return fail(SMCRT_E_INVALID, "run_batch: NULL argument or n < 1");
-  std::vector<JobSpec> jobs;
-  for (int j = 0; j < n; ++j) {
-    if (!scenes[j]) return fail(SMCRT_E_INVALID, "run_batch: scene %d is NULL", j);
-    if (!d_absorbed[j] || !d_tallies[j]) return fail(SMCRT_E_INVALID, "run_batch: job %d lacks d_absorbed or d_tallies", j);
-    const uint64_t first = first_packets ? first_packets[j] : 0;
-    if (first + n_packets[j] < first) return fail(SMCRT_E_INVALID, "run_batch: job %d packet range overflows", j);
-    if (n_packets[j] == 0) continue;
-    jobs.push_back(JobSpec{const_cast<smcrt_scene*>(scenes[j]), seeds[j], first, n_packets[j], d_fluence_raw[j],
-                           d_absorbed[j], d_tallies[j]});
-  }
-  if (jobs.empty()) return SMCRT_OK;
-  HIP_TRY(hipSetDevice(e->device), "hipSetDevice");
-  return launch_jobs(e, jobs, nullptr, (hipStream_t)hip_stream);
+  std::vector<smcrt_outputs> outs((size_t)n);
+  for (int j = 0; j < n; ++j) outs[j] = smcrt_outputs{d_fluence_raw[j], d_absorbed[j], d_tallies[j], nullptr};
+  return smcrt_run_batch_ex(e, n, scenes, seeds, first_packets, n_packets, outs.data(), hip_stream);
 }
 
 extern "C" smcrt_status smcrt_engine_autotune(smcrt_engine* e, const smcrt_scene* scene, uint64_t n_trial,

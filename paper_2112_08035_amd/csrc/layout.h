@@ -77,6 +77,11 @@ struct SceneHeader {
   double g_lo[3], g_inv_d[3], g_d[3], g_hi[3];
   float g_lof[3], g_inv_df[3], g_df[3], g_hif[3];
   double src[8];
+  // escape image: face 2*axis + side, pixels over [det_lo, det_hi] in the
+  // face's two other axes (increasing axis order, first fastest); det_face
+  // -1 = none
+  int32_t det_face, det_dims[2], pad_det;
+  double det_lo[2], det_hi[2];
   double w_threshold, m_d, inv_m;
   float deltaf, pad1;
   Region reg[kMaxRegions + 1];
@@ -113,6 +118,7 @@ struct WalkArgs {
   int32_t acc_region;            // copy of sc->acc.region (-1 = none)
   int32_t geometry;              // copy of sc->geometry
   uint8_t* vox;                  // voxel model: region slot per voxel (nx*ny*nz, x fastest)
+  double* detector;              // escape image (det_dims[0] * det_dims[1]), may be null
 };
 
 // Arguments of one walk launch: a table of jobs in device memory.

@@ -32,12 +32,15 @@ __device__ __forceinline__ void set_comp(V3<T>& a, int i, T x) {
   else a.z = x;
 }
 
+// escape through grid face `face`; on_grid: the packet is on that face (it
+// reached the grid), so it is seen by the escape image
 template <typename T, bool TRACE>
-__device__ __forceinline__ void escape_face(JobRef a, Packet<T>& pk, Lane& ln, LdsTallies& L, int face) {
+__device__ __forceinline__ void escape_face(JobRef a, Packet<T>& pk, Lane& ln, LdsTallies& L, int face, bool on_grid) {
   ScP sc = kptr(a.sc);
   pk.region = sc->n_regions;
   atomicAdd(&L.escaped[face], pk.w);
   atomicAdd(&L.cnt[kCEscapes], 1ull);
+  if (on_grid) detect<T>(a, pk, face, (face & 1) ? Tab<T>::g_hi(sc, face >> 1) : Tab<T>::g_lo(sc, face >> 1));
   record<T, TRACE>(a, pk, ln, SMCRT_EV_ESCAPE);
 }
 
@@ -117,7 +120,7 @@ __device__ bool enter_grid(JobRef a, Packet<T>& pk, int v[3], Lane& ln, LdsTalli
           face = 2 * i + (comp(p, i) > c ? 1 : 0);
         }
       }
-      escape_face<T, TRACE>(a, pk, ln, L, face);
+      escape_face<T, TRACE>(a, pk, ln, L, face, false);
       return false;
     }
     pk.p = p + t0 * u;
@@ -146,7 +149,7 @@ __device__ bool enter_grid(JobRef a, Packet<T>& pk, int v[3], Lane& ln, LdsTalli
   }
   if (voxel_interface<T, TRACE>(a, pk, ln, L, entry, r2, n1, n2)) return true;
   // reflected off the grid: it leaves through the face it came to
-  escape_face<T, TRACE>(a, pk, ln, L, 2 * entry + (comp(pk.u, entry) > T(0) ? 1 : 0));
+  escape_face<T, TRACE>(a, pk, ln, L, 2 * entry + (comp(pk.u, entry) > T(0) ? 1 : 0), true);
   return false;
 }
 
@@ -199,7 +202,7 @@ __device__ bool voxel_step(JobRef a, Packet<T>& pk, int v[3], Lane& ln, LdsTalli
   const double n1 = sc->reg[pk.region].n, n2 = sc->reg[r2].n;
   if (n1 == n2) {
     if (off) {
-      escape_face<T, TRACE>(a, pk, ln, L, face);
+      escape_face<T, TRACE>(a, pk, ln, L, face, true);
       return false;
     }
     v[0] = w2[0]; v[1] = w2[1]; v[2] = w2[2];
@@ -210,6 +213,7 @@ __device__ bool voxel_step(JobRef a, Packet<T>& pk, int v[3], Lane& ln, LdsTalli
   if (off) {  // transmitted out of the grid
     atomicAdd(&L.escaped[face], pk.w);
     atomicAdd(&L.cnt[kCEscapes], 1ull);
+    detect<T>(a, pk, face, (face & 1) ? Tab<T>::g_hi(sc, face >> 1) : Tab<T>::g_lo(sc, face >> 1));
     record<T, TRACE>(a, pk, ln, SMCRT_EV_ESCAPE);
     return false;
   }

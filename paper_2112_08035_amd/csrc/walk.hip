@@ -254,6 +254,7 @@ walk_kernel(const WalkArgs* __restrict__ job_table, BatchArgs B) {
           if (dbb > T(0)) {  // outside the simulation volume
             atomicAdd(&L.escaped[face], pk.w);
             atomicAdd(&L.cnt[kCEscapes], 1ull);
+            detect<T>(a, pk, face, Tab<T>::bb_c(sc, face >> 1) + ((face & 1) ? Tab<T>::bb_h(sc, face >> 1) : -Tab<T>::bb_h(sc, face >> 1)));
             record<T, TRACE>(a, pk, ln, SMCRT_EV_ESCAPE);
             live = false;
           } else {

@@ -116,6 +116,8 @@ struct Tab<float> {
   static __device__ __forceinline__ float inv_mut(RegRef r) { return r.inv_mutf; }
   static __device__ __forceinline__ V3<float> bb_c(ScP s) { return {s->bb_cf[0], s->bb_cf[1], s->bb_cf[2]}; }
   static __device__ __forceinline__ V3<float> bb_h(ScP s) { return {s->bb_hf[0], s->bb_hf[1], s->bb_hf[2]}; }
+  static __device__ __forceinline__ float bb_c(ScP s, int i) { return s->bb_cf[i]; }
+  static __device__ __forceinline__ float bb_h(ScP s, int i) { return s->bb_hf[i]; }
   static __device__ __forceinline__ V3<float> g_lo(ScP s) { return {s->g_lof[0], s->g_lof[1], s->g_lof[2]}; }
   static __device__ __forceinline__ V3<float> g_inv(ScP s) { return {s->g_inv_df[0], s->g_inv_df[1], s->g_inv_df[2]}; }
   static __device__ __forceinline__ float g_d(ScP s, int i) { return s->g_df[i]; }
@@ -137,6 +139,8 @@ struct Tab<double> {
   static __device__ __forceinline__ double inv_mut(RegRef r) { return r.inv_mut; }
   static __device__ __forceinline__ V3<double> bb_c(ScP s) { return {s->bb_c[0], s->bb_c[1], s->bb_c[2]}; }
   static __device__ __forceinline__ V3<double> bb_h(ScP s) { return {s->bb_h[0], s->bb_h[1], s->bb_h[2]}; }
+  static __device__ __forceinline__ double bb_c(ScP s, int i) { return s->bb_c[i]; }
+  static __device__ __forceinline__ double bb_h(ScP s, int i) { return s->bb_h[i]; }
   static __device__ __forceinline__ V3<double> g_lo(ScP s) { return {s->g_lo[0], s->g_lo[1], s->g_lo[2]}; }
   static __device__ __forceinline__ V3<double> g_inv(ScP s) { return {s->g_inv_d[0], s->g_inv_d[1], s->g_inv_d[2]}; }
   static __device__ __forceinline__ double g_d(ScP s, int i) { return s->g_d[i]; }
@@ -549,6 +553,32 @@ __device__ __forceinline__ void flush_tally(JobRef a, Packet<T>& pk, Lane& ln) {
   if (pk.pend > T(0))
     tally_move<T>(a, pk.p - pk.pend * pk.u, pk.u, pk.pend, pk.w, ln);
   pk.pend = T(0);
+}
+
+// Escape image (Sec. 3.2 and Sec. 5: the light at a single plane of
+// interest).  A packet leaving through the detector face adds its weight to
+// the pixel holding the point where its straight path crosses the face's
+// plane: traced back along u from its position when that lies beyond the
+// plane and the packet moves outward, else its position.
+template <typename T>
+__device__ __forceinline__ void detect(JobRef a, const Packet<T>& pk, int face, T plane) {
+  if (a.detector == nullptr) return;
+  ScP sc = kptr(a.sc);
+  if (face != sc->det_face) return;
+  const int ax = face >> 1;
+  const T sg = (face & 1) ? T(1) : T(-1);
+  const T pa = ax == 0 ? pk.p.x : (ax == 1 ? pk.p.y : pk.p.z);
+  const T ua = ax == 0 ? pk.u.x : (ax == 1 ? pk.u.y : pk.u.z);
+  V3<T> q = pk.p;
+  const T over = (pa - plane) * sg, out = ua * sg;
+  if (over > T(0) && out > T(0)) q = pk.p - (over / out) * pk.u;
+  const T c1 = ax == 0 ? q.y : q.x, c2 = ax == 2 ? q.y : q.z;
+  const T x = (c1 - (T)sc->det_lo[0]) / ((T)sc->det_hi[0] - (T)sc->det_lo[0]) * (T)sc->det_dims[0];
+  const T y = (c2 - (T)sc->det_lo[1]) / ((T)sc->det_hi[1] - (T)sc->det_lo[1]) * (T)sc->det_dims[1];
+  if (!(x >= T(0) && y >= T(0))) return;
+  const int i = (int)floor(x), j = (int)floor(y);
+  if (i >= sc->det_dims[0] || j >= sc->det_dims[1]) return;
+  grid_add(a.detector, i + sc->det_dims[0] * j, pk.w);
 }
 
 __device__ __forceinline__ void add_absorbed(LdsTallies& L, Lane& ln, int r, double dA) {

@@ -62,6 +62,12 @@ class Opts(C.Structure):
                 ("reserved", C.c_int32 * 2)]
 
 
+class OutputsStruct(C.Structure):
+    """smcrt_outputs"""
+    _fields_ = [("fluence_raw", C.c_void_p), ("absorbed", C.c_void_p), ("tallies", C.c_void_p),
+                ("detector", C.c_void_p)]
+
+
 _lib = None
 _vp = C.c_void_p
 _dp = C.POINTER(C.c_double)
@@ -79,6 +85,10 @@ _SIGS = {
     "smcrt_scene_set_limits": ([_vp, C.c_int32, C.c_int64], C.c_int),
     "smcrt_scene_set_accel": ([_vp, C.c_int32, C.POINTER(C.c_int32)], C.c_int),
     "smcrt_scene_set_geometry": ([_vp, C.c_int], C.c_int),
+    "smcrt_scene_set_detector": ([_vp, C.c_int, _dp, _dp, C.POINTER(C.c_int32)], C.c_int),
+    "smcrt_run_ex": ([_vp, _vp, C.c_uint64, C.c_uint64, C.c_uint64, C.POINTER(OutputsStruct), _vp], C.c_int),
+    "smcrt_run_batch_ex": ([_vp, C.c_int, C.POINTER(_vp), C.POINTER(C.c_uint64), C.POINTER(C.c_uint64),
+                            C.POINTER(C.c_uint64), C.POINTER(OutputsStruct), _vp], C.c_int),
     "smcrt_scene_info": ([_vp, C.POINTER(C.c_int32), C.POINTER(C.c_int32), _dp, _dp], C.c_int),
     "smcrt_engine_create": ([C.POINTER(_vp), C.c_int], C.c_int),
     "smcrt_engine_destroy": ([_vp], C.c_int),
@@ -184,6 +194,23 @@ GEOM = {"sdf": 0, "voxel": 1}
 
 def smcrt_scene_set_geometry(scene, mode):
     _check(lib().smcrt_scene_set_geometry(scene, GEOM[mode] if isinstance(mode, str) else int(mode)))
+
+
+def smcrt_scene_set_detector(scene, face, lo, hi, dims):
+    _check(lib().smcrt_scene_set_detector(scene, int(face), (C.c_double * 2)(*lo), (C.c_double * 2)(*hi),
+                                          (C.c_int32 * 2)(*[int(d) for d in dims])))
+
+
+def smcrt_run_ex(engine, scene, seed, first_packet, n_packets, outputs, stream):
+    _check(lib().smcrt_run_ex(engine, scene, seed, first_packet, n_packets, C.byref(outputs), stream))
+
+
+def smcrt_run_batch_ex(engine, scenes, seeds, first_packets, n_packets, outputs, stream):
+    n = len(scenes)
+    arr = (OutputsStruct * n)(*outputs)
+    _check(lib().smcrt_run_batch_ex(engine, n, (_vp * n)(*scenes), (C.c_uint64 * n)(*seeds),
+                                    (C.c_uint64 * n)(*first_packets) if first_packets is not None else None,
+                                    (C.c_uint64 * n)(*n_packets), arr, stream))
 
 
 def smcrt_scene_info(scene):
@@ -332,6 +359,10 @@ class Scene:
                 smcrt_scene_set_accel(self.h, r, desc["accel_cells"])
         if desc.get("geometry", "sdf") != "sdf":
             smcrt_scene_set_geometry(self.h, desc["geometry"])
+        det = desc.get("detector")
+        self.det_dims = (int(det["dims"][0]), int(det["dims"][1])) if det else None
+        if det:
+            smcrt_scene_set_detector(self.h, det["face"], det["lo"], det["hi"], det["dims"])
         self.n_regions = len(desc["regions"])
 
     @property
@@ -418,12 +449,21 @@ class Outputs:
         self.absorbed = torch.zeros(scene.n_regions, dtype=torch.float64, device=dev)
         self.tallies = torch.zeros(C.sizeof(Tallies), dtype=torch.uint8, device=dev)
         self.dims = scene.dims
+        self.det_dims = scene.det_dims
+        self.detector = (torch.zeros(self.det_dims[0] * self.det_dims[1], dtype=torch.float64, device=dev)
+                         if self.det_dims else None)
 
     def zero_(self):
         self.fluence.zero_()
         self.absorbed.zero_()
         self.tallies.zero_()
         return self
+
+    def struct(self):
+        """The buffers as an smcrt_outputs."""
+        f, a, t = self.ptrs()
+        d = C.c_void_p(self.detector.data_ptr()) if self.detector is not None else None
+        return OutputsStruct(f, a, t, d)
 
     def ptrs(self):
         f = C.c_void_p(self.fluence.data_ptr()) if self.tally else None
@@ -439,14 +479,15 @@ class Outputs:
         out["absorbed"] = self.absorbed.cpu().numpy()
         nx, ny, nz = self.dims
         out["fluence_raw"] = self.fluence.cpu().numpy().reshape(nz, ny, nx) if self.tally else None
+        if self.detector is not None:
+            out["image"] = self.detector.cpu().numpy().reshape(self.det_dims[1], self.det_dims[0])
         return out
 
 
 def launch(engine, scene, seed, n, first=0, outputs=None, stream=None):
     """Queues one run on the stream; returns the Outputs (not synchronised)."""
     out = outputs if outputs is not None else Outputs(scene, engine.device)
-    f, a, t = out.ptrs()
-    smcrt_run(engine.h, scene.h, seed, first, n, f, a, t, _stream_ptr(stream))
+    smcrt_run_ex(engine.h, scene.h, seed, first, n, out.struct(), _stream_ptr(stream))
     return out
 
 
@@ -454,10 +495,8 @@ def launch_batch(engine, scenes, seeds, n_packets, firsts=None, outputs=None, st
     """Queues one batched run (one persistent launch for all jobs); returns
     the list of Outputs (not synchronised)."""
     outs = outputs if outputs is not None else [Outputs(sc, engine.device) for sc in scenes]
-    ptrs = [o.ptrs() for o in outs]
-    smcrt_run_batch(engine.h, [sc.h for sc in scenes], list(seeds), list(firsts) if firsts is not None else None,
-                    list(n_packets), [p[0] for p in ptrs], [p[1] for p in ptrs], [p[2] for p in ptrs],
-                    _stream_ptr(stream))
+    smcrt_run_batch_ex(engine.h, [sc.h for sc in scenes], list(seeds), list(firsts) if firsts is not None else None,
+                       list(n_packets), [o.struct() for o in outs], _stream_ptr(stream))
     return outs
 
 

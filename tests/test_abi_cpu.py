@@ -221,3 +221,18 @@ def test_geometry_mode_validation(S, W):
             small.submit(S.Scene(dict(W.sphere_scene(n_grid=64), geometry="voxel")), 1, 10)
     finally:
         small.close()
+
+
+def test_detector_validation(S):
+    h = S.smcrt_scene_create(1.0, 1e-5, 1e-4)
+    try:
+        with pytest.raises(S.SmcrtError, match="face"):
+            S.smcrt_scene_set_detector(h, 6, [0, 0], [1, 1], [4, 4])
+        with pytest.raises(S.SmcrtError, match="lo < hi"):
+            S.smcrt_scene_set_detector(h, 5, [0, 1], [1, 1], [4, 4])
+        with pytest.raises(S.SmcrtError, match="negative"):
+            S.smcrt_scene_set_detector(h, 5, [0, 0], [1, 1], [-1, 4])
+        S.smcrt_scene_set_detector(h, 5, [0, 0], [1, 1], [4, 4])
+        S.smcrt_scene_set_detector(h, 9, [0, 0], [1, 1], [0, 0])   # dims 0 remove it (face ignored)
+    finally:
+        S.smcrt_scene_destroy(h)

@@ -1,0 +1,106 @@
+"""GPU escape images: the light leaving through one face of the volume (the
+single-plane output Sec. 3.2 and Sec. 5 single out), against the oracle on
+shared seeds and against the solid angle of pixels seen from a point
+source.  Tolerances as for the fluence: FP64 per pixel to rounding where no
+oracle batch varies, else within 3 Monte Carlo SE (FP32: SE floored at one
+packet's weight)."""
+import math
+
+import numpy as np
+import pytest
+
+from gpu_helpers import batch_se
+
+pytestmark = pytest.mark.gpu
+
+
+def _sphere_det(W):
+    sc = W.absorbing_sphere(mua=0.5, r=1.0, n=1.0)
+    sc["pad"] = 1.0
+    sc["detector"] = {"face": 5, "lo": [-1.0, -1.0], "hi": [1.0, 1.0], "dims": [8, 8]}
+    return sc
+
+
+def _slab_det(W):
+    sc = W.slab_scene(n_grid=32)
+    sc["detector"] = {"face": 5, "lo": [-0.5, -0.5], "hi": [0.5, 0.5], "dims": [40, 40]}
+    return sc
+
+
+def _oracle_images(orc, desc, seed, n, n_batches, voxel=False):
+    step = n // n_batches
+    imgs = [orc.run(desc, seed, step, first=b * step, voxel=voxel)["image"] for b in range(n_batches)]
+    return sum(imgs), batch_se(imgs)
+
+
+def _check_image(g, o, se, prec):
+    if prec == "f64":
+        zero = se == 0
+        assert np.all(np.abs(g[zero] - o[zero]) <= 1e-9 * max(o.max(), 1.0))
+        sel = ~zero
+        z = np.abs(g[sel] - o[sel]) / se[sel]
+    else:
+        z = np.abs(g - o) / np.maximum(se, 1.0)
+    print(f"pixels within 3 SE: {np.mean(z <= 3):.4f}")
+    assert np.mean(z <= 3.0) >= 0.995
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+@pytest.mark.parametrize("name", ["sphere", "slab"])
+def test_escape_image_matches_oracle(S, eng, orc, W, name, prec):
+    desc = _sphere_det(W) if name == "sphere" else _slab_det(W)
+    n, seed = 20000, 314
+    o, se = _oracle_images(orc, desc, seed, n, 10)
+    g = S.run(desc, seed, n, engine=eng, precision=prec)["image"]
+    assert o.sum() > 0
+    _check_image(g, o, se, prec)
+
+
+def _rect_solid_angle(x1, x2, y1, y2, h):
+    def F(x, y):
+        return math.atan(x * y / (h * math.sqrt(x * x + y * y + h * h)))
+    return F(x2, y2) - F(x1, y2) - F(x2, y1) + F(x1, y1)
+
+
+def test_escape_image_solid_angle_on_gpu(S, eng, W):
+    desc = _sphere_det(W)
+    N = 4_000_000
+    img = S.run(desc, 9, N, engine=eng, precision="f32", tally=False)["image"] / N
+    e = np.linspace(-1.0, 1.0, 9)
+    want = np.array([[_rect_solid_angle(e[i], e[i + 1], e[j], e[j + 1], 2.0) for i in range(8)]
+                     for j in range(8)]) / (4 * math.pi) * math.exp(-0.5)
+    assert np.all(np.abs(img - want) < 4 * np.sqrt(want * (1 - want) / N))
+
+
+def test_escape_image_of_a_pencil_beam_both_models(S, eng, W):
+    desc = W.beer_lambert_slab(2.0, 0.5, 1.5)
+    desc["detector"] = {"face": 4, "lo": [-1.0, -1.0], "hi": [1.0, 1.0], "dims": [4, 4]}
+    for geometry in ("sdf", "voxel"):
+        g = S.run(dict(desc, geometry=geometry), 3, 100000, engine=eng, precision="f32")
+        assert g["image"][2, 2] == pytest.approx(g["escaped_face"][4], rel=1e-12)
+        assert g["image"].sum() == pytest.approx(g["image"][2, 2], rel=1e-12)
+
+
+def test_escape_images_in_a_batch_equal_runs_alone(S, W):
+    import torch
+    descs = [_slab_det(W), _sphere_det(W), W.sphere_scene(n_grid=16), dict(_slab_det(W), geometry="voxel")]
+    seeds, ns = [1, 2, 3, 4], [20000, 30000, 10000, 5000]
+    e = S.Engine(0, precision="f64")
+    scenes = [S.Scene(d) for d in descs]
+    outs = S.launch_batch(e, scenes, seeds, ns)
+    torch.cuda.synchronize()
+    for sc, sd, n, b in zip(scenes, seeds, ns, outs):
+        alone = S.run(sc, sd, n, engine=e, precision="f64")
+        hb = b.host()
+        if "image" in alone:
+            np.testing.assert_allclose(hb["image"], alone["image"], rtol=1e-11, atol=1e-12)
+        np.testing.assert_allclose(hb["absorbed"], alone["absorbed"], rtol=1e-11)
+    e.close()
+
+
+def test_tally_free_run_gives_the_same_image(S, eng, W):
+    desc = _slab_det(W)
+    a = S.run(desc, 5, 50000, engine=eng, precision="f64")
+    b = S.run(desc, 5, 50000, engine=eng, precision="f64", tally=False)
+    assert b["fluence_raw"] is None
+    np.testing.assert_allclose(a["image"], b["image"], rtol=1e-11, atol=1e-12)

@@ -428,3 +428,49 @@ def test_torus_tube_chord(orc, W, offset, chord):
     assert abs(got - want) < 4 * math.sqrt(want * (1 - want) / N)
     # every packet enters the tube; those that leave it make a second crossing
     assert r["interfaces"] == N + r["escapes"]
+
+
+# ------------------------------------------------------- escape image ------
+
+def _rect_solid_angle(x1, x2, y1, y2, h):
+    """solid angle of the rectangle [x1, x2] x [y1, y2] in a plane at
+    distance h, seen from the foot point's normal (closed form)"""
+    def F(x, y):
+        return math.atan(x * y / (h * math.sqrt(x * x + y * y + h * h)))
+    return F(x2, y2) - F(x1, y2) - F(x2, y1) + F(x1, y1)
+
+
+def test_escape_image_solid_angle(orc, W):
+    # point source at the centre of an index-matched absorbing sphere: every
+    # escaping ray has crossed R of medium and then flies straight; the top
+    # face of the volume (pad 1 cm) lies h = R + 1 above the source
+    mua, R = 0.5, 1.0
+    sc = W.absorbing_sphere(mua=mua, r=R, n=1.0)
+    sc["pad"] = 1.0
+    h = R + 1.0
+    nd = 8
+    sc["detector"] = {"face": 5, "lo": [-1.0, -1.0], "hi": [1.0, 1.0], "dims": [nd, nd]}
+    N = 400000
+    r = orc.run(sc, seed=41, n=N)
+    img = r["image"] / N
+    edges = np.linspace(-1.0, 1.0, nd + 1)
+    want = np.array([[_rect_solid_angle(edges[i], edges[i + 1], edges[j], edges[j + 1], h)
+                      for i in range(nd)] for j in range(nd)]) / (4 * math.pi) * math.exp(-mua * R)
+    se = np.sqrt(want * (1 - want) / N)
+    assert np.all(np.abs(img - want) < 4 * se + 1e-12)
+    tot = want.sum()
+    assert abs(img.sum() - tot) < 4 * math.sqrt(tot * (1 - tot) / N)
+
+
+def test_escape_image_of_a_pencil_beam(orc, W):
+    # non-scattering slab: every transmitted packet stays on the beam axis
+    sc = W.beer_lambert_slab(2.0, 0.5, 1.5)
+    sc["detector"] = {"face": 4, "lo": [-1.0, -1.0], "hi": [1.0, 1.0], "dims": [4, 4]}
+    N = 20000
+    r = orc.run(sc, seed=42, n=N)
+    img = r["image"]
+    assert img[2, 2] == r["escaped_face"][4]
+    assert img.sum() == img[2, 2] > 0
+    # the same in the voxel model, whose grid is the slab
+    rv = orc.run(sc, seed=42, n=N, voxel=True)
+    assert rv["image"][2, 2] == rv["escaped_face"][4] and rv["image"].sum() == rv["image"][2, 2]
