@@ -337,6 +337,35 @@ def csg_scenes(smcrt, workloads, precision, n=10_000_000):
     return res
 
 
+def escape_images(smcrt, workloads, precision, n=10_000_000):
+    """Single-plane output (Sec. 5): diffuse reflectance image of the Table 1
+    420 nm slab (2 x 2 x 4 cm, uniform normal illumination of its top face)
+    on a 200 x 200 pixel detector over the top face, with no fluence grid and
+    with the 200 x 200 x 400 grid beside it; 1e7 photons, whole runs timed."""
+    import torch
+    slab = workloads.semi_infinite_slab(1.8, 82.0, half_xy=1.0, nz=400)
+    slab = workloads.with_grid(slab, [200, 200, 400], lo=[-1.0, -1.0, -4.0], hi=[1.0, 1.0, 0.0])
+    slab["source"] = {"kind": "rect", "c": [0.0, 0.0, 0.5 * slab["pad"]], "half": [1.0, 1.0], "u": [0.0, 0.0, -1.0]}
+    slab["detector"] = {"face": 5, "lo": [-1.0, -1.0], "hi": [1.0, 1.0], "dims": [200, 200]}
+    res = {}
+    for name, tally in (("image_only", False), ("image_and_fluence", True)):
+        eng = smcrt.Engine(0, precision=precision)
+        sc = smcrt.Scene(slab)
+        smcrt.launch(eng, sc, 99, 200_000, outputs=smcrt.Outputs(sc, tally=tally))  # warm-up
+        out = smcrt.Outputs(sc, tally=tally)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        smcrt.launch(eng, sc, 1, n, outputs=out)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t
+        h = out.host()
+        res[name] = {"packets": n, "packets_per_s": n / dt,
+                     "diffuse_reflectance": float(h["image"].sum()) / n,
+                     "top_face_escape": float(h["escaped_face"][5]) / n}
+        eng.close()
+    return res
+
+
 def copy_calibration(smcrt, desc, steps):
     import torch
     sc = smcrt.Scene(desc)
@@ -499,6 +528,7 @@ def main():
         result["paper_speed_tests"] = paper_speed_tests(smcrt, workloads, args.precision)
         result["csg_scenes"] = csg_scenes(smcrt, workloads, args.precision)
         result["batching"] = batching(smcrt, workloads, args.precision)
+        result["escape_images"] = escape_images(smcrt, workloads, args.precision)
     if args.serve_requests > 0 and not args.no_cpu:
         result["serving"] = serving(smcrt, workloads, args.serve_requests, args.serve_rate,
                                     args.serve_max_packets, args.precision)

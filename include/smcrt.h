@@ -137,7 +137,8 @@ smcrt_status smcrt_scene_set_accel(smcrt_scene* scene, int32_t region, const int
  * image spans [lo[0], hi[0]] x [lo[1], hi[1]] in the face's two other axes
  * in increasing order (x then y for a z face) with dims[0] x dims[1]
  * pixels, first axis fastest; dims of 0 remove the detector.  Errors:
- * SMCRT_E_INVALID for a face outside 0..5, lo >= hi or negative dims. */
+ * SMCRT_E_INVALID for a face outside 0..5, lo >= hi, negative dims or
+ * more than 2^31-1 pixels. */
 smcrt_status smcrt_scene_set_detector(smcrt_scene* scene, int face, const double lo[2], const double hi[2],
                                       const int32_t dims[2]);
 

@@ -365,9 +365,9 @@ static void detect(walker* wk, const packet* pk, int face, double plane) {
   const int a1 = ax == 0 ? 1 : 0, a2 = ax == 2 ? 1 : 2;
   double x = (q[a1] - s->det_lo[0]) / (s->det_hi[0] - s->det_lo[0]) * s->det_dims[0];
   double y = (q[a2] - s->det_lo[1]) / (s->det_hi[1] - s->det_lo[1]) * s->det_dims[1];
-  if (!(x >= 0.0 && y >= 0.0)) return;
+  /* bounds in floating point, before any conversion (NaN fails too) */
+  if (!(x >= 0.0 && y >= 0.0 && x < s->det_dims[0] && y < s->det_dims[1])) return;
   int i = (int)floor(x), j = (int)floor(y);
-  if (i >= s->det_dims[0] || j >= s->det_dims[1]) return;
   wk->img[(size_t)i + (size_t)s->det_dims[0] * (size_t)j] += pk->w;
 }
 

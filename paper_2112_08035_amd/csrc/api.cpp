@@ -240,7 +240,6 @@ extern "C" smcrt_status smcrt_scene_set_accel(smcrt_scene* s, int32_t region, co
   return SMCRT_OK;
 }
 
-// conservative box of a primitive
 extern "C" smcrt_status smcrt_scene_set_detector(smcrt_scene* s, int face, const double lo[2], const double hi[2],
                                                  const int32_t dims[2]) {
   if (!s || !lo || !hi || !dims) return fail(SMCRT_E_INVALID, "set_detector: NULL argument");
@@ -251,6 +250,7 @@ extern "C" smcrt_status smcrt_scene_set_detector(smcrt_scene* s, int face, const
     return SMCRT_OK;
   }
   if (face < 0 || face > 5) return fail(SMCRT_E_INVALID, "set_detector: face %d outside 0..5", face);
+  if ((double)dims[0] * dims[1] > 2147483647.0) return fail(SMCRT_E_INVALID, "set_detector: more than 2^31-1 pixels");
   for (int i = 0; i < 2; ++i)
     if (!(std::isfinite(lo[i]) && std::isfinite(hi[i]) && lo[i] < hi[i]))
       return fail(SMCRT_E_INVALID, "set_detector: need finite lo < hi");
@@ -272,6 +272,7 @@ extern "C" smcrt_status smcrt_scene_set_geometry(smcrt_scene* s, int mode) {
   return SMCRT_OK;
 }
 
+// conservative box of a primitive
 static void prim_box(const HostPrim& p, double lo[3], double hi[3]) {
   for (int i = 0; i < 3; ++i) {
     switch (p.kind) {

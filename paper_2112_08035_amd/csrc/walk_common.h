@@ -559,26 +559,35 @@ __device__ __forceinline__ void flush_tally(JobRef a, Packet<T>& pk, Lane& ln) {
 // interest).  A packet leaving through the detector face adds its weight to
 // the pixel holding the point where its straight path crosses the face's
 // plane: traced back along u from its position when that lies beyond the
-// plane and the packet moves outward, else its position.
+// plane and the packet moves outward, else its position.  The axis is a
+// template argument: selecting a packet coordinate by a run-time axis lets
+// the compiler index the packet in memory, which moves it to scratch.
+template <int AX, typename T>
+__device__ __forceinline__ void detect_on(JobRef a, ScP sc, V3<T> p, V3<T> u, double w, T sg, T plane) {
+  const T pa = AX == 0 ? p.x : (AX == 1 ? p.y : p.z);
+  const T ua = AX == 0 ? u.x : (AX == 1 ? u.y : u.z);
+  const T over = (pa - plane) * sg, out = ua * sg;
+  if (over > T(0) && out > T(0)) p = p - (over / out) * u;
+  const T c1 = AX == 0 ? p.y : p.x, c2 = AX == 2 ? p.y : p.z;
+  const T x = (c1 - (T)sc->det_lo[0]) / ((T)sc->det_hi[0] - (T)sc->det_lo[0]) * (T)sc->det_dims[0];
+  const T y = (c2 - (T)sc->det_lo[1]) / ((T)sc->det_hi[1] - (T)sc->det_lo[1]) * (T)sc->det_dims[1];
+  // bounds in floating point, before any conversion (NaN fails too)
+  if (!(x >= T(0) && y >= T(0) && x < (T)sc->det_dims[0] && y < (T)sc->det_dims[1])) return;
+  const int i = (int)floor(x), j = (int)floor(y);
+  grid_add(a.detector, i + sc->det_dims[0] * j, w);
+}
+
 template <typename T>
 __device__ __forceinline__ void detect(JobRef a, const Packet<T>& pk, int face, T plane) {
   if (a.detector == nullptr) return;
   ScP sc = kptr(a.sc);
   if (face != sc->det_face) return;
-  const int ax = face >> 1;
   const T sg = (face & 1) ? T(1) : T(-1);
-  const T pa = ax == 0 ? pk.p.x : (ax == 1 ? pk.p.y : pk.p.z);
-  const T ua = ax == 0 ? pk.u.x : (ax == 1 ? pk.u.y : pk.u.z);
-  V3<T> q = pk.p;
-  const T over = (pa - plane) * sg, out = ua * sg;
-  if (over > T(0) && out > T(0)) q = pk.p - (over / out) * pk.u;
-  const T c1 = ax == 0 ? q.y : q.x, c2 = ax == 2 ? q.y : q.z;
-  const T x = (c1 - (T)sc->det_lo[0]) / ((T)sc->det_hi[0] - (T)sc->det_lo[0]) * (T)sc->det_dims[0];
-  const T y = (c2 - (T)sc->det_lo[1]) / ((T)sc->det_hi[1] - (T)sc->det_lo[1]) * (T)sc->det_dims[1];
-  if (!(x >= T(0) && y >= T(0))) return;
-  const int i = (int)floor(x), j = (int)floor(y);
-  if (i >= sc->det_dims[0] || j >= sc->det_dims[1]) return;
-  grid_add(a.detector, i + sc->det_dims[0] * j, pk.w);
+  switch (face >> 1) {
+    case 0: detect_on<0>(a, sc, pk.p, pk.u, pk.w, sg, plane); break;
+    case 1: detect_on<1>(a, sc, pk.p, pk.u, pk.w, sg, plane); break;
+    default: detect_on<2>(a, sc, pk.p, pk.u, pk.w, sg, plane); break;
+  }
 }
 
 __device__ __forceinline__ void add_absorbed(LdsTallies& L, Lane& ln, int r, double dA) {

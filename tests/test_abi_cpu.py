@@ -236,3 +236,12 @@ def test_detector_validation(S):
         S.smcrt_scene_set_detector(h, 9, [0, 0], [1, 1], [0, 0])   # dims 0 remove it (face ignored)
     finally:
         S.smcrt_scene_destroy(h)
+
+
+def test_detector_pixel_limit(S):
+    h = S.smcrt_scene_create(1.0, 1e-5, 1e-4)
+    try:
+        with pytest.raises(S.SmcrtError, match="2\\^31"):
+            S.smcrt_scene_set_detector(h, 5, [0, 0], [1, 1], [65536, 65536])
+    finally:
+        S.smcrt_scene_destroy(h)
