@@ -40,7 +40,8 @@ class Scene(C.Structure):
                 ("w_threshold", C.c_double), ("m_survive", C.c_int32), ("max_steps", C.c_int32),
                 ("max_events", C.c_int64),
                 ("det_face", C.c_int32), ("det_dims", C.c_int32 * 2),
-                ("det_lo", C.c_double * 2), ("det_hi", C.c_double * 2)]
+                ("det_lo", C.c_double * 2), ("det_hi", C.c_double * 2),
+                ("relax", C.c_double)]
 
 
 class Tallies(C.Structure):
@@ -217,6 +218,7 @@ class CScene:
         s.m_survive = int(ro["m"])
         s.max_steps = int(scene["max_steps"])
         s.max_events = int(scene["max_events"])
+        s.relax = float(scene.get("relax", 1.0))
         det = scene.get("detector")
         if det:
             s.det_face = int(det["face"])

@@ -570,8 +570,14 @@ static void walk(walker* wk, uint64_t seed, uint64_t pid) {
     /* one event: sphere-trace until interaction (Sec. 2.3) */
     int32_t steps = 0;
     int state = GO_ON;
+    /* the previous sphere-tracing step of this segment: surface distance
+     * at its start pd (< 0: none yet), its length pl; a relaxed one waits
+     * for its check (pending) with its start point q and the depth there */
+    double q[3] = {0.0, 0.0, 0.0}, pd = -1.0, pl = 0.0, tau_q = 0.0;
+    int pending = 0;
     while (state == GO_ON) {
       if (++steps > s->max_steps || (int64_t)pk.k > s->max_events) {
+        if (pending) wk->t->voxel_segments += (uint64_t)orc_tally_segment(s, q, pk.p, pk.w, wk->f);
         wk->t->stalled += pk.w;
         wk->t->stalls++;
         record(wk, &pk, ORC_EV_STALL);
@@ -580,6 +586,23 @@ static void walk(walker* wk, uint64_t seed, uint64_t pid) {
       wk->t->steps++;
       double dmin = ORC_INF;
       for (int r = 0; r < s->n_regions; ++r) dmin = mind(dmin, fabs(orc_region_sdf(s, r, pk.p)));
+      if (pending) {
+        /* check of an over-relaxed step (enhanced sphere tracing, the
+         * remedy for slow grazing steps named in Sec. 5): the open balls of
+         * radius pd around q and dmin around its end hold no surface, so if
+         * together they cover the step (with a margin of delta against
+         * rounding) it crossed none.  Any crossing forces pd + dmin <= pl.
+         * Otherwise fall back to the plain step of pd from q. */
+        const int keep = pd + dmin >= pl + s->delta;
+        if (!keep) {
+          for (int i = 0; i < 3; ++i) pk.p[i] = q[i] + pd * pk.u[i];
+          pk.tau = tau_q - (reg_mua(s, pk.region) + reg_mus(s, pk.region)) * pd;
+          pl = pd;
+        }
+        wk->t->voxel_segments += (uint64_t)orc_tally_segment(s, q, pk.p, pk.w, wk->f);
+        pending = 0;
+        if (!keep) continue; /* the next step starts from the plain step's end */
+      }
       if (orc_box_sdf(s->bb_lo, s->bb_hi, pk.p) > 0.0) { /* left the volume */
         double e[3], best = -ORC_INF;
         int face = 0;
@@ -603,10 +626,28 @@ static void walk(walker* wk, uint64_t seed, uint64_t pid) {
       } else if (dmin < s->delta) { /* on a boundary */
         uint32_t k_before = pk.k;
         state = surface(wk, &pk, s_rem, seed, pid);
-        if (pk.k != k_before) steps = 0; /* an interface event starts a new event */
+        if (pk.k != k_before) { /* an interface event starts a new event */
+          steps = 0;
+          pd = -1.0;
+        }
+      } else if (s->relax > 1.0 && pd >= 0.0 && pd - dmin <= (2.0 - s->relax) / s->relax * pl &&
+                 s->relax * dmin < s_rem) {
+        /* over-relaxed step, taken when the previous step saw the surface
+         * distance fall slowly enough that, were the surface a plane, the
+         * relaxed step would pass its check; its path is credited once the
+         * check passes */
+        for (int i = 0; i < 3; ++i) q[i] = pk.p[i];
+        pd = dmin;
+        pl = s->relax * dmin;
+        tau_q = pk.tau;
+        for (int i = 0; i < 3; ++i) pk.p[i] += pl * pk.u[i];
+        pk.tau -= mut * pl;
+        pending = 1;
       } else { /* sphere-tracing step of the full distance */
         move(wk, &pk, dmin);
         pk.tau -= mut * dmin;
+        pd = dmin;
+        pl = dmin;
       }
     }
     if (!interact(wk, &pk, seed, pid)) return;
@@ -618,6 +659,7 @@ static void walk(walker* wk, uint64_t seed, uint64_t pid) {
 static int check_scene(const orc_scene* s) {
   if (!s || s->n_regions < 1 || s->n_prims < 1 || !s->prims || !s->regions) return -1;
   if (!(s->delta > 0.0) || s->m_survive < 1 || s->max_steps < 1) return -1;
+  if (!(s->relax >= 1.0 && s->relax < 2.0)) return -1;
   for (int r = 0; r < s->n_regions; ++r) {
     const orc_region* rg = &s->regions[r];
     if (rg->first_prim < 0 || rg->n_prims < 1 || rg->first_prim + rg->n_prims > s->n_prims) return -1;

@@ -65,6 +65,9 @@ typedef struct {
   int32_t det_face;
   int32_t det_dims[2];
   double det_lo[2], det_hi[2];
+  /* over-relaxation factor of sphere-tracing steps in [1, 2); 1 = plain
+   * steps of the nearest-surface distance */
+  double relax;
 } orc_scene;
 
 typedef struct {
