@@ -8,6 +8,7 @@ the oracle's own C structs; it shares no code with the GPU path.
 from __future__ import annotations
 
 import ctypes as C
+import math
 import os
 
 import numpy as np
@@ -21,7 +22,11 @@ EVENT_TYPES = ["EMIT", "SCATTER", "ABSORB", "KILL", "REFLECT", "REFRACT", "CROSS
 
 
 class Prim(C.Structure):
-    _fields_ = [("kind", C.c_int32), ("pad", C.c_int32), ("p", C.c_double * 8)]
+    _fields_ = [("kind", C.c_int32), ("flags", C.c_int32), ("p", C.c_double * 8),
+                ("rot", C.c_double * 9), ("t", C.c_double * 3), ("s", C.c_double),
+                ("round_r", C.c_double), ("onion_t", C.c_double),
+                ("twist_k", C.c_double), ("twist_rho", C.c_double), ("twist_zlo", C.c_double),
+                ("twist_zhi", C.c_double)]
 
 
 class Region(C.Structure):
@@ -110,6 +115,19 @@ def _d3(v):
     return (C.c_double * 3)(*[float(x) for x in v])
 
 
+def twist_cylinder(p):
+    """Bounding cylinder about the local z axis of a twisted primitive (its
+    local box grown by rounding and shell): radius 1.001 x the largest
+    distance of that box from the axis, z range the box's grown by 0.1 % of
+    its length at each end."""
+    lo, hi = local_aabb(p)
+    g = float(p.get("round", 0.0)) + float(p.get("onion", 0.0))
+    lo, hi = lo - g, hi + g
+    rho = max(math.hypot(x, y) for x in (lo[0], hi[0]) for y in (lo[1], hi[1]))
+    m = 1e-3 * (hi[2] - lo[2])
+    return 1.001 * rho, lo[2] - m, hi[2] + m
+
+
 def prim_struct(p):
     s = Prim()
     s.kind = PRIM_KINDS[p["kind"]]
@@ -123,14 +141,49 @@ def prim_struct(p):
         vals = list(p["a"]) + list(p["b"]) + [p["r"]]
     for i, v in enumerate(vals):
         s.p[i] = float(v)
+    flags = 0
+    xf = p.get("transform")
+    R, t, sc = np.eye(3), np.zeros(3), 1.0
+    if xf:
+        flags |= 1
+        R, t, sc = np.asarray(xf["R"], float).reshape(3, 3), np.asarray(xf["t"], float), float(xf["s"])
+    s.rot = (C.c_double * 9)(*R.ravel())
+    s.t = (C.c_double * 3)(*t)
+    s.s = sc
+    s.round_r = float(p.get("round", 0.0))
+    s.onion_t = float(p.get("onion", 0.0))
+    if p.get("twist", 0.0) != 0.0:
+        flags |= 2
+        s.twist_k = float(p["twist"])
+        s.twist_rho, s.twist_zlo, s.twist_zhi = twist_cylinder(p)
+    s.flags = flags
     return s
 
 
 def prim_aabb(p):
-    """Conservative box of a primitive: sphere c -/+ r, box c -/+ half,
-    capsule and cylinder the end points' box grown by r, torus with unit
-    axis e: c -/+ (R sqrt(1 - e_i^2) + r) per axis (the ring's box grown by
-    the tube radius)."""
+    """Conservative world box of a primitive: its local box (grown by
+    rounding and shell, or the twist's bounding cylinder's box) with the 8
+    corners placed in the world."""
+    lo, hi = local_aabb(p)
+    g = float(p.get("round", 0.0)) + float(p.get("onion", 0.0))
+    lo, hi = lo - g, hi + g
+    if p.get("twist", 0.0) != 0.0:
+        rho, zlo, zhi = twist_cylinder(p)
+        lo, hi = np.array([-rho, -rho, zlo]), np.array([rho, rho, zhi])
+    xf = p.get("transform")
+    if not xf:
+        return lo, hi
+    R, t, sc = np.asarray(xf["R"], float).reshape(3, 3), np.asarray(xf["t"], float), float(xf["s"])
+    corners = np.array([[x, y, z] for x in (lo[0], hi[0]) for y in (lo[1], hi[1]) for z in (lo[2], hi[2])])
+    w = sc * corners @ R.T + t
+    return w.min(axis=0), w.max(axis=0)
+
+
+def local_aabb(p):
+    """Conservative box of a primitive in its own frame: sphere c -/+ r, box
+    c -/+ half, capsule and cylinder the end points' box grown by r, torus
+    with unit axis e: c -/+ (R sqrt(1 - e_i^2) + r) per axis (the ring's
+    box grown by the tube radius)."""
     if p["kind"] == "sphere":
         c, r = np.array(p["c"], float), float(p["r"])
         return c - r, c + r

@@ -86,8 +86,9 @@ static double mind(double a, double b) { return a < b ? a : b; }
 
 /* --------------------------------------------------------------- SDFs --- */
 
-/* Exact Euclidean distance functions, positive outside (Sec. 2.2, Eq. 2). */
-double orc_prim_sdf(const orc_prim* pr, const double p[3]) {
+/* Exact Euclidean distance functions, positive outside (Sec. 2.2, Eq. 2),
+ * of the primitive shapes in their own frame. */
+static double shape_sdf(const orc_prim* pr, const double p[3]) {
   const double* q = pr->p;
   switch (pr->kind) {
     case ORC_SPHERE: { /* Eq. 3: |p - c| - r */
@@ -136,6 +137,44 @@ double orc_prim_sdf(const orc_prim* pr, const double p[3]) {
     default:
       return ORC_INF;
   }
+}
+
+/* distance from p to the solid capped cylinder about the z axis, radius rho,
+ * z in [zlo, zhi] (positive outside) */
+static double zcyl_sdf(const double p[3], double rho, double zlo, double zhi) {
+  double q1 = sqrt(p[0] * p[0] + p[1] * p[1]) - rho;
+  double q2 = fabs(p[2] - 0.5 * (zlo + zhi)) - 0.5 * (zhi - zlo);
+  double o1 = maxd(q1, 0.0), o2 = maxd(q2, 0.0);
+  return mind(maxd(q1, q2), 0.0) + sqrt(o1 * o1 + o2 * o2);
+}
+
+/* Sec. 2.2: SDFs are translated, rotated, scaled and twisted.  A rigid
+ * motion with uniform scale s keeps a distance exact (times s); rounding
+ * and an onion shell keep it exact; a twist keeps only the sign and, inside
+ * a convex set whose points are within rho of the axis, a Lipschitz bound
+ * of sqrt(1 + (k rho)^2), by which the distance is divided there. */
+double orc_prim_sdf(const orc_prim* pr, const double p[3]) {
+  double q[3] = {p[0], p[1], p[2]};
+  if (pr->flags & 1) { /* local = R^T (p - t) / s */
+    const double* R = pr->rot;
+    double d[3] = {p[0] - pr->t[0], p[1] - pr->t[1], p[2] - pr->t[2]};
+    for (int i = 0; i < 3; ++i) q[i] = (R[i] * d[0] + R[3 + i] * d[1] + R[6 + i] * d[2]) / pr->s;
+  }
+  double d;
+  if (pr->flags & 2) {
+    d = zcyl_sdf(q, pr->twist_rho, pr->twist_zlo, pr->twist_zhi);
+    if (d <= 0.0) { /* inside the bounding cylinder: untwist, rotating by -k z about z */
+      double a = -pr->twist_k * q[2], c = cos(a), sn = sin(a);
+      double u[3] = {c * q[0] - sn * q[1], sn * q[0] + c * q[1], q[2]};
+      d = shape_sdf(pr, u) - pr->round_r;
+      if (pr->onion_t > 0.0) d = fabs(d) - pr->onion_t;
+      d /= sqrt(1.0 + pr->twist_k * pr->twist_k * pr->twist_rho * pr->twist_rho);
+    }
+  } else {
+    d = shape_sdf(pr, q) - pr->round_r;
+    if (pr->onion_t > 0.0) d = fabs(d) - pr->onion_t;
+  }
+  return (pr->flags & 1) ? pr->s * d : d;
 }
 
 /* polynomial smooth minimum of radius k (Sec. 2.2 gallery, panel e):
@@ -191,12 +230,13 @@ void orc_region_normal(const orc_scene* s, int r, const double p[3], double h, d
 /* signed distance of the simulation volume (Sec. 2.3: positive = outside) */
 double orc_box_sdf(const double lo[3], const double hi[3], const double p[3]) {
   orc_prim b;
+  memset(&b, 0, sizeof(b));
   b.kind = ORC_BOX;
   for (int i = 0; i < 3; ++i) {
     b.p[i] = 0.5 * (lo[i] + hi[i]);
     b.p[3 + i] = 0.5 * (hi[i] - lo[i]);
   }
-  return orc_prim_sdf(&b, p);
+  return shape_sdf(&b, p);
 }
 
 /* ------------------------------------------------------------ physics --- */

@@ -36,7 +36,24 @@ enum {
 
 /* sphere: c[3], r | box: c[3], half[3] | capsule and capped cylinder: a[3], b[3], r
  * | torus: c[3], axis[3] (any length), R (ring radius), r (tube radius) */
-typedef struct { int32_t kind; int32_t pad; double p[8]; } orc_prim;
+/* A primitive is defined in its own frame by p[] and placed in the world by
+ * x_world = s * R x_local + t (rotation R, uniform scale s > 0).  Its
+ * distance is modified, in the local frame and in this order, by rounding
+ * (minus round_r), an onion shell (|d| - onion_t) and a twist about the
+ * local z axis (angle twist_k * z).  The twist bends distances, so inside
+ * the bounding cylinder (radius twist_rho, z in [twist_zlo, twist_zhi]) of
+ * the rounded shell the distance is divided by the twist's Lipschitz bound
+ * there, sqrt(1 + (twist_k twist_rho)^2); outside it, the distance to that
+ * cylinder is used.  flags: bit 0 transform, bit 1 twist. */
+typedef struct {
+  int32_t kind;
+  int32_t flags;
+  double p[8];
+  double rot[9];                  /* R, row-major (local -> world) */
+  double t[3], s;
+  double round_r, onion_t;
+  double twist_k, twist_rho, twist_zlo, twist_zhi;
+} orc_prim;
 
 typedef struct {
   int32_t first_prim, n_prims, op, pad;
