@@ -366,6 +366,36 @@ def escape_images(smcrt, workloads, precision, n=10_000_000):
     return res
 
 
+def relaxation(smcrt, workloads, precision, omega=1.9):
+    """Over-relaxed sphere tracing (Sec. 5) against plain steps on the same
+    packets: packets/s and sphere-tracing steps per packet of the layered
+    slab (200^3 grid, 2e6 packets), the vessel cylinder (256^3, 2e6), the
+    glass sphere and the bottle (64^3, 4e6 each)."""
+    import torch
+    res = {}
+    for name, n_grid, n in (("slab", 200, 2_000_000), ("cylinder", 256, 2_000_000),
+                            ("glass_sphere", 64, 4_000_000), ("bottle", 64, 4_000_000)):
+        row = {"packets": n}
+        for mode, w in (("plain", 1.0), ("relaxed", omega)):
+            desc = dict(workloads.WORKLOADS[name](n_grid=n_grid), relax=w)
+            eng = smcrt.Engine(0, precision=precision)
+            sc = smcrt.Scene(desc)
+            smcrt.launch(eng, sc, 77, min(n, 200_000), outputs=smcrt.Outputs(sc))  # warm-up
+            out = smcrt.Outputs(sc)
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            smcrt.launch(eng, sc, 1, n, outputs=out)
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t
+            h = out.host()
+            row[mode] = {"packets_per_s": n / dt, "steps_per_packet": h["steps"] / n}
+            eng.close()
+        row["omega"] = omega
+        row["speedup"] = row["relaxed"]["packets_per_s"] / row["plain"]["packets_per_s"]
+        res[name] = row
+    return res
+
+
 def copy_calibration(smcrt, desc, steps):
     import torch
     sc = smcrt.Scene(desc)
@@ -529,6 +559,7 @@ def main():
         result["csg_scenes"] = csg_scenes(smcrt, workloads, args.precision)
         result["batching"] = batching(smcrt, workloads, args.precision)
         result["escape_images"] = escape_images(smcrt, workloads, args.precision)
+        result["relaxation"] = relaxation(smcrt, workloads, args.precision)
     if args.serve_requests > 0 and not args.no_cpu:
         result["serving"] = serving(smcrt, workloads, args.serve_requests, args.serve_rate,
                                     args.serve_max_packets, args.precision)

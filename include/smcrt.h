@@ -119,6 +119,21 @@ smcrt_status smcrt_scene_set_roulette(smcrt_scene* scene, double w_threshold, in
  * tallied as stalled (defaults 100000 and 1000000). */
 smcrt_status smcrt_scene_set_limits(smcrt_scene* scene, int32_t max_steps, int64_t max_events);
 
+/* Over-relaxed sphere tracing (Sec. 5 names faster marching as the remedy
+ * for the many small steps of paths along surfaces).  With omega > 1 a step
+ * may move omega times the nearest-surface distance d.  It is taken when the
+ * previous step of the same straight segment saw the distance fall by at
+ * most (2 - omega)/omega of its length, which is when such a step toward a
+ * plane would pass the check.  The next evaluation then checks it: the free
+ * balls of radius d at its start and d' at its end must cover it, with
+ * d + d' >= step + delta.  A step that fails goes back to the plain step of
+ * d, so no surface is ever crossed unseen.  Events, tallies and fluence are
+ * those of plain marching, up to rounding and the position of grazing
+ * interface hits (within delta); only the step count changes.  omega in
+ * [1, 2), default 1 (plain steps).  Errors: SMCRT_E_INVALID outside that
+ * range. */
+smcrt_status smcrt_scene_set_relaxation(smcrt_scene* scene, double omega);
+
 /* Uniform-grid acceleration of one union region (Sec. 5 proposes a
  * space-partitioning structure for large SDF collections).  The grid is the
  * box of the region's primitives grown by a margin of one cell, cut into

@@ -58,6 +58,7 @@ struct HostRegion {
 
 struct smcrt_scene {
   double n_ambient = 1.0, delta = 1e-5, pad = 1e-4;
+  double relax = 1.0;  // over-relaxation factor of sphere-tracing steps
   std::vector<HostPrim> prims;
   std::vector<HostRegion> regions;
   bool has_source = false;
@@ -218,6 +219,14 @@ extern "C" smcrt_status smcrt_scene_set_limits(smcrt_scene* s, int32_t max_steps
   if (max_events > 0xFFFFFFF0LL) return fail(SMCRT_E_INVALID, "set_limits: max_events must fit the 32-bit event counter");
   s->max_steps = max_steps;
   s->max_events = max_events;
+  s->dirty = true;
+  return SMCRT_OK;
+}
+
+extern "C" smcrt_status smcrt_scene_set_relaxation(smcrt_scene* s, double omega) {
+  if (!s) return fail(SMCRT_E_INVALID, "set_relaxation: NULL scene");
+  if (!(omega >= 1.0 && omega < 2.0)) return fail(SMCRT_E_INVALID, "set_relaxation: omega must be in [1, 2)");
+  s->relax = omega;
   s->dirty = true;
   return SMCRT_OK;
 }
@@ -493,6 +502,10 @@ static smcrt_status pack(smcrt_scene* s) {
   fill_region(h->reg[s->regions.size()], 0.0, 0.0, 0.0, s->n_ambient, 0.0, kUnion, 0, 0);
   h->delta = s->delta;
   h->deltaf = (float)s->delta;
+  h->relax = s->relax;
+  h->relax_k = (2.0 - s->relax) / s->relax;
+  h->relaxf = (float)s->relax;
+  h->relax_kf = (float)h->relax_k;
   h->h_normal = 1e-2 * s->delta;
   h->snap_cos = 0.1;
   h->offset = 2.0 * s->delta;

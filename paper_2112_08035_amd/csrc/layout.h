@@ -83,7 +83,11 @@ struct SceneHeader {
   int32_t det_face, det_dims[2], pad_det;
   double det_lo[2], det_hi[2];
   double w_threshold, m_d, inv_m;
-  float deltaf, pad1;
+  float deltaf, relaxf;
+  // over-relaxed sphere tracing: factor omega and the bound (2 - omega)/omega
+  // on the relative fall of the surface distance that allows a relaxed step
+  double relax, relax_k;
+  float relax_kf, pad1;
   Region reg[kMaxRegions + 1];
   Accel acc;
   uint64_t prim_offset_d, prim_offset_f;  // byte offsets of the tables in the blob

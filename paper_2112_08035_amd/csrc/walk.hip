@@ -95,6 +95,7 @@ __device__ void surface(JobRef a, Packet<T>& pk, Lane& ln, LdsTallies& L) {
   flush_tally<T>(a, pk, ln);
   pk.k += 1;
   pk.steps = 0;
+  pk.pd = T(-1);
   atomicAdd(&L.cnt[kCInterfaces], 1ull);
   pk.tau = tau;
   pk.state = kTransport;
@@ -140,7 +141,7 @@ __device__ void surface(JobRef a, Packet<T>& pk, Lane& ln, LdsTallies& L) {
 // voxel walk of the voxelised comparison model; the launch takes only the
 // jobs of that model.
 template <typename T, bool TRACE, int GEOM>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 5 : 3)))
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 4 : 3)))
 walk_kernel(const WalkArgs* __restrict__ job_table, BatchArgs B) {
   const SMCRT_K WalkArgs* jobs = kptr(job_table);
   __shared__ LdsTallies Lw[4];
@@ -251,7 +252,24 @@ walk_kernel(const WalkArgs* __restrict__ job_table, BatchArgs B) {
           for (int r = 0; r < nr; ++r) dmin = tmin(dmin, tabs(region_dist<T>(a, r, pk.p)));
           int face;
           const T dbb = volume_sdf<T>(sc, pk.p, &face);
-          if (dbb > T(0)) {  // outside the simulation volume
+          bool rejected = false;
+          if (pk.pl < T(0)) {
+            // check of an over-relaxed step (Sec. 5): the open balls of
+            // radius pd at its start and dmin at its end hold no surface;
+            // unless they cover the step with a margin of delta it goes back
+            // to the plain step of pd, and this evaluation is spent
+            const T len = -pk.pl;
+            if (pk.pd + dmin >= len + delta) {
+              pk.pl = len;
+            } else {
+              rejected = true;
+              step_along(pk, pk.pd - len);
+              pk.pl = pk.pd;
+            }
+          }
+          if (rejected) {
+            // the next evaluation starts from the plain step's end
+          } else if (dbb > T(0)) {  // outside the simulation volume
             atomicAdd(&L.escaped[face], pk.w);
             atomicAdd(&L.cnt[kCEscapes], 1ull);
             detect<T>(a, pk, face, Tab<T>::bb_c(sc, face >> 1) + ((face & 1) ? Tab<T>::bb_h(sc, face >> 1) : -Tab<T>::bb_h(sc, face >> 1)));
@@ -265,19 +283,15 @@ walk_kernel(const WalkArgs* __restrict__ job_table, BatchArgs B) {
               pk.state = kInteract;
             } else if (dmin < delta) {
               pk.state = kSurface;
-            } else if constexpr (sizeof(T) == 4) {
-              // charge the distance the rounded position really moved: for
-              // steps far below the position's ulp-scaled size (grazing
-              // paths far from the origin) it differs from dmin, and
-              // charging dmin would let depth and position drift apart
-              const V3<T> p0 = pk.p;
-              pk.p = pk.p + dmin * pk.u;
-              const T moved = dot(pk.p - p0, pk.u);
-              pk.pend += moved;
-              pk.tau -= (double)pk.mut * (double)moved;
             } else {
-              advance(pk, dmin);
-              pk.tau -= (double)pk.mut * (double)dmin;
+              // a step of dmin, or an over-relaxed one of omega * dmin when
+              // the previous step saw the distance fall slowly enough that a
+              // plane ahead would let it pass its check
+              const T om = Tab<T>::relax(sc);
+              const bool rel = om > T(1) && pk.pd >= T(0) && pk.pd - dmin <= Tab<T>::relax_k(sc) * pk.pl && om * dmin < s;
+              const T moved = step_along(pk, rel ? om * dmin : dmin);
+              pk.pd = dmin;
+              pk.pl = rel ? -moved : moved;
             }
           }
         }

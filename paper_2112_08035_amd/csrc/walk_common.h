@@ -124,6 +124,8 @@ struct Tab<float> {
   static __device__ __forceinline__ float g_lo(ScP s, int i) { return s->g_lof[i]; }
   static __device__ __forceinline__ float g_hi(ScP s, int i) { return s->g_hif[i]; }
   static __device__ __forceinline__ float delta(ScP s) { return s->deltaf; }
+  static __device__ __forceinline__ float relax(ScP s) { return s->relaxf; }
+  static __device__ __forceinline__ float relax_k(ScP s) { return s->relax_kf; }
   static __device__ __forceinline__ V3<float> acc_lo(const SMCRT_K Accel& A) { return {A.lof[0], A.lof[1], A.lof[2]}; }
   static __device__ __forceinline__ V3<float> acc_inv(const SMCRT_K Accel& A) { return {A.inv_cellf[0], A.inv_cellf[1], A.inv_cellf[2]}; }
   static __device__ __forceinline__ V3<float> acc_blo(const SMCRT_K Accel& A) { return {A.box_lof[0], A.box_lof[1], A.box_lof[2]}; }
@@ -147,6 +149,8 @@ struct Tab<double> {
   static __device__ __forceinline__ double g_lo(ScP s, int i) { return s->g_lo[i]; }
   static __device__ __forceinline__ double g_hi(ScP s, int i) { return s->g_hi[i]; }
   static __device__ __forceinline__ double delta(ScP s) { return s->delta; }
+  static __device__ __forceinline__ double relax(ScP s) { return s->relax; }
+  static __device__ __forceinline__ double relax_k(ScP s) { return s->relax_k; }
   static __device__ __forceinline__ V3<double> acc_lo(const SMCRT_K Accel& A) { return {A.lo[0], A.lo[1], A.lo[2]}; }
   static __device__ __forceinline__ V3<double> acc_inv(const SMCRT_K Accel& A) { return {A.inv_cell[0], A.inv_cell[1], A.inv_cell[2]}; }
   static __device__ __forceinline__ V3<double> acc_blo(const SMCRT_K Accel& A) { return {A.box_lo[0], A.box_lo[1], A.box_lo[2]}; }
@@ -508,6 +512,10 @@ struct Packet {
   int state;
   int steps;        // sphere-tracing steps in the current event
   T pend;           // straight path along u since the last tally, ending at p
+  // previous sphere-tracing step of the current straight segment: surface
+  // distance at its start (< 0: none yet) and its length, negated while an
+  // over-relaxed step waits for its check at the next evaluation
+  T pd, pl;
 };
 
 template <typename T>
@@ -546,6 +554,28 @@ template <typename T>
 __device__ __forceinline__ void advance(Packet<T>& pk, T len) {
   pk.p = pk.p + len * pk.u;
   pk.pend += len;
+}
+
+// Sphere-tracing move of len along u (negative: back along u), charged to
+// the pending path and the optical depth.  In FP32 the charge is the
+// distance the rounded position really moved along u: for steps far below
+// the position's ulp-scaled size (grazing paths far from the origin) it
+// differs from len, and charging len would let depth and position drift
+// apart.  Returns the charged distance.
+template <typename T>
+__device__ __forceinline__ T step_along(Packet<T>& pk, T len) {
+  if constexpr (sizeof(T) == 4) {
+    const V3<T> p0 = pk.p;
+    pk.p = pk.p + len * pk.u;
+    const T moved = dot(pk.p - p0, pk.u);
+    pk.pend += moved;
+    pk.tau -= (double)pk.mut * (double)moved;
+    return moved;
+  } else {
+    advance(pk, len);
+    pk.tau -= (double)pk.mut * (double)len;
+    return len;
+  }
 }
 
 template <typename T>
@@ -634,6 +664,8 @@ __device__ void emit(JobRef a, Packet<T>& pk, Lane& ln, LdsTallies& L) {
   pk.tau = (double)(-tlog(x3));
   pk.k = 0;
   pk.steps = 0;
+  pk.pd = T(-1);
+  pk.pl = T(0);
   pk.pend = T(0);
   pk.state = kTransport;
   set_region(sc, pk, region_of<T>(a, p));
@@ -710,6 +742,7 @@ __device__ bool interact(JobRef a, Packet<T>& pk, Lane& ln, LdsTallies& L) {
   }
   pk.tau = (double)(-tlog(xi_of<T>(r.w3)));
   pk.steps = 0;
+  pk.pd = T(-1);
   record<T, TRACE>(a, pk, ln, SMCRT_EV_SCATTER);
   return true;
 }

@@ -83,6 +83,7 @@ _SIGS = {
     "smcrt_scene_set_grid": ([_vp, _dp, _dp, C.POINTER(C.c_int32)], C.c_int),
     "smcrt_scene_set_roulette": ([_vp, C.c_double, C.c_int32], C.c_int),
     "smcrt_scene_set_limits": ([_vp, C.c_int32, C.c_int64], C.c_int),
+    "smcrt_scene_set_relaxation": ([_vp, C.c_double], C.c_int),
     "smcrt_scene_set_accel": ([_vp, C.c_int32, C.POINTER(C.c_int32)], C.c_int),
     "smcrt_scene_set_geometry": ([_vp, C.c_int], C.c_int),
     "smcrt_scene_set_detector": ([_vp, C.c_int, _dp, _dp, C.POINTER(C.c_int32)], C.c_int),
@@ -183,6 +184,10 @@ def smcrt_scene_set_roulette(scene, w_threshold, m_survive):
 
 def smcrt_scene_set_limits(scene, max_steps, max_events):
     _check(lib().smcrt_scene_set_limits(scene, max_steps, max_events))
+
+
+def smcrt_scene_set_relaxation(scene, omega):
+    _check(lib().smcrt_scene_set_relaxation(scene, omega))
 
 
 def smcrt_scene_set_accel(scene, region, cells):
@@ -351,6 +356,7 @@ class Scene:
         ro = desc["roulette"]
         smcrt_scene_set_roulette(self.h, ro["w_threshold"], ro["m"])
         smcrt_scene_set_limits(self.h, desc["max_steps"], desc["max_events"])
+        smcrt_scene_set_relaxation(self.h, float(desc.get("relax", 1.0)))
         if desc.get("accel_cells"):
             # accelerate the union region with the most primitives
             counts = [len(rg["prims"]) if rg["op"] == "union" else 0 for rg in desc["regions"]]

@@ -245,3 +245,15 @@ def test_detector_pixel_limit(S):
             S.smcrt_scene_set_detector(h, 5, [0, 0], [1, 1], [65536, 65536])
     finally:
         S.smcrt_scene_destroy(h)
+
+
+def test_relaxation_validation(S):
+    h = S.smcrt_scene_create(1.0, 1e-5, 1e-4)
+    try:
+        for bad in (0.99, 2.0, float("nan")):
+            with pytest.raises(S.SmcrtError, match="omega"):
+                S.smcrt_scene_set_relaxation(h, bad)
+        S.smcrt_scene_set_relaxation(h, 1.0)
+        S.smcrt_scene_set_relaxation(h, 1.9)
+    finally:
+        S.smcrt_scene_destroy(h)
