@@ -119,6 +119,31 @@ smcrt_status smcrt_scene_set_roulette(smcrt_scene* scene, double w_threshold, in
  * tallied as stalled (defaults 100000 and 1000000). */
 smcrt_status smcrt_scene_set_limits(smcrt_scene* scene, int32_t max_steps, int64_t max_events);
 
+/* Placement of primitive prim (Sec. 2.2: SDFs are translated, rotated and
+ * scaled): its parameters are then read in its own frame, placed in the
+ * world by x_world = scale * R x_local + trans.  rot: host array of 9, R
+ * row-major, orthonormal to 1e-9 with determinant +1; scale > 0.  Distances
+ * stay exact (times scale).  Errors: SMCRT_E_INVALID for an unknown
+ * primitive, a non-rotation, scale <= 0 or non-finite values. */
+smcrt_status smcrt_scene_set_primitive_placement(smcrt_scene* scene, int32_t prim, const double rot[9], double scale,
+                                                 const double trans[3]);
+
+/* Modifiers of primitive prim, in its own frame and in this order (Sec. 2.2
+ * and its gallery: rounded, hollow and twisted shapes): rounding subtracts
+ * round_r (>= 0) from the distance; an onion shell of half-thickness
+ * onion_t > 0 replaces d by |d| - onion_t; a twist turns the shape about
+ * the local z axis by twist_k * z radians.  Rounding and shell keep the
+ * distance exact.  A twist keeps its sign only: inside the bounding
+ * cylinder about the local z axis (radius 1.001 x the largest distance from
+ * the axis of the primitive's local box grown by round_r + onion_t, z range
+ * that box's grown by 0.1 % of its length at each end) the distance of the
+ * untwisted shape is divided by sqrt(1 + (twist_k rho)^2), its Lipschitz
+ * bound there, and outside it the distance to that cylinder is used, so
+ * sphere tracing stays conservative.  Zeros remove the modifiers.  Errors:
+ * SMCRT_E_INVALID for an unknown primitive, negative or non-finite values. */
+smcrt_status smcrt_scene_set_primitive_modifiers(smcrt_scene* scene, int32_t prim, double round_r, double onion_t,
+                                                 double twist_k);
+
 /* Over-relaxed sphere tracing (Sec. 5 names faster marching as the remedy
  * for the many small steps of paths along surfaces).  With omega > 1 a step
  * may move omega times the nearest-surface distance d.  It is taken when the

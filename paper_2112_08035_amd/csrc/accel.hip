@@ -16,35 +16,12 @@
 
 namespace smcrt {
 
-// conservative box of a packed primitive
-__device__ __forceinline__ void packed_prim_box(const PrimD& P, double lo[3], double hi[3]) {
-  const double* v = P.v;
-  for (int i = 0; i < 3; ++i) {
-    if (P.kind == kSphere) {
-      lo[i] = v[i] - v[3];
-      hi[i] = v[i] + v[3];
-    } else if (P.kind == kBox) {
-      lo[i] = v[i] - v[3 + i];
-      hi[i] = v[i] + v[3 + i];
-    } else if (P.kind == kCapsule) {  // a, b - a, ., r
-      const double b = v[i] + v[3 + i];
-      lo[i] = fmin(v[i], b) - v[7];
-      hi[i] = fmax(v[i], b) + v[7];
-    } else {  // cylinder: a, unit axis, L, L/2, r
-      const double b = v[i] + v[3 + i] * v[6];
-      lo[i] = fmin(v[i], b) - v[8];
-      hi[i] = fmax(v[i], b) + v[8];
-    }
-  }
-}
-
-// inclusive cell range [c0, c1] of a primitive's grown box, clamped
+// inclusive cell range [c0, c1] of a primitive's world box (packed by the
+// host for every kind, placement and modifier) grown by the margin, clamped
 __device__ __forceinline__ void cell_range(const Accel& A, const PrimD& P, int c0[3], int c1[3]) {
-  double lo[3], hi[3];
-  packed_prim_box(P, lo, hi);
   for (int i = 0; i < 3; ++i) {
-    const double a = (lo[i] - A.margin - A.lo[i]) * A.inv_cell[i];
-    const double b = (hi[i] + A.margin - A.lo[i]) * A.inv_cell[i];
+    const double a = (P.box_lo[i] - A.margin - A.lo[i]) * A.inv_cell[i];
+    const double b = (P.box_hi[i] + A.margin - A.lo[i]) * A.inv_cell[i];
     int x0 = (int)floor(fmax(a, -1.0)), x1 = (int)floor(fmin(b, (double)A.dims[i]));
     x0 = x0 < 0 ? 0 : (x0 >= A.dims[i] ? A.dims[i] - 1 : x0);
     x1 = x1 < 0 ? 0 : (x1 >= A.dims[i] ? A.dims[i] - 1 : x1);

@@ -49,6 +49,11 @@ extern "C" int smcrt_abi_version(void) { return SMCRT_ABI_VERSION; }
 struct HostPrim {
   int kind;
   double p[8];
+  // placement x = s R x_local + t, rounding, onion shell, twist (local frame)
+  bool placed = false;
+  double rot[9] = {1, 0, 0, 0, 1, 0, 0, 0, 1};
+  double t[3] = {0, 0, 0}, s = 1.0;
+  double round_r = 0.0, onion_t = 0.0, twist_k = 0.0;
 };
 struct HostRegion {
   std::vector<int32_t> prims;
@@ -223,6 +228,48 @@ extern "C" smcrt_status smcrt_scene_set_limits(smcrt_scene* s, int32_t max_steps
   return SMCRT_OK;
 }
 
+extern "C" smcrt_status smcrt_scene_set_primitive_placement(smcrt_scene* s, int32_t prim, const double rot[9],
+                                                            double scale, const double trans[3]) {
+  if (!s || !rot || !trans) return fail(SMCRT_E_INVALID, "set_primitive_placement: NULL argument");
+  if (prim < 0 || prim >= (int32_t)s->prims.size()) return fail(SMCRT_E_INVALID, "set_primitive_placement: no primitive %d", prim);
+  for (int i = 0; i < 9; ++i)
+    if (!std::isfinite(rot[i])) return fail(SMCRT_E_INVALID, "set_primitive_placement: rotation not finite");
+  for (int i = 0; i < 3; ++i)
+    if (!std::isfinite(trans[i])) return fail(SMCRT_E_INVALID, "set_primitive_placement: translation not finite");
+  if (!(scale > 0.0 && std::isfinite(scale))) return fail(SMCRT_E_INVALID, "set_primitive_placement: scale must be > 0");
+  for (int i = 0; i < 3; ++i)  // rows orthonormal
+    for (int j = 0; j < 3; ++j) {
+      const double d = rot[3 * i] * rot[3 * j] + rot[3 * i + 1] * rot[3 * j + 1] + rot[3 * i + 2] * rot[3 * j + 2];
+      if (std::fabs(d - (i == j ? 1.0 : 0.0)) > 1e-9)
+        return fail(SMCRT_E_INVALID, "set_primitive_placement: rotation must be orthonormal (to 1e-9)");
+    }
+  const double det = rot[0] * (rot[4] * rot[8] - rot[5] * rot[7]) - rot[1] * (rot[3] * rot[8] - rot[5] * rot[6]) +
+                     rot[2] * (rot[3] * rot[7] - rot[4] * rot[6]);
+  if (!(det > 0.0)) return fail(SMCRT_E_INVALID, "set_primitive_placement: rotation must have determinant +1");
+  HostPrim& p = s->prims[prim];
+  p.placed = true;
+  std::memcpy(p.rot, rot, sizeof(p.rot));
+  std::memcpy(p.t, trans, sizeof(p.t));
+  p.s = scale;
+  s->dirty = true;
+  return SMCRT_OK;
+}
+
+extern "C" smcrt_status smcrt_scene_set_primitive_modifiers(smcrt_scene* s, int32_t prim, double round_r, double onion_t,
+                                                            double twist_k) {
+  if (!s) return fail(SMCRT_E_INVALID, "set_primitive_modifiers: NULL scene");
+  if (prim < 0 || prim >= (int32_t)s->prims.size()) return fail(SMCRT_E_INVALID, "set_primitive_modifiers: no primitive %d", prim);
+  if (!(round_r >= 0.0 && std::isfinite(round_r)) || !(onion_t >= 0.0 && std::isfinite(onion_t)))
+    return fail(SMCRT_E_INVALID, "set_primitive_modifiers: rounding and shell must be finite and >= 0");
+  if (!std::isfinite(twist_k)) return fail(SMCRT_E_INVALID, "set_primitive_modifiers: twist must be finite");
+  HostPrim& p = s->prims[prim];
+  p.round_r = round_r;
+  p.onion_t = onion_t;
+  p.twist_k = twist_k;
+  s->dirty = true;
+  return SMCRT_OK;
+}
+
 extern "C" smcrt_status smcrt_scene_set_relaxation(smcrt_scene* s, double omega) {
   if (!s) return fail(SMCRT_E_INVALID, "set_relaxation: NULL scene");
   if (!(omega >= 1.0 && omega < 2.0)) return fail(SMCRT_E_INVALID, "set_relaxation: omega must be in [1, 2)");
@@ -281,8 +328,8 @@ extern "C" smcrt_status smcrt_scene_set_geometry(smcrt_scene* s, int mode) {
   return SMCRT_OK;
 }
 
-// conservative box of a primitive
-static void prim_box(const HostPrim& p, double lo[3], double hi[3]) {
+// conservative box of a primitive's shape in its own frame
+static void local_box(const HostPrim& p, double lo[3], double hi[3]) {
   for (int i = 0; i < 3; ++i) {
     switch (p.kind) {
       case kSphere: lo[i] = p.p[i] - p.p[3]; hi[i] = p.p[i] + p.p[3]; break;
@@ -298,6 +345,54 @@ static void prim_box(const HostPrim& p, double lo[3], double hi[3]) {
       default:
         lo[i] = std::min(p.p[i], p.p[3 + i]) - p.p[6];
         hi[i] = std::max(p.p[i], p.p[3 + i]) + p.p[6];
+    }
+  }
+}
+
+// bounding cylinder about the local z axis of a twisted primitive: radius
+// 1.001 x the largest distance from the axis of its local box grown by
+// rounding and shell, z range that box's grown by 0.1 % of its length at
+// each end
+static void twist_cylinder(const HostPrim& p, double* rho, double* zlo, double* zhi) {
+  double lo[3], hi[3];
+  local_box(p, lo, hi);
+  const double g = p.round_r + p.onion_t;
+  double r2 = 0.0;
+  for (double x : {lo[0] - g, hi[0] + g})
+    for (double y : {lo[1] - g, hi[1] + g}) r2 = std::max(r2, x * x + y * y);
+  const double z0 = lo[2] - g, z1 = hi[2] + g, m = 1e-3 * (z1 - z0);
+  *rho = 1.001 * std::sqrt(r2);
+  *zlo = z0 - m;
+  *zhi = z1 + m;
+}
+
+// conservative world box of a primitive: its local box (grown by rounding
+// and shell, or the twist's bounding cylinder's box) with the 8 corners
+// placed in the world
+static void prim_box(const HostPrim& p, double lo[3], double hi[3]) {
+  double a[3], b[3];
+  local_box(p, a, b);
+  const double g = p.round_r + p.onion_t;
+  for (int i = 0; i < 3; ++i) { a[i] -= g; b[i] += g; }
+  if (p.twist_k != 0.0) {
+    double rho, z0, z1;
+    twist_cylinder(p, &rho, &z0, &z1);
+    a[0] = a[1] = -rho;
+    b[0] = b[1] = rho;
+    a[2] = z0;
+    b[2] = z1;
+  }
+  if (!p.placed) {
+    for (int i = 0; i < 3; ++i) { lo[i] = a[i]; hi[i] = b[i]; }
+    return;
+  }
+  for (int i = 0; i < 3; ++i) { lo[i] = 1e300; hi[i] = -1e300; }
+  for (int c = 0; c < 8; ++c) {
+    const double x[3] = {(c & 1) ? b[0] : a[0], (c & 2) ? b[1] : a[1], (c & 4) ? b[2] : a[2]};
+    for (int i = 0; i < 3; ++i) {
+      const double w = p.s * (p.rot[3 * i] * x[0] + p.rot[3 * i + 1] * x[1] + p.rot[3 * i + 2] * x[2]) + p.t[i];
+      lo[i] = std::min(lo[i], w);
+      hi[i] = std::max(hi[i], w);
     }
   }
 }
@@ -378,6 +473,25 @@ static void pack_prim(const HostPrim& h, Prim<T>& o) {
       break;
     }
   }
+  // placement and modifiers
+  o.flags = (h.placed ? kPlaced : 0) | (h.twist_k != 0.0 ? kTwisted : 0) |
+            ((h.round_r != 0.0 || h.onion_t != 0.0) ? kModified : 0);
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j) o.m[3 * i + j] = (T)(h.rot[3 * j + i] / h.s);
+  for (int i = 0; i < 3; ++i) o.t[i] = (T)h.t[i];
+  o.s = (T)h.s;
+  o.round_r = (T)h.round_r;
+  o.onion_t = (T)h.onion_t;
+  if (h.twist_k != 0.0) {
+    double rho, z0, z1;
+    twist_cylinder(h, &rho, &z0, &z1);
+    o.twist_k = (T)h.twist_k;
+    o.twist_rho = (T)rho;
+    o.twist_zc = (T)(0.5 * (z0 + z1));
+    o.twist_zh = (T)(0.5 * (z1 - z0));
+    o.inv_lip = (T)(1.0 / std::sqrt(1.0 + h.twist_k * h.twist_k * rho * rho));
+  }
+  prim_box(h, o.box_lo, o.box_hi);
 }
 
 static void fill_region(Region& r, double mua, double mus, double g, double n, double k, int op, int first, int count) {

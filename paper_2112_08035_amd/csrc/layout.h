@@ -27,11 +27,22 @@ enum Geometry : int32_t { kGeomSdf = 0, kGeomVoxel = 1 };
 //   capsule  : a0 a1 a2 ba0 ba1 ba2 1/|ba|^2 r
 //   cylinder : a0 a1 a2 e0 e1 e2 L L/2 r          (e = unit axis)
 //   torus    : c0 c1 c2 e0 e1 e2 R r              (e = unit axis)
+// A primitive may be placed (local = m (p - t), m = R^T / s, distance times
+// s), rounded or made an onion shell (in its own frame, exact), and twisted
+// about its local z axis: inside the bounding cylinder (radius twist_rho,
+// z in twist_zc -/+ twist_zh) the distance of the untwisted shape is
+// multiplied by inv_lip = 1/sqrt(1 + (twist_k twist_rho)^2), outside it the
+// distance to the cylinder is used.  flags = 0: the plain shape.
+enum PrimFlags { kPlaced = 1, kTwisted = 2, kModified = 4 };
 template <typename T>
 struct Prim {
   int32_t kind;
-  int32_t pad;
+  int32_t flags;
   T v[10];
+  T m[9], t[3], s;
+  T round_r, onion_t;
+  T twist_k, twist_rho, twist_zc, twist_zh, inv_lip;
+  double box_lo[3], box_hi[3];  // world box, for the acceleration build
 };
 using PrimD = Prim<double>;
 using PrimF = Prim<float>;

@@ -158,9 +158,10 @@ struct Tab<double> {
   static __device__ __forceinline__ double acc_margin(const SMCRT_K Accel& A) { return A.margin; }
 };
 
-// exact Euclidean SDF of one primitive (Sec. 2.2; Eq. 3 for the sphere)
+// exact Euclidean SDF of one primitive's shape in its own frame (Sec. 2.2;
+// Eq. 3 for the sphere)
 template <typename T>
-__device__ __forceinline__ T prim_sdf(const SMCRT_K Prim<T>* P, int i, V3<T> p) {
+__device__ __forceinline__ T shape_sdf(const SMCRT_K Prim<T>* P, int i, V3<T> p) {
   const int kind = P[i].kind;
   const SMCRT_K T* v = P[i].v;
   const V3<T> q = p - mk(v[0], v[1], v[2]);
@@ -189,6 +190,96 @@ __device__ __forceinline__ T prim_sdf(const SMCRT_K Prim<T>* P, int i, V3<T> p) 
   const T q2 = tabs(x - v[7]) - v[7];
   const T o1 = tmax(q1, T(0)), o2 = tmax(q2, T(0));
   return tmin(tmax(q1, q2), T(0)) + tsqrt(o1 * o1 + o2 * o2);
+}
+
+// sin and cos of a twist angle (a few radians): Cody-Waite reduction by
+// pi/2 in two parts to r in [-pi/4, pi/4], then the Taylor series of sin and
+// cos to r^17 / r^16 (FP64: last term < 4e-18) or r^11 / r^10 (FP32: < 1e-9),
+// evaluated by Horner's rule; the quadrant n mod 4 picks signs and order.
+// Kept in registers: the library routine's reduction for huge arguments
+// needs a stack array, which in the sphere-tracing loop moved other
+// values to scratch.
+template <typename T>
+__device__ __forceinline__ void tsincos(T a, T* sn, T* cs) {
+  const T n = rint(a * T(0.63661977236758134308));  // 2/pi
+  const T r = (a - n * T(1.5707963267948966)) - n * T(6.123233995736766e-17);
+  const T r2 = r * r;
+  T s, c;
+  if constexpr (sizeof(T) == 8) {
+    s = T(1) / T(355687428096000);
+    s = s * -r2 + T(1) / T(1307674368000);
+    s = s * -r2 + T(1) / T(6227020800);
+    s = s * -r2 + T(1) / T(39916800);
+    s = s * -r2 + T(1) / T(362880);
+    s = s * -r2 + T(1) / T(5040);
+    s = s * -r2 + T(1) / T(120);
+    s = s * -r2 + T(1) / T(6);
+    s = r - r * r2 * s;
+    c = T(1) / T(20922789888000);
+    c = c * -r2 + T(1) / T(87178291200);
+    c = c * -r2 + T(1) / T(479001600);
+    c = c * -r2 + T(1) / T(3628800);
+    c = c * -r2 + T(1) / T(40320);
+    c = c * -r2 + T(1) / T(720);
+    c = c * -r2 + T(1) / T(24);
+    c = c * -r2 + T(1) / T(2);
+    c = T(1) - r2 * c;
+  } else {
+    s = T(1) / T(39916800);
+    s = s * -r2 + T(1) / T(362880);
+    s = s * -r2 + T(1) / T(5040);
+    s = s * -r2 + T(1) / T(120);
+    s = s * -r2 + T(1) / T(6);
+    s = r - r * r2 * s;
+    c = T(1) / T(3628800);
+    c = c * -r2 + T(1) / T(40320);
+    c = c * -r2 + T(1) / T(720);
+    c = c * -r2 + T(1) / T(24);
+    c = c * -r2 + T(1) / T(2);
+    c = T(1) - r2 * c;
+  }
+  const int q = ((int)n) & 3;
+  *sn = q == 0 ? s : (q == 1 ? c : (q == 2 ? -s : -c));
+  *cs = q == 0 ? c : (q == 1 ? -s : (q == 2 ? -c : s));
+}
+
+// SDF of primitive i (Sec. 2.2: SDFs are translated, rotated, scaled and
+// twisted).  Placement with uniform scale keeps the distance exact (times s),
+// and so do rounding and the onion shell.  A twist keeps the sign; inside its
+// bounding cylinder the distance is divided by the twist's Lipschitz bound
+// there, outside it the distance to the cylinder is used.  The flags are the
+// same for every lane (primitives are visited in a wave-uniform order).
+template <typename T>
+__device__ __attribute__((noinline)) T placed_prim_sdf(const SMCRT_K Prim<T>* P, int i, V3<T> p) {
+  const SMCRT_K Prim<T>& Q = P[i];
+  const int fl = Q.flags;
+  V3<T> q = p;
+  if (fl & kPlaced) {
+    const V3<T> d = p - mk(Q.t[0], Q.t[1], Q.t[2]);
+    q = mk(Q.m[0] * d.x + Q.m[1] * d.y + Q.m[2] * d.z, Q.m[3] * d.x + Q.m[4] * d.y + Q.m[5] * d.z,
+           Q.m[6] * d.x + Q.m[7] * d.y + Q.m[8] * d.z);
+  }
+  T dcyl = T(0);
+  if (fl & kTwisted) {  // distance to the bounding cylinder, then untwist by -k z about z
+    const T q1 = tsqrt(q.x * q.x + q.y * q.y) - Q.twist_rho;
+    const T q2 = tabs(q.z - Q.twist_zc) - Q.twist_zh;
+    const T o1 = tmax(q1, T(0)), o2 = tmax(q2, T(0));
+    dcyl = tmin(tmax(q1, q2), T(0)) + tsqrt(o1 * o1 + o2 * o2);
+    T sn, cs;
+    tsincos(-Q.twist_k * q.z, &sn, &cs);
+    q = mk(cs * q.x - sn * q.y, sn * q.x + cs * q.y, q.z);
+  }
+  T d = shape_sdf(P, i, q) - Q.round_r;
+  if (Q.onion_t > T(0)) d = tabs(d) - Q.onion_t;
+  if (fl & kTwisted) d = dcyl > T(0) ? dcyl : d * Q.inv_lip;
+  if (fl & kPlaced) d *= Q.s;
+  return d;
+}
+
+template <typename T>
+__device__ __forceinline__ T prim_sdf(const SMCRT_K Prim<T>* P, int i, V3<T> p) {
+  if (P[i].flags == 0) return shape_sdf(P, i, p);
+  return placed_prim_sdf(P, i, p);
 }
 
 // region SDF from its primitives in order (CSG of Sec. 2.2): union (min),

@@ -84,6 +84,8 @@ _SIGS = {
     "smcrt_scene_set_roulette": ([_vp, C.c_double, C.c_int32], C.c_int),
     "smcrt_scene_set_limits": ([_vp, C.c_int32, C.c_int64], C.c_int),
     "smcrt_scene_set_relaxation": ([_vp, C.c_double], C.c_int),
+    "smcrt_scene_set_primitive_placement": ([_vp, C.c_int32, _dp, C.c_double, _dp], C.c_int),
+    "smcrt_scene_set_primitive_modifiers": ([_vp, C.c_int32, C.c_double, C.c_double, C.c_double], C.c_int),
     "smcrt_scene_set_accel": ([_vp, C.c_int32, C.POINTER(C.c_int32)], C.c_int),
     "smcrt_scene_set_geometry": ([_vp, C.c_int], C.c_int),
     "smcrt_scene_set_detector": ([_vp, C.c_int, _dp, _dp, C.POINTER(C.c_int32)], C.c_int),
@@ -161,6 +163,14 @@ def smcrt_scene_add_primitive(scene, kind, params):
     out = C.c_int32()
     _check(lib().smcrt_scene_add_primitive(scene, kind, _darr(params), len(params), C.byref(out)))
     return out.value
+
+
+def smcrt_scene_set_primitive_placement(scene, prim, rot, scale, trans):
+    _check(lib().smcrt_scene_set_primitive_placement(scene, prim, _darr(rot), scale, _darr(trans)))
+
+
+def smcrt_scene_set_primitive_modifiers(scene, prim, round_r, onion_t, twist_k):
+    _check(lib().smcrt_scene_set_primitive_modifiers(scene, prim, round_r, onion_t, twist_k))
 
 
 def smcrt_scene_add_region(scene, prims, op, k_cm, mu_a, mu_s, g, n):
@@ -332,7 +342,15 @@ class Scene:
                 vals = list(p["c"]) + list(p["axis"]) + [p["R"], p["r"]]
             else:
                 vals = list(p["a"]) + list(p["b"]) + [p["r"]]
-            ids.append(smcrt_scene_add_primitive(self.h, PRIM[p["kind"]], vals))
+            pid = smcrt_scene_add_primitive(self.h, PRIM[p["kind"]], vals)
+            ids.append(pid)
+            xf = p.get("transform")
+            if xf:
+                R = [float(x) for row in xf["R"] for x in row]
+                smcrt_scene_set_primitive_placement(self.h, pid, R, float(xf["s"]), [float(x) for x in xf["t"]])
+            if p.get("round", 0.0) or p.get("onion", 0.0) or p.get("twist", 0.0):
+                smcrt_scene_set_primitive_modifiers(self.h, pid, float(p.get("round", 0.0)),
+                                                    float(p.get("onion", 0.0)), float(p.get("twist", 0.0)))
         for rg in desc["regions"]:
             smcrt_scene_add_region(self.h, [ids[i] for i in rg["prims"]], OP[rg["op"]], rg.get("k", 0.0),
                                    rg["mua"], rg["mus"], rg["g"], rg["n"])

@@ -401,10 +401,52 @@ def with_grid(scene, dims, lo=None, hi=None):
     return sc
 
 
+def rotation(axis, angle):
+    """3 x 3 rotation matrix (nested lists) by angle radians about axis"""
+    a = np.asarray(axis, float)
+    a = a / np.linalg.norm(a)
+    K = np.array([[0.0, -a[2], a[1]], [a[2], 0.0, -a[0]], [-a[1], a[0], 0.0]])
+    return (np.eye(3) + np.sin(angle) * K + (1.0 - np.cos(angle)) * K @ K).tolist()
+
+
+def gallery_scene(n_grid=64):
+    """Shaped like the paper's SDF gallery (Sec. 2.2): placed and modified
+    primitives in a 2 x 2 x 2 cm scattering medium (mu_a 0.1, mu_s 20,
+    g 0.9, n 1.33) lit from above by a 0.5 cm top-hat beam:
+    - a glass box (n 1.5, weakly absorbing) turned 30 deg about (1, 1, 0);
+    - a twisted bar (1 rad/cm) of absorbing tissue;
+    - a rounded capsule and a scaled torus of blood (one union region);
+    - an onion shell of a sphere of dense scatterer."""
+    prims = [
+        {"kind": "box", "c": [0.0, 0.0, 0.0], "half": [1.0, 1.0, 1.0]},
+        {"kind": "box", "c": [0.0, 0.0, 0.0], "half": [0.3, 0.2, 0.15],
+         "transform": {"R": rotation([1, 1, 0], math.pi / 6), "t": [0.35, 0.35, 0.45], "s": 1.0}},
+        {"kind": "box", "c": [0.0, 0.0, 0.0], "half": [0.25, 0.08, 0.5], "twist": 1.0,
+         "transform": {"R": rotation([1, 0, 0], math.pi / 2), "t": [-0.4, 0.0, 0.3], "s": 1.0}},
+        {"kind": "capsule", "a": [-0.6, -0.5, -0.3], "b": [0.5, -0.6, -0.2], "r": 0.04, "round": 0.03},
+        {"kind": "torus", "c": [0.0, 0.0, 0.0], "axis": [0.0, 0.0, 1.0], "R": 1.0, "r": 0.2,
+         "transform": {"R": rotation([0, 1, 0], 0.4), "t": [0.3, 0.3, -0.5], "s": 0.35}},
+        {"kind": "sphere", "c": [0.0, 0.0, 0.0], "r": 0.25, "onion": 0.06,
+         "transform": {"R": rotation([0, 0, 1], 0.0), "t": [-0.45, 0.5, -0.45], "s": 1.0}},
+    ]
+    regions = [
+        _region([0], 0.1, 20.0, 0.9, 1.33),
+        _region([1], 0.05, 0.5, 0.0, 1.5),
+        _region([2], 2.0, 80.0, 0.9, 1.4),
+        _region([3, 4], 20.0, 400.0, 0.98, 1.4),
+        _region([5], 0.5, 300.0, 0.8, 1.45),
+    ]
+    grid = {"lo": [-1.0] * 3, "hi": [1.0] * 3, "dims": [n_grid] * 3}
+    sc = _scene("gallery", prims, regions, None, grid)
+    sc["source"] = {"kind": "disc", "c": [0.0, 0.0, 1.0 + 0.5 * sc["pad"]], "r": 0.5, "u": [0.0, 0.0, -1.0]}
+    return sc
+
+
 WORKLOADS = {
     "sphere": sphere_scene,
     "slab": slab_scene,
     "cylinder": cylinder_scene,
     "glass_sphere": glass_sphere_scene,
     "bottle": bottle_scene,
+    "gallery": gallery_scene,
 }

@@ -85,7 +85,7 @@ def oracle_batches(orc, desc, seed, n, n_batches, voxel=False):
     step = n // n_batches
     outs = [orc.run(desc, seed, step, first=b * step, voxel=voxel) for b in range(n_batches)]
     tot = {k: sum(o[k] for o in outs) for k in ("absorbed", "escaped_face", "roulette_gain", "roulette_loss",
-                                                "stalled", "launched", "interactions", "interfaces")}
+                                                "stalled", "launched", "interactions", "interfaces", "steps")}
     tot["fluence_raw"] = sum(o["fluence_raw"] for o in outs)
     se = batch_se([o["fluence_raw"] for o in outs])
     return tot, se

@@ -96,7 +96,7 @@ def test_regions_limit(S):
         S.smcrt_scene_destroy(h)
 
 
-@pytest.mark.parametrize("name", ["sphere", "slab", "cylinder", "vessels", "glass_sphere", "bottle", "torus"])
+@pytest.mark.parametrize("name", ["sphere", "slab", "cylinder", "vessels", "glass_sphere", "bottle", "torus", "gallery"])
 def test_volume_rule_agrees_with_oracle(S, orc, W, name):
     if name == "vessels":
         desc = W.vessel_scene(3, 1.0, n_caps=50, n_grid=8)
@@ -108,8 +108,11 @@ def test_volume_rule_agrees_with_oracle(S, orc, W, name):
     sc = S.Scene(desc)
     _, npr, lo, hi = S.smcrt_scene_info(sc.h)
     olo, ohi = orc.bounding_box(desc)
-    np.testing.assert_allclose(lo, olo, rtol=0, atol=1e-15)
-    np.testing.assert_allclose(hi, ohi, rtol=0, atol=1e-15)
+    # placed primitives' boxes come from 8 turned corners, summed in another
+    # order on each side
+    atol = 1e-12 if name == "gallery" else 1e-15
+    np.testing.assert_allclose(lo, olo, rtol=0, atol=atol)
+    np.testing.assert_allclose(hi, ohi, rtol=0, atol=atol)
     assert npr == len(desc["prims"])
 
 
@@ -257,3 +260,27 @@ def test_relaxation_validation(S):
         S.smcrt_scene_set_relaxation(h, 1.9)
     finally:
         S.smcrt_scene_destroy(h)
+
+
+def test_primitive_placement_and_modifier_validation(S):
+    h = S.smcrt_scene_create(1.0, 1e-5, 1e-4)
+    try:
+        p = S.smcrt_scene_add_primitive(h, 0, [0, 0, 0, 1.0])
+        I = [1, 0, 0, 0, 1, 0, 0, 0, 1]
+        with pytest.raises(S.SmcrtError, match="no primitive"):
+            S.smcrt_scene_set_primitive_placement(h, 5, I, 1.0, [0, 0, 0])
+        with pytest.raises(S.SmcrtError, match="orthonormal"):
+            S.smcrt_scene_set_primitive_placement(h, p, [2, 0, 0, 0, 1, 0, 0, 0, 1], 1.0, [0, 0, 0])
+        with pytest.raises(S.SmcrtError, match="determinant"):
+            S.smcrt_scene_set_primitive_placement(h, p, [-1, 0, 0, 0, 1, 0, 0, 0, 1], 1.0, [0, 0, 0])
+        with pytest.raises(S.SmcrtError, match="scale"):
+            S.smcrt_scene_set_primitive_placement(h, p, I, 0.0, [0, 0, 0])
+        S.smcrt_scene_set_primitive_placement(h, p, [0, -1, 0, 1, 0, 0, 0, 0, 1], 2.0, [1, 2, 3])
+        with pytest.raises(S.SmcrtError, match=">= 0"):
+            S.smcrt_scene_set_primitive_modifiers(h, p, -0.1, 0.0, 0.0)
+        with pytest.raises(S.SmcrtError, match="finite"):
+            S.smcrt_scene_set_primitive_modifiers(h, p, 0.0, 0.0, float("inf"))
+        S.smcrt_scene_set_primitive_modifiers(h, p, 0.1, 0.05, 2.0)
+    finally:
+        S.smcrt_scene_destroy(h)
+
