@@ -57,8 +57,8 @@ def test_gallery_voxelises_like_the_oracle(S, eng, orc, W):
 
 def test_accelerated_union_of_placed_primitives(S, eng, orc, W):
     # a union region of turned, scaled capsules and tori: the acceleration
-    # grid is built from the packed world boxes, and its walk must equal the
-    # brute-force walk packet for packet
+    # grid is built from the packed world boxes, and its walk must take the
+    # brute-force walk's decisions
     rng = np.random.default_rng(12)
     prims = [{"kind": "box", "c": [0.0, 0.0, 0.0], "half": [0.5, 0.5, 0.5]}]
     for k in range(40):
