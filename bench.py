@@ -470,7 +470,8 @@ def main():
         marks[k][1].record(stream)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
-    launch_ms = float(np.mean([a.elapsed_time(b) for a, b in marks]))
+    step_ms = [a.elapsed_time(b) for a, b in marks]
+    launch_ms = float(np.mean(step_ms))
     h = out.host()
     steps = args.steps
     value = n * steps / wall
@@ -513,6 +514,7 @@ def main():
             "frac": achieved / PEAK_LANE_OPS,
             "traffic": measured_traffic() if args.precision == "f32" else None,
             "kernel_ms": launch_ms,
+            "step_kernel_ms": step_ms,
             "lane_ops_per_launch": lane_ops,
             "grid_atomics_per_s": per["grid_atomics"] / (launch_ms * 1e-3),
             "atomic_ceiling_per_s": ceiling,

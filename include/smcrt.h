@@ -146,10 +146,11 @@ smcrt_status smcrt_scene_set_primitive_modifiers(smcrt_scene* scene, int32_t pri
 
 /* Over-relaxed sphere tracing (Sec. 5 names faster marching as the remedy
  * for the many small steps of paths along surfaces).  With omega > 1 a step
- * may move omega times the nearest-surface distance d.  It is taken when the
- * previous step of the same straight segment saw the distance fall by at
- * most (2 - omega)/omega of its length, which is when such a step toward a
- * plane would pass the check.  The next evaluation then checks it: the free
+ * may move omega times the nearest-surface distance d.  It is taken when it
+ * would pass its check were the surface a plane met at the angle the
+ * previous step of the same straight segment saw (the fall of d per unit
+ * length); near a surface (d below delta/(2 - omega)) it never is.  The
+ * next evaluation then checks it: the free
  * balls of radius d at its start and d' at its end must cover it, with
  * d + d' >= step + delta.  A step that fails goes back to the plain step of
  * d, so no surface is ever crossed unseen.  Events, tallies and fluence are

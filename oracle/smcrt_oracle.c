@@ -670,12 +670,15 @@ static void walk(walker* wk, uint64_t seed, uint64_t pid) {
           steps = 0;
           pd = -1.0;
         }
-      } else if (s->relax > 1.0 && pd >= 0.0 && pd - dmin <= (2.0 - s->relax) / s->relax * pl &&
+      } else if (s->relax > 1.0 && pd >= 0.0 &&
+                 dmin * ((2.0 - s->relax) * pl - s->relax * (pd - dmin)) >= s->delta * pl &&
                  s->relax * dmin < s_rem) {
-        /* over-relaxed step, taken when the previous step saw the surface
-         * distance fall slowly enough that, were the surface a plane, the
-         * relaxed step would pass its check; its path is credited once the
-         * check passes */
+        /* over-relaxed step, taken when it would pass its check were the
+         * surface a plane met at the angle the previous step saw: the
+         * distance falls by (pd - dmin)/pl per unit length, so at the end
+         * of a step w dmin it is dmin - w (pd - dmin) dmin / pl, and the
+         * check needs dmin + that >= w dmin + delta.  Its path is credited
+         * once the check passes */
         for (int i = 0; i < 3; ++i) q[i] = pk.p[i];
         pd = dmin;
         pl = s->relax * dmin;

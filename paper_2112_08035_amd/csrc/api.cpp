@@ -617,7 +617,7 @@ static smcrt_status pack(smcrt_scene* s) {
   h->delta = s->delta;
   h->deltaf = (float)s->delta;
   h->relax = s->relax;
-  h->relax_k = (2.0 - s->relax) / s->relax;
+  h->relax_k = 2.0 - s->relax;
   h->relaxf = (float)s->relax;
   h->relax_kf = (float)h->relax_k;
   h->h_normal = 1e-2 * s->delta;

@@ -95,8 +95,7 @@ struct SceneHeader {
   double det_lo[2], det_hi[2];
   double w_threshold, m_d, inv_m;
   float deltaf, relaxf;
-  // over-relaxed sphere tracing: factor omega and the bound (2 - omega)/omega
-  // on the relative fall of the surface distance that allows a relaxed step
+  // over-relaxed sphere tracing: factor omega and 2 - omega
   double relax, relax_k;
   float relax_kf, pad1;
   Region reg[kMaxRegions + 1];

@@ -284,11 +284,15 @@ walk_kernel(const WalkArgs* __restrict__ job_table, BatchArgs B) {
             } else if (dmin < delta) {
               pk.state = kSurface;
             } else {
-              // a step of dmin, or an over-relaxed one of omega * dmin when
-              // the previous step saw the distance fall slowly enough that a
-              // plane ahead would let it pass its check
+              // a step of dmin, or an over-relaxed one of omega * dmin when it
+              // would pass its check were the surface a plane met at the
+              // angle the previous step saw (its distance falls by
+              // (pd - dmin)/pl per unit length): dmin + dmin - omega (pd -
+              // dmin) dmin / pl >= omega dmin + delta, times pl > 0
               const T om = Tab<T>::relax(sc);
-              const bool rel = om > T(1) && pk.pd >= T(0) && pk.pd - dmin <= Tab<T>::relax_k(sc) * pk.pl && om * dmin < s;
+              const bool rel = om > T(1) && pk.pd >= T(0) &&
+                               dmin * (Tab<T>::relax_k(sc) * pk.pl - om * (pk.pd - dmin)) >= delta * pk.pl &&
+                               om * dmin < s;
               const T moved = step_along(pk, rel ? om * dmin : dmin);
               pk.pd = dmin;
               pk.pl = rel ? -moved : moved;
