@@ -26,7 +26,9 @@ class Prim(C.Structure):
                 ("rot", C.c_double * 9), ("t", C.c_double * 3), ("s", C.c_double),
                 ("round_r", C.c_double), ("onion_t", C.c_double),
                 ("twist_k", C.c_double), ("twist_rho", C.c_double), ("twist_zlo", C.c_double),
-                ("twist_zhi", C.c_double)]
+                ("twist_zhi", C.c_double), ("elong", C.c_double * 3), ("disp_a", C.c_double),
+                ("disp_f", C.c_double), ("rep_c", C.c_double * 3), ("rep_n", C.c_int32 * 3), ("pad", C.c_int32),
+                ("rep_gap", C.c_double)]
 
 
 class Region(C.Structure):
@@ -115,17 +117,47 @@ def _d3(v):
     return (C.c_double * 3)(*[float(x) for x in v])
 
 
+def modified_box(p):
+    """Box of one copy of the modified shape in the primitive's frame: its
+    local box grown by the elongation per axis and by rounding, shell and
+    displacement amplitude on every side"""
+    lo, hi = local_aabb(p)
+    h = np.asarray(p.get("elongate", [0.0, 0.0, 0.0]), float)
+    g = float(p.get("round", 0.0)) + float(p.get("onion", 0.0)) + float(p.get("displace", {}).get("a", 0.0))
+    return lo - h - g, hi + h + g
+
+
 def twist_cylinder(p):
     """Bounding cylinder about the local z axis of a twisted primitive (its
-    local box grown by rounding and shell): radius 1.001 x the largest
-    distance of that box from the axis, z range the box's grown by 0.1 % of
-    its length at each end."""
-    lo, hi = local_aabb(p)
-    g = float(p.get("round", 0.0)) + float(p.get("onion", 0.0))
-    lo, hi = lo - g, hi + g
+    modified box): radius 1.001 x the largest distance of that box from the
+    axis, z range the box's grown by 0.1 % of its length at each end."""
+    lo, hi = modified_box(p)
     rho = max(math.hypot(x, y) for x in (lo[0], hi[0]) for y in (lo[1], hi[1]))
     m = 1e-3 * (hi[2] - lo[2])
     return 1.001 * rho, lo[2] - m, hi[2] + m
+
+
+def copy_box(p):
+    """Box of one copy in the primitive's frame: the modified box, or the
+    twist's bounding cylinder's box"""
+    if p.get("twist", 0.0) != 0.0:
+        rho, zlo, zhi = twist_cylinder(p)
+        return np.array([-rho, -rho, zlo]), np.array([rho, rho, zhi])
+    return modified_box(p)
+
+
+def repetition_gap(p):
+    """Smallest distance from a copy's box to a face of its cell that another
+    copy lies behind; raises if a copy does not fit its cell"""
+    rep = p["repeat"]
+    lo, hi = copy_box(p)
+    gap = math.inf
+    for a in range(3):
+        if int(rep["n"][a]) > 1:
+            gap = min(gap, 0.5 * float(rep["c"][a]) - max(abs(lo[a]), abs(hi[a])))
+    if not gap > 0:
+        raise ValueError("repeated copies must fit their cells")
+    return gap
 
 
 def prim_struct(p):
@@ -156,20 +188,33 @@ def prim_struct(p):
         flags |= 2
         s.twist_k = float(p["twist"])
         s.twist_rho, s.twist_zlo, s.twist_zhi = twist_cylinder(p)
+    s.elong = (C.c_double * 3)(*[float(x) for x in p.get("elongate", [0.0, 0.0, 0.0])])
+    disp = p.get("displace")
+    if disp:
+        s.disp_a, s.disp_f = float(disp["a"]), float(disp["f"])
+    rep = p.get("repeat")
+    if rep and any(int(n) > 1 for n in rep["n"]):
+        flags |= 4
+        s.rep_c = (C.c_double * 3)(*[float(x) for x in rep["c"]])
+        s.rep_n = (C.c_int32 * 3)(*[int(x) for x in rep["n"]])
+        s.rep_gap = repetition_gap(p)
+    else:
+        s.rep_c = (C.c_double * 3)(1.0, 1.0, 1.0)
+        s.rep_n = (C.c_int32 * 3)(1, 1, 1)
     s.flags = flags
     return s
 
 
 def prim_aabb(p):
-    """Conservative world box of a primitive: its local box (grown by
-    rounding and shell, or the twist's bounding cylinder's box) with the 8
-    corners placed in the world."""
-    lo, hi = local_aabb(p)
-    g = float(p.get("round", 0.0)) + float(p.get("onion", 0.0))
-    lo, hi = lo - g, hi + g
-    if p.get("twist", 0.0) != 0.0:
-        rho, zlo, zhi = twist_cylinder(p)
-        lo, hi = np.array([-rho, -rho, zlo]), np.array([rho, rho, zhi])
+    """Conservative world box of a primitive: the box of one copy (grown by
+    elongation, rounding, shell and displacement, or the twist's bounding
+    cylinder's box), over the repeated array, with the 8 corners placed in
+    the world."""
+    lo, hi = copy_box(p)
+    rep = p.get("repeat")
+    if rep:
+        ext = np.array([0.5 * (int(n) - 1) * float(c) for n, c in zip(rep["n"], rep["c"])])
+        lo, hi = lo - ext, hi + ext
     xf = p.get("transform")
     if not xf:
         return lo, hi

@@ -160,20 +160,40 @@ double orc_prim_sdf(const orc_prim* pr, const double p[3]) {
     double d[3] = {p[0] - pr->t[0], p[1] - pr->t[1], p[2] - pr->t[2]};
     for (int i = 0; i < 3; ++i) q[i] = (R[i] * d[0] + R[3 + i] * d[1] + R[6 + i] * d[2]) / pr->s;
   }
-  double d;
-  if (pr->flags & 2) {
-    d = zcyl_sdf(q, pr->twist_rho, pr->twist_zlo, pr->twist_zhi);
-    if (d <= 0.0) { /* inside the bounding cylinder: untwist, rotating by -k z about z */
-      double a = -pr->twist_k * q[2], c = cos(a), sn = sin(a);
-      double u[3] = {c * q[0] - sn * q[1], sn * q[0] + c * q[1], q[2]};
-      d = shape_sdf(pr, u) - pr->round_r;
-      if (pr->onion_t > 0.0) d = fabs(d) - pr->onion_t;
-      d /= sqrt(1.0 + pr->twist_k * pr->twist_k * pr->twist_rho * pr->twist_rho);
+  /* repetition: to the nearest copy; b = distance to the nearest face of
+   * that copy's cell with another copy behind it */
+  double b = ORC_INF;
+  if (pr->flags & 4) {
+    for (int a = 0; a < 3; ++a) {
+      const int n = pr->rep_n[a];
+      const double c = pr->rep_c[a], half = 0.5 * (n - 1) * c;
+      int i = (int)floor((q[a] + half) / c + 0.5);
+      i = i < 0 ? 0 : (i > n - 1 ? n - 1 : i);
+      q[a] -= i * c - half;
+      if (q[a] > 0.0 && i < n - 1) b = mind(b, 0.5 * c - q[a]);
+      if (q[a] < 0.0 && i > 0) b = mind(b, 0.5 * c + q[a]);
     }
-  } else {
-    d = shape_sdf(pr, q) - pr->round_r;
-    if (pr->onion_t > 0.0) d = fabs(d) - pr->onion_t;
   }
+  double d;
+  double dcyl = 0.0;
+  if (pr->flags & 2) {
+    dcyl = zcyl_sdf(q, pr->twist_rho, pr->twist_zlo, pr->twist_zhi);
+    /* untwist: rotate by -k z about z */
+    double a = -pr->twist_k * q[2], c = cos(a), sn = sin(a);
+    double u0 = c * q[0] - sn * q[1], u1 = sn * q[0] + c * q[1];
+    q[0] = u0;
+    q[1] = u1;
+  }
+  double e[3];
+  for (int i = 0; i < 3; ++i) e[i] = q[i] - clampd(q[i], -pr->elong[i], pr->elong[i]);
+  d = shape_sdf(pr, e) - pr->round_r;
+  if (pr->onion_t > 0.0) d = fabs(d) - pr->onion_t;
+  if (pr->disp_a > 0.0)
+    d = (d + pr->disp_a * sin(pr->disp_f * q[0]) * sin(pr->disp_f * q[1]) * sin(pr->disp_f * q[2])) /
+        (1.0 + pr->disp_a * pr->disp_f * sqrt(3.0));
+  if (pr->flags & 2)
+    d = dcyl > 0.0 ? dcyl : d / sqrt(1.0 + pr->twist_k * pr->twist_k * pr->twist_rho * pr->twist_rho);
+  if (pr->flags & 4) d = mind(d, pr->rep_gap + b);
   return (pr->flags & 1) ? pr->s * d : d;
 }
 

@@ -37,14 +37,21 @@ enum {
 /* sphere: c[3], r | box: c[3], half[3] | capsule and capped cylinder: a[3], b[3], r
  * | torus: c[3], axis[3] (any length), R (ring radius), r (tube radius) */
 /* A primitive is defined in its own frame by p[] and placed in the world by
- * x_world = s * R x_local + t (rotation R, uniform scale s > 0).  Its
- * distance is modified, in the local frame and in this order, by rounding
- * (minus round_r), an onion shell (|d| - onion_t) and a twist about the
- * local z axis (angle twist_k * z).  The twist bends distances, so inside
- * the bounding cylinder (radius twist_rho, z in [twist_zlo, twist_zhi]) of
- * the rounded shell the distance is divided by the twist's Lipschitz bound
- * there, sqrt(1 + (twist_k twist_rho)^2); outside it, the distance to that
- * cylinder is used.  flags: bit 0 transform, bit 1 twist. */
+ * x_world = s * R x_local + t (rotation R, uniform scale s > 0).  In the
+ * local frame the query point q is, in this order: repeated (copies of the
+ * shape at offsets (i - (n-1)/2) * rep_c per axis, i = 0..n-1, q taken to
+ * the nearest copy), untwisted (angle -twist_k * z about z) and elongated
+ * (q - clamp(q, -elong, elong)).  The distance of the shape there is
+ * rounded (minus round_r), made an onion shell (|d| - onion_t) and
+ * displaced (plus disp_a * sin(f q0x) sin(f q0y) sin(f q0z), q0 the point
+ * before elongation, divided by 1 + disp_a disp_f sqrt(3)).  A twist bends
+ * distances: inside the bounding cylinder (radius twist_rho, z in
+ * [twist_zlo, twist_zhi]) the distance is divided by the twist's Lipschitz
+ * bound there, sqrt(1 + (twist_k twist_rho)^2); outside it, the distance to
+ * that cylinder is used.  A repeated shape takes the smaller of its copy's
+ * distance and rep_gap plus the distance to the nearest face of its copy's
+ * cell shared with another copy.  flags: bit 0 transform, bit 1 twist,
+ * bit 2 repetition. */
 typedef struct {
   int32_t kind;
   int32_t flags;
@@ -53,6 +60,11 @@ typedef struct {
   double t[3], s;
   double round_r, onion_t;
   double twist_k, twist_rho, twist_zlo, twist_zhi;
+  double elong[3];
+  double disp_a, disp_f;
+  double rep_c[3];
+  int32_t rep_n[3], pad;
+  double rep_gap;
 } orc_prim;
 
 typedef struct {

@@ -175,3 +175,76 @@ def test_world_box_holds_the_shape(orc, W):
         inside = pts[d < 0]
         assert len(inside) > 50
         assert np.all(inside >= lo) and np.all(inside <= hi)
+
+
+# ------------------------------------------- elongation, displacement, repetition --
+
+def test_elongated_sphere_is_a_capsule_and_box_a_box(orc, W):
+    rng = np.random.default_rng(6)
+    el = one_prim_scene(W, {"kind": "sphere", "c": [0, 0, 0], "r": 0.2, "elongate": [0.3, 0.0, 0.0]})
+    cap = one_prim_scene(W, {"kind": "capsule", "a": [-0.3, 0, 0], "b": [0.3, 0, 0], "r": 0.2})
+    eb = one_prim_scene(W, {"kind": "box", "c": [0, 0, 0], "half": [0.1, 0.2, 0.3], "elongate": [0.2, 0.0, 0.1]})
+    big = one_prim_scene(W, {"kind": "box", "c": [0, 0, 0], "half": [0.3, 0.2, 0.4]})
+    for p in rng.uniform(-0.8, 0.8, (300, 3)):
+        assert orc.region_sdf(el, 0, p) == pytest.approx(orc.region_sdf(cap, 0, p), abs=1e-12)
+        d_el, d_big = orc.region_sdf(eb, 0, p), orc.region_sdf(big, 0, p)
+        if d_big >= 0:   # exact outside
+            assert d_el == pytest.approx(d_big, abs=1e-12)
+        else:            # inside: same sign, never beyond the surface
+            assert d_el < 0 and abs(d_el) <= abs(d_big) + 1e-12
+
+
+def test_displaced_sphere_sign_and_lower_bound(orc, W):
+    a, f, r = 0.05, 12.0, 0.5
+    sc = one_prim_scene(W, {"kind": "sphere", "c": [0, 0, 0], "r": r, "displace": {"a": a, "f": f}})
+    D = lambda x: a * np.sin(f * x[..., 0]) * np.sin(f * x[..., 1]) * np.sin(f * x[..., 2])
+    # surface by bisection along rays from the centre: g(t) = t - r + D(t w), increasing since a f sqrt(3) < 1
+    rng = np.random.default_rng(7)
+    W_ = rng.normal(size=(6000, 3))
+    W_ /= np.linalg.norm(W_, axis=1, keepdims=True)
+    lo, hi = np.full(len(W_), r - 2 * a), np.full(len(W_), r + 2 * a)
+    for _ in range(60):
+        mid = 0.5 * (lo + hi)
+        g = mid - r + D(mid[:, None] * W_)
+        lo, hi = np.where(g < 0, mid, lo), np.where(g < 0, hi, mid)
+    surf = 0.5 * (lo + hi)[:, None] * W_
+    L = 1 + a * f * math.sqrt(3)
+    for p in rng.uniform(-0.9, 0.9, (300, 3)):
+        d = orc.region_sdf(sc, 0, p)
+        inside = np.linalg.norm(p) - r + D(p) < 0
+        assert (d < 0) == inside
+        near = np.min(np.linalg.norm(surf - p, axis=1))
+        assert abs(d) <= near + 0.02, (p, d, near)           # 6000 surface samples: spacing ~0.02
+        # the displaced surface is within a of the sphere's and |a D| <= a, so
+        # |d_sphere + a D| >= near - 2a
+        assert abs(d) >= (near - 2 * a) / L - 0.02
+
+
+def test_repeated_sphere_sign_bound_and_walk(orc, W):
+    rep = {"kind": "sphere", "c": [0, 0, 0], "r": 0.15, "repeat": {"c": [0.5, 0.4, 1.0], "n": [3, 2, 1]}}
+    sc = one_prim_scene(W, rep, 0.5, 1.4)
+    centres = [np.array([(i - 1) * 0.5, (j - 0.5) * 0.4, 0.0]) for i in range(3) for j in range(2)]
+    rng = np.random.default_rng(8)
+    for p in rng.uniform(-1.2, 1.2, (400, 3)):
+        d = orc.region_sdf(sc, 0, p)
+        true = min(np.linalg.norm(p - c) - 0.15 for c in centres)
+        assert (d < 0) == (true < 0)
+        assert abs(d) <= abs(true) + 1e-12
+    # the same spheres as one union region: the same events
+    prims = [{"kind": "sphere", "c": c.tolist(), "r": 0.15} for c in centres]
+    union = W._scene("six", prims, [W._region(range(6), 0.5, 0.0, 0.0, 1.4)], {"kind": "point", "p": [0.0, 0.2, 0.0]}, None)
+    sc["source"] = {"kind": "point", "p": [0.0, 0.2, 0.0]}
+    union["regions"][0]["mus"] = sc["regions"][0]["mus"] = 3.0
+    for pid in range(40):
+        a = orc.trace(sc, 9, pid, 80)
+        b = orc.trace(union, 9, pid, 80)
+        assert [(e["type"], e["region"]) for e in a] == [(e["type"], e["region"]) for e in b], pid
+        for ea, eb in zip(a, b):
+            if ea["type"] != "ESCAPE":
+                assert np.abs(ea["p"] - eb["p"]).max() < 1e-6
+
+
+def test_repetition_must_fit_its_cells(W):
+    from oracle.oracle import prim_struct
+    with pytest.raises(ValueError):
+        prim_struct({"kind": "sphere", "c": [0, 0, 0], "r": 0.3, "repeat": {"c": [0.5, 1, 1], "n": [2, 1, 1]}})
