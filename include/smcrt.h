@@ -144,6 +144,35 @@ smcrt_status smcrt_scene_set_primitive_placement(smcrt_scene* scene, int32_t pri
 smcrt_status smcrt_scene_set_primitive_modifiers(smcrt_scene* scene, int32_t prim, double round_r, double onion_t,
                                                  double twist_k);
 
+/* Elongation of primitive prim (gallery: stretched shapes): in its own
+ * frame the point q is replaced by q - clamp(q, -h, h) before the shape is
+ * evaluated, which stretches the shape by 2 h[i] along axis i (a sphere
+ * becomes a capsule).  The result is exact outside and a lower bound with
+ * the exact sign inside.  h: host array of 3, each finite and >= 0.
+ * Errors: SMCRT_E_INVALID for an unknown primitive or a bad h. */
+smcrt_status smcrt_scene_set_primitive_elongation(smcrt_scene* scene, int32_t prim, const double h[3]);
+
+/* Displacement of primitive prim (gallery: bumpy shapes): amplitude *
+ * sin(f x) sin(f y) sin(f z), at the point before elongation, is added to
+ * the shape's distance after rounding and shell, and the sum is divided by
+ * its Lipschitz bound 1 + amplitude * f * sqrt(3), so sphere tracing stays
+ * conservative; the shape is the set where the sum is negative.  Errors:
+ * SMCRT_E_INVALID for an unknown primitive, negative or non-finite values. */
+smcrt_status smcrt_scene_set_primitive_displacement(smcrt_scene* scene, int32_t prim, double amplitude, double frequency);
+
+/* Finite repetition of primitive prim (gallery: repeated shapes): counts[i]
+ * copies along local axis i at offsets (k - (counts[i]-1)/2) * spacing[i],
+ * k = 0..counts[i]-1.  A point is taken to the nearest copy; the distance is
+ * the smaller of that copy's and the gap around a copy plus the distance
+ * to the nearest face of its cell that another copy lies behind, a lower
+ * bound with the exact sign.  Every copy (with its other modifiers, or its
+ * twist's bounding cylinder) must fit inside its cell with a gap > 0.
+ * counts in [1, 4096], spacing > 0.  Errors: SMCRT_E_INVALID for an unknown
+ * primitive, bad values or copies that do not fit (also when a later
+ * modifier makes them not fit: then the run fails). */
+smcrt_status smcrt_scene_set_primitive_repetition(smcrt_scene* scene, int32_t prim, const double spacing[3],
+                                                  const int32_t counts[3]);
+
 /* Over-relaxed sphere tracing (Sec. 5 names faster marching as the remedy
  * for the many small steps of paths along surfaces).  With omega > 1 a step
  * may move omega times the nearest-surface distance d.  It is taken when it

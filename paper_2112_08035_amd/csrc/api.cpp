@@ -54,7 +54,14 @@ struct HostPrim {
   double rot[9] = {1, 0, 0, 0, 1, 0, 0, 0, 1};
   double t[3] = {0, 0, 0}, s = 1.0;
   double round_r = 0.0, onion_t = 0.0, twist_k = 0.0;
+  double elong[3] = {0, 0, 0};
+  double disp_a = 0.0, disp_f = 0.0;
+  double rep_c[3] = {1, 1, 1};
+  int32_t rep_n[3] = {1, 1, 1};
 };
+static bool repeated(const HostPrim& p);
+static double repetition_gap(const HostPrim& p);
+
 struct HostRegion {
   std::vector<int32_t> prims;
   int op;
@@ -270,6 +277,45 @@ extern "C" smcrt_status smcrt_scene_set_primitive_modifiers(smcrt_scene* s, int3
   return SMCRT_OK;
 }
 
+extern "C" smcrt_status smcrt_scene_set_primitive_elongation(smcrt_scene* s, int32_t prim, const double h[3]) {
+  if (!s || !h) return fail(SMCRT_E_INVALID, "set_primitive_elongation: NULL argument");
+  if (prim < 0 || prim >= (int32_t)s->prims.size()) return fail(SMCRT_E_INVALID, "set_primitive_elongation: no primitive %d", prim);
+  for (int i = 0; i < 3; ++i)
+    if (!(h[i] >= 0.0 && std::isfinite(h[i]))) return fail(SMCRT_E_INVALID, "set_primitive_elongation: h must be finite and >= 0");
+  std::memcpy(s->prims[prim].elong, h, sizeof(double) * 3);
+  s->dirty = true;
+  return SMCRT_OK;
+}
+
+extern "C" smcrt_status smcrt_scene_set_primitive_displacement(smcrt_scene* s, int32_t prim, double amplitude, double frequency) {
+  if (!s) return fail(SMCRT_E_INVALID, "set_primitive_displacement: NULL scene");
+  if (prim < 0 || prim >= (int32_t)s->prims.size()) return fail(SMCRT_E_INVALID, "set_primitive_displacement: no primitive %d", prim);
+  if (!(amplitude >= 0.0 && std::isfinite(amplitude)) || !(frequency >= 0.0 && std::isfinite(frequency)))
+    return fail(SMCRT_E_INVALID, "set_primitive_displacement: amplitude and frequency must be finite and >= 0");
+  s->prims[prim].disp_a = amplitude;
+  s->prims[prim].disp_f = frequency;
+  s->dirty = true;
+  return SMCRT_OK;
+}
+
+extern "C" smcrt_status smcrt_scene_set_primitive_repetition(smcrt_scene* s, int32_t prim, const double spacing[3],
+                                                             const int32_t counts[3]) {
+  if (!s || !spacing || !counts) return fail(SMCRT_E_INVALID, "set_primitive_repetition: NULL argument");
+  if (prim < 0 || prim >= (int32_t)s->prims.size()) return fail(SMCRT_E_INVALID, "set_primitive_repetition: no primitive %d", prim);
+  for (int i = 0; i < 3; ++i) {
+    if (counts[i] < 1 || counts[i] > 4096) return fail(SMCRT_E_INVALID, "set_primitive_repetition: counts must be in [1, 4096]");
+    if (!(spacing[i] > 0.0 && std::isfinite(spacing[i]))) return fail(SMCRT_E_INVALID, "set_primitive_repetition: spacing must be > 0");
+  }
+  HostPrim p = s->prims[prim];
+  std::memcpy(p.rep_c, spacing, sizeof(double) * 3);
+  std::memcpy(p.rep_n, counts, sizeof(int32_t) * 3);
+  if (repeated(p) && !(repetition_gap(p) > 0.0))
+    return fail(SMCRT_E_INVALID, "set_primitive_repetition: copies must fit their cells (set the other modifiers first)");
+  s->prims[prim] = p;
+  s->dirty = true;
+  return SMCRT_OK;
+}
+
 extern "C" smcrt_status smcrt_scene_set_relaxation(smcrt_scene* s, double omega) {
   if (!s) return fail(SMCRT_E_INVALID, "set_relaxation: NULL scene");
   if (!(omega >= 1.0 && omega < 2.0)) return fail(SMCRT_E_INVALID, "set_relaxation: omega must be in [1, 2)");
@@ -349,31 +395,36 @@ static void local_box(const HostPrim& p, double lo[3], double hi[3]) {
   }
 }
 
-// bounding cylinder about the local z axis of a twisted primitive: radius
-// 1.001 x the largest distance from the axis of its local box grown by
-// rounding and shell, z range that box's grown by 0.1 % of its length at
-// each end
-static void twist_cylinder(const HostPrim& p, double* rho, double* zlo, double* zhi) {
-  double lo[3], hi[3];
+// box of one copy of the modified shape in the primitive's frame: the local
+// box grown by the elongation per axis and by rounding, shell and
+// displacement amplitude on every side
+static void modified_box(const HostPrim& p, double lo[3], double hi[3]) {
   local_box(p, lo, hi);
-  const double g = p.round_r + p.onion_t;
-  double r2 = 0.0;
-  for (double x : {lo[0] - g, hi[0] + g})
-    for (double y : {lo[1] - g, hi[1] + g}) r2 = std::max(r2, x * x + y * y);
-  const double z0 = lo[2] - g, z1 = hi[2] + g, m = 1e-3 * (z1 - z0);
-  *rho = 1.001 * std::sqrt(r2);
-  *zlo = z0 - m;
-  *zhi = z1 + m;
+  const double g = p.round_r + p.onion_t + p.disp_a;
+  for (int i = 0; i < 3; ++i) {
+    lo[i] -= p.elong[i] + g;
+    hi[i] += p.elong[i] + g;
+  }
 }
 
-// conservative world box of a primitive: its local box (grown by rounding
-// and shell, or the twist's bounding cylinder's box) with the 8 corners
-// placed in the world
-static void prim_box(const HostPrim& p, double lo[3], double hi[3]) {
-  double a[3], b[3];
-  local_box(p, a, b);
-  const double g = p.round_r + p.onion_t;
-  for (int i = 0; i < 3; ++i) { a[i] -= g; b[i] += g; }
+// bounding cylinder about the local z axis of a twisted primitive: radius
+// 1.001 x the largest distance from the axis of its modified box, z range
+// that box's grown by 0.1 % of its length at each end
+static void twist_cylinder(const HostPrim& p, double* rho, double* zlo, double* zhi) {
+  double lo[3], hi[3];
+  modified_box(p, lo, hi);
+  double r2 = 0.0;
+  for (double x : {lo[0], hi[0]})
+    for (double y : {lo[1], hi[1]}) r2 = std::max(r2, x * x + y * y);
+  const double m = 1e-3 * (hi[2] - lo[2]);
+  *rho = 1.001 * std::sqrt(r2);
+  *zlo = lo[2] - m;
+  *zhi = hi[2] + m;
+}
+
+// box of one copy: the modified box, or the twist's bounding cylinder's box
+static void copy_box(const HostPrim& p, double a[3], double b[3]) {
+  modified_box(p, a, b);
   if (p.twist_k != 0.0) {
     double rho, z0, z1;
     twist_cylinder(p, &rho, &z0, &z1);
@@ -381,6 +432,31 @@ static void prim_box(const HostPrim& p, double lo[3], double hi[3]) {
     b[0] = b[1] = rho;
     a[2] = z0;
     b[2] = z1;
+  }
+}
+
+static bool repeated(const HostPrim& p) { return p.rep_n[0] > 1 || p.rep_n[1] > 1 || p.rep_n[2] > 1; }
+
+// smallest distance from a copy's box to a face of its cell that another
+// copy lies behind (<= 0: the copies do not fit their cells)
+static double repetition_gap(const HostPrim& p) {
+  double a[3], b[3];
+  copy_box(p, a, b);
+  double gap = 1e300;
+  for (int i = 0; i < 3; ++i)
+    if (p.rep_n[i] > 1) gap = std::min(gap, 0.5 * p.rep_c[i] - std::max(std::fabs(a[i]), std::fabs(b[i])));
+  return gap;
+}
+
+// conservative world box of a primitive: the box of one copy over the
+// repeated array, with the 8 corners placed in the world
+static void prim_box(const HostPrim& p, double lo[3], double hi[3]) {
+  double a[3], b[3];
+  copy_box(p, a, b);
+  for (int i = 0; i < 3; ++i) {
+    const double ext = 0.5 * (p.rep_n[i] - 1) * p.rep_c[i];
+    a[i] -= ext;
+    b[i] += ext;
   }
   if (!p.placed) {
     for (int i = 0; i < 3; ++i) { lo[i] = a[i]; hi[i] = b[i]; }
@@ -433,6 +509,9 @@ static smcrt_status check_complete(const smcrt_scene* s) {
     if (!(v[i] >= lo[i] && v[i] <= hi[i])) return fail(SMCRT_E_INVALID, "source outside the simulation volume");
   if (s->geometry == kGeomVoxel && !(s->grid_set && s->g_dims[0] > 0 && s->g_dims[1] > 0 && s->g_dims[2] > 0))
     return fail(SMCRT_E_INVALID, "the voxel geometry needs a fluence grid with dims >= 1 in every axis");
+  for (size_t i = 0; i < s->prims.size(); ++i)
+    if (repeated(s->prims[i]) && !(repetition_gap(s->prims[i]) > 0.0))
+      return fail(SMCRT_E_INVALID, "primitive %d: repeated copies no longer fit their cells", (int)i);
   return SMCRT_OK;
 }
 
@@ -474,8 +553,19 @@ static void pack_prim(const HostPrim& h, Prim<T>& o) {
     }
   }
   // placement and modifiers
+  const bool elongated = h.elong[0] != 0.0 || h.elong[1] != 0.0 || h.elong[2] != 0.0;
   o.flags = (h.placed ? kPlaced : 0) | (h.twist_k != 0.0 ? kTwisted : 0) |
-            ((h.round_r != 0.0 || h.onion_t != 0.0) ? kModified : 0);
+            ((h.round_r != 0.0 || h.onion_t != 0.0 || elongated || h.disp_a != 0.0) ? kModified : 0) |
+            (repeated(h) ? kRepeated : 0);
+  for (int i = 0; i < 3; ++i) {
+    o.elong[i] = (T)h.elong[i];
+    o.rep_c[i] = (T)h.rep_c[i];
+    o.rep_n[i] = h.rep_n[i];
+  }
+  o.disp_a = (T)h.disp_a;
+  o.disp_f = (T)h.disp_f;
+  o.disp_inv_lip = (T)(1.0 / (1.0 + h.disp_a * h.disp_f * std::sqrt(3.0)));
+  o.rep_gap = repeated(h) ? (T)repetition_gap(h) : T(0);
   for (int i = 0; i < 3; ++i)
     for (int j = 0; j < 3; ++j) o.m[3 * i + j] = (T)(h.rot[3 * j + i] / h.s);
   for (int i = 0; i < 3; ++i) o.t[i] = (T)h.t[i];
@@ -654,6 +744,11 @@ static smcrt_status pack(smcrt_scene* s) {
     h->g_hif[i] = (float)ghi[i];
   }
   h->geometry = s->geometry;
+  h->xf = 0;
+  for (const HostPrim& hp : s->prims)
+    if (hp.placed || hp.twist_k != 0.0 || hp.round_r != 0.0 || hp.onion_t != 0.0 || hp.disp_a != 0.0 || repeated(hp) ||
+        hp.elong[0] != 0.0 || hp.elong[1] != 0.0 || hp.elong[2] != 0.0)
+      h->xf = 1;
   h->src_kind = s->src_kind;
   std::memcpy(h->src, s->src, sizeof(h->src));
   h->det_face = s->det_face;
@@ -781,11 +876,11 @@ extern "C" smcrt_status smcrt_engine_set_opts(smcrt_engine* e, const smcrt_opts*
   return SMCRT_OK;
 }
 
-static LaunchCfg launch_cfg(smcrt_engine* e, int geometry) {
+static LaunchCfg launch_cfg(smcrt_engine* e, int launch_class) {
   LaunchCfg c;
   c.block = e->opts.block;
   int per_cu = e->opts.blocks_per_cu;
-  if (per_cu <= 0) per_cu = walk_max_blocks_per_cu(e->opts.precision, c.block, geometry);
+  if (per_cu <= 0) per_cu = walk_max_blocks_per_cu(e->opts.precision, c.block, launch_class);
   if (per_cu <= 0) per_cu = 1;
   c.grid = e->n_cu * per_cu;
   c.refill_min = e->opts.refill_min;
@@ -894,7 +989,7 @@ static smcrt_status launch_jobs(smcrt_engine* e, const std::vector<JobSpec>& job
     a.detector = h->det_face >= 0 ? jobs[j].detector : nullptr;
     a.tallies = jobs[j].tallies;
     a.acc_region = h->acc.region;
-    a.geometry = h->geometry;
+    a.geometry = h->geometry + (h->xf ? kLaunchXf : 0);  // launch class
     if (vox_n[u]) a.vox = vox_out ? vox_out : reinterpret_cast<uint8_t*>(base + vox_off[u]);
     if (h->acc.region >= 0) {
       const size_t cb = align256(sizeof(uint32_t) * ((size_t)h->acc.n_cells + 1));
@@ -934,9 +1029,10 @@ static smcrt_status launch_jobs(smcrt_engine* e, const std::vector<JobSpec>& job
   B.n_jobs = (int32_t)jobs.size();
   B.refill_min = e->opts.refill_min;
   B.surface_min = e->opts.surface_min;
-  bool has_geom[2] = {false, false};
-  for (size_t j = 0; j < jobs.size(); ++j) has_geom[table[j].geometry == kGeomVoxel ? 1 : 0] = true;
-  LaunchCfg cg[2] = {launch_cfg(e, kGeomSdf), launch_cfg(e, kGeomVoxel)};
+  bool has_geom[kLaunchClasses] = {false, false, false, false};
+  for (size_t j = 0; j < jobs.size(); ++j) has_geom[table[j].geometry] = true;
+  LaunchCfg cg[kLaunchClasses];
+  for (int g = 0; g < kLaunchClasses; ++g) cg[g] = launch_cfg(e, g);
   if (tr) {
     for (LaunchCfg& c : cg) {
       c.block = 64;
@@ -966,20 +1062,22 @@ static smcrt_status launch_jobs(smcrt_engine* e, const std::vector<JobSpec>& job
     }
     if (vox_out) return SMCRT_OK;
     HIP_TRY(launch_zero_u64_n(reinterpret_cast<unsigned long long*>(base + counters_off), (int)jobs.size(), q), "zero counters");
-    for (int g = 0; g < 2; ++g) {
+    for (int g = 0; g < kLaunchClasses; ++g) {
       if (!has_geom[g]) continue;
       BatchArgs Bg = B;
-      Bg.geometry = g == 1 ? kGeomVoxel : kGeomSdf;
+      Bg.geometry = g;
       HIP_TRY(launch_walk(e->opts.precision, tr != nullptr, cg[g], Bg, q), "walk kernel");
     }
     return SMCRT_OK;
   };
   if (!e->opts.use_graph || tr || vox_out) return enqueue(st);
   // replay the captured sequence when the launch shape is the same
-  std::vector<uint64_t> key = {(uint64_t)(uintptr_t)base, image_bytes, total, jobs.size(), (uint64_t)cg[0].grid,
-                               (uint64_t)cg[1].grid, (uint64_t)cg[0].block, (uint64_t)e->opts.precision,
-                               (uint64_t)B.refill_min, (uint64_t)B.surface_min, (uint64_t)has_geom[0],
-                               (uint64_t)has_geom[1]};
+  std::vector<uint64_t> key = {(uint64_t)(uintptr_t)base, image_bytes, total, jobs.size(), (uint64_t)cg[0].block,
+                               (uint64_t)e->opts.precision, (uint64_t)B.refill_min, (uint64_t)B.surface_min};
+  for (int g = 0; g < kLaunchClasses; ++g) {
+    key.push_back((uint64_t)cg[g].grid);
+    key.push_back((uint64_t)has_geom[g]);
+  }
   for (size_t u = 0; u < uniq.size(); ++u) {
     const Accel& A = reinterpret_cast<const SceneHeader*>(uniq[u]->blob.data())->acc;
     key.push_back(blob_off[u]);

@@ -22,7 +22,7 @@ hipError_t launch_scale(const double* in, double* out, size_t n, double scale, h
 // cursors: n_cells each; offsets: n_cells + 1; ids: the capacity in the header)
 hipError_t launch_accel_build(const SceneHeader* d_sc, const PrimD* d_pd, int n_prims, int n_cells, uint32_t* counts,
                               uint32_t* cursors, uint32_t* offsets, uint32_t* ids, hipStream_t stream);
-// resident workgroups per CU of the walk kernel of this geometry at this block size
-int walk_max_blocks_per_cu(int precision, int block, int geometry);
+// resident workgroups per CU of the walk kernel of this launch class at this block size
+int walk_max_blocks_per_cu(int precision, int block, int launch_class);
 
 }  // namespace smcrt

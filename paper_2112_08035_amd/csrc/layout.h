@@ -20,6 +20,9 @@ enum SourceKind : int32_t { kPoint = 0, kPencil = 1, kDisc = 2, kRect = 3 };
 // the voxel grid they induce (region of each voxel centre) -- the voxelised
 // comparison model of Sec. 3
 enum Geometry : int32_t { kGeomSdf = 0, kGeomVoxel = 1 };
+// launch class of a job: its geometry model, plus kLaunchXf when its scene
+// has placed or modified primitives (a separate kernel instantiation)
+enum LaunchClass : int32_t { kLaunchXf = 2, kLaunchClasses = 4 };
 
 // Primitive parameters, precomputed on the host:
 //   sphere   : c0 c1 c2 r
@@ -28,12 +31,18 @@ enum Geometry : int32_t { kGeomSdf = 0, kGeomVoxel = 1 };
 //   cylinder : a0 a1 a2 e0 e1 e2 L L/2 r          (e = unit axis)
 //   torus    : c0 c1 c2 e0 e1 e2 R r              (e = unit axis)
 // A primitive may be placed (local = m (p - t), m = R^T / s, distance times
-// s), rounded or made an onion shell (in its own frame, exact), and twisted
-// about its local z axis: inside the bounding cylinder (radius twist_rho,
-// z in twist_zc -/+ twist_zh) the distance of the untwisted shape is
+// s).  In its own frame the query point is taken to the nearest of the
+// repeated copies (offsets (i - (n-1)/2) rep_c, i = 0..n-1 per axis),
+// untwisted about z and elongated (q - clamp(q, -elong, elong)); the shape's
+// distance there is rounded, made an onion shell and displaced (plus
+// disp_a sin(f x) sin(f y) sin(f z) at the unelongated point, times
+// disp_inv_lip = 1/(1 + disp_a disp_f sqrt 3)).  Twist: inside the bounding
+// cylinder (radius twist_rho, z in twist_zc -/+ twist_zh) the distance is
 // multiplied by inv_lip = 1/sqrt(1 + (twist_k twist_rho)^2), outside it the
-// distance to the cylinder is used.  flags = 0: the plain shape.
-enum PrimFlags { kPlaced = 1, kTwisted = 2, kModified = 4 };
+// distance to the cylinder is used.  Repetition: the smaller of that and
+// rep_gap plus the distance to the nearest cell face with another copy
+// behind it.  flags = 0: the plain shape.
+enum PrimFlags { kPlaced = 1, kTwisted = 2, kModified = 4, kRepeated = 8 };
 template <typename T>
 struct Prim {
   int32_t kind;
@@ -42,6 +51,9 @@ struct Prim {
   T m[9], t[3], s;
   T round_r, onion_t;
   T twist_k, twist_rho, twist_zc, twist_zh, inv_lip;
+  T elong[3], disp_a, disp_f, disp_inv_lip;
+  T rep_c[3], rep_gap;
+  int32_t rep_n[3], pad;
   double box_lo[3], box_hi[3];  // world box, for the acceleration build
 };
 using PrimD = Prim<double>;
@@ -91,7 +103,8 @@ struct SceneHeader {
   // escape image: face 2*axis + side, pixels over [det_lo, det_hi] in the
   // face's two other axes (increasing axis order, first fastest); det_face
   // -1 = none
-  int32_t det_face, det_dims[2], pad_det;
+  int32_t det_face, det_dims[2];
+  int32_t xf;                     // some primitive is placed or modified
   double det_lo[2], det_hi[2];
   double w_threshold, m_d, inv_m;
   float deltaf, relaxf;
@@ -130,7 +143,7 @@ struct WalkArgs {
   int32_t* trace_count;
   int32_t n_trace, max_records;
   int32_t acc_region;            // copy of sc->acc.region (-1 = none)
-  int32_t geometry;              // copy of sc->geometry
+  int32_t geometry;              // launch class: sc->geometry, plus kLaunchXf when sc->xf
   uint8_t* vox;                  // voxel model: region slot per voxel (nx*ny*nz, x fastest)
   double* detector;              // escape image (det_dims[0] * det_dims[1]), may be null
 };
@@ -140,7 +153,7 @@ struct BatchArgs {
   const WalkArgs* jobs;
   int32_t n_jobs;
   int32_t refill_min, surface_min;
-  int32_t geometry;              // the launch takes only the jobs of this geometry
+  int32_t geometry;              // the launch takes only the jobs of this launch class
 };
 
 }  // namespace smcrt

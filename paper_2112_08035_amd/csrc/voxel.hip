@@ -22,7 +22,7 @@ __global__ void __launch_bounds__(256) voxelize_kernel(const WalkArgs* __restric
     const int iz = (int)(r / (size_t)ny);
     const V3<double> c = mk(sc->g_lo[0] + (ix + 0.5) * sc->g_d[0], sc->g_lo[1] + (iy + 0.5) * sc->g_d[1],
                             sc->g_lo[2] + (iz + 0.5) * sc->g_d[2]);
-    vox[i] = (uint8_t)region_of<double>(a, c);
+    vox[i] = (uint8_t)region_of<double, true>(a, c);
   }
 }
 

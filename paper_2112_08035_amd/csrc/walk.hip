@@ -33,22 +33,22 @@ namespace smcrt {
 // surface, numerical normal, the hit where the ray meets the surface, a
 // probe across it for the medium ahead, then cross, reflect or refract.
 // Sets pk.state to kTransport or kInteract.
-template <typename T, bool TRACE>
+template <typename T, bool TRACE, bool XF>
 __device__ void surface(JobRef a, Packet<T>& pk, Lane& ln, LdsTallies& L) {
   ScP sc = kptr(a.sc);
   const V3<double> p = to_d(pk.p), u = to_d(pk.u);
   const int nr = sc->n_regions;
   int j = 0;
-  double dj = region_dist<double>(a, 0, p);
+  double dj = region_dist<double, XF>(a, 0, p);
   for (int r = 1; r < nr; ++r) {
-    const double d = region_dist<double>(a, r, p);
+    const double d = region_dist<double, XF>(a, r, p);
     if (__builtin_fabs(d) < __builtin_fabs(dj)) {
       dj = d;
       j = r;
     }
   }
   const double h = sc->h_normal, off = sc->offset;
-  const V3<double> n0 = region_normal(a, j, p, h);
+  const V3<double> n0 = region_normal<XF>(a, j, p, h);
   const double c0 = dot(u, n0);
   double t_ray = 0.0;
   V3<double> ps;
@@ -58,11 +58,11 @@ __device__ void surface(JobRef a, Packet<T>& pk, Lane& ln, LdsTallies& L) {
   } else {
     ps = p - dj * n0;
   }
-  const V3<double> nrm = region_normal(a, j, ps, h);
+  const V3<double> nrm = region_normal<XF>(a, j, ps, h);
   const double c = dot(u, nrm);
   const double sg = c > 0.0 ? 1.0 : -1.0;
   const V3<double> q = ps + (sg * off) * nrm;
-  const int r2 = (c == 0.0) ? pk.region : region_of<double>(a, q);
+  const int r2 = (c == 0.0) ? pk.region : region_of<double, XF>(a, q);
   RegRef R1 = sc->reg[pk.region];
   double tau = pk.tau;
   const double s_rem = R1.mut > 0.0 ? tau / R1.mut : __builtin_inf();
@@ -140,7 +140,7 @@ __device__ void surface(JobRef a, Packet<T>& pk, Lane& ln, LdsTallies& L) {
 // GEOM selects the geometry model: sphere tracing through the SDFs, or the
 // voxel walk of the voxelised comparison model; the launch takes only the
 // jobs of that model.
-template <typename T, bool TRACE, int GEOM>
+template <typename T, bool TRACE, int GEOM, bool XF>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 4 : 3)))
 walk_kernel(const WalkArgs* __restrict__ job_table, BatchArgs B) {
   const SMCRT_K WalkArgs* jobs = kptr(job_table);
@@ -200,7 +200,7 @@ walk_kernel(const WalkArgs* __restrict__ job_table, BatchArgs B) {
         ln.rec = reinterpret_cast<smcrt_event*>(a.trace_out) + (size_t)id * a.max_records;
         pk.pid = a.trace_ids[id];
         live = true;
-        emit<T, TRACE>(a, pk, ln, L);
+        emit<T, TRACE, XF>(a, pk, ln, L);
         if constexpr (GEOM == kGeomVoxel) live = enter_grid<T, TRACE>(a, pk, vx, ln, L);
       }
     }
@@ -222,7 +222,7 @@ walk_kernel(const WalkArgs* __restrict__ job_table, BatchArgs B) {
             if (id < a.n) {
               pk.pid = a.first + id;
               live = true;
-              emit<T, TRACE>(a, pk, ln, L);
+              emit<T, TRACE, XF>(a, pk, ln, L);
               if constexpr (GEOM == kGeomVoxel) live = enter_grid<T, TRACE>(a, pk, vx, ln, L);
             }
           }
@@ -249,7 +249,7 @@ walk_kernel(const WalkArgs* __restrict__ job_table, BatchArgs B) {
         } else {
           ++ln.n_steps;
           T dmin = tinf<T>();
-          for (int r = 0; r < nr; ++r) dmin = tmin(dmin, tabs(region_dist<T>(a, r, pk.p)));
+          for (int r = 0; r < nr; ++r) dmin = tmin(dmin, tabs(region_dist<T, XF>(a, r, pk.p)));
           int face;
           const T dbb = volume_sdf<T>(sc, pk.p, &face);
           bool rejected = false;
@@ -306,7 +306,7 @@ walk_kernel(const WalkArgs* __restrict__ job_table, BatchArgs B) {
         const uint64_t smask = __ballot(live && pk.state == kSurface);
         const int nsurf = __popcll(smask);
         if (nsurf > 0 && (nsurf >= B.surface_min || nsurf == __popcll(__ballot(live)))) {
-          if (live && pk.state == kSurface) surface<T, TRACE>(a, pk, ln, L);
+          if (live && pk.state == kSurface) surface<T, TRACE, XF>(a, pk, ln, L);
         }
       }
 
@@ -347,25 +347,31 @@ __global__ void scale_kernel(const double* __restrict__ in, double* __restrict__
     out[i] = in[i] * s;
 }
 
-template <int GEOM>
+template <int GEOM, bool XF>
 static void launch_geom(int precision, bool trace, dim3 grid, dim3 block, const BatchArgs& args, hipStream_t stream) {
   if (precision == 1) {
-    if (trace) hipLaunchKernelGGL((walk_kernel<double, true, GEOM>), grid, block, 0, stream, args.jobs, args);
-    else hipLaunchKernelGGL((walk_kernel<double, false, GEOM>), grid, block, 0, stream, args.jobs, args);
+    if (trace) hipLaunchKernelGGL((walk_kernel<double, true, GEOM, XF>), grid, block, 0, stream, args.jobs, args);
+    else hipLaunchKernelGGL((walk_kernel<double, false, GEOM, XF>), grid, block, 0, stream, args.jobs, args);
   } else {
-    if (trace) hipLaunchKernelGGL((walk_kernel<float, true, GEOM>), grid, block, 0, stream, args.jobs, args);
-    else hipLaunchKernelGGL((walk_kernel<float, false, GEOM>), grid, block, 0, stream, args.jobs, args);
+    if (trace) hipLaunchKernelGGL((walk_kernel<float, true, GEOM, XF>), grid, block, 0, stream, args.jobs, args);
+    else hipLaunchKernelGGL((walk_kernel<float, false, GEOM, XF>), grid, block, 0, stream, args.jobs, args);
   }
 }
 
+// args.geometry is the launch class: the geometry model plus kLaunchXf when
+// the jobs' scenes have placed or modified primitives
 hipError_t launch_walk(int precision, bool trace, const LaunchCfg& cfg, const BatchArgs& args, hipStream_t stream) {
   if (!args.jobs || args.n_jobs < 1 || (trace && args.n_jobs != 1)) return hipErrorInvalidValue;
   if (args.refill_min < 1 || args.refill_min > 64 || args.surface_min < 1 || args.surface_min > 64) return hipErrorInvalidValue;
-  if (args.geometry != kGeomSdf && args.geometry != kGeomVoxel) return hipErrorInvalidValue;
+  if (args.geometry < 0 || args.geometry >= kLaunchClasses) return hipErrorInvalidValue;
   if (cfg.block < 64 || cfg.block > 256 || cfg.block % 64 || cfg.grid < 1) return hipErrorInvalidConfiguration;
   dim3 grid(cfg.grid), block(cfg.block);
-  if (args.geometry == kGeomVoxel) launch_geom<kGeomVoxel>(precision, trace, grid, block, args, stream);
-  else launch_geom<kGeomSdf>(precision, trace, grid, block, args, stream);
+  switch (args.geometry) {
+    case kGeomSdf: launch_geom<kGeomSdf, false>(precision, trace, grid, block, args, stream); break;
+    case kGeomVoxel: launch_geom<kGeomVoxel, false>(precision, trace, grid, block, args, stream); break;
+    case kGeomSdf + kLaunchXf: launch_geom<kGeomSdf, true>(precision, trace, grid, block, args, stream); break;
+    default: launch_geom<kGeomVoxel, true>(precision, trace, grid, block, args, stream); break;
+  }
   return hipGetLastError();
 }
 
@@ -393,15 +399,21 @@ hipError_t launch_scale(const double* in, double* out, size_t n, double scale, h
   return hipGetLastError();
 }
 
-int walk_max_blocks_per_cu(int precision, int block, int geometry) {
+template <int GEOM, bool XF>
+static hipError_t occupancy(int* n, int precision, int block) {
+  return precision == 1 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(n, walk_kernel<double, false, GEOM, XF>, block, 0)
+                        : hipOccupancyMaxActiveBlocksPerMultiprocessor(n, walk_kernel<float, false, GEOM, XF>, block, 0);
+}
+
+int walk_max_blocks_per_cu(int precision, int block, int launch_class) {
   int n = 0;
   hipError_t e;
-  if (geometry == kGeomVoxel)
-    e = precision == 1 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, walk_kernel<double, false, kGeomVoxel>, block, 0)
-                       : hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, walk_kernel<float, false, kGeomVoxel>, block, 0);
-  else
-    e = precision == 1 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, walk_kernel<double, false, kGeomSdf>, block, 0)
-                       : hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, walk_kernel<float, false, kGeomSdf>, block, 0);
+  switch (launch_class) {
+    case kGeomSdf: e = occupancy<kGeomSdf, false>(&n, precision, block); break;
+    case kGeomVoxel: e = occupancy<kGeomVoxel, false>(&n, precision, block); break;
+    case kGeomSdf + kLaunchXf: e = occupancy<kGeomSdf, true>(&n, precision, block); break;
+    default: e = occupancy<kGeomVoxel, true>(&n, precision, block); break;
+  }
   return e == hipSuccess ? n : 0;
 }
 

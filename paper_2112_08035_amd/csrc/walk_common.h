@@ -192,9 +192,10 @@ __device__ __forceinline__ T shape_sdf(const SMCRT_K Prim<T>* P, int i, V3<T> p)
   return tmin(tmax(q1, q2), T(0)) + tsqrt(o1 * o1 + o2 * o2);
 }
 
-// sin and cos of a twist angle (a few radians): Cody-Waite reduction by
-// pi/2 in two parts to r in [-pi/4, pi/4], then the Taylor series of sin and
-// cos to r^17 / r^16 (FP64: last term < 4e-18) or r^11 / r^10 (FP32: < 1e-9),
+// sin and cos of a twist or displacement angle (moderate arguments):
+// Cody-Waite reduction by pi/2, split into the precision's nearest value and
+// its residual, to r in [-pi/4, pi/4], then the Taylor series of sin and cos
+// to r^17 / r^16 (FP64: last term < 4e-18) or r^11 / r^10 (FP32: < 1e-9),
 // evaluated by Horner's rule; the quadrant n mod 4 picks signs and order.
 // Kept in registers: the library routine's reduction for huge arguments
 // needs a stack array, which in the sphere-tracing loop moved other
@@ -202,7 +203,10 @@ __device__ __forceinline__ T shape_sdf(const SMCRT_K Prim<T>* P, int i, V3<T> p)
 template <typename T>
 __device__ __forceinline__ void tsincos(T a, T* sn, T* cs) {
   const T n = rint(a * T(0.63661977236758134308));  // 2/pi
-  const T r = (a - n * T(1.5707963267948966)) - n * T(6.123233995736766e-17);
+  // pi/2 = hi + lo: FP64 0x3FF921FB54442D18 + 6.1232e-17, FP32 0x3FC90FDB - 4.3711e-8
+  const T hi = sizeof(T) == 8 ? T(1.5707963267948966) : T(1.57079637050628662109375);
+  const T lo = sizeof(T) == 8 ? T(6.123233995736766e-17) : T(-4.371139000186241e-08);
+  const T r = (a - n * hi) - n * lo;
   const T r2 = r * r;
   T s, c;
   if constexpr (sizeof(T) == 8) {
@@ -259,6 +263,23 @@ __device__ __attribute__((noinline)) T placed_prim_sdf(const SMCRT_K Prim<T>* P,
     q = mk(Q.m[0] * d.x + Q.m[1] * d.y + Q.m[2] * d.z, Q.m[3] * d.x + Q.m[4] * d.y + Q.m[5] * d.z,
            Q.m[6] * d.x + Q.m[7] * d.y + Q.m[8] * d.z);
   }
+  // repetition: to the nearest copy; b = distance to the nearest face of its
+  // cell with another copy behind it
+  T b = tinf<T>();
+  if (fl & kRepeated) {
+    T c3[3] = {q.x, q.y, q.z};
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      const int n = Q.rep_n[a];
+      const T c = Q.rep_c[a], half = T(0.5) * T(n - 1) * c;
+      int k = (int)floor((c3[a] + half) / c + T(0.5));
+      k = k < 0 ? 0 : (k > n - 1 ? n - 1 : k);
+      c3[a] -= T(k) * c - half;
+      if (c3[a] > T(0) && k < n - 1) b = tmin(b, T(0.5) * c - c3[a]);
+      if (c3[a] < T(0) && k > 0) b = tmin(b, T(0.5) * c + c3[a]);
+    }
+    q = mk(c3[0], c3[1], c3[2]);
+  }
   T dcyl = T(0);
   if (fl & kTwisted) {  // distance to the bounding cylinder, then untwist by -k z about z
     const T q1 = tsqrt(q.x * q.x + q.y * q.y) - Q.twist_rho;
@@ -269,17 +290,33 @@ __device__ __attribute__((noinline)) T placed_prim_sdf(const SMCRT_K Prim<T>* P,
     tsincos(-Q.twist_k * q.z, &sn, &cs);
     q = mk(cs * q.x - sn * q.y, sn * q.x + cs * q.y, q.z);
   }
-  T d = shape_sdf(P, i, q) - Q.round_r;
+  const V3<T> e = mk(q.x - tclamp(q.x, -Q.elong[0], Q.elong[0]), q.y - tclamp(q.y, -Q.elong[1], Q.elong[1]),
+                     q.z - tclamp(q.z, -Q.elong[2], Q.elong[2]));
+  T d = shape_sdf(P, i, e) - Q.round_r;
   if (Q.onion_t > T(0)) d = tabs(d) - Q.onion_t;
+  if (Q.disp_a > T(0)) {
+    T sx, cx, sy, cy, sz, cz;
+    tsincos(Q.disp_f * q.x, &sx, &cx);
+    tsincos(Q.disp_f * q.y, &sy, &cy);
+    tsincos(Q.disp_f * q.z, &sz, &cz);
+    d = (d + Q.disp_a * sx * sy * sz) * Q.disp_inv_lip;
+  }
   if (fl & kTwisted) d = dcyl > T(0) ? dcyl : d * Q.inv_lip;
+  if (fl & kRepeated) d = tmin(d, Q.rep_gap + b);
   if (fl & kPlaced) d *= Q.s;
   return d;
 }
 
-template <typename T>
+// XF: the scene has placed or modified primitives.  Scenes without them
+// run kernels that never call placed_prim_sdf: a call in the sphere-tracing
+// loop makes the caller keep its live values out of the registers the
+// callee may use, which pushed the FP32 walk over its register budget.
+template <typename T, bool XF>
 __device__ __forceinline__ T prim_sdf(const SMCRT_K Prim<T>* P, int i, V3<T> p) {
-  if (P[i].flags == 0) return shape_sdf(P, i, p);
-  return placed_prim_sdf(P, i, p);
+  if constexpr (XF) {
+    if (P[i].flags != 0) return placed_prim_sdf<T>(P, i, p);
+  }
+  return shape_sdf(P, i, p);
 }
 
 // region SDF from its primitives in order (CSG of Sec. 2.2): union (min),
@@ -287,13 +324,13 @@ __device__ __forceinline__ T prim_sdf(const SMCRT_K Prim<T>* P, int i, V3<T> p) 
 // primitive minus the others (max(d, -d_i)).  Intersection and difference
 // are lower bounds of the distance with Lipschitz constant 1, so sphere
 // tracing stays conservative.
-template <typename T>
+template <typename T, bool XF>
 __device__ __forceinline__ T region_sdf(JobRef a, RegRef R, V3<T> p) {
   const SMCRT_K Prim<T>* P = Tab<T>::prims(a);
   const int op = R.op;  // wave uniform: one loop, primitive SDFs inlined once
-  T d = prim_sdf(P, R.first, p);
+  T d = prim_sdf<T, XF>(P, R.first, p);
   for (int i = 1; i < R.count; ++i) {
-    const T b = prim_sdf(P, R.first + i, p);
+    const T b = prim_sdf<T, XF>(P, R.first + i, p);
     if (op == kSmoothUnion) {
       const T h = tclamp(T(0.5) + T(0.5) * (b - d) * Tab<T>::inv_k(R), T(0), T(1));
       d = h * d + (T(1) - h) * b - Tab<T>::k(R) * h * (T(1) - h);
@@ -310,7 +347,7 @@ __device__ __forceinline__ T region_sdf(JobRef a, RegRef R, V3<T> p) {
 // that is below the margin, a lower bound elsewhere; outside the grid box
 // (which is the primitives' box grown by the margin) the distance to the
 // primitives' box is the lower bound.  Every index is checked.
-template <typename T>
+template <typename T, bool XF>
 __device__ __forceinline__ T accel_sdf(JobRef a, V3<T> p) {
   const SMCRT_K Accel& A = kptr(a.sc)->acc;
   const V3<T> lo = Tab<T>::acc_lo(A), ic = Tab<T>::acc_inv(A);
@@ -337,27 +374,27 @@ __device__ __forceinline__ T accel_sdf(JobRef a, V3<T> p) {
   T d = Tab<T>::acc_margin(A);
   for (uint64_t i = b; i < e; ++i) {
     const uint32_t id = ids[i];
-    if (id >= lo_id && id < hi_id) d = tmin(d, prim_sdf(P, (int)id, p));
+    if (id >= lo_id && id < hi_id) d = tmin(d, prim_sdf<T, XF>(P, (int)id, p));
   }
   return d;
 }
 
 // SDF of region r (through the grid when r is the accelerated region)
-template <typename T>
+template <typename T, bool XF>
 __device__ __forceinline__ T region_dist(JobRef a, int r, V3<T> p) {
-  if (r == a.acc_region) return accel_sdf<T>(a, p);
-  return region_sdf<T>(a, kptr(a.sc)->reg[r], p);
+  if (r == a.acc_region) return accel_sdf<T, XF>(a, p);
+  return region_sdf<T, XF>(a, kptr(a.sc)->reg[r], p);
 }
 
 // owner of a point: the highest-index region with a negative SDF, else the
 // ambient slot n_regions
-template <typename T>
+template <typename T, bool XF>
 __device__ __forceinline__ int region_of(JobRef a, V3<T> p) {
   ScP sc = kptr(a.sc);
   const int nr = sc->n_regions;
   int owner = nr;
   for (int r = nr - 1; r >= 0; --r) {
-    if (region_dist<T>(a, r, p) < T(0)) {
+    if (region_dist<T, XF>(a, r, p) < T(0)) {
       owner = r;
       break;
     }
@@ -382,11 +419,12 @@ __device__ __forceinline__ T volume_sdf(ScP sc, V3<T> p, int* face) {
 }
 
 // unit outward normal of region R at p by central differences of step h
+template <bool XF>
 __device__ __forceinline__ V3<double> region_normal(JobRef a, int r, V3<double> p, double h) {
   V3<double> n;
-  n.x = region_dist<double>(a, r, mk(p.x + h, p.y, p.z)) - region_dist<double>(a, r, mk(p.x - h, p.y, p.z));
-  n.y = region_dist<double>(a, r, mk(p.x, p.y + h, p.z)) - region_dist<double>(a, r, mk(p.x, p.y - h, p.z));
-  n.z = region_dist<double>(a, r, mk(p.x, p.y, p.z + h)) - region_dist<double>(a, r, mk(p.x, p.y, p.z - h));
+  n.x = region_dist<double, XF>(a, r, mk(p.x + h, p.y, p.z)) - region_dist<double, XF>(a, r, mk(p.x - h, p.y, p.z));
+  n.y = region_dist<double, XF>(a, r, mk(p.x, p.y + h, p.z)) - region_dist<double, XF>(a, r, mk(p.x, p.y - h, p.z));
+  n.z = region_dist<double, XF>(a, r, mk(p.x, p.y, p.z + h)) - region_dist<double, XF>(a, r, mk(p.x, p.y, p.z - h));
   const double inv = 1.0 / __builtin_sqrt(dot(n, n));
   return inv * n;
 }
@@ -721,7 +759,7 @@ __device__ __forceinline__ void add_absorbed(LdsTallies& L, Lane& ln, int r, dou
 }
 
 // emission, event 0 (Sec. 3.1 sources; Eq. 1)
-template <typename T, bool TRACE>
+template <typename T, bool TRACE, bool XF>
 __device__ void emit(JobRef a, Packet<T>& pk, Lane& ln, LdsTallies& L) {
   ScP sc = kptr(a.sc);
   const U4 r = philox10(0u, (uint32_t)pk.pid, (uint32_t)(pk.pid >> 32), 0u, (uint32_t)a.seed, (uint32_t)(a.seed >> 32));
@@ -759,7 +797,7 @@ __device__ void emit(JobRef a, Packet<T>& pk, Lane& ln, LdsTallies& L) {
   pk.pl = T(0);
   pk.pend = T(0);
   pk.state = kTransport;
-  set_region(sc, pk, region_of<T>(a, p));
+  set_region(sc, pk, region_of<T, XF>(a, p));
   atomicAdd(&L.cnt[kCLaunched], 1ull);
   record<T, TRACE>(a, pk, ln, SMCRT_EV_EMIT);
 }

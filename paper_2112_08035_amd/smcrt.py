@@ -86,6 +86,9 @@ _SIGS = {
     "smcrt_scene_set_relaxation": ([_vp, C.c_double], C.c_int),
     "smcrt_scene_set_primitive_placement": ([_vp, C.c_int32, _dp, C.c_double, _dp], C.c_int),
     "smcrt_scene_set_primitive_modifiers": ([_vp, C.c_int32, C.c_double, C.c_double, C.c_double], C.c_int),
+    "smcrt_scene_set_primitive_elongation": ([_vp, C.c_int32, _dp], C.c_int),
+    "smcrt_scene_set_primitive_displacement": ([_vp, C.c_int32, C.c_double, C.c_double], C.c_int),
+    "smcrt_scene_set_primitive_repetition": ([_vp, C.c_int32, _dp, C.POINTER(C.c_int32)], C.c_int),
     "smcrt_scene_set_accel": ([_vp, C.c_int32, C.POINTER(C.c_int32)], C.c_int),
     "smcrt_scene_set_geometry": ([_vp, C.c_int], C.c_int),
     "smcrt_scene_set_detector": ([_vp, C.c_int, _dp, _dp, C.POINTER(C.c_int32)], C.c_int),
@@ -171,6 +174,19 @@ def smcrt_scene_set_primitive_placement(scene, prim, rot, scale, trans):
 
 def smcrt_scene_set_primitive_modifiers(scene, prim, round_r, onion_t, twist_k):
     _check(lib().smcrt_scene_set_primitive_modifiers(scene, prim, round_r, onion_t, twist_k))
+
+
+def smcrt_scene_set_primitive_elongation(scene, prim, h):
+    _check(lib().smcrt_scene_set_primitive_elongation(scene, prim, _darr(h)))
+
+
+def smcrt_scene_set_primitive_displacement(scene, prim, amplitude, frequency):
+    _check(lib().smcrt_scene_set_primitive_displacement(scene, prim, amplitude, frequency))
+
+
+def smcrt_scene_set_primitive_repetition(scene, prim, spacing, counts):
+    _check(lib().smcrt_scene_set_primitive_repetition(scene, prim, _darr(spacing),
+                                                      (C.c_int32 * 3)(*[int(c) for c in counts])))
 
 
 def smcrt_scene_add_region(scene, prims, op, k_cm, mu_a, mu_s, g, n):
@@ -351,6 +367,13 @@ class Scene:
             if p.get("round", 0.0) or p.get("onion", 0.0) or p.get("twist", 0.0):
                 smcrt_scene_set_primitive_modifiers(self.h, pid, float(p.get("round", 0.0)),
                                                     float(p.get("onion", 0.0)), float(p.get("twist", 0.0)))
+            if p.get("elongate"):
+                smcrt_scene_set_primitive_elongation(self.h, pid, [float(x) for x in p["elongate"]])
+            if p.get("displace"):
+                smcrt_scene_set_primitive_displacement(self.h, pid, float(p["displace"]["a"]), float(p["displace"]["f"]))
+            if p.get("repeat"):
+                smcrt_scene_set_primitive_repetition(self.h, pid, [float(x) for x in p["repeat"]["c"]],
+                                                     [int(x) for x in p["repeat"]["n"]])
         for rg in desc["regions"]:
             smcrt_scene_add_region(self.h, [ids[i] for i in rg["prims"]], OP[rg["op"]], rg.get("k", 0.0),
                                    rg["mua"], rg["mus"], rg["g"], rg["n"])

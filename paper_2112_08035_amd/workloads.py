@@ -416,7 +416,8 @@ def gallery_scene(n_grid=64):
     - a glass box (n 1.5, weakly absorbing) turned 30 deg about (1, 1, 0);
     - a twisted bar (1 rad/cm) of absorbing tissue;
     - a rounded capsule and a scaled torus of blood (one union region);
-    - an onion shell of a sphere of dense scatterer."""
+    - an onion shell of a displaced (bumpy) sphere of dense scatterer;
+    - a 3 x 2 array of elongated spheres (capsule-like rods) of glass."""
     prims = [
         {"kind": "box", "c": [0.0, 0.0, 0.0], "half": [1.0, 1.0, 1.0]},
         {"kind": "box", "c": [0.0, 0.0, 0.0], "half": [0.3, 0.2, 0.15],
@@ -426,8 +427,11 @@ def gallery_scene(n_grid=64):
         {"kind": "capsule", "a": [-0.6, -0.5, -0.3], "b": [0.5, -0.6, -0.2], "r": 0.04, "round": 0.03},
         {"kind": "torus", "c": [0.0, 0.0, 0.0], "axis": [0.0, 0.0, 1.0], "R": 1.0, "r": 0.2,
          "transform": {"R": rotation([0, 1, 0], 0.4), "t": [0.3, 0.3, -0.5], "s": 0.35}},
-        {"kind": "sphere", "c": [0.0, 0.0, 0.0], "r": 0.25, "onion": 0.06,
+        {"kind": "sphere", "c": [0.0, 0.0, 0.0], "r": 0.25, "onion": 0.06, "displace": {"a": 0.01, "f": 25.0},
          "transform": {"R": rotation([0, 0, 1], 0.0), "t": [-0.45, 0.5, -0.45], "s": 1.0}},
+        {"kind": "sphere", "c": [0.0, 0.0, 0.0], "r": 0.05, "elongate": [0.1, 0.0, 0.0],
+         "repeat": {"c": [0.35, 0.2, 1.0], "n": [3, 2, 1]},
+         "transform": {"R": rotation([0, 0, 1], 0.3), "t": [0.45, -0.45, 0.0], "s": 1.0}},
     ]
     regions = [
         _region([0], 0.1, 20.0, 0.9, 1.33),
@@ -435,6 +439,7 @@ def gallery_scene(n_grid=64):
         _region([2], 2.0, 80.0, 0.9, 1.4),
         _region([3, 4], 20.0, 400.0, 0.98, 1.4),
         _region([5], 0.5, 300.0, 0.8, 1.45),
+        _region([6], 0.02, 0.0, 0.0, 1.5),
     ]
     grid = {"lo": [-1.0] * 3, "hi": [1.0] * 3, "dims": [n_grid] * 3}
     sc = _scene("gallery", prims, regions, None, grid)

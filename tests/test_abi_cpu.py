@@ -284,3 +284,22 @@ def test_primitive_placement_and_modifier_validation(S):
     finally:
         S.smcrt_scene_destroy(h)
 
+
+
+def test_elongation_displacement_repetition_validation(S):
+    h = S.smcrt_scene_create(1.0, 1e-5, 1e-4)
+    try:
+        p = S.smcrt_scene_add_primitive(h, 0, [0, 0, 0, 0.1])
+        with pytest.raises(S.SmcrtError, match="h must be"):
+            S.smcrt_scene_set_primitive_elongation(h, p, [-0.1, 0, 0])
+        S.smcrt_scene_set_primitive_elongation(h, p, [0.1, 0, 0])
+        with pytest.raises(S.SmcrtError, match="amplitude"):
+            S.smcrt_scene_set_primitive_displacement(h, p, -1.0, 2.0)
+        S.smcrt_scene_set_primitive_displacement(h, p, 0.01, 20.0)
+        with pytest.raises(S.SmcrtError, match="fit their cells"):   # 0.2 + 0.01 elongated radius > half of 0.3
+            S.smcrt_scene_set_primitive_repetition(h, p, [0.3, 1, 1], [2, 1, 1])
+        with pytest.raises(S.SmcrtError, match="counts"):
+            S.smcrt_scene_set_primitive_repetition(h, p, [1, 1, 1], [0, 1, 1])
+        S.smcrt_scene_set_primitive_repetition(h, p, [1.0, 1, 1], [3, 1, 1])
+    finally:
+        S.smcrt_scene_destroy(h)
