@@ -167,8 +167,8 @@ double orc_prim_sdf(const orc_prim* pr, const double p[3]) {
     for (int a = 0; a < 3; ++a) {
       const int n = pr->rep_n[a];
       const double c = pr->rep_c[a], half = 0.5 * (n - 1) * c;
-      int i = (int)floor((q[a] + half) / c + 0.5);
-      i = i < 0 ? 0 : (i > n - 1 ? n - 1 : i);
+      /* clamp before converting: a far point must not overflow the int */
+      const int i = (int)clampd(floor((q[a] + half) / c + 0.5), 0.0, (double)(n - 1));
       q[a] -= i * c - half;
       if (q[a] > 0.0 && i < n - 1) b = mind(b, 0.5 * c - q[a]);
       if (q[a] < 0.0 && i > 0) b = mind(b, 0.5 * c + q[a]);

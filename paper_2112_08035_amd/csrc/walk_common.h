@@ -272,8 +272,8 @@ __device__ __attribute__((noinline)) T placed_prim_sdf(const SMCRT_K Prim<T>* P,
     for (int a = 0; a < 3; ++a) {
       const int n = Q.rep_n[a];
       const T c = Q.rep_c[a], half = T(0.5) * T(n - 1) * c;
-      int k = (int)floor((c3[a] + half) / c + T(0.5));
-      k = k < 0 ? 0 : (k > n - 1 ? n - 1 : k);
+      // clamp before converting: a far point must not overflow the int
+      const int k = (int)tclamp(floor((c3[a] + half) / c + T(0.5)), T(0), T(n - 1));
       c3[a] -= T(k) * c - half;
       if (c3[a] > T(0) && k < n - 1) b = tmin(b, T(0.5) * c - c3[a]);
       if (c3[a] < T(0) && k > 0) b = tmin(b, T(0.5) * c + c3[a]);
