@@ -15,7 +15,8 @@ import numpy as np
 
 from . import build as _build
 
-PRIM_KINDS = {"sphere": 0, "box": 1, "capsule": 2, "cylinder": 3, "torus": 4}
+PRIM_KINDS = {"sphere": 0, "box": 1, "capsule": 2, "cylinder": 3, "torus": 4,
+              "cone": 5, "octahedron": 6, "hexprism": 7, "ellipsoid": 8}
 OPS = {"union": 0, "smooth_union": 1, "intersect": 2, "subtract": 3}
 SRC_KINDS = {"point": 0, "pencil": 1, "disc": 2, "rect": 3}
 EVENT_TYPES = ["EMIT", "SCATTER", "ABSORB", "KILL", "REFLECT", "REFRACT", "CROSS", "ESCAPE", "STALL"]
@@ -169,6 +170,14 @@ def prim_struct(p):
         vals = list(p["c"]) + list(p["half"])
     elif p["kind"] == "torus":
         vals = list(p["c"]) + list(p["axis"]) + [p["R"], p["r"]]
+    elif p["kind"] == "cone":
+        vals = list(p["a"]) + list(p["b"]) + [p["ra"], p["rb"]]
+    elif p["kind"] == "octahedron":
+        vals = list(p["c"]) + [p["s"]]
+    elif p["kind"] == "hexprism":
+        vals = list(p["c"]) + [p["h"], p["hz"]]
+    elif p["kind"] == "ellipsoid":
+        vals = list(p["c"]) + list(p["radii"])
     else:
         vals = list(p["a"]) + list(p["b"]) + [p["r"]]
     for i, v in enumerate(vals):
@@ -240,6 +249,20 @@ def local_aabb(p):
         e = e / np.linalg.norm(e)
         ext = float(p["R"]) * np.sqrt(np.maximum(1.0 - e * e, 0.0)) + float(p["r"])
         return c - ext, c + ext
+    if p["kind"] == "cone":   # the end points' box grown by the larger radius
+        a, b = np.array(p["a"], float), np.array(p["b"], float)
+        r = max(float(p["ra"]), float(p["rb"]))
+        return np.minimum(a, b) - r, np.maximum(a, b) + r
+    if p["kind"] == "octahedron":
+        c, sz = np.array(p["c"], float), float(p["s"])
+        return c - sz, c + sz
+    if p["kind"] == "hexprism":   # circumradius 2h/sqrt(3) in x and y
+        c = np.array(p["c"], float)
+        e = np.array([2.0 * float(p["h"]) / math.sqrt(3.0), float(p["h"]), float(p["hz"])])
+        return c - e, c + e
+    if p["kind"] == "ellipsoid":
+        c, r = np.array(p["c"], float), np.array(p["radii"], float)
+        return c - r, c + r
     a, b, r = np.array(p["a"], float), np.array(p["b"], float), float(p["r"])
     return np.minimum(a, b) - r, np.maximum(a, b) + r
 

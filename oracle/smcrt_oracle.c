@@ -86,6 +86,22 @@ static double mind(double a, double b) { return a < b ? a : b; }
 
 /* --------------------------------------------------------------- SDFs --- */
 
+/* distance from (x, y) to the segment (ax, ay)-(bx, by) */
+static double seg2_dist(double x, double y, double ax, double ay, double bx, double by) {
+  double dx = bx - ax, dy = by - ay, px = x - ax, py = y - ay;
+  double t = clampd((px * dx + py * dy) / (dx * dx + dy * dy), 0.0, 1.0);
+  double ex = px - t * dx, ey = py - t * dy;
+  return sqrt(ex * ex + ey * ey);
+}
+
+/* distance from p to the segment a-b (3-D) */
+static double seg3_dist(const double p[3], const double a[3], const double b[3]) {
+  double ba[3] = {b[0] - a[0], b[1] - a[1], b[2] - a[2]}, pa[3] = {p[0] - a[0], p[1] - a[1], p[2] - a[2]};
+  double t = clampd(dot3(pa, ba) / dot3(ba, ba), 0.0, 1.0);
+  double d[3] = {pa[0] - t * ba[0], pa[1] - t * ba[1], pa[2] - t * ba[2]};
+  return len3(d);
+}
+
 /* Exact Euclidean distance functions, positive outside (Sec. 2.2, Eq. 2),
  * of the primitive shapes in their own frame. */
 static double shape_sdf(const orc_prim* pr, const double p[3]) {
@@ -133,6 +149,53 @@ static double shape_sdf(const orc_prim* pr, const double p[3]) {
       double radial[3] = {pc[0] - x * e[0], pc[1] - x * e[1], pc[2] - x * e[2]};
       double rho = len3(radial) - q[6];
       return sqrt(rho * rho + x * x) - q[7];
+    }
+    case ORC_CONE: { /* solid cone frustum about a-b, radius ra at a, rb at b:
+                      * in the (axial x, radial y) half plane its boundary is
+                      * the cap at a, the cap at b and the slanted side */
+      double ba[3] = {q[3] - q[0], q[4] - q[1], q[5] - q[2]};
+      double L = len3(ba);
+      double e[3] = {ba[0] / L, ba[1] / L, ba[2] / L};
+      double pa[3] = {p[0] - q[0], p[1] - q[1], p[2] - q[2]};
+      double x = dot3(pa, e);
+      double radial[3] = {pa[0] - x * e[0], pa[1] - x * e[1], pa[2] - x * e[2]};
+      double y = len3(radial), ra = q[6], rb = q[7];
+      double d = mind(mind(seg2_dist(x, y, 0.0, 0.0, 0.0, ra), seg2_dist(x, y, L, 0.0, L, rb)),
+                      seg2_dist(x, y, 0.0, ra, L, rb));
+      int inside = x > 0.0 && x < L && y < ra + (rb - ra) * x / L;
+      return inside ? -d : d;
+    }
+    case ORC_OCTAHEDRON: { /* |x|+|y|+|z| = s about c: by symmetry the face in
+                            * the positive octant, a triangle with corners s e_i */
+      const double sz = q[3];
+      double a[3] = {fabs(p[0] - q[0]), fabs(p[1] - q[1]), fabs(p[2] - q[2])};
+      double m = a[0] + a[1] + a[2] - sz;
+      /* foot of the perpendicular on the face plane; inside the triangle
+       * (all coordinates >= 0) the plane distance is the distance */
+      double f[3] = {a[0] - m / 3.0, a[1] - m / 3.0, a[2] - m / 3.0};
+      if (m <= 0.0 || (f[0] >= 0.0 && f[1] >= 0.0 && f[2] >= 0.0)) return m / sqrt(3.0);
+      double v0[3] = {sz, 0, 0}, v1[3] = {0, sz, 0}, v2[3] = {0, 0, sz};
+      return mind(mind(seg3_dist(a, v0, v1), seg3_dist(a, v1, v2)), seg3_dist(a, v2, v0));
+    }
+    case ORC_HEXPRISM: { /* regular hexagon of apothem h in the xy plane
+                          * (vertices at angles 0, 60, ... deg) extruded over
+                          * z in c -/+ hz */
+      const double h = q[3], hz = q[4], R = 2.0 * h / sqrt(3.0);
+      double x = fabs(p[0] - q[0]), y = fabs(p[1] - q[1]);
+      /* first quadrant: the edges are (R, 0)-(R/2, h) and (R/2, h)-(-R/2, h) */
+      double d2 = mind(seg2_dist(x, y, R, 0.0, 0.5 * R, h), seg2_dist(x, y, 0.5 * R, h, -0.5 * R, h));
+      int in2 = y < h && sqrt(3.0) * x + y < 2.0 * h;  /* below the top edge and the slanted one */
+      if (in2) d2 = -d2;
+      double dz = fabs(p[2] - q[2]) - hz;
+      double o1 = maxd(d2, 0.0), o2 = maxd(dz, 0.0);
+      return mind(maxd(d2, dz), 0.0) + sqrt(o1 * o1 + o2 * o2);
+    }
+    case ORC_ELLIPSOID: { /* radii r about c: r_min (|(p - c)/r| - 1), which is
+                           * 1-Lipschitz and zero on the surface, a lower
+                           * bound of the distance with the exact sign */
+      double rmin = mind(q[3], mind(q[4], q[5]));
+      double u[3] = {(p[0] - q[0]) / q[3], (p[1] - q[1]) / q[4], (p[2] - q[2]) / q[5]};
+      return rmin * (len3(u) - 1.0);
     }
     default:
       return ORC_INF;

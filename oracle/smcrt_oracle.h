@@ -21,7 +21,8 @@ extern "C" {
 
 /* primitive kinds (Sec. 2.2, Eq. 3 for the sphere; box, capsule, capped
  * cylinder and torus are basic shapes of the Sec. 2.2 gallery) */
-enum { ORC_SPHERE = 0, ORC_BOX = 1, ORC_CAPSULE = 2, ORC_CYLINDER = 3, ORC_TORUS = 4 };
+enum { ORC_SPHERE = 0, ORC_BOX = 1, ORC_CAPSULE = 2, ORC_CYLINDER = 3, ORC_TORUS = 4,
+       ORC_CONE = 5, ORC_OCTAHEDRON = 6, ORC_HEXPRISM = 7, ORC_ELLIPSOID = 8 };
 /* CSG operators (Sec. 2.2: union, intersection and difference; gallery
  * panels e to h) */
 enum { ORC_UNION = 0, ORC_SMOOTH_UNION = 1, ORC_INTERSECT = 2, ORC_SUBTRACT = 3 };
