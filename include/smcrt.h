@@ -58,8 +58,18 @@ enum {
   SMCRT_PRIM_BOX = 1,      /* params: cx cy cz hx hy hz    (axis aligned, half extents) */
   SMCRT_PRIM_CAPSULE = 2,  /* params: ax ay az bx by bz r  (segment a-b swept by r) */
   SMCRT_PRIM_CYLINDER = 3, /* params: ax ay az bx by bz r  (axis a-b, flat caps) */
-  SMCRT_PRIM_TORUS = 4     /* params: cx cy cz ex ey ez R r (centre, axis of any length,
+  SMCRT_PRIM_TORUS = 4,    /* params: cx cy cz ex ey ez R r (centre, axis of any length,
                                       ring radius R >= 0, tube radius r > 0) */
+  /* further gallery shapes (Sec. 2.2, Fig. 1's basic shapes) */
+  SMCRT_PRIM_CONE = 5,     /* params: ax ay az bx by bz ra rb (frustum about a-b, radius
+                                      ra at a, rb at b, both >= 0, not both 0; exact) */
+  SMCRT_PRIM_OCTAHEDRON = 6, /* params: cx cy cz s          (|x|+|y|+|z| <= s; exact) */
+  SMCRT_PRIM_HEXPRISM = 7, /* params: cx cy cz h hz       (regular hexagon of apothem h in
+                                      the xy plane, vertices on the x axis, extruded
+                                      over z in cz -/+ hz; exact) */
+  SMCRT_PRIM_ELLIPSOID = 8 /* params: cx cy cz rx ry rz   (radii > 0; distance bound
+                                      min(r) (|(p - c)/r| - 1): exact sign, never more
+                                      than the distance) */
 };
 /* region operators over the region's primitives, in the order given
  * (Sec. 2.2: union, intersection and difference):

@@ -118,8 +118,8 @@ extern "C" smcrt_status smcrt_scene_destroy(smcrt_scene* s) {
 extern "C" smcrt_status smcrt_scene_add_primitive(smcrt_scene* s, int kind, const double* params, int n_params,
                                                   int32_t* out_prim) {
   if (!s || !params) return fail(SMCRT_E_INVALID, "add_primitive: NULL argument");
-  static const int need[5] = {4, 6, 7, 7, 8};
-  if (kind < 0 || kind > 4) return fail(SMCRT_E_INVALID, "add_primitive: unknown kind %d", kind);
+  static const int need[9] = {4, 6, 7, 7, 8, 8, 4, 5, 6};
+  if (kind < 0 || kind > 8) return fail(SMCRT_E_INVALID, "add_primitive: unknown kind %d", kind);
   if (n_params != need[kind]) return fail(SMCRT_E_INVALID, "add_primitive: kind %d takes %d params, got %d", kind, need[kind], n_params);
   for (int i = 0; i < n_params; ++i)
     if (!std::isfinite(params[i])) return fail(SMCRT_E_INVALID, "add_primitive: param %d is not finite", i);
@@ -136,6 +136,17 @@ extern "C" smcrt_status smcrt_scene_add_primitive(smcrt_scene* s, int kind, cons
     if (!(d[0] * d[0] + d[1] * d[1] + d[2] * d[2] > 0)) return fail(SMCRT_E_INVALID, "add_primitive: segment ends must differ");
     if (!(p.p[6] > 0)) return fail(SMCRT_E_INVALID, "add_primitive: radius must be > 0");
   }
+  if (kind == kCone) {
+    double d[3] = {p.p[3] - p.p[0], p.p[4] - p.p[1], p.p[5] - p.p[2]};
+    if (!(d[0] * d[0] + d[1] * d[1] + d[2] * d[2] > 0)) return fail(SMCRT_E_INVALID, "add_primitive: cone ends must differ");
+    if (!(p.p[6] >= 0 && p.p[7] >= 0 && p.p[6] + p.p[7] > 0))
+      return fail(SMCRT_E_INVALID, "add_primitive: cone radii must be >= 0, not both 0");
+  }
+  if (kind == kOctahedron && !(p.p[3] > 0)) return fail(SMCRT_E_INVALID, "add_primitive: octahedron size must be > 0");
+  if (kind == kHexPrism && !(p.p[3] > 0 && p.p[4] > 0))
+    return fail(SMCRT_E_INVALID, "add_primitive: hexagonal prism apothem and half height must be > 0");
+  if (kind == kEllipsoid && !(p.p[3] > 0 && p.p[4] > 0 && p.p[5] > 0))
+    return fail(SMCRT_E_INVALID, "add_primitive: ellipsoid radii must be > 0");
   if (kind == kTorus) {
     if (!(p.p[3] * p.p[3] + p.p[4] * p.p[4] + p.p[5] * p.p[5] > 0)) return fail(SMCRT_E_INVALID, "add_primitive: torus axis must be non-zero");
     if (!(p.p[6] >= 0 && p.p[7] > 0)) return fail(SMCRT_E_INVALID, "add_primitive: torus needs R >= 0 and tube radius r > 0");
@@ -388,6 +399,20 @@ static void local_box(const HostPrim& p, double lo[3], double hi[3]) {
         hi[i] = p.p[i] + ext;
         break;
       }
+      case kCone: {  // the end points' box grown by the larger radius
+        const double r = std::max(p.p[6], p.p[7]);
+        lo[i] = std::min(p.p[i], p.p[3 + i]) - r;
+        hi[i] = std::max(p.p[i], p.p[3 + i]) + r;
+        break;
+      }
+      case kOctahedron: lo[i] = p.p[i] - p.p[3]; hi[i] = p.p[i] + p.p[3]; break;
+      case kHexPrism: {  // circumradius 2h/sqrt(3) in x, apothem h in y
+        const double e = i == 0 ? 2.0 * p.p[3] / std::sqrt(3.0) : (i == 1 ? p.p[3] : p.p[4]);
+        lo[i] = p.p[i] - e;
+        hi[i] = p.p[i] + e;
+        break;
+      }
+      case kEllipsoid: lo[i] = p.p[i] - p.p[3 + i]; hi[i] = p.p[i] + p.p[3 + i]; break;
       default:
         lo[i] = std::min(p.p[i], p.p[3 + i]) - p.p[6];
         hi[i] = std::max(p.p[i], p.p[3 + i]) + p.p[6];
@@ -551,12 +576,32 @@ static void pack_prim(const HostPrim& h, Prim<T>& o) {
       o.v[7] = (T)p[7];
       break;
     }
+    case kCone: {
+      double ba[3] = {p[3] - p[0], p[4] - p[1], p[5] - p[2]};
+      const double L = std::sqrt(ba[0] * ba[0] + ba[1] * ba[1] + ba[2] * ba[2]);
+      for (int i = 0; i < 3; ++i) { o.v[i] = (T)p[i]; o.v[3 + i] = (T)(ba[i] / L); }
+      o.v[6] = (T)L;
+      o.v[7] = (T)p[6];
+      o.v[8] = (T)p[7];
+      break;
+    }
+    case kOctahedron:
+      for (int i = 0; i < 4; ++i) o.v[i] = (T)p[i];
+      break;
+    case kHexPrism:
+      for (int i = 0; i < 5; ++i) o.v[i] = (T)p[i];
+      o.v[5] = (T)(2.0 * p[3] / std::sqrt(3.0));
+      break;
+    case kEllipsoid:
+      for (int i = 0; i < 3; ++i) { o.v[i] = (T)p[i]; o.v[3 + i] = (T)(1.0 / p[3 + i]); }
+      o.v[6] = (T)std::min(p[3], std::min(p[4], p[5]));
+      break;
   }
   // placement and modifiers
   const bool elongated = h.elong[0] != 0.0 || h.elong[1] != 0.0 || h.elong[2] != 0.0;
   o.flags = (h.placed ? kPlaced : 0) | (h.twist_k != 0.0 ? kTwisted : 0) |
             ((h.round_r != 0.0 || h.onion_t != 0.0 || elongated || h.disp_a != 0.0) ? kModified : 0) |
-            (repeated(h) ? kRepeated : 0);
+            (repeated(h) ? kRepeated : 0) | (h.kind >= kCone ? kFurtherShape : 0);
   for (int i = 0; i < 3; ++i) {
     o.elong[i] = (T)h.elong[i];
     o.rep_c[i] = (T)h.rep_c[i];
@@ -746,7 +791,7 @@ static smcrt_status pack(smcrt_scene* s) {
   h->geometry = s->geometry;
   h->xf = 0;
   for (const HostPrim& hp : s->prims)
-    if (hp.placed || hp.twist_k != 0.0 || hp.round_r != 0.0 || hp.onion_t != 0.0 || hp.disp_a != 0.0 || repeated(hp) ||
+    if (hp.kind >= kCone || hp.placed || hp.twist_k != 0.0 || hp.round_r != 0.0 || hp.onion_t != 0.0 || hp.disp_a != 0.0 || repeated(hp) ||
         hp.elong[0] != 0.0 || hp.elong[1] != 0.0 || hp.elong[2] != 0.0)
       h->xf = 1;
   h->src_kind = s->src_kind;

@@ -13,7 +13,11 @@ namespace smcrt {
 constexpr int kMaxRegions = 16;     // regions per scene (ambient adds one slot)
 constexpr int kMaxPrims = 1 << 20;  // primitives per scene
 
-enum PrimKind : int32_t { kSphere = 0, kBox = 1, kCapsule = 2, kCylinder = 3, kTorus = 4 };
+enum PrimKind : int32_t {
+  kSphere = 0, kBox = 1, kCapsule = 2, kCylinder = 3, kTorus = 4,
+  // further shapes: evaluated only on the placed-primitive path
+  kCone = 5, kOctahedron = 6, kHexPrism = 7, kEllipsoid = 8
+};
 enum RegionOp : int32_t { kUnion = 0, kSmoothUnion = 1, kIntersect = 2, kSubtract = 3 };
 enum SourceKind : int32_t { kPoint = 0, kPencil = 1, kDisc = 2, kRect = 3 };
 // geometry model of a scene: the signed distance functions themselves, or
@@ -30,6 +34,10 @@ enum LaunchClass : int32_t { kLaunchXf = 2, kLaunchClasses = 4 };
 //   capsule  : a0 a1 a2 ba0 ba1 ba2 1/|ba|^2 r
 //   cylinder : a0 a1 a2 e0 e1 e2 L L/2 r          (e = unit axis)
 //   torus    : c0 c1 c2 e0 e1 e2 R r              (e = unit axis)
+//   cone     : a0 a1 a2 e0 e1 e2 L ra rb          (e = unit axis, L = |b - a|)
+//   octahedron: c0 c1 c2 s
+//   hexprism : c0 c1 c2 h hz R                    (R = 2h/sqrt 3)
+//   ellipsoid: c0 c1 c2 1/rx 1/ry 1/rz rmin
 // A primitive may be placed (local = m (p - t), m = R^T / s, distance times
 // s).  In its own frame the query point is taken to the nearest of the
 // repeated copies (offsets (i - (n-1)/2) rep_c, i = 0..n-1 per axis),
@@ -42,7 +50,7 @@ enum LaunchClass : int32_t { kLaunchXf = 2, kLaunchClasses = 4 };
 // distance to the cylinder is used.  Repetition: the smaller of that and
 // rep_gap plus the distance to the nearest cell face with another copy
 // behind it.  flags = 0: the plain shape.
-enum PrimFlags { kPlaced = 1, kTwisted = 2, kModified = 4, kRepeated = 8 };
+enum PrimFlags { kPlaced = 1, kTwisted = 2, kModified = 4, kRepeated = 8, kFurtherShape = 16 };
 template <typename T>
 struct Prim {
   int32_t kind;

@@ -253,6 +253,66 @@ __device__ __forceinline__ void tsincos(T a, T* sn, T* cs) {
 // bounding cylinder the distance is divided by the twist's Lipschitz bound
 // there, outside it the distance to the cylinder is used.  The flags are the
 // same for every lane (primitives are visited in a wave-uniform order).
+// distance from (x, y) to the segment (ax, ay)-(bx, by)
+template <typename T>
+__device__ __forceinline__ T seg2_dist(T x, T y, T ax, T ay, T bx, T by) {
+  const T dx = bx - ax, dy = by - ay, px = x - ax, py = y - ay;
+  const T t = tclamp((px * dx + py * dy) / (dx * dx + dy * dy), T(0), T(1));
+  const T ex = px - t * dx, ey = py - t * dy;
+  return tsqrt(ex * ex + ey * ey);
+}
+
+// distance from p to the segment a-b
+template <typename T>
+__device__ __forceinline__ T seg3_dist(V3<T> p, V3<T> a, V3<T> b) {
+  const V3<T> ba = b - a, pa = p - a;
+  const T t = tclamp(dot(pa, ba) / dot(ba, ba), T(0), T(1));
+  const V3<T> d = pa - t * ba;
+  return tsqrt(dot(d, d));
+}
+
+// further gallery shapes in their own frame (Sec. 2.2, Fig. 1's basic
+// shapes): capped cone, octahedron and hexagonal prism (exact distances),
+// ellipsoid (a lower bound with the exact sign)
+template <typename T>
+__device__ __forceinline__ T further_shape_sdf(const SMCRT_K Prim<T>* P, int i, V3<T> p) {
+  const int kind = P[i].kind;
+  const SMCRT_K T* v = P[i].v;
+  const V3<T> q = p - mk(v[0], v[1], v[2]);
+  if (kind == kCone) {  // (axial x, radial y) half plane: the two caps and the slanted side
+    const V3<T> e = mk(v[3], v[4], v[5]);
+    const T L = v[6], ra = v[7], rb = v[8];
+    const T x = dot(q, e);
+    const V3<T> rad = q - x * e;
+    const T y = tsqrt(dot(rad, rad));
+    const T d = tmin(tmin(seg2_dist(x, y, T(0), T(0), T(0), ra), seg2_dist(x, y, L, T(0), L, rb)),
+                     seg2_dist(x, y, T(0), ra, L, rb));
+    const bool inside = x > T(0) && x < L && y < ra + (rb - ra) * x / L;
+    return inside ? -d : d;
+  }
+  if (kind == kOctahedron) {  // by symmetry the face in the positive octant
+    const T s = v[3];
+    const V3<T> a = mk(tabs(q.x), tabs(q.y), tabs(q.z));
+    const T m = a.x + a.y + a.z - s;
+    const T third = m * T(1.0 / 3.0);
+    if (m <= T(0) || (a.x >= third && a.y >= third && a.z >= third)) return m * T(0.57735026918962576451);
+    const V3<T> v0 = mk(s, T(0), T(0)), v1 = mk(T(0), s, T(0)), v2 = mk(T(0), T(0), s);
+    return tmin(tmin(seg3_dist(a, v0, v1), seg3_dist(a, v1, v2)), seg3_dist(a, v2, v0));
+  }
+  if (kind == kHexPrism) {  // first quadrant: edges (R,0)-(R/2,h) and (R/2,h)-(-R/2,h)
+    const T h = v[3], hz = v[4], R = v[5];
+    const T x = tabs(q.x), y = tabs(q.y);
+    T d2 = tmin(seg2_dist(x, y, R, T(0), T(0.5) * R, h), seg2_dist(x, y, T(0.5) * R, h, T(-0.5) * R, h));
+    if (y < h && T(1.7320508075688772935) * x + y < T(2) * h) d2 = -d2;
+    const T dz = tabs(q.z) - hz;
+    const T o1 = tmax(d2, T(0)), o2 = tmax(dz, T(0));
+    return tmin(tmax(d2, dz), T(0)) + tsqrt(o1 * o1 + o2 * o2);
+  }
+  // ellipsoid: rmin (|q / r| - 1), 1-Lipschitz and zero on the surface
+  const V3<T> u = mk(q.x * v[3], q.y * v[4], q.z * v[5]);
+  return v[6] * (tsqrt(dot(u, u)) - T(1));
+}
+
 template <typename T>
 __device__ __attribute__((noinline)) T placed_prim_sdf(const SMCRT_K Prim<T>* P, int i, V3<T> p) {
   const SMCRT_K Prim<T>& Q = P[i];
@@ -292,7 +352,7 @@ __device__ __attribute__((noinline)) T placed_prim_sdf(const SMCRT_K Prim<T>* P,
   }
   const V3<T> e = mk(q.x - tclamp(q.x, -Q.elong[0], Q.elong[0]), q.y - tclamp(q.y, -Q.elong[1], Q.elong[1]),
                      q.z - tclamp(q.z, -Q.elong[2], Q.elong[2]));
-  T d = shape_sdf(P, i, e) - Q.round_r;
+  T d = ((fl & kFurtherShape) ? further_shape_sdf(P, i, e) : shape_sdf(P, i, e)) - Q.round_r;
   if (Q.onion_t > T(0)) d = tabs(d) - Q.onion_t;
   if (Q.disp_a > T(0)) {
     T sx, cx, sy, cy, sz, cz;

@@ -22,7 +22,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libsmcrt.so")
 
 OK, E_INVALID, E_NOMEM, E_HIP, E_BUDGET, E_CANCELLED, E_STATE = 0, -1, -2, -3, -4, -5, -6
-PRIM = {"sphere": 0, "box": 1, "capsule": 2, "cylinder": 3, "torus": 4}
+PRIM = {"sphere": 0, "box": 1, "capsule": 2, "cylinder": 3, "torus": 4,
+        "cone": 5, "octahedron": 6, "hexprism": 7, "ellipsoid": 8}
 OP = {"union": 0, "smooth_union": 1, "intersect": 2, "subtract": 3}
 SRC = {"point": 0, "pencil": 1, "disc": 2, "rect": 3}
 PREC = {"f32": 0, "f64": 1}
@@ -356,6 +357,14 @@ class Scene:
                 vals = list(p["c"]) + list(p["half"])
             elif p["kind"] == "torus":
                 vals = list(p["c"]) + list(p["axis"]) + [p["R"], p["r"]]
+            elif p["kind"] == "cone":
+                vals = list(p["a"]) + list(p["b"]) + [p["ra"], p["rb"]]
+            elif p["kind"] == "octahedron":
+                vals = list(p["c"]) + [p["s"]]
+            elif p["kind"] == "hexprism":
+                vals = list(p["c"]) + [p["h"], p["hz"]]
+            elif p["kind"] == "ellipsoid":
+                vals = list(p["c"]) + list(p["radii"])
             else:
                 vals = list(p["a"]) + list(p["b"]) + [p["r"]]
             pid = smcrt_scene_add_primitive(self.h, PRIM[p["kind"]], vals)

@@ -447,6 +447,33 @@ def gallery_scene(n_grid=64):
     return sc
 
 
+def shapes_scene(n_grid=48):
+    """The further basic shapes of the paper's SDF gallery (Sec. 2.2) in a
+    2 x 2 x 2 cm scattering medium (mu_a 0.1, mu_s 20, g 0.9, n 1.33) lit
+    from above by a 0.6 cm top-hat beam: a glass frustum, a tilted
+    octahedron of absorbing tissue, a hexagonal glass prism and an
+    ellipsoid of dense scatterer, each its own region."""
+    prims = [
+        {"kind": "box", "c": [0.0, 0.0, 0.0], "half": [1.0, 1.0, 1.0]},
+        {"kind": "cone", "a": [-0.5, -0.4, 0.5], "b": [-0.3, -0.3, -0.1], "ra": 0.3, "rb": 0.1},
+        {"kind": "octahedron", "c": [0.0, 0.0, 0.0], "s": 0.3,
+         "transform": {"R": rotation([1, 2, 0], 0.5), "t": [0.45, 0.4, 0.3], "s": 1.0}},
+        {"kind": "hexprism", "c": [0.4, -0.45, -0.4], "h": 0.25, "hz": 0.2},
+        {"kind": "ellipsoid", "c": [-0.4, 0.45, -0.45], "radii": [0.35, 0.2, 0.15]},
+    ]
+    regions = [
+        _region([0], 0.1, 20.0, 0.9, 1.33),
+        _region([1], 0.05, 0.0, 0.0, 1.5),
+        _region([2], 3.0, 60.0, 0.9, 1.4),
+        _region([3], 0.02, 0.0, 0.0, 1.46),
+        _region([4], 0.5, 300.0, 0.8, 1.38),
+    ]
+    grid = {"lo": [-1.0] * 3, "hi": [1.0] * 3, "dims": [n_grid] * 3}
+    sc = _scene("shapes", prims, regions, None, grid)
+    sc["source"] = {"kind": "disc", "c": [0.0, 0.0, 1.0 + 0.5 * sc["pad"]], "r": 0.6, "u": [0.0, 0.0, -1.0]}
+    return sc
+
+
 WORKLOADS = {
     "sphere": sphere_scene,
     "slab": slab_scene,
@@ -454,4 +481,5 @@ WORKLOADS = {
     "glass_sphere": glass_sphere_scene,
     "bottle": bottle_scene,
     "gallery": gallery_scene,
+    "shapes": shapes_scene,
 }

@@ -56,6 +56,18 @@ def test_scene_validation_rejects_bad_input(S):
         with pytest.raises(S.SmcrtError, match="tube radius"):
             S.smcrt_scene_add_primitive(h, 4, [0, 0, 0, 0, 0, 1, 1.0, 0.0])
         with pytest.raises(S.SmcrtError, match="unknown kind"):
+            S.smcrt_scene_add_primitive(h, 9, [0, 0, 0, 1])
+        with pytest.raises(S.SmcrtError, match="cone ends"):
+            S.smcrt_scene_add_primitive(h, 5, [0, 0, 0, 0, 0, 0, 1.0, 0.5])
+        with pytest.raises(S.SmcrtError, match="cone radii"):
+            S.smcrt_scene_add_primitive(h, 5, [0, 0, 0, 0, 0, 1, 0.0, 0.0])
+        with pytest.raises(S.SmcrtError, match="octahedron"):
+            S.smcrt_scene_add_primitive(h, 6, [0, 0, 0, 0.0])
+        with pytest.raises(S.SmcrtError, match="hexagonal prism"):
+            S.smcrt_scene_add_primitive(h, 7, [0, 0, 0, 0.3, -1.0])
+        with pytest.raises(S.SmcrtError, match="ellipsoid"):
+            S.smcrt_scene_add_primitive(h, 8, [0, 0, 0, 1.0, 0.0, 1.0])
+        with pytest.raises(S.SmcrtError, match="takes 8"):
             S.smcrt_scene_add_primitive(h, 5, [0, 0, 0, 1])
         p = S.smcrt_scene_add_primitive(h, 0, [0, 0, 0, 1])
         with pytest.raises(S.SmcrtError, match="out of range"):
@@ -96,7 +108,8 @@ def test_regions_limit(S):
         S.smcrt_scene_destroy(h)
 
 
-@pytest.mark.parametrize("name", ["sphere", "slab", "cylinder", "vessels", "glass_sphere", "bottle", "torus", "gallery"])
+@pytest.mark.parametrize("name", ["sphere", "slab", "cylinder", "vessels", "glass_sphere", "bottle", "torus", "gallery",
+                                  "shapes"])
 def test_volume_rule_agrees_with_oracle(S, orc, W, name):
     if name == "vessels":
         desc = W.vessel_scene(3, 1.0, n_caps=50, n_grid=8)
@@ -110,7 +123,7 @@ def test_volume_rule_agrees_with_oracle(S, orc, W, name):
     olo, ohi = orc.bounding_box(desc)
     # placed primitives' boxes come from 8 turned corners, summed in another
     # order on each side
-    atol = 1e-12 if name == "gallery" else 1e-15
+    atol = 1e-12 if name in ("gallery", "shapes") else 1e-15
     np.testing.assert_allclose(lo, olo, rtol=0, atol=atol)
     np.testing.assert_allclose(hi, ohi, rtol=0, atol=atol)
     assert npr == len(desc["prims"])
