@@ -11,16 +11,21 @@
 //
 // T is the transport type (float or double): positions, directions, step
 // lengths, the SDFs of the stepping loop and the transcendentals.  The
-// interface step, weights, absorbed energy and tallies are FP64 in both.
+// interface step, remaining optical depth, weights, absorbed energy and
+// tallies are FP64 in both.  Steps may be over-relaxed (a multiple of the
+// surface distance, checked at the next evaluation; Sec. 5).
 //
 // Divergence control: lanes that reach a surface wait until surface_min
 // lanes of the wave are there (or nothing else can move), so the long FP64
 // interface step runs with many lanes on; dead lanes wait for refill_min
 // before a wave emits.
 //
-// Tally: each lane merges consecutive pieces that fall in the same voxel
-// (across steps, events and even packets) and issues one FP64 atomic per
-// run of equal voxels.
+// Tally: a lane keeps the straight path since its last tally pending and
+// credits it through the voxel grid (a register-only DDA) before an
+// interaction, an interface event or the packet's end.  Consecutive pieces
+// in the same voxel (across steps, events and even packets) merge into one
+// run; each run is staged in the wave's LDS stage, which is drained as
+// full-wave FP64 atomics.
 #include <hip/hip_runtime.h>
 
 #include "launch.h"
@@ -138,8 +143,10 @@ __device__ void surface(JobRef a, Packet<T>& pk, Lane& ln, LdsTallies& L) {
 // packets are all handed out and their lanes have drained, flush their sums
 // into that job's outputs and move on to the next job with packets left.
 // GEOM selects the geometry model: sphere tracing through the SDFs, or the
-// voxel walk of the voxelised comparison model; the launch takes only the
-// jobs of that model.
+// voxel walk of the voxelised comparison model.  XF adds the path of placed,
+// modified and further-shape primitives.  The launch takes only the jobs of
+// its (GEOM, XF) class.  4 waves per SIMD in FP32 (3 in FP64) keep the
+// walk's state in registers.
 template <typename T, bool TRACE, int GEOM, bool XF>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 4 : 3)))
 walk_kernel(const WalkArgs* __restrict__ job_table, BatchArgs B) {
