@@ -49,7 +49,7 @@ class Scene(C.Structure):
                 ("max_events", C.c_int64),
                 ("det_face", C.c_int32), ("det_dims", C.c_int32 * 2),
                 ("det_lo", C.c_double * 2), ("det_hi", C.c_double * 2),
-                ("relax", C.c_double)]
+                ("relax", C.c_double), ("no_reuse", C.c_int32), ("pad_reuse", C.c_int32)]
 
 
 class Tallies(C.Structure):
@@ -340,6 +340,7 @@ class CScene:
         s.max_steps = int(scene["max_steps"])
         s.max_events = int(scene["max_events"])
         s.relax = float(scene.get("relax", 1.0))
+        s.no_reuse = 0 if scene.get("reuse", True) else 1
         det = scene.get("detector")
         if det:
             s.det_face = int(det["face"])

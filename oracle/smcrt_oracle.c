@@ -689,6 +689,11 @@ static void walk(walker* wk, uint64_t seed, uint64_t pid) {
   const orc_scene* s = wk->s;
   packet pk;
   emit(wk, &pk, seed, pid);
+  /* free-flight reuse: a ball of radius safe around the packet that holds
+   * no surface (< 0: none known), and the interactions taken in it since
+   * the distance was evaluated */
+  double safe = -1.0;
+  int links = 0;
   for (;;) {
     /* one event: sphere-trace until interaction (Sec. 2.3) */
     int32_t steps = 0;
@@ -699,6 +704,26 @@ static void walk(walker* wk, uint64_t seed, uint64_t pid) {
     double q[3] = {0.0, 0.0, 0.0}, pd = -1.0, pl = 0.0, tau_q = 0.0;
     int pending = 0;
     while (state == GO_ON) {
+      if (!s->no_reuse && safe > 0.0 && pk.region >= 0 && links < ORC_REUSE_LINKS) {
+        /* the last evaluated distance, less the path since, bounds the
+         * distance to every surface: an interaction inside that ball is the
+         * one a new evaluation would give, so none is made.  Inside a region
+         * the ball is inside the volume too.  Margin: delta, plus per
+         * interaction in the ball 4 units in the last place of the position
+         * for the rounding of the moves */
+        const double mut_r = reg_mua(s, pk.region) + reg_mus(s, pk.region);
+        const double s_r = mut_r > 0.0 ? pk.tau / mut_r : ORC_INF;
+        const double pmax = maxd(fabs(pk.p[0]), maxd(fabs(pk.p[1]), fabs(pk.p[2])));
+        if (s_r <= safe - s->delta - (links + 1) * pmax * 0x1p-50) {
+          move(wk, &pk, s_r);
+          pk.tau = 0.0;
+          safe -= s_r;
+          ++links;
+          state = DO_INTERACT;
+          continue;
+        }
+      }
+      safe = -1.0;
       if (++steps > s->max_steps || (int64_t)pk.k > s->max_events) {
         if (pending) wk->t->voxel_segments += (uint64_t)orc_tally_segment(s, q, pk.p, pk.w, wk->f);
         wk->t->stalled += pk.w;
@@ -746,6 +771,10 @@ static void walk(walker* wk, uint64_t seed, uint64_t pid) {
         move(wk, &pk, s_rem);
         pk.tau = 0.0;
         state = DO_INTERACT;
+        if (pk.region >= 0) { /* the ball of radius dmin about the step's start holds no surface */
+          safe = dmin - s_rem;
+          links = 0;
+        }
       } else if (dmin < s->delta) { /* on a boundary */
         uint32_t k_before = pk.k;
         state = surface(wk, &pk, s_rem, seed, pid);

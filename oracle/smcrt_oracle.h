@@ -98,7 +98,12 @@ typedef struct {
   /* over-relaxation factor of sphere-tracing steps in [1, 2); 1 = plain
    * steps of the nearest-surface distance */
   double relax;
+  /* 1: evaluate the SDFs before every interaction (no free-flight reuse) */
+  int32_t no_reuse, pad_reuse;
 } orc_scene;
+
+/* free-flight reuse: at most this many interactions per evaluation */
+#define ORC_REUSE_LINKS 32
 
 typedef struct {
   double launched, escaped_face[6], roulette_gain, roulette_loss, stalled;

@@ -258,7 +258,7 @@ walk_kernel(const WalkArgs* __restrict__ job_table, BatchArgs B) {
           T dmin = tinf<T>();
           for (int r = 0; r < nr; ++r) dmin = tmin(dmin, tabs(region_dist<T, XF>(a, r, pk.p)));
           int face;
-          const T dbb = volume_sdf<T>(sc, pk.p, &face);
+          const bool outside = outside_volume<T>(sc, pk.p, &face);
           bool rejected = false;
           if (pk.pl < T(0)) {
             // check of an over-relaxed step (Sec. 5): the open balls of
@@ -276,7 +276,7 @@ walk_kernel(const WalkArgs* __restrict__ job_table, BatchArgs B) {
           }
           if (rejected) {
             // the next evaluation starts from the plain step's end
-          } else if (dbb > T(0)) {  // outside the simulation volume
+          } else if (outside) {  // outside the simulation volume
             atomicAdd(&L.escaped[face], pk.w);
             atomicAdd(&L.cnt[kCEscapes], 1ull);
             detect<T>(a, pk, face, Tab<T>::bb_c(sc, face >> 1) + ((face & 1) ? Tab<T>::bb_h(sc, face >> 1) : -Tab<T>::bb_h(sc, face >> 1)));

@@ -462,9 +462,12 @@ __device__ __forceinline__ int region_of(JobRef a, V3<T> p) {
   return owner;
 }
 
-// signed distance of the simulation volume and, when outside, the face
+// Outside the simulation volume (Sec. 2.3: escape when the volume's box
+// SDF is positive).  The box SDF is positive exactly when the largest of
+// |q_i| - h_i is, so the sign needs no square root; face = 2*axis + side of
+// that largest component, the face the packet left through.
 template <typename T>
-__device__ __forceinline__ T volume_sdf(ScP sc, V3<T> p, int* face) {
+__device__ __forceinline__ bool outside_volume(ScP sc, V3<T> p, int* face) {
   const V3<T> c = Tab<T>::bb_c(sc), h = Tab<T>::bb_h(sc);
   const V3<T> q = p - c;
   const T ex = tabs(q.x) - h.x, ey = tabs(q.y) - h.y, ez = tabs(q.z) - h.z;
@@ -474,8 +477,7 @@ __device__ __forceinline__ T volume_sdf(ScP sc, V3<T> p, int* face) {
   if (ez > best) { best = ez; ax = 2; }
   const T qa = ax == 0 ? q.x : (ax == 1 ? q.y : q.z);
   *face = 2 * ax + (qa > T(0) ? 1 : 0);
-  const V3<T> o = mk(tmax(ex, T(0)), tmax(ey, T(0)), tmax(ez, T(0)));
-  return tsqrt(dot(o, o)) + tmin(best, T(0));
+  return best > T(0);
 }
 
 // unit outward normal of region R at p by central differences of step h
