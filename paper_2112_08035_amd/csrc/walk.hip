@@ -246,8 +246,31 @@ walk_kernel(const WalkArgs* __restrict__ job_table, BatchArgs B) {
         if (live && pk.state == kTransport && !voxel_step<T, TRACE>(a, pk, vx, ln, L, max_steps, max_events)) live = false;
       }
 
+      // ---- free-flight reuse: the distance evaluated at the last step's
+      // start, less the path since, bounds the distance to every surface;
+      // an interaction inside that ball (inside a region, so inside the
+      // volume) is the one an evaluation would give, so none is made.
+      // Margin: delta, plus per reuse 4 units in the last place of the
+      // position for the rounding of the moves
+      bool reused = false;
+      if (GEOM == kGeomSdf && live && pk.state == kTransport && pk.safe > T(0) && pk.region < nr &&
+          pk.links < kReuseLinks) {
+        const T s = pk.mut > T(0) ? (T)(pk.tau * (double)pk.inv_mut) : tinf<T>();
+        const T pmax = tmax(tabs(pk.p.x), tmax(tabs(pk.p.y), tabs(pk.p.z)));
+        const T ulp4 = sizeof(T) == 4 ? T(0x1p-21) : T(0x1p-50);
+        if (s <= pk.safe - delta - T(pk.links + 1) * pmax * ulp4) {
+          advance(pk, s);
+          pk.tau = 0.0;
+          pk.state = kInteract;
+          pk.safe -= s;
+          ++pk.links;
+          reused = true;
+        }
+      }
+
       // ---- one sphere-tracing step (Sec. 2.3)
-      if (GEOM == kGeomSdf && live && pk.state == kTransport) {
+      if (GEOM == kGeomSdf && live && pk.state == kTransport && !reused) {
+        pk.safe = T(-1);
         if (++pk.steps > max_steps || pk.k > max_events) {
           atomicAdd(&L.stalled, pk.w);
           atomicAdd(&L.cnt[kCStalls], 1ull);
@@ -288,6 +311,10 @@ walk_kernel(const WalkArgs* __restrict__ job_table, BatchArgs B) {
               advance(pk, s);
               pk.tau = 0.0;
               pk.state = kInteract;
+              if (pk.region < nr) {  // the ball of radius dmin about the step's start holds no surface
+                pk.safe = dmin - s;
+                pk.links = 0;
+              }
             } else if (dmin < delta) {
               pk.state = kSurface;
             } else {

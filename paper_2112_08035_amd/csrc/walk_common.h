@@ -707,7 +707,14 @@ struct Packet {
   // distance at its start (< 0: none yet) and its length, negated while an
   // over-relaxed step waits for its check at the next evaluation
   T pd, pl;
+  // free-flight reuse: radius of a ball about p that holds no surface
+  // (< 0: none known) and the interactions taken in it since the distance
+  // was evaluated
+  T safe;
+  int links;
 };
+
+constexpr int kReuseLinks = 32;  // interactions per evaluation at most
 
 template <typename T>
 __device__ __forceinline__ void set_region(ScP sc, Packet<T>& pk, int r) {
@@ -857,6 +864,8 @@ __device__ void emit(JobRef a, Packet<T>& pk, Lane& ln, LdsTallies& L) {
   pk.steps = 0;
   pk.pd = T(-1);
   pk.pl = T(0);
+  pk.safe = T(-1);
+  pk.links = 0;
   pk.pend = T(0);
   pk.state = kTransport;
   set_region(sc, pk, region_of<T, XF>(a, p));

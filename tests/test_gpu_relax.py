@@ -92,3 +92,14 @@ def test_relaxed_grazing_beam_steps_on_gpu(S, eng, W):
         relaxed = S.run(_relaxed(sc), 1, 1000, engine=eng, precision=prec, tally=False)
         assert plain["escaped_face"][1] == pytest.approx(1000.0) and relaxed["escaped_face"][1] == pytest.approx(1000.0)
         assert relaxed["steps"] < 0.6 * plain["steps"], (prec, relaxed["steps"], plain["steps"])
+
+
+@pytest.mark.parametrize("name,relax", [("slab", 1.0), ("cylinder", 1.0), ("slab", 1.9)])
+def test_fp64_evaluations_match_oracle(S, eng, orc, W, name, relax):
+    # free-flight reuse and relaxed steps decide the same way on both sides:
+    # the FP64 walk makes the oracle's number of SDF evaluations
+    desc = dict(W.WORKLOADS[name](n_grid=16), relax=relax)
+    g = S.run(desc, 21, 3000, engine=eng, precision="f64", tally=False)
+    o = orc.run(desc, 21, 3000)
+    assert g["interactions"] == o["interactions"]
+    assert abs(g["steps"] - o["steps"]) <= 1e-5 * o["steps"], (g["steps"], o["steps"])
