@@ -35,7 +35,7 @@ class Prim(C.Structure):
 class Region(C.Structure):
     _fields_ = [("first_prim", C.c_int32), ("n_prims", C.c_int32), ("op", C.c_int32), ("pad", C.c_int32),
                 ("k", C.c_double), ("mua", C.c_double), ("mus", C.c_double), ("g", C.c_double),
-                ("n", C.c_double)]
+                ("n", C.c_double), ("box_lo", C.c_double * 3), ("box_hi", C.c_double * 3)]
 
 
 class Scene(C.Structure):
@@ -49,7 +49,7 @@ class Scene(C.Structure):
                 ("max_events", C.c_int64),
                 ("det_face", C.c_int32), ("det_dims", C.c_int32 * 2),
                 ("det_lo", C.c_double * 2), ("det_hi", C.c_double * 2),
-                ("relax", C.c_double), ("no_reuse", C.c_int32), ("pad_reuse", C.c_int32)]
+                ("relax", C.c_double), ("no_reuse", C.c_int32), ("no_skip", C.c_int32)]
 
 
 class Tallies(C.Structure):
@@ -303,6 +303,12 @@ class CScene:
             r.op = OPS[rg["op"]]
             r.k = float(rg.get("k", 0.0))
             r.mua, r.mus, r.g, r.n = (float(rg[x]) for x in ("mua", "mus", "g", "n"))
+            # ambient skip: the region's surface lies in its primitives'
+            # boxes; a smooth union reaches at most k/4 beyond them
+            los, his = zip(*[prim_aabb(scene["prims"][i]) for i in rg["prims"]])
+            grow = (r.k if rg["op"] == "smooth_union" else 0.0) + 0.5 * float(scene["delta"])
+            r.box_lo = _d3(np.min(los, axis=0) - grow)
+            r.box_hi = _d3(np.max(his, axis=0) + grow)
             regs.append(r)
         # region primitive lists are stored contiguously in region order
         self.prims = (Prim * len(order))(*[prims[i] for i in order])
@@ -341,6 +347,7 @@ class CScene:
         s.max_events = int(scene["max_events"])
         s.relax = float(scene.get("relax", 1.0))
         s.no_reuse = 0 if scene.get("reuse", True) else 1
+        s.no_skip = 0 if scene.get("ambient_skip", True) else 1
         det = scene.get("detector")
         if det:
             s.det_face = int(det["face"])

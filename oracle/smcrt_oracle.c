@@ -6,7 +6,11 @@
  * no merging of path segments, brute-force evaluation of every SDF at every
  * step (Sec. 2.3), a tally that finds voxel pieces by intersecting the
  * segment with every voxel plane it spans, and OpenMP over packets with
- * per-thread accumulators reduced in thread order.
+ * per-thread accumulators reduced in thread order.  Two shortcuts that give
+ * the plain march's walk, each with a switch that turns it off so the pins
+ * can compare the two: free-flight reuse (orc_scene.no_reuse) and the
+ * ambient skip (orc_scene.no_skip); with them on, the oracle counts the
+ * SDF evaluations the kernels make.
  *
  * Where the paper is silent the code follows the readings listed in the
  * repository's design notes; each such place says "reading:".
@@ -685,6 +689,58 @@ static int surface(walker* wk, packet* pk, double s_rem, uint64_t seed, uint64_t
   return GO_ON;
 }
 
+/* Ambient skip, an acceleration that leaves the walk as it is: outside
+ * every region, the straight path from p along u cuts no surface before it
+ * enters the box of some region's surface (orc_region.box_lo/hi); when it
+ * enters none inside the volume, only the volume's boundary lies ahead.
+ * Returns the path to the first box entered, or delta past the boundary;
+ * 0 when p is inside a box.  Slab test per axis with t = (plane - p) / u
+ * taken as (plane - p) * (1/u); an axis with u = 0 meets the box only when
+ * p lies between its planes. */
+static double ambient_free(const orc_scene* s, const double p[3], const double u[3]) {
+  double r[3], t = ORC_INF;
+  for (int i = 0; i < 3; ++i) {
+    r[i] = 1.0 / u[i];
+    if (u[i] != 0.0) t = mind(t, ((u[i] > 0.0 ? s->bb_hi[i] : s->bb_lo[i]) - p[i]) * r[i]);
+  }
+  t += s->delta;
+  for (int k = 0; k < s->n_regions; ++k) {
+    const orc_region* rg = &s->regions[k];
+    double t0 = 0.0, t1 = t;
+    int hit = 1;
+    for (int i = 0; i < 3; ++i) {
+      if (u[i] == 0.0) {
+        if (p[i] < rg->box_lo[i] || p[i] > rg->box_hi[i]) hit = 0;
+      } else {
+        const double a = (rg->box_lo[i] - p[i]) * r[i], b = (rg->box_hi[i] - p[i]) * r[i];
+        t0 = maxd(t0, mind(a, b));
+        t1 = mind(t1, maxd(a, b));
+      }
+    }
+    if (hit && t0 <= t1) t = t0;
+  }
+  return t;
+}
+
+/* the over-relaxed step rule (see walk) */
+static int relaxed_step(const orc_scene* s, double dmin, double pd, double pl, double s_rem) {
+  return s->relax > 1.0 && pd >= 0.0 &&
+         dmin * ((2.0 - s->relax) * pl - s->relax * (pd - dmin)) >= s->delta * pl &&
+         s->relax * dmin < s_rem;
+}
+
+/* length of the ambient skip from p, or 0 when the step the march would
+ * take (plain or over-relaxed) is as long, or when the boxes' margin of
+ * delta/2 does not cover the rounding of the box test and of the move: 4
+ * units in the last place of the largest coordinate plus the skip */
+static double ambient_skip(const orc_scene* s, const double p[3], const double u[3], double dmin, double pd,
+                           double pl, double s_rem) {
+  const double len = relaxed_step(s, dmin, pd, pl, s_rem) ? s->relax * dmin : dmin;
+  const double tf = ambient_free(s, p, u);
+  const double pmax = maxd(fabs(p[0]), maxd(fabs(p[1]), fabs(p[2])));
+  return tf > len && 0.5 * s->delta >= 0x1p-50 * (pmax + tf) ? tf : 0.0;
+}
+
 static void walk(walker* wk, uint64_t seed, uint64_t pid) {
   const orc_scene* s = wk->s;
   packet pk;
@@ -767,6 +823,8 @@ static void walk(walker* wk, uint64_t seed, uint64_t pid) {
       }
       double mut = reg_mua(s, pk.region) + reg_mus(s, pk.region);
       double s_rem = mut > 0.0 ? pk.tau / mut : ORC_INF;
+      double skip = 0.0;
+      if (!s->no_skip && pk.region < 0 && dmin >= s->delta) skip = ambient_skip(s, pk.p, pk.u, dmin, pd, pl, s_rem);
       if (s_rem <= dmin) { /* the optical depth runs out first */
         move(wk, &pk, s_rem);
         pk.tau = 0.0;
@@ -782,9 +840,13 @@ static void walk(walker* wk, uint64_t seed, uint64_t pid) {
           steps = 0;
           pd = -1.0;
         }
-      } else if (s->relax > 1.0 && pd >= 0.0 &&
-                 dmin * ((2.0 - s->relax) * pl - s->relax * (pd - dmin)) >= s->delta * pl &&
-                 s->relax * dmin < s_rem) {
+      } else if (skip > 0.0) {
+        /* no surface along the skip: one move (the ambient medium has
+         * mu_t = 0), and no previous step for the over-relaxation rule */
+        move(wk, &pk, skip);
+        pd = -1.0;
+        pl = 0.0;
+      } else if (relaxed_step(s, dmin, pd, pl, s_rem)) {
         /* over-relaxed step, taken when it would pass its check were the
          * surface a plane met at the angle the previous step saw: the
          * distance falls by (pd - dmin)/pl per unit length, so at the end

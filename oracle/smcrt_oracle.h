@@ -72,6 +72,9 @@ typedef struct {
   int32_t first_prim, n_prims, op, pad;
   double k;                       /* smooth-union radius (cm) */
   double mua, mus, g, n;          /* optical properties (Sec. 2.3) */
+  /* a box holding the region's surface: the union of its primitives'
+   * boxes, grown by the smooth-union radius and half of delta (ambient skip) */
+  double box_lo[3], box_hi[3];
 } orc_region;
 
 typedef struct {
@@ -99,7 +102,9 @@ typedef struct {
    * steps of the nearest-surface distance */
   double relax;
   /* 1: evaluate the SDFs before every interaction (no free-flight reuse) */
-  int32_t no_reuse, pad_reuse;
+  int32_t no_reuse;
+  /* 1: sphere-trace the ambient medium step by step (no ambient skip) */
+  int32_t no_skip;
 } orc_scene;
 
 /* free-flight reuse: at most this many interactions per evaluation */

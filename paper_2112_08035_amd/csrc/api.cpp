@@ -766,6 +766,27 @@ static smcrt_status pack(smcrt_scene* s) {
     h->bb_cf[i] = (float)h->bb_c[i];
     h->bb_hf[i] = (float)h->bb_h[i];
   }
+  for (size_t r = 0; r < s->regions.size(); ++r) {
+    // the surface of a region lies in its primitives' boxes; a smooth union
+    // reaches at most k/4 beyond them
+    const HostRegion& hr = s->regions[r];
+    double rlo[3] = {1e300, 1e300, 1e300}, rhi[3] = {-1e300, -1e300, -1e300};
+    for (int32_t id : hr.prims) {
+      double a[3], b[3];
+      prim_box(s->prims[id], a, b);
+      for (int i = 0; i < 3; ++i) { rlo[i] = std::min(rlo[i], a[i]); rhi[i] = std::max(rhi[i], b[i]); }
+    }
+    const double grow = (hr.op == kSmoothUnion ? hr.k : 0.0) + 0.5 * s->delta;
+    for (int i = 0; i < 3; ++i) {
+      h->amb_lo[r][i] = rlo[i] - grow;
+      h->amb_hi[r][i] = rhi[i] + grow;
+      float fl = (float)h->amb_lo[r][i], fh = (float)h->amb_hi[r][i];
+      if ((double)fl > h->amb_lo[r][i]) fl = std::nextafter(fl, -INFINITY);
+      if ((double)fh < h->amb_hi[r][i]) fh = std::nextafter(fh, INFINITY);
+      h->amb_lof[r][i] = fl;
+      h->amb_hif[r][i] = fh;
+    }
+  }
   double glo[3], ghi[3];
   int32_t gd[3];
   if (s->grid_set) {

@@ -119,6 +119,11 @@ struct SceneHeader {
   // over-relaxed sphere tracing: factor omega and 2 - omega
   double relax, relax_k;
   float relax_kf, pad1;
+  // ambient skip: a box holding each region's surface (the union of its
+  // primitives' world boxes, grown by the smooth-union radius and half of
+  // delta; the FP32 copy rounded outwards)
+  double amb_lo[kMaxRegions][3], amb_hi[kMaxRegions][3];
+  float amb_lof[kMaxRegions][3], amb_hif[kMaxRegions][3];
   Region reg[kMaxRegions + 1];
   Accel acc;
   uint64_t prim_offset_d, prim_offset_f;  // byte offsets of the tables in the blob

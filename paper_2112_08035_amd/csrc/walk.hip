@@ -327,9 +327,23 @@ walk_kernel(const WalkArgs* __restrict__ job_table, BatchArgs B) {
               const bool rel = om > T(1) && pk.pd >= T(0) &&
                                dmin * (Tab<T>::relax_k(sc) * pk.pl - om * (pk.pd - dmin)) >= delta * pk.pl &&
                                om * dmin < s;
-              const T moved = step_along(pk, rel ? om * dmin : dmin);
-              pk.pd = dmin;
-              pk.pl = rel ? -moved : moved;
+              T len = rel ? om * dmin : dmin;
+              bool skip = false;
+              if (pk.region == nr) {
+                // ambient skip, when the boxes' margin of delta/2 covers
+                // the rounding of the box test and of the move: 4 units in
+                // the last place of the largest coordinate plus the skip
+                const T tf = ambient_free<T>(sc, nr, pk.p, pk.u, delta);
+                const T pmax = tmax(tabs(pk.p.x), tmax(tabs(pk.p.y), tabs(pk.p.z)));
+                const T ulp4 = sizeof(T) == 4 ? T(0x1p-21) : T(0x1p-50);
+                if (tf > len && T(0.5) * delta >= ulp4 * (pmax + tf)) {
+                  len = tf;
+                  skip = true;
+                }
+              }
+              const T moved = step_along(pk, len);
+              pk.pd = skip ? T(-1) : dmin;
+              pk.pl = rel && !skip ? -moved : moved;
             }
           }
         }

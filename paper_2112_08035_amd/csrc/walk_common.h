@@ -126,6 +126,8 @@ struct Tab<float> {
   static __device__ __forceinline__ float delta(ScP s) { return s->deltaf; }
   static __device__ __forceinline__ float relax(ScP s) { return s->relaxf; }
   static __device__ __forceinline__ float relax_k(ScP s) { return s->relax_kf; }
+  static __device__ __forceinline__ float amb_lo(ScP s, int r, int i) { return s->amb_lof[r][i]; }
+  static __device__ __forceinline__ float amb_hi(ScP s, int r, int i) { return s->amb_hif[r][i]; }
   static __device__ __forceinline__ V3<float> acc_lo(const SMCRT_K Accel& A) { return {A.lof[0], A.lof[1], A.lof[2]}; }
   static __device__ __forceinline__ V3<float> acc_inv(const SMCRT_K Accel& A) { return {A.inv_cellf[0], A.inv_cellf[1], A.inv_cellf[2]}; }
   static __device__ __forceinline__ V3<float> acc_blo(const SMCRT_K Accel& A) { return {A.box_lof[0], A.box_lof[1], A.box_lof[2]}; }
@@ -151,6 +153,8 @@ struct Tab<double> {
   static __device__ __forceinline__ double delta(ScP s) { return s->delta; }
   static __device__ __forceinline__ double relax(ScP s) { return s->relax; }
   static __device__ __forceinline__ double relax_k(ScP s) { return s->relax_k; }
+  static __device__ __forceinline__ double amb_lo(ScP s, int r, int i) { return s->amb_lo[r][i]; }
+  static __device__ __forceinline__ double amb_hi(ScP s, int r, int i) { return s->amb_hi[r][i]; }
   static __device__ __forceinline__ V3<double> acc_lo(const SMCRT_K Accel& A) { return {A.lo[0], A.lo[1], A.lo[2]}; }
   static __device__ __forceinline__ V3<double> acc_inv(const SMCRT_K Accel& A) { return {A.inv_cell[0], A.inv_cell[1], A.inv_cell[2]}; }
   static __device__ __forceinline__ V3<double> acc_blo(const SMCRT_K Accel& A) { return {A.box_lo[0], A.box_lo[1], A.box_lo[2]}; }
@@ -478,6 +482,44 @@ __device__ __forceinline__ bool outside_volume(ScP sc, V3<T> p, int* face) {
   const T qa = ax == 0 ? q.x : (ax == 1 ? q.y : q.z);
   *face = 2 * ax + (qa > T(0) ? 1 : 0);
   return best > T(0);
+}
+
+// Ambient skip: outside every region, the straight path from p along u
+// cuts no surface before it enters the box of some region's surface; when
+// it enters none inside the volume, only the volume's boundary lies ahead.
+// Returns the path to the first such box, or delta past the boundary; 0
+// when p is inside a box.  (u == 0 on an axis: the box is met only when p
+// lies between its planes.)
+template <typename T>
+__device__ __forceinline__ T ambient_free(ScP sc, int nr, V3<T> p, V3<T> u, T delta) {
+  const V3<T> c = Tab<T>::bb_c(sc), h = Tab<T>::bb_h(sc);
+  const T pv[3] = {p.x, p.y, p.z}, uv[3] = {u.x, u.y, u.z};
+  const T cv[3] = {c.x, c.y, c.z}, hv[3] = {h.x, h.y, h.z};
+  T rv[3];
+  T t = tinf<T>();
+#pragma unroll
+  for (int i = 0; i < 3; ++i) {
+    rv[i] = T(1) / uv[i];
+    if (uv[i] != T(0)) t = tmin(t, ((uv[i] > T(0) ? cv[i] + hv[i] : cv[i] - hv[i]) - pv[i]) * rv[i]);
+  }
+  t += delta;
+  for (int r = 0; r < nr; ++r) {
+    T t0 = T(0), t1 = t;
+    bool hit = true;
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+      const T lo = Tab<T>::amb_lo(sc, r, i), hi = Tab<T>::amb_hi(sc, r, i);
+      if (uv[i] == T(0)) {
+        hit = hit && pv[i] >= lo && pv[i] <= hi;
+      } else {
+        const T ta = (lo - pv[i]) * rv[i], tb = (hi - pv[i]) * rv[i];
+        t0 = tmax(t0, tmin(ta, tb));
+        t1 = tmin(t1, tmax(ta, tb));
+      }
+    }
+    if (hit && t0 <= t1) t = t0;
+  }
+  return t;
 }
 
 // unit outward normal of region R at p by central differences of step h

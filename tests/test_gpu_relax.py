@@ -83,14 +83,16 @@ def test_relaxed_step_does_not_jump_a_thin_plate_on_gpu(S, eng, W, u, thick):
 
 
 def test_relaxed_grazing_beam_steps_on_gpu(S, eng, W):
+    # a beam skimming 0.01 cm under the top face of a clear, index-matched
+    # 10 cm block
     prims = [{"kind": "box", "c": [0.0, 0.0, -0.5], "half": [5.0, 5.0, 0.5]}]
-    regions = [W._region([0], 1.0, 0.0, 0.0, 1.0)]
+    regions = [W._region([0], 1e-4, 0.0, 0.0, 1.0)]
     sc = W._scene("graze", prims, regions, None, None, pad=0.5)
-    sc["source"] = {"kind": "pencil", "p": [-5.2, 0.0, 0.01], "u": [1.0, 0.0, 0.0]}
+    sc["source"] = {"kind": "pencil", "p": [-5.2, 0.0, -0.01], "u": [1.0, 0.0, 0.0]}
     for prec in ("f64", "f32"):
         plain = S.run(sc, 1, 1000, engine=eng, precision=prec, tally=False)
         relaxed = S.run(_relaxed(sc), 1, 1000, engine=eng, precision=prec, tally=False)
-        assert plain["escaped_face"][1] == pytest.approx(1000.0) and relaxed["escaped_face"][1] == pytest.approx(1000.0)
+        assert plain["escaped_face"][1] >= 990.0 and abs(relaxed["escaped_face"][1] - plain["escaped_face"][1]) <= 1.0
         assert relaxed["steps"] < 0.6 * plain["steps"], (prec, relaxed["steps"], plain["steps"])
 
 

@@ -117,15 +117,16 @@ def test_relaxed_fluence_and_ledger_equal_plain(orc, W):
 
 
 def test_relaxed_march_saves_grazing_steps(orc, W):
-    # a beam skimming 0.01 cm above a 10 cm face: plain steps are the height
-    # above the face, relaxed ones w times that (1/w as many steps)
+    # a beam skimming 0.01 cm under the top face of a clear, index-matched
+    # 10 cm block: plain steps are the depth under the face, relaxed ones w
+    # times that (1/w as many steps)
     prims = [{"kind": "box", "c": [0.0, 0.0, -0.5], "half": [5.0, 5.0, 0.5]}]
-    regions = [W._region([0], 1.0, 0.0, 0.0, 1.0)]
+    regions = [W._region([0], 1e-4, 0.0, 0.0, 1.0)]
     sc = W._scene("graze", prims, regions, None, None, pad=0.5)
-    sc["source"] = {"kind": "pencil", "p": [-5.2, 0.0, 0.01], "u": [1.0, 0.0, 0.0]}
+    sc["source"] = {"kind": "pencil", "p": [-5.2, 0.0, -0.01], "u": [1.0, 0.0, 0.0]}
     plain = orc.run(sc, 1, 200)
     relaxed = orc.run(_relaxed(sc, 1.9), 1, 200)
-    assert plain["escaped_face"][1] == pytest.approx(200.0) and relaxed["escaped_face"][1] == pytest.approx(200.0)
+    assert plain["escaped_face"][1] >= 198.0 and abs(relaxed["escaped_face"][1] - plain["escaped_face"][1]) <= 1.0
     assert relaxed["steps"] < 0.6 * plain["steps"], (relaxed["steps"], plain["steps"])
 
 
