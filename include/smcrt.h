@@ -147,8 +147,10 @@ smcrt_status smcrt_scene_set_primitive_placement(smcrt_scene* scene, int32_t pri
  * cylinder about the local z axis (radius 1.001 x the largest distance from
  * the axis of the primitive's local box grown by round_r + onion_t, z range
  * that box's grown by 0.1 % of its length at each end) the distance of the
- * untwisted shape is divided by sqrt(1 + (twist_k rho)^2), its Lipschitz
- * bound there, and outside it the distance to that cylinder is used, so
+ * untwisted shape is divided by (k rho + sqrt((k rho)^2 + 4)) / 2 with
+ * k = |twist_k|, the untwist map's Lipschitz bound there (the largest
+ * singular value of its Jacobian), and outside it the distance to that
+ * cylinder is used, so
  * sphere tracing stays conservative.  Zeros remove the modifiers.  Errors:
  * SMCRT_E_INVALID for an unknown primitive, negative or non-finite values. */
 smcrt_status smcrt_scene_set_primitive_modifiers(smcrt_scene* scene, int32_t prim, double round_r, double onion_t,

@@ -128,10 +128,17 @@ def modified_box(p):
     return lo - h - g, hi + h + g
 
 
+def turn_k(p):
+    """Turn rate of a twisted (about z, by k z) or bent (about z, by k x)
+    primitive, 0 for neither"""
+    return float(p.get("twist", 0.0)) or float(p.get("bend", 0.0))
+
+
 def twist_cylinder(p):
-    """Bounding cylinder about the local z axis of a twisted primitive (its
-    modified box): radius 1.001 x the largest distance of that box from the
-    axis, z range the box's grown by 0.1 % of its length at each end."""
+    """Bounding cylinder about the local z axis of a twisted or bent
+    primitive (its modified box; a turn about z keeps the distance from the
+    axis): radius 1.001 x the largest distance of that box from the axis,
+    z range the box's grown by 0.1 % of its length at each end."""
     lo, hi = modified_box(p)
     rho = max(math.hypot(x, y) for x in (lo[0], hi[0]) for y in (lo[1], hi[1]))
     m = 1e-3 * (hi[2] - lo[2])
@@ -140,8 +147,8 @@ def twist_cylinder(p):
 
 def copy_box(p):
     """Box of one copy in the primitive's frame: the modified box, or the
-    twist's bounding cylinder's box"""
-    if p.get("twist", 0.0) != 0.0:
+    twist's or bend's bounding cylinder's box"""
+    if turn_k(p) != 0.0:
         rho, zlo, zhi = twist_cylinder(p)
         return np.array([-rho, -rho, zlo]), np.array([rho, rho, zhi])
     return modified_box(p)
@@ -193,9 +200,11 @@ def prim_struct(p):
     s.s = sc
     s.round_r = float(p.get("round", 0.0))
     s.onion_t = float(p.get("onion", 0.0))
-    if p.get("twist", 0.0) != 0.0:
-        flags |= 2
-        s.twist_k = float(p["twist"])
+    if p.get("twist", 0.0) != 0.0 and p.get("bend", 0.0) != 0.0:
+        raise ValueError("a primitive is either twisted or bent")
+    if turn_k(p) != 0.0:
+        flags |= 2 | (8 if p.get("bend", 0.0) != 0.0 else 0)
+        s.twist_k = turn_k(p)
         s.twist_rho, s.twist_zlo, s.twist_zhi = twist_cylinder(p)
     s.elong = (C.c_double * 3)(*[float(x) for x in p.get("elongate", [0.0, 0.0, 0.0])])
     disp = p.get("displace")

@@ -215,11 +215,17 @@ static double zcyl_sdf(const double p[3], double rho, double zlo, double zhi) {
   return mind(maxd(q1, q2), 0.0) + sqrt(o1 * o1 + o2 * o2);
 }
 
-/* Sec. 2.2: SDFs are translated, rotated, scaled and twisted.  A rigid
- * motion with uniform scale s keeps a distance exact (times s); rounding
- * and an onion shell keep it exact; a twist keeps only the sign and, inside
- * a convex set whose points are within rho of the axis, a Lipschitz bound
- * of sqrt(1 + (k rho)^2), by which the distance is divided there. */
+/* Sec. 2.2: SDFs are translated, rotated, scaled, twisted and bent.  A
+ * rigid motion with uniform scale s keeps a distance exact (times s);
+ * rounding and an onion shell keep it exact; a twist or a bend keeps only
+ * the sign.  The untwist map q(p) = (Rot(-k z)(x, y), z) has Jacobian Rot *
+ * [[1, 0, -k y], [0, 1, k x], [0, 0, 1]], whose largest singular value at
+ * radius rho is (k rho + sqrt((k rho)^2 + 4)) / 2.  The unbend map
+ * q(p) = (Rot(-k x)(x, y), z) has Jacobian Rot * (I + k [[y, 0, 0],
+ * [-x, 0, 0], [0, 0, 0]]), whose largest singular value is at most
+ * 1 + k rho (reached at x = 0).  Inside a convex set whose points are
+ * within rho of the z axis these bound the map's Lipschitz constant, and
+ * the distance is divided by them there. */
 double orc_prim_sdf(const orc_prim* pr, const double p[3]) {
   double q[3] = {p[0], p[1], p[2]};
   if (pr->flags & 1) { /* local = R^T (p - t) / s */
@@ -245,8 +251,8 @@ double orc_prim_sdf(const orc_prim* pr, const double p[3]) {
   double dcyl = 0.0;
   if (pr->flags & 2) {
     dcyl = zcyl_sdf(q, pr->twist_rho, pr->twist_zlo, pr->twist_zhi);
-    /* untwist: rotate by -k z about z */
-    double a = -pr->twist_k * q[2], c = cos(a), sn = sin(a);
+    /* untwist: rotate by -k z about z; unbend: by -k x */
+    double a = -pr->twist_k * ((pr->flags & 8) ? q[0] : q[2]), c = cos(a), sn = sin(a);
     double u0 = c * q[0] - sn * q[1], u1 = sn * q[0] + c * q[1];
     q[0] = u0;
     q[1] = u1;
@@ -258,8 +264,10 @@ double orc_prim_sdf(const orc_prim* pr, const double p[3]) {
   if (pr->disp_a > 0.0)
     d = (d + pr->disp_a * sin(pr->disp_f * q[0]) * sin(pr->disp_f * q[1]) * sin(pr->disp_f * q[2])) /
         (1.0 + pr->disp_a * pr->disp_f * sqrt(3.0));
-  if (pr->flags & 2)
-    d = dcyl > 0.0 ? dcyl : d / sqrt(1.0 + pr->twist_k * pr->twist_k * pr->twist_rho * pr->twist_rho);
+  if (pr->flags & 2) {
+    const double kr = fabs(pr->twist_k) * pr->twist_rho;
+    d = dcyl > 0.0 ? dcyl : d / ((pr->flags & 8) ? 1.0 + kr : 0.5 * (kr + sqrt(kr * kr + 4.0)));
+  }
   if (pr->flags & 4) d = mind(d, pr->rep_gap + b);
   return (pr->flags & 1) ? pr->s * d : d;
 }

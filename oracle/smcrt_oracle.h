@@ -41,18 +41,21 @@ enum {
  * x_world = s * R x_local + t (rotation R, uniform scale s > 0).  In the
  * local frame the query point q is, in this order: repeated (copies of the
  * shape at offsets (i - (n-1)/2) * rep_c per axis, i = 0..n-1, q taken to
- * the nearest copy), untwisted (angle -twist_k * z about z) and elongated
- * (q - clamp(q, -elong, elong)).  The distance of the shape there is
- * rounded (minus round_r), made an onion shell (|d| - onion_t) and
- * displaced (plus disp_a * sin(f q0x) sin(f q0y) sin(f q0z), q0 the point
- * before elongation, divided by 1 + disp_a disp_f sqrt(3)).  A twist bends
- * distances: inside the bounding cylinder (radius twist_rho, z in
- * [twist_zlo, twist_zhi]) the distance is divided by the twist's Lipschitz
- * bound there, sqrt(1 + (twist_k twist_rho)^2); outside it, the distance to
- * that cylinder is used.  A repeated shape takes the smaller of its copy's
- * distance and rep_gap plus the distance to the nearest face of its copy's
- * cell shared with another copy.  flags: bit 0 transform, bit 1 twist,
- * bit 2 repetition. */
+ * the nearest copy), untwisted (angle -twist_k * z about z) or unbent
+ * (angle -twist_k * x about z), and elongated (q - clamp(q, -elong,
+ * elong)).  The distance of the shape there is rounded (minus round_r),
+ * made an onion shell (|d| - onion_t) and displaced (plus disp_a *
+ * sin(f q0x) sin(f q0y) sin(f q0z), q0 the point before elongation,
+ * divided by 1 + disp_a disp_f sqrt(3)).  A twist or a bend stretches
+ * distances: inside the bounding cylinder about z (radius twist_rho, z in
+ * [twist_zlo, twist_zhi]; a turn about z keeps the distance from the axis)
+ * the distance is divided by the map's Lipschitz bound there, with
+ * kr = |twist_k| twist_rho: (kr + sqrt(kr^2 + 4)) / 2 for a twist, 1 + kr
+ * for a bend; outside it, the distance to that cylinder is used.  A
+ * repeated shape takes the smaller of its copy's distance and rep_gap plus
+ * the distance to the nearest face of its copy's cell shared with another
+ * copy.  flags: bit 0 transform, bit 1 twist, bit 2 repetition, bit 3 bend
+ * (with bit 1: the turn angle follows x instead of z). */
 typedef struct {
   int32_t kind;
   int32_t flags;

@@ -624,7 +624,10 @@ static void pack_prim(const HostPrim& h, Prim<T>& o) {
     o.twist_rho = (T)rho;
     o.twist_zc = (T)(0.5 * (z0 + z1));
     o.twist_zh = (T)(0.5 * (z1 - z0));
-    o.inv_lip = (T)(1.0 / std::sqrt(1.0 + h.twist_k * h.twist_k * rho * rho));
+    // Lipschitz bound of the untwist map within radius rho: the largest
+    // singular value of its Jacobian, (k rho + sqrt((k rho)^2 + 4)) / 2
+    const double kr = std::fabs(h.twist_k) * rho;
+    o.inv_lip = (T)(2.0 / (kr + std::sqrt(kr * kr + 4.0)));
   }
   prim_box(h, o.box_lo, o.box_hi);
 }

@@ -254,8 +254,10 @@ __device__ __forceinline__ void tsincos(T a, T* sn, T* cs) {
 // SDF of primitive i (Sec. 2.2: SDFs are translated, rotated, scaled and
 // twisted).  Placement with uniform scale keeps the distance exact (times s),
 // and so do rounding and the onion shell.  A twist keeps the sign; inside its
-// bounding cylinder the distance is divided by the twist's Lipschitz bound
-// there, outside it the distance to the cylinder is used.  The flags are the
+// bounding cylinder (radius rho) the distance is divided by the untwist
+// map's Lipschitz bound there, the largest singular value of its Jacobian,
+// (k rho + sqrt((k rho)^2 + 4)) / 2; outside it the distance to the cylinder
+// is used.  The flags are the
 // same for every lane (primitives are visited in a wave-uniform order).
 // distance from (x, y) to the segment (ax, ay)-(bx, by)
 template <typename T>

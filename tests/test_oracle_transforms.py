@@ -93,7 +93,7 @@ def test_twisted_box_sign_and_lower_bound(orc, W):
     a = k * S[:, 2]
     surf = np.stack([np.cos(a) * S[:, 0] - np.sin(a) * S[:, 1], np.sin(a) * S[:, 0] + np.cos(a) * S[:, 1], S[:, 2]], 1)
     rho = 1.001 * math.hypot(half[0], half[1])
-    L = math.sqrt(1 + (k * rho) ** 2)
+    L = 0.5 * (k * rho + math.sqrt((k * rho) ** 2 + 4))
     rng = np.random.default_rng(4)
     n_in = 0
     for p in rng.uniform(-0.8, 0.8, (400, 3)):
@@ -109,6 +109,109 @@ def test_twisted_box_sign_and_lower_bound(orc, W):
         if np.linalg.norm(p[:2]) < rho and abs(p[2]) < 0.6:    # and not needlessly short
             assert abs(d) >= near / L - spacing, (p, d, near)
     assert n_in > 20
+
+
+@pytest.mark.parametrize("prim", [
+    {"kind": "sphere", "c": [0.25, 0.0, 0.0], "r": 0.05, "twist": 3.0},
+    {"kind": "capsule", "a": [-0.3, 0.0, 0.0], "b": [0.3, 0.0, 0.0], "r": 0.1, "twist": 2.5},
+    {"kind": "box", "c": [0.0, 0.0, 0.0], "half": [0.3, 0.1, 0.5], "twist": -2.5},
+    {"kind": "sphere", "c": [0.0, 0.25, 0.0], "r": 0.05, "bend": 3.0},
+    {"kind": "capsule", "a": [-0.3, 0.0, 0.0], "b": [0.3, 0.0, 0.0], "r": 0.1, "bend": 2.5},
+    {"kind": "box", "c": [0.0, 0.0, 0.0], "half": [0.4, 0.1, 0.1], "bend": -2.0},
+])
+def test_turned_distance_is_1_lipschitz(orc, prim):
+    # a lower bound of the distance must not grow faster than the distance:
+    # the gradient of the twisted or bent SDF inside its bounding cylinder
+    # has norm <= 1.  The untwist map's Jacobian reaches (k rho +
+    # sqrt((k rho)^2 + 4)) / 2 where the shape's gradient mixes the turning
+    # direction with the axis (a sphere off the axis, a capsule's caps);
+    # dividing by sqrt(1 + (k rho)^2) instead leaves gradients up to 1.07
+    # here.  The unbend map's reaches 1 + k rho on the y axis
+    rho, zlo, zhi = orc.twist_cylinder(prim)
+    rng = np.random.default_rng(9)
+    h, worst = 1e-6, 0.0
+    for _ in range(6000):
+        r = (rho - 1e-4) * math.sqrt(rng.uniform()); th = rng.uniform(0, 2 * math.pi)
+        p = np.array([r * math.cos(th), r * math.sin(th), rng.uniform(zlo + 1e-4, zhi - 1e-4)])
+        g = [(orc.prim_sdf(prim, p + h * e) - orc.prim_sdf(prim, p - h * e)) / (2 * h) for e in np.eye(3)]
+        worst = max(worst, float(np.linalg.norm(g)))
+    assert worst <= 1.0 + 1e-6, worst
+    assert worst > 0.6   # the bound is not needlessly loose
+
+
+def bent_points(Q, k):
+    """the points p of the bent shape whose unbent image is Q: p_z = q_z and
+    p_xy = Rot(k p_x) q_xy, solved for p_x by bisection (unique while
+    k |q_xy| < 1)"""
+    out = np.empty_like(Q)
+    for i, (qx, qy, qz) in enumerate(Q):
+        f = lambda t: t - (math.cos(k * t) * qx - math.sin(k * t) * qy)
+        a, b = -2.0, 2.0
+        for _ in range(60):
+            m = 0.5 * (a + b)
+            a, b = (m, b) if f(m) < 0 else (a, m)
+        t = 0.5 * (a + b)
+        out[i] = (t, math.sin(k * t) * qx + math.cos(k * t) * qy, qz)
+    return out
+
+
+def test_bent_capsule_sign_and_lower_bound(orc, W):
+    # a rod along x bent by k x radians about z: surface points are the
+    # capsule's surface carried forward by the bend; the oracle takes the
+    # inverse (unbend) map, so the two meet only through the geometry
+    r, k = 0.06, 1.5
+    prim = {"kind": "capsule", "a": [-0.3, 0.0, 0.0], "b": [0.3, 0.0, 0.0], "r": r, "bend": k}
+    sc = one_prim_scene(W, prim)
+    m = 60
+    g = np.linspace(0, 1, m)
+    U, V = np.meshgrid(g, g)
+    ang = 2 * math.pi * U.ravel()
+    side = np.column_stack([-0.3 + 0.6 * V.ravel(), r * np.cos(ang), r * np.sin(ang)])
+    caps = []
+    for cx, sgn in ((-0.3, -1), (0.3, 1)):
+        th = 0.5 * math.pi * V.ravel()
+        caps.append(np.column_stack([cx + sgn * r * np.sin(th), r * np.cos(th) * np.cos(ang), r * np.cos(th) * np.sin(ang)]))
+    surf = bent_points(np.concatenate([side] + caps), k)
+    rho = orc.twist_cylinder(prim)[0]
+    L = 1 + k * rho
+    rng = np.random.default_rng(14)
+    n_in = 0
+    for p in rng.uniform([-0.45, -0.25, -0.12], [0.45, 0.25, 0.12], (400, 3)):
+        d = orc.region_sdf(sc, 0, p)
+        b = -k * p[0]
+        u = np.array([math.cos(b) * p[0] - math.sin(b) * p[1], math.sin(b) * p[0] + math.cos(b) * p[1], p[2]])
+        x = min(max(u[0], -0.3), 0.3)
+        inside = math.hypot(u[0] - x, math.hypot(u[1], u[2])) < r
+        n_in += inside
+        assert (d < 0) == inside, p
+        near = np.min(np.linalg.norm(surf - p, axis=1))
+        spacing = 0.03
+        assert abs(d) <= near + spacing, (p, d, near)
+        if np.linalg.norm(p[:2]) < rho and abs(p[2]) < r:
+            assert abs(d) >= near / L - spacing, (p, d, near)
+    assert n_in > 10
+
+
+def test_cylinder_bent_about_its_axis_is_the_cylinder(orc, W):
+    # a bend turns about the local z axis: a cylinder on that axis is
+    # unchanged, and the walk meets the same events
+    base = {"kind": "cylinder", "a": [0, 0, -0.5], "b": [0, 0, 0.5], "r": 0.4}
+    plain = one_prim_scene(W, base, 0.5, 1.4)
+    bent = one_prim_scene(W, dict(base, bend=2.0), 0.5, 1.4)
+    plain["regions"][0]["mus"] = bent["regions"][0]["mus"] = 5.0
+    for pid in range(40):
+        a = orc.trace(plain, 8, pid, 80)
+        b = orc.trace(bent, 8, pid, 80)
+        assert [(e["type"], e["region"]) for e in a] == [(e["type"], e["region"]) for e in b], pid
+        for ea, eb in zip(a, b):
+            if ea["type"] != "ESCAPE":
+                assert np.abs(ea["p"] - eb["p"]).max() < 1e-3
+
+
+def test_twist_and_bend_are_exclusive(orc, W):
+    prim = {"kind": "box", "c": [0, 0, 0], "half": [0.2, 0.2, 0.2], "twist": 1.0, "bend": 1.0}
+    with pytest.raises(ValueError):
+        orc.run(one_prim_scene(W, prim), 1, 10)
 
 
 def test_onion_sphere_equals_sphere_difference(orc, W):
