@@ -156,6 +156,19 @@ smcrt_status smcrt_scene_set_primitive_placement(smcrt_scene* scene, int32_t pri
 smcrt_status smcrt_scene_set_primitive_modifiers(smcrt_scene* scene, int32_t prim, double round_r, double onion_t,
                                                  double twist_k);
 
+/* Bend of primitive prim (Sec. 2.2 gallery: bent shapes): the shape turns
+ * by bend_k * x radians about its local z axis at each x, so a rod along x
+ * curves in the local x-y plane.  The sign is kept; inside the bounding
+ * cylinder about the local z axis (as for a twist: a turn about z keeps the
+ * distance from the axis) the distance of the unbent shape is divided by
+ * 1 + |bend_k| rho, the unbend map's Lipschitz bound there (its Jacobian's
+ * largest singular value, reached on the local y axis), and outside it the
+ * distance to that cylinder is used.  0 removes the bend.  A primitive is
+ * either twisted or bent.  Errors: SMCRT_E_INVALID for an unknown
+ * primitive, a non-finite bend_k, or a bend of a twisted primitive (and
+ * smcrt_scene_set_primitive_modifiers rejects a twist of a bent one). */
+smcrt_status smcrt_scene_set_primitive_bend(smcrt_scene* scene, int32_t prim, double bend_k);
+
 /* Elongation of primitive prim (gallery: stretched shapes): in its own
  * frame the point q is replaced by q - clamp(q, -h, h) before the shape is
  * evaluated, which stretches the shape by 2 h[i] along axis i (a sphere

@@ -54,6 +54,7 @@ struct HostPrim {
   double rot[9] = {1, 0, 0, 0, 1, 0, 0, 0, 1};
   double t[3] = {0, 0, 0}, s = 1.0;
   double round_r = 0.0, onion_t = 0.0, twist_k = 0.0;
+  double bend_k = 0.0;  // turn by bend_k * x about the local z axis (exclusive with twist_k)
   double elong[3] = {0, 0, 0};
   double disp_a = 0.0, disp_f = 0.0;
   double rep_c[3] = {1, 1, 1};
@@ -280,10 +281,23 @@ extern "C" smcrt_status smcrt_scene_set_primitive_modifiers(smcrt_scene* s, int3
   if (!(round_r >= 0.0 && std::isfinite(round_r)) || !(onion_t >= 0.0 && std::isfinite(onion_t)))
     return fail(SMCRT_E_INVALID, "set_primitive_modifiers: rounding and shell must be finite and >= 0");
   if (!std::isfinite(twist_k)) return fail(SMCRT_E_INVALID, "set_primitive_modifiers: twist must be finite");
+  if (twist_k != 0.0 && s->prims[prim].bend_k != 0.0)
+    return fail(SMCRT_E_INVALID, "set_primitive_modifiers: primitive %d is bent; a primitive is either twisted or bent", prim);
   HostPrim& p = s->prims[prim];
   p.round_r = round_r;
   p.onion_t = onion_t;
   p.twist_k = twist_k;
+  s->dirty = true;
+  return SMCRT_OK;
+}
+
+extern "C" smcrt_status smcrt_scene_set_primitive_bend(smcrt_scene* s, int32_t prim, double bend_k) {
+  if (!s) return fail(SMCRT_E_INVALID, "set_primitive_bend: NULL scene");
+  if (prim < 0 || prim >= (int32_t)s->prims.size()) return fail(SMCRT_E_INVALID, "set_primitive_bend: no primitive %d", prim);
+  if (!std::isfinite(bend_k)) return fail(SMCRT_E_INVALID, "set_primitive_bend: bend must be finite");
+  if (bend_k != 0.0 && s->prims[prim].twist_k != 0.0)
+    return fail(SMCRT_E_INVALID, "set_primitive_bend: primitive %d is twisted; a primitive is either twisted or bent", prim);
+  s->prims[prim].bend_k = bend_k;
   s->dirty = true;
   return SMCRT_OK;
 }
@@ -432,9 +446,13 @@ static void modified_box(const HostPrim& p, double lo[3], double hi[3]) {
   }
 }
 
-// bounding cylinder about the local z axis of a twisted primitive: radius
-// 1.001 x the largest distance from the axis of its modified box, z range
-// that box's grown by 0.1 % of its length at each end
+// turn rate of a twisted or bent primitive (0: neither)
+static double turn_k(const HostPrim& p) { return p.twist_k != 0.0 ? p.twist_k : p.bend_k; }
+
+// bounding cylinder about the local z axis of a twisted or bent primitive
+// (a turn about z keeps the distance from the axis): radius 1.001 x the
+// largest distance from the axis of its modified box, z range that box's
+// grown by 0.1 % of its length at each end
 static void twist_cylinder(const HostPrim& p, double* rho, double* zlo, double* zhi) {
   double lo[3], hi[3];
   modified_box(p, lo, hi);
@@ -447,10 +465,11 @@ static void twist_cylinder(const HostPrim& p, double* rho, double* zlo, double* 
   *zhi = hi[2] + m;
 }
 
-// box of one copy: the modified box, or the twist's bounding cylinder's box
+// box of one copy: the modified box, or the twist's or bend's bounding
+// cylinder's box
 static void copy_box(const HostPrim& p, double a[3], double b[3]) {
   modified_box(p, a, b);
-  if (p.twist_k != 0.0) {
+  if (turn_k(p) != 0.0) {
     double rho, z0, z1;
     twist_cylinder(p, &rho, &z0, &z1);
     a[0] = a[1] = -rho;
@@ -599,7 +618,7 @@ static void pack_prim(const HostPrim& h, Prim<T>& o) {
   }
   // placement and modifiers
   const bool elongated = h.elong[0] != 0.0 || h.elong[1] != 0.0 || h.elong[2] != 0.0;
-  o.flags = (h.placed ? kPlaced : 0) | (h.twist_k != 0.0 ? kTwisted : 0) |
+  o.flags = (h.placed ? kPlaced : 0) | (turn_k(h) != 0.0 ? kTwisted : 0) | (h.bend_k != 0.0 ? kBent : 0) |
             ((h.round_r != 0.0 || h.onion_t != 0.0 || elongated || h.disp_a != 0.0) ? kModified : 0) |
             (repeated(h) ? kRepeated : 0) | (h.kind >= kCone ? kFurtherShape : 0);
   for (int i = 0; i < 3; ++i) {
@@ -617,17 +636,18 @@ static void pack_prim(const HostPrim& h, Prim<T>& o) {
   o.s = (T)h.s;
   o.round_r = (T)h.round_r;
   o.onion_t = (T)h.onion_t;
-  if (h.twist_k != 0.0) {
+  if (turn_k(h) != 0.0) {
     double rho, z0, z1;
     twist_cylinder(h, &rho, &z0, &z1);
-    o.twist_k = (T)h.twist_k;
+    o.twist_k = (T)turn_k(h);
     o.twist_rho = (T)rho;
     o.twist_zc = (T)(0.5 * (z0 + z1));
     o.twist_zh = (T)(0.5 * (z1 - z0));
-    // Lipschitz bound of the untwist map within radius rho: the largest
-    // singular value of its Jacobian, (k rho + sqrt((k rho)^2 + 4)) / 2
-    const double kr = std::fabs(h.twist_k) * rho;
-    o.inv_lip = (T)(2.0 / (kr + std::sqrt(kr * kr + 4.0)));
+    // Lipschitz bound of the untwist (unbend) map within radius rho: the
+    // largest singular value of its Jacobian, (k rho + sqrt((k rho)^2 + 4))
+    // / 2 (at most 1 + k rho)
+    const double kr = std::fabs(turn_k(h)) * rho;
+    o.inv_lip = (T)(h.bend_k != 0.0 ? 1.0 / (1.0 + kr) : 2.0 / (kr + std::sqrt(kr * kr + 4.0)));
   }
   prim_box(h, o.box_lo, o.box_hi);
 }
@@ -815,7 +835,7 @@ static smcrt_status pack(smcrt_scene* s) {
   h->geometry = s->geometry;
   h->xf = 0;
   for (const HostPrim& hp : s->prims)
-    if (hp.kind >= kCone || hp.placed || hp.twist_k != 0.0 || hp.round_r != 0.0 || hp.onion_t != 0.0 || hp.disp_a != 0.0 || repeated(hp) ||
+    if (hp.kind >= kCone || hp.placed || turn_k(hp) != 0.0 || hp.round_r != 0.0 || hp.onion_t != 0.0 || hp.disp_a != 0.0 || repeated(hp) ||
         hp.elong[0] != 0.0 || hp.elong[1] != 0.0 || hp.elong[2] != 0.0)
       h->xf = 1;
   h->src_kind = s->src_kind;

@@ -50,7 +50,8 @@ enum LaunchClass : int32_t { kLaunchXf = 2, kLaunchClasses = 4 };
 // distance to the cylinder is used.  Repetition: the smaller of that and
 // rep_gap plus the distance to the nearest cell face with another copy
 // behind it.  flags = 0: the plain shape.
-enum PrimFlags { kPlaced = 1, kTwisted = 2, kModified = 4, kRepeated = 8, kFurtherShape = 16 };
+// kBent (with kTwisted): the turn about the local z axis follows x, not z
+enum PrimFlags { kPlaced = 1, kTwisted = 2, kModified = 4, kRepeated = 8, kFurtherShape = 16, kBent = 32 };
 template <typename T>
 struct Prim {
   int32_t kind;

@@ -251,12 +251,13 @@ __device__ __forceinline__ void tsincos(T a, T* sn, T* cs) {
   *cs = q == 0 ? c : (q == 1 ? -s : (q == 2 ? -c : s));
 }
 
-// SDF of primitive i (Sec. 2.2: SDFs are translated, rotated, scaled and
-// twisted).  Placement with uniform scale keeps the distance exact (times s),
-// and so do rounding and the onion shell.  A twist keeps the sign; inside its
-// bounding cylinder (radius rho) the distance is divided by the untwist
-// map's Lipschitz bound there, the largest singular value of its Jacobian,
-// (k rho + sqrt((k rho)^2 + 4)) / 2; outside it the distance to the cylinder
+// SDF of primitive i (Sec. 2.2: SDFs are translated, rotated, scaled,
+// twisted and bent).  Placement with uniform scale keeps the distance exact
+// (times s), and so do rounding and the onion shell.  A twist or a bend
+// keeps the sign; inside its bounding cylinder (radius rho) the distance is
+// divided by the untwist (unbend) map's Lipschitz bound there, the largest
+// singular value of its Jacobian, (k rho + sqrt((k rho)^2 + 4)) / 2 for a
+// twist and 1 + k rho for a bend; outside it the distance to the cylinder
 // is used.  The flags are the
 // same for every lane (primitives are visited in a wave-uniform order).
 // distance from (x, y) to the segment (ax, ay)-(bx, by)
@@ -347,13 +348,13 @@ __device__ __attribute__((noinline)) T placed_prim_sdf(const SMCRT_K Prim<T>* P,
     q = mk(c3[0], c3[1], c3[2]);
   }
   T dcyl = T(0);
-  if (fl & kTwisted) {  // distance to the bounding cylinder, then untwist by -k z about z
+  if (fl & kTwisted) {  // distance to the bounding cylinder, then untwist by -k z (unbend: -k x) about z
     const T q1 = tsqrt(q.x * q.x + q.y * q.y) - Q.twist_rho;
     const T q2 = tabs(q.z - Q.twist_zc) - Q.twist_zh;
     const T o1 = tmax(q1, T(0)), o2 = tmax(q2, T(0));
     dcyl = tmin(tmax(q1, q2), T(0)) + tsqrt(o1 * o1 + o2 * o2);
     T sn, cs;
-    tsincos(-Q.twist_k * q.z, &sn, &cs);
+    tsincos(-Q.twist_k * ((fl & kBent) ? q.x : q.z), &sn, &cs);
     q = mk(cs * q.x - sn * q.y, sn * q.x + cs * q.y, q.z);
   }
   const V3<T> e = mk(q.x - tclamp(q.x, -Q.elong[0], Q.elong[0]), q.y - tclamp(q.y, -Q.elong[1], Q.elong[1]),

@@ -88,6 +88,7 @@ _SIGS = {
     "smcrt_scene_set_primitive_placement": ([_vp, C.c_int32, _dp, C.c_double, _dp], C.c_int),
     "smcrt_scene_set_primitive_modifiers": ([_vp, C.c_int32, C.c_double, C.c_double, C.c_double], C.c_int),
     "smcrt_scene_set_primitive_elongation": ([_vp, C.c_int32, _dp], C.c_int),
+    "smcrt_scene_set_primitive_bend": ([_vp, C.c_int32, C.c_double], C.c_int),
     "smcrt_scene_set_primitive_displacement": ([_vp, C.c_int32, C.c_double, C.c_double], C.c_int),
     "smcrt_scene_set_primitive_repetition": ([_vp, C.c_int32, _dp, C.POINTER(C.c_int32)], C.c_int),
     "smcrt_scene_set_accel": ([_vp, C.c_int32, C.POINTER(C.c_int32)], C.c_int),
@@ -175,6 +176,10 @@ def smcrt_scene_set_primitive_placement(scene, prim, rot, scale, trans):
 
 def smcrt_scene_set_primitive_modifiers(scene, prim, round_r, onion_t, twist_k):
     _check(lib().smcrt_scene_set_primitive_modifiers(scene, prim, round_r, onion_t, twist_k))
+
+
+def smcrt_scene_set_primitive_bend(scene, prim, bend_k):
+    _check(lib().smcrt_scene_set_primitive_bend(scene, prim, bend_k))
 
 
 def smcrt_scene_set_primitive_elongation(scene, prim, h):
@@ -376,6 +381,8 @@ class Scene:
             if p.get("round", 0.0) or p.get("onion", 0.0) or p.get("twist", 0.0):
                 smcrt_scene_set_primitive_modifiers(self.h, pid, float(p.get("round", 0.0)),
                                                     float(p.get("onion", 0.0)), float(p.get("twist", 0.0)))
+            if p.get("bend", 0.0):
+                smcrt_scene_set_primitive_bend(self.h, pid, float(p["bend"]))
             if p.get("elongate"):
                 smcrt_scene_set_primitive_elongation(self.h, pid, [float(x) for x in p["elongate"]])
             if p.get("displace"):

@@ -451,8 +451,9 @@ def shapes_scene(n_grid=48):
     """The further basic shapes of the paper's SDF gallery (Sec. 2.2) in a
     2 x 2 x 2 cm scattering medium (mu_a 0.1, mu_s 20, g 0.9, n 1.33) lit
     from above by a 0.6 cm top-hat beam: a glass frustum, a tilted
-    octahedron of absorbing tissue, a hexagonal glass prism and an
-    ellipsoid of dense scatterer, each its own region."""
+    octahedron of absorbing tissue, a hexagonal glass prism, an ellipsoid
+    of dense scatterer and a bent rod (a capsule curved by 1.5 rad/cm) of
+    blood, each its own region."""
     prims = [
         {"kind": "box", "c": [0.0, 0.0, 0.0], "half": [1.0, 1.0, 1.0]},
         {"kind": "cone", "a": [-0.5, -0.4, 0.5], "b": [-0.3, -0.3, -0.1], "ra": 0.3, "rb": 0.1},
@@ -460,6 +461,8 @@ def shapes_scene(n_grid=48):
          "transform": {"R": rotation([1, 2, 0], 0.5), "t": [0.45, 0.4, 0.3], "s": 1.0}},
         {"kind": "hexprism", "c": [0.4, -0.45, -0.4], "h": 0.25, "hz": 0.2},
         {"kind": "ellipsoid", "c": [-0.4, 0.45, -0.45], "radii": [0.35, 0.2, 0.15]},
+        {"kind": "capsule", "a": [-0.35, 0.0, 0.0], "b": [0.35, 0.0, 0.0], "r": 0.05, "bend": 1.5,
+         "transform": {"R": rotation([1, 0, 0], math.pi / 2), "t": [0.1, 0.0, -0.1], "s": 1.0}},
     ]
     regions = [
         _region([0], 0.1, 20.0, 0.9, 1.33),
@@ -467,6 +470,7 @@ def shapes_scene(n_grid=48):
         _region([2], 3.0, 60.0, 0.9, 1.4),
         _region([3], 0.02, 0.0, 0.0, 1.46),
         _region([4], 0.5, 300.0, 0.8, 1.38),
+        _region([5], 20.0, 400.0, 0.98, 1.4),
     ]
     grid = {"lo": [-1.0] * 3, "hi": [1.0] * 3, "dims": [n_grid] * 3}
     sc = _scene("shapes", prims, regions, None, grid)

@@ -294,6 +294,20 @@ def test_primitive_placement_and_modifier_validation(S):
         with pytest.raises(S.SmcrtError, match="finite"):
             S.smcrt_scene_set_primitive_modifiers(h, p, 0.0, 0.0, float("inf"))
         S.smcrt_scene_set_primitive_modifiers(h, p, 0.1, 0.05, 2.0)
+        # a primitive is either twisted or bent
+        with pytest.raises(S.SmcrtError, match="twisted or bent"):
+            S.smcrt_scene_set_primitive_bend(h, p, 1.0)
+        q = S.smcrt_scene_add_primitive(h, 0, [0, 0, 0, 1.0])
+        with pytest.raises(S.SmcrtError, match="finite"):
+            S.smcrt_scene_set_primitive_bend(h, q, float("nan"))
+        with pytest.raises(S.SmcrtError, match="no primitive"):
+            S.smcrt_scene_set_primitive_bend(h, 9, 1.0)
+        S.smcrt_scene_set_primitive_bend(h, q, 1.5)
+        with pytest.raises(S.SmcrtError, match="twisted or bent"):
+            S.smcrt_scene_set_primitive_modifiers(h, q, 0.0, 0.0, 1.0)
+        S.smcrt_scene_set_primitive_modifiers(h, q, 0.02, 0.0, 0.0)   # rounding of a bent primitive
+        S.smcrt_scene_set_primitive_bend(h, q, 0.0)                   # removed: a twist is allowed again
+        S.smcrt_scene_set_primitive_modifiers(h, q, 0.0, 0.0, 1.0)
     finally:
         S.smcrt_scene_destroy(h)
 

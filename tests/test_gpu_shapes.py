@@ -1,6 +1,6 @@
 """GPU parity of the further gallery shapes (Sec. 2.2: capped cone,
-octahedron, hexagonal prism, ellipsoid) against the oracle on a scene
-holding all four, and their escape closed forms on the GPU.  Same tolerances
+octahedron, hexagonal prism, ellipsoid, and a bent rod) against the oracle
+on a scene holding all five, and escape closed forms on the GPU.  Same tolerances
 as the SDF walk's parity tests; the ellipsoid's distance is a bound, so run
 parity is held to one packet's weight as for the other Lipschitz-scaled
 shapes."""
@@ -46,7 +46,7 @@ def test_shapes_voxelise_like_the_oracle(S, eng, orc, W):
     desc = W.shapes_scene(n_grid=48)
     gv, ov = S.voxelize(desc, engine=eng), orc.voxelize(desc)
     assert len(np.argwhere(gv != ov)) <= max(2, 1e-4 * ov.size)
-    assert set(np.unique(gv)) == {0, 1, 2, 3, 4}
+    assert set(np.unique(gv)) == {0, 1, 2, 3, 4, 5}
 
 
 def _fib(n):

@@ -103,3 +103,16 @@ def test_twisted_cylinder_is_the_cylinder_on_gpu(S, eng, W):
     ea, eb = a["escaped_face"].sum() / N, b["escaped_face"].sum() / N
     assert abs(ea - eb) < 4 * math.sqrt(ea * (1 - ea) / N)
     assert b["steps"] > a["steps"]   # the Lipschitz-scaled distance takes shorter steps
+
+
+def test_cylinder_bent_about_its_axis_is_the_cylinder_on_gpu(S, eng, W):
+    # a bend turns about the local z axis, which a cylinder on that axis
+    # does not see; the Lipschitz-scaled distance takes shorter steps
+    base = {"kind": "cylinder", "a": [0, 0, -0.5], "b": [0, 0, 0.5], "r": 0.4}
+    mk = lambda p: W._scene("one", [p], [W._region([0], 0.5, 5.0, 0.0, 1.4)], {"kind": "point", "p": [0.0, 0.0, 0.0]}, None)
+    N = 200000
+    a = S.run(mk(base), 8, N, engine=eng, precision="f32", tally=False)
+    b = S.run(mk(dict(base, bend=2.0)), 8, N, engine=eng, precision="f32", tally=False)
+    ea, eb = a["escaped_face"].sum() / N, b["escaped_face"].sum() / N
+    assert abs(ea - eb) < 4 * math.sqrt(ea * (1 - ea) / N)
+    assert b["steps"] > a["steps"]
