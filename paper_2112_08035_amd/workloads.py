@@ -478,6 +478,97 @@ def shapes_scene(n_grid=48):
     return sc
 
 
+def random_scene(seed, n_grid=16):
+    """A seeded random scene for property tests: a scattering medium box
+    (2 cm) holding 2-4 further regions of 1-3 primitives each, of every
+    kind, placed (rotation, uniform scale, translation) or not, with random
+    modifiers (rounding, onion shell, twist or bend, elongation,
+    displacement, finite repetition of small spheres), region operations
+    (union, smooth union, intersection, difference), optical properties
+    (index-matched, glass, scattering) and source (point inside, pencil or
+    disc from above)."""
+    rng = np.random.default_rng(seed)
+    u = lambda a, b: float(rng.uniform(a, b))
+    prims = [{"kind": "box", "c": [0.0, 0.0, 0.0], "half": [1.0, 1.0, 1.0]}]
+    regions = [_region([0], u(0.05, 1.0), u(5.0, 40.0), u(0.0, 0.95), u(1.0, 1.45))]
+
+    def shape():
+        kind = str(rng.choice(["sphere", "box", "capsule", "cylinder", "torus", "cone", "octahedron",
+                               "hexprism", "ellipsoid"]))
+        c = [0.0, 0.0, 0.0]
+        if kind == "sphere":
+            return {"kind": kind, "c": c, "r": u(0.08, 0.25)}
+        if kind == "box":
+            return {"kind": kind, "c": c, "half": [u(0.05, 0.25) for _ in range(3)]}
+        if kind in ("capsule", "cylinder"):
+            h = u(0.05, 0.25)
+            return {"kind": kind, "a": [-h, 0.0, 0.0], "b": [h, 0.0, 0.0], "r": u(0.03, 0.12)}
+        if kind == "torus":
+            R = u(0.1, 0.25)
+            return {"kind": kind, "c": c, "axis": rng.normal(size=3).tolist(), "R": R, "r": u(0.02, 0.5 * R)}
+        if kind == "cone":
+            h = u(0.05, 0.25)
+            return {"kind": kind, "a": [0.0, 0.0, -h], "b": [0.0, 0.0, h], "ra": u(0.03, 0.2), "rb": u(0.0, 0.15)}
+        if kind == "octahedron":
+            return {"kind": kind, "c": c, "s": u(0.1, 0.3)}
+        if kind == "hexprism":
+            return {"kind": kind, "c": c, "h": u(0.05, 0.2), "hz": u(0.05, 0.2)}
+        return {"kind": kind, "c": c, "radii": [u(0.05, 0.25) for _ in range(3)]}
+
+    def prim(centre):
+        p = shape()
+        r = rng.uniform()
+        if r < 0.12:  # a small repeated sphere
+            p = {"kind": "sphere", "c": [0.0, 0.0, 0.0], "r": u(0.03, 0.06),
+                 "repeat": {"c": [0.2, 0.2, 0.2], "n": [int(rng.integers(1, 4)) for _ in range(3)]}}
+        else:
+            if rng.uniform() < 0.3:
+                p["round"] = u(0.005, 0.03)
+            if rng.uniform() < 0.2:
+                p["onion"] = u(0.01, 0.03)
+            t = rng.uniform()
+            if t < 0.12:
+                p["twist"] = u(-3.0, 3.0)
+            elif t < 0.24:
+                p["bend"] = u(-2.0, 2.0)
+            if rng.uniform() < 0.15:
+                p["elongate"] = [u(0.0, 0.1) for _ in range(3)]
+            if rng.uniform() < 0.12:
+                p["displace"] = {"a": u(0.002, 0.01), "f": u(5.0, 30.0)}
+        p["transform"] = {"R": rotation(rng.normal(size=3), u(0.0, math.pi)) if rng.uniform() < 0.6 else np.eye(3).tolist(),
+                          "t": list(centre), "s": u(0.6, 1.4)}
+        return p
+
+    for _ in range(int(rng.integers(2, 5))):
+        centre = rng.uniform(-0.55, 0.55, 3)
+        ids = []
+        for _ in range(int(rng.integers(1, 4))):
+            ids.append(len(prims))
+            prims.append(prim(centre + rng.uniform(-0.12, 0.12, 3)))
+        op = "union"
+        if len(ids) > 1:
+            op = str(rng.choice(["union", "smooth_union", "intersect", "subtract"]))
+        k = u(0.01, 0.08) if op == "smooth_union" else 0.0
+        kind = rng.uniform()
+        if kind < 0.25:    # index-matched
+            mua, mus, g, n = u(0.1, 5.0), u(1.0, 50.0), u(0.0, 0.9), regions[0]["n"]
+        elif kind < 0.5:   # glass
+            mua, mus, g, n = u(0.01, 0.5), 0.0, 0.0, u(1.3, 1.6)
+        else:
+            mua, mus, g, n = u(0.1, 10.0), u(5.0, 200.0), u(0.0, 0.98), u(1.3, 1.6)
+        regions.append(_region(ids, mua, mus, g, n, op=op, k=k))
+    grid = {"lo": [-1.0] * 3, "hi": [1.0] * 3, "dims": [n_grid] * 3}
+    sc = _scene(f"random{seed}", prims, regions, None, grid)
+    src = rng.uniform()
+    if src < 0.3:
+        sc["source"] = {"kind": "point", "p": rng.uniform(-0.9, 0.9, 3).tolist()}
+    elif src < 0.65:
+        sc["source"] = {"kind": "pencil", "p": [u(-0.5, 0.5), u(-0.5, 0.5), 1.0 + 0.5 * sc["pad"]], "u": [0.0, 0.0, -1.0]}
+    else:
+        sc["source"] = {"kind": "disc", "c": [0.0, 0.0, 1.0 + 0.5 * sc["pad"]], "r": u(0.2, 0.8), "u": [0.0, 0.0, -1.0]}
+    return sc
+
+
 WORKLOADS = {
     "sphere": sphere_scene,
     "slab": slab_scene,

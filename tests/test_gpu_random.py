@@ -1,0 +1,57 @@
+"""GPU parity with the oracle on seeded random scenes (every primitive kind,
+placements, modifiers, repetition, region operations and sources; see
+workloads.random_scene), through the C ABI: event traces, run totals,
+fluence and voxelisation.  Same tolerances as the fixed scenes' parity
+tests; scenes with bounded distances (twist, bend, displacement,
+ellipsoid) are held to one packet's weight, as there."""
+import numpy as np
+import pytest
+
+from gpu_helpers import check_fluence, compare_traces, extent_of, identity_residual, oracle_batches
+
+pytestmark = pytest.mark.gpu
+
+SEEDS = list(range(12))
+
+
+@pytest.mark.parametrize("seed", SEEDS)
+def test_random_scene_runs_match_oracle(S, eng, orc, W, seed):
+    desc = W.random_scene(seed)
+    n, B = 4000, 8
+    o, se = oracle_batches(orc, desc, 11, n, B)
+    # Monte Carlo standard error of the absorbed total, from the batches
+    per = [orc.run(desc, 11, n // B, first=b * (n // B))["absorbed"].sum() for b in range(B)]
+    se_abs = float(np.sqrt(B * np.var(per, ddof=1)))
+    for prec in ("f64", "f32"):
+        g = S.run(desc, 11, n, engine=eng, precision=prec)
+        assert g["launched"] == n
+        assert abs(identity_residual(g)) <= 1e-9 * n
+        diff = abs(g["absorbed"].sum() - o["absorbed"].sum())
+        print(f"random {seed} {prec}: absorbed difference {diff:.3f} (SE {se_abs:.3f}), "
+              f"interfaces {g['interfaces']} vs {o['interfaces']}")
+        if prec == "f64":   # the same walks, up to one packet a rounding flip sends elsewhere
+            assert diff <= 1.0 + 1e-9 * n, seed
+            assert abs(g["interfaces"] - o["interfaces"]) <= max(2, 2e-3 * o["interfaces"]), seed
+        else:               # FP32 flips send a few packets on other valid walks
+            assert diff <= max(1.0, 3 * se_abs), seed
+            assert abs(g["interfaces"] - o["interfaces"]) <= max(5, 0.02 * o["interfaces"]), seed
+        check_fluence(g, o, se, desc, "f32")
+
+
+@pytest.mark.parametrize("seed", SEEDS[:6])
+def test_random_scene_traces_match_oracle(S, eng, orc, W, seed):
+    desc = W.random_scene(seed)
+    n = 128
+    g = S.trace(desc, 13, list(range(n)), 40, engine=eng, precision="f64")
+    o = [orc.trace(desc, 13, pid, 40) for pid in range(n)]
+    mut = [rg["mua"] + rg["mus"] for rg in desc["regions"]]
+    frac, worst, bad = compare_traces(o, g, extent_of(S, desc), 1e-6, cap=40, mut=mut)
+    print(f"random {seed}: agree {frac:.4f} worst {worst} first disagreements {bad[:5]}")
+    assert frac >= 0.97, (seed, frac, worst, bad[:10])
+
+
+@pytest.mark.parametrize("seed", SEEDS)
+def test_random_scene_voxelises_like_the_oracle(S, eng, orc, W, seed):
+    desc = W.random_scene(seed, n_grid=32)
+    gv, ov = S.voxelize(desc, engine=eng), orc.voxelize(desc)
+    assert len(np.argwhere(gv != ov)) <= max(2, 1e-4 * ov.size), seed
