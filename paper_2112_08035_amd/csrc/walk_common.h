@@ -57,14 +57,25 @@ __device__ __forceinline__ void tsincos_2pi(float xi, float* s, float* c) {
 __device__ __forceinline__ void tsincos_2pi(double xi, double* s, double* c) { sincos(2.0 * M_PI * xi, s, c); }
 __device__ __forceinline__ float tdiv(float a, float b) { return __fdividef(a, b); }
 __device__ __forceinline__ double tdiv(double a, double b) { return a / b; }
+// min, max, abs and clamp as single instructions (v_min/v_max, an abs
+// source modifier, v_med3 for a clamp); a NaN operand yields the other one
 template <typename T>
-__device__ __forceinline__ T tmin(T a, T b) { return a < b ? a : b; }
+__device__ __forceinline__ T tmin(T a, T b) {
+  if constexpr (sizeof(T) == 4) return __builtin_fminf(a, b);
+  else return __builtin_fmin(a, b);
+}
 template <typename T>
-__device__ __forceinline__ T tmax(T a, T b) { return a > b ? a : b; }
+__device__ __forceinline__ T tmax(T a, T b) {
+  if constexpr (sizeof(T) == 4) return __builtin_fmaxf(a, b);
+  else return __builtin_fmax(a, b);
+}
 template <typename T>
-__device__ __forceinline__ T tabs(T a) { return a < T(0) ? -a : a; }
+__device__ __forceinline__ T tabs(T a) {
+  if constexpr (sizeof(T) == 4) return __builtin_fabsf(a);
+  else return __builtin_fabs(a);
+}
 template <typename T>
-__device__ __forceinline__ T tclamp(T x, T lo, T hi) { return x < lo ? lo : (x > hi ? hi : x); }
+__device__ __forceinline__ T tclamp(T x, T lo, T hi) { return tmin(tmax(x, lo), hi); }
 template <typename T>
 __device__ __forceinline__ T tinf();
 template <>
