@@ -293,11 +293,13 @@ def test_split_runs_add_up(S, eng, W):
         assert ha[k] == hb[k]
 
 
-@pytest.mark.parametrize("n", [1, 63, 65, 100003])
+@pytest.mark.parametrize("n", [0, 1, 63, 65, 100003])
 def test_ragged_packet_counts(S, eng, orc, W, n):
     desc = W.sphere_scene(n_grid=10)
     g = S.run(desc, 31, n, engine=eng, precision="f64")
     assert g["launched"] == n
+    if n == 0:   # an empty run adds nothing
+        assert g["interactions"] == g["steps"] == 0 and not g["fluence_raw"].any() and not g["absorbed"].any()
     assert abs(identity_residual(g)) <= 1e-9 * max(n, 1)
     if n <= 65:
         # same walks; positions differ by FP64 rounding amplified by repeated
@@ -372,3 +374,45 @@ def test_full_size_slab_bench_config(S, orc, W):
     assert np.all(np.abs(absorbed_g - absorbed_o) <= 4 * np.sqrt(0.25 / n_o) + 1e-12)
     e.close()
     torch.cuda.synchronize()
+
+
+@pytest.mark.parametrize("prec", ["f32", "f64"])
+def test_largest_grid(S, eng, W, prec):
+    """A grid at the size limit (2048 x 1024 x 1023 voxels, 2^31 - 2.1e6 of
+    them, 17 GB of FP64): a clear, index-matched block fills it and a pencil
+    beam runs along +x through the centres of the last voxel row (largest y
+    and z, so the largest linear indices).  Every packet crosses the row in
+    a straight line: each inner voxel of the row receives exactly dx per
+    packet and no other voxel receives anything."""
+    import torch
+    nx, ny, nz = 2048, 1024, 1023
+    lo, hi = np.array([0.0, 0.0, 0.0]), np.array([2.048, 1.024, 1.023])
+    d = (hi - lo) / [nx, ny, nz]
+    prims = [{"kind": "box", "c": (0.5 * (lo + hi)).tolist(), "half": (0.5 * (hi - lo)).tolist()}]
+    regions = [W._region([0], 1e-12, 0.0, 0.0, 1.0)]
+    sc = W._scene("largest_grid", prims, regions, None, {"lo": lo.tolist(), "hi": hi.tolist(), "dims": [nx, ny, nz]},
+                  pad=0.01)
+    yc, zc = hi[1] - 0.5 * d[1], hi[2] - 0.5 * d[2]
+    sc["source"] = {"kind": "pencil", "p": [-0.005, yc, zc], "u": [1.0, 0.0, 0.0]}
+    N = 2000
+    eng.set_opts(precision=prec)
+    scene = S.Scene(sc)
+    out = S.Outputs(scene)
+    assert out.fluence.numel() == nx * ny * nz
+    S.launch(eng, scene, 1, N, outputs=out)
+    torch.cuda.synchronize()
+    F = out.fluence
+    row0 = (nz - 1) * nx * ny + (ny - 1) * nx          # first voxel of the last row
+    assert row0 + nx == nx * ny * nz
+    row = F[row0:].double().cpu().numpy()
+    # FP32 transport: the piece lengths are differences of ray parameters up
+    # to 2 cm, so each carries up to about one unit in the last place of 2
+    # (2.4e-7 cm, 2.4e-4 of a voxel); the pieces of a row telescope
+    tol = 5e-4 if prec == "f32" else 1e-9
+    np.testing.assert_allclose(row[1:-1], N * d[0], rtol=tol)
+    assert abs(row.sum() - N * (hi[0] - lo[0])) <= N * 4e-5      # the entry face: 2 delta not credited
+    assert int(torch.count_nonzero(F[:row0]).item()) == 0       # nothing anywhere else
+    t = S.Tallies.from_buffer_copy(bytes(out.tallies.cpu().numpy().tobytes()))
+    assert t.launched == N and t.escaped_face[1] == pytest.approx(N, rel=1e-9)
+    del F, out
+    torch.cuda.empty_cache()
