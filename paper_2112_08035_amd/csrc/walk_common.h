@@ -639,6 +639,13 @@ template <>
 __device__ __forceinline__ float trcp<float>(float x) { return __builtin_amdgcn_rcpf(x); }
 template <>
 __device__ __forceinline__ double trcp<double>(double x) { return 1.0 / x; }
+// 1/sqrt(x): one instruction (1 ulp) in FP32, correctly rounded in FP64
+template <typename T>
+__device__ __forceinline__ T trsqrt(T x);
+template <>
+__device__ __forceinline__ float trsqrt<float>(float x) { return __builtin_amdgcn_rsqf(x); }
+template <>
+__device__ __forceinline__ double trsqrt<double>(double x) { return 1.0 / __builtin_sqrt(x); }
 
 // One axis of the voxel walk: voxel index, step (+1, -1 or 0), ray
 // parameter of the next plane crossing, and the spacing of the crossings.
@@ -977,12 +984,12 @@ __device__ bool interact(JobRef a, Packet<T>& pk, Lane& ln, LdsTallies& L) {
   } else {
     // sqrt(1 - uz^2) from the other two components: no cancellation near the poles
     const T tt = tsqrt(u.x * u.x + u.y * u.y);
-    const T itt = T(1) / tt;
+    const T itt = trcp(tt);
     v.x = st * (u.x * u.z * cp - u.y * sp) * itt + u.x * ct;
     v.y = st * (u.y * u.z * cp + u.x * sp) * itt + u.y * ct;
     v.z = -st * cp * tt + u.z * ct;
   }
-  pk.u = (T(1) / tsqrt(dot(v, v))) * v;
+  pk.u = trsqrt(dot(v, v)) * v;
   // Russian roulette on the weight
   if (pk.w < sc->w_threshold) {
     const double x2 = xi_of<double>(r.w2);
