@@ -52,9 +52,10 @@ def slab_lane_ops(t, n_prims):
             + (t["interfaces"] + t["advances"]) * surf + t["voxel_pieces"] * COST["voxel"])
 
 
-def measured_traffic():
-    """HBM-side bytes per launch from the committed rocprofv3 counter summary,
-    or None when the kernel sources changed since those counters were taken."""
+def measured_counters():
+    """Per-launch figures of the committed rocprofv3 counter summary (HBM
+    traffic, atomic requests), or {} when the kernel sources changed since
+    those counters were taken."""
     import hashlib
     csrc = os.path.join(ROOT, "paper_2112_08035_amd", "csrc")
     h = hashlib.sha256()
@@ -63,28 +64,35 @@ def measured_traffic():
             h.update(fh.read())
     path = os.path.join(ROOT, "profiles", "walk_kernel_slab_1e7_f32_traffic.md")
     if not os.path.exists(path):
-        return None
+        return {}
     vals = {}
     for line in open(path):
         if ":" in line and not line.startswith((" ", "|", "#")):
             k, v = line.split(":", 1)
             vals[k.strip()] = v.strip()
     if vals.get("kernel_source_sha256_16") != h.hexdigest()[:16]:
-        return None
-    return float(vals["traffic_bytes_per_launch"])
+        return {}
+    return {k: float(vals[k]) for k in ("traffic_bytes_per_launch", "atomic_requests_per_launch") if k in vals}
+
+
+def measured_traffic():
+    """HBM-side bytes per launch (committed counter summary), or None."""
+    return measured_counters().get("traffic_bytes_per_launch")
 
 
 SERVE_GRIDS = (32, 64, 128)
 
 
-def atomic_ceiling():
-    """FP64 global atomic adds per second measured on the device by
-    paper_2112_08035_amd/atomic_ceiling (committed summary), or None."""
+def atomic_ceiling(key="requests_per_s"):
+    """FP64 global atomic 64-byte requests per second measured on the device
+    by paper_2112_08035_amd/atomic_ceiling (committed summary), or None.
+    The rate is per request: the adds of one instruction that fall in one
+    64-byte segment travel as one request."""
     path = os.path.join(ROOT, "profiles", "fp64_atomic_ceiling.md")
     if not os.path.exists(path):
         return None
     for line in open(path):
-        if line.startswith("atomics_per_s:"):
+        if line.startswith(key + ":"):
             return float(line.split(":", 1)[1])
     return None
 
@@ -480,6 +488,8 @@ def main():
     lane_ops = slab_lane_ops(per, len(desc["prims"]))
     achieved = lane_ops / (launch_ms * 1e-3)
     ceiling = atomic_ceiling()
+    counters = measured_counters() if args.precision == "f32" else {}
+    reqs = counters.get("atomic_requests_per_launch")
     identity = (h["absorbed"].sum() + h["escaped_face"].sum() + h["roulette_loss"] - h["roulette_gain"]
                 + h["stalled"] - h["launched"])
 
@@ -512,13 +522,14 @@ def main():
             "peak": PEAK_LANE_OPS / 1e12,
             "unit": "Tlane-op/s",
             "frac": achieved / PEAK_LANE_OPS,
-            "traffic": measured_traffic() if args.precision == "f32" else None,
+            "traffic": counters.get("traffic_bytes_per_launch"),
             "kernel_ms": launch_ms,
             "step_kernel_ms": step_ms,
             "lane_ops_per_launch": lane_ops,
             "grid_atomics_per_s": per["grid_atomics"] / (launch_ms * 1e-3),
-            "atomic_ceiling_per_s": ceiling,
-            "atomic_frac": (per["grid_atomics"] / (launch_ms * 1e-3) / ceiling) if ceiling else None,
+            "atomic_requests_per_launch": reqs,
+            "atomic_request_ceiling_per_s": ceiling,
+            "atomic_request_frac": (reqs / (launch_ms * 1e-3) / ceiling) if (ceiling and reqs) else None,
         },
     }
 

@@ -10,8 +10,12 @@
 // workgroup scope, and per-XCD private copies of the grid (each workgroup
 // adds into the copy of the XCD it runs on).  Every index is reduced modulo
 // the grid size; the exact total of the adds is checked after each run.
-// Prints one line per form and pattern, then "atomics_per_s: <best of the
-// builtin form>".
+// A second part gives the lanes of each instruction hashed segments shared
+// by g consecutive lanes (g = 1, 2, 4, 8, 16, 64 contiguous doubles), to show
+// whether the rate is per add or per 64-byte memory request (a segment of
+// g < 8 doubles is one request, a wider one g / 8).
+// Prints one line per form and pattern, one per segment width, then
+// "atomics_per_s: <best of the builtin form>".
 #include <hip/hip_runtime.h>
 
 #include <cstdio>
@@ -69,6 +73,17 @@ __global__ void __launch_bounds__(256) adds(double* F, uint32_t nx, uint32_t ny,
   }
 }
 
+// lanes tid..tid+g-1 (g divides 64) add at g consecutive doubles of one
+// hashed, g-aligned segment of the n-element grid (g divides n)
+__global__ void __launch_bounds__(256) segment_adds(double* F, uint32_t n, int iters, int g) {
+  const uint32_t tid = blockIdx.x * blockDim.x + threadIdx.x;
+  const uint32_t seg = tid / (uint32_t)g, nseg = n / (uint32_t)g;
+  for (int i = 0; i < iters; ++i) {
+    const uint32_t base = (hash32(seg ^ hash32((uint32_t)i + 777U)) % nseg) * (uint32_t)g;
+    __builtin_amdgcn_global_atomic_fadd_f64((__attribute__((address_space(1))) double*)(F + base + (threadIdx.x & 63u) % (uint32_t)g), 1.0);
+  }
+}
+
 __global__ void sum_kernel(const double* F, size_t n, double* out) {
   double s = 0.0;
   for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) s += F[i];
@@ -117,6 +132,31 @@ int main() {
                   sum == want ? "exact" : "WRONG");
       std::fflush(stdout);
     }
+  }
+  const int widths[] = {1, 2, 4, 8, 16, 64};
+  for (int wi = 0; wi < 6; ++wi) {
+    const int g = widths[wi];
+    if (n % (uint32_t)g != 0) return 2;
+    float ms = 0.0f;
+    double sum = 0.0;
+    for (int rep = 0; rep < 2; ++rep) {
+      CHECK(hipMemset(F, 0, sizeof(double) * n));
+      CHECK(hipMemset(d_sum, 0, sizeof(double)));
+      CHECK(hipDeviceSynchronize());
+      CHECK(hipEventRecord(a, 0));
+      hipLaunchKernelGGL(segment_adds, dim3(blocks), dim3(threads), 0, 0, F, n, iters, g);
+      CHECK(hipGetLastError());
+      CHECK(hipEventRecord(b, 0));
+      CHECK(hipEventSynchronize(b));
+      CHECK(hipEventElapsedTime(&ms, a, b));
+      hipLaunchKernelGGL(sum_kernel, dim3(1024), dim3(256), 0, 0, F, (size_t)n, d_sum);
+      CHECK(hipGetLastError());
+      CHECK(hipMemcpy(&sum, d_sum, sizeof(double), hipMemcpyDeviceToHost));
+    }
+    std::printf("segment of %2d doubles per %2d lanes %8.2f ms  %.3e atomics/s  %.3e 64-byte requests/s  total %s\n", g, g,
+                ms, want / (ms * 1e-3), want / (ms * 1e-3) / (g < 8 ? g : 8),
+                sum == want ? "exact" : "WRONG");
+    std::fflush(stdout);
   }
   std::printf("atomics_per_s: %.4e\n", best_builtin);
   CHECK(hipFree(F));
