@@ -55,3 +55,23 @@ def test_random_scene_voxelises_like_the_oracle(S, eng, orc, W, seed):
     desc = W.random_scene(seed, n_grid=32)
     gv, ov = S.voxelize(desc, engine=eng), orc.voxelize(desc)
     assert len(np.argwhere(gv != ov)) <= max(2, 1e-4 * ov.size), seed
+
+
+@pytest.mark.parametrize("seed", SEEDS[:6])
+def test_random_scene_escape_images(S, eng, orc, W, seed):
+    # a 12 x 12 escape image on a face that changes with the seed, against
+    # the oracle's on the same packets: per pixel within 3 Monte Carlo SE
+    # (floored at one packet's weight), totals within one packet
+    from gpu_helpers import batch_se
+    desc = W.random_scene(seed)
+    desc["detector"] = {"face": seed % 6, "lo": [-1.0, -1.0], "hi": [1.0, 1.0], "dims": [12, 12]}
+    n, B = 6000, 8
+    imgs = [orc.run(desc, 17, n // B, first=b * (n // B))["image"] for b in range(B)]
+    o, se = sum(imgs), batch_se(imgs)
+    for prec in ("f64", "f32"):
+        g = S.run(desc, 17, n, engine=eng, precision=prec)["image"]
+        z = np.abs(g - o) / np.maximum(se, 1.0)
+        print(f"random {seed} face {seed % 6} {prec}: image total {g.sum():.3f} vs {o.sum():.3f}, "
+              f"pixels within 3 SE {np.mean(z <= 3):.4f}")
+        assert np.mean(z <= 3.0) >= 0.99, seed
+        assert abs(g.sum() - o.sum()) <= 1.0 + 1e-9 * n or prec == "f32" and abs(g.sum() - o.sum()) <= 3.0, seed
