@@ -75,3 +75,32 @@ def test_random_scene_escape_images(S, eng, orc, W, seed):
               f"pixels within 3 SE {np.mean(z <= 3):.4f}")
         assert np.mean(z <= 3.0) >= 0.99, seed
         assert abs(g.sum() - o.sum()) <= 1.0 + 1e-9 * n or prec == "f32" and abs(g.sum() - o.sum()) <= 3.0, seed
+
+
+@pytest.mark.parametrize("seed", SEEDS[:6])
+def test_random_scene_relaxed_runs_match_oracle(S, eng, orc, W, seed):
+    # over-relaxed steps (w = 1.9) on the random scenes: the FP64 walk takes
+    # the relaxed oracle's decisions
+    desc = dict(W.random_scene(seed), relax=1.9)
+    n = 3000
+    o = orc.run(desc, 23, n)
+    g = S.run(desc, 23, n, engine=eng, precision="f64")
+    assert abs(g["absorbed"].sum() - o["absorbed"].sum()) <= 1.0 + 1e-9 * n, seed
+    assert abs(g["interfaces"] - o["interfaces"]) <= max(2, 2e-3 * o["interfaces"]), seed
+    assert abs(identity_residual(g)) <= 1e-9 * n
+
+
+@pytest.mark.parametrize("seed", SEEDS)
+def test_random_scene_acceleration_grid(S, eng, W, seed):
+    # the uniform grid over a union region of placed and modified primitives
+    # changes how far steps go, never a decision
+    desc = W.random_scene(seed)
+    regs = [i for i, rg in enumerate(desc["regions"]) if rg["op"] == "union" and len(rg["prims"]) >= 2]
+    if not regs:
+        pytest.skip("no union region of several primitives in this scene")
+    desc = dict(desc, accel_cells=[8, 8, 8])   # the binding takes the union region with most primitives
+    plain = S.run(dict(desc, accel_cells=None), 29, 3000, engine=eng, precision="f64")
+    accel = S.run(desc, 29, 3000, engine=eng, precision="f64")
+    for k in ("interactions", "interfaces", "reflections", "refractions", "kills", "escapes"):
+        assert abs(accel[k] - plain[k]) <= max(1, 1e-3 * plain[k]), (seed, k, accel[k], plain[k])
+    assert abs(accel["absorbed"].sum() - plain["absorbed"].sum()) <= 1.0 + 1e-9 * 3000
