@@ -286,7 +286,15 @@ typedef struct {
   int32_t use_graph;    /* 1: capture the device work of a launch (grid builds,
                            counter reset, walk) in a hipGraph and replay it
                            while the launch shape is unchanged */
-  int32_t reserved[2];
+  int32_t tally_layout; /* 0: the library picks: FP32 SDF jobs whose voxels are
+                           cubes (grids up to 2^27 voxels) tally into an
+                           engine-owned grid of 2x2x2 bricks (the eight voxels
+                           of a brick in one 64-byte segment, so neighbouring
+                           voxels share atomic requests), added into the
+                           caller's x-fastest grid after the walk; 1: always
+                           tally into the caller's grid directly.  Results
+                           agree to the order of FP64 sums. */
+  int32_t reserved;
 } smcrt_opts;
 
 smcrt_status smcrt_engine_get_opts(const smcrt_engine* engine, smcrt_opts* out);

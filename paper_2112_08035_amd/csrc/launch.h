@@ -14,6 +14,10 @@ hipError_t launch_walk(int precision, bool trace, const LaunchCfg& cfg, const Ba
 hipError_t launch_voxelize(const WalkArgs* d_jobs, int job, uint8_t* vox, size_t n_vox, hipStream_t stream);
 // p[i] = 0 for i < n (a kernel, so resets can sit inside captured graphs)
 hipError_t launch_zero_u64_n(unsigned long long* p, int n, hipStream_t stream);
+// zero n doubles (a kernel, so it can sit in a captured graph)
+hipError_t launch_zero_f64(double* p, size_t n, hipStream_t stream);
+// F (x fastest, nx*ny*nz) += S (the 2x2x2-brick grid the walk tallied into)
+hipError_t launch_brick_add(const double* S, double* F, int nx, int ny, int nz, hipStream_t stream);
 // *p = 0 (a one-thread kernel, so the reset can sit inside captured graphs)
 hipError_t launch_zero_u64(unsigned long long* p, hipStream_t stream);
 // out[i] = in[i] * scale for i < n

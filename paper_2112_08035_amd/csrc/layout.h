@@ -158,6 +158,7 @@ struct WalkArgs {
   int32_t n_trace, max_records;
   int32_t acc_region;            // copy of sc->acc.region (-1 = none)
   int32_t geometry;              // launch class: sc->geometry, plus kLaunchXf when sc->xf
+  int32_t brick, pad_brick;      // 1: fluence is the 2x2x2-brick scratch grid (brick_index)
   uint8_t* vox;                  // voxel model: region slot per voxel (nx*ny*nz, x fastest)
   double* detector;              // escape image (det_dims[0] * det_dims[1]), may be null
 };

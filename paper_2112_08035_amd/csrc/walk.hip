@@ -434,6 +434,33 @@ hipError_t launch_zero_u64_n(unsigned long long* p, int n, hipStream_t stream) {
   return hipGetLastError();
 }
 
+__global__ void zero_f64_kernel(double* p, size_t n) {
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) p[i] = 0.0;
+}
+
+// F (x fastest, nx*ny*nz) += S (2x2x2 bricks)
+__global__ void brick_add_kernel(const double* __restrict__ S, double* __restrict__ F, int nx, int ny, int nz) {
+  const size_t n = (size_t)nx * ny * nz;
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
+    const int x = (int)(i % (size_t)nx), y = (int)((i / (size_t)nx) % (size_t)ny), z = (int)(i / ((size_t)nx * ny));
+    F[i] += S[brick_index(x, y, z, nx, ny)];
+  }
+}
+
+hipError_t launch_zero_f64(double* p, size_t n, hipStream_t stream) {
+  if (!p || n == 0) return hipErrorInvalidValue;
+  const size_t blocks = (n + 255) / 256;
+  hipLaunchKernelGGL(zero_f64_kernel, dim3(blocks < 4096 ? (unsigned)blocks : 4096u), dim3(256), 0, stream, p, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_brick_add(const double* S, double* F, int nx, int ny, int nz, hipStream_t stream) {
+  if (!S || !F || nx < 1 || ny < 1 || nz < 1) return hipErrorInvalidValue;
+  const size_t n = (size_t)nx * ny * nz, blocks = (n + 255) / 256;
+  hipLaunchKernelGGL(brick_add_kernel, dim3(blocks < 4096 ? (unsigned)blocks : 4096u), dim3(256), 0, stream, S, F, nx, ny, nz);
+  return hipGetLastError();
+}
+
 hipError_t launch_zero_u64(unsigned long long* p, hipStream_t stream) {
   hipLaunchKernelGGL(zero_u64_kernel, dim3(1), dim3(1), 0, stream, p);
   return hipGetLastError();

@@ -633,6 +633,16 @@ __device__ __forceinline__ void run_add(double* F, Lane& ln, int v, double val) 
   }
 }
 
+// Index of voxel (x, y, z) in a grid of 2x2x2 bricks ((nx+1)/2 by (ny+1)/2
+// by (nz+1)/2 bricks, x fastest), a brick's eight voxels consecutive (x
+// fastest inside): the neighbours of a path share 64-byte segments, so more
+// of a wave's atomic adds travel in one request.
+__device__ __forceinline__ int brick_index(int x, int y, int z, int nx, int ny) {
+  const int bx = (nx + 1) >> 1, by = (ny + 1) >> 1;
+  const int b = ((z >> 1) * by + (y >> 1)) * bx + (x >> 1);
+  return (b << 3) | ((z & 1) << 2) | ((y & 1) << 1) | (x & 1);
+}
+
 template <typename T>
 __device__ __forceinline__ T trcp(T x);
 template <>
@@ -714,7 +724,7 @@ __device__ __forceinline__ void tally_move(JobRef a, V3<T> p, V3<T> u, T len, do
   for (int it = 0; it < cap; ++it) {
     const T tn = tmin(tmin(X.tn, Y.tn), tmin(Z.tn, t1));
     const T piece = tn - t;
-    if (piece > T(0)) run_add(a.fluence, ln, lin, w * (double)piece);
+    if (piece > T(0)) run_add(a.fluence, ln, a.brick ? brick_index(X.i, Y.i, Z.i, nx, ny) : lin, w * (double)piece);
     if (tn >= t1) break;
     // cross the nearest plane (ties: x before y before z)
     const bool bx = X.tn <= Y.tn && X.tn <= Z.tn;

@@ -180,14 +180,16 @@ def test_many_small_jobs_share_one_launch(S, eng, W):
     assert total == 200 * 500
 
 
-def test_graph_replays_match_eager_runs(S, W):
-    """A captured launch sequence (grid builds, counter reset, walk) replayed
-    several times, with eager work and synchronisations in between: every
-    replay equals the eager run of the same seeds."""
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_graph_replays_match_eager_runs(S, W, prec):
+    """A captured launch sequence (grid builds, counter reset, brick-grid
+    zeroing in FP32, walk, brick-grid addition) replayed several times, with
+    eager work and synchronisations in between: every replay equals the
+    eager run of the same seeds."""
     import torch
     descs = [W.vessel_scene(21, 1.0, n_caps=200, n_grid=16), W.sphere_scene(n_grid=12)]
-    g_eng = S.Engine(0, precision="f64", use_graph=1)
-    e_eng = S.Engine(0, precision="f64")
+    g_eng = S.Engine(0, precision=prec, use_graph=1)
+    e_eng = S.Engine(0, precision=prec)
     scenes = [S.Scene(d) for d in descs]
     for rep in range(4):
         seeds = [100 + rep, 200 + rep]
@@ -338,6 +340,35 @@ def test_invalid_options_rejected(S, eng):
         eng.set_opts(block=100)
     with pytest.raises(S.SmcrtError, match="precision"):
         eng.set_opts(precision=5)
+    with pytest.raises(S.SmcrtError, match="tally_layout"):
+        eng.set_opts(tally_layout=2)
+
+
+@pytest.mark.parametrize("dims", [[32, 32, 32], [17, 18, 19]])
+def test_brick_tally_equals_direct(S, W, dims):
+    """Cubic voxels: the FP32 walk tallies into 2x2x2 bricks and adds them into
+    the caller's x-fastest grid; with bricks refused (tally_layout 1) it adds
+    directly.  Same walks, same fluence up to the order of FP64 sums, also
+    for odd sizes (partial bricks at the far faces) and in a batch beside a
+    flat-voxel job that keeps the direct layout."""
+    h = 2.0 / max(dims)
+    desc = W.sphere_scene(n_grid=8)
+    desc["grid"] = {"lo": [-1.0] * 3, "hi": [-1.0 + h * n for n in dims], "dims": list(dims)}
+    flat = W.slab_scene(n_grid=16)
+    e_b, e_d = S.Engine(0, precision="f32"), S.Engine(0, precision="f32", tally_layout=1)
+    assert e_b.opts()["tally_layout"] == 0 and e_d.opts()["tally_layout"] == 1
+    a = S.run(desc, 41, 20000, engine=e_b, precision="f32")
+    b = S.run(desc, 41, 20000, engine=e_d, precision="f32")
+    for k in ("interactions", "interfaces", "escapes", "voxel_pieces", "grid_atomics"):
+        assert a[k] == b[k], k
+    np.testing.assert_allclose(a["fluence_raw"], b["fluence_raw"], rtol=1e-9, atol=1e-12 * b["fluence_raw"].max())
+    assert a["fluence_raw"].sum() > 0
+    ga = S.run_batch([desc, flat], [41, 42], [20000, 20000], engine=e_b, precision="f32")
+    gb = S.run_batch([desc, flat], [41, 42], [20000, 20000], engine=e_d, precision="f32")
+    for x, y in zip(ga, gb):
+        np.testing.assert_allclose(x["fluence_raw"], y["fluence_raw"], rtol=1e-9, atol=1e-12 * y["fluence_raw"].max())
+    e_b.close()
+    e_d.close()
 
 
 def test_full_size_slab_bench_config(S, orc, W):
