@@ -41,7 +41,9 @@ namespace smcrt {
 template <typename T, bool TRACE, bool XF>
 __device__ void surface(JobRef a, Packet<T>& pk, Lane& ln, LdsTallies& L) {
   ScP sc = kptr(a.sc);
-  const V3<double> p = to_d(pk.p), u = to_d(pk.u);
+  V3<double> p = to_d(pk.p);
+  if constexpr (sizeof(T) == 4) p = p + to_d(pk.pe);   // the position's compensated sum
+  const V3<double> u = to_d(pk.u);
   const int nr = sc->n_regions;
   int j = 0;
   double dj = region_dist<double, XF>(a, 0, p);
@@ -107,6 +109,7 @@ __device__ void surface(JobRef a, Packet<T>& pk, Lane& ln, LdsTallies& L) {
   const double n1 = R1.n, n2 = sc->reg[r2].n;
   if (n1 == n2) {  // index matched: cross undeflected
     pk.p = from_d<T>(q);
+    pk.pe = mk(T(0), T(0), T(0));
     set_region(sc, pk, r2);
     atomicAdd(&L.cnt[kCCrossings], 1ull);
     record<T, TRACE>(a, pk, ln, SMCRT_EV_CROSS);
@@ -121,6 +124,7 @@ __device__ void surface(JobRef a, Packet<T>& pk, Lane& ln, LdsTallies& L) {
   if (x0 < R) {  // specular reflection, back on the incident side
     v = u - (2.0 * c) * nrm;
     pk.p = from_d<T>(ps - (sg * off) * nrm);
+    pk.pe = mk(T(0), T(0), T(0));
     v = (1.0 / __builtin_sqrt(dot(v, v))) * v;
     pk.u = from_d<T>(v);
     atomicAdd(&L.cnt[kCReflections], 1ull);
@@ -130,6 +134,7 @@ __device__ void surface(JobRef a, Packet<T>& pk, Lane& ln, LdsTallies& L) {
     v = (1.0 / __builtin_sqrt(dot(v, v))) * v;
     pk.u = from_d<T>(v);
     pk.p = from_d<T>(q);
+    pk.pe = mk(T(0), T(0), T(0));
     set_region(sc, pk, r2);
     atomicAdd(&L.cnt[kCRefractions], 1ull);
     record<T, TRACE>(a, pk, ln, SMCRT_EV_REFRACT);

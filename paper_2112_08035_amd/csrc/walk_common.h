@@ -764,6 +764,9 @@ enum State : int { kTransport = 0, kSurface = 1, kInteract = 2 };
 template <typename T>
 struct Packet {
   V3<T> p, u;
+  // FP32 only: the part of the position that rounding left out of p
+  // (compensated summation of the moves; zero after a jump of position)
+  V3<T> pe;
   // remaining optical depth, FP64 in both transport precisions: it is used
   // up over many sphere-tracing steps, and along a grazing path (thousands
   // of steps of delta size) FP32 rounding would let it drift
@@ -821,32 +824,34 @@ __device__ __forceinline__ void record(JobRef a, const Packet<T>& pk, Lane& ln, 
 // changes or the position jumps (interactions, interface events) and when
 // the packet ends.  Collinear sphere-tracing steps thus share one DDA, and
 // the lanes of a wave run it together.
+//
+// In FP32 the position is a compensated sum (Fast2Sum per axis): pe keeps
+// what rounding dropped from p and is added back on the next move.  A
+// sphere-tracing step that runs nearly parallel to a face a few surface
+// thresholds away moves p across that face by far less than p's ulp; a
+// plain sum would drop every one of those moves, the packet would slide
+// along the face at a fixed depth in steps of that depth, and a walk of
+// 0.5 cm would take some 4e4 steps where the FP64 walk takes 2e3.
 template <typename T>
 __device__ __forceinline__ void advance(Packet<T>& pk, T len) {
-  pk.p = pk.p + len * pk.u;
+  if constexpr (sizeof(T) == 4) {
+    const V3<T> d = len * pk.u + pk.pe;
+    const V3<T> q = pk.p + d;
+    pk.pe = d - (q - pk.p);
+    pk.p = q;
+  } else {
+    pk.p = pk.p + len * pk.u;
+  }
   pk.pend += len;
 }
 
 // Sphere-tracing move of len along u (negative: back along u), charged to
-// the pending path and the optical depth.  In FP32 the charge is the
-// distance the rounded position really moved along u: for steps far below
-// the position's ulp-scaled size (grazing paths far from the origin) it
-// differs from len, and charging len would let depth and position drift
-// apart.  Returns the charged distance.
+// the pending path and the optical depth.  Returns the charged distance.
 template <typename T>
 __device__ __forceinline__ T step_along(Packet<T>& pk, T len) {
-  if constexpr (sizeof(T) == 4) {
-    const V3<T> p0 = pk.p;
-    pk.p = pk.p + len * pk.u;
-    const T moved = dot(pk.p - p0, pk.u);
-    pk.pend += moved;
-    pk.tau -= (double)pk.mut * (double)moved;
-    return moved;
-  } else {
-    advance(pk, len);
-    pk.tau -= (double)pk.mut * (double)len;
-    return len;
-  }
+  advance(pk, len);
+  pk.tau -= (double)pk.mut * (double)len;
+  return len;
 }
 
 template <typename T>
@@ -930,6 +935,7 @@ __device__ void emit(JobRef a, Packet<T>& pk, Lane& ln, LdsTallies& L) {
   }
   const T il = T(1) / tsqrt(dot(u, u));
   pk.p = p;
+  pk.pe = mk(T(0), T(0), T(0));
   pk.u = il * u;
   pk.w = 1.0;
   pk.tau = (double)(-tlog(x3));
