@@ -49,7 +49,7 @@ class Scene(C.Structure):
                 ("max_events", C.c_int64),
                 ("det_face", C.c_int32), ("det_dims", C.c_int32 * 2),
                 ("det_lo", C.c_double * 2), ("det_hi", C.c_double * 2),
-                ("relax", C.c_double), ("no_reuse", C.c_int32), ("no_skip", C.c_int32)]
+                ("relax", C.c_double), ("reuse", C.c_int32), ("skip", C.c_int32)]
 
 
 class Tallies(C.Structure):
@@ -355,8 +355,10 @@ class CScene:
         s.max_steps = int(scene["max_steps"])
         s.max_events = int(scene["max_events"])
         s.relax = float(scene.get("relax", 1.0))
-        s.no_reuse = 0 if scene.get("reuse", True) else 1
-        s.no_skip = 0 if scene.get("ambient_skip", True) else 1
+        # the plain Sec. 2.3 march unless the scene asks for the kernels'
+        # shortcuts (used by tests that compare SDF evaluation counts)
+        s.reuse = 1 if scene.get("reuse", False) else 0
+        s.skip = 1 if scene.get("ambient_skip", False) else 0
         det = scene.get("detector")
         if det:
             s.det_face = int(det["face"])

@@ -6,11 +6,15 @@
  * no merging of path segments, brute-force evaluation of every SDF at every
  * step (Sec. 2.3), a tally that finds voxel pieces by intersecting the
  * segment with every voxel plane it spans, and OpenMP over packets with
- * per-thread accumulators reduced in thread order.  Two shortcuts that give
- * the plain march's walk, each with a switch that turns it off so the pins
- * can compare the two: free-flight reuse (orc_scene.no_reuse) and the
- * ambient skip (orc_scene.no_skip); with them on, the oracle counts the
- * SDF evaluations the kernels make.
+ * per-thread accumulators reduced in thread order.
+ *
+ * walk_plain is the walk: the step loop of Sec. 2.3 and nothing else.  A
+ * second walk, walk_mirror, takes the same steps through the shortcuts the
+ * kernels take -- free-flight reuse, the ambient skip and over-relaxed
+ * steps (Sec. 5) -- and runs only when a scene asks for one of them
+ * (orc_scene.reuse, .skip, .relax > 1): pins compare its events and tallies
+ * with walk_plain's, and tests that count SDF evaluations use its step
+ * counts.  Every other comparison is against walk_plain.
  *
  * Where the paper is silent the code follows the readings listed in the
  * repository's design notes; each such place says "reading:".
@@ -749,7 +753,83 @@ static double ambient_skip(const orc_scene* s, const double p[3], const double u
   return tf > len && 0.5 * s->delta >= 0x1p-50 * (pmax + tf) ? tf : 0.0;
 }
 
-static void walk(walker* wk, uint64_t seed, uint64_t pid) {
+/* escape (Sec. 2.3: the bounding-box SDF is positive): the weight leaves
+ * through the face of the box's largest component of |p - c| - h
+ * (reading: escape bookkeeping per face) */
+static void leave(walker* wk, packet* pk) {
+  const orc_scene* s = wk->s;
+  double best = -ORC_INF;
+  int face = 0;
+  for (int i = 0; i < 3; ++i) {
+    double c = 0.5 * (s->bb_lo[i] + s->bb_hi[i]), hw = 0.5 * (s->bb_hi[i] - s->bb_lo[i]);
+    double e = fabs(pk->p[i] - c) - hw;
+    if (e > best) { best = e; face = 2 * i + (pk->p[i] > c ? 1 : 0); }
+  }
+  wk->t->escaped_face[face] += pk->w;
+  wk->t->escapes++;
+  detect(wk, pk, face, (face % 2) ? s->bb_hi[face / 2] : s->bb_lo[face / 2]);
+  record(wk, pk, ORC_EV_ESCAPE);
+}
+
+/* reading: a packet past the safety caps (grazing stalls, Sec. 5) ends,
+ * its weight kept in the stalled ledger */
+static void stall(walker* wk, packet* pk) {
+  wk->t->stalled += pk->w;
+  wk->t->stalls++;
+  record(wk, pk, ORC_EV_STALL);
+}
+
+/* The walk of one packet, Sec. 2.3.  Emit (event 0), then repeat: sphere
+ * trace -- evaluate every region's SDF at p, d = min |d_r| -- and, in this
+ * order (reading: the order of the checks), escape when the bounding box's
+ * SDF is positive; move the remaining free path s = tau/mu_t and interact
+ * when s <= d; handle the surface when d < delta; else move d along u,
+ * spending mu_t d of optical depth.  Every move is tallied. */
+static void walk_plain(walker* wk, uint64_t seed, uint64_t pid) {
+  const orc_scene* s = wk->s;
+  packet pk;
+  emit(wk, &pk, seed, pid);
+  for (;;) {
+    int32_t steps = 0; /* sphere-tracing steps in this event */
+    int state = GO_ON;
+    while (state == GO_ON) {
+      if (++steps > s->max_steps || (int64_t)pk.k > s->max_events) {
+        stall(wk, &pk);
+        return;
+      }
+      wk->t->steps++;
+      double d = ORC_INF;
+      for (int r = 0; r < s->n_regions; ++r) d = mind(d, fabs(orc_region_sdf(s, r, pk.p)));
+      if (orc_box_sdf(s->bb_lo, s->bb_hi, pk.p) > 0.0) {
+        leave(wk, &pk);
+        return;
+      }
+      const double mut = reg_mua(s, pk.region) + reg_mus(s, pk.region);
+      const double s_rem = mut > 0.0 ? pk.tau / mut : ORC_INF; /* reading: tau compared as a length */
+      if (s_rem <= d) {
+        move(wk, &pk, s_rem);
+        pk.tau = 0.0;
+        state = DO_INTERACT;
+      } else if (d < s->delta) {
+        const uint32_t k_before = pk.k;
+        state = surface(wk, &pk, s_rem, seed, pid);
+        if (pk.k != k_before) steps = 0; /* an interface event starts a new event */
+      } else {
+        move(wk, &pk, d);
+        pk.tau -= mut * d;
+      }
+    }
+    if (!interact(wk, &pk, seed, pid)) return;
+  }
+}
+
+/* The same walk through the kernels' shortcuts, for step counts.  None of
+ * them changes an event: an interaction inside the free ball of the last
+ * evaluation is the one a new evaluation would give (free-flight reuse);
+ * outside every region no surface lies before the first region box the ray
+ * enters (ambient skip); an over-relaxed step is kept only when the free
+ * balls at its ends cover it (Sec. 5), else replaced by the plain step. */
+static void walk_mirror(walker* wk, uint64_t seed, uint64_t pid) {
   const orc_scene* s = wk->s;
   packet pk;
   emit(wk, &pk, seed, pid);
@@ -768,7 +848,7 @@ static void walk(walker* wk, uint64_t seed, uint64_t pid) {
     double q[3] = {0.0, 0.0, 0.0}, pd = -1.0, pl = 0.0, tau_q = 0.0;
     int pending = 0;
     while (state == GO_ON) {
-      if (!s->no_reuse && safe > 0.0 && pk.region >= 0 && links < ORC_REUSE_LINKS) {
+      if (s->reuse && safe > 0.0 && pk.region >= 0 && links < ORC_REUSE_LINKS) {
         /* the last evaluated distance, less the path since, bounds the
          * distance to every surface: an interaction inside that ball is the
          * one a new evaluation would give, so none is made.  Inside a region
@@ -790,9 +870,7 @@ static void walk(walker* wk, uint64_t seed, uint64_t pid) {
       safe = -1.0;
       if (++steps > s->max_steps || (int64_t)pk.k > s->max_events) {
         if (pending) wk->t->voxel_segments += (uint64_t)orc_tally_segment(s, q, pk.p, pk.w, wk->f);
-        wk->t->stalled += pk.w;
-        wk->t->stalls++;
-        record(wk, &pk, ORC_EV_STALL);
+        stall(wk, &pk);
         return;
       }
       wk->t->steps++;
@@ -816,23 +894,13 @@ static void walk(walker* wk, uint64_t seed, uint64_t pid) {
         if (!keep) continue; /* the next step starts from the plain step's end */
       }
       if (orc_box_sdf(s->bb_lo, s->bb_hi, pk.p) > 0.0) { /* left the volume */
-        double e[3], best = -ORC_INF;
-        int face = 0;
-        for (int i = 0; i < 3; ++i) {
-          double c = 0.5 * (s->bb_lo[i] + s->bb_hi[i]), hw = 0.5 * (s->bb_hi[i] - s->bb_lo[i]);
-          e[i] = fabs(pk.p[i] - c) - hw;
-          if (e[i] > best) { best = e[i]; face = 2 * i + (pk.p[i] > c ? 1 : 0); }
-        }
-        wk->t->escaped_face[face] += pk.w;
-        wk->t->escapes++;
-        detect(wk, &pk, face, (face % 2) ? s->bb_hi[face / 2] : s->bb_lo[face / 2]);
-        record(wk, &pk, ORC_EV_ESCAPE);
+        leave(wk, &pk);
         return;
       }
       double mut = reg_mua(s, pk.region) + reg_mus(s, pk.region);
       double s_rem = mut > 0.0 ? pk.tau / mut : ORC_INF;
       double skip = 0.0;
-      if (!s->no_skip && pk.region < 0 && dmin >= s->delta) skip = ambient_skip(s, pk.p, pk.u, dmin, pd, pl, s_rem);
+      if (s->skip && pk.region < 0 && dmin >= s->delta) skip = ambient_skip(s, pk.p, pk.u, dmin, pd, pl, s_rem);
       if (s_rem <= dmin) { /* the optical depth runs out first */
         move(wk, &pk, s_rem);
         pk.tau = 0.0;
@@ -877,6 +945,13 @@ static void walk(walker* wk, uint64_t seed, uint64_t pid) {
     }
     if (!interact(wk, &pk, seed, pid)) return;
   }
+}
+
+/* the plain walk unless the scene asks for the shortcuts */
+static void walk(walker* wk, uint64_t seed, uint64_t pid) {
+  const orc_scene* s = wk->s;
+  if (s->reuse || s->skip || s->relax > 1.0) walk_mirror(wk, seed, pid);
+  else walk_plain(wk, seed, pid);
 }
 
 /* --------------------------------------------------------------- runs --- */

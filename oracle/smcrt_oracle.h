@@ -104,10 +104,15 @@ typedef struct {
   /* over-relaxation factor of sphere-tracing steps in [1, 2); 1 = plain
    * steps of the nearest-surface distance */
   double relax;
-  /* 1: evaluate the SDFs before every interaction (no free-flight reuse) */
-  int32_t no_reuse;
-  /* 1: sphere-trace the ambient medium step by step (no ambient skip) */
-  int32_t no_skip;
+  /* The plain march (reuse = skip = 0, relax = 1) is the default walk.  The
+   * switches below select the step-count mirror of the kernels' shortcuts,
+   * used only where a pin or a test compares numbers of SDF evaluations:
+   * 1: free-flight reuse (no new evaluation for an interaction inside the
+   * last evaluated free ball) */
+  int32_t reuse;
+  /* 1: ambient skip (outside every region, move to the first region box
+   * the ray enters in one move) */
+  int32_t skip;
 } orc_scene;
 
 /* free-flight reuse: at most this many interactions per evaluation */

@@ -925,14 +925,20 @@ static smcrt_status check_opts(const smcrt_opts* o) {
 // SDF walks on cubic voxels, up to 2^27 voxels.  Measured: on cubes the
 // shared segments save more atomic requests than the brick index costs; on
 // the flat voxels of the layered slab they do not.
-static bool brick_tally(const smcrt_engine* e, const SceneHeader* h) {
-  if (e->opts.tally_layout != 0 || e->opts.precision != SMCRT_PREC_F32 || h->geometry != kGeomSdf || !h->has_grid)
+static bool brick_tally(const smcrt_opts& o, const SceneHeader* h) {
+  if (o.tally_layout != 0 || o.precision != SMCRT_PREC_F32 || h->geometry != kGeomSdf || !h->has_grid)
     return false;
   const double n = (double)h->g_dims[0] * h->g_dims[1] * h->g_dims[2];
   if (n > (double)(1 << 27)) return false;
   for (int i = 1; i < 3; ++i)
     if (std::fabs(h->g_d[i] - h->g_d[0]) > 1e-9 * h->g_d[0]) return false;
   return true;
+}
+
+// voxels of the 2x2x2-brick grid of a scene's fluence grid (partial bricks
+// at the far faces are whole)
+static size_t brick_voxels(const SceneHeader* h) {
+  return 8ull * (size_t)((h->g_dims[0] + 1) / 2) * (size_t)((h->g_dims[1] + 1) / 2) * (size_t)((h->g_dims[2] + 1) / 2);
 }
 
 extern "C" smcrt_status smcrt_engine_create(smcrt_engine** out, int device) {
@@ -1062,8 +1068,8 @@ static smcrt_status launch_jobs(smcrt_engine* e, const std::vector<JobSpec>& job
   std::vector<size_t> brick_off(jobs.size(), 0), brick_n(jobs.size(), 0);
   for (size_t j = 0; j < jobs.size(); ++j) {
     const SceneHeader* h = reinterpret_cast<const SceneHeader*>(uniq[job_scene[j]]->blob.data());
-    if (tr || vox_out || !jobs[j].fluence || !brick_tally(e, h)) continue;
-    brick_n[j] = 8ull * (size_t)((h->g_dims[0] + 1) / 2) * (size_t)((h->g_dims[1] + 1) / 2) * (size_t)((h->g_dims[2] + 1) / 2);
+    if (tr || vox_out || !jobs[j].fluence || !brick_tally(e->opts, h)) continue;
+    brick_n[j] = brick_voxels(h);
     brick_off[j] = off;
     off = align256(off + sizeof(double) * brick_n[j]);
   }
@@ -1453,6 +1459,7 @@ struct Request {
 
 struct smcrt_server {
   smcrt_engine* engine = nullptr;  // NULL: dry run (scheduling only)
+  smcrt_opts opts;                 // launch options (the engine's, also in a dry run)
   uint64_t budget = 0, used = 0, epoch_packets = 0, min_chunk = 0;
   std::mutex mu;
   std::condition_variable cv_work, cv_done;
@@ -1472,12 +1479,15 @@ static double server_now(const smcrt_server* sv) {
   return std::chrono::duration<double>(std::chrono::steady_clock::now() - sv->t0).count();
 }
 
-// device bytes a request holds while admitted: its outputs, its scene tables
-// and the grid buffers of its accelerated region
-static uint64_t request_footprint(const smcrt_scene* s) {
+// device bytes a request holds while admitted: its outputs, its scene
+// tables, the grid buffers of its accelerated region, and the brick grid its
+// walk tallies into when the server's options give it one (as large as the
+// output grid, rounded up to whole bricks)
+static uint64_t request_footprint(const smcrt_scene* s, const smcrt_opts& o) {
   const SceneHeader* h = reinterpret_cast<const SceneHeader*>(s->blob.data());
   uint64_t b = s->blob.size() + sizeof(WalkArgs) + sizeof(smcrt_tallies) + 8 * kMaxRegions + 256;
   if (h->has_grid) b += 8ull * h->g_dims[0] * h->g_dims[1] * h->g_dims[2];
+  if (brick_tally(o, h)) b += 8ull * brick_voxels(h);
   if (h->acc.region >= 0) b += 12ull * ((uint64_t)h->acc.n_cells + 1) + 4ull * h->acc.capacity;
   if (h->geometry == kGeomVoxel) b += (uint64_t)h->g_dims[0] * h->g_dims[1] * h->g_dims[2];
   return b;
@@ -1579,13 +1589,15 @@ extern "C" smcrt_status smcrt_server_create(smcrt_server** out, int device, uint
   sv->epoch_packets = epoch_packets ? epoch_packets : 2000000;
   sv->min_chunk = std::max<uint64_t>(1, std::min<uint64_t>(10000, sv->epoch_packets));
   sv->t0 = std::chrono::steady_clock::now();
+  default_opts(&sv->opts);
+  if (opts) sv->opts = *opts;
   if (device >= 0) {
     smcrt_status st = smcrt_engine_create(&sv->engine, device);
     if (st != SMCRT_OK) {
       delete sv;
       return st;
     }
-    if (opts) sv->engine->opts = *opts;
+    sv->engine->opts = sv->opts;
     hipError_t e = hipStreamCreateWithFlags(&sv->stream, hipStreamNonBlocking);
     if (e != hipSuccess) {
       smcrt_engine_destroy(sv->engine);
@@ -1630,7 +1642,7 @@ extern "C" smcrt_status smcrt_submit(smcrt_server* sv, const smcrt_scene* scene,
     if (st != SMCRT_OK) return st;
     if (sv->engine && (!d_absorbed || !d_tallies))
       return fail(SMCRT_E_INVALID, "submit: output buffers missing");
-    fp = request_footprint(s);
+    fp = request_footprint(s, sv->opts);
     if (fp > sv->budget)
       return fail(SMCRT_E_BUDGET, "submit: request needs %llu bytes, budget is %llu", (unsigned long long)fp,
                   (unsigned long long)sv->budget);

@@ -123,7 +123,7 @@ __device__ bool enter_grid(JobRef a, Packet<T>& pk, int v[3], Lane& ln, LdsTalli
       escape_face<T, TRACE>(a, pk, ln, L, face, false);
       return false;
     }
-    pk.p = p + t0 * u;
+    shift(pk, t0);
     set_region(sc, pk, nr);  // in the ambient medium, on the grid face
   }
   // voxel holding the point; on a voxel face, the one the packet moves into
@@ -175,7 +175,8 @@ __device__ bool voxel_step(JobRef a, Packet<T>& pk, int v[3], Lane& ln, LdsTalli
     const T ui = comp(pk.u, i);
     if (ui == T(0)) continue;
     const T face = Tab<T>::g_lo(sc, i) + T(v[i] + (ui > T(0) ? 1 : 0)) * Tab<T>::g_d(sc, i);
-    const T t = tmax((face - comp(pk.p, i)) / ui, T(0));
+    // from the compensated position (FP32: p + pe)
+    const T t = tmax(((face - comp(pk.p, i)) - comp(pk.pe, i)) / ui, T(0));
     if (t < texit) {
       texit = t;
       ax = i;
@@ -185,13 +186,13 @@ __device__ bool voxel_step(JobRef a, Packet<T>& pk, int v[3], Lane& ln, LdsTalli
   const T s = pk.mut > T(0) ? (T)(pk.tau * (double)pk.inv_mut) : tinf<T>();
   if (s <= texit) {  // interaction inside this voxel
     if (a.fluence != nullptr && s > T(0)) run_add(a.fluence, ln, idx, pk.w * (double)s);
-    pk.p = pk.p + s * pk.u;
+    shift(pk, s);
     pk.tau = 0.0;
     pk.state = kInteract;
     return true;
   }
   if (a.fluence != nullptr && texit > T(0)) run_add(a.fluence, ln, idx, pk.w * (double)texit);
-  pk.p = pk.p + texit * pk.u;
+  shift(pk, texit);
   pk.tau -= (double)pk.mut * (double)texit;
   const T ua = comp(pk.u, ax);
   int w2[3] = {v[0], v[1], v[2]};

@@ -108,8 +108,7 @@ __device__ void surface(JobRef a, Packet<T>& pk, Lane& ln, LdsTallies& L) {
   pk.state = kTransport;
   const double n1 = R1.n, n2 = sc->reg[r2].n;
   if (n1 == n2) {  // index matched: cross undeflected
-    pk.p = from_d<T>(q);
-    pk.pe = mk(T(0), T(0), T(0));
+    set_position(pk, q);
     set_region(sc, pk, r2);
     atomicAdd(&L.cnt[kCCrossings], 1ull);
     record<T, TRACE>(a, pk, ln, SMCRT_EV_CROSS);
@@ -123,8 +122,7 @@ __device__ void surface(JobRef a, Packet<T>& pk, Lane& ln, LdsTallies& L) {
   V3<double> v;
   if (x0 < R) {  // specular reflection, back on the incident side
     v = u - (2.0 * c) * nrm;
-    pk.p = from_d<T>(ps - (sg * off) * nrm);
-    pk.pe = mk(T(0), T(0), T(0));
+    set_position(pk, ps - (sg * off) * nrm);
     v = (1.0 / __builtin_sqrt(dot(v, v))) * v;
     pk.u = from_d<T>(v);
     atomicAdd(&L.cnt[kCReflections], 1ull);
@@ -133,8 +131,7 @@ __device__ void surface(JobRef a, Packet<T>& pk, Lane& ln, LdsTallies& L) {
     v = eta * u + ((ctr - eta * ci) * sg) * nrm;
     v = (1.0 / __builtin_sqrt(dot(v, v))) * v;
     pk.u = from_d<T>(v);
-    pk.p = from_d<T>(q);
-    pk.pe = mk(T(0), T(0), T(0));
+    set_position(pk, q);
     set_region(sc, pk, r2);
     atomicAdd(&L.cnt[kCRefractions], 1ull);
     record<T, TRACE>(a, pk, ln, SMCRT_EV_REFRACT);

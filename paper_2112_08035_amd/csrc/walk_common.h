@@ -808,7 +808,10 @@ __device__ __forceinline__ void record(JobRef a, const Packet<T>& pk, Lane& ln, 
       e.type = (uint32_t)type;
       e.region = pk.region == a.sc->n_regions ? -1 : pk.region;
       e.pad = 0;
-      e.p[0] = pk.p.x; e.p[1] = pk.p.y; e.p[2] = pk.p.z;
+      // FP32: the position with its compensation, as the walk carries it
+      e.p[0] = (double)pk.p.x + (double)pk.pe.x;
+      e.p[1] = (double)pk.p.y + (double)pk.pe.y;
+      e.p[2] = (double)pk.p.z + (double)pk.pe.z;
       e.u[0] = pk.u.x; e.u[1] = pk.u.y; e.u[2] = pk.u.z;
       e.w = pk.w;
       e.tau = pk.tau;
@@ -825,23 +828,53 @@ __device__ __forceinline__ void record(JobRef a, const Packet<T>& pk, Lane& ln, 
 // the packet ends.  Collinear sphere-tracing steps thus share one DDA, and
 // the lanes of a wave run it together.
 //
-// In FP32 the position is a compensated sum (Fast2Sum per axis): pe keeps
-// what rounding dropped from p and is added back on the next move.  A
+// In FP32 the position is a compensated sum (2Sum per axis, exact for any
+// magnitudes, also where a move is longer than the coordinate near the
+// coordinate planes): pe keeps what rounding dropped from p and is added
+// back on the next move.  A
 // sphere-tracing step that runs nearly parallel to a face a few surface
 // thresholds away moves p across that face by far less than p's ulp; a
 // plain sum would drop every one of those moves, the packet would slide
 // along the face at a fixed depth in steps of that depth, and a walk of
 // 0.5 cm would take some 4e4 steps where the FP64 walk takes 2e3.
+// s = fl(a + b) and *e = a + b - s exactly (Knuth's 2Sum; six additions,
+// no condition on |a| and |b|)
 template <typename T>
-__device__ __forceinline__ void advance(Packet<T>& pk, T len) {
+__device__ __forceinline__ T two_sum(T a, T b, T* e) {
+  const T s = a + b;
+  const T bb = s - a;
+  *e = (a - (s - bb)) + (b - bb);
+  return s;
+}
+
+// The packet is put at the FP64 point q: in FP32 as the float nearest q
+// plus the float nearest the rest, so a re-placement at an interface keeps
+// q to about 2^-48 of its size, as the compensated moves do.
+template <typename T>
+__device__ __forceinline__ void set_position(Packet<T>& pk, V3<double> q) {
+  pk.p = from_d<T>(q);
+  if constexpr (sizeof(T) == 4) pk.pe = from_d<T>(q - to_d(pk.p));
+  else pk.pe = mk(T(0), T(0), T(0));
+}
+
+// The move itself: p (+ pe) += len u, compensated in FP32.
+template <typename T>
+__device__ __forceinline__ void shift(Packet<T>& pk, T len) {
   if constexpr (sizeof(T) == 4) {
     const V3<T> d = len * pk.u + pk.pe;
-    const V3<T> q = pk.p + d;
-    pk.pe = d - (q - pk.p);
-    pk.p = q;
+    V3<T> e;
+    pk.p.x = two_sum(pk.p.x, d.x, &e.x);
+    pk.p.y = two_sum(pk.p.y, d.y, &e.y);
+    pk.p.z = two_sum(pk.p.z, d.z, &e.z);
+    pk.pe = e;
   } else {
     pk.p = pk.p + len * pk.u;
   }
+}
+
+template <typename T>
+__device__ __forceinline__ void advance(Packet<T>& pk, T len) {
+  shift(pk, len);
   pk.pend += len;
 }
 
@@ -912,7 +945,8 @@ __device__ void emit(JobRef a, Packet<T>& pk, Lane& ln, LdsTallies& L) {
   const U4 r = philox10(0u, (uint32_t)pk.pid, (uint32_t)(pk.pid >> 32), 0u, (uint32_t)a.seed, (uint32_t)(a.seed >> 32));
   const T x0 = xi_of<T>(r.w0), x1 = xi_of<T>(r.w1), x3 = xi_of<T>(r.w3);
   const SMCRT_K double* s = sc->src;
-  V3<T> p = mk((T)s[0], (T)s[1], (T)s[2]);
+  // the emission point in FP64 (the source's place plus the sampled offset)
+  V3<double> p = mk(s[0], s[1], s[2]);
   V3<T> u;
   const int kind = sc->src_kind;
   if (kind == kPoint) {
@@ -927,15 +961,14 @@ __device__ void emit(JobRef a, Packet<T>& pk, Lane& ln, LdsTallies& L) {
     const T rr = (T)s[3] * tsqrt(x0);
     T sp, cp;
     tsincos_2pi(x1, &sp, &cp);
-    p = mk(p.x + rr * cp, p.y + rr * sp, p.z);
+    p = mk(p.x + (double)(rr * cp), p.y + (double)(rr * sp), p.z);
     u = mk((T)s[4], (T)s[5], (T)s[6]);
   } else {
-    p = mk(p.x + (T)s[3] * (T(2) * x0 - T(1)), p.y + (T)s[4] * (T(2) * x1 - T(1)), p.z);
+    p = mk(p.x + s[3] * (2.0 * (double)x0 - 1.0), p.y + s[4] * (2.0 * (double)x1 - 1.0), p.z);
     u = mk((T)s[5], (T)s[6], (T)s[7]);
   }
   const T il = T(1) / tsqrt(dot(u, u));
-  pk.p = p;
-  pk.pe = mk(T(0), T(0), T(0));
+  set_position(pk, p);
   pk.u = il * u;
   pk.w = 1.0;
   pk.tau = (double)(-tlog(x3));
@@ -947,7 +980,7 @@ __device__ void emit(JobRef a, Packet<T>& pk, Lane& ln, LdsTallies& L) {
   pk.links = 0;
   pk.pend = T(0);
   pk.state = kTransport;
-  set_region(sc, pk, region_of<T, XF>(a, p));
+  set_region(sc, pk, region_of<T, XF>(a, pk.p));
   atomicAdd(&L.cnt[kCLaunched], 1ull);
   record<T, TRACE>(a, pk, ln, SMCRT_EV_EMIT);
 }

@@ -520,6 +520,8 @@ class Outputs:
         self.fluence.zero_()
         self.absorbed.zero_()
         self.tallies.zero_()
+        if self.detector is not None:
+            self.detector.zero_()
         return self
 
     def struct(self):

@@ -2,13 +2,14 @@
 intersection and difference regions, and two scenes shaped like the
 paper's curved-geometry examples (a glass sphere under a beam in a
 scattering medium; a partly filled glass bottle).  Same tolerances as the
-SDF walk's parity tests."""
+SDF walk's parity tests (the bottle, a chaotic billiard of total internal
+reflections, with the FP32 allowance of gpu_helpers.absorbed_agrees)."""
 import math
 
 import numpy as np
 import pytest
 
-from gpu_helpers import check_fluence, compare_traces, extent_of, identity_residual, oracle_batches
+from gpu_helpers import absorbed_agrees, check_fluence, compare_traces, extent_of, identity_residual, oracle_batches
 
 pytestmark = pytest.mark.gpu
 
@@ -61,11 +62,9 @@ def test_csg_run_parity(S, eng, orc, W, name, prec, abs_tol):
     diff = abs(g["absorbed"].sum() - o["absorbed"].sum())
     rel = diff / o["absorbed"].sum()
     print(f"{name} {prec}: absorbed relative difference {rel:.3e}")
+    assert absorbed_agrees(g["absorbed"].sum(), o["absorbed"].sum(), n, prec, name), (rel, diff)
     if prec == "f64":
-        assert rel <= abs_tol
         assert g["interfaces"] == o["interfaces"]
-    else:
-        assert rel <= abs_tol or diff <= 1.0   # at most one packet's weight
     check_fluence(g, o, se, desc, prec)
 
 

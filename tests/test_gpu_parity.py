@@ -11,16 +11,20 @@ Tolerances:
   turns a reflected direction by 2e, and chords re-hit the surface).
 - FP32 transport: event records to 1e-5 relative for the first 50 events,
   total absorbed weight to 1e-4 relative, fluence per voxel within 3 Monte
-  Carlo standard errors.  FP32 positions carry ~1e-7 relative rounding per
-  step, so 50 events stay well inside 1e-5 unless a threshold decision
-  flips; the agreeing fraction is required to be at least 97% of packets.
+  Carlo standard errors.  FP32 positions are compensated sums (also across
+  interface re-placements), so what remains is the FP32 rounding of
+  directions and step lengths, which curved surfaces amplify by
+  (position)/(radius of curvature) at each hit: on 1024 packets at least
+  99 % agree to 1e-5 on every scene, the 5-50 um vessels included, and at
+  most one packet in 1024 takes another decision (diverged fraction).
 """
 import math
 
 import numpy as np
 import pytest
 
-from gpu_helpers import batch_se, check_fluence, compare_traces, extent_of, identity_residual, oracle_batches
+from gpu_helpers import (batch_se, check_fluence, compare_traces, diverged_fraction, extent_of, identity_residual,
+                         independent_fluence_check, oracle_batches)
 
 pytestmark = pytest.mark.gpu
 
@@ -38,22 +42,20 @@ def _scene(W, name):
     return W.WORKLOADS[name](n_grid=16)
 
 
-@pytest.mark.parametrize("prec,need", [("f64", 0.99), ("f32", 0.97)])
+@pytest.mark.parametrize("prec,need", [("f64", 0.99), ("f32", 0.99)])
 @pytest.mark.parametrize("name", TRACE_SCENES)
 def test_event_traces_match_oracle(S, eng, orc, W, name, prec, need):
     desc = _scene(W, name)
-    # FP32 positions near a surface of curvature radius R turn a rounding of
-    # 2^-24 |p| into a normal error of 2^-24 |p| / R, doubled by reflection:
-    # ~5e-5 for the 5-50 um vessels at |p| ~ 0.2 cm, so that scene is held
-    # to 1e-4; cm-scale scenes (|p|/R <= 20) to 1e-5.
-    tol = 1e-6 if prec == "f64" else (1e-4 if name == "vessels" else 1e-5)
-    n, seed = 256, 20211215
+    tol = 1e-6 if prec == "f64" else 1e-5
+    n, seed = 1024, 20211215
     g = S.trace(desc, seed, list(range(n)), 50, engine=eng, precision=prec)
     o = [orc.trace(desc, seed, pid, 50) for pid in range(n)]
     mut = [rg["mua"] + rg["mus"] for rg in desc["regions"]]
     frac, worst, bad = compare_traces(o, g, extent_of(S, desc), tol, mut=mut)
-    print(f"{name} {prec}: agree {frac:.4f} worst {worst} first disagreements {bad[:5]}")
+    div = diverged_fraction(o, g)
+    print(f"{name} {prec}: agree {frac:.4f} diverged {div:.5f} worst {worst} first disagreements {bad[:5]}")
     assert frac >= need, (frac, worst, bad[:10])
+    assert div <= 1.0 / n, div
 
 
 # ------------------------------------------------------------ full runs --
@@ -374,37 +376,58 @@ def test_brick_tally_equals_direct(S, W, dims):
 def test_full_size_slab_bench_config(S, orc, W):
     """Layered slab at its full size (1e7 packets, 200^3 grid) in the default
     launch configuration: energy identity exactly, and the fluence against
-    an oracle run on 2e4 packets voxel-block by voxel-block (8^3 blocks) in
-    combined standard errors."""
+    an independent oracle run on 8e4 packets, voxel-block by voxel-block (8^3
+    blocks): the oracle's SE per block from 40 batches (nu = 39), with the
+    GPU's own variance added at the same per-packet rate (8e4/1e7 of it), at
+    least 98.5 % of the blocks every batch reached within 3 SE (t_39 puts
+    0.5 % beyond) and the chi-square per degree of freedom, corrected by
+    (nu - 2)/nu, in [0.9, 1.1]."""
     import torch
     desc = W.slab_scene()
     e = S.Engine(0)
     g = S.run(desc, 2021, 10_000_000, engine=e, precision="f32")
     assert g["launched"] == 1e7
     assert abs(identity_residual(g)) <= 1e-9 * 1e7
-    n_o = 20000
-    outs = [orc.run(desc, 5, n_o // 10, first=b * (n_o // 10)) for b in range(10)]
+    n_o, n_g, B = 80000, 10_000_000, 40
+    outs = [orc.run(desc, 5, n_o // B, first=b * (n_o // B)) for b in range(B)]
     o = {"fluence_raw": sum(x["fluence_raw"] for x in outs), "absorbed": sum(x["absorbed"] for x in outs)}
 
     def blocks(F):
         return F.reshape(25, 8, 25, 8, 25, 8).sum(axis=(1, 3, 5))
 
     Fo = blocks(o["fluence_raw"]) / n_o
-    Fg = blocks(g["fluence_raw"]) / 1e7
+    Fg = blocks(g["fluence_raw"]) / n_g
     bo = np.stack([blocks(x["fluence_raw"]) for x in outs])
-    se = batch_se(list(bo)) / n_o
-    # test the blocks every oracle batch reached: elsewhere ten batches
-    # cannot estimate the standard error (one visit gives se = its value)
+    se = batch_se(list(bo)) / n_o * np.sqrt(1.0 + n_o / n_g)
+    # test the blocks every oracle batch reached: elsewhere a few visits
+    # cannot estimate the standard error
     keep = np.all(bo > 0, axis=0)
-    assert keep.mean() > 0.2
+    assert keep.sum() > 4000
     z = np.abs(Fg[keep] - Fo[keep]) / se[keep]
-    print(f"blocks within 3 SE: {np.mean(z <= 3):.4f}; max z {z.max():.2f}")
-    assert np.mean(z <= 3) >= 0.98
+    nu = B - 1
+    chi2 = float(np.mean(z ** 2)) * (nu - 2) / nu
+    print(f"blocks {int(keep.sum())}, within 3 SE: {np.mean(z <= 3):.4f}; max z {z.max():.2f}; chi2/dof {chi2:.4f}")
+    assert np.mean(z <= 3) >= 0.985
+    assert 0.9 <= chi2 <= 1.1
     absorbed_o = o["absorbed"] / n_o
-    absorbed_g = g["absorbed"] / 1e7
+    absorbed_g = g["absorbed"] / n_g
     assert np.all(np.abs(absorbed_g - absorbed_o) <= 4 * np.sqrt(0.25 / n_o) + 1e-12)
     e.close()
     torch.cuda.synchronize()
+
+
+@pytest.mark.parametrize("prec", ["f32", "f64"])
+@pytest.mark.parametrize("name,ng,N", [("sphere", 24, 40000), ("slab", 40, 20000), ("cylinder", 32, 20000)])
+def test_fluence_distribution_on_independent_packets(S, eng, orc, W, name, ng, N, prec):
+    """Not the same walks but the same distribution: the GPU on packet ids
+    [N, 2N) against the oracle on [0, N), each in 20 batches, by the
+    independent-sample test (t_38 per voxel; chi-square per degree of
+    freedom in [0.9, 1.1])."""
+    desc = W.WORKLOADS[name](n_grid=ng)
+    B, st = 20, N // 20
+    o = [orc.run(desc, 5, st, first=b * st)["fluence_raw"] for b in range(B)]
+    g = [S.run(desc, 5, st, first=N + b * st, engine=eng, precision=prec)["fluence_raw"] for b in range(B)]
+    independent_fluence_check(g, o)
 
 
 @pytest.mark.parametrize("prec", ["f32", "f64"])

@@ -32,8 +32,8 @@ def test_random_scene_runs_match_oracle(S, eng, orc, W, seed):
         if prec == "f64":   # the same walks, up to one packet a rounding flip sends elsewhere
             assert diff <= 1.0 + 1e-9 * n, seed
             assert abs(g["interfaces"] - o["interfaces"]) <= max(2, 2e-3 * o["interfaces"]), seed
-        else:               # FP32 flips send a few packets on other valid walks
-            assert diff <= max(1.0, 3 * se_abs), seed
+        else:               # FP32: 1e-4, or 2 packets per 1e4 where reflections are chaotic
+            assert diff <= max(1e-4 * o["absorbed"].sum(), 2.0 * n / 1e4), seed
             assert abs(g["interfaces"] - o["interfaces"]) <= max(5, 0.02 * o["interfaces"]), seed
         check_fluence(g, o, se, desc, "f32")
 
@@ -80,24 +80,34 @@ def test_random_scene_escape_images(S, eng, orc, W, seed):
 @pytest.mark.parametrize("seed", SEEDS[:6])
 def test_random_scene_relaxed_runs_match_oracle(S, eng, orc, W, seed):
     # over-relaxed steps (w = 1.9) on the random scenes: the FP64 walk takes
-    # the relaxed oracle's decisions
+    # the plain march's decisions (to one packet where distances are bounds)
     desc = dict(W.random_scene(seed), relax=1.9)
     n = 3000
-    o = orc.run(desc, 23, n)
+    o = orc.run(W.random_scene(seed), 23, n)
     g = S.run(desc, 23, n, engine=eng, precision="f64")
     assert abs(g["absorbed"].sum() - o["absorbed"].sum()) <= 1.0 + 1e-9 * n, seed
     assert abs(g["interfaces"] - o["interfaces"]) <= max(2, 2e-3 * o["interfaces"]), seed
     assert abs(identity_residual(g)) <= 1e-9 * n
 
 
+def _with_union(desc):
+    """The scene itself when it has a union region of several primitives;
+    else its first two inner regions merged into one union (the first's
+    properties), so every seed has a region to accelerate."""
+    if any(rg["op"] == "union" and len(rg["prims"]) >= 2 for rg in desc["regions"]):
+        return desc
+    r = [dict(rg) for rg in desc["regions"]]
+    r[1] = dict(r[1], prims=r[1]["prims"] + r[2]["prims"], op="union", k=0.0)
+    del r[2]
+    return dict(desc, regions=r)
+
+
 @pytest.mark.parametrize("seed", SEEDS)
 def test_random_scene_acceleration_grid(S, eng, W, seed):
     # the uniform grid over a union region of placed and modified primitives
     # changes how far steps go, never a decision
-    desc = W.random_scene(seed)
-    regs = [i for i, rg in enumerate(desc["regions"]) if rg["op"] == "union" and len(rg["prims"]) >= 2]
-    if not regs:
-        pytest.skip("no union region of several primitives in this scene")
+    desc = _with_union(W.random_scene(seed))
+    assert any(rg["op"] == "union" and len(rg["prims"]) >= 2 for rg in desc["regions"])
     desc = dict(desc, accel_cells=[8, 8, 8])   # the binding takes the union region with most primitives
     plain = S.run(dict(desc, accel_cells=None), 29, 3000, engine=eng, precision="f64")
     accel = S.run(desc, 29, 3000, engine=eng, precision="f64")

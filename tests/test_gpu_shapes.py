@@ -1,15 +1,17 @@
 """GPU parity of the further gallery shapes (Sec. 2.2: capped cone,
 octahedron, hexagonal prism, ellipsoid, and a bent rod) against the oracle
 on a scene holding all five, and escape closed forms on the GPU.  Same tolerances
-as the SDF walk's parity tests; the ellipsoid's distance is a bound, so run
-parity is held to one packet's weight as for the other Lipschitz-scaled
-shapes."""
+as the SDF walk's parity tests.  The scene's glass shapes make long
+chains of internal reflections, a chaotic billiard: FP32 runs have the
+allowance of gpu_helpers.absorbed_agrees.  The ellipsoid's distance is a
+bound, so in FP64 an interface hit can land up to delta apart from the
+oracle's (a step more or less): FP64 runs are held to one packet's weight."""
 import math
 
 import numpy as np
 import pytest
 
-from gpu_helpers import check_fluence, compare_traces, extent_of, identity_residual, oracle_batches
+from gpu_helpers import absorbed_agrees, check_fluence, compare_traces, extent_of, identity_residual, oracle_batches
 
 pytestmark = pytest.mark.gpu
 
@@ -37,7 +39,10 @@ def test_shapes_run_parity(S, eng, orc, W, prec):
     assert abs(identity_residual(g)) <= 1e-9 * n
     diff = abs(g["absorbed"].sum() - o["absorbed"].sum())
     print(f"shapes {prec}: absorbed relative difference {diff / o['absorbed'].sum():.3e}")
-    assert diff <= 1.0
+    if prec == "f32":
+        assert absorbed_agrees(g["absorbed"].sum(), o["absorbed"].sum(), n, prec, "shapes"), diff
+    else:
+        assert diff <= 1.0
     assert abs(g["interfaces"] - o["interfaces"]) <= 1e-3 * o["interfaces"]
     check_fluence(g, o, se, desc, "f32")
 

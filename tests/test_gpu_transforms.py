@@ -43,10 +43,13 @@ def test_gallery_run_parity(S, eng, orc, W, prec, abs_tol):
     # the twisted bar and the displaced shell have Lipschitz-scaled distances,
     # so an interface hit lands where the march stopped (within delta), not
     # on the surface; an FP64 rounding difference that costs one more step
-    # moves it by up to delta and the packet walks on slightly apart: both
-    # precisions are held to at most one packet's weight and to the SE-floored
+    # moves it by up to delta and the packet walks on slightly apart: FP64
+    # is held to one packet's weight, FP32 to 1e-4, both to the SE-floored
     # fluence check
-    assert rel <= abs_tol or diff <= 1.0
+    if prec == "f64":
+        assert rel <= abs_tol or diff <= 1.0
+    else:
+        assert rel <= abs_tol
     assert abs(g["interfaces"] - o["interfaces"]) <= 1e-3 * o["interfaces"]
     check_fluence(g, o, se, desc, "f32")
 

@@ -14,7 +14,7 @@ SEEDS = list(range(12))
 def test_shortcuts_keep_the_walk(orc, W, seed):
     desc = W.random_scene(seed)
     plain = orc.run(dict(desc, reuse=False, ambient_skip=False), 5, 300)
-    fast = orc.run(desc, 5, 300)
+    fast = orc.run(dict(desc, reuse=True, ambient_skip=True), 5, 300)
     for k in ("interactions", "interfaces", "reflections", "refractions", "kills", "escapes", "stalls"):
         # a bounded distance (twist, bend, displacement, ellipsoid) can be
         # re-evaluated shorter by the plain march and reach an interface
