@@ -382,6 +382,26 @@ smcrt_status smcrt_run_batch_ex(smcrt_engine* engine, int n, const smcrt_scene* 
                                 const uint64_t* first_packets, const uint64_t* n_packets, const smcrt_outputs* outs,
                                 void* hip_stream);
 
+/* smcrt_run_ex for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc): it calls no hipMalloc, hipFree or other allocating routine.
+ * Its device scratch -- the scene's tables, the job record, the packet
+ * counter, the uniform-grid build buffers and the voxel model's region
+ * grid -- lives in a fixed array of 32 MiB that each GPU the library runs
+ * on holds from its first use until the process ends; the walk tallies
+ * straight into out->fluence_raw (no brick grid), so results equal
+ * smcrt_run_ex's up to the order of FP64 sums.  The engine supplies the
+ * device and launch options only.  Every call on one GPU shares that GPU's
+ * scratch: calls that overlap on one GPU (on different streams, or from
+ * different engines or threads) race and must be serialised by the caller.
+ * The scene's packed tables are copied from host memory on hip_stream: the
+ * scene must not change or be destroyed until that work has completed.
+ * Errors: as smcrt_run_ex, and SMCRT_E_INVALID when the scene needs more
+ * scratch than 32 MiB (e.g. a voxel-model grid above about 3.3e7 voxels, or
+ * tables of about 6e4 primitives); nothing is queued then. */
+smcrt_status smcrt_run_ex_static(smcrt_engine* engine, const smcrt_scene* scene, uint64_t seed, uint64_t first_packet,
+                                 uint64_t n_packets, const smcrt_outputs* out, void* hip_stream);
+
 /* Fluence normalisation: d_phi[v] = d_raw[v] / (launched * voxel volume),
  * in cm^-2 per launched unit weight.  d_raw and d_phi: device, nx*ny*nz
  * doubles (may alias). */

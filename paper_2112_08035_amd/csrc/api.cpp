@@ -1272,6 +1272,88 @@ extern "C" smcrt_status smcrt_run(smcrt_engine* e, const smcrt_scene* scene, uin
   return smcrt_run_ex(e, scene, seed, first_packet, n_packets, &out, hip_stream);
 }
 
+// smcrt_run_ex without device allocation: the scene tables, the job record,
+// the packet counter, the uniform-grid build buffers and the voxel grid are
+// laid out in the library's fixed device scratch (static_run.hip), and the
+// walk tallies straight into the caller's grid (no brick grid).  Device
+// work: the table upload (from the scene's own packed tables), then kernels
+// only (job record, counter reset, grid builds, walk).
+extern "C" smcrt_status smcrt_run_ex_static(smcrt_engine* e, const smcrt_scene* scene, uint64_t seed,
+                                            uint64_t first_packet, uint64_t n_packets, const smcrt_outputs* out,
+                                            void* hip_stream) {
+  if (!e || !scene || !out) return fail(SMCRT_E_INVALID, "run_ex_static: NULL engine, scene or outputs");
+  if (!out->absorbed || !out->tallies) return fail(SMCRT_E_INVALID, "run_ex_static: absorbed and tallies are required");
+  if (n_packets == 0) return SMCRT_OK;
+  if (first_packet + n_packets < first_packet) return fail(SMCRT_E_INVALID, "run_ex_static: packet range overflows 64 bits");
+  smcrt_scene* s = const_cast<smcrt_scene*>(scene);
+  smcrt_status st = pack(s);
+  if (st != SMCRT_OK) return st;
+  const SceneHeader* h = reinterpret_cast<const SceneHeader*>(s->blob.data());
+  // layout in the scratch: tables, job record, counter, grid-build buffers, voxels
+  const size_t jobs_off = align256(s->blob.size());
+  const size_t counter_off = align256(jobs_off + sizeof(WalkArgs));
+  size_t off = align256(counter_off + sizeof(unsigned long long));
+  size_t acc_off = 0, cb = 0, vox_off = 0, vox_n = 0;
+  if (h->acc.region >= 0) {
+    acc_off = off;
+    cb = align256(sizeof(uint32_t) * ((size_t)h->acc.n_cells + 1));
+    off = acc_off + 3 * cb + align256(sizeof(uint32_t) * h->acc.capacity);
+  }
+  if (h->geometry == kGeomVoxel) {
+    vox_n = (size_t)h->g_dims[0] * h->g_dims[1] * h->g_dims[2];
+    vox_off = off;
+    off = align256(off + vox_n);
+  }
+  if (off > kStaticScratchBytes)
+    return fail(SMCRT_E_INVALID, "run_ex_static: the scene needs %zu bytes of device scratch, the static scratch holds %zu",
+                off, kStaticScratchBytes);
+  HIP_TRY(hipSetDevice(e->device), "hipSetDevice");
+  void* base_v = nullptr;
+  HIP_TRY(static_scratch(e->device, &base_v), "static scratch address");
+  char* base = static_cast<char*>(base_v);
+  const hipStream_t q = (hipStream_t)hip_stream;
+  WalkArgs a;
+  std::memset(&a, 0, sizeof(a));
+  a.sc = reinterpret_cast<const SceneHeader*>(base);
+  a.pd = reinterpret_cast<const PrimD*>(base + h->prim_offset_d);
+  a.pf = reinterpret_cast<const PrimF*>(base + h->prim_offset_f);
+  a.seed = seed;
+  a.first = first_packet;
+  a.n = n_packets;
+  a.counter = reinterpret_cast<unsigned long long*>(base + counter_off);
+  a.fluence = h->has_grid ? out->fluence_raw : nullptr;
+  a.absorbed = out->absorbed;
+  a.detector = h->det_face >= 0 ? out->detector : nullptr;
+  a.tallies = out->tallies;
+  a.acc_region = h->acc.region;
+  a.geometry = h->geometry + (h->xf ? kLaunchXf : 0);
+  if (vox_n) a.vox = reinterpret_cast<uint8_t*>(base + vox_off);
+  if (h->acc.region >= 0) {
+    a.acc_offsets = reinterpret_cast<const uint32_t*>(base + acc_off + 2 * cb);
+    a.acc_ids = reinterpret_cast<const uint32_t*>(base + acc_off + 3 * cb);
+  }
+  WalkArgs* d_job = reinterpret_cast<WalkArgs*>(base + jobs_off);
+  HIP_TRY(hipMemcpyAsync(base, s->blob.data(), s->blob.size(), hipMemcpyHostToDevice, q), "hipMemcpyAsync(tables)");
+  HIP_TRY(launch_write_job(a, d_job, q), "job record");
+  if (h->acc.region >= 0)
+    HIP_TRY(launch_accel_build(a.sc, a.pd, h->acc.n_prims, h->acc.n_cells, reinterpret_cast<uint32_t*>(base + acc_off),
+                               reinterpret_cast<uint32_t*>(base + acc_off + cb),
+                               reinterpret_cast<uint32_t*>(base + acc_off + 2 * cb),
+                               reinterpret_cast<uint32_t*>(base + acc_off + 3 * cb), q),
+            "accel build");
+  if (vox_n) HIP_TRY(launch_voxelize(d_job, 0, a.vox, vox_n, q), "voxelize");
+  HIP_TRY(launch_zero_u64(a.counter, q), "zero counter");
+  BatchArgs B;
+  std::memset(&B, 0, sizeof(B));
+  B.jobs = d_job;
+  B.n_jobs = 1;
+  B.refill_min = e->opts.refill_min;
+  B.surface_min = e->opts.surface_min;
+  B.geometry = a.geometry;
+  HIP_TRY(launch_walk(e->opts.precision, false, launch_cfg(e, a.geometry), B, q), "walk kernel");
+  return SMCRT_OK;
+}
+
 extern "C" smcrt_status smcrt_run_batch_ex(smcrt_engine* e, int n, const smcrt_scene* const* scenes, const uint64_t* seeds,
                                            const uint64_t* first_packets, const uint64_t* n_packets,
                                            const smcrt_outputs* outs, void* hip_stream) {

@@ -29,4 +29,12 @@ hipError_t launch_accel_build(const SceneHeader* d_sc, const PrimD* d_pd, int n_
 // resident workgroups per CU of the walk kernel of this launch class at this block size
 int walk_max_blocks_per_cu(int precision, int block, int launch_class);
 
+// Fixed device scratch of the run that allocates nothing (static_run.hip):
+// its size, and its address on `device`, which must be the current device
+// (looked up once per device and kept).
+constexpr size_t kStaticScratchBytes = size_t(32) << 20;
+hipError_t static_scratch(int device, void** out);
+// *dst = a, with a passed as a kernel argument
+hipError_t launch_write_job(const WalkArgs& a, WalkArgs* dst, hipStream_t stream);
+
 }  // namespace smcrt

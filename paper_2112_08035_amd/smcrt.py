@@ -95,6 +95,7 @@ _SIGS = {
     "smcrt_scene_set_geometry": ([_vp, C.c_int], C.c_int),
     "smcrt_scene_set_detector": ([_vp, C.c_int, _dp, _dp, C.POINTER(C.c_int32)], C.c_int),
     "smcrt_run_ex": ([_vp, _vp, C.c_uint64, C.c_uint64, C.c_uint64, C.POINTER(OutputsStruct), _vp], C.c_int),
+    "smcrt_run_ex_static": ([_vp, _vp, C.c_uint64, C.c_uint64, C.c_uint64, C.POINTER(OutputsStruct), _vp], C.c_int),
     "smcrt_run_batch_ex": ([_vp, C.c_int, C.POINTER(_vp), C.POINTER(C.c_uint64), C.POINTER(C.c_uint64),
                             C.POINTER(C.c_uint64), C.POINTER(OutputsStruct), _vp], C.c_int),
     "smcrt_scene_info": ([_vp, C.POINTER(C.c_int32), C.POINTER(C.c_int32), _dp, _dp], C.c_int),
@@ -240,6 +241,10 @@ def smcrt_scene_set_detector(scene, face, lo, hi, dims):
 
 def smcrt_run_ex(engine, scene, seed, first_packet, n_packets, outputs, stream):
     _check(lib().smcrt_run_ex(engine, scene, seed, first_packet, n_packets, C.byref(outputs), stream))
+
+
+def smcrt_run_ex_static(engine, scene, seed, first_packet, n_packets, outputs, stream):
+    _check(lib().smcrt_run_ex_static(engine, scene, seed, first_packet, n_packets, C.byref(outputs), stream))
 
 
 def smcrt_run_batch_ex(engine, scenes, seeds, first_packets, n_packets, outputs, stream):
