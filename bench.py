@@ -425,6 +425,44 @@ def copy_calibration(smcrt, desc, steps):
                                            "GB/s": 16 * n / (ms * 1e-3) / 1e9, "launches": steps + 1}}))
 
 
+def vessel_profile(smcrt, workloads, n_scenes, n, steps, warmup, precision):
+    """The batched microvascular network alone (for profiling): n_scenes
+    vessel scenes (2000 capsules each through the uniform grid, 128^3 grids,
+    mu_s scaled 0.5-2x) in one persistent launch, n packets per scene per
+    step; one JSON line with packets/s, kernel time per launch and the work
+    counters per packet."""
+    import numpy as np
+    import torch
+    descs = workloads.vessel_batch(n_scenes, n_caps=2000, n_grid=128)
+    eng = smcrt.Engine(0, precision=precision)
+    scenes = [smcrt.Scene(d) for d in descs]
+    outs = [smcrt.Outputs(sc) for sc in scenes]
+    st = torch.cuda.current_stream()
+    for w in range(warmup):
+        smcrt.launch_batch(eng, scenes, [900 + w] * n_scenes, [n] * n_scenes, outputs=outs, stream=st)
+    torch.cuda.synchronize()
+    for o in outs:
+        o.zero_()
+    marks = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
+    t0 = time.perf_counter()
+    for k in range(steps):
+        marks[k][0].record(st)
+        smcrt.launch_batch(eng, scenes, [k * n_scenes + i for i in range(n_scenes)], [n] * n_scenes, outputs=outs,
+                           stream=st)
+        marks[k][1].record(st)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    hs = [o.host() for o in outs]
+    tot = {k: sum(h[k] for h in hs) for k in ("launched", "steps", "interactions", "interfaces", "voxel_pieces")}
+    print(json.dumps({"vessel_batch": {
+        "scenes": n_scenes, "packets_per_scene": n, "precision": precision, "steps": steps,
+        "packets_per_s": n * n_scenes * steps / wall,
+        "launch_ms": float(np.mean([a.elapsed_time(b) for a, b in marks])),
+        "per_packet": {k: tot[k] / tot["launched"] for k in ("steps", "interactions", "interfaces", "voxel_pieces")},
+        "launch": eng.opts()}}))
+    eng.close()
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -440,6 +478,8 @@ def main():
     ap.add_argument("--serve-rate", type=float, default=0.0,
                     help="Poisson arrival rate of the serving leg (1/s); 0 = 70%% of the measured capacity")
     ap.add_argument("--serve-max-packets", type=float, default=1e6, help="largest request of the serving leg")
+    ap.add_argument("--vessels", type=int, default=0,
+                    help="only run the batched vessel networks: this many scenes, --packets per scene per step")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only stream the 200^3 FP64 grid through the fluence normalisation kernel "
                          "(a plain read-once/write-once copy of known size) and report its bandwidth")
@@ -454,6 +494,9 @@ def main():
 
     from paper_2112_08035_amd import smcrt, workloads
 
+    if args.vessels > 0:
+        vessel_profile(smcrt, workloads, args.vessels, int(args.packets), args.steps, args.warmup, args.precision)
+        return
     desc = workloads.slab_scene()
     if args.copy_calibration:
         copy_calibration(smcrt, desc, args.steps)

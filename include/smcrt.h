@@ -294,7 +294,12 @@ typedef struct {
                            caller's x-fastest grid after the walk; 1: always
                            tally into the caller's grid directly.  Results
                            agree to the order of FP64 sums. */
-  int32_t reserved;
+  int32_t no_stage;     /* 0: FP32 SDF jobs whose accelerated region is plain
+                           capsules (at most 3072) run in workgroups of 1024
+                           threads that hold the job's capsule records in LDS
+                           (Sec. 5's grid queries then gather from LDS); 1:
+                           they read the records from global memory.  Same
+                           arithmetic, same results. */
 } smcrt_opts;
 
 smcrt_status smcrt_engine_get_opts(const smcrt_engine* engine, smcrt_opts* out);

@@ -30,6 +30,27 @@ __device__ __forceinline__ void cell_range(const Accel& A, const PrimD& P, int c
   }
 }
 
+// Whether cell (x, y, z) lists the primitive.  A primitive whose box grown
+// by the margin overlaps the cell is listed, except a plain capsule whose
+// axis segment lies farther than r + margin + (half the cell diagonal) from
+// the cell centre: every point of the cell is then more than margin from
+// its surface, so a query there never needs it.  The test errs towards
+// listing (a relative slack of 1e-9 covers the rounding of the distance).
+__device__ __forceinline__ bool cell_lists(const Accel& A, const PrimD& P, int x, int y, int z) {
+  if (P.kind != kCapsule || P.flags != 0) return true;
+  double c[3], hd2 = 0.0;
+  const int ix[3] = {x, y, z};
+  for (int i = 0; i < 3; ++i) {
+    const double w = 1.0 / A.inv_cell[i];
+    c[i] = A.lo[i] + (ix[i] + 0.5) * w - P.v[i];  // cell centre relative to the segment start
+    hd2 += 0.25 * w * w;
+  }
+  const double t = fmin(fmax((c[0] * P.v[3] + c[1] * P.v[4] + c[2] * P.v[5]) * P.v[6], 0.0), 1.0);
+  const double d0 = c[0] - t * P.v[3], d1 = c[1] - t * P.v[4], d2 = c[2] - t * P.v[5];
+  const double reach = (P.v[7] + A.margin + sqrt(hd2)) * (1.0 + 1e-9);
+  return d0 * d0 + d1 * d1 + d2 * d2 <= reach * reach;
+}
+
 __global__ void accel_zero(uint32_t* __restrict__ a, uint32_t* __restrict__ b, int n) {
   for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
     a[i] = 0u;
@@ -42,10 +63,12 @@ __global__ void accel_count(const SceneHeader* __restrict__ sc, const PrimD* __r
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= A.n_prims) return;
   int c0[3], c1[3];
-  cell_range(A, pd[A.first_prim + i], c0, c1);
+  const PrimD& P = pd[A.first_prim + i];
+  cell_range(A, P, c0, c1);
   for (int z = c0[2]; z <= c1[2]; ++z)
     for (int y = c0[1]; y <= c1[1]; ++y)
-      for (int x = c0[0]; x <= c1[0]; ++x) atomicAdd(&counts[x + A.dims[0] * (y + A.dims[1] * z)], 1u);
+      for (int x = c0[0]; x <= c1[0]; ++x)
+        if (cell_lists(A, P, x, y, z)) atomicAdd(&counts[x + A.dims[0] * (y + A.dims[1] * z)], 1u);
 }
 
 // exclusive scan of counts into offsets[0..n_cells]; one workgroup of 1024
@@ -80,10 +103,12 @@ __global__ void accel_fill(const SceneHeader* __restrict__ sc, const PrimD* __re
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= A.n_prims) return;
   int c0[3], c1[3];
-  cell_range(A, pd[A.first_prim + i], c0, c1);
+  const PrimD& P = pd[A.first_prim + i];
+  cell_range(A, P, c0, c1);
   for (int z = c0[2]; z <= c1[2]; ++z)
     for (int y = c0[1]; y <= c1[1]; ++y)
       for (int x = c0[0]; x <= c1[0]; ++x) {
+        if (!cell_lists(A, P, x, y, z)) continue;
         const int c = x + A.dims[0] * (y + A.dims[1] * z);
         const uint64_t slot = (uint64_t)offsets[c] + atomicAdd(&cursors[c], 1u);
         if (slot < A.capacity) ids[slot] = (uint32_t)(A.first_prim + i);

@@ -755,6 +755,24 @@ static smcrt_status pack(smcrt_scene* s) {
   size_t off_d = (sizeof(SceneHeader) + 255) & ~size_t(255);
   size_t off_f = (off_d + np * sizeof(PrimD) + 255) & ~size_t(255);
   size_t bytes = off_f + np * sizeof(PrimF);
+  // compact capsule records of the accelerated region when it holds plain
+  // capsules only (the grid queries then read 32 or 64 bytes per capsule)
+  size_t n_caps = 0, cap_d = 0, cap_f = 0;
+  if (s->accel_region >= 0 && s->accel_region < (int)s->regions.size()) {
+    bool plain = true;
+    for (int32_t id : s->regions[s->accel_region].prims) {
+      const HostPrim& hp = s->prims[id];
+      if (hp.kind != kCapsule || hp.placed || turn_k(hp) != 0.0 || hp.round_r != 0.0 || hp.onion_t != 0.0 ||
+          hp.disp_a != 0.0 || repeated(hp) || hp.elong[0] != 0.0 || hp.elong[1] != 0.0 || hp.elong[2] != 0.0)
+        plain = false;
+    }
+    if (plain) {
+      n_caps = s->regions[s->accel_region].prims.size();
+      cap_d = (bytes + 255) & ~size_t(255);
+      cap_f = (cap_d + n_caps * 8 * sizeof(double) + 255) & ~size_t(255);
+      bytes = cap_f + n_caps * 8 * sizeof(float);
+    }
+  }
   s->blob.assign(bytes, 0);
   SceneHeader* h = reinterpret_cast<SceneHeader*>(s->blob.data());
   PrimD* pd = reinterpret_cast<PrimD*>(s->blob.data() + off_d);
@@ -854,6 +872,18 @@ static smcrt_status pack(smcrt_scene* s) {
   h->max_events = s->max_events;
   st = pack_accel(s, h, order);
   if (st != SMCRT_OK) return st;
+  if (n_caps && h->acc.region >= 0) {
+    double* cd = reinterpret_cast<double*>(s->blob.data() + cap_d);
+    float* cf = reinterpret_cast<float*>(s->blob.data() + cap_f);
+    for (size_t i = 0; i < n_caps; ++i)
+      for (int k = 0; k < 8; ++k) {
+        cd[8 * i + k] = pd[h->acc.first_prim + i].v[k];
+        cf[8 * i + k] = pf[h->acc.first_prim + i].v[k];
+      }
+    h->acc.caps = 1;
+    h->acc.cap_offset_d = cap_d;
+    h->acc.cap_offset_f = cap_f;
+  }
   h->prim_offset_d = off_d;
   h->prim_offset_f = off_f;
   h->blob_bytes = bytes;
@@ -918,6 +948,7 @@ static smcrt_status check_opts(const smcrt_opts* o) {
   if (o->refill_min < 1 || o->refill_min > 64) return fail(SMCRT_E_INVALID, "opts: refill_min must be in [1, 64]");
   if (o->surface_min < 1 || o->surface_min > 64) return fail(SMCRT_E_INVALID, "opts: surface_min must be in [1, 64]");
   if (o->tally_layout != 0 && o->tally_layout != 1) return fail(SMCRT_E_INVALID, "opts: tally_layout must be 0 or 1");
+  if (o->no_stage != 0 && o->no_stage != 1) return fail(SMCRT_E_INVALID, "opts: no_stage must be 0 or 1");
   return SMCRT_OK;
 }
 
@@ -933,6 +964,18 @@ static bool brick_tally(const smcrt_opts& o, const SceneHeader* h) {
   for (int i = 1; i < 3; ++i)
     if (std::fabs(h->g_d[i] - h->g_d[0]) > 1e-9 * h->g_d[0]) return false;
   return true;
+}
+
+// Launch class of a job (the kernel that runs it): its geometry model, plus
+// kLaunchXf for placed or modified primitives; FP32 SDF jobs whose
+// accelerated region is plain capsules that fit the LDS table run in the
+// staged-capsule kernel (not for traces, which run one packet per thread).
+static int job_class(const smcrt_opts& o, const SceneHeader* h, bool trace) {
+  const int c = h->geometry + (h->xf ? kLaunchXf : 0);
+  if (!trace && !o.no_stage && c == kGeomSdf && o.precision == SMCRT_PREC_F32 && h->acc.region >= 0 && h->acc.caps &&
+      h->acc.n_prims <= kStageCaps)
+    return kLaunchStaged;
+  return c;
 }
 
 // voxels of the 2x2x2-brick grid of a scene's fluence grid (partial bricks
@@ -988,8 +1031,8 @@ extern "C" smcrt_status smcrt_engine_set_opts(smcrt_engine* e, const smcrt_opts*
 
 static LaunchCfg launch_cfg(smcrt_engine* e, int launch_class) {
   LaunchCfg c;
-  c.block = e->opts.block;
-  int per_cu = e->opts.blocks_per_cu;
+  c.block = launch_class == kLaunchStaged ? 1024 : e->opts.block;
+  int per_cu = launch_class == kLaunchStaged ? 0 : e->opts.blocks_per_cu;
   if (per_cu <= 0) per_cu = walk_max_blocks_per_cu(e->opts.precision, c.block, launch_class);
   if (per_cu <= 0) per_cu = 1;
   c.grid = e->n_cu * per_cu;
@@ -1108,7 +1151,11 @@ static smcrt_status launch_jobs(smcrt_engine* e, const std::vector<JobSpec>& job
     a.detector = h->det_face >= 0 ? jobs[j].detector : nullptr;
     a.tallies = jobs[j].tallies;
     a.acc_region = h->acc.region;
-    a.geometry = h->geometry + (h->xf ? kLaunchXf : 0);  // launch class
+    a.geometry = tr ? job_class(e->opts, h, true) : job_class(e->opts, h, false);
+    if (h->acc.region >= 0 && h->acc.caps) {
+      a.acc_capd = reinterpret_cast<const double*>(sc + h->acc.cap_offset_d);
+      a.acc_capf = reinterpret_cast<const float*>(sc + h->acc.cap_offset_f);
+    }
     if (vox_n[u]) a.vox = vox_out ? vox_out : reinterpret_cast<uint8_t*>(base + vox_off[u]);
     if (brick_n[j]) {
       a.fluence = reinterpret_cast<double*>(base + brick_off[j]);
@@ -1152,7 +1199,7 @@ static smcrt_status launch_jobs(smcrt_engine* e, const std::vector<JobSpec>& job
   B.n_jobs = (int32_t)jobs.size();
   B.refill_min = e->opts.refill_min;
   B.surface_min = e->opts.surface_min;
-  bool has_geom[kLaunchClasses] = {false, false, false, false};
+  bool has_geom[kLaunchClasses] = {};
   for (size_t j = 0; j < jobs.size(); ++j) has_geom[table[j].geometry] = true;
   LaunchCfg cg[kLaunchClasses];
   for (int g = 0; g < kLaunchClasses; ++g) cg[g] = launch_cfg(e, g);
@@ -1326,7 +1373,11 @@ extern "C" smcrt_status smcrt_run_ex_static(smcrt_engine* e, const smcrt_scene* 
   a.detector = h->det_face >= 0 ? out->detector : nullptr;
   a.tallies = out->tallies;
   a.acc_region = h->acc.region;
-  a.geometry = h->geometry + (h->xf ? kLaunchXf : 0);
+  a.geometry = job_class(e->opts, h, false);
+  if (h->acc.region >= 0 && h->acc.caps) {
+    a.acc_capd = reinterpret_cast<const double*>(base + h->acc.cap_offset_d);
+    a.acc_capf = reinterpret_cast<const float*>(base + h->acc.cap_offset_f);
+  }
   if (vox_n) a.vox = reinterpret_cast<uint8_t*>(base + vox_off);
   if (h->acc.region >= 0) {
     a.acc_offsets = reinterpret_cast<const uint32_t*>(base + acc_off + 2 * cb);

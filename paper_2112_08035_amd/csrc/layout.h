@@ -25,8 +25,13 @@ enum SourceKind : int32_t { kPoint = 0, kPencil = 1, kDisc = 2, kRect = 3 };
 // comparison model of Sec. 3
 enum Geometry : int32_t { kGeomSdf = 0, kGeomVoxel = 1 };
 // launch class of a job: its geometry model, plus kLaunchXf when its scene
-// has placed or modified primitives (a separate kernel instantiation)
-enum LaunchClass : int32_t { kLaunchXf = 2, kLaunchClasses = 4 };
+// has placed or modified primitives (a separate kernel instantiation);
+// kLaunchStaged: an FP32 SDF job whose accelerated region is plain capsules
+// that fit the workgroup's LDS table (the staged-capsule kernel)
+enum LaunchClass : int32_t { kLaunchXf = 2, kLaunchStaged = 4, kLaunchClasses = 5 };
+
+// capsules an FP32 staged-capsule workgroup holds in LDS (two float4 each)
+constexpr int kStageCaps = 3072;
 
 // Primitive parameters, precomputed on the host:
 //   sphere   : c0 c1 c2 r
@@ -89,7 +94,12 @@ struct Region {
 struct Accel {
   int32_t region;                 // accelerated region, -1 = none
   int32_t dims[3];
-  int32_t n_cells, first_prim, n_prims, pad;
+  int32_t n_cells, first_prim, n_prims;
+  // 1: every primitive of the region is a plain capsule, also stored as a
+  // compact record (a, b - a, 1/|b - a|^2, r: 8 values, FP64 and FP32
+  // copies at cap_offset_d / cap_offset_f of the blob, region order)
+  int32_t caps;
+  uint64_t cap_offset_d, cap_offset_f;
   uint64_t capacity;              // entries the id list can hold
   double lo[3], inv_cell[3], margin;
   double box_lo[3], box_hi[3];    // bounding box of the region's primitives
@@ -159,6 +169,8 @@ struct WalkArgs {
   int32_t acc_region;            // copy of sc->acc.region (-1 = none)
   int32_t geometry;              // launch class: sc->geometry, plus kLaunchXf when sc->xf
   int32_t brick, pad_brick;      // 1: fluence is the 2x2x2-brick scratch grid (brick_index)
+  const double* acc_capd;        // compact capsule records of the accelerated region
+  const float* acc_capf;         //   (8 values each), or null when acc.caps = 0
   uint8_t* vox;                  // voxel model: region slot per voxel (nx*ny*nz, x fastest)
   double* detector;              // escape image (det_dims[0] * det_dims[1]), may be null
 };

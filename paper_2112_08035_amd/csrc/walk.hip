@@ -149,12 +149,32 @@ __device__ void surface(JobRef a, Packet<T>& pk, Lane& ln, LdsTallies& L) {
 // modified and further-shape primitives.  The launch takes only the jobs of
 // its (GEOM, XF) class.  4 waves per SIMD in FP32 (3 in FP64) keep the
 // walk's state in registers.
-template <typename T, bool TRACE, int GEOM, bool XF>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 4 : 3)))
+//
+// STAGE (FP32, scenes whose accelerated region is plain capsules): the
+// workgroup is 16 waves, one per SIMD slot of a CU, that work on one job
+// together.  It copies the job's capsule records into an LDS table once per
+// job, so the grid queries of the step loop -- a gather of a few capsules
+// per lane per step -- read LDS instead of global memory; the waves meet at
+// a barrier when the job is drained, and the workgroup takes the next job
+// and its table together.
+template <typename T, bool TRACE, int GEOM, bool XF, bool STAGE>
+__global__ void __launch_bounds__(STAGE ? 1024 : 256) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 4 : 3)))
 walk_kernel(const WalkArgs* __restrict__ job_table, BatchArgs B) {
+  static_assert(!STAGE || (sizeof(T) == 4 && GEOM == kGeomSdf && !XF && !TRACE), "staged capsules: FP32 SDF walks");
+  constexpr int kWaves = STAGE ? 16 : 4;
   const SMCRT_K WalkArgs* jobs = kptr(job_table);
-  __shared__ LdsTallies Lw[4];
-  __shared__ WaveStage Sw[4];
+  __shared__ LdsTallies Lw[kWaves];
+  __shared__ WaveStage Sw[kWaves];
+  LdsCaps caps_lds = nullptr;
+  F4* caps_fill = nullptr;
+  int* wg_job = nullptr;
+  if constexpr (STAGE) {
+    __shared__ F4 s_caps[2 * kStageCaps];
+    __shared__ int s_job;
+    caps_lds = (LdsCaps)s_caps;
+    caps_fill = s_caps;
+    wg_job = &s_job;
+  }
   const int lane = lane_id();
   const int wib = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // wave index in the block (wave uniform)
   LdsTallies& L = Lw[wib];
@@ -178,7 +198,18 @@ walk_kernel(const WalkArgs* __restrict__ job_table, BatchArgs B) {
   ln.n_rec = 0;
 
   int cur = 0;
-  if constexpr (!TRACE) {
+  if constexpr (STAGE) {
+    // the workgroup's first job (spread over the jobs in proportion), then its table
+    if (wib == 0) {
+      const int j = pick_job(jobs, B, (int)(((long)blockIdx.x * B.n_jobs) / gridDim.x));
+      if (lane == 0) *wg_job = j;
+    }
+    __syncthreads();
+    cur = *wg_job;
+    if (cur < 0) return;  // every wave of the workgroup leaves together
+    if (!stage_caps(jobs[cur], caps_fill)) caps_lds = nullptr;
+    __syncthreads();
+  } else if constexpr (!TRACE) {
     const int waves_per_block = blockDim.x >> 6;
     const long gw = (long)blockIdx.x * waves_per_block + wib;
     const long tw = (long)gridDim.x * waves_per_block;
@@ -281,7 +312,7 @@ walk_kernel(const WalkArgs* __restrict__ job_table, BatchArgs B) {
         } else {
           ++ln.n_steps;
           T dmin = tinf<T>();
-          for (int r = 0; r < nr; ++r) dmin = tmin(dmin, tabs(region_dist<T, XF>(a, r, pk.p)));
+          for (int r = 0; r < nr; ++r) dmin = tmin(dmin, tabs(region_dist<T, XF>(a, r, pk.p, caps_lds)));
           int face;
           const bool outside = outside_volume<T>(sc, pk.p, &face);
           bool rejected = false;
@@ -381,6 +412,21 @@ walk_kernel(const WalkArgs* __restrict__ job_table, BatchArgs B) {
       if (id < a.n_trace) a.trace_count[id] = ln.n_rec < a.max_records ? ln.n_rec : a.max_records;
       flush_wave(a, ln, L, lane);
       break;
+    } else if constexpr (STAGE) {
+      // job drained by this wave: hand in its sums; once every wave is done
+      // with the job (and its table), the workgroup takes the next one
+      flush_wave(a, ln, L, lane);
+      __syncthreads();
+      if (wib == 0) {
+        const int j = pick_job(jobs, B, cur + 1);
+        if (lane == 0) *wg_job = j;
+      }
+      __syncthreads();
+      cur = *wg_job;
+      if (cur < 0) break;
+      caps_lds = (LdsCaps)caps_fill;
+      if (!stage_caps(jobs[cur], caps_fill)) caps_lds = nullptr;
+      __syncthreads();
     } else {
       // job drained by this wave: hand in its sums, take the next job
       flush_wave(a, ln, L, lane);
@@ -400,11 +446,11 @@ __global__ void scale_kernel(const double* __restrict__ in, double* __restrict__
 template <int GEOM, bool XF>
 static void launch_geom(int precision, bool trace, dim3 grid, dim3 block, const BatchArgs& args, hipStream_t stream) {
   if (precision == 1) {
-    if (trace) hipLaunchKernelGGL((walk_kernel<double, true, GEOM, XF>), grid, block, 0, stream, args.jobs, args);
-    else hipLaunchKernelGGL((walk_kernel<double, false, GEOM, XF>), grid, block, 0, stream, args.jobs, args);
+    if (trace) hipLaunchKernelGGL((walk_kernel<double, true, GEOM, XF, false>), grid, block, 0, stream, args.jobs, args);
+    else hipLaunchKernelGGL((walk_kernel<double, false, GEOM, XF, false>), grid, block, 0, stream, args.jobs, args);
   } else {
-    if (trace) hipLaunchKernelGGL((walk_kernel<float, true, GEOM, XF>), grid, block, 0, stream, args.jobs, args);
-    else hipLaunchKernelGGL((walk_kernel<float, false, GEOM, XF>), grid, block, 0, stream, args.jobs, args);
+    if (trace) hipLaunchKernelGGL((walk_kernel<float, true, GEOM, XF, false>), grid, block, 0, stream, args.jobs, args);
+    else hipLaunchKernelGGL((walk_kernel<float, false, GEOM, XF, false>), grid, block, 0, stream, args.jobs, args);
   }
 }
 
@@ -414,6 +460,13 @@ hipError_t launch_walk(int precision, bool trace, const LaunchCfg& cfg, const Ba
   if (!args.jobs || args.n_jobs < 1 || (trace && args.n_jobs != 1)) return hipErrorInvalidValue;
   if (args.refill_min < 1 || args.refill_min > 64 || args.surface_min < 1 || args.surface_min > 64) return hipErrorInvalidValue;
   if (args.geometry < 0 || args.geometry >= kLaunchClasses) return hipErrorInvalidValue;
+  if (args.geometry == kLaunchStaged) {
+    // FP32 staged-capsule walk: workgroups of 16 waves, no trace variant
+    if (precision != 0 || trace || cfg.block != 1024 || cfg.grid < 1) return hipErrorInvalidConfiguration;
+    hipLaunchKernelGGL((walk_kernel<float, false, kGeomSdf, false, true>), dim3(cfg.grid), dim3(1024), 0, stream,
+                       args.jobs, args);
+    return hipGetLastError();
+  }
   if (cfg.block < 64 || cfg.block > 256 || cfg.block % 64 || cfg.grid < 1) return hipErrorInvalidConfiguration;
   dim3 grid(cfg.grid), block(cfg.block);
   switch (args.geometry) {
@@ -478,13 +531,18 @@ hipError_t launch_scale(const double* in, double* out, size_t n, double scale, h
 
 template <int GEOM, bool XF>
 static hipError_t occupancy(int* n, int precision, int block) {
-  return precision == 1 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(n, walk_kernel<double, false, GEOM, XF>, block, 0)
-                        : hipOccupancyMaxActiveBlocksPerMultiprocessor(n, walk_kernel<float, false, GEOM, XF>, block, 0);
+  return precision == 1 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(n, walk_kernel<double, false, GEOM, XF, false>, block, 0)
+                        : hipOccupancyMaxActiveBlocksPerMultiprocessor(n, walk_kernel<float, false, GEOM, XF, false>, block, 0);
 }
 
 int walk_max_blocks_per_cu(int precision, int block, int launch_class) {
   int n = 0;
   hipError_t e;
+  if (launch_class == kLaunchStaged) {
+    if (precision != 0 || block != 1024) return 0;
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, walk_kernel<float, false, kGeomSdf, false, true>, 1024, 0);
+    return e == hipSuccess ? n : 0;
+  }
   switch (launch_class) {
     case kGeomSdf: e = occupancy<kGeomSdf, false>(&n, precision, block); break;
     case kGeomVoxel: e = occupancy<kGeomVoxel, false>(&n, precision, block); break;

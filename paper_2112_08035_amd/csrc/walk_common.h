@@ -116,11 +116,17 @@ __device__ __forceinline__ T xi_of(uint32_t w) {
 
 // ------------------------------------------------------------------ scene
 
+// the capsule table a staged-capsule workgroup holds in LDS (two float4 per
+// capsule: a.x a.y a.z ba.x | ba.y ba.z 1/|ba|^2 r)
+typedef float F4 __attribute__((ext_vector_type(4)));
+using LdsCaps = const __attribute__((address_space(3))) F4*;
+
 template <typename T>
 struct Tab;
 template <>
 struct Tab<float> {
   static __device__ __forceinline__ const SMCRT_K PrimF* prims(JobRef a) { return kptr(a.pf); }
+  static __device__ __forceinline__ const SMCRT_K float* caps(JobRef a) { return kptr(a.acc_capf); }
   static __device__ __forceinline__ float k(RegRef r) { return r.kf; }
   static __device__ __forceinline__ float inv_k(RegRef r) { return r.inv_kf; }
   static __device__ __forceinline__ float mut(RegRef r) { return r.mutf; }
@@ -148,6 +154,7 @@ struct Tab<float> {
 template <>
 struct Tab<double> {
   static __device__ __forceinline__ const SMCRT_K PrimD* prims(JobRef a) { return kptr(a.pd); }
+  static __device__ __forceinline__ const SMCRT_K double* caps(JobRef a) { return kptr(a.acc_capd); }
   static __device__ __forceinline__ double k(RegRef r) { return r.k; }
   static __device__ __forceinline__ double inv_k(RegRef r) { return r.inv_k; }
   static __device__ __forceinline__ double mut(RegRef r) { return r.mut; }
@@ -420,13 +427,26 @@ __device__ __forceinline__ T region_sdf(JobRef a, RegRef R, V3<T> p) {
   return d;
 }
 
+// capsule SDF from a compact record c = (a, b - a, 1/|b - a|^2, r): the
+// capsule branch of shape_sdf, operation for operation
+template <typename T>
+__device__ __forceinline__ T cap_sdf(T a0, T a1, T a2, T e0, T e1, T e2, T inv, T r, V3<T> p) {
+  const V3<T> q = p - mk(a0, a1, a2);
+  const V3<T> e = mk(e0, e1, e2);
+  const T t = tclamp(dot(q, e) * inv, T(0), T(1));
+  const V3<T> d = q - t * e;
+  return tsqrt(dot(d, d)) - r;
+}
+
 // SDF of the accelerated region through its uniform grid: min(margin, min
 // over the primitives listed in p's cell).  Equal to the region SDF where
 // that is below the margin, a lower bound elsewhere; outside the grid box
 // (which is the primitives' box grown by the margin) the distance to the
-// primitives' box is the lower bound.  Every index is checked.
+// primitives' box is the lower bound.  Every index is checked.  Regions of
+// plain capsules read their compact records: from the workgroup's LDS
+// table when lds is given (FP32 staged walk), else from global memory.
 template <typename T, bool XF>
-__device__ __forceinline__ T accel_sdf(JobRef a, V3<T> p) {
+__device__ __forceinline__ T accel_sdf(JobRef a, V3<T> p, LdsCaps lds = nullptr) {
   const SMCRT_K Accel& A = kptr(a.sc)->acc;
   const V3<T> lo = Tab<T>::acc_lo(A), ic = Tab<T>::acc_inv(A);
   const T cx = (p.x - lo.x) * ic.x, cy = (p.y - lo.y) * ic.y, cz = (p.z - lo.z) * ic.z;
@@ -450,6 +470,30 @@ __device__ __forceinline__ T accel_sdf(JobRef a, V3<T> p) {
   const SMCRT_K Prim<T>* P = Tab<T>::prims(a);
   const uint32_t lo_id = (uint32_t)A.first_prim, hi_id = (uint32_t)(A.first_prim + A.n_prims);
   T d = Tab<T>::acc_margin(A);
+  if (A.caps) {
+    if constexpr (sizeof(T) == 4) {
+      if (lds) {
+        for (uint64_t i = b; i < e; ++i) {
+          const uint32_t id = ids[i];
+          if (id >= lo_id && id < hi_id) {
+            const uint32_t k = id - lo_id;
+            const F4 x = lds[2 * k], y = lds[2 * k + 1];
+            d = tmin(d, cap_sdf<T>(x.x, x.y, x.z, x.w, y.x, y.y, y.z, y.w, p));
+          }
+        }
+        return d;
+      }
+    }
+    const SMCRT_K T* C = Tab<T>::caps(a);
+    for (uint64_t i = b; i < e; ++i) {
+      const uint32_t id = ids[i];
+      if (id >= lo_id && id < hi_id) {
+        const SMCRT_K T* c = C + 8 * (size_t)(id - lo_id);
+        d = tmin(d, cap_sdf<T>(c[0], c[1], c[2], c[3], c[4], c[5], c[6], c[7], p));
+      }
+    }
+    return d;
+  }
   for (uint64_t i = b; i < e; ++i) {
     const uint32_t id = ids[i];
     if (id >= lo_id && id < hi_id) d = tmin(d, prim_sdf<T, XF>(P, (int)id, p));
@@ -459,8 +503,8 @@ __device__ __forceinline__ T accel_sdf(JobRef a, V3<T> p) {
 
 // SDF of region r (through the grid when r is the accelerated region)
 template <typename T, bool XF>
-__device__ __forceinline__ T region_dist(JobRef a, int r, V3<T> p) {
-  if (r == a.acc_region) return accel_sdf<T, XF>(a, p);
+__device__ __forceinline__ T region_dist(JobRef a, int r, V3<T> p, LdsCaps lds = nullptr) {
+  if (r == a.acc_region) return accel_sdf<T, XF>(a, p, lds);
   return region_sdf<T, XF>(a, kptr(a.sc)->reg[r], p);
 }
 
@@ -1075,6 +1119,19 @@ __device__ __forceinline__ int pick_job(const SMCRT_K WalkArgs* jobs, const Batc
     if (cu < J.n) return j;
   }
   return -1;
+}
+
+// Copies job a's FP32 capsule records into the workgroup's LDS table (two
+// float4 per capsule); false, with nothing copied, when the job has none or
+// more than the table holds.  Called by every thread of the workgroup; the
+// caller's barrier makes the table visible.
+__device__ __forceinline__ bool stage_caps(JobRef a, F4* dst) {
+  const SMCRT_K Accel& A = kptr(a.sc)->acc;
+  if (A.region < 0 || !A.caps || A.n_prims > kStageCaps || a.acc_capf == nullptr) return false;
+  const F4* src = reinterpret_cast<const F4*>(a.acc_capf);
+  const int n = 2 * A.n_prims;
+  for (int i = threadIdx.x; i < n; i += blockDim.x) dst[i] = src[i];
+  return true;
 }
 
 // Adds a wave's pending sums to job a's outputs and clears them.  Called with

@@ -60,7 +60,7 @@ REQ_STATES = ["QUEUED", "RUNNING", "DONE", "FAILED", "CANCELLED"]
 class Opts(C.Structure):
     _fields_ = [("precision", C.c_int32), ("block", C.c_int32), ("blocks_per_cu", C.c_int32),
                 ("refill_min", C.c_int32), ("surface_min", C.c_int32), ("use_graph", C.c_int32),
-                ("tally_layout", C.c_int32), ("reserved", C.c_int32)]
+                ("tally_layout", C.c_int32), ("no_stage", C.c_int32)]
 
 
 class OutputsStruct(C.Structure):
@@ -466,12 +466,13 @@ class Engine:
             self.set_opts(**opts)
 
     def set_opts(self, precision=None, block=None, blocks_per_cu=None, refill_min=None, surface_min=None,
-                 use_graph=None, tally_layout=None):
+                 use_graph=None, tally_layout=None, no_stage=None):
         o = smcrt_engine_get_opts(self.h)
         if precision is not None:
             o.precision = PREC[precision] if isinstance(precision, str) else int(precision)
         for k, v in (("block", block), ("blocks_per_cu", blocks_per_cu), ("refill_min", refill_min),
-                     ("surface_min", surface_min), ("use_graph", use_graph), ("tally_layout", tally_layout)):
+                     ("surface_min", surface_min), ("use_graph", use_graph), ("tally_layout", tally_layout),
+                     ("no_stage", no_stage)):
             if v is not None:
                 setattr(o, k, int(v))
         smcrt_engine_set_opts(self.h, o)
@@ -486,7 +487,7 @@ class Engine:
     def opts(self):
         o = smcrt_engine_get_opts(self.h)
         return {k: getattr(o, k) for k in ("precision", "block", "blocks_per_cu", "refill_min", "surface_min",
-                                           "use_graph", "tally_layout")}
+                                           "use_graph", "tally_layout", "no_stage")}
 
     def close(self):
         if self.h:

@@ -218,7 +218,11 @@ def vessel_scene(seed, mus_scale=1.0, n_caps=2000, n_grid=128, side=0.2):
     sc["source"] = {"kind": "rect", "c": [0.5 * side, 0.5 * side, side + 0.5 * sc["pad"]],
                     "half": [0.5 * side, 0.5 * side], "u": [0.0, 0.0, -1.0]}
     sc["seed_tree"] = int(seed)
-    sc["accel_cells"] = [32, 32, 32]
+    # uniform grid of 64^3 cells (31 um): measured on 16 scenes of 2000
+    # capsules (FP32, staged capsules) 6.1e6 packets/s at 32^3, 8.7e6 at
+    # 48^3, 9.8e6 at 64^3, 9.7e6 at 96^3 -- shorter cell lists outweigh the
+    # extra steps the smaller margin costs
+    sc["accel_cells"] = [64, 64, 64]
     return sc
 
 

@@ -153,6 +153,29 @@ def _close(a, b, rtol):
         assert a[k] == b[k], k
 
 
+def test_staged_capsule_tables_change_nothing(S, W):
+    """FP32 vessel networks run by workgroups that hold the capsule records
+    in LDS (the default) and by waves that read them from global memory
+    (no_stage = 1): the same arithmetic, so the same walks -- equal event
+    and step counts, fluence to the order of FP64 sums -- in a batch of
+    scenes of 2000 capsules and alone."""
+    descs = W.vessel_batch(3, n_caps=2000, n_grid=64)
+    e_lds = S.Engine(0, precision="f32")
+    e_glb = S.Engine(0, precision="f32", no_stage=1)
+    assert e_lds.opts()["no_stage"] == 0 and e_glb.opts()["no_stage"] == 1
+    a = S.run_batch(descs, [3, 4, 5], [30000] * 3, engine=e_lds, precision="f32")
+    b = S.run_batch(descs, [3, 4, 5], [30000] * 3, engine=e_glb, precision="f32")
+    a.append(S.run(descs[0], 9, 20000, engine=e_lds, precision="f32"))
+    b.append(S.run(descs[0], 9, 20000, engine=e_glb, precision="f32"))
+    for x, y in zip(a, b):
+        for k in ("launched", "interactions", "interfaces", "reflections", "refractions", "steps", "voxel_pieces"):
+            assert x[k] == y[k], k
+        np.testing.assert_allclose(x["absorbed"], y["absorbed"], rtol=1e-12)
+        np.testing.assert_allclose(x["fluence_raw"], y["fluence_raw"], rtol=1e-9, atol=1e-12 * y["fluence_raw"].max())
+    e_lds.close()
+    e_glb.close()
+
+
 @pytest.mark.parametrize("prec", ["f64", "f32"])
 def test_batch_equals_runs_alone(S, eng, W, prec):
     """Mixed scene families in one persistent launch: every job's tallies
