@@ -414,19 +414,30 @@ smcrt_status smcrt_normalize_fluence(const smcrt_scene* scene, const double* d_r
                                      double* d_phi, void* hip_stream);
 
 /* ------------------------------------------------------------ serving --- */
-/* Continuous batching of requests.  A server owns an engine on `device` and
- * a worker thread.  Requests are admitted in arrival order while the device
- * bytes they hold (outputs, scene tables, grid buffers) fit the budget; the
- * worker runs epochs -- one batched launch in which every admitted request
- * runs its next chunk of packet ids (about epoch_packets in total, split
- * evenly) -- so requests arriving while others run join the next epoch.  A
- * request is done when all its packets have run; its outputs then equal an
- * smcrt_run of the same scene, seed and packets up to FP64 summation order.
- * Scenes and outputs are borrowed until the request is DONE, FAILED or
- * CANCELLED and must not change meanwhile.  device = -1 runs the scheduler
- * without a device (epochs complete at once, outputs untouched): a dry run
- * for admission, ordering, budget and cancellation.  Times are seconds since
- * the server was created. */
+/* Continuous batching of requests with device-resident state.  A server
+ * owns an engine on `device` and a worker thread.  Requests are admitted in
+ * arrival order, up to 128 at a time, while the device bytes they hold
+ * (outputs, scene tables, grid buffers, voxel grid) fit the budget; an
+ * admitted request keeps its tables and a packet-id counter on the device.
+ * The worker runs epochs of a fixed length of device time (20 ms unless
+ * smcrt_server_set_epoch_us says otherwise): one launch per kernel class in
+ * which every resident request is a job; waves resume the packets the last
+ * epoch left in flight, then take new ids, and when the epoch's time is up
+ * the packets still in flight are saved whole to device memory and resumed
+ * by the next epoch -- so requests arriving meanwhile join at the next
+ * epoch without waiting for long packets to end.  Served requests tally
+ * straight into their outputs.  A request is done when all its ids are
+ * handed out and none of its packets is in flight; its outputs then equal
+ * an smcrt_run of the same scene, seed and packets up to FP64 summation
+ * order.  Beside the budget the server holds fixed device memory: two slabs
+ * of 256 bytes per resident lane (one packet each) and small per-slot
+ * tables.  Scenes and outputs are borrowed until the request is DONE,
+ * FAILED or CANCELLED and must not change meanwhile.  device = -1 runs the
+ * scheduler without a device (epochs in which every admitted request takes
+ * its next epoch_packets / (admitted requests) ids, at least 1e4, and
+ * completes at once; outputs untouched): a dry run for admission, ordering,
+ * budget and cancellation.  Times are seconds since the server was
+ * created. */
 
 typedef struct smcrt_server smcrt_server;
 enum { SMCRT_REQ_QUEUED = 0, SMCRT_REQ_RUNNING = 1, SMCRT_REQ_DONE = 2, SMCRT_REQ_FAILED = 3, SMCRT_REQ_CANCELLED = 4 };
@@ -434,9 +445,12 @@ enum { SMCRT_REQ_QUEUED = 0, SMCRT_REQ_RUNNING = 1, SMCRT_REQ_DONE = 2, SMCRT_RE
 typedef struct {
   uint64_t epochs, packets_done, queued, active, bytes_in_use;
   double busy_s, uptime_s;
+  uint64_t in_flight;    /* packets saved at the end of the last epoch (device servers) */
+  uint64_t saved_total;  /* packets saved at epoch ends so far, summed (each resumed later) */
 } smcrt_server_info;
 
-/* hbm_budget_bytes > 0; epoch_packets 0 = 2e6; opts NULL = engine defaults */
+/* hbm_budget_bytes > 0; epoch_packets: dry runs only (0 = 2e6); opts NULL =
+ * engine defaults */
 smcrt_status smcrt_server_create(smcrt_server** out, int device, uint64_t hbm_budget_bytes,
                                  uint64_t epoch_packets, const smcrt_opts* opts);
 /* cancels queued requests, finishes the running epoch, frees everything */
@@ -452,6 +466,10 @@ smcrt_status smcrt_wait(smcrt_server* server, uint64_t request, double timeout_s
 /* queued: dropped; running: dropped at the end of the current epoch */
 smcrt_status smcrt_cancel(smcrt_server* server, uint64_t request);
 smcrt_status smcrt_server_stats(smcrt_server* server, smcrt_server_info* out);
+/* length of a device epoch in microseconds of device time, 100 to 1e7
+ * (default 20000): shorter epochs admit arrivals sooner, longer ones spend
+ * less time between launches */
+smcrt_status smcrt_server_set_epoch_us(smcrt_server* server, uint64_t epoch_us);
 
 /* ------------------------------------------------------------ traces ---- */
 

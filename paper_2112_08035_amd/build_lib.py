@@ -6,7 +6,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libsmcrt.so")
-SOURCES = [os.path.join(CSRC, f) for f in ("api.cpp", "walk.hip", "voxel.hip", "accel.hip", "static_run.hip")]
+SOURCES = [os.path.join(CSRC, f) for f in ("api.cpp", "walk.hip", "voxel.hip", "accel.hip", "static_run.hip", "serve.hip")]
 HEADERS = [os.path.join(CSRC, f) for f in ("layout.h", "launch.h", "walk_common.h", "voxel_model.h")] + [
     os.path.join(os.path.dirname(HERE), "include", "smcrt.h")]
 

@@ -1557,13 +1557,22 @@ extern "C" smcrt_status smcrt_normalize_fluence(const smcrt_scene* scene, const 
 
 // ------------------------------------------------------------------ serving
 //
-// Continuous batching: a worker thread admits queued requests in arrival
-// order while their device footprint fits the budget, then runs epochs.
-// An epoch is ONE batched launch in which every admitted request takes its
-// next chunk of packet ids; requests admitted while an epoch runs join the
-// next one, and a request is done once all its packets have run.  Packets
-// are keyed by (seed, packet id, event), and tallies add, so a request's
-// result equals its run alone up to FP64 summation order.
+// Continuous batching with device-resident state.  A worker thread admits
+// queued requests in arrival order into slots while their device
+// footprint fits the budget: each admitted request gets its scene tables,
+// grid-build buffers and voxel grid on the device and a packet-id counter
+// that persists while it is resident.  The device runs epochs of a fixed
+// length of device time: every resident request is a job of one batched
+// launch per kernel class; waves first resume the packets the previous
+// epoch left in flight, then take new ids, and at the epoch's deadline the
+// packets still in flight are written to an HBM slab (their whole state)
+// instead of being run to their end.  Between epochs the slab is sorted by
+// slot, new requests join, finished ones leave: arrivals never wait for the
+// longest packet of an epoch, and the device stays busy.  A request is done
+// when all its ids are handed out and none of its packets is in flight.
+// Packets are keyed by (seed, packet id, event) and tallies add, so its
+// result equals its run alone up to FP64 summation order.  Dry runs (no
+// device) keep a packet-chunk scheduler, for admission and cancellation.
 
 #include <chrono>
 #include <condition_variable>
@@ -1590,10 +1599,14 @@ struct Request {
 
 }  // namespace
 
+struct Resident;
+
 struct smcrt_server {
   smcrt_engine* engine = nullptr;  // NULL: dry run (scheduling only)
   smcrt_opts opts;                 // launch options (the engine's, also in a dry run)
   uint64_t budget = 0, used = 0, epoch_packets = 0, min_chunk = 0;
+  uint64_t epoch_us = 20000;       // device epochs: length in microseconds of device time
+  Resident* res = nullptr;         // device state of a device server
   std::mutex mu;
   std::condition_variable cv_work, cv_done;
   std::deque<Request*> queue;
@@ -1604,7 +1617,7 @@ struct smcrt_server {
   std::thread worker;
   hipStream_t stream = nullptr;
   std::chrono::steady_clock::time_point t0;
-  uint64_t epochs = 0, packets_done = 0;
+  uint64_t epochs = 0, packets_done = 0, in_flight = 0, saved_total = 0;
   double busy_s = 0;
 };
 
@@ -1613,20 +1626,20 @@ static double server_now(const smcrt_server* sv) {
 }
 
 // device bytes a request holds while admitted: its outputs, its scene
-// tables, the grid buffers of its accelerated region, and the brick grid its
-// walk tallies into when the server's options give it one (as large as the
-// output grid, rounded up to whole bricks)
-static uint64_t request_footprint(const smcrt_scene* s, const smcrt_opts& o) {
+// tables, the grid buffers of its accelerated region and its voxel grid
+// (served requests tally straight into their output grid: no brick grid)
+static uint64_t request_footprint(const smcrt_scene* s) {
   const SceneHeader* h = reinterpret_cast<const SceneHeader*>(s->blob.data());
   uint64_t b = s->blob.size() + sizeof(WalkArgs) + sizeof(smcrt_tallies) + 8 * kMaxRegions + 256;
   if (h->has_grid) b += 8ull * h->g_dims[0] * h->g_dims[1] * h->g_dims[2];
-  if (brick_tally(o, h)) b += 8ull * brick_voxels(h);
-  if (h->acc.region >= 0) b += 12ull * ((uint64_t)h->acc.n_cells + 1) + 4ull * h->acc.capacity;
-  if (h->geometry == kGeomVoxel) b += (uint64_t)h->g_dims[0] * h->g_dims[1] * h->g_dims[2];
+  if (h->acc.region >= 0) b += 12ull * ((uint64_t)h->acc.n_cells + 1) + 4ull * h->acc.capacity + 3 * 256;
+  if (h->geometry == kGeomVoxel) b += (uint64_t)h->g_dims[0] * h->g_dims[1] * h->g_dims[2] + 256;
   return b;
 }
 
-static void server_loop(smcrt_server* sv) {
+// Dry run (no device): epochs in which every admitted request takes its
+// next chunk of packet ids and completes at once.
+static void dry_loop(smcrt_server* sv) {
   std::unique_lock<std::mutex> lk(sv->mu);
   for (;;) {
     // admit in arrival order while the budget allows
@@ -1652,28 +1665,18 @@ static void server_loop(smcrt_server* sv) {
       continue;
     }
     // one epoch over every admitted request
-    std::vector<JobSpec> jobs;
     std::vector<std::pair<Request*, uint64_t>> taken;
     const uint64_t share = std::max<uint64_t>(sv->min_chunk, sv->epoch_packets / sv->active.size());
     for (Request* r : sv->active) {
       if (r->cancel) continue;
       const uint64_t chunk = std::min<uint64_t>(r->n - r->next, share);
       if (chunk == 0) continue;
-      jobs.push_back(JobSpec{r->scene, r->seed, r->next, chunk, r->fluence, r->absorbed, r->tallies});
       taken.push_back({r, chunk});
     }
     lk.unlock();
     const double t_start = server_now(sv);
-    smcrt_status st = SMCRT_OK;
+    const smcrt_status st = SMCRT_OK;
     std::string err;
-    if (sv->engine && !jobs.empty()) {
-      st = launch_jobs(sv->engine, jobs, nullptr, sv->stream);
-      if (st == SMCRT_OK) {
-        hipError_t e = hipStreamSynchronize(sv->stream);
-        if (e != hipSuccess) st = hip_fail(e, "epoch");
-      }
-      if (st != SMCRT_OK) err = smcrt_last_error();
-    }
     lk.lock();
     sv->busy_s += server_now(sv) - t_start;
     ++sv->epochs;
@@ -1708,6 +1711,376 @@ static void server_loop(smcrt_server* sv) {
   }
 }
 
+// ---- device servers
+
+namespace {
+
+constexpr int kMaxSlots = 128;
+
+// a resident request and its device allocation: scene tables, the
+// accelerated region's grid buffers, the voxel model's region grid
+struct Slot {
+  Request* r = nullptr;
+  char* dev = nullptr;
+  size_t acc_off = 0, acc_cb = 0, vox_off = 0, vox_n = 0;
+  uint64_t handed = 0;     // packet ids handed out so far
+  uint32_t saved = 0;      // packets in flight at the end of the last epoch
+  bool draining = false;   // left with packets saved (cancelled): idle for one epoch before reuse
+};
+
+}  // namespace
+
+struct Resident {
+  Slot slots[kMaxSlots];
+  int n_used = 0;  // slots 0..n_used-1 appear in the job table
+  // device state (persistent across epochs)
+  WalkArgs* d_jobs = nullptr;
+  unsigned long long* d_counters = nullptr;  // ids handed out, per slot
+  unsigned int* d_resume_next = nullptr;     // resumed packets taken, per slot
+  unsigned int* d_counts = nullptr;          // packets saved, per slot
+  unsigned int* d_cursors = nullptr;         // scatter cursors, per slot
+  unsigned int* d_offsets = nullptr;         // resume segment of each slot
+  unsigned int* d_save_count = nullptr;      // records in the save slab
+  unsigned char* d_save = nullptr;           // packets saved at the end of an epoch
+  unsigned char* d_resume = nullptr;         // the same, sorted by slot, resumed by the next epoch
+  uint32_t cap = 0;                          // records each slab holds
+  // pinned host mirrors
+  WalkArgs* h_jobs = nullptr;
+  unsigned long long* h_counters = nullptr;
+  unsigned int* h_counts = nullptr;
+  unsigned int* h_offsets = nullptr;
+  unsigned int* h_save_count = nullptr;
+  LaunchCfg cfg[kLaunchClasses];
+  uint64_t ticks_per_us = 0;
+  unsigned int prev_saved = 0;               // records the last epoch saved
+};
+
+static void resident_free(smcrt_server* sv) {
+  Resident* R = sv->res;
+  if (!R) return;
+  for (Slot& sl : R->slots)
+    if (sl.dev) (void)hipFree(sl.dev);
+  void* dev[] = {R->d_jobs, R->d_counters, R->d_resume_next, R->d_counts, R->d_cursors, R->d_offsets, R->d_save_count,
+                 R->d_save, R->d_resume};
+  for (void* p : dev)
+    if (p) (void)hipFree(p);
+  void* host[] = {R->h_jobs, R->h_counters, R->h_counts, R->h_offsets, R->h_save_count};
+  for (void* p : host)
+    if (p) (void)hipHostFree(p);
+  delete R;
+  sv->res = nullptr;
+}
+
+// Device state of a server: per-slot counters and job table, the two
+// packet slabs (one record per lane of every kernel class of an epoch),
+// pinned mirrors, the launch shapes and the wall-clock rate.
+static smcrt_status resident_init(smcrt_server* sv) {
+  Resident* R = new (std::nothrow) Resident();
+  if (!R) return fail(SMCRT_E_NOMEM, "server_create: out of host memory");
+  sv->res = R;
+  smcrt_engine* e = sv->engine;
+  uint64_t lanes = 0;
+  for (int g = 0; g < kLaunchClasses; ++g) {
+    R->cfg[g] = launch_cfg(e, g);
+    if (g == kLaunchStaged && e->opts.precision != SMCRT_PREC_F32) continue;
+    lanes += (uint64_t)R->cfg[g].grid * R->cfg[g].block;
+  }
+  if (lanes > 0xffffffffull) return fail(SMCRT_E_INVALID, "server_create: too many resident lanes");
+  R->cap = (uint32_t)lanes;
+  int khz = 0;
+  HIP_TRY(hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, e->device), "wall clock rate");
+  if (khz <= 0) return fail(SMCRT_E_HIP, "server_create: the device reports no wall-clock rate");
+  R->ticks_per_us = (uint64_t)khz / 1000 ? (uint64_t)khz / 1000 : 1;
+  HIP_TRY(hipMalloc(&R->d_jobs, sizeof(WalkArgs) * kMaxSlots), "hipMalloc(server jobs)");
+  HIP_TRY(hipMalloc(&R->d_counters, sizeof(unsigned long long) * kMaxSlots), "hipMalloc(server counters)");
+  HIP_TRY(hipMalloc(&R->d_resume_next, sizeof(unsigned int) * kMaxSlots), "hipMalloc(server resume)");
+  HIP_TRY(hipMalloc(&R->d_counts, sizeof(unsigned int) * kMaxSlots), "hipMalloc(server counts)");
+  HIP_TRY(hipMalloc(&R->d_cursors, sizeof(unsigned int) * kMaxSlots), "hipMalloc(server cursors)");
+  HIP_TRY(hipMalloc(&R->d_offsets, sizeof(unsigned int) * kMaxSlots), "hipMalloc(server offsets)");
+  HIP_TRY(hipMalloc(&R->d_save_count, sizeof(unsigned int)), "hipMalloc(server save count)");
+  HIP_TRY(hipMalloc(&R->d_save, (size_t)R->cap * kSavedPacketBytes), "hipMalloc(server save slab)");
+  HIP_TRY(hipMalloc(&R->d_resume, (size_t)R->cap * kSavedPacketBytes), "hipMalloc(server resume slab)");
+  HIP_TRY(hipHostMalloc(&R->h_jobs, sizeof(WalkArgs) * kMaxSlots, hipHostMallocDefault), "hipHostMalloc(jobs)");
+  HIP_TRY(hipHostMalloc(&R->h_counters, sizeof(unsigned long long) * kMaxSlots, hipHostMallocDefault), "hipHostMalloc");
+  HIP_TRY(hipHostMalloc(&R->h_counts, sizeof(unsigned int) * kMaxSlots, hipHostMallocDefault), "hipHostMalloc");
+  HIP_TRY(hipHostMalloc(&R->h_offsets, sizeof(unsigned int) * kMaxSlots, hipHostMallocDefault), "hipHostMalloc");
+  HIP_TRY(hipHostMalloc(&R->h_save_count, sizeof(unsigned int), hipHostMallocDefault), "hipHostMalloc");
+  std::memset(R->h_counts, 0, sizeof(unsigned int) * kMaxSlots);
+  HIP_TRY(launch_zero_u32(R->d_save_count, 1, sv->stream), "zero");
+  HIP_TRY(hipStreamSynchronize(sv->stream), "hipStreamSynchronize");
+  return SMCRT_OK;
+}
+
+// Job record of slot s for the next epoch (an empty one for a free slot)
+static void resident_job(smcrt_server* sv, int s, WalkArgs& a) {
+  Resident* R = sv->res;
+  Slot& sl = R->slots[s];
+  std::memset(&a, 0, sizeof(a));
+  a.counter = R->d_counters + s;
+  a.resume_next = R->d_resume_next + s;
+  a.slot = s;
+  a.geometry = -1;  // in no launch class
+  if (!sl.r) return;
+  const Request* r = sl.r;
+  const SceneHeader* h = reinterpret_cast<const SceneHeader*>(r->scene->blob.data());
+  a.sc = reinterpret_cast<const SceneHeader*>(sl.dev);
+  a.pd = reinterpret_cast<const PrimD*>(sl.dev + h->prim_offset_d);
+  a.pf = reinterpret_cast<const PrimF*>(sl.dev + h->prim_offset_f);
+  a.seed = r->seed;
+  a.first = 0;
+  a.n = r->cancel ? std::min(sl.handed, r->n) : r->n;  // a cancelled request takes no new ids
+  a.fluence = h->has_grid ? r->fluence : nullptr;
+  a.absorbed = r->absorbed;
+  a.tallies = r->tallies;
+  a.acc_region = h->acc.region;
+  a.geometry = job_class(sv->opts, h, false);
+  if (h->acc.region >= 0) {
+    a.acc_offsets = reinterpret_cast<const uint32_t*>(sl.dev + sl.acc_off + 2 * sl.acc_cb);
+    a.acc_ids = reinterpret_cast<const uint32_t*>(sl.dev + sl.acc_off + 3 * sl.acc_cb);
+    if (h->acc.caps) {
+      a.acc_capd = reinterpret_cast<const double*>(sl.dev + h->acc.cap_offset_d);
+      a.acc_capf = reinterpret_cast<const float*>(sl.dev + h->acc.cap_offset_f);
+    }
+  }
+  if (sl.vox_n) a.vox = reinterpret_cast<uint8_t*>(sl.dev + sl.vox_off);
+  if (!r->cancel && R->h_counts[s] > 0) {
+    a.resume = R->d_resume + (size_t)R->h_offsets[s] * kSavedPacketBytes;
+    a.resume_n = R->h_counts[s];
+  }
+}
+
+// Puts request r in free slot s: its tables, grid buffers and voxel grid on
+// the device, the grids built, its id counter zeroed.  Synchronous.
+static smcrt_status resident_admit(smcrt_server* sv, int s, Request* r) {
+  Resident* R = sv->res;
+  Slot& sl = R->slots[s];
+  const SceneHeader* h = reinterpret_cast<const SceneHeader*>(r->scene->blob.data());
+  size_t off = align256(r->scene->blob.size());
+  sl.acc_off = sl.acc_cb = sl.vox_off = sl.vox_n = 0;
+  if (h->acc.region >= 0) {
+    sl.acc_cb = align256(sizeof(uint32_t) * ((size_t)h->acc.n_cells + 1));
+    sl.acc_off = off;
+    off += 3 * sl.acc_cb + align256(sizeof(uint32_t) * h->acc.capacity);
+  }
+  if (h->geometry == kGeomVoxel) {
+    sl.vox_n = (size_t)h->g_dims[0] * h->g_dims[1] * h->g_dims[2];
+    sl.vox_off = off;
+    off = align256(off + sl.vox_n);
+  }
+  HIP_TRY(hipMalloc(&sl.dev, off), "hipMalloc(request tables)");
+  sl.r = r;
+  sl.handed = 0;
+  sl.saved = 0;
+  R->h_counts[s] = 0;
+  HIP_TRY(hipMemcpy(sl.dev, r->scene->blob.data(), r->scene->blob.size(), hipMemcpyHostToDevice), "upload tables");
+  resident_job(sv, s, R->h_jobs[s]);
+  HIP_TRY(hipMemcpyAsync(R->d_jobs + s, R->h_jobs + s, sizeof(WalkArgs), hipMemcpyHostToDevice, sv->stream),
+          "upload job");
+  HIP_TRY(launch_zero_u64(R->d_counters + s, sv->stream), "zero counter");
+  if (h->acc.region >= 0) {
+    char* ab = sl.dev + sl.acc_off;
+    HIP_TRY(launch_accel_build(reinterpret_cast<const SceneHeader*>(sl.dev),
+                               reinterpret_cast<const PrimD*>(sl.dev + h->prim_offset_d), h->acc.n_prims, h->acc.n_cells,
+                               reinterpret_cast<uint32_t*>(ab), reinterpret_cast<uint32_t*>(ab + sl.acc_cb),
+                               reinterpret_cast<uint32_t*>(ab + 2 * sl.acc_cb), reinterpret_cast<uint32_t*>(ab + 3 * sl.acc_cb),
+                               sv->stream),
+            "accel build");
+  }
+  if (sl.vox_n)
+    HIP_TRY(launch_voxelize(R->d_jobs, s, reinterpret_cast<uint8_t*>(sl.dev + sl.vox_off), sl.vox_n, sv->stream),
+            "voxelize");
+  HIP_TRY(hipStreamSynchronize(sv->stream), "hipStreamSynchronize(admit)");
+  return SMCRT_OK;
+}
+
+static void resident_release(smcrt_server* sv, int s) {
+  Slot& sl = sv->res->slots[s];
+  if (sl.dev) (void)hipFree(sl.dev);
+  sl.dev = nullptr;
+  sl.r = nullptr;
+  sl.draining = sl.saved > 0;
+  sl.handed = 0;
+  sl.saved = 0;
+}
+
+// The next epoch's job table and resume segments (the last epoch's
+// counts, in slot order) in the pinned mirrors; has[g]: class g has jobs.
+// Under the server's lock.
+static void resident_prepare(smcrt_server* sv, bool has[kLaunchClasses]) {
+  Resident* R = sv->res;
+  unsigned int acc = 0;
+  for (int s = 0; s < R->n_used; ++s) {
+    R->h_offsets[s] = acc;
+    acc += R->h_counts[s];
+  }
+  for (int g = 0; g < kLaunchClasses; ++g) has[g] = false;
+  for (int s = 0; s < R->n_used; ++s) {
+    resident_job(sv, s, R->h_jobs[s]);
+    const int g = R->h_jobs[s].geometry;
+    if (g >= 0 && g < kLaunchClasses) has[g] = true;
+  }
+}
+
+// One epoch on the device: job table, the previous epoch's packets sorted
+// by slot, one deadline-bounded launch per kernel class with jobs, the
+// packets not resumed carried over, the new slab counted by slot, counters
+// and counts copied back.  Synchronous.
+static smcrt_status resident_epoch(smcrt_server* sv, const bool has[kLaunchClasses]) {
+  Resident* R = sv->res;
+  smcrt_engine* e = sv->engine;
+  const hipStream_t q = sv->stream;
+  const int n = R->n_used;
+  HIP_TRY(hipMemcpyAsync(R->d_jobs, R->h_jobs, sizeof(WalkArgs) * n, hipMemcpyHostToDevice, q), "upload jobs");
+  HIP_TRY(hipMemcpyAsync(R->d_offsets, R->h_offsets, sizeof(unsigned int) * n, hipMemcpyHostToDevice, q), "offsets");
+  if (R->prev_saved > 0) {
+    HIP_TRY(launch_zero_u32(R->d_cursors, n, q), "zero cursors");
+    HIP_TRY(launch_saved_scatter(R->d_save, R->d_save_count, R->cap, R->d_offsets, R->d_cursors, R->d_resume, n, q),
+            "sort saved packets");
+  }
+  HIP_TRY(launch_zero_u32(R->d_resume_next, n, q), "zero resume cursors");
+  HIP_TRY(launch_zero_u32(R->d_save_count, 1, q), "zero save count");
+  BatchArgs B;
+  std::memset(&B, 0, sizeof(B));
+  B.jobs = R->d_jobs;
+  B.n_jobs = n;
+  B.refill_min = e->opts.refill_min;
+  B.surface_min = e->opts.surface_min;
+  B.deadline = sv->epoch_us * R->ticks_per_us;
+  B.save = R->d_save;
+  B.save_count = R->d_save_count;
+  B.save_cap = R->cap;
+  for (int g = 0; g < kLaunchClasses; ++g) {
+    if (!has[g]) continue;
+    B.geometry = g;
+    HIP_TRY(launch_walk(e->opts.precision, false, R->cfg[g], B, q), "walk kernel (epoch)");
+  }
+  HIP_TRY(launch_saved_carry(R->d_jobs, n, R->d_save, R->d_save_count, R->cap, q), "carry saved packets");
+  HIP_TRY(launch_zero_u32(R->d_counts, n, q), "zero counts");
+  HIP_TRY(launch_saved_count(R->d_save, R->d_save_count, R->cap, R->d_counts, n, q), "count saved packets");
+  HIP_TRY(hipMemcpyAsync(R->h_counters, R->d_counters, sizeof(unsigned long long) * n, hipMemcpyDeviceToHost, q), "read");
+  HIP_TRY(hipMemcpyAsync(R->h_counts, R->d_counts, sizeof(unsigned int) * n, hipMemcpyDeviceToHost, q), "read");
+  HIP_TRY(hipMemcpyAsync(R->h_save_count, R->d_save_count, sizeof(unsigned int), hipMemcpyDeviceToHost, q), "read");
+  HIP_TRY(hipStreamSynchronize(q), "hipStreamSynchronize(epoch)");
+  if (*R->h_save_count > R->cap)
+    return fail(SMCRT_E_HIP, "epoch: %u packets in flight, the slab holds %u", *R->h_save_count, R->cap);
+  R->prev_saved = *R->h_save_count;
+  return SMCRT_OK;
+}
+
+static void resident_loop(smcrt_server* sv) {
+  Resident* R = sv->res;
+  std::unique_lock<std::mutex> lk(sv->mu);
+  for (;;) {
+    if (sv->stop)  // shutting down: what runs is cancelled at the end of this epoch
+      for (int s = 0; s < R->n_used; ++s)
+        if (R->slots[s].r) R->slots[s].r->cancel = true;
+    // admit in arrival order while the budget and a slot allow
+    while (!sv->queue.empty()) {
+      Request* r = sv->queue.front();
+      if (r->cancel) {
+        sv->queue.pop_front();
+        r->state = SMCRT_REQ_CANCELLED;
+        r->t_done = server_now(sv);
+        sv->cv_done.notify_all();
+        continue;
+      }
+      if (sv->used + r->footprint > sv->budget) break;
+      int s = -1;
+      for (int k = 0; k < kMaxSlots && s < 0; ++k)
+        if (!R->slots[k].r && !R->slots[k].draining) s = k;
+      if (s < 0) break;
+      sv->queue.pop_front();
+      sv->used += r->footprint;
+      r->state = SMCRT_REQ_RUNNING;
+      r->t_admit = server_now(sv);
+      lk.unlock();
+      const smcrt_status st = resident_admit(sv, s, r);
+      const std::string err = st == SMCRT_OK ? std::string() : std::string(smcrt_last_error());
+      lk.lock();
+      if (st != SMCRT_OK) {
+        resident_release(sv, s);
+        R->slots[s].draining = false;
+        sv->used -= r->footprint;
+        r->state = SMCRT_REQ_FAILED;
+        r->error = err;
+        r->t_done = server_now(sv);
+        sv->cv_done.notify_all();
+        continue;
+      }
+      R->n_used = std::max(R->n_used, s + 1);
+    }
+    bool any = false, draining = false;
+    for (int s = 0; s < R->n_used; ++s) {
+      any = any || R->slots[s].r != nullptr;
+      draining = draining || R->slots[s].draining;
+    }
+    if (!any && !draining) {
+      R->n_used = 0;
+      if (sv->stop) return;
+      sv->cv_work.wait(lk);
+      continue;
+    }
+    bool has[kLaunchClasses];
+    resident_prepare(sv, has);
+    lk.unlock();
+    const double t_start = server_now(sv);
+    const smcrt_status st = resident_epoch(sv, has);
+    const std::string err = st == SMCRT_OK ? std::string() : std::string(smcrt_last_error());
+    lk.lock();
+    sv->busy_s += server_now(sv) - t_start;
+    ++sv->epochs;
+    if (st == SMCRT_OK) {
+      sv->in_flight = R->prev_saved;
+      sv->saved_total += R->prev_saved;
+    }
+    const double t = server_now(sv);
+    for (int s = 0; s < R->n_used; ++s) {
+      Slot& sl = R->slots[s];
+      if (!sl.r) {
+        sl.draining = false;  // its saved packets were neither resumed nor carried: gone
+        continue;
+      }
+      Request* r = sl.r;
+      const uint64_t was_done = sl.handed - sl.saved;
+      if (st == SMCRT_OK) {
+        sl.handed = std::min<uint64_t>(R->h_counters[s], r->n);
+        sl.saved = R->h_counts[s];
+        r->next = sl.handed;
+        sv->packets_done += (sl.handed - sl.saved) - was_done;
+      }
+      bool finished = true;
+      if (st != SMCRT_OK) {
+        r->state = SMCRT_REQ_FAILED;
+        r->error = err;
+      } else if (r->cancel) {
+        r->state = SMCRT_REQ_CANCELLED;
+      } else if (sl.handed >= r->n && sl.saved == 0) {
+        r->state = SMCRT_REQ_DONE;
+      } else {
+        finished = false;
+      }
+      if (finished) {
+        r->t_done = t;
+        sv->used -= r->footprint;
+        resident_release(sv, s);
+      }
+    }
+    if (st != SMCRT_OK) {  // a failed epoch leaves no trustworthy packet state
+      R->prev_saved = 0;
+      for (int s = 0; s < kMaxSlots; ++s) {
+        R->slots[s].draining = false;
+        R->h_counts[s] = 0;
+      }
+    }
+    sv->cv_done.notify_all();
+  }
+}
+
+static void server_loop(smcrt_server* sv) {
+  if (sv->engine) resident_loop(sv);
+  else dry_loop(sv);
+}
+
 extern "C" smcrt_status smcrt_server_create(smcrt_server** out, int device, uint64_t hbm_budget_bytes,
                                             uint64_t epoch_packets, const smcrt_opts* opts) {
   if (!out) return fail(SMCRT_E_INVALID, "server_create: out is NULL");
@@ -1737,6 +2110,15 @@ extern "C" smcrt_status smcrt_server_create(smcrt_server** out, int device, uint
       delete sv;
       return hip_fail(e, "server stream");
     }
+    st = resident_init(sv);
+    if (st != SMCRT_OK) {
+      const std::string msg = smcrt_last_error();
+      resident_free(sv);
+      (void)hipStreamDestroy(sv->stream);
+      smcrt_engine_destroy(sv->engine);
+      delete sv;
+      return fail(st, "%s", msg.c_str());
+    }
   }
   sv->worker = std::thread([sv]() {
     if (sv->engine) (void)hipSetDevice(sv->engine->device);
@@ -1756,6 +2138,11 @@ extern "C" smcrt_status smcrt_server_destroy(smcrt_server* sv) {
   sv->cv_work.notify_all();
   if (sv->worker.joinable()) sv->worker.join();
   for (auto& kv : sv->all) delete kv.second;
+  if (sv->engine) {
+    (void)hipSetDevice(sv->engine->device);
+    if (sv->stream) (void)hipStreamSynchronize(sv->stream);
+    resident_free(sv);
+  }
   if (sv->stream) (void)hipStreamDestroy(sv->stream);
   if (sv->engine) smcrt_engine_destroy(sv->engine);
   delete sv;
@@ -1775,7 +2162,7 @@ extern "C" smcrt_status smcrt_submit(smcrt_server* sv, const smcrt_scene* scene,
     if (st != SMCRT_OK) return st;
     if (sv->engine && (!d_absorbed || !d_tallies))
       return fail(SMCRT_E_INVALID, "submit: output buffers missing");
-    fp = request_footprint(s, sv->opts);
+    fp = request_footprint(s);
     if (fp > sv->budget)
       return fail(SMCRT_E_BUDGET, "submit: request needs %llu bytes, budget is %llu", (unsigned long long)fp,
                   (unsigned long long)sv->budget);
@@ -1843,6 +2230,14 @@ extern "C" smcrt_status smcrt_cancel(smcrt_server* sv, uint64_t req) {
   return SMCRT_OK;
 }
 
+extern "C" smcrt_status smcrt_server_set_epoch_us(smcrt_server* sv, uint64_t epoch_us) {
+  if (!sv) return fail(SMCRT_E_INVALID, "server_set_epoch_us: NULL server");
+  if (epoch_us < 100 || epoch_us > 10000000) return fail(SMCRT_E_INVALID, "server_set_epoch_us: epoch must be 100 us to 10 s");
+  std::lock_guard<std::mutex> g(sv->mu);
+  sv->epoch_us = epoch_us;
+  return SMCRT_OK;
+}
+
 extern "C" smcrt_status smcrt_server_stats(smcrt_server* sv, smcrt_server_info* out) {
   if (!sv || !out) return fail(SMCRT_E_INVALID, "server_stats: NULL argument");
   std::lock_guard<std::mutex> g(sv->mu);
@@ -1850,8 +2245,14 @@ extern "C" smcrt_status smcrt_server_stats(smcrt_server* sv, smcrt_server_info* 
   out->packets_done = sv->packets_done;
   out->queued = sv->queue.size();
   out->active = sv->active.size();
+  if (sv->res) {
+    out->active = 0;
+    for (const Slot& sl : sv->res->slots) out->active += sl.r != nullptr;
+  }
   out->bytes_in_use = sv->used;
   out->busy_s = sv->busy_s;
   out->uptime_s = server_now(sv);
+  out->in_flight = sv->in_flight;
+  out->saved_total = sv->saved_total;
   return SMCRT_OK;
 }

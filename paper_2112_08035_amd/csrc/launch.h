@@ -29,6 +29,20 @@ hipError_t launch_accel_build(const SceneHeader* d_sc, const PrimD* d_pd, int n_
 // resident workgroups per CU of the walk kernel of this launch class at this block size
 int walk_max_blocks_per_cu(int precision, int block, int launch_class);
 
+// Resident serving (serve.hip): packets saved at the end of an epoch are
+// fixed-size records in a slab, slot first.  counts[slot] += records of the
+// slot; scatter puts each record at offsets[slot] + k (cursors count k);
+// carry appends the records a job did not resume back to the save slab.
+// n: device count of records (clamped to cap).
+hipError_t launch_saved_count(const unsigned char* slab, const unsigned int* n, unsigned int cap, unsigned int* counts,
+                              int n_slots, hipStream_t stream);
+hipError_t launch_saved_scatter(const unsigned char* src, const unsigned int* n, unsigned int cap,
+                                const unsigned int* offsets, unsigned int* cursors, unsigned char* dst, int n_slots,
+                                hipStream_t stream);
+hipError_t launch_saved_carry(const WalkArgs* jobs, int n_jobs, unsigned char* save, unsigned int* save_count,
+                              unsigned int cap, hipStream_t stream);
+hipError_t launch_zero_u32(unsigned int* p, int n, hipStream_t stream);
+
 // Fixed device scratch of the run that allocates nothing (static_run.hip):
 // its size, and its address on `device`, which must be the current device
 // (looked up once per device and kept).

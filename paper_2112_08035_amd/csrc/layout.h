@@ -171,6 +171,14 @@ struct WalkArgs {
   int32_t brick, pad_brick;      // 1: fluence is the 2x2x2-brick scratch grid (brick_index)
   const double* acc_capd;        // compact capsule records of the accelerated region
   const float* acc_capf;         //   (8 values each), or null when acc.caps = 0
+  // resident serving: packets of this job saved at the end of the previous
+  // epoch (SavedPacket records of the launch's precision), taken through
+  // resume_next before new ids; slot = the job's stable index, written into
+  // the packets this launch saves
+  const void* resume;
+  unsigned int* resume_next;
+  uint32_t resume_n;
+  int32_t slot;
   uint8_t* vox;                  // voxel model: region slot per voxel (nx*ny*nz, x fastest)
   double* detector;              // escape image (det_dims[0] * det_dims[1]), may be null
 };
@@ -181,6 +189,19 @@ struct BatchArgs {
   int32_t n_jobs;
   int32_t refill_min, surface_min;
   int32_t geometry;              // the launch takes only the jobs of this launch class
+  // resident serving: a launch that runs for at most deadline ticks of the
+  // device wall clock (0 = to the end) writes the packets still live then
+  // to save (SavedPacket records, save_count of them, at most save_cap)
+  uint64_t deadline;
+  void* save;
+  unsigned int* save_count;
+  uint32_t save_cap;
+  int32_t pad_save;
 };
+
+// A packet in flight at the end of a resident-serving epoch: its whole
+// state (Packet<T> of the walk), the voxel of the voxel model, and the slot
+// (job) it belongs to.  Stored at a fixed size for both precisions.
+constexpr int kSavedPacketBytes = 256;
 
 }  // namespace smcrt

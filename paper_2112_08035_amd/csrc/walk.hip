@@ -157,10 +157,16 @@ __device__ void surface(JobRef a, Packet<T>& pk, Lane& ln, LdsTallies& L) {
 // per lane per step -- read LDS instead of global memory; the waves meet at
 // a barrier when the job is drained, and the workgroup takes the next job
 // and its table together.
-template <typename T, bool TRACE, int GEOM, bool XF, bool STAGE>
+//
+// EPOCH (resident serving): the launch stops at B.deadline, saving the
+// packets in flight, and resumes the jobs' saved packets before taking new
+// ids.  A separate instantiation: the save and resume paths cost registers
+// the plain walk does not spend.
+template <typename T, bool TRACE, int GEOM, bool XF, bool STAGE, bool EPOCH>
 __global__ void __launch_bounds__(STAGE ? 1024 : 256) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 4 : 3)))
 walk_kernel(const WalkArgs* __restrict__ job_table, BatchArgs B) {
   static_assert(!STAGE || (sizeof(T) == 4 && GEOM == kGeomSdf && !XF && !TRACE), "staged capsules: FP32 SDF walks");
+  static_assert(!EPOCH || !TRACE, "epochs are for runs, not traces");
   constexpr int kWaves = STAGE ? 16 : 4;
   const SMCRT_K WalkArgs* jobs = kptr(job_table);
   __shared__ LdsTallies Lw[kWaves];
@@ -168,12 +174,15 @@ walk_kernel(const WalkArgs* __restrict__ job_table, BatchArgs B) {
   LdsCaps caps_lds = nullptr;
   F4* caps_fill = nullptr;
   int* wg_job = nullptr;
+  uint64_t* wg_t0 = nullptr;
   if constexpr (STAGE) {
     __shared__ F4 s_caps[2 * kStageCaps];
     __shared__ int s_job;
+    __shared__ uint64_t s_t0;
     caps_lds = (LdsCaps)s_caps;
     caps_fill = s_caps;
     wg_job = &s_job;
+    wg_t0 = &s_t0;
   }
   const int lane = lane_id();
   const int wib = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // wave index in the block (wave uniform)
@@ -197,14 +206,27 @@ walk_kernel(const WalkArgs* __restrict__ job_table, BatchArgs B) {
   ln.rec = nullptr;
   ln.n_rec = 0;
 
+  // resident serving: a launch with a deadline stops when the device wall
+  // clock has run deadline ticks past its start (the workgroup's start in
+  // the staged kernel, so that its waves agree), saving the packets still
+  // in flight for the next epoch
+  uint64_t t0 = 0;
+  bool stop = false;
+  int iter = 0;
+  if constexpr (EPOCH && !STAGE) t0 = __builtin_amdgcn_s_memrealtime();
+
   int cur = 0;
   if constexpr (STAGE) {
     // the workgroup's first job (spread over the jobs in proportion), then its table
     if (wib == 0) {
       const int j = pick_job(jobs, B, (int)(((long)blockIdx.x * B.n_jobs) / gridDim.x));
-      if (lane == 0) *wg_job = j;
+      if (lane == 0) {
+        *wg_job = j;
+        *wg_t0 = __builtin_amdgcn_s_memrealtime();
+      }
     }
     __syncthreads();
+    t0 = *wg_t0;
     cur = *wg_job;
     if (cur < 0) return;  // every wave of the workgroup leaves together
     if (!stage_caps(jobs[cur], caps_fill)) caps_lds = nullptr;
@@ -231,7 +253,8 @@ walk_kernel(const WalkArgs* __restrict__ job_table, BatchArgs B) {
     const T delta = Tab<T>::delta(sc);
     const int max_steps = sc->max_steps;
     const uint32_t max_events = (uint32_t)sc->max_events;
-    bool exhausted = false;  // wave uniform
+    bool exhausted = false;     // wave uniform: no packet of this job left to take
+    bool resumed_all = false;   // wave uniform: no saved packet of this job left to resume
 
     if constexpr (TRACE) {
       const int id = blockIdx.x * blockDim.x + threadIdx.x;
@@ -246,24 +269,51 @@ walk_kernel(const WalkArgs* __restrict__ job_table, BatchArgs B) {
     }
 
     for (;;) {
-      // ---- refill dead lanes from the job's packet counter
+      // ---- end of a resident-serving epoch: save the packets in flight
+      if constexpr (EPOCH) {
+        if (!stop && (++iter & 15) == 0 && __builtin_amdgcn_s_memrealtime() - t0 > B.deadline) stop = true;
+        if (stop) {
+          save_live<T>(B, a, live, pk, vx, lane);
+          live = false;
+          exhausted = true;
+          break;
+        }
+      }
+
+      // ---- refill dead lanes: packets saved by the previous epoch first,
+      // then new ids from the job's packet counter
       if constexpr (!TRACE) {
         const uint64_t dmask = __ballot(!live);
         const int ndead = __popcll(dmask);
         if (!exhausted && ndead > 0 && (ndead >= B.refill_min || ndead == __popcll(__ballot(1)))) {
           const int leader = __ffsll((unsigned long long)dmask) - 1;
-          unsigned long long base = 0;
-          if (lane == leader) base = atomicAdd(a.counter, (unsigned long long)ndead);
-          base = __shfl(base, leader);
-          if (base + (uint64_t)ndead >= a.n) exhausted = true;
-          if (!live) {
-            const int rank = __popcll(dmask & ((1ull << lane) - 1ull));
-            const uint64_t id = base + (uint64_t)rank;
-            if (id < a.n) {
-              pk.pid = a.first + id;
+          const int rank = __popcll(dmask & ((1ull << lane) - 1ull));
+          int rtake = 0;
+          if (EPOCH && a.resume_n > 0 && !resumed_all) {
+            unsigned int rb = 0;
+            if (lane == leader) rb = atomicAdd(a.resume_next, (unsigned int)ndead);
+            rb = __shfl(rb, leader);
+            rtake = rb < a.resume_n ? (int)min((unsigned int)ndead, a.resume_n - rb) : 0;
+            if (rtake < ndead) resumed_all = true;
+            if (!live && rank < rtake) {
+              load_saved<T>(a, rb + (unsigned int)rank, pk, vx);
               live = true;
-              emit<T, TRACE, XF>(a, pk, ln, L);
-              if constexpr (GEOM == kGeomVoxel) live = enter_grid<T, TRACE>(a, pk, vx, ln, L);
+            }
+          }
+          const int rest = ndead - rtake;
+          if (rest > 0) {
+            unsigned long long base = 0;
+            if (lane == leader) base = atomicAdd(a.counter, (unsigned long long)rest);
+            base = __shfl(base, leader);
+            if (base + (uint64_t)rest >= a.n) exhausted = true;
+            if (!live && rank >= rtake) {
+              const uint64_t id = base + (uint64_t)(rank - rtake);
+              if (id < a.n) {
+                pk.pid = a.first + id;
+                live = true;
+                emit<T, TRACE, XF>(a, pk, ln, L);
+                if constexpr (GEOM == kGeomVoxel) live = enter_grid<T, TRACE>(a, pk, vx, ln, L);
+              }
             }
           }
         }
@@ -418,7 +468,8 @@ walk_kernel(const WalkArgs* __restrict__ job_table, BatchArgs B) {
       flush_wave(a, ln, L, lane);
       __syncthreads();
       if (wib == 0) {
-        const int j = pick_job(jobs, B, cur + 1);
+        const bool late = EPOCH && __builtin_amdgcn_s_memrealtime() - t0 > B.deadline;
+        const int j = late ? -1 : pick_job(jobs, B, cur + 1);
         if (lane == 0) *wg_job = j;
       }
       __syncthreads();
@@ -428,8 +479,10 @@ walk_kernel(const WalkArgs* __restrict__ job_table, BatchArgs B) {
       if (!stage_caps(jobs[cur], caps_fill)) caps_lds = nullptr;
       __syncthreads();
     } else {
-      // job drained by this wave: hand in its sums, take the next job
+      // job drained by this wave (or the epoch ended): hand in its sums,
+      // take the next job
       flush_wave(a, ln, L, lane);
+      if (stop) break;
       cur = pick_job(jobs, B, cur + 1);
       if (cur < 0) break;
     }
@@ -445,12 +498,15 @@ __global__ void scale_kernel(const double* __restrict__ in, double* __restrict__
 
 template <int GEOM, bool XF>
 static void launch_geom(int precision, bool trace, dim3 grid, dim3 block, const BatchArgs& args, hipStream_t stream) {
+  const bool epoch = args.deadline != 0;
   if (precision == 1) {
-    if (trace) hipLaunchKernelGGL((walk_kernel<double, true, GEOM, XF, false>), grid, block, 0, stream, args.jobs, args);
-    else hipLaunchKernelGGL((walk_kernel<double, false, GEOM, XF, false>), grid, block, 0, stream, args.jobs, args);
+    if (trace) hipLaunchKernelGGL((walk_kernel<double, true, GEOM, XF, false, false>), grid, block, 0, stream, args.jobs, args);
+    else if (epoch) hipLaunchKernelGGL((walk_kernel<double, false, GEOM, XF, false, true>), grid, block, 0, stream, args.jobs, args);
+    else hipLaunchKernelGGL((walk_kernel<double, false, GEOM, XF, false, false>), grid, block, 0, stream, args.jobs, args);
   } else {
-    if (trace) hipLaunchKernelGGL((walk_kernel<float, true, GEOM, XF, false>), grid, block, 0, stream, args.jobs, args);
-    else hipLaunchKernelGGL((walk_kernel<float, false, GEOM, XF, false>), grid, block, 0, stream, args.jobs, args);
+    if (trace) hipLaunchKernelGGL((walk_kernel<float, true, GEOM, XF, false, false>), grid, block, 0, stream, args.jobs, args);
+    else if (epoch) hipLaunchKernelGGL((walk_kernel<float, false, GEOM, XF, false, true>), grid, block, 0, stream, args.jobs, args);
+    else hipLaunchKernelGGL((walk_kernel<float, false, GEOM, XF, false, false>), grid, block, 0, stream, args.jobs, args);
   }
 }
 
@@ -463,8 +519,12 @@ hipError_t launch_walk(int precision, bool trace, const LaunchCfg& cfg, const Ba
   if (args.geometry == kLaunchStaged) {
     // FP32 staged-capsule walk: workgroups of 16 waves, no trace variant
     if (precision != 0 || trace || cfg.block != 1024 || cfg.grid < 1) return hipErrorInvalidConfiguration;
-    hipLaunchKernelGGL((walk_kernel<float, false, kGeomSdf, false, true>), dim3(cfg.grid), dim3(1024), 0, stream,
-                       args.jobs, args);
+    if (args.deadline)
+      hipLaunchKernelGGL((walk_kernel<float, false, kGeomSdf, false, true, true>), dim3(cfg.grid), dim3(1024), 0, stream,
+                         args.jobs, args);
+    else
+      hipLaunchKernelGGL((walk_kernel<float, false, kGeomSdf, false, true, false>), dim3(cfg.grid), dim3(1024), 0, stream,
+                         args.jobs, args);
     return hipGetLastError();
   }
   if (cfg.block < 64 || cfg.block > 256 || cfg.block % 64 || cfg.grid < 1) return hipErrorInvalidConfiguration;
@@ -531,8 +591,9 @@ hipError_t launch_scale(const double* in, double* out, size_t n, double scale, h
 
 template <int GEOM, bool XF>
 static hipError_t occupancy(int* n, int precision, int block) {
-  return precision == 1 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(n, walk_kernel<double, false, GEOM, XF, false>, block, 0)
-                        : hipOccupancyMaxActiveBlocksPerMultiprocessor(n, walk_kernel<float, false, GEOM, XF, false>, block, 0);
+  return precision == 1
+             ? hipOccupancyMaxActiveBlocksPerMultiprocessor(n, walk_kernel<double, false, GEOM, XF, false, false>, block, 0)
+             : hipOccupancyMaxActiveBlocksPerMultiprocessor(n, walk_kernel<float, false, GEOM, XF, false, false>, block, 0);
 }
 
 int walk_max_blocks_per_cu(int precision, int block, int launch_class) {
@@ -540,7 +601,7 @@ int walk_max_blocks_per_cu(int precision, int block, int launch_class) {
   hipError_t e;
   if (launch_class == kLaunchStaged) {
     if (precision != 0 || block != 1024) return 0;
-    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, walk_kernel<float, false, kGeomSdf, false, true>, 1024, 0);
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, walk_kernel<float, false, kGeomSdf, false, true, false>, 1024, 0);
     return e == hipSuccess ? n : 0;
   }
   switch (launch_class) {

@@ -836,6 +836,54 @@ struct Packet {
 
 constexpr int kReuseLinks = 32;  // interactions per evaluation at most
 
+// A packet still in flight when a resident-serving epoch ends (slot first,
+// at the same offset in both precisions, for the host-side kernels that
+// sort the records by slot).
+template <typename T>
+struct SavedPacket {
+  int32_t slot;
+  int32_t vx[3];
+  Packet<T> pk;
+};
+static_assert(sizeof(SavedPacket<double>) <= kSavedPacketBytes, "saved packet record too large");
+static_assert(sizeof(SavedPacket<float>) <= kSavedPacketBytes, "saved packet record too large");
+
+// Writes the live packets of the calling lanes (all lanes of the wave
+// active; live lanes save) to the launch's save slab.  The host sizes the
+// slab for one packet per lane of every launch of the epoch; a record
+// beyond it is counted but not written, and the host fails the epoch.
+template <typename T>
+__device__ __forceinline__ void save_live(const BatchArgs& B, JobRef a, bool live, const Packet<T>& pk,
+                                          const int vx[3], int lane) {
+  const uint64_t m = __ballot(live);
+  const int n = __popcll(m);
+  if (n == 0) return;
+  const int leader = __ffsll((unsigned long long)m) - 1;
+  unsigned int base = 0;
+  if (lane == leader) base = atomicAdd(B.save_count, (unsigned int)n);
+  base = __shfl(base, leader);
+  if (!live) return;
+  const unsigned int i = base + (unsigned int)__popcll(m & ((1ull << lane) - 1ull));
+  if (i >= B.save_cap) return;
+  SavedPacket<T>* s = reinterpret_cast<SavedPacket<T>*>(static_cast<char*>(B.save) + (size_t)i * kSavedPacketBytes);
+  s->slot = a.slot;
+  s->vx[0] = vx[0];
+  s->vx[1] = vx[1];
+  s->vx[2] = vx[2];
+  s->pk = pk;
+}
+
+// Packet i of job a's resumed packets
+template <typename T>
+__device__ __forceinline__ void load_saved(JobRef a, unsigned int i, Packet<T>& pk, int vx[3]) {
+  const SavedPacket<T>* s =
+      reinterpret_cast<const SavedPacket<T>*>(static_cast<const char*>(a.resume) + (size_t)i * kSavedPacketBytes);
+  pk = s->pk;
+  vx[0] = s->vx[0];
+  vx[1] = s->vx[1];
+  vx[2] = s->vx[2];
+}
+
 template <typename T>
 __device__ __forceinline__ void set_region(ScP sc, Packet<T>& pk, int r) {
   pk.region = r;
@@ -1117,6 +1165,10 @@ __device__ __forceinline__ int pick_job(const SMCRT_K WalkArgs* jobs, const Batc
     const uint64_t cu = ((uint64_t)__builtin_amdgcn_readfirstlane((unsigned)(c >> 32)) << 32) |
                         (uint64_t)__builtin_amdgcn_readfirstlane((unsigned)c);
     if (cu < J.n) return j;
+    if (J.resume_n > 0) {  // packets of an earlier epoch left to resume
+      const unsigned int r = __hip_atomic_load(J.resume_next, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      if (__builtin_amdgcn_readfirstlane(r) < J.resume_n) return j;
+    }
   }
   return -1;
 }

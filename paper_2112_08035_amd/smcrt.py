@@ -51,7 +51,8 @@ class Event(C.Structure):
 
 class ServerInfo(C.Structure):
     _fields_ = [("epochs", C.c_uint64), ("packets_done", C.c_uint64), ("queued", C.c_uint64), ("active", C.c_uint64),
-                ("bytes_in_use", C.c_uint64), ("busy_s", C.c_double), ("uptime_s", C.c_double)]
+                ("bytes_in_use", C.c_uint64), ("busy_s", C.c_double), ("uptime_s", C.c_double),
+                ("in_flight", C.c_uint64), ("saved_total", C.c_uint64)]
 
 
 REQ_STATES = ["QUEUED", "RUNNING", "DONE", "FAILED", "CANCELLED"]
@@ -118,6 +119,7 @@ _SIGS = {
     "smcrt_wait": ([_vp, C.c_uint64, C.c_double], C.c_int),
     "smcrt_cancel": ([_vp, C.c_uint64], C.c_int),
     "smcrt_server_stats": ([_vp, C.POINTER(ServerInfo)], C.c_int),
+    "smcrt_server_set_epoch_us": ([_vp, C.c_uint64], C.c_int),
 }
 
 
@@ -343,6 +345,10 @@ def smcrt_wait(server, request, timeout_s=-1.0):
 
 def smcrt_cancel(server, request):
     _check(lib().smcrt_cancel(server, request))
+
+
+def smcrt_server_set_epoch_us(server, epoch_us):
+    _check(lib().smcrt_server_set_epoch_us(server, int(epoch_us)))
 
 
 def smcrt_server_stats(server):
@@ -641,7 +647,7 @@ class Server:
     """Continuous-batching request server (smcrt_server_*).  device=-1 runs
     the scheduler alone (no device work)."""
 
-    def __init__(self, device=0, hbm_budget_bytes=32 << 30, epoch_packets=0, **opts):
+    def __init__(self, device=0, hbm_budget_bytes=32 << 30, epoch_packets=0, epoch_us=0, **opts):
         o = None
         if opts:
             o = Opts()
@@ -652,6 +658,8 @@ class Server:
         if device >= 0:
             _torch_device_init()
         self.h = smcrt_server_create(device, hbm_budget_bytes, epoch_packets, o)
+        if epoch_us:
+            smcrt_server_set_epoch_us(self.h, epoch_us)
         self._keep = {}
 
     def submit(self, scene, seed, n_packets, outputs=None):

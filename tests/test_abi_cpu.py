@@ -174,8 +174,8 @@ def test_server_dry_run_completes_in_arrival_order(S, W):
 
 
 def test_server_budget_admits_one_at_a_time_and_rejects_oversize(S, W):
-    big = _small_scene(S, W, 64)      # 64^3 doubles = 2 MiB grid, and 2 MiB of bricks in FP32
-    sv = S.Server(device=-1, hbm_budget_bytes=5 << 20, epoch_packets=100)
+    big = _small_scene(S, W, 64)      # 64^3 doubles = 2 MiB grid
+    sv = S.Server(device=-1, hbm_budget_bytes=3 << 20, epoch_packets=100)
     try:
         with pytest.raises(S.SmcrtError, match="budget"):
             sv.submit(_small_scene(S, W, 128), 1, 10)  # 16 MiB grid never fits
@@ -191,7 +191,7 @@ def test_server_budget_admits_one_at_a_time_and_rejects_oversize(S, W):
 
 def test_server_cancel_queued_request(S, W):
     big = _small_scene(S, W, 64)
-    sv = S.Server(device=-1, hbm_budget_bytes=5 << 20, epoch_packets=10)
+    sv = S.Server(device=-1, hbm_budget_bytes=3 << 20, epoch_packets=10)
     try:
         a = sv.submit(big, 1, 200000)[0]   # many epochs
         b = sv.submit(big, 2, 1000)[0]     # waits for the budget
@@ -207,28 +207,22 @@ def test_server_cancel_queued_request(S, W):
         sv.close()
 
 
-def test_server_footprint_counts_the_brick_grid(S, W):
-    # an FP32 SDF request on cubic voxels tallies into an engine-held grid of
-    # 2x2x2 bricks as large as its output grid: admission counts it.  FP64
-    # transport, the direct layout and flat voxels need no brick grid.
+def test_server_footprint_is_what_a_served_request_holds(S, W):
+    # served requests tally straight into their output grid (no brick grid,
+    # in either precision): a request needs its grid and tables, and FP32
+    # cubic voxels cost no more than FP64 ones
     G = 64 ** 3 * 8
     cubic = _small_scene(S, W, 64)
-    flat = S.Scene(dict(W.sphere_scene(n_grid=8), grid={"lo": [-1.0] * 3, "hi": [1.0] * 3, "dims": [64, 64, 32]}))
-    for opts, sc, fits in (({}, cubic, False), ({"precision": "f64"}, cubic, True),
-                           ({"tally_layout": 1}, cubic, True), ({}, flat, True)):
-        sv = S.Server(device=-1, hbm_budget_bytes=G + G // 2, epoch_packets=100, **opts)
+    for opts in ({}, {"precision": "f64"}, {"tally_layout": 1}):
+        sv = S.Server(device=-1, hbm_budget_bytes=G + G // 8, epoch_packets=100, **opts)
         try:
-            if fits:
-                sv.wait(sv.submit(sc, 1, 10)[0], 10.0)
-            else:
-                with pytest.raises(S.SmcrtError, match="budget"):
-                    sv.submit(sc, 1, 10)
+            sv.wait(sv.submit(cubic, 1, 10)[0], 10.0)
         finally:
             sv.close()
-    # with room for both grids the cubic FP32 request is admitted
-    sv = S.Server(device=-1, hbm_budget_bytes=2 * G + (1 << 20), epoch_packets=100)
+    sv = S.Server(device=-1, hbm_budget_bytes=G - 1, epoch_packets=100)
     try:
-        sv.wait(sv.submit(cubic, 1, 10)[0], 10.0)
+        with pytest.raises(S.SmcrtError, match="budget"):
+            sv.submit(cubic, 1, 10)
     finally:
         sv.close()
 

@@ -270,17 +270,48 @@ def test_served_requests_equal_runs_alone(S, W):
     eng.close()
 
 
+@pytest.mark.parametrize("prec,rtol", [("f64", 1e-11), ("f32", 1e-9)])
+def test_served_packets_resume_across_epochs(S, W, prec, rtol):
+    """Epochs of 300 us of device time: most packets are still in flight
+    when an epoch ends, are saved whole to device memory and resumed by the
+    next epoch, many times over.  Every request -- a vessel network (its
+    capsule records staged in LDS in FP32), the layered slab, the voxel
+    model, an isotropic sphere -- still ends with the packets, events and
+    tallies of its run alone."""
+    import torch
+    descs = [W.vessel_scene(6, 1.0, n_caps=400, n_grid=24), W.slab_scene(n_grid=24),
+             dict(W.cylinder_scene(n_grid=24), geometry="voxel"), W.scattering_sphere(10.0)]
+    ns = [20000, 30000, 20000, 40000]
+    sv = S.Server(0, hbm_budget_bytes=1 << 30, epoch_us=300, precision=prec)
+    reqs = [(d, n) + sv.submit(d, 700 + i, n) for i, (d, n) in enumerate(zip(descs, ns))]
+    for d, n, rid, out in reqs:
+        sv.wait(rid, 120.0)
+        assert sv.poll(rid)[0] == "DONE"
+    st = sv.stats()
+    print(f"{prec}: epochs {st['epochs']}, packets saved at epoch ends {st['saved_total']}")
+    assert st["epochs"] >= 5 and st["saved_total"] > sum(ns) // 10
+    assert st["packets_done"] == sum(ns) and st["in_flight"] == 0
+    torch.cuda.synchronize()
+    eng = S.Engine(0, tally_layout=1)
+    for i, (d, n, rid, out) in enumerate(reqs):
+        _close(out.host(), S.run(d, 700 + i, n, engine=eng, precision=prec), rtol)
+    sv.close()
+    eng.close()
+
+
 def test_cancel_running_request_leaves_others_intact(S, W):
     import time
     import torch
-    sv = S.Server(0, hbm_budget_bytes=1 << 30, epoch_packets=20000, precision="f64")
+    sv = S.Server(0, hbm_budget_bytes=1 << 30, precision="f64")
     d = W.sphere_scene(n_grid=16)
-    long_id, _ = sv.submit(d, 1, 5_000_000)
+    long_id, _ = sv.submit(d, 1, 500_000_000)   # some 10 s of device time
     short_id, short_out = sv.submit(d, 2, 30000)
     time.sleep(0.05)
+    t_cancel = time.perf_counter()
     sv.cancel(long_id)
     with pytest.raises(S.SmcrtError, match="cancelled"):
         sv.wait(long_id, 120.0)
+    assert time.perf_counter() - t_cancel < 1.0   # dropped at the end of an epoch, not run out
     sv.wait(short_id, 120.0)
     torch.cuda.synchronize()
     _close(short_out.host(), S.run(d, 2, 30000, engine=S.Engine(0), precision="f64"), 1e-11)
