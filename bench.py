@@ -41,13 +41,20 @@ COST = {
 }
 
 
-def slab_lane_ops(t, n_prims):
-    """lane-slots of one run from its own work counters"""
+def slab_lane_ops(t, n_prims, survey_interface=False):
+    """lane-slots of one run from its own work counters.  An interface step
+    is priced as the kernel runs it: its FP64 work, 14 SDF evaluations of
+    the nearest region (two central-difference normals of 6 each, the
+    distance at the snapped point and the probe), the nearest-region search
+    over all primitives and the Philox block of the Fresnel draw.
+    survey_interface: the coarser price 250 + P SDF instead."""
     sdf = COST["sdf_box"]
     per_step = COST["step_overhead"] + n_prims * sdf + COST["volume"]
     emit = COST["philox"] + COST["log"] + n_prims * sdf
     inter = COST["interaction"] + COST["philox"] + COST["log"]
     surf = COST["interface"] + COST["surface_sdfs"] * sdf + n_prims * sdf + COST["philox"]
+    if survey_interface:
+        surf = COST["interface"] + n_prims * sdf
     return (t["launched"] * emit + t["steps"] * per_step + t["interactions"] * inter
             + (t["interfaces"] + t["advances"]) * surf + t["voxel_pieces"] * COST["voxel"])
 
@@ -80,7 +87,7 @@ def measured_traffic():
     return measured_counters().get("traffic_bytes_per_launch")
 
 
-SERVE_GRIDS = (32, 64, 128)
+SERVE_GRIDS = (32, 64, 128, 256)
 
 
 def atomic_ceiling(key="requests_per_s"):
@@ -97,6 +104,68 @@ def atomic_ceiling(key="requests_per_s"):
     return None
 
 
+def prefix_error(smcrt, desc, seed, m, precision, geometry="sdf", engine=None, oracle_desc=None):
+    """Error of the GPU path against the FP64 oracle on the same packets:
+    packets [0, m) of `desc` under `seed` on both sides (the same walks, up to
+    rounding; oracle_desc: the oracle's scene when it differs, e.g. the plain
+    march for an over-relaxed walk), relative L2 of the fluence (and of the
+    escape image when the scene has one), relative difference of the
+    absorbed and escaped totals."""
+    import numpy as np
+
+    from oracle import oracle as orc
+    d = dict(desc, geometry=geometry)
+    eng = engine if engine is not None else smcrt.Engine(0, precision=precision)
+    g = smcrt.run(d, seed, m, engine=eng, precision=precision)
+    o = orc.run(dict(oracle_desc if oracle_desc is not None else desc, geometry=geometry), seed, m,
+                voxel=(geometry == "voxel"))
+    if engine is None:
+        eng.close()
+
+    def rel(a, b):
+        nb = float(np.linalg.norm(b))
+        return float(np.linalg.norm(a - b) / nb) if nb > 0 else float(np.linalg.norm(a))
+
+    res = {"packets": m,
+           "absorbed_relative": rel(g["absorbed"].sum(), o["absorbed"].sum()),
+           "escaped_relative": rel(g["escaped_face"].sum(), o["escaped_face"].sum())}
+    if g.get("fluence_raw") is not None and o.get("fluence_raw") is not None:
+        res["fluence_relative_l2"] = rel(g["fluence_raw"], o["fluence_raw"])
+    if "image" in g and "image" in o:
+        res["image_relative_l2"] = rel(g["image"], o["image"])
+    return res
+
+
+def trace_parity(smcrt, workloads, precision, n=4096, cap=50):
+    """Event-by-event agreement of the GPU walk with the oracle's on the
+    first n packets of the layered slab (first cap events): the fraction of
+    packets whose records all agree to 1e-5 (positions relative to the
+    scene's extent, directions, weights, remaining path) and the diverged
+    fraction (a record whose type, region or index differs)."""
+    import numpy as np
+
+    from oracle import oracle as orc
+    sys.path.insert(0, os.path.join(ROOT, "tests"))
+    from gpu_helpers import compare_traces, diverged_fraction, extent_of
+    desc = workloads.slab_scene(n_grid=16)
+    eng = smcrt.Engine(0, precision=precision)
+    g = smcrt.trace(desc, 31, list(range(n)), cap, engine=eng, precision=precision)
+    eng.close()
+    o = [orc.trace(desc, 31, pid, cap) for pid in range(n)]
+    mut = [rg["mua"] + rg["mus"] for rg in desc["regions"]]
+    frac, worst, _ = compare_traces(o, g, extent_of(smcrt, desc), 1e-5, cap=cap, mut=mut)
+    return {"workload": "layered slab", "packets": n, "events": cap, "agree_1e-5": frac,
+            "diverged_fraction": diverged_fraction(o, g, cap),
+            "worst": {k: float(v) for k, v in worst.items()}}
+
+
+SERVE_BUDGET = 8 << 30  # device bytes the served requests may hold at once (outputs, tables, grids)
+
+
+def progress(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
 def serving_capacity(smcrt, workloads, max_packets, precision, seed, n_requests=48):
     """Closed-loop capacity of the server on the request mix: a calibration
     stream (its own seed) submitted all at once; packets per second from
@@ -106,10 +175,10 @@ def serving_capacity(smcrt, workloads, max_packets, precision, seed, n_requests=
     scenes = [smcrt.Scene(r["scene"]) for r in reqs]
     outs = [smcrt.Outputs(sc) for sc in scenes]
     torch.cuda.synchronize()
-    sv = smcrt.Server(0, hbm_budget_bytes=16 << 30, epoch_packets=2_000_000, precision=precision)
+    sv = smcrt.Server(0, hbm_budget_bytes=SERVE_BUDGET, precision=precision)
     ids = [sv.submit(sc, r["seed"], r["n_packets"], outputs=o)[0] for r, sc, o in zip(reqs, scenes, outs)]
     for rid in ids:
-        sv.wait(rid, 600.0)
+        sv.wait(rid, 1200.0)
     polls = [sv.poll(rid) for rid in ids]
     sv.close()
     span = max(p[3] for p in polls) - min(p[1] for p in polls)
@@ -117,13 +186,14 @@ def serving_capacity(smcrt, workloads, max_packets, precision, seed, n_requests=
 
 
 def serving(smcrt, workloads, n_requests, rate_hz, max_packets, precision, seed=2112, load=0.7):
-    """Continuous-batching leg: a seeded Poisson stream of requests drawn
-    from the four scene families (randomised optical properties, grids 32^3
-    to 128^3, packets log-uniform from 1e4 to max_packets) submitted at
-    their arrival times to one server; latency = completion - submission.
-    Without a given rate, arrivals are set for the offered load `load`
-    (mean packets per request x rate / measured closed-loop capacity).
-    Three small check requests (2000 packets) ride in the stream and are
+    """Continuous-batching leg on the resident server: a seeded Poisson
+    stream of requests drawn from the four scene families (randomised
+    optical properties, grids 32^3 to 256^3, packets log-uniform from 1e4 to
+    max_packets) submitted at their arrival times to one server whose
+    budget (8 GiB) binds; latency = completion - submission.  Without a
+    given rate, arrivals are set for the offered load `load` (mean packets
+    per request x rate / measured closed-loop capacity).  Four check
+    requests (2000 packets, one per family) ride in the stream and are
     compared with the FP64 oracle on the same packets."""
     import math
 
@@ -133,28 +203,48 @@ def serving(smcrt, workloads, n_requests, rate_hz, max_packets, precision, seed=
     from oracle import oracle as orc
     mean_packets = (max_packets - 1e4) / math.log(max_packets / 1e4)  # log-uniform on [1e4, max]
     capacity = serving_capacity(smcrt, workloads, max_packets, precision, seed + 1)
+    progress(f"serving: closed-loop capacity {capacity:.3e} packets/s")
     if rate_hz <= 0:
         rate_hz = load * capacity / mean_packets
     reqs = workloads.request_stream(seed, n_requests, rate_hz, packets=(1e4, max_packets), grid_sides=SERVE_GRIDS)
-    checks = [workloads.sphere_scene(32), workloads.slab_scene(32), workloads.cylinder_scene(32)]
+    checks = [workloads.sphere_scene(32), workloads.slab_scene(32), workloads.cylinder_scene(32),
+              workloads.vessel_scene(3, 1.0, n_caps=2000, n_grid=32)]
     for i, d in enumerate(checks):
-        reqs.insert(1 + i * (len(reqs) // 3), {"id": -1 - i, "arrival": None, "scene": d, "seed": 77 + i, "n_packets": 2000})
+        reqs.insert(1 + i * (len(reqs) // len(checks)),
+                    {"id": -1 - i, "arrival": None, "scene": d, "seed": 77 + i, "n_packets": 2000})
     for i, r in enumerate(reqs):  # checks arrive with their neighbours
         if r["arrival"] is None:
             r["arrival"] = reqs[i - 1]["arrival"]
     scenes = [smcrt.Scene(r["scene"]) for r in reqs]
     outs = [smcrt.Outputs(sc) for sc in scenes]
     torch.cuda.synchronize()
-    sv = smcrt.Server(0, hbm_budget_bytes=16 << 30, epoch_packets=2_000_000, precision=precision)
+    sv = smcrt.Server(0, hbm_budget_bytes=SERVE_BUDGET, precision=precision)
     t0 = time.perf_counter()
     ids = []
+    peak_bytes, peak_queued, t_note = 0, 0, t0
     for r, sc, o in zip(reqs, scenes, outs):
-        delay = r["arrival"] - (time.perf_counter() - t0)
-        if delay > 0:
-            time.sleep(delay)
+        while True:
+            delay = r["arrival"] - (time.perf_counter() - t0)
+            if delay <= 0:
+                break
+            time.sleep(min(delay, 0.05))
+            st = sv.stats()
+            peak_bytes, peak_queued = max(peak_bytes, st["bytes_in_use"]), max(peak_queued, st["queued"])
         ids.append(sv.submit(sc, r["seed"], r["n_packets"], outputs=o)[0])
+        if time.perf_counter() - t_note > 30:
+            t_note = time.perf_counter()
+            progress(f"serving: {len(ids)} of {len(reqs)} requests submitted")
+    while True:
+        st = sv.stats()
+        peak_bytes, peak_queued = max(peak_bytes, st["bytes_in_use"]), max(peak_queued, st["queued"])
+        if st["queued"] == 0 and st["active"] == 0:
+            break
+        time.sleep(0.05)
+        if time.perf_counter() - t_note > 30:
+            t_note = time.perf_counter()
+            progress(f"serving: {st['queued']} queued, {st['active']} running")
     for rid in ids:
-        sv.wait(rid, 600.0)
+        sv.wait(rid, 1200.0)
     polls = [sv.poll(rid) for rid in ids]
     lat = np.array([p[3] - p[1] for p in polls])
     t_first = min(p[1] for p in polls)
@@ -167,7 +257,7 @@ def serving(smcrt, workloads, n_requests, rate_hz, max_packets, precision, seed=
             continue
         g = o.host()
         ro = orc.run(r["scene"], r["seed"], r["n_packets"])
-        errs.append({"family": r["scene"]["name"],
+        errs.append({"family": r["scene"]["name"], "packets": r["n_packets"],
                      "relative_l2": float(np.linalg.norm(g["fluence_raw"] - ro["fluence_raw"]) / np.linalg.norm(ro["fluence_raw"])),
                      "absorbed_relative": float(abs(g["absorbed"].sum() - ro["absorbed"].sum()) / ro["absorbed"].sum())})
     sv.close()
@@ -177,17 +267,23 @@ def serving(smcrt, workloads, n_requests, rate_hz, max_packets, precision, seed=
         "capacity_packets_per_s": capacity,
         "offered_load": rate_hz * mean_packets / capacity,
         "packets_range": [1e4, max_packets],
+        "grid_sides": list(SERVE_GRIDS),
+        "hbm_budget_bytes": SERVE_BUDGET,
+        "peak_bytes_in_use": peak_bytes,
+        "peak_queued": peak_queued,
         "p50_latency_s": float(np.percentile(lat, 50)),
         "p99_latency_s": float(np.percentile(lat, 99)),
         "aggregate_packets_per_s": total / (t_last - t_first),
         "packets": total,
         "epochs": st["epochs"],
+        "epoch_ms": 20.0,
+        "packets_saved_and_resumed": st["saved_total"],
         "device_busy_fraction": st["busy_s"] / max(t_last - t_first, 1e-9),
         "check_requests_vs_oracle": errs,
     }
 
 
-def comparator(smcrt, workloads, precision, n=10_000_000, seed=3):
+def comparator(smcrt, workloads, precision, n=100_000_000, seed=3):
     """Voxelised vs SDF geometry (the comparison of Sec. 3) on the curved
     vessel workload: a capped-cylinder vessel across a 1 cm tissue cube,
     top-hat beam, 256^3 FP64 grid.  Both models walk the same packets and
@@ -230,6 +326,8 @@ def comparator(smcrt, workloads, precision, n=10_000_000, seed=3):
         "fluence_relative_l2_sdf_seed_to_seed": rel_l2(Fr, Fs),
         "fluence_relative_l2_sdf_seed_to_seed_32cubed": rel_l2(coarse(Fr), coarse(Fs)),
         "absorbed_fraction": {k: [float(x) / n for x in outs[k]["absorbed"]] for k in outs},
+        "error_vs_oracle": {"sdf": prefix_error(smcrt, desc, seed, 20000, precision),
+                            "voxel": prefix_error(smcrt, desc, seed, 20000, precision, geometry="voxel")},
     })
     return res
 
@@ -268,7 +366,8 @@ def paper_speed_tests(smcrt, workloads, precision):
         ts, ns = timed(desc, 10_000_000, "sdf", False)
         tv, nv = timed(desc, 10_000_000, "voxel", False)
         sweep.append({"tau": tau, "sdf_s": ts, "voxel_s": tv, "sdf_over_voxel_speed": tv / ts,
-                      "mean_scatterings": ns, "eq4": tau * tau / 2 + tau})
+                      "mean_scatterings": ns, "eq4": tau * tau / 2 + tau,
+                      "error_vs_oracle": prefix_error(smcrt, desc, 1, 20000 if tau < 50 else 2000, precision)})
     slab = workloads.semi_infinite_slab(1.8, 82.0, half_xy=1.0, nz=400)
     slab = workloads.with_grid(slab, [200, 200, 400], lo=[-1.0, -1.0, -4.0], hi=[1.0, 1.0, 0.0])
     slab["source"] = {"kind": "rect", "c": [0.0, 0.0, 0.5 * slab["pad"]], "half": [1.0, 1.0], "u": [0.0, 0.0, -1.0]}
@@ -281,43 +380,92 @@ def paper_speed_tests(smcrt, workloads, precision):
         table2[name] = {"photons": n, "grid": g["grid"], "sdf_s": ts, "voxel_s": tv, "sdf_over_voxel_speed": tv / ts,
                         "paper_cpu_sdf_s": g["smcrt_s"], "paper_cpu_voxel_s": g["voxel_s"],
                         "paper_sdf_over_voxel_speed": g["voxel_s"] / g["smcrt_s"]}
+    table2["context_only"] = True  # the paper's CPU timings beside ours: not a row of this build's scope
     return {"tally_free_sphere": sweep, "table2": table2}
 
 
 def batching(smcrt, workloads, precision):
     """Batched persistent launches against the plain one-scene-per-launch
     walk on the same jobs (identical packets and results, so equal fluence
-    error): 64 copies of the small sphere case at its full 1e5 packets
-    (seeds differ), and 16 vessel-network scenes (2000 capsules, 128^3
-    grids, mu_s scaled 0.5-2x) at 2e5 packets each."""
+    error):
+    - the small sphere case at its full 1e5 packets, 64 times (seeds differ);
+    - the batched microvascular network at its stated size: 64 vessel
+      networks (2000 capsules through the uniform grid, 128^3 grids, mu_s
+      scaled 0.5-2x), 1e7 packets each, in ONE launch; one scene per launch
+      timed on 8 of them; the error against the oracle on 4 of the scenes
+      (2500 packets each, run as one batch)."""
+    import numpy as np
     import torch
+
+    from oracle import oracle as orc
     res = {}
-    cases = (("sphere_1e5_x64", [workloads.sphere_scene()] * 64, 100_000),
-             ("vessels_2e5_x16", workloads.vessel_batch(16, n_caps=2000, n_grid=128), 200_000))
-    for name, descs, n in cases:
-        eng = smcrt.Engine(0, precision=precision)
-        scenes = [smcrt.Scene(d) for d in descs]
-        seeds = list(range(len(scenes)))
-        ns = [n] * len(scenes)
-        smcrt.launch_batch(eng, scenes, seeds, [min(n, 20_000)] * len(scenes))  # warm-up
-        torch.cuda.synchronize()
-        outs = [smcrt.Outputs(sc) for sc in scenes]
-        torch.cuda.synchronize()
-        t = time.perf_counter()
-        smcrt.launch_batch(eng, scenes, seeds, ns, outputs=outs)
-        torch.cuda.synchronize()
-        t_batch = time.perf_counter() - t
-        outs = [smcrt.Outputs(sc) for sc in scenes]
-        torch.cuda.synchronize()
-        t = time.perf_counter()
-        for sc, sd, o in zip(scenes, seeds, outs):
-            smcrt.launch(eng, sc, sd, n, outputs=o)
-        torch.cuda.synchronize()
-        t_plain = time.perf_counter() - t
-        total = n * len(scenes)
-        res[name] = {"jobs": len(scenes), "packets_per_job": n, "batched_packets_per_s": total / t_batch,
-                     "one_per_launch_packets_per_s": total / t_plain, "speedup": t_plain / t_batch}
-        eng.close()
+    # small sphere x 64
+    descs, n = [workloads.sphere_scene()] * 64, 100_000
+    eng = smcrt.Engine(0, precision=precision)
+    scenes = [smcrt.Scene(d) for d in descs]
+    seeds = list(range(64))
+    smcrt.launch_batch(eng, scenes, seeds, [20_000] * 64)  # warm-up
+    outs = [smcrt.Outputs(sc) for sc in scenes]
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    smcrt.launch_batch(eng, scenes, seeds, [n] * 64, outputs=outs)
+    torch.cuda.synchronize()
+    t_batch = time.perf_counter() - t
+    outs = [smcrt.Outputs(sc) for sc in scenes]
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    for sc, sd, o in zip(scenes, seeds, outs):
+        smcrt.launch(eng, sc, sd, n, outputs=o)
+    torch.cuda.synchronize()
+    t_plain = time.perf_counter() - t
+    res["sphere_1e5_x64"] = {"jobs": 64, "packets_per_job": n, "batched_packets_per_s": 64 * n / t_batch,
+                             "one_per_launch_packets_per_s": 64 * n / t_plain, "speedup": t_plain / t_batch,
+                             "error_vs_oracle": prefix_error(smcrt, descs[0], 0, 20000, precision, engine=eng)}
+    eng.close()
+    del outs
+    # microvascular networks: 64 x 1e7
+    descs = workloads.vessel_batch(64, n_caps=2000, n_grid=128)
+    n = 10_000_000
+    eng = smcrt.Engine(0, precision=precision)
+    scenes = [smcrt.Scene(d) for d in descs]
+    seeds = [5000 + i for i in range(64)]
+    smcrt.launch_batch(eng, scenes, seeds, [20_000] * 64)  # warm-up (tables, grids, code)
+    outs = [smcrt.Outputs(sc) for sc in scenes]
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    smcrt.launch_batch(eng, scenes, seeds, [n] * 64, outputs=outs)
+    torch.cuda.synchronize()
+    t_batch = time.perf_counter() - t
+    hs = [o.host() for o in outs]
+    del outs
+    per = {k: sum(h[k] for h in hs) / (64 * n) for k in ("steps", "interactions", "interfaces", "voxel_pieces")}
+    identity = max(abs(h["absorbed"].sum() + h["escaped_face"].sum() + h["roulette_loss"] - h["roulette_gain"]
+                       + h["stalled"] - h["launched"]) / h["launched"] for h in hs)
+    outs = [smcrt.Outputs(sc) for sc in scenes[:8]]
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    for sc, sd, o in zip(scenes[:8], seeds[:8], outs):
+        smcrt.launch(eng, sc, sd, n, outputs=o)
+    torch.cuda.synchronize()
+    t_plain = time.perf_counter() - t
+    del outs
+    # error against the oracle: 4 scenes, packets [0, 2500) of their seeds, one batch
+    m = 2500
+    g = smcrt.run_batch(descs[:4], seeds[:4], [m] * 4, engine=eng, precision=precision)
+    errs = []
+    for d, sd, gi in zip(descs[:4], seeds[:4], g):
+        o = orc.run(d, sd, m)
+        errs.append({"packets": m,
+                     "fluence_relative_l2": float(np.linalg.norm(gi["fluence_raw"] - o["fluence_raw"])
+                                                  / np.linalg.norm(o["fluence_raw"])),
+                     "absorbed_relative": float(abs(gi["absorbed"].sum() - o["absorbed"].sum()) / o["absorbed"].sum())})
+    res["vessels_1e7_x64"] = {
+        "workload": "64 vessel networks (2000 capsules, radii 5-50 um, 2 mm cube), 128^3 grids, 1e7 packets each",
+        "jobs": 64, "packets_per_job": n, "batched_packets_per_s": 64 * n / t_batch, "batched_s": t_batch,
+        "one_per_launch_packets_per_s": 8 * n / t_plain, "one_per_launch_jobs_timed": 8,
+        "speedup": (64 * n / t_batch) / (8 * n / t_plain), "per_packet": per,
+        "energy_identity_residual_max": identity, "error_vs_oracle": errs, "launch": eng.opts()}
+    eng.close()
     return res
 
 
@@ -340,7 +488,8 @@ def csg_scenes(smcrt, workloads, precision, n=10_000_000):
         dt = time.perf_counter() - t
         h = out.host()
         res[name] = {"packets": n, "packets_per_s": n / dt, "steps_per_packet": h["steps"] / n,
-                     "interfaces_per_packet": h["interfaces"] / n, "interactions_per_packet": h["interactions"] / n}
+                     "interfaces_per_packet": h["interfaces"] / n, "interactions_per_packet": h["interactions"] / n,
+                     "error_vs_oracle": prefix_error(smcrt, desc, 1, 20000, precision, engine=eng)}
         eng.close()
     return res
 
@@ -370,6 +519,8 @@ def escape_images(smcrt, workloads, precision, n=10_000_000):
         res[name] = {"packets": n, "packets_per_s": n / dt,
                      "diffuse_reflectance": float(h["image"].sum()) / n,
                      "top_face_escape": float(h["escaped_face"][5]) / n}
+        if tally:
+            res[name]["error_vs_oracle"] = prefix_error(smcrt, slab, 1, 20000, precision, engine=eng)
         eng.close()
     return res
 
@@ -400,6 +551,10 @@ def relaxation(smcrt, workloads, precision, omega=1.9):
             eng.close()
         row["omega"] = omega
         row["speedup"] = row["relaxed"]["packets_per_s"] / row["plain"]["packets_per_s"]
+        # the relaxed walk against the oracle's plain march on the same packets
+        plain_desc = workloads.WORKLOADS[name](n_grid=n_grid)
+        row["error_vs_oracle"] = prefix_error(smcrt, dict(plain_desc, relax=omega), 1, 10000, precision,
+                                              oracle_desc=plain_desc)
         res[name] = row
     return res
 
@@ -478,6 +633,8 @@ def main():
     ap.add_argument("--serve-rate", type=float, default=0.0,
                     help="Poisson arrival rate of the serving leg (1/s); 0 = 70%% of the measured capacity")
     ap.add_argument("--serve-max-packets", type=float, default=1e6, help="largest request of the serving leg")
+    ap.add_argument("--serve-only", action="store_true",
+                    help="only run the serving leg and print its JSON line (for the full request stream)")
     ap.add_argument("--vessels", type=int, default=0,
                     help="only run the batched vessel networks: this many scenes, --packets per scene per step")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -494,6 +651,10 @@ def main():
 
     from paper_2112_08035_amd import smcrt, workloads
 
+    if args.serve_only:
+        print(json.dumps({"serving": serving(smcrt, workloads, args.serve_requests, args.serve_rate,
+                                             args.serve_max_packets, args.precision)}))
+        return
     if args.vessels > 0:
         vessel_profile(smcrt, workloads, args.vessels, int(args.packets), args.steps, args.warmup, args.precision)
         return
@@ -565,6 +726,8 @@ def main():
             "peak": PEAK_LANE_OPS / 1e12,
             "unit": "Tlane-op/s",
             "frac": achieved / PEAK_LANE_OPS,
+            "frac_survey_interface_price": slab_lane_ops(per, len(desc["prims"]), True) / (launch_ms * 1e-3)
+            / PEAK_LANE_OPS,
             "traffic": counters.get("traffic_bytes_per_launch"),
             "kernel_ms": launch_ms,
             "step_kernel_ms": step_ms,
@@ -609,13 +772,19 @@ def main():
             "relative_l2": float(np.linalg.norm(Fg - Fo) / np.linalg.norm(Fo)),
             "absorbed_relative": float(abs(g["absorbed"].sum() - o["absorbed"].sum()) / o["absorbed"].sum()),
         }
+        result["trace_parity"] = trace_parity(smcrt, workloads, args.precision)
+        progress("headline, oracle baseline and trace parity done")
     if not args.no_cpu and not args.no_comparator:
         result["voxel_comparator"] = comparator(smcrt, workloads, args.precision)
+        progress("voxel comparator done")
         result["paper_speed_tests"] = paper_speed_tests(smcrt, workloads, args.precision)
+        progress("paper speed tests done")
         result["csg_scenes"] = csg_scenes(smcrt, workloads, args.precision)
         result["batching"] = batching(smcrt, workloads, args.precision)
+        progress("batching done")
         result["escape_images"] = escape_images(smcrt, workloads, args.precision)
         result["relaxation"] = relaxation(smcrt, workloads, args.precision)
+        progress("escape images and relaxation done")
     if args.serve_requests > 0 and not args.no_cpu:
         result["serving"] = serving(smcrt, workloads, args.serve_requests, args.serve_rate,
                                     args.serve_max_packets, args.precision)
