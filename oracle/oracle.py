@@ -49,7 +49,8 @@ class Scene(C.Structure):
                 ("max_events", C.c_int64),
                 ("det_face", C.c_int32), ("det_dims", C.c_int32 * 2),
                 ("det_lo", C.c_double * 2), ("det_hi", C.c_double * 2),
-                ("relax", C.c_double), ("reuse", C.c_int32), ("skip", C.c_int32)]
+                ("relax", C.c_double), ("reuse", C.c_int32), ("skip", C.c_int32),
+                ("segment", C.c_int32), ("pad_segment", C.c_int32)]
 
 
 class Tallies(C.Structure):
@@ -110,6 +111,8 @@ def lib():
         L.orc_run_ex.restype = C.c_int
         L.orc_trace_voxel.argtypes = L.orc_trace.argtypes
         L.orc_trace_voxel.restype = C.c_int
+        L.orc_segment_bound.argtypes = [C.POINTER(Scene), C.c_int, dp, dp]
+        L.orc_segment_bound.restype = C.c_double
         _lib = L
     return _lib
 
@@ -359,6 +362,7 @@ class CScene:
         # shortcuts (used by tests that compare SDF evaluation counts)
         s.reuse = 1 if scene.get("reuse", False) else 0
         s.skip = 1 if scene.get("ambient_skip", False) else 0
+        s.segment = 1 if scene.get("segment", False) else 0
         det = scene.get("detector")
         if det:
             s.det_face = int(det["face"])
@@ -454,6 +458,12 @@ def smooth_union(a, b, k):
 def region_sdf(scene, r, p, _cache={}):
     cs = CScene(scene)
     return lib().orc_region_sdf(cs.ref, r, _d3(p))
+
+
+def segment_bound(scene, r, p, u):
+    """no surface of region r lies on the ray p + t u closer than this"""
+    cs = CScene(scene)
+    return lib().orc_segment_bound(cs.ref, r, _d3(p), _d3(u))
 
 
 def region_of(scene, p):

@@ -10,11 +10,12 @@
  *
  * walk_plain is the walk: the step loop of Sec. 2.3 and nothing else.  A
  * second walk, walk_mirror, takes the same steps through the shortcuts the
- * kernels take -- free-flight reuse, the ambient skip and over-relaxed
- * steps (Sec. 5) -- and runs only when a scene asks for one of them
- * (orc_scene.reuse, .skip, .relax > 1): pins compare its events and tallies
- * with walk_plain's, and tests that count SDF evaluations use its step
- * counts.  Every other comparison is against walk_plain.
+ * kernels take -- free-flight reuse, the ambient skip, over-relaxed steps
+ * and segment-traced steps (both named in Sec. 5) -- and runs only when a
+ * scene asks for one of them (orc_scene.reuse, .skip, .segment, .relax > 1):
+ * pins compare its events and tallies with walk_plain's, and tests that
+ * count SDF evaluations use its step counts.  Every other comparison is
+ * against walk_plain.
  *
  * Where the paper is silent the code follows the readings listed in the
  * repository's design notes; each such place says "reading:".
@@ -734,6 +735,129 @@ static double ambient_free(const orc_scene* s, const double p[3], const double u
   return t;
 }
 
+/* Segment tracing (Sec. 5 names it beside enhanced sphere tracing against
+ * the many small steps near surfaces).  Outside a convex shape the exact
+ * distance along a ray, f(t) = d(p + t u), is a convex function of t, so it
+ * never falls below its tangent: f(t) >= f(0) + f'(0) t.  The ray cannot
+ * reach the shape before t = f(0) / (-f'(0)), and never when f'(0) >= 0.
+ * f'(0) = grad d . u, and outside the shape grad d is the unit vector from
+ * the nearest surface point to p.  A union is reached when one of its
+ * members is, so the smallest member bound holds for it; an intersection
+ * only when every member is, so the largest bound of a member not yet
+ * reached holds; a subtraction (the first member less the others) lies
+ * inside its first member and is not reached before it.  The distance
+ * itself is a bound too, and the larger of two bounds holds.  Inside a
+ * region, and for smooth unions and every other shape, the bound is the
+ * distance alone. */
+
+/* whether a primitive is one of the convex shapes with exact distances,
+ * unplaced and unmodified */
+static int plain_convex(const orc_prim* pr) {
+  if (pr->flags != 0 || pr->round_r != 0.0 || pr->onion_t != 0.0 || pr->disp_a != 0.0 ||
+      pr->elong[0] != 0.0 || pr->elong[1] != 0.0 || pr->elong[2] != 0.0)
+    return 0;
+  return pr->kind == ORC_SPHERE || pr->kind == ORC_BOX || pr->kind == ORC_CAPSULE || pr->kind == ORC_CYLINDER;
+}
+
+/* outward unit gradient of the distance to a plain convex primitive at a
+ * point p outside it */
+static void convex_gradient(const orc_prim* pr, const double p[3], double g[3]) {
+  const double* q = pr->p;
+  double v[3] = {0.0, 0.0, 0.0};
+  switch (pr->kind) {
+    case ORC_SPHERE: /* from the centre */
+      for (int i = 0; i < 3; ++i) v[i] = p[i] - q[i];
+      break;
+    case ORC_BOX: /* from the nearest point of the box */
+      for (int i = 0; i < 3; ++i) {
+        double e = fabs(p[i] - q[i]) - q[3 + i];
+        v[i] = e > 0.0 ? (p[i] > q[i] ? e : -e) : 0.0;
+      }
+      break;
+    case ORC_CAPSULE: { /* from the nearest point of the axis segment */
+      double ba[3] = {q[3] - q[0], q[4] - q[1], q[5] - q[2]};
+      double pa[3] = {p[0] - q[0], p[1] - q[1], p[2] - q[2]};
+      double t = clampd(dot3(pa, ba) / dot3(ba, ba), 0.0, 1.0);
+      for (int i = 0; i < 3; ++i) v[i] = pa[i] - t * ba[i];
+      break;
+    }
+    case ORC_CYLINDER: { /* in the (radial, axial) half plane: from the nearest point of the rectangle */
+      double ba[3] = {q[3] - q[0], q[4] - q[1], q[5] - q[2]};
+      double L = len3(ba);
+      double e[3] = {ba[0] / L, ba[1] / L, ba[2] / L};
+      double pa[3] = {p[0] - q[0], p[1] - q[1], p[2] - q[2]};
+      double x = dot3(pa, e);
+      double radial[3] = {pa[0] - x * e[0], pa[1] - x * e[1], pa[2] - x * e[2]};
+      double rho = len3(radial);
+      double o1 = maxd(rho - q[6], 0.0), o2 = maxd(fabs(x - 0.5 * L) - 0.5 * L, 0.0);
+      double sa = x > 0.5 * L ? 1.0 : -1.0;
+      for (int i = 0; i < 3; ++i) v[i] = (rho > 0.0 ? o1 * radial[i] / rho : 0.0) + o2 * sa * e[i];
+      break;
+    }
+  }
+  double l = len3(v);
+  for (int i = 0; i < 3; ++i) g[i] = l > 0.0 ? v[i] / l : 0.0;
+}
+
+/* rounding slack of the directional derivative (FP64) */
+#define ORC_SEG_EPS 1e-12
+
+/* the tangent bound of a plain convex primitive at p, where its distance
+ * is a > 0 */
+static double convex_bound(const orc_prim* pr, const double p[3], const double u[3], double a) {
+  double g[3];
+  convex_gradient(pr, p, g);
+  const double slope = ORC_SEG_EPS - dot3(g, u); /* -f'(0), made no smaller by the slack */
+  return slope > 0.0 ? a / slope : ORC_INF;
+}
+
+double orc_segment_bound(const orc_scene* s, int r, const double p[3], const double u[3]) {
+  const double d = orc_region_sdf(s, r, p);
+  const orc_region* rg = &s->regions[r];
+  const orc_prim* pr = &s->prims[rg->first_prim];
+  if (d <= 0.0) return fabs(d);
+  double T = d;
+  switch (rg->op) {
+    case ORC_UNION: {
+      for (int i = 0; i < rg->n_prims; ++i)
+        if (!plain_convex(&pr[i])) return d;
+      double t = ORC_INF;
+      for (int i = 0; i < rg->n_prims; ++i) t = mind(t, convex_bound(&pr[i], p, u, shape_sdf(&pr[i], p)));
+      T = maxd(T, t);
+      break;
+    }
+    case ORC_INTERSECT:
+      for (int i = 0; i < rg->n_prims; ++i)
+        if (!plain_convex(&pr[i])) return d;
+      for (int i = 0; i < rg->n_prims; ++i) {
+        const double a = shape_sdf(&pr[i], p);
+        if (a > 0.0) T = maxd(T, convex_bound(&pr[i], p, u, a));
+      }
+      break;
+    case ORC_SUBTRACT:
+      if (plain_convex(pr)) {
+        const double a = shape_sdf(pr, p);
+        if (a > 0.0) T = maxd(T, convex_bound(pr, p, u, a));
+      }
+      break;
+    default:
+      break;
+  }
+  return T;
+}
+
+/* length of a segment-traced step from p: the smallest bound over the
+ * regions and the way out of the simulation volume (plus delta, so a ray
+ * that meets nothing leaves it), less delta; never shorter than d */
+static double segment_step(const orc_scene* s, const double p[3], const double u[3], double d) {
+  double T = ORC_INF;
+  for (int i = 0; i < 3; ++i)
+    if (u[i] != 0.0) T = mind(T, ((u[i] > 0.0 ? s->bb_hi[i] : s->bb_lo[i]) - p[i]) / u[i]);
+  T += s->delta;
+  for (int r = 0; r < s->n_regions; ++r) T = mind(T, orc_segment_bound(s, r, p, u));
+  return maxd(d, T - s->delta);
+}
+
 /* the over-relaxed step rule (see walk) */
 static int relaxed_step(const orc_scene* s, double dmin, double pd, double pl, double s_rem) {
   return s->relax > 1.0 && pd >= 0.0 &&
@@ -901,7 +1025,15 @@ static void walk_mirror(walker* wk, uint64_t seed, uint64_t pid) {
       double s_rem = mut > 0.0 ? pk.tau / mut : ORC_INF;
       double skip = 0.0;
       if (s->skip && pk.region < 0 && dmin >= s->delta) skip = ambient_skip(s, pk.p, pk.u, dmin, pd, pl, s_rem);
-      if (s_rem <= dmin) { /* the optical depth runs out first */
+      /* segment-traced step: the ray is free of surfaces for seg */
+      const double seg = s->segment && dmin >= s->delta ? segment_step(s, pk.p, pk.u, dmin) : dmin;
+      if (seg > dmin && s_rem <= seg && s_rem > dmin) {
+        /* the interaction point lies on the free segment: the one plain
+         * steps reach; no free ball about it is known */
+        move(wk, &pk, s_rem);
+        pk.tau = 0.0;
+        state = DO_INTERACT;
+      } else if (s_rem <= dmin) { /* the optical depth runs out first */
         move(wk, &pk, s_rem);
         pk.tau = 0.0;
         state = DO_INTERACT;
@@ -916,10 +1048,15 @@ static void walk_mirror(walker* wk, uint64_t seed, uint64_t pid) {
           steps = 0;
           pd = -1.0;
         }
-      } else if (skip > 0.0) {
+      } else if (skip > 0.0 && skip >= seg) {
         /* no surface along the skip: one move (the ambient medium has
          * mu_t = 0), and no previous step for the over-relaxation rule */
         move(wk, &pk, skip);
+        pd = -1.0;
+        pl = 0.0;
+      } else if (seg > dmin) { /* segment-traced step */
+        move(wk, &pk, seg);
+        pk.tau -= mut * seg;
         pd = -1.0;
         pl = 0.0;
       } else if (relaxed_step(s, dmin, pd, pl, s_rem)) {
@@ -950,7 +1087,7 @@ static void walk_mirror(walker* wk, uint64_t seed, uint64_t pid) {
 /* the plain walk unless the scene asks for the shortcuts */
 static void walk(walker* wk, uint64_t seed, uint64_t pid) {
   const orc_scene* s = wk->s;
-  if (s->reuse || s->skip || s->relax > 1.0) walk_mirror(wk, seed, pid);
+  if (s->reuse || s->skip || s->segment || s->relax > 1.0) walk_mirror(wk, seed, pid);
   else walk_plain(wk, seed, pid);
 }
 
@@ -960,6 +1097,7 @@ static int check_scene(const orc_scene* s) {
   if (!s || s->n_regions < 1 || s->n_prims < 1 || !s->prims || !s->regions) return -1;
   if (!(s->delta > 0.0) || s->m_survive < 1 || s->max_steps < 1) return -1;
   if (!(s->relax >= 1.0 && s->relax < 2.0)) return -1;
+  if (s->segment && s->relax > 1.0) return -1;
   for (int r = 0; r < s->n_regions; ++r) {
     const orc_region* rg = &s->regions[r];
     if (rg->first_prim < 0 || rg->n_prims < 1 || rg->first_prim + rg->n_prims > s->n_prims) return -1;

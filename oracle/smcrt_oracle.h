@@ -113,7 +113,17 @@ typedef struct {
   /* 1: ambient skip (outside every region, move to the first region box
    * the ray enters in one move) */
   int32_t skip;
+  /* 1: segment-traced steps (outside a region built of plain convex
+   * primitives, the ray is free up to the tangent bounds of its members);
+   * excludes relax > 1 */
+  int32_t segment;
+  int32_t pad_segment;
 } orc_scene;
+
+/* Segment bound of region r at p along the unit direction u (segment
+ * tracing): no surface of the region lies on the ray closer than the value
+ * returned.  Exposed for the pins. */
+double orc_segment_bound(const orc_scene* s, int r, const double p[3], const double u[3]);
 
 /* free-flight reuse: at most this many interactions per evaluation */
 #define ORC_REUSE_LINKS 32
