@@ -525,18 +525,27 @@ def escape_images(smcrt, workloads, precision, n=10_000_000):
     return res
 
 
-def relaxation(smcrt, workloads, precision, omega=1.9):
-    """Over-relaxed sphere tracing (Sec. 5) against plain steps on the same
-    packets: packets/s and sphere-tracing steps per packet of the layered
-    slab (200^3 grid, 2e6 packets), the vessel cylinder (256^3, 2e6), the
-    glass sphere and the bottle (64^3, 4e6 each)."""
+def step_shortcuts(smcrt, workloads, precision, omega=1.9):
+    """The two step shortcuts of Sec. 5 against plain steps on the same
+    packets -- over-relaxed sphere tracing (omega) and segment-traced steps
+    (tangent bounds of convex shapes) -- : packets/s and sphere-tracing
+    steps per packet of the layered slab (200^3 grid, 2e6 packets), the
+    vessel cylinder (256^3, 2e6), the glass sphere and the bottle (64^3, 4e6
+    each) and the 2000-capsule vessel network (128^3, 4e6); each shortcut's
+    walk against the oracle's plain march on 1e4 of the same packets."""
     import torch
     res = {}
-    for name, n_grid, n in (("slab", 200, 2_000_000), ("cylinder", 256, 2_000_000),
-                            ("glass_sphere", 64, 4_000_000), ("bottle", 64, 4_000_000)):
+    cases = (("slab", 200, 2_000_000), ("cylinder", 256, 2_000_000), ("glass_sphere", 64, 4_000_000),
+             ("bottle", 64, 4_000_000), ("vessels", 128, 4_000_000))
+    for name, n_grid, n in cases:
+        progress(f"step shortcuts: {name}")
+        if name == "vessels":
+            base = workloads.vessel_scene(3, 1.0, n_caps=2000, n_grid=n_grid)
+        else:
+            base = workloads.WORKLOADS[name](n_grid=n_grid)
         row = {"packets": n}
-        for mode, w in (("plain", 1.0), ("relaxed", omega)):
-            desc = dict(workloads.WORKLOADS[name](n_grid=n_grid), relax=w)
+        for mode, extra in (("plain", {}), ("relaxed", {"relax": omega}), ("segment", {"segment": True})):
+            desc = dict(base, **extra)
             eng = smcrt.Engine(0, precision=precision)
             sc = smcrt.Scene(desc)
             smcrt.launch(eng, sc, 77, min(n, 200_000), outputs=smcrt.Outputs(sc))  # warm-up
@@ -549,12 +558,12 @@ def relaxation(smcrt, workloads, precision, omega=1.9):
             h = out.host()
             row[mode] = {"packets_per_s": n / dt, "steps_per_packet": h["steps"] / n}
             eng.close()
+            if mode != "plain":
+                row[mode]["speedup"] = row[mode]["packets_per_s"] / row["plain"]["packets_per_s"]
+                # the shortcut's walk against the oracle's plain march on the same packets
+                row[mode]["error_vs_oracle"] = prefix_error(smcrt, desc, 1, 2000 if name == "vessels" else 10000,
+                                                            precision, oracle_desc=base)
         row["omega"] = omega
-        row["speedup"] = row["relaxed"]["packets_per_s"] / row["plain"]["packets_per_s"]
-        # the relaxed walk against the oracle's plain march on the same packets
-        plain_desc = workloads.WORKLOADS[name](n_grid=n_grid)
-        row["error_vs_oracle"] = prefix_error(smcrt, dict(plain_desc, relax=omega), 1, 10000, precision,
-                                              oracle_desc=plain_desc)
         res[name] = row
     return res
 
@@ -783,8 +792,8 @@ def main():
         result["batching"] = batching(smcrt, workloads, args.precision)
         progress("batching done")
         result["escape_images"] = escape_images(smcrt, workloads, args.precision)
-        result["relaxation"] = relaxation(smcrt, workloads, args.precision)
-        progress("escape images and relaxation done")
+        result["step_shortcuts"] = step_shortcuts(smcrt, workloads, args.precision)
+        progress("escape images and step shortcuts done")
     if args.serve_requests > 0 and not args.no_cpu:
         result["serving"] = serving(smcrt, workloads, args.serve_requests, args.serve_rate,
                                     args.serve_max_packets, args.precision)

@@ -214,6 +214,32 @@ smcrt_status smcrt_scene_set_primitive_repetition(smcrt_scene* scene, int32_t pr
  * range. */
 smcrt_status smcrt_scene_set_relaxation(smcrt_scene* scene, double omega);
 
+/* Segment-traced steps (Sec. 5 names segment tracing, beside enhanced
+ * sphere tracing, as a cure for the many small steps of paths along
+ * surfaces).  Outside a convex shape the exact distance along the ray is a
+ * convex function of the path length, so its tangent at the step's start
+ * bounds the way to the shape from below: distance / rate of approach, and
+ * no bound at all when the ray moves away.  With on = 1 every evaluation
+ * also bounds, per region, the way along the ray to its surface: from
+ * outside a union of plain spheres, boxes, capsules and capped cylinders
+ * the smallest member bound, from outside an intersection of them the
+ * largest, from outside a subtraction the bound of its first member when
+ * that is such a shape; from inside a region, and for every other region
+ * (smooth unions, tori), the distance alone.  A step then runs to the
+ * nearest bound less delta (or delta past the volume's boundary) when that
+ * is longer than the distance, and an interaction on that free way is taken
+ * there.  Each bound is taken less the rounding of a distance (16 units in
+ * the last place of the scene's largest coordinate), so no surface is
+ * crossed unseen.  Events, tallies and fluence are those of plain marching
+ * up to where in the delta band a surface is met, which moves interface
+ * points by O(delta^2 curvature), by O(delta) for rays that meet a surface
+ * at a grazing angle, and decides anew for rays that pass within delta of a
+ * surface without crossing it.  on in {0, 1}, default 0.  Errors:
+ * SMCRT_E_INVALID for another value or when the scene takes relaxed steps
+ * (omega > 1: the two exclude each other); at run time, for a scene with
+ * placed, modified or further primitives or the voxel geometry. */
+smcrt_status smcrt_scene_set_segment_tracing(smcrt_scene* scene, int32_t on);
+
 /* Uniform-grid acceleration of one union region (Sec. 5 proposes a
  * space-partitioning structure for large SDF collections).  The grid is the
  * box of the region's primitives grown by a margin of one cell, cut into

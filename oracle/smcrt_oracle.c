@@ -847,15 +847,15 @@ double orc_segment_bound(const orc_scene* s, int r, const double p[3], const dou
 }
 
 /* length of a segment-traced step from p: the smallest bound over the
- * regions and the way out of the simulation volume (plus delta, so a ray
- * that meets nothing leaves it), less delta; never shorter than d */
+ * regions less delta, or delta past the simulation volume's boundary when
+ * that comes first (so that a ray that meets nothing leaves); never
+ * shorter than d */
 static double segment_step(const orc_scene* s, const double p[3], const double u[3], double d) {
-  double T = ORC_INF;
+  double exit = ORC_INF, T = ORC_INF;
   for (int i = 0; i < 3; ++i)
-    if (u[i] != 0.0) T = mind(T, ((u[i] > 0.0 ? s->bb_hi[i] : s->bb_lo[i]) - p[i]) / u[i]);
-  T += s->delta;
+    if (u[i] != 0.0) exit = mind(exit, ((u[i] > 0.0 ? s->bb_hi[i] : s->bb_lo[i]) - p[i]) / u[i]);
   for (int r = 0; r < s->n_regions; ++r) T = mind(T, orc_segment_bound(s, r, p, u));
-  return maxd(d, T - s->delta);
+  return maxd(d, mind(T - s->delta, exit + s->delta));
 }
 
 /* the over-relaxed step rule (see walk) */

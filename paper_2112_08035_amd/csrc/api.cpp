@@ -72,6 +72,7 @@ struct HostRegion {
 struct smcrt_scene {
   double n_ambient = 1.0, delta = 1e-5, pad = 1e-4;
   double relax = 1.0;  // over-relaxation factor of sphere-tracing steps
+  bool segment = false;  // segment-traced steps
   std::vector<HostPrim> prims;
   std::vector<HostRegion> regions;
   bool has_source = false;
@@ -344,7 +345,19 @@ extern "C" smcrt_status smcrt_scene_set_primitive_repetition(smcrt_scene* s, int
 extern "C" smcrt_status smcrt_scene_set_relaxation(smcrt_scene* s, double omega) {
   if (!s) return fail(SMCRT_E_INVALID, "set_relaxation: NULL scene");
   if (!(omega >= 1.0 && omega < 2.0)) return fail(SMCRT_E_INVALID, "set_relaxation: omega must be in [1, 2)");
+  if (omega > 1.0 && s->segment)
+    return fail(SMCRT_E_INVALID, "set_relaxation: the scene takes segment-traced steps; relaxed steps exclude them");
   s->relax = omega;
+  s->dirty = true;
+  return SMCRT_OK;
+}
+
+extern "C" smcrt_status smcrt_scene_set_segment_tracing(smcrt_scene* s, int32_t on) {
+  if (!s) return fail(SMCRT_E_INVALID, "set_segment_tracing: NULL scene");
+  if (on != 0 && on != 1) return fail(SMCRT_E_INVALID, "set_segment_tracing: on must be 0 or 1");
+  if (on && s->relax > 1.0)
+    return fail(SMCRT_E_INVALID, "set_segment_tracing: the scene takes relaxed steps; segment-traced steps exclude them");
+  s->segment = on != 0;
   s->dirty = true;
   return SMCRT_OK;
 }
@@ -543,6 +556,12 @@ static void scene_bbox(const smcrt_scene* s, double lo[3], double hi[3], bool wi
   for (int i = 0; i < 3; ++i) { lo[i] -= pad; hi[i] += pad; }
 }
 
+// a primitive as given: one of the basic shapes, unplaced and unmodified
+static bool plain_shape(const HostPrim& hp) {
+  return hp.kind < kCone && !hp.placed && turn_k(hp) == 0.0 && hp.round_r == 0.0 && hp.onion_t == 0.0 &&
+         hp.disp_a == 0.0 && !repeated(hp) && hp.elong[0] == 0.0 && hp.elong[1] == 0.0 && hp.elong[2] == 0.0;
+}
+
 static smcrt_status check_complete(const smcrt_scene* s) {
   if (s->regions.empty()) return fail(SMCRT_E_INVALID, "scene has no region");
   if (!s->has_source) return fail(SMCRT_E_INVALID, "scene has no source");
@@ -556,7 +575,34 @@ static smcrt_status check_complete(const smcrt_scene* s) {
   for (size_t i = 0; i < s->prims.size(); ++i)
     if (repeated(s->prims[i]) && !(repetition_gap(s->prims[i]) > 0.0))
       return fail(SMCRT_E_INVALID, "primitive %d: repeated copies no longer fit their cells", (int)i);
+  if (s->segment && s->geometry != kGeomSdf)
+    return fail(SMCRT_E_INVALID, "segment-traced steps need the SDF geometry, not the voxel model");
+  if (s->segment)
+    for (size_t i = 0; i < s->prims.size(); ++i)
+      if (!plain_shape(s->prims[i]))
+        return fail(SMCRT_E_INVALID, "segment-traced steps: primitive %d is placed, modified or of a further shape", (int)i);
   return SMCRT_OK;
+}
+
+// the segment-tracing rule of a region (the rounding-free argument needs
+// exact distances of convex shapes): a union or intersection of plain
+// convex primitives, or a subtraction from a plain convex one
+static int seg_rule(const smcrt_scene* s, const HostRegion& r) {
+  auto convex = [&](int32_t id) {
+    const HostPrim& hp = s->prims[id];
+    return plain_shape(hp) && hp.kind != kTorus;
+  };
+  switch (r.op) {
+    case kUnion:
+    case kIntersect:
+      for (int32_t id : r.prims)
+        if (!convex(id)) return kSegNone;
+      return r.op == kUnion ? kSegUnion : kSegIntersect;
+    case kSubtract:
+      return convex(r.prims[0]) ? kSegSubtract : kSegNone;
+    default:
+      return kSegNone;
+  }
 }
 
 template <typename T>
@@ -787,6 +833,7 @@ static smcrt_status pack(smcrt_scene* s) {
   for (size_t r = 0; r < s->regions.size(); ++r) {
     const HostRegion& hr = s->regions[r];
     fill_region(h->reg[r], hr.mua, hr.mus, hr.g, hr.n, hr.k, hr.op, first, (int)hr.prims.size());
+    h->reg[r].seg = s->segment ? seg_rule(s, hr) : kSegNone;
     first += (int)hr.prims.size();
   }
   fill_region(h->reg[s->regions.size()], 0.0, 0.0, 0.0, s->n_ambient, 0.0, kUnion, 0, 0);
@@ -796,6 +843,7 @@ static smcrt_status pack(smcrt_scene* s) {
   h->relax_k = 2.0 - s->relax;
   h->relaxf = (float)s->relax;
   h->relax_kf = (float)h->relax_k;
+  h->segment = s->segment ? 1 : 0;
   h->h_normal = 1e-2 * s->delta;
   h->snap_cos = 0.1;
   h->offset = 2.0 * s->delta;
@@ -806,6 +854,19 @@ static smcrt_status pack(smcrt_scene* s) {
     h->bb_h[i] = 0.5 * (hi[i] - lo[i]);
     h->bb_cf[i] = (float)h->bb_c[i];
     h->bb_hf[i] = (float)h->bb_h[i];
+  }
+  {
+    // rounding of a distance: 16 units in the last place of the largest
+    // coordinate the computation meets (the volume's and the primitives')
+    double big = 0.0;
+    for (int i = 0; i < 3; ++i) big = std::max(big, std::fabs(h->bb_c[i]) + h->bb_h[i]);
+    for (const HostPrim& hp : s->prims) {
+      double a[3], b[3];
+      prim_box(hp, a, b);
+      for (int i = 0; i < 3; ++i) big = std::max(big, std::max(std::fabs(a[i]), std::fabs(b[i])));
+    }
+    h->seg_err = 16.0 * 0x1p-53 * big;
+    h->seg_errf = (float)(16.0 * 0x1p-24 * big);
   }
   for (size_t r = 0; r < s->regions.size(); ++r) {
     // the surface of a region lies in its primitives' boxes; a smooth union
@@ -969,8 +1030,11 @@ static bool brick_tally(const smcrt_opts& o, const SceneHeader* h) {
 // Launch class of a job (the kernel that runs it): its geometry model, plus
 // kLaunchXf for placed or modified primitives; FP32 SDF jobs whose
 // accelerated region is plain capsules that fit the LDS table run in the
-// staged-capsule kernel (not for traces, which run one packet per thread).
+// staged-capsule kernel (not for traces, which run one packet per thread);
+// scenes with segment-traced steps (plain SDF scenes: the packer checks) in
+// the segment kernel.
 static int job_class(const smcrt_opts& o, const SceneHeader* h, bool trace) {
+  if (h->segment) return kLaunchSegment;
   const int c = h->geometry + (h->xf ? kLaunchXf : 0);
   if (!trace && !o.no_stage && c == kGeomSdf && o.precision == SMCRT_PREC_F32 && h->acc.region >= 0 && h->acc.caps &&
       h->acc.n_prims <= kStageCaps)

@@ -27,8 +27,12 @@ enum Geometry : int32_t { kGeomSdf = 0, kGeomVoxel = 1 };
 // launch class of a job: its geometry model, plus kLaunchXf when its scene
 // has placed or modified primitives (a separate kernel instantiation);
 // kLaunchStaged: an FP32 SDF job whose accelerated region is plain capsules
-// that fit the workgroup's LDS table (the staged-capsule kernel)
-enum LaunchClass : int32_t { kLaunchXf = 2, kLaunchStaged = 4, kLaunchClasses = 5 };
+// that fit the workgroup's LDS table (the staged-capsule kernel);
+// kLaunchSegment: an SDF job with segment-traced steps
+enum LaunchClass : int32_t { kLaunchXf = 2, kLaunchStaged = 4, kLaunchSegment = 5, kLaunchClasses = 6 };
+// segment-tracing rule of a region: how the tangent bounds of its members
+// bound the way to its surface (none: the distance alone)
+enum SegRule : int32_t { kSegNone = 0, kSegUnion = 1, kSegIntersect = 2, kSegSubtract = 3 };
 
 // capsules an FP32 staged-capsule workgroup holds in LDS (two float4 each)
 constexpr int kStageCaps = 3072;
@@ -74,7 +78,9 @@ using PrimD = Prim<double>;
 using PrimF = Prim<float>;
 
 struct Region {
-  int32_t first, count, op, pad;  // primitive range (region order) and CSG op
+  int32_t first, count, op;       // primitive range (region order) and CSG op
+  int32_t seg;                    // SegRule: union or intersection of plain convex
+                                  // primitives, or a subtraction from one
   double k, inv_k;                // smooth-union radius
   double mua, mus, mut, inv_mut;  // inv_mut = 0 for the ambient slot
   double absorb;                  // mua / mut
@@ -129,7 +135,13 @@ struct SceneHeader {
   float deltaf, relaxf;
   // over-relaxed sphere tracing: factor omega and 2 - omega
   double relax, relax_k;
-  float relax_kf, pad1;
+  float relax_kf;
+  // segment-traced steps (kLaunchSegment jobs): a bound on the rounding of
+  // a primitive's distance, 16 units in the last place of the largest
+  // coordinate of the volume and the primitives
+  float seg_errf;
+  double seg_err;
+  int32_t segment, pad_seg;
   // ambient skip: a box holding each region's surface (the union of its
   // primitives' world boxes, grown by the smooth-union radius and half of
   // delta; the FP32 copy rounded outwards)

@@ -162,11 +162,16 @@ __device__ void surface(JobRef a, Packet<T>& pk, Lane& ln, LdsTallies& L) {
 // packets in flight, and resumes the jobs' saved packets before taking new
 // ids.  A separate instantiation: the save and resume paths cost registers
 // the plain walk does not spend.
-template <typename T, bool TRACE, int GEOM, bool XF, bool STAGE, bool EPOCH>
+//
+// SEG (kLaunchSegment jobs): every evaluation also bounds the way along the
+// ray to each region's surface (segment tracing), and a step runs to the
+// nearest such bound less delta when that is longer than the distance.
+template <typename T, bool TRACE, int GEOM, bool XF, bool STAGE, bool EPOCH, bool SEG>
 __global__ void __launch_bounds__(STAGE ? 1024 : 256) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 4 : 3)))
 walk_kernel(const WalkArgs* __restrict__ job_table, BatchArgs B) {
   static_assert(!STAGE || (sizeof(T) == 4 && GEOM == kGeomSdf && !XF && !TRACE), "staged capsules: FP32 SDF walks");
   static_assert(!EPOCH || !TRACE, "epochs are for runs, not traces");
+  static_assert(!SEG || (GEOM == kGeomSdf && !XF && !STAGE), "segment tracing: plain SDF walks");
   constexpr int kWaves = STAGE ? 16 : 4;
   const SMCRT_K WalkArgs* jobs = kptr(job_table);
   __shared__ LdsTallies Lw[kWaves];
@@ -361,8 +366,17 @@ walk_kernel(const WalkArgs* __restrict__ job_table, BatchArgs B) {
           live = false;
         } else {
           ++ln.n_steps;
-          T dmin = tinf<T>();
-          for (int r = 0; r < nr; ++r) dmin = tmin(dmin, tabs(region_dist<T, XF>(a, r, pk.p, caps_lds)));
+          T dmin = tinf<T>(), tseg = tinf<T>();
+          if constexpr (SEG) {
+            const T err = Tab<T>::seg_err(sc);
+            for (int r = 0; r < nr; ++r) {
+              T tb;
+              dmin = tmin(dmin, tabs(region_seg<T, XF>(a, r, pk.p, pk.u, err, &tb)));
+              tseg = tmin(tseg, tb);
+            }
+          } else {
+            for (int r = 0; r < nr; ++r) dmin = tmin(dmin, tabs(region_dist<T, XF>(a, r, pk.p, caps_lds)));
+          }
           int face;
           const bool outside = outside_volume<T>(sc, pk.p, &face);
           bool rejected = false;
@@ -390,6 +404,11 @@ walk_kernel(const WalkArgs* __restrict__ job_table, BatchArgs B) {
             live = false;
           } else {
             const T s = pk.mut > T(0) ? (T)(pk.tau * (double)pk.inv_mut) : tinf<T>();
+            // segment tracing: a step may run to the nearest bound along the
+            // ray less delta, or delta past the volume's boundary when that
+            // comes first
+            T seg = dmin;
+            if constexpr (SEG) seg = tmax(dmin, tmin(tseg - delta, volume_exit<T>(sc, pk.p, pk.u) + delta));
             if (s <= dmin) {  // the optical depth runs out before any surface
               advance(pk, s);
               pk.tau = 0.0;
@@ -400,6 +419,13 @@ walk_kernel(const WalkArgs* __restrict__ job_table, BatchArgs B) {
               }
             } else if (dmin < delta) {
               pk.state = kSurface;
+            } else if (SEG && seg > dmin && s <= seg) {
+              // segment tracing: the interaction point lies on the free
+              // segment ahead, where plain steps would reach it; no free
+              // ball about it is known
+              advance(pk, s);
+              pk.tau = 0.0;
+              pk.state = kInteract;
             } else {
               // a step of dmin, or an over-relaxed one of omega * dmin when it
               // would pass its check were the surface a plane met at the
@@ -419,13 +445,15 @@ walk_kernel(const WalkArgs* __restrict__ job_table, BatchArgs B) {
                 const T tf = ambient_free<T>(sc, nr, pk.p, pk.u, delta);
                 const T pmax = tmax(tabs(pk.p.x), tmax(tabs(pk.p.y), tabs(pk.p.z)));
                 const T ulp4 = sizeof(T) == 4 ? T(0x1p-21) : T(0x1p-50);
-                if (tf > len && T(0.5) * delta >= ulp4 * (pmax + tf)) {
+                if (tf > len && tf >= seg && T(0.5) * delta >= ulp4 * (pmax + tf)) {
                   len = tf;
                   skip = true;
                 }
               }
+              const bool segment = !skip && seg > len;
+              if (segment) len = seg;
               const T moved = step_along(pk, len);
-              pk.pd = skip ? T(-1) : dmin;
+              pk.pd = skip || segment ? T(-1) : dmin;
               pk.pl = rel && !skip ? -moved : moved;
             }
           }
@@ -496,17 +524,17 @@ __global__ void scale_kernel(const double* __restrict__ in, double* __restrict__
     out[i] = in[i] * s;
 }
 
-template <int GEOM, bool XF>
+template <int GEOM, bool XF, bool SEG = false>
 static void launch_geom(int precision, bool trace, dim3 grid, dim3 block, const BatchArgs& args, hipStream_t stream) {
   const bool epoch = args.deadline != 0;
   if (precision == 1) {
-    if (trace) hipLaunchKernelGGL((walk_kernel<double, true, GEOM, XF, false, false>), grid, block, 0, stream, args.jobs, args);
-    else if (epoch) hipLaunchKernelGGL((walk_kernel<double, false, GEOM, XF, false, true>), grid, block, 0, stream, args.jobs, args);
-    else hipLaunchKernelGGL((walk_kernel<double, false, GEOM, XF, false, false>), grid, block, 0, stream, args.jobs, args);
+    if (trace) hipLaunchKernelGGL((walk_kernel<double, true, GEOM, XF, false, false, SEG>), grid, block, 0, stream, args.jobs, args);
+    else if (epoch) hipLaunchKernelGGL((walk_kernel<double, false, GEOM, XF, false, true, SEG>), grid, block, 0, stream, args.jobs, args);
+    else hipLaunchKernelGGL((walk_kernel<double, false, GEOM, XF, false, false, SEG>), grid, block, 0, stream, args.jobs, args);
   } else {
-    if (trace) hipLaunchKernelGGL((walk_kernel<float, true, GEOM, XF, false, false>), grid, block, 0, stream, args.jobs, args);
-    else if (epoch) hipLaunchKernelGGL((walk_kernel<float, false, GEOM, XF, false, true>), grid, block, 0, stream, args.jobs, args);
-    else hipLaunchKernelGGL((walk_kernel<float, false, GEOM, XF, false, false>), grid, block, 0, stream, args.jobs, args);
+    if (trace) hipLaunchKernelGGL((walk_kernel<float, true, GEOM, XF, false, false, SEG>), grid, block, 0, stream, args.jobs, args);
+    else if (epoch) hipLaunchKernelGGL((walk_kernel<float, false, GEOM, XF, false, true, SEG>), grid, block, 0, stream, args.jobs, args);
+    else hipLaunchKernelGGL((walk_kernel<float, false, GEOM, XF, false, false, SEG>), grid, block, 0, stream, args.jobs, args);
   }
 }
 
@@ -520,10 +548,10 @@ hipError_t launch_walk(int precision, bool trace, const LaunchCfg& cfg, const Ba
     // FP32 staged-capsule walk: workgroups of 16 waves, no trace variant
     if (precision != 0 || trace || cfg.block != 1024 || cfg.grid < 1) return hipErrorInvalidConfiguration;
     if (args.deadline)
-      hipLaunchKernelGGL((walk_kernel<float, false, kGeomSdf, false, true, true>), dim3(cfg.grid), dim3(1024), 0, stream,
+      hipLaunchKernelGGL((walk_kernel<float, false, kGeomSdf, false, true, true, false>), dim3(cfg.grid), dim3(1024), 0, stream,
                          args.jobs, args);
     else
-      hipLaunchKernelGGL((walk_kernel<float, false, kGeomSdf, false, true, false>), dim3(cfg.grid), dim3(1024), 0, stream,
+      hipLaunchKernelGGL((walk_kernel<float, false, kGeomSdf, false, true, false, false>), dim3(cfg.grid), dim3(1024), 0, stream,
                          args.jobs, args);
     return hipGetLastError();
   }
@@ -533,6 +561,7 @@ hipError_t launch_walk(int precision, bool trace, const LaunchCfg& cfg, const Ba
     case kGeomSdf: launch_geom<kGeomSdf, false>(precision, trace, grid, block, args, stream); break;
     case kGeomVoxel: launch_geom<kGeomVoxel, false>(precision, trace, grid, block, args, stream); break;
     case kGeomSdf + kLaunchXf: launch_geom<kGeomSdf, true>(precision, trace, grid, block, args, stream); break;
+    case kLaunchSegment: launch_geom<kGeomSdf, false, true>(precision, trace, grid, block, args, stream); break;
     default: launch_geom<kGeomVoxel, true>(precision, trace, grid, block, args, stream); break;
   }
   return hipGetLastError();
@@ -589,11 +618,11 @@ hipError_t launch_scale(const double* in, double* out, size_t n, double scale, h
   return hipGetLastError();
 }
 
-template <int GEOM, bool XF>
+template <int GEOM, bool XF, bool SEG = false>
 static hipError_t occupancy(int* n, int precision, int block) {
   return precision == 1
-             ? hipOccupancyMaxActiveBlocksPerMultiprocessor(n, walk_kernel<double, false, GEOM, XF, false, false>, block, 0)
-             : hipOccupancyMaxActiveBlocksPerMultiprocessor(n, walk_kernel<float, false, GEOM, XF, false, false>, block, 0);
+             ? hipOccupancyMaxActiveBlocksPerMultiprocessor(n, walk_kernel<double, false, GEOM, XF, false, false, SEG>, block, 0)
+             : hipOccupancyMaxActiveBlocksPerMultiprocessor(n, walk_kernel<float, false, GEOM, XF, false, false, SEG>, block, 0);
 }
 
 int walk_max_blocks_per_cu(int precision, int block, int launch_class) {
@@ -601,13 +630,14 @@ int walk_max_blocks_per_cu(int precision, int block, int launch_class) {
   hipError_t e;
   if (launch_class == kLaunchStaged) {
     if (precision != 0 || block != 1024) return 0;
-    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, walk_kernel<float, false, kGeomSdf, false, true, false>, 1024, 0);
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, walk_kernel<float, false, kGeomSdf, false, true, false, false>, 1024, 0);
     return e == hipSuccess ? n : 0;
   }
   switch (launch_class) {
     case kGeomSdf: e = occupancy<kGeomSdf, false>(&n, precision, block); break;
     case kGeomVoxel: e = occupancy<kGeomVoxel, false>(&n, precision, block); break;
     case kGeomSdf + kLaunchXf: e = occupancy<kGeomSdf, true>(&n, precision, block); break;
+    case kLaunchSegment: e = occupancy<kGeomSdf, false, true>(&n, precision, block); break;
     default: e = occupancy<kGeomVoxel, true>(&n, precision, block); break;
   }
   return e == hipSuccess ? n : 0;

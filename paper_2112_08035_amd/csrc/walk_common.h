@@ -150,6 +150,9 @@ struct Tab<float> {
   static __device__ __forceinline__ V3<float> acc_blo(const SMCRT_K Accel& A) { return {A.box_lof[0], A.box_lof[1], A.box_lof[2]}; }
   static __device__ __forceinline__ V3<float> acc_bhi(const SMCRT_K Accel& A) { return {A.box_hif[0], A.box_hif[1], A.box_hif[2]}; }
   static __device__ __forceinline__ float acc_margin(const SMCRT_K Accel& A) { return A.marginf; }
+  static __device__ __forceinline__ float seg_err(ScP s) { return s->seg_errf; }
+  // slack of a rate of approach: a few units in the last place
+  static __device__ __forceinline__ float seg_eps() { return 0x1p-20f; }
 };
 template <>
 struct Tab<double> {
@@ -178,6 +181,8 @@ struct Tab<double> {
   static __device__ __forceinline__ V3<double> acc_blo(const SMCRT_K Accel& A) { return {A.box_lo[0], A.box_lo[1], A.box_lo[2]}; }
   static __device__ __forceinline__ V3<double> acc_bhi(const SMCRT_K Accel& A) { return {A.box_hi[0], A.box_hi[1], A.box_hi[2]}; }
   static __device__ __forceinline__ double acc_margin(const SMCRT_K Accel& A) { return A.margin; }
+  static __device__ __forceinline__ double seg_err(ScP s) { return s->seg_err; }
+  static __device__ __forceinline__ double seg_eps() { return 1e-12; }
 };
 
 // exact Euclidean SDF of one primitive's shape in its own frame (Sec. 2.2;
@@ -577,6 +582,185 @@ __device__ __forceinline__ T ambient_free(ScP sc, int nr, V3<T> p, V3<T> u, T de
     }
     if (hit && t0 <= t1) t = t0;
   }
+  return t;
+}
+
+// ---- segment tracing (Sec. 5 names it beside enhanced sphere tracing as a
+// cure for the many small steps of rays that run along surfaces).  Outside
+// a convex shape the exact distance along a ray, f(t) = d(p + t u), is a
+// convex function of t and never falls below its tangent f(0) - c t, where
+// c = -grad d . u is the rate at which the ray approaches the shape: the ray
+// cannot reach the shape before f(0) / c, nor ever when c <= 0.  A union is
+// reached when one member is (the smallest bound), an intersection only when
+// every member is (the largest bound), a subtraction not before its first
+// member.  Rounding: f(0) is taken less err, the scene's bound on the
+// rounding of a distance, and c more err / f(0) (the gradient is the
+// direction of a difference known to err) plus a few units in the last
+// place.
+
+// the length a ray runs before it can reach a convex shape at distance a
+// that it approaches at rate c: 0 when a is within the rounding (or c is not
+// a number), infinite when the ray moves away
+template <typename T>
+__device__ __forceinline__ T tangent_bound(T a, T c, T err) {
+  if (!(a > err)) return T(0);
+  const T den = c + tdiv(err, a) + Tab<T>::seg_eps();
+  if (den > T(0)) return tdiv(a - err, den);
+  return den <= T(0) ? tinf<T>() : T(0);
+}
+
+// distance of a plain convex primitive (sphere, box, capsule or capped
+// cylinder, unplaced and unmodified) at p, computed as shape_sdf computes
+// it, and in *c the rate at which the ray along u approaches it (from the
+// nearest surface point towards p; meaningful outside the shape)
+template <typename T>
+__device__ __forceinline__ T convex_sdf_rate(const SMCRT_K Prim<T>* P, int i, V3<T> p, V3<T> u, T* c) {
+  const int kind = P[i].kind;
+  const SMCRT_K T* v = P[i].v;
+  const V3<T> q = p - mk(v[0], v[1], v[2]);
+  if (kind == kSphere) {
+    const T l = tsqrt(dot(q, q));
+    *c = -tdiv(dot(q, u), l);
+    return l - v[3];
+  }
+  if (kind == kBox) {
+    const T ex = tabs(q.x) - v[3], ey = tabs(q.y) - v[4], ez = tabs(q.z) - v[5];
+    const V3<T> o = mk(tmax(ex, T(0)), tmax(ey, T(0)), tmax(ez, T(0)));
+    const T l = tsqrt(dot(o, o));
+    const V3<T> g = mk(q.x < T(0) ? -o.x : o.x, q.y < T(0) ? -o.y : o.y, q.z < T(0) ? -o.z : o.z);
+    *c = -tdiv(dot(g, u), l);
+    return l + tmin(tmax(ex, tmax(ey, ez)), T(0));
+  }
+  const V3<T> e = mk(v[3], v[4], v[5]);
+  if (kind == kCapsule) {
+    const T t = tclamp(dot(q, e) * v[6], T(0), T(1));
+    const V3<T> d = q - t * e;
+    const T l = tsqrt(dot(d, d));
+    *c = -tdiv(dot(d, u), l);
+    return l - v[7];
+  }
+  // capped cylinder, in the half plane of (radial, axial) coordinates
+  const T x = dot(q, e);
+  const V3<T> rad = q - x * e;
+  const T rho = tsqrt(dot(rad, rad));
+  const T q1 = rho - v[8];
+  const T q2 = tabs(x - v[7]) - v[7];
+  const T o1 = tmax(q1, T(0)), o2 = tmax(q2, T(0));
+  const T l = tsqrt(o1 * o1 + o2 * o2);
+  const T kr = o1 > T(0) ? tdiv(o1, rho) : T(0);
+  const T ka = x > v[7] ? o2 : -o2;
+  *c = -tdiv(kr * dot(rad, u) + ka * dot(e, u), l);
+  return tmin(tmax(q1, q2), T(0)) + l;
+}
+
+// the accelerated region's distance (accel_sdf's value) and in *tb the
+// way along u to its surface: inside the grid, the capsules listed in p's
+// cell bound it by their tangents, and every other primitive lies farther
+// than the margin; outside the grid (and for regions without a rule) the
+// distance alone
+template <typename T, bool XF>
+__device__ __forceinline__ T accel_seg(JobRef a, V3<T> p, V3<T> u, T err, T* tb) {
+  const SMCRT_K Accel& A = kptr(a.sc)->acc;
+  const int rule = kptr(a.sc)->reg[A.region].seg;
+  const V3<T> lo = Tab<T>::acc_lo(A), ic = Tab<T>::acc_inv(A);
+  const T cx = (p.x - lo.x) * ic.x, cy = (p.y - lo.y) * ic.y, cz = (p.z - lo.z) * ic.z;
+  const int dx = A.dims[0], dy = A.dims[1], dz = A.dims[2];
+  if (rule != kSegUnion || !(cx >= T(0) && cy >= T(0) && cz >= T(0) && cx < T(dx) && cy < T(dy) && cz < T(dz))) {
+    const T d = accel_sdf<T, XF>(a, p);
+    *tb = tabs(d);
+    return d;
+  }
+  int ix = (int)cx, iy = (int)cy, iz = (int)cz;
+  ix = ix < dx ? ix : dx - 1;
+  iy = iy < dy ? iy : dy - 1;
+  iz = iz < dz ? iz : dz - 1;
+  const int cell = ix + dx * (iy + dy * iz);
+  const SMCRT_K uint32_t* offs = kptr(a.acc_offsets);
+  const SMCRT_K uint32_t* ids = kptr(a.acc_ids);
+  const uint32_t b = offs[cell];
+  uint64_t e = offs[cell + 1];
+  e = e < A.capacity ? e : A.capacity;
+  const uint32_t lo_id = (uint32_t)A.first_prim, hi_id = (uint32_t)(A.first_prim + A.n_prims);
+  T d = Tab<T>::acc_margin(A), t = d;
+  if (A.caps) {
+    const SMCRT_K T* C = Tab<T>::caps(a);
+    for (uint64_t i = b; i < e; ++i) {
+      const uint32_t id = ids[i];
+      if (id >= lo_id && id < hi_id) {
+        const SMCRT_K T* r = C + 8 * (size_t)(id - lo_id);
+        const V3<T> q = p - mk(r[0], r[1], r[2]);
+        const V3<T> ax = mk(r[3], r[4], r[5]);
+        const T s = tclamp(dot(q, ax) * r[6], T(0), T(1));
+        const V3<T> w = q - s * ax;
+        const T l = tsqrt(dot(w, w));
+        const T di = l - r[7];
+        d = tmin(d, di);
+        t = tmin(t, tangent_bound<T>(di, -tdiv(dot(w, u), l), err));
+      }
+    }
+  } else {
+    const SMCRT_K Prim<T>* P = Tab<T>::prims(a);
+    for (uint64_t i = b; i < e; ++i) {
+      const uint32_t id = ids[i];
+      if (id >= lo_id && id < hi_id) {
+        T c;
+        const T di = convex_sdf_rate<T>(P, (int)id, p, u, &c);
+        d = tmin(d, di);
+        t = tmin(t, tangent_bound<T>(di, c, err));
+      }
+    }
+  }
+  *tb = d > T(0) ? tmax(d, t) : tabs(d);
+  return d;
+}
+
+// distance of region r at p (region_dist's value) and in *tb a length the
+// ray along u runs before it can meet the region's surface: from outside a
+// region with a rule, the tangent bounds of its members; else the
+// distance's magnitude
+template <typename T, bool XF>
+__device__ __forceinline__ T region_seg(JobRef a, int r, V3<T> p, V3<T> u, T err, T* tb) {
+  if (r == a.acc_region) return accel_seg<T, XF>(a, p, u, err, tb);
+  const SMCRT_K Region& R = kptr(a.sc)->reg[r];
+  const int rule = R.seg;  // wave uniform
+  if (rule == kSegNone) {
+    const T d = region_sdf<T, XF>(a, R, p);
+    *tb = tabs(d);
+    return d;
+  }
+  const SMCRT_K Prim<T>* P = Tab<T>::prims(a);
+  T c;
+  T d = convex_sdf_rate<T>(P, R.first, p, u, &c);
+  T t = tangent_bound<T>(d, c, err);
+  if (rule == kSegSubtract) {
+    for (int i = 1; i < R.count; ++i) d = tmax(d, -prim_sdf<T, XF>(P, R.first + i, p));
+  } else {
+    for (int i = 1; i < R.count; ++i) {
+      const T di = convex_sdf_rate<T>(P, R.first + i, p, u, &c);
+      const T ti = tangent_bound<T>(di, c, err);
+      if (rule == kSegUnion) {
+        d = tmin(d, di);
+        t = tmin(t, ti);
+      } else {
+        d = tmax(d, di);
+        t = tmax(t, ti);
+      }
+    }
+  }
+  *tb = d > T(0) ? tmax(d, t) : tabs(d);
+  return d;
+}
+
+// the way along u out of the simulation volume
+template <typename T>
+__device__ __forceinline__ T volume_exit(ScP sc, V3<T> p, V3<T> u) {
+  const V3<T> c = Tab<T>::bb_c(sc), h = Tab<T>::bb_h(sc);
+  const T pv[3] = {p.x, p.y, p.z}, uv[3] = {u.x, u.y, u.z};
+  const T cv[3] = {c.x, c.y, c.z}, hv[3] = {h.x, h.y, h.z};
+  T t = tinf<T>();
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+    if (uv[i] != T(0)) t = tmin(t, tdiv((uv[i] > T(0) ? cv[i] + hv[i] : cv[i] - hv[i]) - pv[i], uv[i]));
   return t;
 }
 

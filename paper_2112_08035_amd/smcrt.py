@@ -86,6 +86,7 @@ _SIGS = {
     "smcrt_scene_set_roulette": ([_vp, C.c_double, C.c_int32], C.c_int),
     "smcrt_scene_set_limits": ([_vp, C.c_int32, C.c_int64], C.c_int),
     "smcrt_scene_set_relaxation": ([_vp, C.c_double], C.c_int),
+    "smcrt_scene_set_segment_tracing": ([_vp, C.c_int32], C.c_int),
     "smcrt_scene_set_primitive_placement": ([_vp, C.c_int32, _dp, C.c_double, _dp], C.c_int),
     "smcrt_scene_set_primitive_modifiers": ([_vp, C.c_int32, C.c_double, C.c_double, C.c_double], C.c_int),
     "smcrt_scene_set_primitive_elongation": ([_vp, C.c_int32, _dp], C.c_int),
@@ -223,6 +224,10 @@ def smcrt_scene_set_limits(scene, max_steps, max_events):
 
 def smcrt_scene_set_relaxation(scene, omega):
     _check(lib().smcrt_scene_set_relaxation(scene, omega))
+
+
+def smcrt_scene_set_segment_tracing(scene, on):
+    _check(lib().smcrt_scene_set_segment_tracing(scene, int(on)))
 
 
 def smcrt_scene_set_accel(scene, region, cells):
@@ -424,7 +429,9 @@ class Scene:
         ro = desc["roulette"]
         smcrt_scene_set_roulette(self.h, ro["w_threshold"], ro["m"])
         smcrt_scene_set_limits(self.h, desc["max_steps"], desc["max_events"])
+        smcrt_scene_set_segment_tracing(self.h, 0)
         smcrt_scene_set_relaxation(self.h, float(desc.get("relax", 1.0)))
+        smcrt_scene_set_segment_tracing(self.h, bool(desc.get("segment", False)))
         if desc.get("accel_cells"):
             # accelerate the union region with the most primitives
             counts = [len(rg["prims"]) if rg["op"] == "union" else 0 for rg in desc["regions"]]

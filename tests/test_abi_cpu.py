@@ -352,3 +352,34 @@ def test_elongation_displacement_repetition_validation(S):
         S.smcrt_scene_set_primitive_repetition(h, p, [1.0, 1, 1], [3, 1, 1])
     finally:
         S.smcrt_scene_destroy(h)
+
+
+def test_segment_tracing_validation(S, W):
+    h = S.smcrt_scene_create(1.0, 1e-5, 1e-4)
+    try:
+        with pytest.raises(S.SmcrtError, match="0 or 1"):
+            S.smcrt_scene_set_segment_tracing(h, 2)
+        # relaxed and segment-traced steps exclude each other, in either order
+        S.smcrt_scene_set_relaxation(h, 1.5)
+        with pytest.raises(S.SmcrtError, match="relaxed steps"):
+            S.smcrt_scene_set_segment_tracing(h, 1)
+        S.smcrt_scene_set_relaxation(h, 1.0)
+        S.smcrt_scene_set_segment_tracing(h, 1)
+        with pytest.raises(S.SmcrtError, match="segment-traced steps"):
+            S.smcrt_scene_set_relaxation(h, 1.5)
+        S.smcrt_scene_set_segment_tracing(h, 0)
+        S.smcrt_scene_set_relaxation(h, 1.5)
+    finally:
+        S.smcrt_scene_destroy(h)
+    sv = S.Server(device=-1, hbm_budget_bytes=1 << 30, epoch_packets=100)
+    try:
+        # placed or modified primitives and the voxel model: rejected when packed
+        with pytest.raises(S.SmcrtError, match="placed, modified"):
+            sv.submit(S.Scene(dict(W.gallery_scene(n_grid=16), segment=True)), 1, 10)
+        with pytest.raises(S.SmcrtError, match="voxel model"):
+            sv.submit(S.Scene(dict(W.sphere_scene(n_grid=16), geometry="voxel", segment=True)), 1, 10)
+        for name in ("glass_sphere", "bottle", "cylinder"):
+            rid = sv.submit(S.Scene(dict(W.WORKLOADS[name](n_grid=16), segment=True)), 1, 10)[0]
+            sv.wait(rid, 10.0)
+    finally:
+        sv.close()
