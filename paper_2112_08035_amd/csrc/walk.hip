@@ -220,11 +220,19 @@ walk_kernel(const WalkArgs* __restrict__ job_table, BatchArgs B) {
   int iter = 0;
   if constexpr (EPOCH && !STAGE) t0 = __builtin_amdgcn_s_memrealtime();
 
+  // First jobs, XCD-aware: workgroups go to the 8 XCDs in turn (block b to
+  // XCD b mod 8), and each XCD has its own L2.  The jobs are split into 8
+  // runs of consecutive jobs, one per XCD, and every workgroup of an XCD
+  // starts at the first job of its run; a job that runs out sends its
+  // workgroups on to the next one (pick_job scans forward).  So an XCD's L2
+  // holds the grid lists and tables of about one job at a time instead of
+  // a slice of every job's.
+  const int first_job = (int)(((long)(blockIdx.x & 7) * B.n_jobs) / 8);
   int cur = 0;
   if constexpr (STAGE) {
-    // the workgroup's first job (spread over the jobs in proportion), then its table
+    // the workgroup's first job, then its table
     if (wib == 0) {
-      const int j = pick_job(jobs, B, (int)(((long)blockIdx.x * B.n_jobs) / gridDim.x));
+      const int j = pick_job(jobs, B, first_job);
       if (lane == 0) {
         *wg_job = j;
         *wg_t0 = __builtin_amdgcn_s_memrealtime();
@@ -237,10 +245,7 @@ walk_kernel(const WalkArgs* __restrict__ job_table, BatchArgs B) {
     if (!stage_caps(jobs[cur], caps_fill)) caps_lds = nullptr;
     __syncthreads();
   } else if constexpr (!TRACE) {
-    const int waves_per_block = blockDim.x >> 6;
-    const long gw = (long)blockIdx.x * waves_per_block + wib;
-    const long tw = (long)gridDim.x * waves_per_block;
-    cur = pick_job(jobs, B, (int)((gw * B.n_jobs) / tw));
+    cur = pick_job(jobs, B, first_job);
     if (cur < 0) return;
   }
   Packet<T> pk;
@@ -408,7 +413,9 @@ walk_kernel(const WalkArgs* __restrict__ job_table, BatchArgs B) {
             // ray less delta, or delta past the volume's boundary when that
             // comes first
             T seg = dmin;
-            if constexpr (SEG) seg = tmax(dmin, tmin(tseg - delta, volume_exit<T>(sc, pk.p, pk.u) + delta));
+            if constexpr (SEG) {
+              if (tseg - delta > dmin) seg = tmax(dmin, tmin(tseg - delta, volume_exit<T>(sc, pk.p, pk.u) + delta));
+            }
             if (s <= dmin) {  // the optical depth runs out before any surface
               advance(pk, s);
               pk.tau = 0.0;

@@ -599,58 +599,61 @@ __device__ __forceinline__ T ambient_free(ScP sc, int nr, V3<T> p, V3<T> u, T de
 // place.
 
 // the length a ray runs before it can reach a convex shape at distance a
-// that it approaches at rate c: 0 when a is within the rounding (or c is not
-// a number), infinite when the ray moves away
+// that it approaches at rate c = -dv / l (dv = v . u for a vector v of
+// length l > 0 from the nearest surface point towards p), with the rounding
+// slack: (a - err) / (c + err / a + eps), taken as l a (a - err) / (l (err
+// + eps a) - a dv), one division.  0 when a is within the rounding (or the
+// rate is not a number), infinite when the ray moves away.
 template <typename T>
-__device__ __forceinline__ T tangent_bound(T a, T c, T err) {
+__device__ __forceinline__ T tangent_bound(T a, T dv, T l, T err) {
   if (!(a > err)) return T(0);
-  const T den = c + tdiv(err, a) + Tab<T>::seg_eps();
-  if (den > T(0)) return tdiv(a - err, den);
+  const T den = l * (err + Tab<T>::seg_eps() * a) - a * dv;
+  if (den > T(0)) return tdiv(l * a * (a - err), den);
   return den <= T(0) ? tinf<T>() : T(0);
 }
 
 // distance of a plain convex primitive (sphere, box, capsule or capped
 // cylinder, unplaced and unmodified) at p, computed as shape_sdf computes
-// it, and in *c the rate at which the ray along u approaches it (from the
-// nearest surface point towards p; meaningful outside the shape)
+// it, and the ray's rate of approach to it as -(*dv) / (*l): v points from
+// the nearest surface point towards p (meaningful outside the shape)
 template <typename T>
-__device__ __forceinline__ T convex_sdf_rate(const SMCRT_K Prim<T>* P, int i, V3<T> p, V3<T> u, T* c) {
+__device__ __forceinline__ T convex_sdf_rate(const SMCRT_K Prim<T>* P, int i, V3<T> p, V3<T> u, T* dv, T* l) {
   const int kind = P[i].kind;
   const SMCRT_K T* v = P[i].v;
   const V3<T> q = p - mk(v[0], v[1], v[2]);
   if (kind == kSphere) {
-    const T l = tsqrt(dot(q, q));
-    *c = -tdiv(dot(q, u), l);
-    return l - v[3];
+    *l = tsqrt(dot(q, q));
+    *dv = dot(q, u);
+    return *l - v[3];
   }
   if (kind == kBox) {
     const T ex = tabs(q.x) - v[3], ey = tabs(q.y) - v[4], ez = tabs(q.z) - v[5];
     const V3<T> o = mk(tmax(ex, T(0)), tmax(ey, T(0)), tmax(ez, T(0)));
-    const T l = tsqrt(dot(o, o));
-    const V3<T> g = mk(q.x < T(0) ? -o.x : o.x, q.y < T(0) ? -o.y : o.y, q.z < T(0) ? -o.z : o.z);
-    *c = -tdiv(dot(g, u), l);
-    return l + tmin(tmax(ex, tmax(ey, ez)), T(0));
+    *l = tsqrt(dot(o, o));
+    *dv = (q.x < T(0) ? -o.x : o.x) * u.x + (q.y < T(0) ? -o.y : o.y) * u.y + (q.z < T(0) ? -o.z : o.z) * u.z;
+    return *l + tmin(tmax(ex, tmax(ey, ez)), T(0));
   }
   const V3<T> e = mk(v[3], v[4], v[5]);
   if (kind == kCapsule) {
     const T t = tclamp(dot(q, e) * v[6], T(0), T(1));
     const V3<T> d = q - t * e;
-    const T l = tsqrt(dot(d, d));
-    *c = -tdiv(dot(d, u), l);
-    return l - v[7];
+    *l = tsqrt(dot(d, d));
+    *dv = dot(d, u);
+    return *l - v[7];
   }
-  // capped cylinder, in the half plane of (radial, axial) coordinates
+  // capped cylinder, in the half plane of (radial, axial) coordinates: v =
+  // o1 rad / rho +/- o2 e, scaled by rho when o1 > 0
   const T x = dot(q, e);
   const V3<T> rad = q - x * e;
   const T rho = tsqrt(dot(rad, rad));
   const T q1 = rho - v[8];
   const T q2 = tabs(x - v[7]) - v[7];
   const T o1 = tmax(q1, T(0)), o2 = tmax(q2, T(0));
-  const T l = tsqrt(o1 * o1 + o2 * o2);
-  const T kr = o1 > T(0) ? tdiv(o1, rho) : T(0);
-  const T ka = x > v[7] ? o2 : -o2;
-  *c = -tdiv(kr * dot(rad, u) + ka * dot(e, u), l);
-  return tmin(tmax(q1, q2), T(0)) + l;
+  const T len = tsqrt(o1 * o1 + o2 * o2);
+  const T sc = o1 > T(0) ? rho : T(1);
+  *l = sc * len;
+  *dv = o1 * dot(rad, u) + (x > v[7] ? o2 : -o2) * sc * dot(e, u);
+  return tmin(tmax(q1, q2), T(0)) + len;
 }
 
 // the accelerated region's distance (accel_sdf's value) and in *tb the
@@ -695,7 +698,7 @@ __device__ __forceinline__ T accel_seg(JobRef a, V3<T> p, V3<T> u, T err, T* tb)
         const T l = tsqrt(dot(w, w));
         const T di = l - r[7];
         d = tmin(d, di);
-        t = tmin(t, tangent_bound<T>(di, -tdiv(dot(w, u), l), err));
+        t = tmin(t, tangent_bound<T>(di, dot(w, u), l, err));
       }
     }
   } else {
@@ -703,10 +706,10 @@ __device__ __forceinline__ T accel_seg(JobRef a, V3<T> p, V3<T> u, T err, T* tb)
     for (uint64_t i = b; i < e; ++i) {
       const uint32_t id = ids[i];
       if (id >= lo_id && id < hi_id) {
-        T c;
-        const T di = convex_sdf_rate<T>(P, (int)id, p, u, &c);
+        T dv, l;
+        const T di = convex_sdf_rate<T>(P, (int)id, p, u, &dv, &l);
         d = tmin(d, di);
-        t = tmin(t, tangent_bound<T>(di, c, err));
+        t = tmin(t, tangent_bound<T>(di, dv, l, err));
       }
     }
   }
@@ -729,15 +732,15 @@ __device__ __forceinline__ T region_seg(JobRef a, int r, V3<T> p, V3<T> u, T err
     return d;
   }
   const SMCRT_K Prim<T>* P = Tab<T>::prims(a);
-  T c;
-  T d = convex_sdf_rate<T>(P, R.first, p, u, &c);
-  T t = tangent_bound<T>(d, c, err);
+  T dv, l;
+  T d = convex_sdf_rate<T>(P, R.first, p, u, &dv, &l);
+  T t = tangent_bound<T>(d, dv, l, err);
   if (rule == kSegSubtract) {
     for (int i = 1; i < R.count; ++i) d = tmax(d, -prim_sdf<T, XF>(P, R.first + i, p));
   } else {
     for (int i = 1; i < R.count; ++i) {
-      const T di = convex_sdf_rate<T>(P, R.first + i, p, u, &c);
-      const T ti = tangent_bound<T>(di, c, err);
+      const T di = convex_sdf_rate<T>(P, R.first + i, p, u, &dv, &l);
+      const T ti = tangent_bound<T>(di, dv, l, err);
       if (rule == kSegUnion) {
         d = tmin(d, di);
         t = tmin(t, ti);

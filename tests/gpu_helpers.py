@@ -146,13 +146,16 @@ def voxel_diagonal(desc):
     return float(np.linalg.norm(d))
 
 
-def check_fluence(g, o, se, desc, prec, frac_needed=0.995):
+def check_fluence(g, o, se, desc, prec, frac_needed=0.995, n_batches=10):
     """Per voxel within 3 Monte Carlo SE (estimated from oracle batches).
     FP64: where no batch varies, the two must agree to rounding.  FP32: a
     packet whose FP32 walk flips a discrete decision becomes another valid
     walk; the voxels only it reaches have zero oracle variance, so the SE
     is floored at one packet's largest possible deposit (weight <= 1 times
-    the voxel diagonal)."""
+    the voxel diagonal).  The grid's chi-square per degree of freedom --
+    the mean squared z times (nu - 2)/nu, nu = n_batches - 1, which makes a
+    Student-t z average 1 -- is at most 1.1: two independent samples would
+    put it near 1, the same packets walked the same way near 0."""
     Fg, Fo = g["fluence_raw"], o["fluence_raw"]
     if prec == "f64":
         zero = se == 0
@@ -164,9 +167,12 @@ def check_fluence(g, o, se, desc, prec, frac_needed=0.995):
         se_eff = np.maximum(se[sel], voxel_diagonal(desc))
     z = np.abs(Fg[sel] - Fo[sel]) / se_eff
     within = np.mean(z <= 3.0)
+    nu = n_batches - 1
+    chi2 = float(np.mean(z ** 2)) * (nu - 2) / nu
     l2 = np.linalg.norm(Fg - Fo) / np.linalg.norm(Fo)
-    print(f"voxels within 3 SE: {within:.5f}, max z {z.max():.3f}, relative L2 {l2:.3e}")
+    print(f"voxels within 3 SE: {within:.5f}, max z {z.max():.3f}, chi2/dof {chi2:.4f}, relative L2 {l2:.3e}")
     assert within >= frac_needed
+    assert chi2 <= 1.1, chi2
     return l2
 
 

@@ -116,7 +116,7 @@ def test_long_straight_paths(S, eng, orc, W, prec, abs_tol):
     assert g["voxel_pieces"] > 40 * n
     rel = abs(g["absorbed"].sum() - o["absorbed"].sum()) / o["absorbed"].sum()
     assert rel <= abs_tol
-    check_fluence(g, o, se, desc, prec)
+    check_fluence(g, o, se, desc, prec, n_batches=6)
 
 
 @pytest.mark.parametrize("prec", ["f64", "f32"])

@@ -35,7 +35,7 @@ def test_random_scene_runs_match_oracle(S, eng, orc, W, seed):
         else:               # FP32: 1e-4, or 2 packets per 1e4 where reflections are chaotic
             assert diff <= max(1e-4 * o["absorbed"].sum(), 2.0 * n / 1e4), seed
             assert abs(g["interfaces"] - o["interfaces"]) <= max(5, 0.02 * o["interfaces"]), seed
-        check_fluence(g, o, se, desc, "f32")
+        check_fluence(g, o, se, desc, "f32", n_batches=B)
 
 
 @pytest.mark.parametrize("seed", SEEDS[:6])
