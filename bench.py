@@ -166,7 +166,7 @@ def progress(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-def serving_capacity(smcrt, workloads, max_packets, precision, seed, n_requests=48):
+def serving_capacity(smcrt, workloads, max_packets, precision, seed, n_requests=48, budget=SERVE_BUDGET):
     """Closed-loop capacity of the server on the request mix: a calibration
     stream (its own seed) submitted all at once; packets per second from
     the first submission to the last completion."""
@@ -175,7 +175,7 @@ def serving_capacity(smcrt, workloads, max_packets, precision, seed, n_requests=
     scenes = [smcrt.Scene(r["scene"]) for r in reqs]
     outs = [smcrt.Outputs(sc) for sc in scenes]
     torch.cuda.synchronize()
-    sv = smcrt.Server(0, hbm_budget_bytes=SERVE_BUDGET, precision=precision)
+    sv = smcrt.Server(0, hbm_budget_bytes=budget, precision=precision)
     ids = [sv.submit(sc, r["seed"], r["n_packets"], outputs=o)[0] for r, sc, o in zip(reqs, scenes, outs)]
     for rid in ids:
         sv.wait(rid, 1200.0)
@@ -185,12 +185,14 @@ def serving_capacity(smcrt, workloads, max_packets, precision, seed, n_requests=
     return sum(r["n_packets"] for r in reqs) / span
 
 
-def serving(smcrt, workloads, n_requests, rate_hz, max_packets, precision, seed=2112, load=0.7):
+def serving(smcrt, workloads, n_requests, rate_hz, max_packets, precision, seed=2112, load=0.7, budget=SERVE_BUDGET):
     """Continuous-batching leg on the resident server: a seeded Poisson
     stream of requests drawn from the four scene families (randomised
     optical properties, grids 32^3 to 256^3, packets log-uniform from 1e4 to
-    max_packets) submitted at their arrival times to one server whose
-    budget (8 GiB) binds; latency = completion - submission.  Without a
+    max_packets) submitted at their arrival times to one server with an
+    HBM budget (8 GiB unless given; the peak bytes held are reported, so a
+    run shows whether the budget bound); latency = completion - submission.
+    Without a
     given rate, arrivals are set for the offered load `load` (mean packets
     per request x rate / measured closed-loop capacity).  Four check
     requests (2000 packets, one per family) ride in the stream and are
@@ -202,7 +204,7 @@ def serving(smcrt, workloads, n_requests, rate_hz, max_packets, precision, seed=
 
     from oracle import oracle as orc
     mean_packets = (max_packets - 1e4) / math.log(max_packets / 1e4)  # log-uniform on [1e4, max]
-    capacity = serving_capacity(smcrt, workloads, max_packets, precision, seed + 1)
+    capacity = serving_capacity(smcrt, workloads, max_packets, precision, seed + 1, budget=budget)
     progress(f"serving: closed-loop capacity {capacity:.3e} packets/s")
     if rate_hz <= 0:
         rate_hz = load * capacity / mean_packets
@@ -218,7 +220,7 @@ def serving(smcrt, workloads, n_requests, rate_hz, max_packets, precision, seed=
     scenes = [smcrt.Scene(r["scene"]) for r in reqs]
     outs = [smcrt.Outputs(sc) for sc in scenes]
     torch.cuda.synchronize()
-    sv = smcrt.Server(0, hbm_budget_bytes=SERVE_BUDGET, precision=precision)
+    sv = smcrt.Server(0, hbm_budget_bytes=budget, precision=precision)
     t0 = time.perf_counter()
     ids = []
     peak_bytes, peak_queued, t_note = 0, 0, t0
@@ -268,7 +270,7 @@ def serving(smcrt, workloads, n_requests, rate_hz, max_packets, precision, seed=
         "offered_load": rate_hz * mean_packets / capacity,
         "packets_range": [1e4, max_packets],
         "grid_sides": list(SERVE_GRIDS),
-        "hbm_budget_bytes": SERVE_BUDGET,
+        "hbm_budget_bytes": budget,
         "peak_bytes_in_use": peak_bytes,
         "peak_queued": peak_queued,
         "p50_latency_s": float(np.percentile(lat, 50)),
@@ -642,6 +644,8 @@ def main():
     ap.add_argument("--serve-rate", type=float, default=0.0,
                     help="Poisson arrival rate of the serving leg (1/s); 0 = 70%% of the measured capacity")
     ap.add_argument("--serve-max-packets", type=float, default=1e6, help="largest request of the serving leg")
+    ap.add_argument("--serve-budget", type=float, default=float(SERVE_BUDGET),
+                    help="HBM budget of the serving leg's server in bytes")
     ap.add_argument("--serve-only", action="store_true",
                     help="only run the serving leg and print its JSON line (for the full request stream)")
     ap.add_argument("--vessels", type=int, default=0,
@@ -662,7 +666,7 @@ def main():
 
     if args.serve_only:
         print(json.dumps({"serving": serving(smcrt, workloads, args.serve_requests, args.serve_rate,
-                                             args.serve_max_packets, args.precision)}))
+                                             args.serve_max_packets, args.precision, budget=int(args.serve_budget))}))
         return
     if args.vessels > 0:
         vessel_profile(smcrt, workloads, args.vessels, int(args.packets), args.steps, args.warmup, args.precision)

@@ -6,7 +6,8 @@
 //   count : every primitive adds 1 to each cell its bounding box, grown by
 //           the margin, overlaps;
 //   scan  : one workgroup turns the counts into CSR offsets;
-//   fill  : every primitive writes its index into those cells' lists.
+//   fill  : every primitive writes its index into those cells' lists;
+// then the ring distances of the empty cells, over the counts buffer.
 // count and fill share one cell-range routine, so they agree exactly; fill
 // still checks every write against the capacity the host allocated.
 #include <hip/hip_runtime.h>
@@ -115,6 +116,39 @@ __global__ void accel_fill(const SceneHeader* __restrict__ sc, const PrimD* __re
       }
 }
 
+// ring distances: 0 for a cell that lists a primitive, kRingMax otherwise,
+// then relaxed over the 26 neighbours (out = min(in, 1 + neighbours' min));
+// pass j makes every distance up to j exact
+__global__ void accel_ring_init(const SceneHeader* __restrict__ sc, const uint32_t* __restrict__ counts,
+                                uint32_t* __restrict__ ring) {
+  const int n = sc->acc.n_cells;
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x)
+    ring[i] = counts[i] ? 0u : (uint32_t)kRingMax;
+}
+
+__global__ void accel_ring_pass(const SceneHeader* __restrict__ sc, const uint32_t* __restrict__ in,
+                                uint32_t* __restrict__ out) {
+  const Accel& A = sc->acc;
+  const int dx = A.dims[0], dy = A.dims[1], dz = A.dims[2];
+  const int n = A.n_cells;
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+    const int x = i % dx, y = (i / dx) % dy, z = i / (dx * dy);
+    uint32_t m = in[i];
+    for (int cz = z - 1; cz <= z + 1; ++cz) {
+      if (cz < 0 || cz >= dz) continue;
+      for (int cy = y - 1; cy <= y + 1; ++cy) {
+        if (cy < 0 || cy >= dy) continue;
+        for (int cx = x - 1; cx <= x + 1; ++cx) {
+          if (cx < 0 || cx >= dx) continue;
+          const uint32_t v = in[cx + dx * (cy + dy * cz)] + 1u;
+          m = v < m ? v : m;
+        }
+      }
+    }
+    out[i] = m;
+  }
+}
+
 hipError_t launch_accel_build(const SceneHeader* d_sc, const PrimD* d_pd, int n_prims, int n_cells, uint32_t* counts,
                               uint32_t* cursors, uint32_t* offsets, uint32_t* ids, hipStream_t stream) {
   if (!d_sc || !d_pd || !counts || !cursors || !offsets || !ids || n_prims < 1 || n_cells < 1) return hipErrorInvalidValue;
@@ -124,6 +158,14 @@ hipError_t launch_accel_build(const SceneHeader* d_sc, const PrimD* d_pd, int n_
   hipLaunchKernelGGL(accel_count, dim3(pb), dim3(256), 0, stream, d_sc, d_pd, counts);
   hipLaunchKernelGGL(accel_scan, dim3(1), dim3(1024), 0, stream, d_sc, counts, offsets);
   hipLaunchKernelGGL(accel_fill, dim3(pb), dim3(256), 0, stream, d_sc, d_pd, offsets, cursors, ids);
+  // counts and cursors are free now: ring distances, ending in counts
+  hipLaunchKernelGGL(accel_ring_init, dim3(zb < 4096 ? zb : 4096), dim3(256), 0, stream, d_sc, counts, cursors);
+  for (int j = 1; j < kRingMax; ++j) {
+    uint32_t* src = (j & 1) ? cursors : counts;
+    uint32_t* dst = (j & 1) ? counts : cursors;
+    hipLaunchKernelGGL(accel_ring_pass, dim3(zb < 4096 ? zb : 4096), dim3(256), 0, stream, d_sc, src, dst);
+  }
+  static_assert((kRingMax - 1) % 2 == 1, "the last ring pass writes counts");
   return hipGetLastError();
 }
 

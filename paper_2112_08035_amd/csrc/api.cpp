@@ -757,6 +757,12 @@ static smcrt_status pack_accel(const smcrt_scene* s, SceneHeader* h, const std::
   A.n_prims = (int32_t)R.prims.size();
   A.margin = margin;
   A.marginf = (float)margin;
+  {
+    double cmin = 1e300;
+    for (int i = 0; i < 3; ++i) cmin = std::min(cmin, (hi[i] - lo[i] + 2.0 * margin) / s->accel_cells[i]);
+    A.cell_min = cmin;
+    A.cell_minf = std::nextafter((float)cmin, 0.0f);  // rounded down
+  }
   int64_t cells = 1;
   for (int i = 0; i < 3; ++i) {
     A.dims[i] = s->accel_cells[i];
@@ -1229,6 +1235,7 @@ static smcrt_status launch_jobs(smcrt_engine* e, const std::vector<JobSpec>& job
       const size_t cb = align256(sizeof(uint32_t) * ((size_t)h->acc.n_cells + 1));
       a.acc_offsets = reinterpret_cast<const uint32_t*>(base + acc_off[u] + 2 * cb);
       a.acc_ids = reinterpret_cast<const uint32_t*>(base + acc_off[u] + 3 * cb);
+      a.acc_rings = reinterpret_cast<const uint32_t*>(base + acc_off[u]);
     }
     if (tr) {
       a.trace_ids = tr->ids;
@@ -1446,6 +1453,7 @@ extern "C" smcrt_status smcrt_run_ex_static(smcrt_engine* e, const smcrt_scene* 
   if (h->acc.region >= 0) {
     a.acc_offsets = reinterpret_cast<const uint32_t*>(base + acc_off + 2 * cb);
     a.acc_ids = reinterpret_cast<const uint32_t*>(base + acc_off + 3 * cb);
+    a.acc_rings = reinterpret_cast<const uint32_t*>(base + acc_off);
   }
   WalkArgs* d_job = reinterpret_cast<WalkArgs*>(base + jobs_off);
   HIP_TRY(hipMemcpyAsync(base, s->blob.data(), s->blob.size(), hipMemcpyHostToDevice, q), "hipMemcpyAsync(tables)");
@@ -1901,6 +1909,7 @@ static void resident_job(smcrt_server* sv, int s, WalkArgs& a) {
   if (h->acc.region >= 0) {
     a.acc_offsets = reinterpret_cast<const uint32_t*>(sl.dev + sl.acc_off + 2 * sl.acc_cb);
     a.acc_ids = reinterpret_cast<const uint32_t*>(sl.dev + sl.acc_off + 3 * sl.acc_cb);
+    a.acc_rings = reinterpret_cast<const uint32_t*>(sl.dev + sl.acc_off);
     if (h->acc.caps) {
       a.acc_capd = reinterpret_cast<const double*>(sl.dev + h->acc.cap_offset_d);
       a.acc_capf = reinterpret_cast<const float*>(sl.dev + h->acc.cap_offset_f);

@@ -36,6 +36,8 @@ enum SegRule : int32_t { kSegNone = 0, kSegUnion = 1, kSegIntersect = 2, kSegSub
 
 // capsules an FP32 staged-capsule workgroup holds in LDS (two float4 each)
 constexpr int kStageCaps = 3072;
+// largest ring distance the acceleration build resolves (farther cells keep it)
+constexpr int kRingMax = 16;
 
 // Primitive parameters, precomputed on the host:
 //   sphere   : c0 c1 c2 r
@@ -96,7 +98,12 @@ struct Region {
 // step).  Cell c lists the primitives whose bounding box grown by `margin`
 // overlaps c; a query returns min(margin, min over the listed primitives),
 // which equals the region SDF wherever that is below margin and is a lower
-// bound elsewhere.  Built on the device into the engine's accel buffers.
+// bound elsewhere.  A cell that lists none also has its Chebyshev distance
+// in cells to the nearest cell that lists one (kRingMax at most): every
+// surface point lies in a cell that lists its primitive, so there the query
+// returns (distance - 1) whole cells plus the way to the cell's own faces,
+// when that is more than the margin.  Built on the device into the engine's
+// accel buffers.
 struct Accel {
   int32_t region;                 // accelerated region, -1 = none
   int32_t dims[3];
@@ -108,8 +115,9 @@ struct Accel {
   uint64_t cap_offset_d, cap_offset_f;
   uint64_t capacity;              // entries the id list can hold
   double lo[3], inv_cell[3], margin;
+  double cell_min;                // the smallest cell side
   double box_lo[3], box_hi[3];    // bounding box of the region's primitives
-  float lof[3], inv_cellf[3], marginf, padf;
+  float lof[3], inv_cellf[3], marginf, cell_minf;
   float box_lof[3], box_hif[3];
 };
 
@@ -172,6 +180,8 @@ struct WalkArgs {
   double* absorbed;              // n_regions
   const uint32_t* acc_offsets;   // n_cells + 1 (accelerated scenes)
   const uint32_t* acc_ids;       // capacity
+  const uint32_t* acc_rings;     // n_cells: 0 for a cell that lists primitives, else
+                                 // its Chebyshev distance to one in cells (<= kRingMax)
   void* tallies;                 // smcrt_tallies
   // trace mode
   const uint64_t* trace_ids;

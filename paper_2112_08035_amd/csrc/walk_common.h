@@ -150,6 +150,7 @@ struct Tab<float> {
   static __device__ __forceinline__ V3<float> acc_blo(const SMCRT_K Accel& A) { return {A.box_lof[0], A.box_lof[1], A.box_lof[2]}; }
   static __device__ __forceinline__ V3<float> acc_bhi(const SMCRT_K Accel& A) { return {A.box_hif[0], A.box_hif[1], A.box_hif[2]}; }
   static __device__ __forceinline__ float acc_margin(const SMCRT_K Accel& A) { return A.marginf; }
+  static __device__ __forceinline__ float acc_cell_min(const SMCRT_K Accel& A) { return A.cell_minf; }
   static __device__ __forceinline__ float seg_err(ScP s) { return s->seg_errf; }
   // slack of a rate of approach: a few units in the last place
   static __device__ __forceinline__ float seg_eps() { return 0x1p-20f; }
@@ -181,6 +182,7 @@ struct Tab<double> {
   static __device__ __forceinline__ V3<double> acc_blo(const SMCRT_K Accel& A) { return {A.box_lo[0], A.box_lo[1], A.box_lo[2]}; }
   static __device__ __forceinline__ V3<double> acc_bhi(const SMCRT_K Accel& A) { return {A.box_hi[0], A.box_hi[1], A.box_hi[2]}; }
   static __device__ __forceinline__ double acc_margin(const SMCRT_K Accel& A) { return A.margin; }
+  static __device__ __forceinline__ double acc_cell_min(const SMCRT_K Accel& A) { return A.cell_min; }
   static __device__ __forceinline__ double seg_err(ScP s) { return s->seg_err; }
   static __device__ __forceinline__ double seg_eps() { return 1e-12; }
 };
@@ -443,6 +445,25 @@ __device__ __forceinline__ T cap_sdf(T a0, T a1, T a2, T e0, T e1, T e2, T inv, 
   return tsqrt(dot(d, d)) - r;
 }
 
+// Lower bound of the accelerated region's SDF at p in a cell that lists no
+// primitive, from the cell's ring distance k (in cells) to the nearest cell
+// that lists one: every surface point lies in such a cell, so the surface is
+// at least k - 1 whole cells plus p's way to its own cell's faces away (the
+// smallest side counted; cell coordinates cx, cy, cz of p and its cell
+// ix, iy, iz).  Never below the margin; a relative 2^-20 less against
+// rounding.
+template <typename T>
+__device__ __forceinline__ T ring_bound(JobRef a, const SMCRT_K Accel& A, int c, T cx, T cy, T cz, int ix, int iy,
+                                        int iz) {
+  const T m = Tab<T>::acc_margin(A);
+  if (a.acc_rings == nullptr) return m;
+  const uint32_t k = kptr(a.acc_rings)[c];
+  const T fx = cx - T(ix), fy = cy - T(iy), fz = cz - T(iz);
+  const T f = tmin(tmin(tmin(fx, T(1) - fx), tmin(fy, T(1) - fy)), tmin(fz, T(1) - fz));
+  const T r = (T(k) - T(1) + tmax(f, T(0))) * Tab<T>::acc_cell_min(A) * (T(1) - T(0x1p-20));
+  return tmax(m, r);
+}
+
 // SDF of the accelerated region through its uniform grid: min(margin, min
 // over the primitives listed in p's cell).  Equal to the region SDF where
 // that is below the margin, a lower bound elsewhere; outside the grid box
@@ -473,6 +494,7 @@ __device__ __forceinline__ T accel_sdf(JobRef a, V3<T> p, LdsCaps lds = nullptr)
   uint64_t e = offs[c + 1];
   e = e < A.capacity ? e : A.capacity;
   const SMCRT_K Prim<T>* P = Tab<T>::prims(a);
+  if (b >= e) return ring_bound<T>(a, A, c, cx, cy, cz, ix, iy, iz);
   const uint32_t lo_id = (uint32_t)A.first_prim, hi_id = (uint32_t)(A.first_prim + A.n_prims);
   T d = Tab<T>::acc_margin(A);
   if (A.caps) {
@@ -683,6 +705,11 @@ __device__ __forceinline__ T accel_seg(JobRef a, V3<T> p, V3<T> u, T err, T* tb)
   const uint32_t b = offs[cell];
   uint64_t e = offs[cell + 1];
   e = e < A.capacity ? e : A.capacity;
+  if (b >= e) {
+    const T d = ring_bound<T>(a, A, cell, cx, cy, cz, ix, iy, iz);
+    *tb = d;
+    return d;
+  }
   const uint32_t lo_id = (uint32_t)A.first_prim, hi_id = (uint32_t)(A.first_prim + A.n_prims);
   T d = Tab<T>::acc_margin(A), t = d;
   if (A.caps) {
