@@ -393,9 +393,11 @@ def batching(smcrt, workloads, precision):
     - the small sphere case at its full 1e5 packets, 64 times (seeds differ);
     - the batched microvascular network at its stated size: 64 vessel
       networks (2000 capsules through the uniform grid, 128^3 grids, mu_s
-      scaled 0.5-2x), 1e7 packets each, in ONE launch; one scene per launch
-      timed on 8 of them; the error against the oracle on 4 of the scenes
-      (2500 packets each, run as one batch)."""
+      scaled 0.5-2x), 1e7 packets each, in ONE launch whose launch options
+      the engine's autotuner picks on one of the scenes (both forms then
+      run with them); one scene per launch timed on 8 of them; the error
+      against the oracle on 4 of the scenes (2500 packets each, run as one
+      batch)."""
     import numpy as np
     import torch
 
@@ -431,6 +433,8 @@ def batching(smcrt, workloads, precision):
     eng = smcrt.Engine(0, precision=precision)
     scenes = [smcrt.Scene(d) for d in descs]
     seeds = [5000 + i for i in range(64)]
+    default_opts = eng.opts()
+    _, tuned_rate = eng.autotune(scenes[0], n_trial=500_000)
     smcrt.launch_batch(eng, scenes, seeds, [20_000] * 64)  # warm-up (tables, grids, code)
     outs = [smcrt.Outputs(sc) for sc in scenes]
     torch.cuda.synchronize()
@@ -466,7 +470,8 @@ def batching(smcrt, workloads, precision):
         "jobs": 64, "packets_per_job": n, "batched_packets_per_s": 64 * n / t_batch, "batched_s": t_batch,
         "one_per_launch_packets_per_s": 8 * n / t_plain, "one_per_launch_jobs_timed": 8,
         "speedup": (64 * n / t_batch) / (8 * n / t_plain), "per_packet": per,
-        "energy_identity_residual_max": identity, "error_vs_oracle": errs, "launch": eng.opts()}
+        "energy_identity_residual_max": identity, "error_vs_oracle": errs, "launch": eng.opts(),
+        "launch_default": default_opts, "autotune_trial_packets_per_s": tuned_rate}
     eng.close()
     return res
 
