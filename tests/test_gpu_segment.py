@@ -139,3 +139,59 @@ def test_segment_steps_through_the_vessel_grid(S, eng, orc, W, prec):
     assert diff <= 2e-3 * n, diff
     assert g["steps"] < p["steps"]
     check_fluence(g, o, se, desc, "f32")
+
+
+def _sphere_box_cloud(W, seed, n=120):
+    """A scattering cube holding one accelerated union of n small plain
+    spheres and boxes (the grid's general path: primitives, not capsule
+    records), a beam from above."""
+    rng = np.random.default_rng(seed)
+    prims = [{"kind": "box", "c": [0.0, 0.0, 0.0], "half": [0.5, 0.5, 0.5]}]
+    for i in range(n):
+        c = rng.uniform(-0.42, 0.42, 3).tolist()
+        if i % 2:
+            prims.append({"kind": "sphere", "c": c, "r": float(rng.uniform(0.01, 0.05))})
+        else:
+            prims.append({"kind": "box", "c": c, "half": rng.uniform(0.01, 0.04, 3).tolist()})
+    regions = [W._region([0], 0.2, 20.0, 0.9, 1.38), W._region(range(1, n + 1), 2.0, 60.0, 0.95, 1.45)]
+    grid = {"lo": [-0.5] * 3, "hi": [0.5] * 3, "dims": [24] * 3}
+    sc = W._scene("cloud", prims, regions, None, grid)
+    sc["source"] = {"kind": "disc", "c": [0.0, 0.0, 0.5 + 0.5 * sc["pad"]], "r": 0.3, "u": [0.0, 0.0, -1.0]}
+    sc["accel_cells"] = [16, 16, 16]
+    return sc
+
+
+def test_segment_steps_through_a_grid_of_spheres_and_boxes(S, eng, orc, W):
+    # an accelerated union of plain spheres and boxes: the grid's general
+    # path bounds the listed primitives by their tangents; in FP64 every
+    # event up to the first surface is the plain march's, nearly every
+    # packet takes its events throughout, and the run's tallies match the
+    # plain oracle on the same packets
+    desc = _sphere_box_cloud(W, 4)
+    n, seed = 256, 61
+    print("segment sphere/box grid traces", flush=True)
+    g = S.trace(dict(desc, segment=True), seed, list(range(n)), 60, engine=eng, precision="f64")
+    o = [orc.trace(desc, seed, pid, 60) for pid in range(n)]
+    same = 0
+    for pid in range(n):
+        a, b = o[pid], g[pid]
+        for ea, eb in zip(a, b):
+            assert (ea["type"], ea["region"], ea["event"]) == (eb["type"], eb["region"], eb["event"]), pid
+            if ea["type"] in ("REFLECT", "REFRACT", "CROSS"):
+                break
+            if ea["type"] != "ESCAPE":
+                assert np.max(np.abs(ea["p"] - eb["p"])) <= 1e-9, (pid, ea["type"])
+        same += len(a) == len(b) and all((x["type"], x["region"]) == (y["type"], y["region"]) for x, y in zip(a, b))
+    print(f"sphere/box grid: {same} of {n} packets take the plain march's events")
+    assert same >= 0.97 * n
+    N = 4000
+    ob, se = oracle_batches(orc, desc, 8, N, 10)
+    for prec in ("f64", "f32"):
+        gs = S.run(dict(desc, segment=True), 8, N, engine=eng, precision=prec)
+        gp = S.run(desc, 8, N, engine=eng, precision=prec)
+        assert abs(identity_residual(gs)) <= 1e-9 * N
+        diff = abs(gs["absorbed"].sum() - ob["absorbed"].sum())
+        print(f"{prec}: absorbed difference {diff:.3e} of {ob['absorbed'].sum():.1f}, steps {gs['steps']} vs {gp['steps']}")
+        assert diff <= 2e-3 * N, diff
+        assert gs["steps"] < gp["steps"]
+        check_fluence(gs, ob, se, desc, "f32")
