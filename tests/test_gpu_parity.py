@@ -524,3 +524,41 @@ def test_largest_grid(S, eng, W, prec):
     assert t.launched == N and t.escaped_face[1] == pytest.approx(N, rel=1e-9)
     del F, out
     torch.cuda.empty_cache()
+
+
+def test_sparse_acceleration_grid_ring_bounds(S, eng, orc, W):
+    """Few small spheres scattered through a large clear-ish medium on a
+    fine uniform grid: most cells list nothing, and there the grid query
+    returns its ring bound (whole cells to the nearest cell that lists a
+    sphere), far beyond the margin.  Those steps must stay conservative:
+    FP64 traces equal the oracle's (which evaluates every sphere at every
+    step) record by record, and the accelerated run takes the brute-force
+    run's events.  (Thirty spheres are no case for a grid: it takes more
+    steps than the exact distance does; here its bounds are what is tested.
+    A grazing hit snaps to the normal's foot
+    from where the march stopped, which the grid's longer steps move within
+    delta: such a packet may take another valid walk after it, as in the
+    acceleration tests of the random scenes.)"""
+    rng = np.random.default_rng(77)
+    prims = [{"kind": "box", "c": [0.0, 0.0, 0.0], "half": [2.0, 2.0, 2.0]}]
+    for _ in range(30):
+        prims.append({"kind": "sphere", "c": rng.uniform(-1.8, 1.8, 3).tolist(), "r": float(rng.uniform(0.02, 0.08))})
+    regions = [W._region([0], 0.05, 1.0, 0.8, 1.33), W._region(range(1, 31), 1.0, 20.0, 0.9, 1.45)]
+    grid = {"lo": [-2.0] * 3, "hi": [2.0] * 3, "dims": [20] * 3}
+    desc = W._scene("sparse", prims, regions, None, grid)
+    desc["source"] = {"kind": "point", "p": [0.0, 0.0, 0.0]}
+    acc = dict(desc, accel_cells=[48, 48, 48])
+    n, seed = 512, 4040
+    g = S.trace(acc, seed, list(range(n)), 50, engine=eng, precision="f64")
+    o = [orc.trace(desc, seed, pid, 50) for pid in range(n)]
+    mut = [rg["mua"] + rg["mus"] for rg in desc["regions"]]
+    frac, worst, bad = compare_traces(o, g, extent_of(S, desc), 1e-6, mut=mut)
+    print(f"sparse grid traces: agree {frac:.4f} worst {worst} {bad[:5]}")
+    assert frac >= 0.99, (frac, worst, bad[:10])
+    N = 20000
+    plain = S.run(desc, 9, N, engine=eng, precision="f64")
+    fast = S.run(acc, 9, N, engine=eng, precision="f64")
+    for k in ("interactions", "interfaces", "reflections", "refractions", "kills", "escapes"):
+        assert abs(fast[k] - plain[k]) <= max(2, 1e-3 * plain[k]), (k, fast[k], plain[k])
+    assert abs(fast["absorbed"].sum() - plain["absorbed"].sum()) <= 2.0 + 1e-9 * N
+    print(f"sparse grid: steps {fast['steps']} with the grid, {plain['steps']} brute force")
