@@ -396,7 +396,7 @@ def batching(smcrt, workloads, precision):
       scaled 0.5-2x), 1e7 packets each, in ONE launch whose launch options
       the engine's autotuner picks on one of the scenes (both forms then
       run with them); one scene per launch timed on 8 of them; the error
-      against the oracle on 4 of the scenes (2500 packets each, run as one
+      against the oracle on 4 of the scenes (1e4 packets each, run as one
       batch)."""
     import numpy as np
     import torch
@@ -455,8 +455,8 @@ def batching(smcrt, workloads, precision):
     torch.cuda.synchronize()
     t_plain = time.perf_counter() - t
     del outs
-    # error against the oracle: 4 scenes, packets [0, 2500) of their seeds, one batch
-    m = 2500
+    # error against the oracle: 4 scenes, packets [0, 1e4) of their seeds, one batch
+    m = 10_000
     g = smcrt.run_batch(descs[:4], seeds[:4], [m] * 4, engine=eng, precision=precision)
     errs = []
     for d, sd, gi in zip(descs[:4], seeds[:4], g):
