@@ -169,7 +169,10 @@ def progress(msg):
 def serving_capacity(smcrt, workloads, max_packets, precision, seed, n_requests=48, budget=SERVE_BUDGET):
     """Closed-loop capacity of the server on the request mix: a calibration
     stream (its own seed) submitted all at once; packets per second from
-    the first submission to the last completion."""
+    the first submission to the last completion.  Beside it, the same
+    requests run one per launch on a plain engine, one after another (the
+    plain one-scene-per-launch walk the server is to beat); returns both
+    rates."""
     import torch
     reqs = workloads.request_stream(seed, n_requests, 1.0, packets=(1e4, max_packets), grid_sides=SERVE_GRIDS)
     scenes = [smcrt.Scene(r["scene"]) for r in reqs]
@@ -182,7 +185,19 @@ def serving_capacity(smcrt, workloads, max_packets, precision, seed, n_requests=
     polls = [sv.poll(rid) for rid in ids]
     sv.close()
     span = max(p[3] for p in polls) - min(p[1] for p in polls)
-    return sum(r["n_packets"] for r in reqs) / span
+    total = sum(r["n_packets"] for r in reqs)
+    eng = smcrt.Engine(0, precision=precision)
+    smcrt.launch(eng, scenes[0], 1, 10_000, outputs=smcrt.Outputs(scenes[0]))  # warm-up
+    for o in outs:
+        o.zero_()
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    for r, sc, o in zip(reqs, scenes, outs):
+        smcrt.launch(eng, sc, r["seed"], r["n_packets"], outputs=o)
+    torch.cuda.synchronize()
+    plain = total / (time.perf_counter() - t)
+    eng.close()
+    return total / span, plain
 
 
 def serving(smcrt, workloads, n_requests, rate_hz, max_packets, precision, seed=2112, load=0.7, budget=SERVE_BUDGET):
@@ -204,8 +219,8 @@ def serving(smcrt, workloads, n_requests, rate_hz, max_packets, precision, seed=
 
     from oracle import oracle as orc
     mean_packets = (max_packets - 1e4) / math.log(max_packets / 1e4)  # log-uniform on [1e4, max]
-    capacity = serving_capacity(smcrt, workloads, max_packets, precision, seed + 1, budget=budget)
-    progress(f"serving: closed-loop capacity {capacity:.3e} packets/s")
+    capacity, one_per_launch = serving_capacity(smcrt, workloads, max_packets, precision, seed + 1, budget=budget)
+    progress(f"serving: closed-loop capacity {capacity:.3e} packets/s ({one_per_launch:.3e} one per launch)")
     if rate_hz <= 0:
         rate_hz = load * capacity / mean_packets
     reqs = workloads.request_stream(seed, n_requests, rate_hz, packets=(1e4, max_packets), grid_sides=SERVE_GRIDS)
@@ -267,6 +282,8 @@ def serving(smcrt, workloads, n_requests, rate_hz, max_packets, precision, seed=
         "requests": len(reqs),
         "rate_hz": rate_hz,
         "capacity_packets_per_s": capacity,
+        "one_per_launch_packets_per_s": one_per_launch,
+        "capacity_over_one_per_launch": capacity / one_per_launch,
         "offered_load": rate_hz * mean_packets / capacity,
         "packets_range": [1e4, max_packets],
         "grid_sides": list(SERVE_GRIDS),
