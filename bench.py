@@ -41,19 +41,19 @@ COST = {
 }
 
 
-def slab_lane_ops(t, n_prims, survey_interface=False):
+def slab_lane_ops(t, n_prims, coarse_interface=False):
     """lane-slots of one run from its own work counters.  An interface step
     is priced as the kernel runs it: its FP64 work, 14 SDF evaluations of
     the nearest region (two central-difference normals of 6 each, the
     distance at the snapped point and the probe), the nearest-region search
     over all primitives and the Philox block of the Fresnel draw.
-    survey_interface: the coarser price 250 + P SDF instead."""
+    coarse_interface: the coarser price 250 + P SDF instead."""
     sdf = COST["sdf_box"]
     per_step = COST["step_overhead"] + n_prims * sdf + COST["volume"]
     emit = COST["philox"] + COST["log"] + n_prims * sdf
     inter = COST["interaction"] + COST["philox"] + COST["log"]
     surf = COST["interface"] + COST["surface_sdfs"] * sdf + n_prims * sdf + COST["philox"]
-    if survey_interface:
+    if coarse_interface:
         surf = COST["interface"] + n_prims * sdf
     return (t["launched"] * emit + t["steps"] * per_step + t["interactions"] * inter
             + (t["interfaces"] + t["advances"]) * surf + t["voxel_pieces"] * COST["voxel"])
@@ -399,7 +399,7 @@ def paper_speed_tests(smcrt, workloads, precision):
         table2[name] = {"photons": n, "grid": g["grid"], "sdf_s": ts, "voxel_s": tv, "sdf_over_voxel_speed": tv / ts,
                         "paper_cpu_sdf_s": g["smcrt_s"], "paper_cpu_voxel_s": g["voxel_s"],
                         "paper_sdf_over_voxel_speed": g["voxel_s"] / g["smcrt_s"]}
-    table2["context_only"] = True  # the paper's CPU timings beside ours: not a row of this build's scope
+    table2["context_only"] = True  # the paper's CPU timings beside ours: context, not a measured target
     return {"tally_free_sphere": sweep, "table2": table2}
 
 
@@ -678,7 +678,7 @@ def main():
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
+        print(json.dumps({"error": "this benchmark runs on one GPU only; --gpus must be 1"}))
         sys.exit(2)
 
     import numpy as np
@@ -761,7 +761,7 @@ def main():
             "peak": PEAK_LANE_OPS / 1e12,
             "unit": "Tlane-op/s",
             "frac": achieved / PEAK_LANE_OPS,
-            "frac_survey_interface_price": slab_lane_ops(per, len(desc["prims"]), True) / (launch_ms * 1e-3)
+            "frac_coarse_interface_price": slab_lane_ops(per, len(desc["prims"]), True) / (launch_ms * 1e-3)
             / PEAK_LANE_OPS,
             "traffic": counters.get("traffic_bytes_per_launch"),
             "kernel_ms": launch_ms,
