@@ -266,6 +266,13 @@ def serving(smcrt, workloads, n_requests, rate_hz, max_packets, precision, seed=
     lat = np.array([p[3] - p[1] for p in polls])
     t_first = min(p[1] for p in polls)
     t_last = max(p[3] for p in polls)
+    # time with at least one request submitted and not done: the union of
+    # the requests' [submission, completion] intervals
+    pending, open_end = 0.0, -math.inf
+    for a, b in sorted((p[1], p[3]) for p in polls):
+        if b > open_end:
+            pending += b - max(a, open_end)
+            open_end = b
     total = sum(r["n_packets"] for r in reqs)
     st = sv.stats()
     errs = []
@@ -298,6 +305,8 @@ def serving(smcrt, workloads, n_requests, rate_hz, max_packets, precision, seed=
         "epoch_ms": 20.0,
         "packets_saved_and_resumed": st["saved_total"],
         "device_busy_fraction": st["busy_s"] / max(t_last - t_first, 1e-9),
+        "device_busy_while_pending": st["busy_s"] / max(pending, 1e-9),
+        "pending_fraction": pending / max(t_last - t_first, 1e-9),
         "check_requests_vs_oracle": errs,
     }
 
