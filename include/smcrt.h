@@ -334,7 +334,10 @@ smcrt_status smcrt_engine_set_opts(smcrt_engine* engine, const smcrt_opts* opts)
 /* Autotuner: times runs of n_trial packets (>= 1000) of the scene under a
  * small grid of launch options -- block 256 or 128, as many workgroups per
  * CU as fit or one fewer, refill_min 1/4/16, surface_min 4/8/16 -- keeping
- * the engine's precision, and sets the fastest as the engine's options.
+ * the engine's precision; then, from the fastest of these, the other
+ * tally_layout where the scene's grid could take bricks and the other
+ * no_stage where its capsules could be staged in LDS.  Sets the fastest
+ * of all as the engine's options.
  * Synchronous; allocates and frees its own scratch outputs and stream.
  * out_best and out_packets_per_s (host, may be NULL) receive the winner. */
 smcrt_status smcrt_engine_autotune(smcrt_engine* engine, const smcrt_scene* scene, uint64_t n_trial,

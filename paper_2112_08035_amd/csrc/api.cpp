@@ -1552,35 +1552,56 @@ extern "C" smcrt_status smcrt_engine_autotune(smcrt_engine* e, const smcrt_scene
   smcrt_status r = SMCRT_OK;
   std::vector<JobSpec> jobs(1);
   jobs[0] = JobSpec{s, 0x5eedull, 0, n_trial, f, ab, t};
-  for (const Shape& sh : shapes) {
-    for (int rf : refills) {
+  // one warm run and one timed run under o; false on an error (in r or err)
+  auto trial = [&](const smcrt_opts& o) {
+    e->opts = o;
+    e->opts.use_graph = 0;
+    r = launch_jobs(e, jobs, nullptr, q);  // warm
+    if (r != SMCRT_OK) return false;
+    if ((err = hipEventRecord(e0, q)) != hipSuccess) return false;
+    r = launch_jobs(e, jobs, nullptr, q);
+    if (r != SMCRT_OK) return false;
+    if ((err = hipEventRecord(e1, q)) != hipSuccess || (err = hipEventSynchronize(e1)) != hipSuccess) return false;
+    float ms = 0.f;
+    if ((err = hipEventElapsedTime(&ms, e0, e1)) != hipSuccess) return false;
+    const double rate = (double)n_trial / (ms * 1e-3);
+    if (rate > best_rate) {
+      best_rate = rate;
+      best = o;
+    }
+    return true;
+  };
+  bool ok = true;
+  for (const Shape& sh : shapes)
+    for (int rf : refills)
       for (int sf : surfaces) {
+        if (!ok) break;
         smcrt_opts o = base;
         o.block = sh.block;
         o.blocks_per_cu = sh.per_cu;
         o.refill_min = rf;
         o.surface_min = sf;
-        o.use_graph = 0;
-        e->opts = o;
-        r = launch_jobs(e, jobs, nullptr, q);  // warm
-        if (r != SMCRT_OK) break;
-        if ((err = hipEventRecord(e0, q)) != hipSuccess) break;
-        r = launch_jobs(e, jobs, nullptr, q);
-        if (r != SMCRT_OK) break;
-        if ((err = hipEventRecord(e1, q)) != hipSuccess || (err = hipEventSynchronize(e1)) != hipSuccess) break;
-        float ms = 0.f;
-        if ((err = hipEventElapsedTime(&ms, e0, e1)) != hipSuccess) break;
-        const double rate = (double)n_trial / (ms * 1e-3);
-        if (rate > best_rate) {
-          best_rate = rate;
-          best = o;
-          best.use_graph = base.use_graph;
-        }
+        ok = trial(o);
       }
-      if (r != SMCRT_OK || err != hipSuccess) break;
+  // then, from the best shape, the tally layout and the capsule staging
+  // where the scene gives a choice (the brick grid, the LDS capsule table)
+  if (ok) {
+    smcrt_opts o = best;
+    o.tally_layout = 0;
+    if (brick_tally(o, h)) {
+      o.tally_layout = 1 - best.tally_layout;
+      ok = trial(o);
     }
-    if (r != SMCRT_OK || err != hipSuccess) break;
   }
+  if (ok) {
+    smcrt_opts o = best;
+    o.no_stage = 0;
+    if (job_class(o, h, false) == kLaunchStaged) {
+      o.no_stage = 1 - best.no_stage;
+      ok = trial(o);
+    }
+  }
+  best.use_graph = base.use_graph;
   cleanup();
   e->opts = (r == SMCRT_OK && err == hipSuccess) ? best : base;
   if (r != SMCRT_OK) return r;

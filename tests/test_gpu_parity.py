@@ -240,6 +240,28 @@ def test_autotune_picks_valid_options_and_keeps_results(S, W):
     e.close()
 
 
+def test_autotune_fp32_capsules_tries_layout_and_staging(S, W):
+    """FP32 on a capsule network with cubic voxels, where both the brick
+    tally and the LDS capsule table apply: the tuner's options are valid
+    and the tuned engine walks the same packets as the default one (event
+    and step counts equal, fluence to the order of FP64 sums)."""
+    desc = W.vessel_scene(5, 1.0, n_caps=600, n_grid=32)
+    e = S.Engine(0, precision="f32")
+    opts, rate = e.autotune(desc, n_trial=100_000)
+    assert rate > 0
+    assert opts["precision"] == S.Engine(0, precision="f32").opts()["precision"]
+    assert opts["tally_layout"] in (0, 1) and opts["no_stage"] in (0, 1)
+    assert opts["block"] in (128, 256) and opts["refill_min"] in (1, 4, 16) and opts["surface_min"] in (4, 8, 16)
+    tuned = S.run(desc, 9, 20000, engine=e, precision="f32")
+    plain = S.run(desc, 9, 20000, engine=S.Engine(0, precision="f32"), precision="f32")
+    for k in ("launched", "interactions", "interfaces", "reflections", "refractions", "steps", "voxel_pieces"):
+        assert tuned[k] == plain[k], k
+    np.testing.assert_allclose(tuned["absorbed"], plain["absorbed"], rtol=1e-12)
+    np.testing.assert_allclose(tuned["fluence_raw"], plain["fluence_raw"], rtol=1e-9,
+                               atol=1e-12 * plain["fluence_raw"].max())
+    e.close()
+
+
 # ------------------------------------------------------------ serving ----
 
 def test_served_requests_equal_runs_alone(S, W):
