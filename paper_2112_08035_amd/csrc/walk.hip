@@ -482,14 +482,19 @@ walk_kernel(const WalkArgs* __restrict__ job_table, BatchArgs B) {
         if (pk.pend > T(0) && (!live || pk.state == kInteract)) flush_tally<T>(a, pk, ln);
       }
 
-      // ---- grid additions staged this iteration, as full-wave atomics
-      if (a.fluence != nullptr) stage_drain(a.fluence, *ln.stage, kDrain, lane);
-
       // ---- interactions
       if (live && pk.state == kInteract) {
         pk.state = kTransport;
         if (!interact<T, TRACE>(a, pk, ln, L)) live = false;
       }
+
+      // ---- grid additions staged this iteration, as full-wave atomics.
+      // Last in the iteration: one counter tracks a wave's vector loads and
+      // its atomics in issue order, so the first per-lane table load after
+      // a drain (the region's coefficients in the interaction) waits until
+      // every drained atomic has completed at the L2.  Issued here, they
+      // complete while the next iteration's step runs.
+      if (a.fluence != nullptr) stage_drain(a.fluence, *ln.stage, kDrain, lane);
     }
 
     if constexpr (TRACE) {
