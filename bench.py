@@ -785,7 +785,12 @@ def main():
 
     if not args.no_cpu:
         from oracle import oracle as orc
-        threads = os.cpu_count() or 1
+        # the oracle's OpenMP team: OMP_NUM_THREADS when set, else the CPUs
+        # this process may run on
+        avail = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else (os.cpu_count() or 1)
+        threads = int(os.environ.get("OMP_NUM_THREADS", "0") or 0) or avail
+        cpu_model = next((ln.split(":", 1)[1].strip() for ln in open("/proc/cpuinfo")
+                          if ln.startswith("model name")), "unknown") if os.path.exists("/proc/cpuinfo") else "unknown"
         # calibrate on a run long enough to hide the per-thread grid set-up,
         # then time a sample of about cpu_seconds
         # time = fixed set-up (per-thread grids) + packets / rate: fit both
@@ -801,12 +806,21 @@ def main():
         t = time.perf_counter()
         o = orc.run(desc, 0, n_cpu)
         cpu_s = time.perf_counter() - t
+        # the same oracle on one thread, on a sample of about 4 s
+        n_one = int(max(2000, min(n_cpu, 4.0 * n_cpu / cpu_s / threads)) // 1000 * 1000)
+        t = time.perf_counter()
+        orc.run(desc, 0, n_one, threads=1)
+        one_s = time.perf_counter() - t
         result["cpu_baseline"] = {
             "value": n_cpu / cpu_s,
             "unit": "packets/s",
             "cores": threads,
             "kind": "oracle",
             "sample": f"packets [0, {n_cpu}) of the same slab workload, seed 0, FP64 oracle, {cpu_s:.1f} s",
+            "one_thread_value": n_one / one_s,
+            "one_thread_sample": f"packets [0, {n_one}), {one_s:.1f} s",
+            "cpu_model": cpu_model,
+            "cpus_available": avail,
         }
         # fluence error of the GPU path on the same packets
         g = smcrt.run(sc, 0, n_cpu, engine=eng, precision=args.precision)
