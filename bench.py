@@ -166,6 +166,49 @@ def progress(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
+def fluence_z_scores(smcrt, sc, eng, precision, desc, n, Fo):
+    """Per-voxel z-scores of the GPU fluence against the oracle's Fo (packets
+    [0, n), seed 0), with Monte Carlo standard errors from GPU batches.
+    Same packets: the GPU sum of 10 batches of [0, n) against Fo, the SE of
+    that sum from the batches (floored at one packet's largest deposit, the
+    voxel diagonal); the same walks put the chi-square per degree of freedom
+    near 0 (at most 1.1 passes).  Independent packets: 20 batches of
+    [n, 2n) against Fo, the SE of the difference from those batches (both
+    sums have the batch variance times 20); the same distribution puts it
+    near 1.  Both scale the mean squared z by (nu - 2)/nu, nu the batch
+    degrees of freedom, so that a Student-t z averages 1."""
+    import numpy as np
+    lo, hi, dims = desc["grid"]["lo"], desc["grid"]["hi"], desc["grid"]["dims"]
+    diag = float(np.sqrt(sum(((hi[i] - lo[i]) / dims[i]) ** 2 for i in range(3))))
+
+    def batches(first, B):
+        m = n // B
+        s1 = s2 = mn = None
+        for b in range(B):
+            F = smcrt.run(sc, 0, m, first=first + b * m, engine=eng, precision=precision)["fluence_raw"]
+            s1 = F.copy() if s1 is None else s1 + F
+            s2 = F * F if s2 is None else s2 + F * F
+            mn = F.copy() if mn is None else np.minimum(mn, F)
+        var = np.maximum(s2 - s1 * s1 / B, 0.0) / (B - 1)
+        return s1, var, mn
+
+    B = 10
+    Fg, var, _ = batches(0, B)
+    se = np.sqrt(B * var)
+    sel = (se > 0) | (Fg != Fo)
+    z = np.abs(Fg[sel] - Fo[sel]) / np.maximum(se[sel], diag)
+    same = {"batches": B, "voxels": int(sel.sum()), "within_3se": float(np.mean(z <= 3.0)),
+            "max_z": float(z.max()), "chi2_per_dof": float(np.mean(z ** 2)) * (B - 3) / (B - 1)}
+    B2 = 20
+    Gs, var2, mn = batches(n, B2)
+    keep = (mn > 0) & (Fo > 0) & (var2 > 0)  # voxels every batch reaches (elsewhere a few visits are not Gaussian)
+    z2 = (Gs[keep] - Fo[keep]) ** 2 / (2.0 * B2 * var2[keep])
+    nu = B2 - 1
+    indep = {"batches": B2, "packets": [n, 2 * n], "voxels": int(keep.sum()),
+             "within_3se": float(np.mean(np.sqrt(z2) <= 3.0)), "chi2_per_dof": float(z2.mean()) * (nu - 2) / nu}
+    return {"same_packets": same, "independent_packets": indep}
+
+
 def serving_capacity(smcrt, workloads, max_packets, precision, seed, n_requests=48, budget=SERVE_BUDGET):
     """Closed-loop capacity of the server on the request mix: a calibration
     stream (its own seed) submitted all at once; packets per second from
@@ -829,6 +872,7 @@ def main():
             "packets": n_cpu,
             "relative_l2": float(np.linalg.norm(Fg - Fo) / np.linalg.norm(Fo)),
             "absorbed_relative": float(abs(g["absorbed"].sum() - o["absorbed"].sum()) / o["absorbed"].sum()),
+            "z_scores": fluence_z_scores(smcrt, sc, eng, args.precision, desc, n_cpu, Fo),
         }
         result["trace_parity"] = trace_parity(smcrt, workloads, args.precision)
         progress("headline, oracle baseline and trace parity done")
