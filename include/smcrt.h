@@ -534,6 +534,24 @@ smcrt_status smcrt_trace(smcrt_engine* engine, const smcrt_scene* scene, uint64_
  * a NULL argument; SMCRT_E_HIP on a device failure. */
 smcrt_status smcrt_voxelize(smcrt_engine* engine, const smcrt_scene* scene, uint8_t* d_out, void* hip_stream);
 
+/* Point queries of the scene SDF (Sec. 2.2: the primitives' distances,
+ * Eq. 3 for the sphere, their placement and modifiers, and each region's
+ * CSG of them), by the device functions the walk steps with, in the
+ * engine's precision (FP32 engines evaluate at the points rounded to
+ * float).  d_points: device, n x 3 doubles (x, y, z per point).  d_dist:
+ * device, n x n_regions doubles, one row per point, region order.
+ * accelerated: 0 = every region's SDF from all its primitives; 1 = the
+ * accelerated region (smcrt_scene_set_accel) through its uniform grid, the
+ * lower bound the walk steps by (equal to the SDF within the grid's margin
+ * of a surface).  d_owner (device, may be NULL): n int32, the highest-index
+ * region whose distance is negative, else n_regions (ambient), as the walk
+ * assigns regions.  n = 0 does nothing.  Asynchronous on hip_stream; the
+ * caller owns the buffers.  Errors: SMCRT_E_INVALID for a NULL engine,
+ * scene, d_points or d_dist (n > 0), accelerated outside {0, 1}, or an
+ * incomplete scene; SMCRT_E_HIP on a device failure. */
+smcrt_status smcrt_scene_distance(smcrt_engine* engine, const smcrt_scene* scene, const double* d_points, uint64_t n,
+                                  int32_t accelerated, double* d_dist, int32_t* d_owner, void* hip_stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -1127,6 +1127,15 @@ struct TraceSpec {
   int n_ids, max_records;
 };
 
+// a point query (smcrt_scene_distance) of one job's scene
+struct DistSpec {
+  const double* points;
+  uint64_t n;
+  int accelerated;
+  double* dist;
+  int32_t* owner;
+};
+
 static size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
 // Lays the jobs' scenes, the job table, the per-job counters, the uniform
@@ -1135,7 +1144,7 @@ static size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 // counters and launches the walk of each geometry present -- all on `st`.
 // With vox_out (one job) it stops after voxelising that scene into vox_out.
 static smcrt_status launch_jobs(smcrt_engine* e, const std::vector<JobSpec>& jobs, const TraceSpec* tr, hipStream_t st,
-                                uint8_t* vox_out = nullptr) {
+                                uint8_t* vox_out = nullptr, const DistSpec* dq = nullptr) {
   if (jobs.empty()) return SMCRT_OK;
   std::vector<smcrt_scene*> uniq;
   std::vector<int> job_scene(jobs.size());
@@ -1171,7 +1180,7 @@ static smcrt_status launch_jobs(smcrt_engine* e, const std::vector<JobSpec>& job
   }
   for (size_t u = 0; u < uniq.size(); ++u) {
     const SceneHeader* h = reinterpret_cast<const SceneHeader*>(uniq[u]->blob.data());
-    if (h->geometry != kGeomVoxel && !vox_out) continue;
+    if (dq || (h->geometry != kGeomVoxel && !vox_out)) continue;
     vox_n[u] = (size_t)h->g_dims[0] * h->g_dims[1] * h->g_dims[2];
     if (vox_out) continue;
     vox_off[u] = off;
@@ -1181,7 +1190,7 @@ static smcrt_status launch_jobs(smcrt_engine* e, const std::vector<JobSpec>& job
   std::vector<size_t> brick_off(jobs.size(), 0), brick_n(jobs.size(), 0);
   for (size_t j = 0; j < jobs.size(); ++j) {
     const SceneHeader* h = reinterpret_cast<const SceneHeader*>(uniq[job_scene[j]]->blob.data());
-    if (tr || vox_out || !jobs[j].fluence || !brick_tally(e->opts, h)) continue;
+    if (tr || vox_out || dq || !jobs[j].fluence || !brick_tally(e->opts, h)) continue;
     brick_n[j] = brick_voxels(h);
     brick_off[j] = off;
     off = align256(off + sizeof(double) * brick_n[j]);
@@ -1302,6 +1311,11 @@ static smcrt_status launch_jobs(smcrt_engine* e, const std::vector<JobSpec>& job
       HIP_TRY(launch_voxelize(B.jobs, j0, vb, vox_n[u], q), "voxelize");
     }
     if (vox_out) return SMCRT_OK;
+    if (dq) {
+      HIP_TRY(launch_distance(e->opts.precision, B.jobs, 0, dq->points, dq->n, dq->accelerated, dq->dist, dq->owner, q),
+              "distance kernel");
+      return SMCRT_OK;
+    }
     HIP_TRY(launch_zero_u64_n(reinterpret_cast<unsigned long long*>(base + counters_off), (int)jobs.size(), q), "zero counters");
     for (size_t j = 0; j < jobs.size(); ++j)
       if (brick_n[j]) HIP_TRY(launch_zero_f64(reinterpret_cast<double*>(base + brick_off[j]), brick_n[j], q), "zero brick grid");
@@ -1319,7 +1333,7 @@ static smcrt_status launch_jobs(smcrt_engine* e, const std::vector<JobSpec>& job
     }
     return SMCRT_OK;
   };
-  if (!e->opts.use_graph || tr || vox_out) return enqueue(st);
+  if (!e->opts.use_graph || tr || vox_out || dq) return enqueue(st);
   // replay the captured sequence when the launch shape is the same
   std::vector<uint64_t> key = {(uint64_t)(uintptr_t)base, image_bytes, total, jobs.size(), (uint64_t)cg[0].block,
                                (uint64_t)e->opts.precision, (uint64_t)B.refill_min, (uint64_t)B.surface_min};
@@ -1631,6 +1645,19 @@ extern "C" smcrt_status smcrt_voxelize(smcrt_engine* e, const smcrt_scene* scene
   std::vector<JobSpec> jobs(1);
   jobs[0] = JobSpec{const_cast<smcrt_scene*>(scene), 0, 0, 0, nullptr, nullptr, nullptr};
   return launch_jobs(e, jobs, nullptr, (hipStream_t)hip_stream, d_out);
+}
+
+extern "C" smcrt_status smcrt_scene_distance(smcrt_engine* e, const smcrt_scene* scene, const double* d_points, uint64_t n,
+                                             int32_t accelerated, double* d_dist, int32_t* d_owner, void* hip_stream) {
+  if (!e || !scene) return fail(SMCRT_E_INVALID, "scene_distance: NULL engine or scene");
+  if (accelerated != 0 && accelerated != 1) return fail(SMCRT_E_INVALID, "scene_distance: accelerated must be 0 or 1");
+  if (n == 0) return SMCRT_OK;
+  if (!d_points || !d_dist) return fail(SMCRT_E_INVALID, "scene_distance: NULL points or distances");
+  HIP_TRY(hipSetDevice(e->device), "hipSetDevice");
+  std::vector<JobSpec> jobs(1);
+  jobs[0] = JobSpec{const_cast<smcrt_scene*>(scene), 0, 0, 0, nullptr, nullptr, nullptr};
+  const DistSpec dq{d_points, n, (int)accelerated, d_dist, d_owner};
+  return launch_jobs(e, jobs, nullptr, (hipStream_t)hip_stream, nullptr, &dq);
 }
 
 extern "C" smcrt_status smcrt_normalize_fluence(const smcrt_scene* scene, const double* d_raw, double launched,

@@ -2,7 +2,8 @@
 // geometry of the voxelised comparison model (Sec. 3): each voxel takes the
 // region that owns its centre (the highest-index region whose SDF is
 // negative there, else the ambient slot), evaluated in FP64 through the same
-// region SDFs, uniform-grid acceleration included, that the SDF walk uses.
+// region SDFs, uniform-grid acceleration included, that the SDF walk uses;
+// and point queries of those SDFs.
 #include <hip/hip_runtime.h>
 
 #include "launch.h"
@@ -24,6 +25,42 @@ __global__ void __launch_bounds__(256) voxelize_kernel(const WalkArgs* __restric
                             sc->g_lo[2] + (iz + 0.5) * sc->g_d[2]);
     vox[i] = (uint8_t)region_of<double, true>(a, c);
   }
+}
+
+// Point queries: every region's SDF at each point (through the uniform grid
+// for the accelerated region when accelerated), and the point's owner by
+// the walk's rule, in transport type T.
+template <typename T>
+__global__ void __launch_bounds__(256) distance_kernel(const WalkArgs* __restrict__ job_table, int job,
+                                                       const double* __restrict__ pts, uint64_t n, int accelerated,
+                                                       double* __restrict__ dist, int32_t* __restrict__ owner) {
+  JobRef a = kptr(job_table)[job];
+  ScP sc = kptr(a.sc);
+  const int nr = sc->n_regions;
+  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x) {
+    const V3<T> p = mk((T)pts[3 * i], (T)pts[3 * i + 1], (T)pts[3 * i + 2]);
+    int own = nr;
+    for (int r = 0; r < nr; ++r) {
+      const T d = accelerated ? region_dist<T, true>(a, r, p) : region_sdf<T, true>(a, sc->reg[r], p);
+      dist[i * (uint64_t)nr + r] = (double)d;
+      if (d < T(0)) own = r;
+    }
+    if (owner) owner[i] = own;
+  }
+}
+
+hipError_t launch_distance(int precision, const WalkArgs* d_jobs, int job, const double* points, uint64_t n, int accelerated,
+                           double* dist, int32_t* owner, hipStream_t stream) {
+  if (!d_jobs || !points || !dist || job < 0 || n == 0) return hipErrorInvalidValue;
+  uint64_t blocks = (n + 255) / 256;
+  if (blocks > 16384) blocks = 16384;
+  if (precision == 1)
+    hipLaunchKernelGGL(distance_kernel<double>, dim3((unsigned)blocks), dim3(256), 0, stream, d_jobs, job, points, n,
+                       accelerated, dist, owner);
+  else
+    hipLaunchKernelGGL(distance_kernel<float>, dim3((unsigned)blocks), dim3(256), 0, stream, d_jobs, job, points, n,
+                       accelerated, dist, owner);
+  return hipGetLastError();
 }
 
 hipError_t launch_voxelize(const WalkArgs* d_jobs, int job, uint8_t* vox, size_t n_vox, hipStream_t stream) {

@@ -383,3 +383,13 @@ def test_segment_tracing_validation(S, W):
             sv.wait(rid, 10.0)
     finally:
         sv.close()
+
+
+def test_scene_distance_validation(S):
+    # argument checks come before any device work
+    h = S.smcrt_scene_create(1.0, 1e-5, 1e-4)
+    try:
+        with pytest.raises(S.SmcrtError, match="NULL engine"):
+            S.smcrt_scene_distance(None, h, None, 0, 0, None, None, None)
+    finally:
+        S.smcrt_scene_destroy(h)

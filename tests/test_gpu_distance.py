@@ -1,0 +1,114 @@
+"""Point queries of the scene SDF (smcrt_scene_distance) against the
+oracle's region SDFs (Sec. 2.2: primitives, placement, modifiers and the
+regions' CSG): every region's distance at seeded points spread over the
+simulation volume and gathered near the surfaces, on the workload families,
+the CSG, shape and gallery scenes, a vessel network and the random scenes
+of every primitive kind, placement and modifier.
+
+Tolerances, relative to the scene extent: FP64 1e-12 (the same formulas;
+FMA contraction and the last bits of library transcendentals differ); FP32
+2e-6 (the point rounded to float, then FP32 arithmetic on coordinates of
+order the extent).  Owners (the walk's region rule) agree wherever no
+region's surface is within that tolerance.  Through the acceleration grid
+the accelerated region's distance is a lower bound of the exact one, equal
+to it near the surface."""
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+TOL = {"f64": 1e-12, "f32": 2e-6}
+
+
+def _box(S, desc):
+    sc = S.Scene(desc)  # held while the library reads it
+    _, _, lo, hi = S.smcrt_scene_info(sc.h)
+    return np.asarray(lo, dtype=float), np.asarray(hi, dtype=float)
+
+
+def _points(S, orc, desc, seed, n_uniform=3000, n_near=1000):
+    """Uniform points in the simulation volume, then points within 2 % of
+    the extent of some region's surface (by rejection), with the oracle's
+    distances at each."""
+    rng = np.random.default_rng(seed)
+    lo, hi = _box(S, desc)
+    ext = float(np.max(hi - lo))
+    cs = orc.CScene(desc)
+    L = orc.lib()
+    nr = len(desc["regions"])
+
+    def exact(p):
+        return [L.orc_region_sdf(cs.ref, r, orc._d3(p)) for r in range(nr)]
+
+    pts = list(rng.uniform(lo, hi, size=(n_uniform, 3)))
+    near = []
+    for _ in range(200):
+        if len(near) >= n_near:
+            break
+        for p in rng.uniform(lo, hi, size=(2000, 3)):
+            if min(abs(d) for d in exact(p)) < 0.02 * ext:
+                near.append(p)
+    pts = np.array(pts + near[:n_near])
+    ref = np.array([exact(p) for p in pts])
+    own = np.array([L.orc_region_of(cs.ref, orc._d3(p)) for p in pts])
+    return pts, ref, own, ext
+
+
+def _check(S, eng, orc, desc, seed, prec):
+    pts, ref, own, ext = _points(S, orc, desc, seed)
+    d, o = S.distance(desc, pts, engine=eng, precision=prec)
+    err = np.abs(d - ref).max() / ext
+    clear = np.min(np.abs(ref), axis=1) > 10 * TOL[prec] * ext
+    print(f"{desc['name']} {prec}: {len(pts)} points, worst |d - d_oracle| / extent {err:.2e}, "
+          f"owners equal {np.mean(o[clear] == own[clear]):.5f} of {int(clear.sum())}")
+    assert err <= TOL[prec], err
+    assert np.array_equal(o[clear], own[clear])
+
+
+FAMILIES = ["sphere", "slab", "cylinder", "glass_sphere", "bottle", "gallery", "shapes"]
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+@pytest.mark.parametrize("name", FAMILIES)
+def test_family_distances_match_oracle(S, eng, orc, W, name, prec):
+    _check(S, eng, orc, W.WORKLOADS[name](n_grid=8), 100 + FAMILIES.index(name), prec)
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+@pytest.mark.parametrize("seed", range(12))
+def test_random_scene_distances_match_oracle(S, eng, orc, W, seed, prec):
+    _check(S, eng, orc, W.random_scene(seed, n_grid=8), 200 + seed, prec)
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_vessel_distances_exact_and_through_the_grid(S, eng, orc, W, prec):
+    desc = W.vessel_scene(3, 1.0, n_caps=300, n_grid=8)
+    _check(S, eng, orc, dict(desc, accel_cells=None), 300, prec)
+    pts, ref, _, ext = _points(S, orc, desc, 301)
+    d, o = S.distance(desc, pts, engine=eng, precision=prec)
+    da, oa = S.distance(desc, pts, engine=eng, precision=prec, accelerated=True)
+    tol = TOL[prec] * ext
+    acc = int(np.argmax([len(rg["prims"]) for rg in desc["regions"]]))
+    others = [r for r in range(len(desc["regions"])) if r != acc]
+    assert np.array_equal(da[:, others], d[:, others])
+    assert np.all(da[:, acc] <= ref[:, acc] + tol)  # a lower bound: steps never pass a surface
+    # the grid's query is the exact SDF wherever that is below its margin
+    # (one cell); a quarter of the volume's side over the cell count is less
+    near = ref[:, acc] < 0.25 * ext / max(desc["accel_cells"])
+    print(f"vessels {prec}: {int(near.sum())} points near the capsules, "
+          f"worst grid deviation there {np.abs(da[near, acc] - ref[near, acc]).max() / ext:.2e}")
+    assert near.sum() >= 50
+    assert np.all(np.abs(da[near, acc] - ref[near, acc]) <= tol)
+    clear = np.min(np.abs(ref), axis=1) > 10 * tol
+    assert np.array_equal(oa[clear], o[clear])  # the grid's bound keeps every sign
+
+
+def test_distance_of_no_points_and_bad_arguments(S, eng, W):
+    desc = W.sphere_scene(n_grid=8)
+    d, o = S.distance(desc, np.zeros((0, 3)), engine=eng)
+    assert d.shape == (0, 1) and o.shape == (0,)
+    sc = S.Scene(desc)
+    with pytest.raises(S.SmcrtError, match="accelerated"):
+        S.smcrt_scene_distance(eng.h, sc.h, None, 1, 2, None, None, None)
+    with pytest.raises(S.SmcrtError, match="NULL points"):
+        S.smcrt_scene_distance(eng.h, sc.h, None, 1, 0, None, None, None)
