@@ -19,7 +19,8 @@ import os
 import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "libsmcrt.so")
+# another build of the same library (a sanitizer build, say) when SMCRT_LIB names one
+LIB_PATH = os.environ.get("SMCRT_LIB") or os.path.join(HERE, "libsmcrt.so")
 
 OK, E_INVALID, E_NOMEM, E_HIP, E_BUDGET, E_CANCELLED, E_STATE = 0, -1, -2, -3, -4, -5, -6
 PRIM = {"sphere": 0, "box": 1, "capsule": 2, "cylinder": 3, "torus": 4,
