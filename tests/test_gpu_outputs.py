@@ -137,3 +137,21 @@ def test_served_mix_matches_oracle(S, orc, W, prec):
             _check_job(orc, desc, seed, n, voxel, out.host(), prec, name)
     finally:
         sv.close()
+
+
+@pytest.mark.parametrize("prec", ["f32", "f64"])
+def test_same_seed_twice_agrees(S, eng, W, prec):
+    """Determinism: a run repeated with the same seed takes the same walks
+    (every event count equal) and its tallies differ only by the order of
+    the FP64 atomic sums (1e-12 relative)."""
+    descs = [W.WORKLOADS[n](n_grid=24) for n in ("sphere", "slab", "cylinder", "glass_sphere")]
+    descs.append(W.vessel_scene(2, 1.0, n_caps=400, n_grid=24))
+    for d in descs:
+        a = S.run(d, 77, 40000, engine=eng, precision=prec)
+        b = S.run(d, 77, 40000, engine=eng, precision=prec)
+        for k in ("launched", "interactions", "interfaces", "reflections", "refractions", "steps", "voxel_pieces",
+                  "kills", "escapes"):
+            assert a[k] == b[k], (d["name"], k)
+        np.testing.assert_allclose(a["absorbed"], b["absorbed"], rtol=1e-12)
+        np.testing.assert_allclose(a["escaped_face"], b["escaped_face"], rtol=1e-12, atol=1e-12)
+        np.testing.assert_allclose(a["fluence_raw"], b["fluence_raw"], rtol=1e-12, atol=1e-14 * a["fluence_raw"].max())
