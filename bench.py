@@ -703,6 +703,41 @@ def vessel_profile(smcrt, workloads, n_scenes, n, steps, warmup, precision):
     eng.close()
 
 
+def scene_profile(smcrt, workloads, name, n, steps, warmup, precision):
+    """One workload family alone (for profiling): the scene at its stated
+    grid, n packets per launch on one engine with default options; one JSON
+    line with packets/s, kernel time per launch and the work counters per
+    packet."""
+    import numpy as np
+    import torch
+    desc = workloads.WORKLOADS[name]()
+    eng = smcrt.Engine(0, precision=precision)
+    sc = smcrt.Scene(desc)
+    out = smcrt.Outputs(sc)
+    st = torch.cuda.current_stream()
+    for w in range(warmup):
+        smcrt.launch(eng, sc, 900 + w, n, outputs=out, stream=st)
+    torch.cuda.synchronize()
+    out.zero_()
+    marks = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
+    t0 = time.perf_counter()
+    for k in range(steps):
+        marks[k][0].record(st)
+        smcrt.launch(eng, sc, k, n, outputs=out, stream=st)
+        marks[k][1].record(st)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    h = out.host()
+    print(json.dumps({"scene_profile": {
+        "scene": name, "grid": desc["grid"]["dims"], "packets": n, "precision": precision, "steps": steps,
+        "packets_per_s": n * steps / wall,
+        "launch_ms": [round(a.elapsed_time(b), 2) for a, b in marks],
+        "per_packet": {k: h[k] / h["launched"] for k in ("steps", "interactions", "interfaces", "voxel_pieces",
+                                                         "grid_atomics")},
+        "launch": eng.opts()}}))
+    eng.close()
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -724,6 +759,9 @@ def main():
                     help="only run the serving leg and print its JSON line (for the full request stream)")
     ap.add_argument("--vessels", type=int, default=0,
                     help="only run the batched vessel networks: this many scenes, --packets per scene per step")
+    ap.add_argument("--scene", default="",
+                    help="only run this workload family (sphere, cylinder, glass_sphere, ...) at its stated grid, "
+                         "--packets per launch, and print its JSON line (for profiling)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only stream the 200^3 FP64 grid through the fluence normalisation kernel "
                          "(a plain read-once/write-once copy of known size) and report its bandwidth")
@@ -741,6 +779,9 @@ def main():
     if args.serve_only:
         print(json.dumps({"serving": serving(smcrt, workloads, args.serve_requests, args.serve_rate,
                                              args.serve_max_packets, args.precision, budget=int(args.serve_budget))}))
+        return
+    if args.scene:
+        scene_profile(smcrt, workloads, args.scene, int(args.packets), args.steps, args.warmup, args.precision)
         return
     if args.vessels > 0:
         vessel_profile(smcrt, workloads, args.vessels, int(args.packets), args.steps, args.warmup, args.precision)
