@@ -582,3 +582,35 @@ WORKLOADS = {
     "gallery": gallery_scene,
     "shapes": shapes_scene,
 }
+
+
+# ------------------------------------------------------------ scene files
+
+def _plain(x):
+    """numpy scalars and arrays as plain JSON values"""
+    if isinstance(x, dict):
+        return {k: _plain(v) for k, v in x.items()}
+    if isinstance(x, (list, tuple)):
+        return [_plain(v) for v in x]
+    if isinstance(x, np.ndarray):
+        return _plain(x.tolist())
+    if isinstance(x, np.integer):
+        return int(x)
+    if isinstance(x, np.floating):
+        return float(x)
+    return x
+
+
+def save_scene(scene, path):
+    """Writes a scene dictionary as JSON (the same keys the binding and the
+    oracle read)."""
+    import json
+    with open(path, "w") as f:
+        json.dump(_plain(scene), f, indent=1)
+
+
+def load_scene(path):
+    """Reads a scene dictionary written by save_scene (or by hand)."""
+    import json
+    with open(path) as f:
+        return json.load(f)
