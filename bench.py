@@ -463,8 +463,9 @@ def batching(smcrt, workloads, precision):
     - the batched microvascular network at its stated size: 64 vessel
       networks (2000 capsules through the uniform grid, 128^3 grids, mu_s
       scaled 0.5-2x), 1e7 packets each, in ONE launch whose launch options
-      the engine's autotuner picks on one of the scenes (both forms then
-      run with them); one scene per launch timed on 8 of them; the error
+      the engine's autotuner picks on a batched launch of the 64 scenes at
+      1e5 packets each (both forms then run with them); one scene per
+      launch timed on 8 of them; the error
       against the oracle on 4 of the scenes (1e4 packets each, run as one
       batch)."""
     import numpy as np
@@ -503,7 +504,7 @@ def batching(smcrt, workloads, precision):
     scenes = [smcrt.Scene(d) for d in descs]
     seeds = [5000 + i for i in range(64)]
     default_opts = eng.opts()
-    _, tuned_rate = eng.autotune(scenes[0], n_trial=500_000)
+    _, tuned_rate = eng.autotune(scenes, n_trial=100_000)  # timed on the batch itself
     smcrt.launch_batch(eng, scenes, seeds, [20_000] * 64)  # warm-up (tables, grids, code)
     outs = [smcrt.Outputs(sc) for sc in scenes]
     torch.cuda.synchronize()

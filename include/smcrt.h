@@ -342,6 +342,13 @@ smcrt_status smcrt_engine_set_opts(smcrt_engine* engine, const smcrt_opts* opts)
  * out_best and out_packets_per_s (host, may be NULL) receive the winner. */
 smcrt_status smcrt_engine_autotune(smcrt_engine* engine, const smcrt_scene* scene, uint64_t n_trial,
                                    smcrt_opts* out_best, double* out_packets_per_s);
+/* The same search timed on one batched launch of n scenes (n_trial packets
+ * each, n >= 1), for engines that run batches: the batch decides what one
+ * scene cannot show (jobs sharing the device, their tables in the L2s).
+ * out_packets_per_s counts the packets of all n jobs.  Errors as
+ * smcrt_engine_autotune, and SMCRT_E_INVALID for a NULL scene or n < 1. */
+smcrt_status smcrt_engine_autotune_batch(smcrt_engine* engine, int n, const smcrt_scene* const* scenes,
+                                         uint64_t n_trial, smcrt_opts* out_best, double* out_packets_per_s);
 
 /* ------------------------------------------------------------ tallies --- */
 

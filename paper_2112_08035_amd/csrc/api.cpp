@@ -1521,16 +1521,23 @@ extern "C" smcrt_status smcrt_run_batch(smcrt_engine* e, int n, const smcrt_scen
   return smcrt_run_batch_ex(e, n, scenes, seeds, first_packets, n_packets, outs.data(), hip_stream);
 }
 
-extern "C" smcrt_status smcrt_engine_autotune(smcrt_engine* e, const smcrt_scene* scene, uint64_t n_trial,
-                                              smcrt_opts* out_best, double* out_packets_per_s) {
-  if (!e || !scene) return fail(SMCRT_E_INVALID, "autotune: NULL engine or scene");
+// The autotuner over one launch of the given scenes (n_trial packets each):
+// the launch-shape grid, then the tally layout and the capsule staging where
+// a scene gives that choice.  Scratch outputs are shared by the jobs (their
+// sums are not read).
+static smcrt_status autotune_jobs(smcrt_engine* e, const std::vector<smcrt_scene*>& scenes, uint64_t n_trial,
+                                  smcrt_opts* out_best, double* out_packets_per_s) {
   if (n_trial < 1000) return fail(SMCRT_E_INVALID, "autotune: n_trial must be >= 1000");
-  smcrt_scene* s = const_cast<smcrt_scene*>(scene);
-  smcrt_status st = pack(s);
-  if (st != SMCRT_OK) return st;
+  std::vector<const SceneHeader*> hs;
+  size_t nvox = 0;
+  for (smcrt_scene* s : scenes) {
+    smcrt_status st = pack(s);
+    if (st != SMCRT_OK) return st;
+    const SceneHeader* h = reinterpret_cast<const SceneHeader*>(s->blob.data());
+    hs.push_back(h);
+    if (h->has_grid) nvox = std::max(nvox, (size_t)h->g_dims[0] * h->g_dims[1] * h->g_dims[2]);
+  }
   HIP_TRY(hipSetDevice(e->device), "hipSetDevice");
-  const SceneHeader* h = reinterpret_cast<const SceneHeader*>(s->blob.data());
-  const size_t nvox = h->has_grid ? (size_t)h->g_dims[0] * h->g_dims[1] * h->g_dims[2] : 0;
   // scratch outputs and a private stream
   double *f = nullptr, *ab = nullptr;
   smcrt_tallies* t = nullptr;
@@ -1564,8 +1571,9 @@ extern "C" smcrt_status smcrt_engine_autotune(smcrt_engine* e, const smcrt_scene
   smcrt_opts best = base;
   double best_rate = -1.0;
   smcrt_status r = SMCRT_OK;
-  std::vector<JobSpec> jobs(1);
-  jobs[0] = JobSpec{s, 0x5eedull, 0, n_trial, f, ab, t};
+  std::vector<JobSpec> jobs(scenes.size());
+  for (size_t j = 0; j < scenes.size(); ++j) jobs[j] = JobSpec{scenes[j], 0x5eedull + j, 0, n_trial, f, ab, t};
+  const double packets = (double)n_trial * (double)scenes.size();
   // one warm run and one timed run under o; false on an error (in r or err)
   auto trial = [&](const smcrt_opts& o) {
     e->opts = o;
@@ -1578,7 +1586,7 @@ extern "C" smcrt_status smcrt_engine_autotune(smcrt_engine* e, const smcrt_scene
     if ((err = hipEventRecord(e1, q)) != hipSuccess || (err = hipEventSynchronize(e1)) != hipSuccess) return false;
     float ms = 0.f;
     if ((err = hipEventElapsedTime(&ms, e0, e1)) != hipSuccess) return false;
-    const double rate = (double)n_trial / (ms * 1e-3);
+    const double rate = packets / (ms * 1e-3);
     if (rate > best_rate) {
       best_rate = rate;
       best = o;
@@ -1602,7 +1610,9 @@ extern "C" smcrt_status smcrt_engine_autotune(smcrt_engine* e, const smcrt_scene
   if (ok) {
     smcrt_opts o = best;
     o.tally_layout = 0;
-    if (brick_tally(o, h)) {
+    bool choice = false;
+    for (const SceneHeader* h : hs) choice = choice || brick_tally(o, h);
+    if (choice) {
       o.tally_layout = 1 - best.tally_layout;
       ok = trial(o);
     }
@@ -1610,7 +1620,9 @@ extern "C" smcrt_status smcrt_engine_autotune(smcrt_engine* e, const smcrt_scene
   if (ok) {
     smcrt_opts o = best;
     o.no_stage = 0;
-    if (job_class(o, h, false) == kLaunchStaged) {
+    bool choice = false;
+    for (const SceneHeader* h : hs) choice = choice || job_class(o, h, false) == kLaunchStaged;
+    if (choice) {
       o.no_stage = 1 - best.no_stage;
       ok = trial(o);
     }
@@ -1623,6 +1635,23 @@ extern "C" smcrt_status smcrt_engine_autotune(smcrt_engine* e, const smcrt_scene
   if (out_best) *out_best = best;
   if (out_packets_per_s) *out_packets_per_s = best_rate;
   return SMCRT_OK;
+}
+
+extern "C" smcrt_status smcrt_engine_autotune(smcrt_engine* e, const smcrt_scene* scene, uint64_t n_trial,
+                                              smcrt_opts* out_best, double* out_packets_per_s) {
+  if (!e || !scene) return fail(SMCRT_E_INVALID, "autotune: NULL engine or scene");
+  return autotune_jobs(e, {const_cast<smcrt_scene*>(scene)}, n_trial, out_best, out_packets_per_s);
+}
+
+extern "C" smcrt_status smcrt_engine_autotune_batch(smcrt_engine* e, int n, const smcrt_scene* const* scenes,
+                                                    uint64_t n_trial, smcrt_opts* out_best, double* out_packets_per_s) {
+  if (!e || n < 1 || !scenes) return fail(SMCRT_E_INVALID, "autotune_batch: NULL engine or scenes, or n < 1");
+  std::vector<smcrt_scene*> v((size_t)n);
+  for (int j = 0; j < n; ++j) {
+    if (!scenes[j]) return fail(SMCRT_E_INVALID, "autotune_batch: NULL scene %d", j);
+    v[j] = const_cast<smcrt_scene*>(scenes[j]);
+  }
+  return autotune_jobs(e, v, n_trial, out_best, out_packets_per_s);
 }
 
 extern "C" smcrt_status smcrt_trace(smcrt_engine* e, const smcrt_scene* scene, uint64_t seed, const uint64_t* d_packet_ids,

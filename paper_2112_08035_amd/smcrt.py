@@ -107,6 +107,8 @@ _SIGS = {
     "smcrt_engine_get_opts": ([_vp, C.POINTER(Opts)], C.c_int),
     "smcrt_engine_set_opts": ([_vp, C.POINTER(Opts)], C.c_int),
     "smcrt_engine_autotune": ([_vp, _vp, C.c_uint64, C.POINTER(Opts), C.POINTER(C.c_double)], C.c_int),
+    "smcrt_engine_autotune_batch": ([_vp, C.c_int, C.POINTER(_vp), C.c_uint64, C.POINTER(Opts), C.POINTER(C.c_double)],
+                                    C.c_int),
     "smcrt_run": ([_vp, _vp, C.c_uint64, C.c_uint64, C.c_uint64, _vp, _vp, _vp, _vp], C.c_int),
     "smcrt_run_batch": ([_vp, C.c_int, C.POINTER(_vp), C.POINTER(C.c_uint64), C.POINTER(C.c_uint64),
                          C.POINTER(C.c_uint64), C.POINTER(_vp), C.POINTER(_vp), C.POINTER(_vp), _vp], C.c_int),
@@ -295,6 +297,14 @@ def smcrt_engine_autotune(engine, scene, n_trial):
     o = Opts()
     rate = C.c_double()
     _check(lib().smcrt_engine_autotune(engine, scene, n_trial, C.byref(o), C.byref(rate)))
+    return o, rate.value
+
+
+def smcrt_engine_autotune_batch(engine, scenes, n_trial):
+    o = Opts()
+    rate = C.c_double()
+    arr = (_vp * len(scenes))(*scenes)
+    _check(lib().smcrt_engine_autotune_batch(engine, len(scenes), arr, n_trial, C.byref(o), C.byref(rate)))
     return o, rate.value
 
 
@@ -497,10 +507,15 @@ class Engine:
         smcrt_engine_set_opts(self.h, o)
 
     def autotune(self, scene, n_trial=500_000):
-        """Times launch options on the scene and keeps the fastest; returns
-        (options dict, packets/s of the winner)."""
-        sc = scene if isinstance(scene, Scene) else Scene(scene)
-        _, rate = smcrt_engine_autotune(self.h, sc.h, n_trial)
+        """Times launch options on the scene -- or, given a list of scenes, on
+        one batched launch of them, n_trial packets each -- and keeps the
+        fastest; returns (options dict, packets/s of the winner)."""
+        if isinstance(scene, (list, tuple)):
+            scs = [s if isinstance(s, Scene) else Scene(s) for s in scene]
+            _, rate = smcrt_engine_autotune_batch(self.h, [s.h for s in scs], n_trial)
+        else:
+            sc = scene if isinstance(scene, Scene) else Scene(scene)
+            _, rate = smcrt_engine_autotune(self.h, sc.h, n_trial)
         return self.opts(), rate
 
     def opts(self):

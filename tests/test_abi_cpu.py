@@ -393,3 +393,8 @@ def test_scene_distance_validation(S):
             S.smcrt_scene_distance(None, h, None, 0, 0, None, None, None)
     finally:
         S.smcrt_scene_destroy(h)
+
+
+def test_autotune_batch_validation(S):
+    with pytest.raises(S.SmcrtError, match="NULL engine"):
+        S.smcrt_engine_autotune_batch(None, [], 1000)

@@ -262,6 +262,28 @@ def test_autotune_fp32_capsules_tries_layout_and_staging(S, W):
     e.close()
 
 
+def test_autotune_on_a_batch_keeps_results(S, W):
+    """The tuner timed on one batched launch (vessel networks and a sphere,
+    FP32): valid options, and the batch it tuned walks the same packets as
+    under the default options (event and step counts equal, fluence to the
+    order of FP64 sums)."""
+    descs = [W.vessel_scene(s, 1.0, n_caps=400, n_grid=24) for s in (1, 2, 3)] + [W.sphere_scene(n_grid=24)]
+    e = S.Engine(0, precision="f32")
+    opts, rate = e.autotune(descs, n_trial=20_000)
+    assert rate > 0
+    assert opts["tally_layout"] in (0, 1) and opts["no_stage"] in (0, 1)
+    assert opts["block"] in (128, 256) and opts["refill_min"] in (1, 4, 16) and opts["surface_min"] in (4, 8, 16)
+    seeds, ns = [7, 8, 9, 10], [15000, 12000, 9000, 20000]
+    tuned = S.run_batch(descs, seeds, ns, engine=e, precision="f32")
+    plain = S.run_batch(descs, seeds, ns, engine=S.Engine(0, precision="f32"), precision="f32")
+    for x, y in zip(tuned, plain):
+        for k in ("launched", "interactions", "interfaces", "reflections", "refractions", "steps", "voxel_pieces"):
+            assert x[k] == y[k], k
+        np.testing.assert_allclose(x["absorbed"], y["absorbed"], rtol=1e-12)
+        np.testing.assert_allclose(x["fluence_raw"], y["fluence_raw"], rtol=1e-9, atol=1e-12 * y["fluence_raw"].max())
+    e.close()
+
+
 # ------------------------------------------------------------ serving ----
 
 def test_served_requests_equal_runs_alone(S, W):
