@@ -103,6 +103,79 @@ def test_vessel_distances_exact_and_through_the_grid(S, eng, orc, W, prec):
     assert np.array_equal(oa[clear], o[clear])  # the grid's bound keeps every sign
 
 
+def _with_union(desc):
+    """the scene itself when it has a union of several primitives; else its
+    first two inner regions merged into one union (the first's properties)"""
+    if any(rg["op"] == "union" and len(rg["prims"]) >= 2 for rg in desc["regions"]):
+        return desc
+    r = [dict(rg) for rg in desc["regions"]]
+    r[1] = dict(r[1], prims=r[1]["prims"] + r[2]["prims"], op="union", k=0.0)
+    del r[2]
+    return dict(desc, regions=r)
+
+
+BOUNDED = ("twist", "bend", "displace")  # modifiers whose SDFs are bounds, like the ellipsoid's
+
+
+def _exact_union(desc, r):
+    return all(desc["prims"][i]["kind"] != "ellipsoid" and not any(m in desc["prims"][i] for m in BOUNDED)
+               for i in desc["regions"][r]["prims"])
+
+
+def _ball_holds_no_surface(orc, desc, r, p, R, rng, n=3000):
+    """no point of the open ball of radius R about p (outside region r) is
+    inside region r: sampled uniformly in the ball, most samples near its
+    rim"""
+    cs, L = orc.CScene(desc), orc.lib()
+    v = rng.normal(size=(n, 3))
+    v /= np.linalg.norm(v, axis=1)[:, None]
+    q = p + v * (0.999 * R * rng.random(n) ** (1 / 3))[:, None]
+    return all(L.orc_region_sdf(cs.ref, r, orc._d3(x)) >= 0 for x in q)
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+@pytest.mark.parametrize("seed", range(12))
+def test_random_scene_grid_bounds(S, eng, orc, W, seed, prec):
+    """The uniform grid over a union of placed and modified primitives of
+    every kind is conservative: where the union's SDF is exact, the grid's
+    distance is at most the SDF everywhere; where some member's SDF is only
+    a bound (ellipsoid, twist, bend, displacement) the grid may exceed that
+    bound, and then no surface lies within the grid's distance (checked by
+    sampling the ball).  Near the surface it equals the SDF (every decision
+    there is the brute-force one); the other regions and every owner are
+    unchanged."""
+    desc = dict(_with_union(W.random_scene(seed, n_grid=8)), accel_cells=[8, 8, 8])
+    pts, ref, own, ext = _points(S, orc, desc, 400 + seed)
+    da, oa = S.distance(desc, pts, engine=eng, precision=prec, accelerated=True)
+    d, _ = S.distance(desc, pts, engine=eng, precision=prec)
+    tol = TOL[prec] * ext
+    # the region the binding accelerates: the union with most primitives (first of equals)
+    unions = [(len(rg["prims"]), -i) for i, rg in enumerate(desc["regions"])
+              if rg["op"] == "union" and len(rg["prims"]) >= 2]
+    acc = -max(unions)[1]
+    others = [r for r in range(len(desc["regions"])) if r != acc]
+    assert np.array_equal(da[:, others], d[:, others])
+    over = np.where(da[:, acc] > ref[:, acc] + tol)[0]
+    if _exact_union(desc, acc):
+        assert len(over) == 0, over[:5]
+    else:
+        rng = np.random.default_rng(seed)
+        for i in rng.permutation(over)[:60]:
+            assert ref[i, acc] > 0 and _ball_holds_no_surface(orc, desc, acc, pts[i], da[i, acc], rng), i
+    # near the surface: within a quarter cell by the SDF -- and, where some
+    # member's SDF is only a bound (it may be small far from its surface, in
+    # cells that do not list it), by the grid too
+    near = ref[:, acc] < 0.25 * ext / 8
+    if not _exact_union(desc, acc):
+        near &= da[:, acc] < 0.25 * ext / 8
+    print(f"random {seed} {prec}: {int(near.sum())} points within a quarter cell of region {acc}, "
+          f"worst deviation there {np.abs(da[near, acc] - ref[near, acc]).max() / ext:.2e}")
+    assert near.sum() >= 20
+    assert np.all(np.abs(da[near, acc] - ref[near, acc]) <= tol)
+    clear = np.min(np.abs(ref), axis=1) > 10 * tol
+    assert np.array_equal(oa[clear], own[clear])
+
+
 def test_distance_of_no_points_and_bad_arguments(S, eng, W):
     desc = W.sphere_scene(n_grid=8)
     d, o = S.distance(desc, np.zeros((0, 3)), engine=eng)
