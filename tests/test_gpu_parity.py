@@ -343,6 +343,33 @@ def test_served_packets_resume_across_epochs(S, W, prec, rtol):
     eng.close()
 
 
+@pytest.mark.parametrize("prec,rtol", [("f64", 1e-11), ("f32", 1e-9)])
+def test_served_shortcut_scenes_resume_across_epochs(S, W, prec, rtol):
+    """The epoch kernels of the step shortcuts: segment-traced scenes (a
+    sphere, the glass sphere under its beam) and an over-relaxed slab,
+    served in 300-us epochs beside a plain scene, their packets saved and
+    resumed many times, each end with the packets, events and tallies of
+    its run alone."""
+    import torch
+    descs = [dict(W.sphere_scene(n_grid=16), segment=True), dict(W.glass_sphere_scene(n_grid=16), segment=True),
+             dict(W.slab_scene(n_grid=16), relax=1.9), W.cylinder_scene(n_grid=16)]
+    ns = [40000, 20000, 20000, 20000]
+    sv = S.Server(0, hbm_budget_bytes=1 << 30, epoch_us=300, precision=prec)
+    reqs = [(d, n) + sv.submit(d, 800 + i, n) for i, (d, n) in enumerate(zip(descs, ns))]
+    for d, n, rid, out in reqs:
+        sv.wait(rid, 120.0)
+        assert sv.poll(rid)[0] == "DONE"
+    st = sv.stats()
+    print(f"{prec}: epochs {st['epochs']}, packets saved at epoch ends {st['saved_total']}")
+    assert st["epochs"] >= 5 and st["saved_total"] > sum(ns) // 10
+    torch.cuda.synchronize()
+    eng = S.Engine(0, tally_layout=1)
+    for i, (d, n, rid, out) in enumerate(reqs):
+        _close(out.host(), S.run(d, 800 + i, n, engine=eng, precision=prec), rtol)
+    sv.close()
+    eng.close()
+
+
 def test_cancel_running_request_leaves_others_intact(S, W):
     import time
     import torch
