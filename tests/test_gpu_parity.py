@@ -212,15 +212,20 @@ def test_graph_replays_match_eager_runs(S, W, prec):
     eager work and synchronisations in between: every replay equals the
     eager run of the same seeds."""
     import torch
-    descs = [W.vessel_scene(21, 1.0, n_caps=200, n_grid=16), W.sphere_scene(n_grid=12)]
+    # every launch class in one captured sequence: staged capsules, plain,
+    # placed primitives, voxel model, segment-traced steps
+    descs = [W.vessel_scene(21, 1.0, n_caps=200, n_grid=16), W.sphere_scene(n_grid=12),
+             W.gallery_scene(n_grid=12), dict(W.cylinder_scene(n_grid=16), geometry="voxel"),
+             dict(W.glass_sphere_scene(n_grid=12), segment=True)]
+    ns = [3000, 5000, 2000, 2000, 2000]
     g_eng = S.Engine(0, precision=prec, use_graph=1)
     e_eng = S.Engine(0, precision=prec)
     scenes = [S.Scene(d) for d in descs]
     for rep in range(4):
-        seeds = [100 + rep, 200 + rep]
-        got = S.launch_batch(g_eng, scenes, seeds, [3000, 5000])
+        seeds = [100 * (j + 1) + rep for j in range(len(descs))]
+        got = S.launch_batch(g_eng, scenes, seeds, ns)
         torch.cuda.synchronize()
-        want = S.launch_batch(e_eng, scenes, seeds, [3000, 5000])   # eager work between replays
+        want = S.launch_batch(e_eng, scenes, seeds, ns)   # eager work between replays
         torch.cuda.synchronize()
         for a, b in zip(got, want):
             _close(a.host(), b.host(), 1e-11)
