@@ -178,12 +178,16 @@ def test_staged_capsule_tables_change_nothing(S, W):
 
 @pytest.mark.parametrize("prec", ["f64", "f32"])
 def test_batch_equals_runs_alone(S, eng, W, prec):
-    """Mixed scene families in one persistent launch: every job's tallies
-    equal its run alone (same packets, same walks; FP64 sums reordered)."""
+    """Mixed scene families in one persistent launch -- plain, staged
+    capsules, segment-traced, over-relaxed and placed-primitive jobs: every
+    job's tallies equal its run alone (same packets, same walks; FP64 sums
+    reordered)."""
     descs = [W.sphere_scene(n_grid=20), W.slab_scene(n_grid=24), W.cylinder_scene(n_grid=16),
-             W.vessel_scene(3, 0.7, n_caps=300, n_grid=16), W.sphere_scene(n_grid=20)]
-    seeds = [11, 12, 13, 14, 15]
-    ns = [20000, 5000, 4000, 3000, 777]
+             W.vessel_scene(3, 0.7, n_caps=300, n_grid=16), W.sphere_scene(n_grid=20),
+             dict(W.sphere_scene(n_grid=16), segment=True), dict(W.slab_scene(n_grid=16), relax=1.9),
+             W.gallery_scene(n_grid=12)]
+    seeds = [11, 12, 13, 14, 15, 16, 17, 18]
+    ns = [20000, 5000, 4000, 3000, 777, 6000, 3000, 2000]
     batch = S.run_batch(descs, seeds, ns, engine=eng, precision=prec)
     for d, sd, n, b in zip(descs, seeds, ns, batch):
         alone = S.run(d, sd, n, engine=eng, precision=prec)
