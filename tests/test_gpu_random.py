@@ -88,6 +88,13 @@ def test_random_scene_relaxed_runs_match_oracle(S, eng, orc, W, seed):
     assert abs(g["absorbed"].sum() - o["absorbed"].sum()) <= 1.0 + 1e-9 * n, seed
     assert abs(g["interfaces"] - o["interfaces"]) <= max(2, 2e-3 * o["interfaces"]), seed
     assert abs(identity_residual(g)) <= 1e-9 * n
+    # FP32 with over-relaxed steps: as the plain FP32 walk on these scenes
+    # (1e-4, or 2 packets per 1e4 where reflections are chaotic)
+    g = S.run(desc, 23, n, engine=eng, precision="f32")
+    diff = abs(g["absorbed"].sum() - o["absorbed"].sum())
+    assert diff <= max(1e-4 * o["absorbed"].sum(), 2.0 * n / 1e4), (seed, diff)
+    assert abs(g["interfaces"] - o["interfaces"]) <= max(5, 0.02 * o["interfaces"]), seed
+    assert abs(identity_residual(g)) <= 1e-9 * n
 
 
 def _with_union(desc):
