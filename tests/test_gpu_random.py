@@ -38,16 +38,19 @@ def test_random_scene_runs_match_oracle(S, eng, orc, W, seed):
         check_fluence(g, o, se, desc, "f32", n_batches=B)
 
 
+@pytest.mark.parametrize("prec,tol,need", [("f64", 1e-6, 0.97), ("f32", 1e-4, 0.95)])
 @pytest.mark.parametrize("seed", SEEDS[:6])
-def test_random_scene_traces_match_oracle(S, eng, orc, W, seed):
+def test_random_scene_traces_match_oracle(S, eng, orc, W, seed, prec, tol, need):
+    # FP32: the tolerance of the placed and modified shapes' scenes (their
+    # rotations, twists and bends round in FP32 at every evaluation)
     desc = W.random_scene(seed)
     n = 128
-    g = S.trace(desc, 13, list(range(n)), 40, engine=eng, precision="f64")
+    g = S.trace(desc, 13, list(range(n)), 40, engine=eng, precision=prec)
     o = [orc.trace(desc, 13, pid, 40) for pid in range(n)]
     mut = [rg["mua"] + rg["mus"] for rg in desc["regions"]]
-    frac, worst, bad = compare_traces(o, g, extent_of(S, desc), 1e-6, cap=40, mut=mut)
-    print(f"random {seed}: agree {frac:.4f} worst {worst} first disagreements {bad[:5]}")
-    assert frac >= 0.97, (seed, frac, worst, bad[:10])
+    frac, worst, bad = compare_traces(o, g, extent_of(S, desc), tol, cap=40, mut=mut)
+    print(f"random {seed} {prec}: agree {frac:.4f} worst {worst} first disagreements {bad[:5]}")
+    assert frac >= need, (seed, frac, worst, bad[:10])
 
 
 @pytest.mark.parametrize("seed", SEEDS)
