@@ -38,7 +38,7 @@ def test_random_scene_runs_match_oracle(S, eng, orc, W, seed):
         check_fluence(g, o, se, desc, "f32", n_batches=B)
 
 
-@pytest.mark.parametrize("prec,tol,need", [("f64", 1e-6, 0.97), ("f32", 1e-4, 0.95)])
+@pytest.mark.parametrize("prec,tol,need", [("f64", 1e-6, 0.97), ("f32", 1e-4, 0.97)])
 @pytest.mark.parametrize("seed", SEEDS[:6])
 def test_random_scene_traces_match_oracle(S, eng, orc, W, seed, prec, tol, need):
     # FP32: the tolerance of the placed and modified shapes' scenes (their
