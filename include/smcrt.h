@@ -552,12 +552,17 @@ smcrt_status smcrt_voxelize(smcrt_engine* engine, const smcrt_scene* scene, uint
  * lower bound the walk steps by (equal to the SDF within the grid's margin
  * of a surface).  d_owner (device, may be NULL): n int32, the highest-index
  * region whose distance is negative, else n_regions (ambient), as the walk
- * assigns regions.  n = 0 does nothing.  Asynchronous on hip_stream; the
- * caller owns the buffers.  Errors: SMCRT_E_INVALID for a NULL engine,
- * scene, d_points or d_dist (n > 0), accelerated outside {0, 1}, or an
- * incomplete scene; SMCRT_E_HIP on a device failure. */
+ * assigns regions.  d_normals (device, may be NULL): n x n_regions x 3
+ * doubles, each region's unit normal at the point by the interface step's
+ * FP64 central differences (Sec. 1: normals by numerical differentiation;
+ * step delta/100), through the grid when accelerated.  n = 0 does nothing.
+ * Asynchronous on hip_stream; the caller owns the buffers.  Errors:
+ * SMCRT_E_INVALID for a NULL engine, scene, d_points or d_dist (n > 0),
+ * accelerated outside {0, 1}, or an incomplete scene; SMCRT_E_HIP on a
+ * device failure. */
 smcrt_status smcrt_scene_distance(smcrt_engine* engine, const smcrt_scene* scene, const double* d_points, uint64_t n,
-                                  int32_t accelerated, double* d_dist, int32_t* d_owner, void* hip_stream);
+                                  int32_t accelerated, double* d_dist, int32_t* d_owner, double* d_normals,
+                                  void* hip_stream);
 
 #ifdef __cplusplus
 }

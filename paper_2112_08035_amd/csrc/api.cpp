@@ -1134,6 +1134,7 @@ struct DistSpec {
   int accelerated;
   double* dist;
   int32_t* owner;
+  double* normals;
 };
 
 static size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
@@ -1312,7 +1313,8 @@ static smcrt_status launch_jobs(smcrt_engine* e, const std::vector<JobSpec>& job
     }
     if (vox_out) return SMCRT_OK;
     if (dq) {
-      HIP_TRY(launch_distance(e->opts.precision, B.jobs, 0, dq->points, dq->n, dq->accelerated, dq->dist, dq->owner, q),
+      HIP_TRY(launch_distance(e->opts.precision, B.jobs, 0, dq->points, dq->n, dq->accelerated, dq->dist, dq->owner,
+                              dq->normals, q),
               "distance kernel");
       return SMCRT_OK;
     }
@@ -1677,7 +1679,8 @@ extern "C" smcrt_status smcrt_voxelize(smcrt_engine* e, const smcrt_scene* scene
 }
 
 extern "C" smcrt_status smcrt_scene_distance(smcrt_engine* e, const smcrt_scene* scene, const double* d_points, uint64_t n,
-                                             int32_t accelerated, double* d_dist, int32_t* d_owner, void* hip_stream) {
+                                             int32_t accelerated, double* d_dist, int32_t* d_owner, double* d_normals,
+                                             void* hip_stream) {
   if (!e || !scene) return fail(SMCRT_E_INVALID, "scene_distance: NULL engine or scene");
   if (accelerated != 0 && accelerated != 1) return fail(SMCRT_E_INVALID, "scene_distance: accelerated must be 0 or 1");
   if (n == 0) return SMCRT_OK;
@@ -1685,7 +1688,7 @@ extern "C" smcrt_status smcrt_scene_distance(smcrt_engine* e, const smcrt_scene*
   HIP_TRY(hipSetDevice(e->device), "hipSetDevice");
   std::vector<JobSpec> jobs(1);
   jobs[0] = JobSpec{const_cast<smcrt_scene*>(scene), 0, 0, 0, nullptr, nullptr, nullptr};
-  const DistSpec dq{d_points, n, (int)accelerated, d_dist, d_owner};
+  const DistSpec dq{d_points, n, (int)accelerated, d_dist, d_owner, d_normals};
   return launch_jobs(e, jobs, nullptr, (hipStream_t)hip_stream, nullptr, &dq);
 }
 

@@ -13,7 +13,7 @@ hipError_t launch_walk(int precision, bool trace, const LaunchCfg& cfg, const Ba
 // region slot of every voxel centre of job `job`'s scene into vox (n_vox bytes)
 hipError_t launch_voxelize(const WalkArgs* d_jobs, int job, uint8_t* vox, size_t n_vox, hipStream_t stream);
 hipError_t launch_distance(int precision, const WalkArgs* d_jobs, int job, const double* points, uint64_t n, int accelerated,
-                           double* dist, int32_t* owner, hipStream_t stream);
+                           double* dist, int32_t* owner, double* normals, hipStream_t stream);
 // p[i] = 0 for i < n (a kernel, so resets can sit inside captured graphs)
 hipError_t launch_zero_u64_n(unsigned long long* p, int n, hipStream_t stream);
 // zero n doubles (a kernel, so it can sit in a captured graph)

@@ -28,12 +28,14 @@ __global__ void __launch_bounds__(256) voxelize_kernel(const WalkArgs* __restric
 }
 
 // Point queries: every region's SDF at each point (through the uniform grid
-// for the accelerated region when accelerated), and the point's owner by
-// the walk's rule, in transport type T.
+// for the accelerated region when accelerated), the point's owner by the
+// walk's rule, in transport type T; and, when asked, every region's unit
+// normal by the interface step's FP64 central differences (step h_normal).
 template <typename T>
 __global__ void __launch_bounds__(256) distance_kernel(const WalkArgs* __restrict__ job_table, int job,
                                                        const double* __restrict__ pts, uint64_t n, int accelerated,
-                                                       double* __restrict__ dist, int32_t* __restrict__ owner) {
+                                                       double* __restrict__ dist, int32_t* __restrict__ owner,
+                                                       double* __restrict__ normals) {
   JobRef a = kptr(job_table)[job];
   ScP sc = kptr(a.sc);
   const int nr = sc->n_regions;
@@ -46,20 +48,37 @@ __global__ void __launch_bounds__(256) distance_kernel(const WalkArgs* __restric
       if (d < T(0)) own = r;
     }
     if (owner) owner[i] = own;
+    if (normals) {
+      const V3<double> q = mk(pts[3 * i], pts[3 * i + 1], pts[3 * i + 2]);
+      const double h = sc->h_normal;
+      for (int r = 0; r < nr; ++r) {
+        auto f = [&](V3<double> x) {
+          return accelerated ? region_dist<double, true>(a, r, x) : region_sdf<double, true>(a, sc->reg[r], x);
+        };
+        V3<double> g = mk(f(mk(q.x + h, q.y, q.z)) - f(mk(q.x - h, q.y, q.z)),
+                          f(mk(q.x, q.y + h, q.z)) - f(mk(q.x, q.y - h, q.z)),
+                          f(mk(q.x, q.y, q.z + h)) - f(mk(q.x, q.y, q.z - h)));
+        g = (1.0 / __builtin_sqrt(dot(g, g))) * g;
+        double* o = normals + 3 * (i * (uint64_t)nr + r);
+        o[0] = g.x;
+        o[1] = g.y;
+        o[2] = g.z;
+      }
+    }
   }
 }
 
 hipError_t launch_distance(int precision, const WalkArgs* d_jobs, int job, const double* points, uint64_t n, int accelerated,
-                           double* dist, int32_t* owner, hipStream_t stream) {
+                           double* dist, int32_t* owner, double* normals, hipStream_t stream) {
   if (!d_jobs || !points || !dist || job < 0 || n == 0) return hipErrorInvalidValue;
   uint64_t blocks = (n + 255) / 256;
   if (blocks > 16384) blocks = 16384;
   if (precision == 1)
     hipLaunchKernelGGL(distance_kernel<double>, dim3((unsigned)blocks), dim3(256), 0, stream, d_jobs, job, points, n,
-                       accelerated, dist, owner);
+                       accelerated, dist, owner, normals);
   else
     hipLaunchKernelGGL(distance_kernel<float>, dim3((unsigned)blocks), dim3(256), 0, stream, d_jobs, job, points, n,
-                       accelerated, dist, owner);
+                       accelerated, dist, owner, normals);
   return hipGetLastError();
 }
 

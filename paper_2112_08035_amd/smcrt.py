@@ -115,7 +115,7 @@ _SIGS = {
     "smcrt_normalize_fluence": ([_vp, _vp, C.c_double, _vp, _vp], C.c_int),
     "smcrt_trace": ([_vp, _vp, C.c_uint64, _vp, C.c_int, C.c_int, _vp, _vp, _vp], C.c_int),
     "smcrt_voxelize": ([_vp, _vp, _vp, _vp], C.c_int),
-    "smcrt_scene_distance": ([_vp, _vp, _vp, C.c_uint64, C.c_int32, _vp, _vp, _vp], C.c_int),
+    "smcrt_scene_distance": ([_vp, _vp, _vp, C.c_uint64, C.c_int32, _vp, _vp, _vp, _vp], C.c_int),
     "smcrt_server_create": ([C.POINTER(_vp), C.c_int, C.c_uint64, C.c_uint64, C.POINTER(Opts)], C.c_int),
     "smcrt_server_destroy": ([_vp], C.c_int),
     "smcrt_submit": ([_vp, _vp, C.c_uint64, C.c_uint64, _vp, _vp, _vp, C.POINTER(C.c_uint64)], C.c_int),
@@ -333,8 +333,8 @@ def smcrt_voxelize(engine, scene, d_out, stream):
     _check(lib().smcrt_voxelize(engine, scene, d_out, stream))
 
 
-def smcrt_scene_distance(engine, scene, d_points, n, accelerated, d_dist, d_owner, stream):
-    _check(lib().smcrt_scene_distance(engine, scene, d_points, n, accelerated, d_dist, d_owner, stream))
+def smcrt_scene_distance(engine, scene, d_points, n, accelerated, d_dist, d_owner, d_normals, stream):
+    _check(lib().smcrt_scene_distance(engine, scene, d_points, n, accelerated, d_dist, d_owner, d_normals, stream))
 
 
 def smcrt_server_create(device, hbm_budget_bytes, epoch_packets=0, opts=None):
@@ -671,10 +671,11 @@ def voxelize(desc, engine=None):
     return v.reshape(sc.dims[2], sc.dims[1], sc.dims[0])
 
 
-def distance(desc, points, engine=None, precision="f64", accelerated=False):
+def distance(desc, points, engine=None, precision="f64", accelerated=False, normals=False):
     """Every region's SDF at the points (array-like, shape (n, 3)) from the
     device, and each point's owning region (-1 = ambient): returns
-    (distances (n, n_regions), owners (n,)) as host arrays."""
+    (distances (n, n_regions), owners (n,)) as host arrays, and with
+    normals=True also every region's FP64 numerical normal (n, n_regions, 3)."""
     import torch
     eng = engine if engine is not None else Engine(0)
     eng.set_opts(precision=precision)
@@ -684,11 +685,15 @@ def distance(desc, points, engine=None, precision="f64", accelerated=False):
     n = pts.shape[0]
     dist = torch.empty((n, sc.n_regions), dtype=torch.float64, device=dev)
     own = torch.empty(n, dtype=torch.int32, device=dev)
+    nrm = torch.empty((n, sc.n_regions, 3), dtype=torch.float64, device=dev) if normals else None
     smcrt_scene_distance(eng.h, sc.h, C.c_void_p(pts.data_ptr()), n, 1 if accelerated else 0,
-                         C.c_void_p(dist.data_ptr()), C.c_void_p(own.data_ptr()), _stream_ptr(None))
+                         C.c_void_p(dist.data_ptr()), C.c_void_p(own.data_ptr()),
+                         C.c_void_p(nrm.data_ptr()) if normals else None, _stream_ptr(None))
     torch.cuda.synchronize()
     o = own.cpu().numpy().astype(np.int64)
     o[o == sc.n_regions] = -1
+    if normals:
+        return dist.cpu().numpy(), o, nrm.cpu().numpy()
     return dist.cpu().numpy(), o
 
 

@@ -390,7 +390,7 @@ def test_scene_distance_validation(S):
     h = S.smcrt_scene_create(1.0, 1e-5, 1e-4)
     try:
         with pytest.raises(S.SmcrtError, match="NULL engine"):
-            S.smcrt_scene_distance(None, h, None, 0, 0, None, None, None)
+            S.smcrt_scene_distance(None, h, None, 0, 0, None, None, None, None)
     finally:
         S.smcrt_scene_destroy(h)
 

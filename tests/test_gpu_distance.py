@@ -68,6 +68,25 @@ def _check(S, eng, orc, desc, seed, prec):
 FAMILIES = ["sphere", "slab", "cylinder", "glass_sphere", "bottle", "gallery", "shapes"]
 
 
+@pytest.mark.parametrize("make", FAMILIES + ["random3", "random7", "random10"])
+def test_numerical_normals_match_oracle(S, eng, orc, W, make):
+    """The interface step's FP64 normals (Sec. 1: central differences of
+    step delta/100 on both sides) against the oracle's at points within 2 %
+    of the extent of a surface, every region: unit vectors equal to 1e-7
+    (the difference quotient divides the SDFs' last-bit differences by
+    2 delta/100)."""
+    desc = W.random_scene(int(make[6:]), n_grid=8) if make.startswith("random") else W.WORKLOADS[make](n_grid=8)
+    pts, ref, _, ext = _points(S, orc, desc, 500, n_uniform=0, n_near=600)
+    _, _, nrm = S.distance(desc, pts, engine=eng, precision="f64", normals=True)
+    h = 1e-2 * desc["delta"]
+    nr = len(desc["regions"])
+    o = np.array([[orc.region_normal(desc, r, p, h) for r in range(nr)] for p in pts])
+    err = np.abs(nrm - o).max()
+    print(f"{make}: {len(pts)} points x {nr} regions, worst normal difference {err:.2e}")
+    assert np.allclose(np.linalg.norm(nrm, axis=2), 1.0, atol=1e-12)
+    assert err <= 1e-7, err
+
+
 @pytest.mark.parametrize("prec", ["f64", "f32"])
 @pytest.mark.parametrize("name", FAMILIES)
 def test_family_distances_match_oracle(S, eng, orc, W, name, prec):
@@ -182,6 +201,6 @@ def test_distance_of_no_points_and_bad_arguments(S, eng, W):
     assert d.shape == (0, 1) and o.shape == (0,)
     sc = S.Scene(desc)
     with pytest.raises(S.SmcrtError, match="accelerated"):
-        S.smcrt_scene_distance(eng.h, sc.h, None, 1, 2, None, None, None)
+        S.smcrt_scene_distance(eng.h, sc.h, None, 1, 2, None, None, None, None)
     with pytest.raises(S.SmcrtError, match="NULL points"):
-        S.smcrt_scene_distance(eng.h, sc.h, None, 1, 0, None, None, None)
+        S.smcrt_scene_distance(eng.h, sc.h, None, 1, 0, None, None, None, None)
